@@ -1,0 +1,11 @@
+"""CPU float64 oracle of the hierarchical MAT SVD and its comparison metrics.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg; never by the library's execution path.
+Parity status of each function is recorded in its docstring and in the pins
+under tests/test_oracle.py.
+"""
+from .hsvd_oracle import (EPS, balanced_split, truncation_rank, leaf, merge,  # noqa: F401
+                          merge_complement, merge_tree, slab_nodes, project, improve,
+                          sign_normalise, hsvd, flop_model)
+from . import metrics  # noqa: F401

@@ -1,0 +1,251 @@
+"""CPU float64 oracle of the hierarchical merge-and-truncate (MAT) truncated SVD.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the library's own execution path never
+calls it and shares no code with it.
+
+It follows Vasudevan & Ramakrishna, "A Hierarchical Singular Value Decomposition
+Algorithm for Low Rank Matrices" (arXiv:1710.02812):
+
+  * Section 3, Algorithm 1 (DoSVDofBlocks / DoSVDofColSlices / DoMergeOfSlices /
+    BlockMerge): row slabs outermost; inside each slab the column blocks get
+    truncated SVDs that are merged pairwise up a tree (left factors only); the
+    slab's right factor comes from the SVD of U_i^T X_i; the slab nodes are then
+    merged pairwise the same way (right factors only).
+  * Section 3, truncation: keep singular values >= gamma * sigma_1 of the matrix
+    being truncated, before and after every merge.
+  * Section 3, left vectors by projection: SVD(X V) = U_y S_y V_y^T gives
+    U = U_y, S = S_y, V = V V_y.
+  * Section 3, Algorithm 2: iterative improvement (a power step on the subspace).
+
+Each step uses the plain definition with LAPACK SVDs: a merge is the truncated
+SVD of the concatenated scaled factors [U1 S1, U2 S2] (the column-split
+identity of Section 3); the faster complement form (eqs. orthmerge1/orthmerge)
+is implemented separately in ``merge_complement`` and is used only to cross-check
+that identity, never as the reference.
+
+Readings where the paper is silent or garbled (each is listed in the design doc):
+  R1 truncation keeps s_i >= tol * s_0 (ties kept), caps r <= k, and drops values
+     <= max(shape) * 2^-52 * s_0 (numerical zero).  tol = 0 means fixed rank k.
+  R2 the same rule is applied to leaves, merges and the slab re-projection; the
+     final projection applies only the zero floor.
+  R3 E's lower-right block is R S2 (the printed S2 R does not follow from
+     U2 S2 = U1 (U1^T U2) S2 + U_o R S2), and V = diag(V1, V2) V_E.
+  R4 slice counts: the block grid is given as counts (p, q); rows/columns are
+     split evenly, the first (m mod p) row blocks one row taller.
+  R5 the tree pairs neighbours (0,1), (2,3), ... left to right and carries an odd
+     last node up unchanged, looping until one node is left.
+  R6 Algorithm 2 updates V-hat every iteration; the rank is frozen.
+  R7 a rank-0 node is the identity of a merge.
+  R8 singular vector signs: flip (u_i, v_i) so that the entry of u_i with the
+     largest magnitude is positive (ties: lowest index).
+  R9 'frob' rule (used by the learned-rank workload): smallest r whose discarded
+     tail energy sum_{i>=r} s_i^2 is <= tol^2 * sum s_i^2, then the zero floor.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS = 2.0 ** -52
+
+
+# ----------------------------------------------------------------------------- partition
+def balanced_split(n: int, parts: int) -> list[tuple[int, int]]:
+    """Half-open [start, stop) ranges splitting n into `parts` nearly equal pieces (R4).
+
+    Algorithm 1 fills its lists with row/column slices of fixed size d (or c); with
+    the grid given as counts the sizes differ by at most one, larger pieces first.
+    """
+    if parts < 1 or parts > max(n, 1):
+        raise ValueError("need 1 <= parts <= n")
+    base, extra = divmod(n, parts)
+    out, start = [], 0
+    for i in range(parts):
+        size = base + (1 if i < extra else 0)
+        out.append((start, start + size))
+        start += size
+    return out
+
+
+# ----------------------------------------------------------------------------- truncation
+def truncation_rank(s, k: int, tol: float, rule: str, shape) -> int:
+    """Number of leading singular values kept (Section 3 truncation criterion; R1, R9).
+
+    `s` is sorted in decreasing order; `shape` is the shape of the matrix whose
+    singular values these are (it scales the numerical-zero floor).
+    """
+    s = np.asarray(s, dtype=np.float64)
+    if s.size == 0 or not s[0] > 0.0:
+        return 0
+    floor = max(shape) * EPS * s[0]
+    nonzero = int(np.count_nonzero(s > floor))
+    if rule == "gamma":
+        r = int(np.count_nonzero(s >= tol * s[0]))
+    elif rule == "frob":
+        e = s * s
+        tail = np.concatenate([np.cumsum(e[::-1])[::-1], [0.0]])   # tail[r] = sum_{i>=r} e_i
+        r = int(np.argmax(tail <= tol * tol * e.sum()))
+    else:
+        raise ValueError(f"unknown rule {rule!r}")
+    return min(r, nonzero, k)
+
+
+def _svd(M: np.ndarray):
+    """Thin LAPACK SVD that also accepts matrices with an empty dimension."""
+    h, w = M.shape
+    if h == 0 or w == 0:
+        return np.zeros((h, 0)), np.zeros(0), np.zeros((0, w))
+    return np.linalg.svd(M, full_matrices=False)
+
+
+# ----------------------------------------------------------------------------- one MAT step
+def leaf(block: np.ndarray, k: int, tol: float, rule: str):
+    """Truncated SVD of one block: Algorithm 1, DoSVDofColSlices' per-slice SVD."""
+    U, s, _ = _svd(block)
+    r = truncation_rank(s, k, tol, rule, block.shape)
+    return U[:, :r], s[:r]
+
+
+def merge(U1, s1, U2, s2, k: int, tol: float, rule: str):
+    """One merge-and-truncate step on left factors (Section 3, column-split identity).
+
+    [X1 X2] ~ [U1 S1, U2 S2] diag(V1^T, V2^T); the left singular vectors and values
+    of [X1 X2] are those of F = [U1 S1, U2 S2], truncated by the same rule.  The
+    row-split case is the same operation on right factors (F = [V1 S1, V2 S2]).
+    """
+    F = np.hstack([U1 * s1, U2 * s2])
+    U, s, _ = _svd(F)
+    r = truncation_rank(s, k, tol, rule, F.shape)
+    return U[:, :r], s[:r]
+
+
+def merge_complement(U1, s1, U2, s2, k: int | None = None, tol: float = 0.0,
+                     rule: str = "gamma", truncate: bool = True):
+    """The orthogonal-complement form of one merge (Section 3, eqs. orthmerge1/orthmerge).
+
+    Q = U2 - U1 (U1^T U2) = U_o R;  E = [[S1, (U1^T U2) S2], [0, R S2]] (reading R3);
+    E = U_E S_E V_E^T;  U = [U1 U_o] U_E, S = S_E.  Used only to cross-check the
+    identity against ``merge``.  Returns (U, s, pieces) where pieces holds
+    Uo, E and V_E for reconstruction checks.
+    """
+    C = U1.T @ U2
+    Q = U2 - U1 @ C
+    Uo, R = np.linalg.qr(Q)
+    k1, k2 = s1.size, s2.size
+    E = np.zeros((k1 + R.shape[0], k1 + k2))
+    E[:k1, :k1] = np.diag(s1)
+    E[:k1, k1:] = C * s2
+    E[k1:, k1:] = R * s2
+    UE, sE, VEt = _svd(E)
+    U = np.hstack([U1, Uo]) @ UE
+    r = sE.size
+    if truncate:
+        r = truncation_rank(sE, k if k is not None else sE.size, tol, rule,
+                            (U1.shape[0], k1 + k2))
+    return U[:, :r], sE[:r], {"Uo": Uo, "E": E, "VEt": VEt, "UE": UE, "sE": sE}
+
+
+def merge_tree(nodes, k: int, tol: float, rule: str, merge_fn=None):
+    """Pairwise merge levels until one node is left (Algorithm 1, DoMergeOfSlices; R5, R7)."""
+    merge_fn = merge if merge_fn is None else merge_fn
+    nodes = list(nodes)
+    if not nodes:
+        raise ValueError("empty node list")
+    while len(nodes) > 1:
+        nxt = [merge_fn(*nodes[i], *nodes[i + 1], k, tol, rule)
+               for i in range(0, len(nodes) - 1, 2)]
+        if len(nodes) % 2:
+            nxt.append(nodes[-1])
+        nodes = nxt
+    return nodes[0]
+
+
+# ----------------------------------------------------------------------------- Algorithm 1
+def slab_nodes(A, p: int, q: int, k: int, tol: float, rule: str, merge_fn=None):
+    """For each row slab: column MAT tree, then V_i, S_i = SVD(U_i^T X_i) (Algorithm 1)."""
+    m, n = A.shape
+    out = []
+    for (r0, r1) in balanced_split(m, p):
+        X = A[r0:r1]
+        leaves = [leaf(X[:, c0:c1], k, tol, rule) for (c0, c1) in balanced_split(n, q)]
+        Ui, si = merge_tree(leaves, k, tol, rule, merge_fn)
+        W = Ui.T @ X                                    # r_i x n
+        _, sw, Vwt = _svd(W)
+        r = truncation_rank(sw, k, tol, rule, W.shape)  # R2
+        out.append((Vwt[:r].T, sw[:r]))
+    return out
+
+
+def project(A, V):
+    """Left vectors by projection: SVD(A V) = U_y S_y V_y^T; U = U_y, V <- V V_y (Section 3)."""
+    Y = A @ V
+    Uy, sy, Vyt = _svd(Y)
+    r = truncation_rank(sy, sy.size, 0.0, "gamma", Y.shape)   # zero floor only (R2)
+    return Uy[:, :r], sy[:r], V @ Vyt[:r].T
+
+
+def improve(A, V, r_freeze: int, iters: int, eps: float | None = None):
+    """Algorithm 2 (iterative improvement; R6).  Runs `iters` iterations, or until the
+    relative change of the singular values is <= eps when eps is given (at most `iters`)."""
+    s_prev = None
+    U = s = None
+    for _ in range(iters):
+        Ui, si, _ = _svd(A @ V)
+        Ui = Ui[:, :r_freeze]
+        Ut, st, Vtt = _svd(Ui.T @ A)
+        U, s, V = Ui @ Ut, st, Vtt.T
+        if eps is not None and s_prev is not None:
+            if np.linalg.norm(s_prev - s) <= eps * np.linalg.norm(s_prev):
+                break
+        s_prev = s
+    return U, s, V
+
+
+def sign_normalise(U, V):
+    """Flip (u_i, v_i) so the largest-magnitude entry of u_i is positive (R8)."""
+    U = U.copy()
+    V = V.copy()
+    for i in range(U.shape[1]):
+        j = int(np.argmax(np.abs(U[:, i])))
+        if U[j, i] < 0.0:
+            U[:, i] *= -1.0
+            V[:, i] *= -1.0
+    return U, V
+
+
+def hsvd(A, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
+         refine: int = 0, merge_fn=None):
+    """The whole method: returns (U [m x k], s [k], Vt [k x n], r), zero padded past r.
+
+    Algorithm 1 gives (V-hat, S-hat); U follows by projection; `refine` runs
+    that many iterations of Algorithm 2.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= p <= m and 1 <= q <= n and 1 <= k <= min(m, n) and 0.0 <= tol < 1.0):
+        raise ValueError("invalid arguments")
+    slabs = slab_nodes(A, p, q, k, tol, rule, merge_fn)
+    Vh, sh = merge_tree(slabs, k, tol, rule, merge_fn)
+    U, s, V = project(A, Vh)
+    r = s.size
+    if refine > 0 and r > 0:
+        U, s, V = improve(A, V, r, refine)
+    U, V = sign_normalise(U, V)
+    Uo = np.zeros((m, k))
+    so = np.zeros(k)
+    Vto = np.zeros((k, n))
+    Uo[:, :r] = U
+    so[:r] = s
+    Vto[:r] = V.T
+    return Uo, so, Vto, r
+
+
+def flop_model(m: int, n: int, P: int, k: int) -> dict:
+    """Section 3.1 cost model for a column split into P blocks of s = n/P columns."""
+    s = n / P
+    return {
+        "full_svd": 6 * m * n * n + 16 * n ** 3,
+        "blocks": P * (6 * m * s * s + 16 * s ** 3),
+        "merges": (P - 1) * (14 * m * k * k + 176 * k ** 3),
+        "bound": 20 * m * n * n / P + 192 * n ** 3 / P ** 2,
+    }

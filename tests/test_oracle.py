@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the part of the paper it pins and the external fact used:
+closed forms, constructed matrices with a known SVD, brute-force optimisation on
+tiny inputs, exact identities of Section 3 checked by reconstruction, and
+invariants of the projection step.  The last group plants mistakes in copies
+of the oracle and checks that the pins catch them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import oracle
+from oracle import metrics
+from paper_1710_02812_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- truncation
+def test_truncation_rule_golden_cases():
+    """Section 3 truncation criterion (keep s >= gamma*s_1) on hand-written spectra."""
+    with open(os.path.join(GOLDEN, "truncation_cases.json")) as f:
+        cases = json.load(f)["cases"]
+    assert len(cases) >= 8
+    for c in cases:
+        r = oracle.truncation_rank(np.array(c["s"], dtype=float), c["k"], c["tol"],
+                                   c["rule"], tuple(c["shape"]))
+        assert r == c["r"], c
+
+
+def test_balanced_split():
+    assert oracle.balanced_split(10, 3) == [(0, 4), (4, 7), (7, 10)]
+    assert oracle.balanced_split(8192, 8) == [(i * 1024, (i + 1) * 1024) for i in range(8)]
+    for n, p in [(1, 1), (7, 7), (1000, 3), (4097, 9)]:
+        b = oracle.balanced_split(n, p)
+        sizes = [e - s for s, e in b]
+        assert sum(sizes) == n and max(sizes) - min(sizes) <= 1 and b[0][0] == 0
+    with pytest.raises(ValueError):
+        oracle.balanced_split(3, 4)
+
+
+# ----------------------------------------------------------------------------- Eckart-Young
+def _tail_energy_bruteforce(A, k, rng):
+    """min over rank-k orthogonal projectors P of ||A - A P||_F^2, by search."""
+    n = A.shape[1]
+    assert n == 3
+
+    def unit(a, b):
+        return np.array([np.sin(a) * np.cos(b), np.sin(a) * np.sin(b), np.cos(a)])
+
+    def loss(x):
+        v = unit(*x)
+        if k == 1:
+            P = np.outer(v, v)           # projector on v
+        else:
+            P = np.eye(3) - np.outer(v, v)  # rank-2 projector: v is its normal
+        return np.sum((A - A @ P) ** 2)
+
+    grid = np.linspace(0, np.pi, 181)
+    best = min(((loss((a, b)), (a, b)) for a in grid for b in np.linspace(0, 2 * np.pi, 361)))
+    res = minimize(loss, best[1], method="Nelder-Mead",
+                   options={"xatol": 1e-12, "fatol": 1e-16, "maxiter": 20000})
+    return res.fun
+
+
+@pytest.mark.parametrize("shape,k,seed", [((3, 3), 1, 0), ((3, 3), 2, 1), ((4, 3), 1, 2),
+                                          ((4, 3), 2, 3)])
+def test_eckart_young_bruteforce(shape, k, seed):
+    """p = q = 1: the oracle's rank-k result attains the minimal error over all
+    rank-k approximations (Section 1), found here by direct search."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal(shape)
+    U, s, Vt, r = oracle.hsvd(A, 1, 1, k)
+    assert r == k
+    err_oracle = np.sum((A - (U[:, :r] * s[:r]) @ Vt[:r]) ** 2)
+    err_search = _tail_energy_bruteforce(A, k, rng)
+    assert abs(err_oracle - err_search) <= 1e-9 * max(err_search, 1e-300) + 1e-14
+    # 10^5 random rank-k products never beat it
+    X = rng.standard_normal((100000, shape[0], k))
+    Y = rng.standard_normal((100000, k, shape[1]))
+    errs = np.sum((A[None] - X @ Y) ** 2, axis=(1, 2))
+    assert errs.min() >= err_oracle * (1 - 1e-12)
+
+
+# ----------------------------------------------------------------------------- exact recovery
+@pytest.mark.parametrize("p,q", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 5), (5, 3), (8, 8), (5, 8)])
+def test_exact_recovery_low_rank(p, q):
+    """Row/column-split identities of Section 3 lose nothing when rank(A) <= k:
+    the result equals the constructed SVD (non-powers-of-two exercise the odd carry)."""
+    rng = np.random.default_rng(100 + 10 * p + q)
+    m, n, rank, k = 240, 200, 6, 8
+    sigma = np.exp(-np.arange(rank) / 2.0) * 3.0
+    A, U0, s0, V0 = synth.low_rank(rng, m, n, sigma)
+    U, s, Vt, r = oracle.hsvd(A, p, q, k)
+    assert r == rank
+    assert metrics.e_sigma(s[:r], s0) <= 1e-12
+    assert metrics.sin_theta(U[:, :r], U0) <= 1e-12
+    assert metrics.sin_theta(Vt[:r].T, V0) <= 1e-12
+    assert metrics.e_frob(U[:, :r], s[:r], Vt[:r].T, U0, s0, V0) <= 1e-12
+
+
+def test_tree_pairing_invariance_exact_case():
+    """For an exactly low-rank input any pairing gives the same result (Section 3)."""
+    rng = np.random.default_rng(7)
+    A, U0, s0, V0 = synth.low_rank(rng, 300, 280, np.linspace(2, 1, 5))
+
+    def reversed_merge(U1, s1, U2, s2, k, tol, rule):
+        return oracle.merge(U2, s2, U1, s1, k, tol, rule)
+
+    a = oracle.hsvd(A, 3, 5, 7)
+    b = oracle.hsvd(A, 3, 5, 7, merge_fn=reversed_merge)
+    assert a[3] == b[3] == 5
+    assert metrics.e_frob(a[0][:, :5], a[1][:5], a[2][:5].T, b[0][:, :5], b[1][:5],
+                          b[2][:5].T) <= 1e-12
+
+
+def test_one_block_is_truncated_svd():
+    """p = q = 1 reduces to the ordinary truncated SVD; the known SVD is constructed."""
+    rng = np.random.default_rng(11)
+    m, n = 90, 70
+    sigma = np.sort(rng.uniform(0.1, 10.0, n))[::-1]
+    A, U0, s0, V0 = synth.low_rank(rng, m, n, sigma)
+    for k in (1, 5, 33, 70):
+        U, s, Vt, r = oracle.hsvd(A, 1, 1, k)
+        assert r == k
+        assert metrics.e_sigma(s[:k], s0[:k]) <= 1e-13
+        assert metrics.e_frob(U[:, :k], s[:k], Vt[:k].T, U0[:, :k], s0[:k], V0[:, :k]) <= 1e-12
+
+
+# ----------------------------------------------------------------------------- merge identity
+def _two_blocks(rng, h, w1, w2, k1, k2, overlap=False):
+    X1 = rng.standard_normal((h, w1))
+    X2 = rng.standard_normal((h, w2))
+    if overlap:
+        X2 = X1[:, :1] @ rng.standard_normal((1, w2)) + X1 @ rng.standard_normal((w1, w2))
+    U1, s1, V1t = np.linalg.svd(X1, full_matrices=False)
+    U2, s2, V2t = np.linalg.svd(X2, full_matrices=False)
+    return (U1[:, :k1], s1[:k1], V1t[:k1].T), (U2[:, :k2], s2[:k2], V2t[:k2].T)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_merge_complement_identity(overlap):
+    """Eq. orthmerge1 with the lower-right block R*S2: [U1 U_o] E diag(V1^T, V2^T)
+    reconstructs [X1 X2] exactly, and its singular values equal those of the
+    concatenation route."""
+    rng = np.random.default_rng(21 + overlap)
+    h, w1, w2 = 60, 9, 7
+    (U1, s1, V1), (U2, s2, V2) = _two_blocks(rng, h, w1, w2, w1, w2, overlap)
+    X = np.hstack([(U1 * s1) @ V1.T, (U2 * s2) @ V2.T])
+    _, _, pieces = oracle.merge_complement(U1, s1, U2, s2, truncate=False)
+    Ubig = np.hstack([U1, pieces["Uo"]])
+    Vblk = np.zeros((w1 + w2, w1 + w2))
+    Vblk[:w1, :w1] = V1.T
+    Vblk[w1:, w1:] = V2.T
+    rec = Ubig @ pieces["E"] @ Vblk
+    assert np.linalg.norm(rec - X) <= 1e-13 * np.linalg.norm(X)
+    Uc, sc = oracle.merge(U1, s1, U2, s2, w1 + w2, 0.0, "gamma")
+    Ux, sx, _ = oracle.merge_complement(U1, s1, U2, s2, w1 + w2, 0.0, "gamma")
+    assert sc.size == sx.size
+    assert np.max(np.abs(sc - sx)) <= 1e-13 * sc[0]
+    r = sc.size
+    assert metrics.sin_theta(Ux[:, :r], Uc[:, :r]) <= 1e-12 * metrics.amplification(sc, r - 1) + 1e-12
+
+
+def test_merge_printed_block_order_is_wrong():
+    """The printed lower-right block S2*R does not reconstruct [X1 X2] (reading R3)."""
+    rng = np.random.default_rng(5)
+    (U1, s1, V1), (U2, s2, V2) = _two_blocks(rng, 40, 6, 6, 6, 6)
+    _, _, pc = oracle.merge_complement(U1, s1, U2, s2, truncate=False)
+    E_bad = pc["E"].copy()
+    R = np.linalg.qr(U2 - U1 @ (U1.T @ U2))[1]
+    E_bad[6:, 6:] = np.diag(s2) @ R
+    X = np.hstack([(U1 * s1) @ V1.T, (U2 * s2) @ V2.T])
+    Vblk = np.zeros((12, 12))
+    Vblk[:6, :6] = V1.T
+    Vblk[6:, 6:] = V2.T
+    rec = np.hstack([U1, pc["Uo"]]) @ E_bad @ Vblk
+    assert np.linalg.norm(rec - X) > 1e-3 * np.linalg.norm(X)
+
+
+def test_merge_zero_complement():
+    """span(U2) inside span(U1): the complement is empty and the merge keeps rank k1."""
+    rng = np.random.default_rng(9)
+    U1 = synth.orth(rng, 50, 5)
+    U2 = U1 @ synth.orth(rng, 5, 3)
+    s1 = np.array([5.0, 4, 3, 2, 1])
+    s2 = np.array([3.0, 2, 1])
+    U, s = oracle.merge(U1, s1, U2, s2, 10, 0.0, "gamma")
+    assert s.size == 5
+    assert metrics.sin_theta(U, U1) <= 1e-13
+    # energy is preserved exactly: sum s^2 = sum s1^2 + sum s2^2
+    assert abs(np.sum(s ** 2) - np.sum(s1 ** 2) - np.sum(s2 ** 2)) <= 1e-12 * np.sum(s ** 2)
+
+
+def test_rank_zero_node_is_identity():
+    """R7: a zero block contributes nothing; merging with it returns the other node."""
+    rng = np.random.default_rng(3)
+    U1 = synth.orth(rng, 30, 4)
+    s1 = np.array([4.0, 3, 2, 1])
+    U, s = oracle.merge(U1, s1, np.zeros((30, 0)), np.zeros(0), 8, 0.0, "gamma")
+    assert np.allclose(s, s1, rtol=0, atol=1e-14)
+    assert metrics.sin_theta(U, U1) <= 1e-14
+    Uz, sz = oracle.leaf(np.zeros((10, 12)), 5, 0.0, "gamma")
+    assert sz.size == 0 and Uz.shape == (10, 0)
+
+
+# ----------------------------------------------------------------------------- block diagonal
+def test_block_diagonal_union_of_spectra():
+    """Off-diagonal blocks zero: sigma(A) is the union of the blocks' spectra (closed form)."""
+    rng = np.random.default_rng(31)
+    B1, U1, sg1, V1 = synth.low_rank(rng, 64, 48, np.array([9.0, 5, 2]))
+    B2, U2, sg2, V2 = synth.low_rank(rng, 56, 40, np.array([7.0, 3, 1, 0.5]))
+    A = np.zeros((120, 88))
+    A[:64, :48] = B1
+    A[64:, 48:] = B2
+    U, s, Vt, r = oracle.hsvd(A, 2, 2, 10)
+    want = np.sort(np.concatenate([sg1, sg2]))[::-1]
+    assert r == 7
+    assert np.max(np.abs(s[:r] - want)) <= 1e-13 * want[0]
+
+
+# ----------------------------------------------------------------------------- projection
+def test_projection_invariants_inexact_input():
+    """Section 3 projection: U S V^T = A V V^T, ||A - U S V^T||^2 = ||A||^2 - sum s^2,
+    s_i <= sigma_i(A) (interlacing), orthonormal factors -- for any input."""
+    rng = np.random.default_rng(41)
+    m, n = 200, 160
+    sigma = np.exp(-np.arange(n) / 12.0) * 10
+    A, U0, s0, V0 = synth.low_rank(rng, m, n, sigma)
+    U, s, Vt, r = oracle.hsvd(A, 3, 4, 12, tol=0.0)
+    Ur, sr, Vr = U[:, :r], s[:r], Vt[:r].T
+    assert np.linalg.norm(Ur.T @ Ur - np.eye(r)) <= 1e-13
+    assert np.linalg.norm(Vr.T @ Vr - np.eye(r)) <= 1e-13
+    X = (Ur * sr) @ Vr.T
+    assert np.linalg.norm(X - A @ Vr @ Vr.T) <= 1e-12 * np.linalg.norm(A)
+    lhs = np.linalg.norm(A - X) ** 2
+    rhs = np.linalg.norm(A) ** 2 - np.sum(sr ** 2)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(A) ** 2
+    assert np.all(sr <= s0[:r] * (1 + 1e-13))
+    # slow decay (no gap at r): a truncated tree is an approximation, not exact
+    e = metrics.e_frob(Ur, sr, Vr, U0[:, :r], s0[:r], V0[:, :r])
+    assert 1e-6 < e < 0.2
+
+
+def test_algorithm2_converges_to_top_subspace():
+    """Algorithm 2 is a power iteration: more iterations approach the top-r
+    subspace (constructed), monotonically, to ~1e-10 on a gapped spectrum."""
+    rng = np.random.default_rng(51)
+    m, n, r = 300, 240, 10
+    sigma = np.concatenate([np.linspace(10, 5, r), 0.8 * np.exp(-np.arange(n - r) / 30)])
+    A, U0, s0, V0 = synth.low_rank(rng, m, n, sigma)
+    U, s, Vt, rr = oracle.hsvd(A, 4, 4, r, tol=0.0)
+    assert rr == r
+    prev = metrics.sin_theta(Vt[:r].T, V0[:, :r])
+    Vh = Vt[:r].T
+    errs = [prev]
+    for it in range(1, 12):
+        _, _, V = oracle.improve(A, Vh, r, it)
+        errs.append(metrics.sin_theta(V, V0[:, :r]))
+    assert all(b <= a * 1.0001 + 1e-15 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 1e-10
+    # ratio per step ~ (sigma_{r+1}/sigma_r)^2 = (0.8/5)^2
+    assert errs[2] <= errs[1] * 0.1
+
+
+# ----------------------------------------------------------------------------- config C0
+def test_config0_against_constructed_svd():
+    """C0 (512^2, rank 20, noise 1e-8): result within noise of the constructed factors."""
+    w = synth.config0(0)
+    U, s, Vt, r = oracle.hsvd(w.A, w.p, w.q, w.k, w.tol)
+    assert r == 20
+    assert metrics.e_sigma(s[:r], w.meta["sigma"]) <= 1e-6
+    assert metrics.e_frob(U[:, :r], s[:r], Vt[:r].T, w.meta["U"], w.meta["sigma"],
+                          w.meta["V"]) <= 1e-5
+
+
+def test_flop_model_bound():
+    """Section 3.1: for k <= s the flop total stays below 20 m n^2/P + 192 n^3/P^2."""
+    for (m, n, P, k) in [(132098, 1024, 64, 16), (10000, 400, 4, 50), (66049, 1024, 16, 64)]:
+        f = oracle.flop_model(m, n, P, k)
+        assert f["blocks"] + f["merges"] < f["bound"]
+        assert f["bound"] < f["full_svd"]
+
+
+# ----------------------------------------------------------------------------- metrics pins
+def test_metrics_closed_forms():
+    """sin_theta of a known rotation angle; e_frob of a known perturbation."""
+    th = 1e-11
+    U = np.array([[1.0], [0.0], [0.0]])
+    Uh = np.array([[np.cos(th)], [np.sin(th)], [0.0]])
+    assert abs(metrics.sin_theta(Uh, U) - np.sin(th)) <= 1e-20
+    rng = np.random.default_rng(0)
+    U = synth.orth(rng, 20, 3)
+    V = synth.orth(rng, 15, 3)
+    s = np.array([3.0, 2.0, 1.0])
+    s2 = s.copy()
+    s2[2] += 1e-12
+    # ||U diag(ds) V^T||_F = 1e-12, ||s|| = sqrt(14); the factored form resolves
+    # differences down to ~eps*||s||
+    assert abs(metrics.e_frob(U, s2, V, U, s, V) - 1e-12 / np.sqrt(14)) <= 1e-15
+    assert metrics.e_sigma([3, 2, 1 + 3e-12], s) == pytest.approx(1e-12, rel=1e-3)
+
+
+# ----------------------------------------------------------------------------- merge pin
+def _merge_pin(merge_fn, seed=61):
+    """Merge of two exact column blocks of X = U diag(sigma) V^T (constructed) must
+    return sigma and span(U): Section 3 column-split identity without truncation."""
+    rng = np.random.default_rng(seed)
+    h, w1, w2 = 50, 7, 6
+    sigma = np.linspace(4.0, 0.5, 8)
+    X, U0, s0, V0 = synth.low_rank(rng, h, w1 + w2, sigma)
+    U1, s1 = oracle.leaf(X[:, :w1], w1, 0.0, "gamma")
+    U2, s2 = oracle.leaf(X[:, w1:], w2, 0.0, "gamma")
+    U, s = merge_fn(U1, s1, U2, s2, 20, 0.0, "gamma")
+    return (s.size == 8 and metrics.e_sigma(s, s0) <= 1e-13
+            and metrics.sin_theta(U, U0) <= 1e-12)
+
+
+def test_merge_matches_constructed_svd():
+    assert _merge_pin(oracle.merge)
+    assert _merge_pin(lambda *a: oracle.merge_complement(*a)[:2])
+
+
+def _pipeline_pin(merge_fn):
+    rng = np.random.default_rng(77)
+    A, U0, s0, V0 = synth.low_rank(rng, 120, 110, np.array([5.0, 3.0, 2.0, 1.0]))
+    U, s, Vt, r = oracle.hsvd(A, 2, 3, 6, merge_fn=merge_fn)
+    return (r == 4 and metrics.e_sigma(s[:r], s0) <= 1e-12
+            and metrics.e_frob(U[:, :r], s[:r], Vt[:r].T, U0, s0, V0) <= 1e-12)
+
+
+# ----------------------------------------------------------------------------- planted mistakes
+def _mutants():
+    def drop_sigma2(U1, s1, U2, s2, k, tol, rule):          # dropped term: S2 not applied
+        return oracle.merge(U1, s1, U2, np.ones_like(s2), k, tol, rule)
+
+    def complement_sign(U1, s1, U2, s2, k, tol, rule):      # wrong sign: Q = U2 + U1 C
+        C = U1.T @ U2
+        Uo, R = np.linalg.qr(U2 + U1 @ C)
+        k1, k2 = s1.size, s2.size
+        E = np.zeros((k1 + k2, k1 + k2))
+        E[:k1, :k1] = np.diag(s1)
+        E[:k1, k1:] = C * s2
+        E[k1:, k1:] = R * s2
+        UE, sE, _ = np.linalg.svd(E)
+        r = oracle.truncation_rank(sE, k, tol, rule, (U1.shape[0], k1 + k2))
+        return (np.hstack([U1, Uo]) @ UE)[:, :r], sE[:r]
+
+    def transposed_C(U1, s1, U2, s2, k, tol, rule):         # transposed operand U2^T U1
+        C = (U2.T @ U1)[:s1.size, :s2.size] if s1.size == s2.size else U1.T @ U2 * 0
+        Uo, R = np.linalg.qr(U2 - U1 @ C)
+        k1, k2 = s1.size, s2.size
+        E = np.zeros((k1 + k2, k1 + k2))
+        E[:k1, :k1] = np.diag(s1)
+        E[:k1, k1:] = C * s2
+        E[k1:, k1:] = R * s2
+        UE, sE, _ = np.linalg.svd(E)
+        r = oracle.truncation_rank(sE, k, tol, rule, (U1.shape[0], k1 + k2))
+        return (np.hstack([U1, Uo]) @ UE)[:, :r], sE[:r]
+
+    def right_vectors(U1, s1, U2, s2, k, tol, rule):        # keeps V instead of U
+        F = np.hstack([U1 * s1, U2 * s2])
+        _, s, Vt = np.linalg.svd(F, full_matrices=False)
+        r = oracle.truncation_rank(s, k, tol, rule, F.shape)
+        Vpad = np.zeros((U1.shape[0], r))
+        m = min(U1.shape[0], Vt.shape[1])
+        Vpad[:m] = Vt[:r, :m].T
+        return Vpad, s[:r]
+
+    def shifted_truncation(U1, s1, U2, s2, k, tol, rule):   # off-by-one index in the rule
+        U, s = oracle.merge(U1, s1, U2, s2, k + 1, tol, rule)
+        return U[:, 1:], s[1:]
+
+    return [drop_sigma2, complement_sign, transposed_C, right_vectors, shifted_truncation]
+
+
+@pytest.mark.parametrize("mutant", _mutants(), ids=lambda f: f.__name__)
+def test_planted_mistakes_are_caught(mutant):
+    """Each plausible slip in a merge fails the merge pin or the pipeline pin."""
+    assert _pipeline_pin(oracle.merge)
+    assert not (_merge_pin(mutant) and _pipeline_pin(mutant))
