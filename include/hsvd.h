@@ -1,0 +1,128 @@
+/*
+ * hsvd.h -- C ABI of the MI355X (gfx950) hierarchical merge-and-truncate SVD.
+ *
+ * Method: Vasudevan & Ramakrishna, "A Hierarchical Singular Value Decomposition
+ * Algorithm for Low Rank Matrices" (arXiv:1710.02812), Section 3, Algorithm 1,
+ * followed by the left-vector projection of Section 3 and optionally
+ * Algorithm 2 (iterative improvement).
+ *
+ * Problem statement (Algorithm 1 inputs): a matrix X (m x n), a block grid and the
+ * truncation parameter gamma.  Here the grid is given as counts: p row slabs and
+ * q column slices; rows and columns are split as evenly as possible (the first
+ * m mod p slabs one row taller, likewise columns).  gamma is `tol`; `k` caps
+ * every kept rank (the fixed-rank variant of Section 3.1).  Outputs are the
+ * approximate leading singular triplets: U (m x k), S (k), Vt (k x n).
+ *
+ * Conventions for every function:
+ *   - Every call returns an hsvd_status; nothing throws across the ABI.
+ *   - A non-OK return stores a message retrievable with hsvd_last_error()
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Argument errors are detected on the host, return HSVD_ERR_INVALID and
+ *     have no side effects.
+ *   - Pointers named A, U, S, Vt are DEVICE pointers owned by the caller
+ *     (e.g. torch tensor data pointers on the ROCm device).  Pointers ending in
+ *     _host are host pointers owned by the caller.
+ *   - A plan owns the device workspace it allocates at plan time and frees it in
+ *     hsvd_destroy.  Plans are immutable after creation; one plan must not run
+ *     on two streams at once.
+ */
+#ifndef HSVD_H
+#define HSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsvd_plan_st* hsvd_plan_t;
+
+typedef enum {
+    HSVD_OK = 0,
+    HSVD_ERR_INVALID = 1,      /* bad argument (host-side check; no side effects)      */
+    HSVD_ERR_ALLOC = 2,        /* device or host allocation failed                      */
+    HSVD_ERR_HIP = 3,          /* a HIP runtime call failed (see hsvd_last_error)       */
+    HSVD_ERR_NONFINITE = 4,    /* reserved: reported through hsvd_get_status flags      */
+    HSVD_ERR_NOCONV = 5,       /* reserved: reported through hsvd_get_status flags      */
+    HSVD_ERR_UNSUPPORTED = 6   /* valid request this build does not implement           */
+} hsvd_status;
+
+/* Storage and arithmetic of the passes over A.
+ *   FP64: A, U, S, Vt are double; all arithmetic float64.
+ *   FP32: A, U, S, Vt are float; the products with A run in float32 with float32
+ *         accumulation; factor panels, QR and the Jacobi cores are float64.      */
+typedef enum { HSVD_FP64 = 0, HSVD_FP32 = 1 } hsvd_precision;
+
+/* Truncation rule (Section 3): GAMMA keeps s_i >= tol * s_1 of the matrix being
+ * truncated; FROB keeps the shortest prefix whose discarded energy
+ * sum_{i>=r} s_i^2 is <= tol^2 * sum_i s_i^2.  Both cap r <= k and drop values at
+ * or below the numerical-zero floor max(rows, cols) * 2^-52 * s_1.              */
+typedef enum { HSVD_RULE_GAMMA = 0, HSVD_RULE_FROB = 1 } hsvd_rule;
+
+typedef struct {
+    int32_t  precision;     /* hsvd_precision, default HSVD_FP64                        */
+    int32_t  rule;          /* hsvd_rule, default HSVD_RULE_GAMMA                       */
+    int32_t  oversample;    /* leaf sketch width l = k + oversample (capped by the block
+                               sides), default 14                                       */
+    int32_t  power_steps;   /* extra products with A per leaf after sketch and
+                               projection (0 = sketch + one projection), default 1     */
+    int32_t  refine_steps;  /* iterations of Algorithm 2 after the projection, default 0 */
+    int32_t  max_sweeps;    /* Jacobi sweep cap per core, default 40                    */
+    uint64_t seed;          /* seed of the leaves' Gaussian test matrices, default 0    */
+} hsvd_options;
+
+/* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
+#define HSVD_FLAG_NONFINITE 0x1u   /* a core matrix held NaN or Inf                        */
+#define HSVD_FLAG_NOCONV    0x2u   /* a Jacobi core hit max_sweeps before convergence      */
+
+/* Fills *opt with the defaults listed above. */
+hsvd_status hsvd_default_options(hsvd_options* opt);
+
+/* Creates a plan for an m x n input on a p x q grid, rank cap k, truncation tol.
+ *   Requires 1 <= p <= m, 1 <= q <= n, 1 <= k <= min(m, n), 0 <= tol < 1, out != NULL.
+ *   k may exceed a block side: leaf ranks are capped by min(block rows, block cols).
+ *   Allocates the device workspace on the current HIP device and generates the
+ *   leaves' Gaussian test matrices there (synchronously).  Uses default options. */
+hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
+                      int32_t k, double tol);
+
+/* As hsvd_plan with explicit options (opt == NULL means defaults). */
+hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
+                         int32_t k, double tol, const hsvd_options* opt);
+
+/* Runs the method on A and writes the result.  Asynchronous, ordered on `stream`
+ * (0 = the null stream); no host synchronisation inside.
+ *   A  : m x n, row-major, contiguous (leading dimension n), read only.
+ *   U  : m x k, row-major.   S : k, descending.   Vt : k x n, row-major.
+ *   Element type double (FP64 plans) or float (FP32 plans).
+ *   The effective rank r <= k is kept on the device (hsvd_get_rank); columns of U,
+ *   entries of S and rows of Vt at index >= r are written as zero.
+ *   Signs: each column u_i has its largest-magnitude entry positive (ties: lowest
+ *   row index), with v_i flipped alike.
+ *   A, U, S, Vt must not overlap.                                               */
+hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
+                         hipStream_t stream);
+
+/* Frees the plan and its workspace after synchronising its last stream.
+ * plan == NULL is accepted and does nothing. */
+hsvd_status hsvd_destroy(hsvd_plan_t plan);
+
+/* Copies the effective rank of the last execute to *r_host (synchronises that
+ * execute's stream). */
+hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host);
+
+/* Copies the status flags of the last execute to *flags_host (synchronises). */
+hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
+
+/* Device workspace owned by the plan, in bytes. */
+hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* hsvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSVD_H */

@@ -1,0 +1,42 @@
+/*
+ * hsvd_debug.h -- kernel-level entry points of libhsvd for parity tests.
+ *
+ * They run one building block of the hierarchical SVD on caller data so that
+ * each kernel can be checked against a CPU reference on its own.  Same
+ * conventions as hsvd.h: hsvd_status returns, hsvd_last_error() messages,
+ * device pointers owned by the caller, asynchronous on `stream`, float64
+ * col-major matrices stored back to back for a batch.  Each call allocates and
+ * frees its own scratch (it synchronises `stream` before freeing).
+ */
+#ifndef HSVD_DEBUG_H
+#define HSVD_DEBUG_H
+#include "hsvd.h"
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One-sided Jacobi SVD of `batch` dense n x n matrices M (n <= 128).
+ * Writes the left singular vectors U (n x n, columns by descending sigma),
+ * S (n, descending) and, when V != NULL (then n <= 64), the right singular
+ * vectors V (n x n), so that M = U diag(S) V^T.  Columns with sigma = 0 are 0.
+ * *flags_host (may be NULL) receives the status flags (HSVD_FLAG_*).          */
+hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double* U, double* S,
+                              double* V, int32_t max_sweeps, uint32_t* flags_host,
+                              hipStream_t stream);
+
+/* Builds and bounds-checks a plan on the host only (no device work): every task
+ * of every launch is checked against the workspace and A.  *workspace_bytes (may be
+ * NULL) receives the float64 arena size.  Returns what hsvd_plan_ex would return
+ * for the arguments, short of device allocation. */
+hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                                  double tol, const hsvd_options* opt, size_t* workspace_bytes);
+
+/* Householder TSQR of `batch` h x w panels P (w <= 96): Q (h x w, orthonormal
+ * columns) and R (w x w upper triangular) with P = Q R.  P is not modified.   */
+hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
+                            double* R, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,5 +1,8 @@
 """MI355X-native hierarchical merge-and-truncate truncated SVD (arXiv:1710.02812).
 
-The compute path is the HIP library ``libhsvd.so`` built from ``csrc/``; this
-package only marshals arguments to its C ABI (see ``hsvd.py``).
+The compute path is the HIP library ``libhsvd.so`` built from ``csrc/``; the
+``hsvd`` module only marshals arguments to its C ABI.  ``synth`` holds the
+seeded synthetic workloads.
 """
+from .hsvd import (Plan, svd, HsvdError, FP64, FP32, RULE_GAMMA, RULE_FROB,  # noqa: F401
+                   FLAG_NONFINITE, FLAG_NOCONV)

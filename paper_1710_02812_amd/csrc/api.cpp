@@ -1,0 +1,1091 @@
+// C ABI and plan construction for the hierarchical MAT SVD (arXiv:1710.02812).
+//
+// A plan fixes everything that does not depend on the values of A: the balanced
+// p x q partition (Algorithm 1 slicing, with the grid given as counts), the
+// pairwise merge schedule of both trees (Algorithm 1, DoMergeOfSlices: neighbours
+// (0,1), (2,3), ... left to right, an odd last node carried up), the layout of
+// every panel in one device arena, and the task tables of each launch.  Ranks
+// chosen by the truncation rule stay on the device; kernels read them, so an
+// execute is a fixed sequence of launches with no host round trip.
+//
+// Execute = the stages below, in order:
+//   leaves      : Y = A_b Omega, then alternately QR and products with A_b^T / A_b
+//                 (randomised range finder with power steps), QR of the last
+//                 product, Jacobi core -> (U_b, s_b, r_b) per block;
+//   column tree : per level, for all slabs at once: CGS2 projection coefficients
+//                 C = U1^T U2, complement Q = U2 - U1 C (twice), TSQR of Q,
+//                 Jacobi core of E = [[S1, C S2],[0, R S2]], U = U1 T + Q X;
+//   re-project  : W_i^T = A_i^T U_i, TSQR, Jacobi -> (V_i, s_i) (Algorithm 1);
+//   row tree    : the same merge on the V panels (height n);
+//   projection  : Y = A V (split over column blocks), TSQR, Jacobi with rotations
+//                 -> U = Q_Y Z, V = V J (Section 3, left vectors by projection);
+//   refinement  : optional Algorithm 2 iterations;
+//   output      : sign normalisation and the row-major U, S, Vt writes.
+#include "../../include/hsvd.h"
+#include "hsvd_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace hsvd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hsvd_status fail(hsvd_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+}  // namespace
+
+namespace hsvd_detail {
+hsvd_status set_error(hsvd_status st, const std::string& msg) { return fail(st, msg); }
+}
+
+namespace {
+
+hsvd_status hip_fail(hipError_t e, const char* what) {
+    return fail(HSVD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE };
+
+struct Stage {
+    StageKind kind;
+    int op = 0;          // gemm op
+    int n = 0;           // tiles / chunks / tasks
+    int w = 0, ch = 0, c = 0, N = 0;
+    int maxdim = 0, with_v = 0;
+    size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
+};
+
+int pow2floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+int tsqr_chunk(int w, int c) {
+    const int mx = std::max(w, c);
+    int ch = std::min(1024, pow2floor(std::max(1, 16384 / std::max(mx, 1))));
+    if (ch < mx) ch = mx;
+    return ch;
+}
+
+constexpr int THIN_CH = 256;
+
+}  // namespace
+
+struct hsvd_plan_st {
+    int64_t m = 0, n = 0;
+    int p = 0, q = 0, k = 0;
+    double tol = 0.0;
+    hsvd_options opt{};
+    int W = 0, L = 0, g = 0;
+    std::vector<int64_t> rs, cs;   // split points
+
+    // arenas (host-side bookkeeping)
+    int64_t ws_elems = 0;
+    int iws_elems = 0;
+    std::vector<unsigned char> blob;
+    std::vector<Stage> stages;
+    std::vector<std::pair<int64_t, std::vector<double>>> ws_init;   // constant panels
+    std::vector<std::pair<int64_t, double>> ws_fill;                  // (off, count) zero fills
+    std::vector<std::pair<int64_t, int64_t>> zero_ranges;
+    int64_t omega_off = 0, omega_count = 0;
+
+    // device
+    int device = 0;
+    double* ws = nullptr;
+    int* iws = nullptr;
+    unsigned* flags = nullptr;
+    void* dblob = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool executed = false;
+
+    // final
+    OutputArgs out{};
+    int rank_slot = -1;
+
+    int64_t alloc(int64_t elems) {
+        const int64_t off = ws_elems;
+        ws_elems += (elems + 31) / 32 * 32;
+        return off;
+    }
+    int ialloc(int count) {
+        const int off = iws_elems;
+        iws_elems += count;
+        return off;
+    }
+    template <typename T>
+    size_t put(const std::vector<T>& v) {
+        size_t off = (blob.size() + 255) / 256 * 256;
+        blob.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+    int64_t brow(int i) const { return rs[i + 1] - rs[i]; }
+    int64_t bcol(int j) const { return cs[j + 1] - cs[j]; }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ schedule builders
+struct Node {            // a factor node: panel (h x W, ld), sigma (W), rank slot
+    int64_t panel, sig;
+    int ld, h, rank;
+};
+
+struct TsqrBuild {
+    std::vector<TsqrTask> tasks;
+    std::vector<ChunkRef> chunks;
+};
+
+// Adds TSQR bookkeeping for a panel; returns index into tb.tasks.
+int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w, int ch) {
+    TsqrTask t{};
+    t.p_off = panel;
+    t.h = h;
+    t.p_ld = ld;
+    t.nch = (h + ch - 1) / ch;
+    t.chunk0 = (int)tb.chunks.size();
+    int nodes = 0, levels = 0;
+    for (int nn = t.nch;; nn = (nn + 1) >> 1) {
+        nodes += nn;
+        if (nn == 1) break;
+        ++levels;
+    }
+    t.levels = levels;
+    t.store_off = P.alloc((int64_t)nodes * (3LL * w * w + w));
+    t.cnt_off = P.ialloc(nodes);
+    t.r_out = P.alloc((int64_t)w * w);
+    for (int c = 0; c < t.nch; ++c) tb.chunks.push_back({(int)tb.tasks.size(), c});
+    tb.tasks.push_back(t);
+    return (int)tb.tasks.size() - 1;
+}
+
+void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
+    Stage s{};
+    s.kind = ST_TSQR_F;
+    s.n = (int)tb.chunks.size();
+    s.w = w;
+    s.ch = ch;
+    s.tasks_off = P.put(tb.tasks);
+    s.refs_off = P.put(tb.chunks);
+    P.stages.push_back(s);
+}
+
+// Apply stage for tasks applying the factors of `tb` (one ApplyTask per tsqr task, in order).
+void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<ApplyTask>& at,
+                     int w, int ch, int c) {
+    Stage s{};
+    s.kind = ST_TSQR_A;
+    s.n = (int)tb.chunks.size();
+    s.w = w;
+    s.ch = ch;
+    s.c = c;
+    s.tsqr_off = P.put(tb.tasks);
+    s.tasks_off = P.put(at);
+    s.refs_off = P.put(tb.chunks);   // chunk.task indexes both arrays
+    P.stages.push_back(s);
+}
+
+void push_gemm(hsvd_plan_st& P, int op, const std::vector<GemmTask>& tasks, int N) {
+    std::vector<TileRef> tiles;
+    const int nct = (N + 63) / 64;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+        const int out_rows = (op == 0) ? tasks[t].rows : tasks[t].cols;
+        const int nrt = (out_rows + 63) / 64;
+        for (int i = 0; i < nrt * nct; ++i) tiles.push_back({(int)t, i});
+    }
+    Stage s{};
+    s.kind = ST_GEMM;
+    s.op = op;
+    s.n = (int)tiles.size();
+    s.N = N;
+    s.tasks_off = P.put(tasks);
+    s.refs_off = P.put(tiles);
+    P.stages.push_back(s);
+}
+
+// Thin ops over row chunks: builds chunk refs for each task.
+void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks) {
+    std::vector<ChunkRef> chunks;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+        tasks[t].nch = (tasks[t].h + THIN_CH - 1) / THIN_CH;
+        tasks[t].chunk0 = (int)chunks.size();
+        if (kind != ST_REDUCE)
+            for (int c = 0; c < tasks[t].nch; ++c) chunks.push_back({(int)t, c});
+    }
+    Stage s{};
+    s.kind = kind;
+    s.n = (kind == ST_REDUCE) ? (int)tasks.size() : (int)chunks.size();
+    s.tasks_off = P.put(tasks);
+    s.refs_off = P.put(chunks);
+    P.stages.push_back(s);
+}
+
+void push_core(hsvd_plan_st& P, const std::vector<CoreTask>& tasks, int maxdim, int with_v) {
+    Stage s{};
+    s.kind = ST_CORE;
+    s.n = (int)tasks.size();
+    s.maxdim = maxdim;
+    s.with_v = with_v;
+    s.tasks_off = P.put(tasks);
+    P.stages.push_back(s);
+}
+
+CoreTask core_defaults(const hsvd_plan_st& P) {
+    CoreTask c{};
+    c.rank_in = -1;
+    c.u_off = c.t_off = c.v_off = -1;
+    c.rank1 = c.rank2 = -1;
+    c.kcap = P.k;
+    c.rule = P.opt.rule;
+    c.tol = P.tol;
+    c.floor_cols = -1;
+    c.fixed_rank_slot = -1;
+    return c;
+}
+
+// Identity (w x w) constant panel.
+int64_t identity_panel(hsvd_plan_st& P, int w) {
+    const int64_t off = P.alloc((int64_t)w * w);
+    std::vector<double> I((size_t)w * w, 0.0);
+    for (int i = 0; i < w; ++i) I[(size_t)i * w + i] = 1.0;
+    P.ws_init.push_back({off, I});
+    return off;
+}
+
+// One level of merges (all pairs of all trees at this level), in place of the
+// right operand's panel for the complement.
+std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node, Node>>& pairs) {
+    const int W = P.W;
+    const int chq = tsqr_chunk(W, W);
+    std::vector<Node> outs;
+    std::vector<ThinTask> gram1, red1, sub1, gram2, red2, sub2;
+    TsqrBuild tb;
+    std::vector<CoreTask> cores;
+    std::vector<ApplyTask> applies;
+    for (const auto& pr : pairs) {
+        const Node& a = pr.first;
+        const Node& b = pr.second;
+        const int h = a.h;
+        const int nch = (h + THIN_CH - 1) / THIN_CH;
+        const int64_t part = P.alloc((int64_t)nch * W * W);
+        const int64_t C1 = P.alloc((int64_t)W * W), C2 = P.alloc((int64_t)W * W);
+        const int64_t Cacc = P.alloc((int64_t)W * W);
+        ThinTask g{};
+        g.x_off = a.panel; g.x_ld = a.ld;
+        g.y_off = b.panel; g.y_ld = b.ld;
+        g.h = h; g.wx = W; g.wy = W;
+        g.part_off = part; g.acc_off = -1;
+        gram1.push_back(g);
+        ThinTask r = g;
+        r.c_off = C1; r.c_ld = W; r.acc_off = Cacc; r.accumulate = 0;
+        red1.push_back(r);
+        ThinTask sb{};
+        sb.x_off = a.panel; sb.x_ld = a.ld;
+        sb.y_off = b.panel; sb.y_ld = b.ld;
+        sb.c_off = C1; sb.c_ld = W;
+        sb.h = h; sb.wx = W; sb.wy = W; sb.accumulate = 2; sb.acc_off = -1;
+        sub1.push_back(sb);
+        gram2.push_back(g);
+        ThinTask r2 = r;
+        r2.c_off = C2; r2.accumulate = 1;
+        red2.push_back(r2);
+        ThinTask sb2 = sb;
+        sb2.c_off = C2;
+        sub2.push_back(sb2);
+
+        const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq);
+        Node o{};
+        o.h = h;
+        o.ld = a.ld;
+        o.panel = P.alloc((int64_t)o.ld * W);
+        o.sig = P.alloc(W);
+        o.rank = P.ialloc(1);
+        const int64_t T = P.alloc((int64_t)W * W), X = P.alloc((int64_t)W * W);
+        CoreTask c = core_defaults(P);
+        c.mode = CORE_MERGE;
+        c.s1_off = a.sig; c.s2_off = b.sig;
+        c.c_off = Cacc; c.c_ld = W;
+        c.r_off = tb.tasks[ti].r_out; c.r_ld = W;
+        c.rank1 = a.rank; c.rank2 = b.rank;
+        c.t_off = T; c.t_ld = W;
+        c.u_off = X; c.u_ld = W;
+        c.sig_off = o.sig;
+        c.out_w = W;
+        c.rank_out = o.rank;
+        c.floor_rows = h;
+        c.floor_cols = -1;
+        cores.push_back(c);
+        ApplyTask ap{};
+        ap.tsqr = ti;
+        ap.x_off = X;
+        ap.out_off = o.panel;
+        ap.out_ld = o.ld;
+        ap.add_u_off = a.panel;
+        ap.add_u_ld = a.ld;
+        ap.add_t_off = T;
+        ap.add_w = W;
+        applies.push_back(ap);
+        outs.push_back(o);
+    }
+    push_thin(P, ST_GRAM, gram1);
+    push_thin(P, ST_REDUCE, red1);
+    push_thin(P, ST_NN, sub1);
+    push_thin(P, ST_GRAM, gram2);
+    push_thin(P, ST_REDUCE, red2);
+    push_thin(P, ST_NN, sub2);
+    push_tsqr_factor(P, tb, W, chq);
+    push_core(P, cores, 2 * W, 0);
+    push_tsqr_apply(P, tb, applies, W, chq, W);
+    return outs;
+}
+
+// Runs the merge tree of several independent forests level by level.
+std::vector<Node> merge_forest(hsvd_plan_st& P, std::vector<std::vector<Node>> trees) {
+    for (;;) {
+        bool any = false;
+        std::vector<std::pair<Node, Node>> pairs;
+        std::vector<std::vector<int>> where(trees.size());
+        for (size_t t = 0; t < trees.size(); ++t) {
+            const auto& lv = trees[t];
+            if (lv.size() > 1) any = true;
+            for (size_t i = 0; i + 1 < lv.size(); i += 2) {
+                where[t].push_back((int)pairs.size());
+                pairs.push_back({lv[i], lv[i + 1]});
+            }
+        }
+        if (!any) break;
+        const std::vector<Node> outs = merge_level(P, pairs);
+        for (size_t t = 0; t < trees.size(); ++t) {
+            const auto& lv = trees[t];
+            if (lv.size() <= 1) continue;
+            std::vector<Node> nxt;
+            for (int idx : where[t]) nxt.push_back(outs[idx]);
+            if (lv.size() % 2) nxt.push_back(lv.back());
+            trees[t] = nxt;
+        }
+    }
+    std::vector<Node> roots;
+    for (auto& t : trees) roots.push_back(t[0]);
+    return roots;
+}
+
+// Leaves: randomised range finder with power steps, per block.
+std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
+    const int L = P.L, W = P.W, g = P.g;
+    const int p = P.p, q = P.q;
+    const int64_t brmax = P.brow(0), bcmax = P.bcol(0);
+    P.omega_count = bcmax * L;
+    P.omega_off = P.alloc(P.omega_count);
+    const int64_t I_L = identity_panel(P, L);
+
+    struct Leaf { int i, j; int64_t rowsz, colsz, aoff; int64_t Y, Z, Qy, Qz; };
+    std::vector<Leaf> leaves;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < q; ++j) {
+            Leaf l{};
+            l.i = i; l.j = j;
+            l.rowsz = P.brow(i);
+            l.colsz = P.bcol(j);
+            l.aoff = P.rs[i] * P.n + P.cs[j];
+            l.Y = P.alloc(brmax * L);
+            l.Z = P.alloc(bcmax * L);
+            l.Qy = P.alloc(brmax * L);
+            l.Qz = P.alloc(bcmax * L);
+            leaves.push_back(l);
+        }
+    // product t = 0: Y = A_b Omega
+    {
+        std::vector<GemmTask> gt;
+        for (auto& l : leaves) {
+            GemmTask t{};
+            t.a_off = l.aoff; t.rows = (int)l.rowsz; t.cols = (int)l.colsz;
+            t.x_off = P.omega_off; t.x_ld = (int)bcmax;
+            t.y_off = l.Y; t.y_ld = (int)brmax;
+            gt.push_back(t);
+        }
+        push_gemm(P, 0, gt, L);
+    }
+    const int ch = tsqr_chunk(L, std::max(L, W));
+    std::vector<int> last_tsqr(leaves.size());
+    TsqrBuild tb_last;
+    for (int t = 1; t <= g; ++t) {
+        // QR of the previous product (Y if t-1 even, Z if odd)
+        const bool prev_is_y = ((t - 1) % 2 == 0);
+        TsqrBuild tb;
+        for (auto& l : leaves) {
+            if (prev_is_y) add_tsqr(P, tb, l.Y, (int)l.rowsz, (int)brmax, L, ch);
+            else add_tsqr(P, tb, l.Z, (int)l.colsz, (int)bcmax, L, ch);
+        }
+        push_tsqr_factor(P, tb, L, ch);
+        if (t == g) { tb_last = tb; break; }
+        std::vector<ApplyTask> at;
+        for (size_t b = 0; b < leaves.size(); ++b) {
+            ApplyTask a{};
+            a.tsqr = (int)b;
+            a.x_off = I_L;
+            a.out_off = prev_is_y ? leaves[b].Qy : leaves[b].Qz;
+            a.out_ld = prev_is_y ? (int)brmax : (int)bcmax;
+            a.add_u_off = -1;
+            at.push_back(a);
+        }
+        push_tsqr_apply(P, tb, at, L, ch, L);
+        // next product
+        std::vector<GemmTask> gt;
+        for (auto& l : leaves) {
+            GemmTask x{};
+            x.a_off = l.aoff; x.rows = (int)l.rowsz; x.cols = (int)l.colsz;
+            if (prev_is_y) {            // Z = A_b^T Qy
+                x.x_off = l.Qy; x.x_ld = (int)brmax;
+                x.y_off = l.Z; x.y_ld = (int)bcmax;
+            } else {                    // Y = A_b Qz
+                x.x_off = l.Qz; x.x_ld = (int)bcmax;
+                x.y_off = l.Y; x.y_ld = (int)brmax;
+            }
+            gt.push_back(x);
+        }
+        push_gemm(P, prev_is_y ? 1 : 0, gt, L);
+    }
+    // core of the last product
+    const bool last_is_y = ((g - 1) % 2 == 0);
+    std::vector<CoreTask> cores;
+    std::vector<Node> nodes;
+    std::vector<int64_t> ur(leaves.size());
+    for (size_t b = 0; b < leaves.size(); ++b) {
+        const Leaf& l = leaves[b];
+        Node nd{};
+        nd.h = (int)l.rowsz;
+        nd.ld = (int)brmax;
+        nd.panel = P.alloc(brmax * W);
+        nd.sig = P.alloc(W);
+        nd.rank = P.ialloc(1);
+        nodes.push_back(nd);
+        ur[b] = P.alloc((int64_t)L * W);
+        CoreTask c = core_defaults(P);
+        c.mode = last_is_y ? CORE_UPPER : CORE_UPPER_T;
+        c.dim = L;
+        c.m_off = tb_last.tasks[b].r_out;
+        c.m_ld = L;
+        c.u_off = ur[b];
+        c.u_ld = L;
+        c.sig_off = nd.sig;
+        c.out_w = W;
+        c.rank_out = nd.rank;
+        c.floor_rows = (int)l.rowsz;
+        c.floor_cols = (int)l.colsz;
+        cores.push_back(c);
+    }
+    push_core(P, cores, L, 0);
+    if (last_is_y) {
+        std::vector<ApplyTask> at;
+        for (size_t b = 0; b < leaves.size(); ++b) {
+            ApplyTask a{};
+            a.tsqr = (int)b;
+            a.x_off = ur[b];
+            a.out_off = nodes[b].panel;
+            a.out_ld = nodes[b].ld;
+            a.add_u_off = -1;
+            at.push_back(a);
+        }
+        push_tsqr_apply(P, tb_last, at, L, ch, W);
+    } else {
+        std::vector<ThinTask> nn;
+        for (size_t b = 0; b < leaves.size(); ++b) {
+            ThinTask t{};
+            t.x_off = leaves[b].Qy; t.x_ld = (int)brmax;
+            t.c_off = ur[b]; t.c_ld = L;
+            t.y_off = nodes[b].panel; t.y_ld = nodes[b].ld;
+            t.h = (int)leaves[b].rowsz; t.wx = L; t.wy = W;
+            t.accumulate = 0; t.acc_off = -1;
+            nn.push_back(t);
+        }
+        push_thin(P, ST_NN, nn);
+    }
+    std::vector<std::vector<Node>> slabs(p);
+    for (size_t b = 0; b < leaves.size(); ++b) slabs[leaves[b].i].push_back(nodes[b]);
+    return slabs;
+}
+
+// Slab re-projection: V_i, s_i = SVD(U_i^T A_i).
+std::vector<Node> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& roots) {
+    const int W = P.W;
+    const int n = (int)P.n;
+    const int ch = tsqr_chunk(W, W);
+    std::vector<GemmTask> gt;
+    TsqrBuild tb;
+    std::vector<int64_t> Zs(roots.size());
+    for (size_t i = 0; i < roots.size(); ++i) {
+        Zs[i] = P.alloc((int64_t)n * W);
+        GemmTask t{};
+        t.a_off = P.rs[i] * P.n;
+        t.rows = (int)P.brow((int)i);
+        t.cols = n;
+        t.x_off = roots[i].panel; t.x_ld = roots[i].ld;
+        t.y_off = Zs[i]; t.y_ld = n;
+        gt.push_back(t);
+    }
+    push_gemm(P, 1, gt, W);
+    for (size_t i = 0; i < roots.size(); ++i) add_tsqr(P, tb, Zs[i], n, n, W, ch);
+    push_tsqr_factor(P, tb, W, ch);
+    std::vector<CoreTask> cores;
+    std::vector<ApplyTask> at;
+    std::vector<Node> out;
+    for (size_t i = 0; i < roots.size(); ++i) {
+        Node nd{};
+        nd.h = n;
+        nd.ld = n;
+        nd.panel = P.alloc((int64_t)n * W);
+        nd.sig = P.alloc(W);
+        nd.rank = P.ialloc(1);
+        const int64_t X = P.alloc((int64_t)W * W);
+        CoreTask c = core_defaults(P);
+        c.mode = CORE_UPPER;
+        c.dim = W;
+        c.m_off = tb.tasks[i].r_out;
+        c.m_ld = W;
+        c.rank_in = roots[i].rank;
+        c.u_off = X;
+        c.u_ld = W;
+        c.sig_off = nd.sig;
+        c.out_w = W;
+        c.rank_out = nd.rank;
+        c.floor_rows = n;
+        c.floor_cols = 0;
+        cores.push_back(c);
+        ApplyTask a{};
+        a.tsqr = (int)i;
+        a.x_off = X;
+        a.out_off = nd.panel;
+        a.out_ld = n;
+        a.add_u_off = -1;
+        at.push_back(a);
+        out.push_back(nd);
+    }
+    push_core(P, cores, W, 0);
+    push_tsqr_apply(P, tb, at, W, ch, W);
+    return out;
+}
+
+struct Factors { int64_t U, V, sig; int rank; };
+
+// Left vectors by projection: Y = A V (split over column blocks), TSQR(Y) = Q R,
+// Jacobi on R (with rotations J): U = Q Z, V <- V J.
+Factors build_projection(hsvd_plan_st& P, int64_t Vpanel, int vld, int rank_slot) {
+    const int W = P.W;
+    const int64_t m = P.m, n = P.n;
+    const int ch = tsqr_chunk(W, W);
+    const int64_t parts = P.alloc((int64_t)P.q * m * W);
+    std::vector<GemmTask> gt;
+    for (int i = 0; i < P.p; ++i)
+        for (int j = 0; j < P.q; ++j) {
+            GemmTask t{};
+            t.a_off = P.rs[i] * n + P.cs[j];
+            t.rows = (int)P.brow(i);
+            t.cols = (int)P.bcol(j);
+            t.x_off = Vpanel + P.cs[j];
+            t.x_ld = vld;
+            t.y_off = parts + (int64_t)j * m * W + P.rs[i];
+            t.y_ld = (int)m;
+            gt.push_back(t);
+        }
+    push_gemm(P, 0, gt, W);
+    const int64_t Y = P.alloc(m * W);
+    {
+        ThinTask s{};
+        s.x_off = parts; s.x_ld = (int)m;
+        s.c_ld = (int)(m * W);      // stride between partials
+        s.wx = P.q; s.wy = W;
+        s.y_off = Y; s.y_ld = (int)m;
+        s.h = (int)m;
+        s.acc_off = -1;
+        push_thin(P, ST_SUM, {s});
+    }
+    TsqrBuild tb;
+    add_tsqr(P, tb, Y, (int)m, (int)m, W, ch);
+    push_tsqr_factor(P, tb, W, ch);
+    Factors f{};
+    f.U = P.alloc(m * W);
+    f.V = P.alloc(n * W);
+    f.sig = P.alloc(W);
+    f.rank = P.ialloc(1);
+    const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
+    CoreTask c = core_defaults(P);
+    c.mode = CORE_UPPER;
+    c.dim = W;
+    c.m_off = tb.tasks[0].r_out;
+    c.m_ld = W;
+    c.rank_in = rank_slot;
+    c.u_off = X; c.u_ld = W;
+    c.v_off = J; c.v_ld = W;
+    c.sig_off = f.sig;
+    c.out_w = W;
+    c.rank_out = f.rank;
+    c.floor_rows = (int)m;
+    c.floor_cols = -1;
+    c.fixed_rank_slot = rank_slot;
+    push_core(P, {c}, W, 1);
+    ApplyTask a{};
+    a.tsqr = 0;
+    a.x_off = X;
+    a.out_off = f.U;
+    a.out_ld = (int)m;
+    a.add_u_off = -1;
+    push_tsqr_apply(P, tb, {a}, W, ch, W);
+    ThinTask nn{};
+    nn.x_off = Vpanel; nn.x_ld = vld;
+    nn.c_off = J; nn.c_ld = W;
+    nn.y_off = f.V; nn.y_ld = (int)n;
+    nn.h = (int)n; nn.wx = W; nn.wy = W;
+    nn.accumulate = 0; nn.acc_off = -1;
+    push_thin(P, ST_NN, {nn});
+    return f;
+}
+
+// One Algorithm 2 step from (U_i = left vectors of A V): W^T = A^T U_i = Q R;
+// Jacobi on R with rotations J: V~ = Q Z, U^ = U_i J, S~.
+Factors build_refine_step(hsvd_plan_st& P, const Factors& in) {
+    const int W = P.W;
+    const int64_t m = P.m, n = P.n;
+    const int ch = tsqr_chunk(W, W);
+    const int64_t parts = P.alloc((int64_t)P.p * n * W);
+    std::vector<GemmTask> gt;
+    for (int i = 0; i < P.p; ++i) {
+        GemmTask t{};
+        t.a_off = P.rs[i] * n;
+        t.rows = (int)P.brow(i);
+        t.cols = (int)n;
+        t.x_off = in.U + P.rs[i];
+        t.x_ld = (int)m;
+        t.y_off = parts + (int64_t)i * n * W;
+        t.y_ld = (int)n;
+        gt.push_back(t);
+    }
+    push_gemm(P, 1, gt, W);
+    const int64_t Z = P.alloc(n * W);
+    {
+        ThinTask s{};
+        s.x_off = parts; s.x_ld = (int)n;
+        s.c_ld = (int)(n * W);
+        s.wx = P.p; s.wy = W;
+        s.y_off = Z; s.y_ld = (int)n;
+        s.h = (int)n;
+        s.acc_off = -1;
+        push_thin(P, ST_SUM, {s});
+    }
+    TsqrBuild tb;
+    add_tsqr(P, tb, Z, (int)n, (int)n, W, ch);
+    push_tsqr_factor(P, tb, W, ch);
+    Factors f{};
+    f.U = P.alloc(m * W);
+    f.V = P.alloc(n * W);
+    f.sig = P.alloc(W);
+    f.rank = P.ialloc(1);
+    const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
+    CoreTask c = core_defaults(P);
+    c.mode = CORE_UPPER;
+    c.dim = W;
+    c.m_off = tb.tasks[0].r_out;
+    c.m_ld = W;
+    c.rank_in = in.rank;
+    c.u_off = X; c.u_ld = W;
+    c.v_off = J; c.v_ld = W;
+    c.sig_off = f.sig;
+    c.out_w = W;
+    c.rank_out = f.rank;
+    c.floor_rows = (int)n;
+    c.floor_cols = -1;
+    c.fixed_rank_slot = in.rank;
+    push_core(P, {c}, W, 1);
+    ApplyTask a{};
+    a.tsqr = 0;
+    a.x_off = X;
+    a.out_off = f.V;
+    a.out_ld = (int)n;
+    a.add_u_off = -1;
+    push_tsqr_apply(P, tb, {a}, W, ch, W);
+    ThinTask nn{};
+    nn.x_off = in.U; nn.x_ld = (int)m;
+    nn.c_off = J; nn.c_ld = W;
+    nn.y_off = f.U; nn.y_ld = (int)m;
+    nn.h = (int)m; nn.wx = W; nn.wy = W;
+    nn.accumulate = 0; nn.acc_off = -1;
+    push_thin(P, ST_NN, {nn});
+    return f;
+}
+
+hsvd_status build_plan(hsvd_plan_st& P) {
+    auto leaves = build_leaves(P);
+    auto col_roots = merge_forest(P, leaves);
+    auto slab_nodes = build_reprojection(P, col_roots);
+    auto row_root = merge_forest(P, {slab_nodes})[0];
+    Factors f = build_projection(P, row_root.panel, row_root.ld, row_root.rank);
+    for (int it = 0; it < P.opt.refine_steps; ++it) {
+        f = build_refine_step(P, f);
+        if (it + 1 < P.opt.refine_steps) f = build_projection(P, f.V, (int)P.n, f.rank);
+    }
+    P.out.u_off = f.U;
+    P.out.v_off = f.V;
+    P.out.sig_off = f.sig;
+    P.out.u_ld = (int)P.m;
+    P.out.v_ld = (int)P.n;
+    P.out.m = (int)P.m;
+    P.out.n = (int)P.n;
+    P.out.k = P.k;
+    P.out.rank_slot = f.rank;
+    P.out.sign_off = P.ialloc(P.k);
+    P.rank_slot = f.rank;
+    return HSVD_OK;
+}
+
+// Host-side bounds check of every task in every stage against the arenas and A:
+// each kernel's index range is recomputed here from the task fields, so a plan
+// whose footprint leaves its buffers is rejected before anything is launched.
+std::string validate_plan(const hsvd_plan_st& P) {
+    const int64_t WS = P.ws_elems, IW = P.iws_elems, AN = P.m * P.n;
+    const unsigned char* b = P.blob.data();
+    char msg[256];
+    auto span = [&](const char* what, int64_t off, int64_t last, int64_t lim) -> bool {
+        if (off < 0 || last >= lim) {
+            snprintf(msg, sizeof msg, "%s out of bounds: off=%lld last=%lld limit=%lld", what,
+                     (long long)off, (long long)last, (long long)lim);
+            return false;
+        }
+        return true;
+    };
+    auto panel = [&](const char* what, int64_t off, int64_t ld, int64_t rows, int64_t cols) {
+        if (rows <= 0 || cols <= 0) return true;
+        if (ld < rows) { snprintf(msg, sizeof msg, "%s: ld %lld < rows %lld", what, (long long)ld, (long long)rows); return false; }
+        return span(what, off, off + (cols - 1) * ld + rows - 1, WS);
+    };
+    for (size_t si = 0; si < P.stages.size(); ++si) {
+        const Stage& s = P.stages[si];
+        std::string err;
+        switch (s.kind) {
+            case ST_GEMM: {
+                const GemmTask* T = (const GemmTask*)(b + s.tasks_off);
+                const TileRef* R = (const TileRef*)(b + s.refs_off);
+                int ntask = 0;
+                for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
+                for (int i = 0; i < ntask; ++i) {
+                    const GemmTask& t = T[i];
+                    if (!span("gemm A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * P.n + t.cols - 1, AN)) return msg;
+                    if (t.cols > P.n || t.a_off % P.n + t.cols > P.n) return "gemm A block crosses a row";
+                    const int xr = s.op == 0 ? t.cols : t.rows, yr = s.op == 0 ? t.rows : t.cols;
+                    if (!panel("gemm X", t.x_off, t.x_ld, xr, s.N)) return msg;
+                    if (!panel("gemm Y", t.y_off, t.y_ld, yr, s.N)) return msg;
+                }
+                break;
+            }
+            case ST_TSQR_F:
+            case ST_TSQR_A: {
+                const TsqrTask* T = (const TsqrTask*)(b + (s.kind == ST_TSQR_F ? s.tasks_off : s.tsqr_off));
+                const ChunkRef* R = (const ChunkRef*)(b + s.refs_off);
+                int ntask = 0;
+                for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
+                if (s.w > 96 || s.ch < s.w || s.ch < s.c) return "tsqr geometry";
+                for (int i = 0; i < ntask; ++i) {
+                    const TsqrTask& t = T[i];
+                    int nodes = 0;
+                    for (int nn = t.nch;; nn = (nn + 1) >> 1) { nodes += nn; if (nn == 1) break; }
+                    if (t.nch != (t.h + s.ch - 1) / s.ch) return "tsqr chunk count";
+                    if (!panel("tsqr panel", t.p_off, t.p_ld, t.h, s.w)) return msg;
+                    if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * (3LL * s.w * s.w + s.w) - 1, WS)) return msg;
+                    if (!span("tsqr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
+                    if (!span("tsqr counters", t.cnt_off, t.cnt_off + nodes - 1, IW)) return msg;
+                    if (s.kind == ST_TSQR_A) {
+                        const ApplyTask& a = ((const ApplyTask*)(b + s.tasks_off))[i];
+                        if (a.tsqr != i) return "apply/tsqr order";
+                        if (!span("apply X", a.x_off, a.x_off + (int64_t)s.w * s.c - 1, WS)) return msg;
+                        if (!panel("apply out", a.out_off, a.out_ld, t.h, s.c)) return msg;
+                        if (a.add_u_off >= 0) {
+                            if (!panel("apply U1", a.add_u_off, a.add_u_ld, t.h, a.add_w)) return msg;
+                            if (!span("apply T", a.add_t_off, a.add_t_off + (int64_t)a.add_w * s.c - 1, WS)) return msg;
+                        }
+                    }
+                }
+                for (int i = 0; i < s.n; ++i)
+                    if (R[i].chunk < 0 || R[i].chunk >= T[R[i].task].nch) return "tsqr chunk ref";
+                break;
+            }
+            case ST_GRAM:
+            case ST_REDUCE:
+            case ST_NN:
+            case ST_SUM: {
+                const ThinTask* T = (const ThinTask*)(b + s.tasks_off);
+                int ntask = s.n;
+                if (s.kind != ST_REDUCE) {
+                    const ChunkRef* R = (const ChunkRef*)(b + s.refs_off);
+                    ntask = 0;
+                    for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
+                }
+                for (int i = 0; i < ntask; ++i) {
+                    const ThinTask& t = T[i];
+                    if (t.wx > 128 || t.wy > 128) return "thin width";
+                    if (s.kind == ST_GRAM) {
+                        if (!panel("gram X", t.x_off, t.x_ld, t.h, t.wx)) return msg;
+                        if (!panel("gram Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
+                        if (!span("gram part", t.part_off, t.part_off + (int64_t)t.nch * t.wx * t.wy - 1, WS)) return msg;
+                    } else if (s.kind == ST_REDUCE) {
+                        if (!span("reduce part", t.part_off, t.part_off + (int64_t)t.nch * t.wx * t.wy - 1, WS)) return msg;
+                        if (!panel("reduce C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
+                        if (t.acc_off >= 0 && !panel("reduce acc", t.acc_off, t.c_ld, t.wx, t.wy)) return msg;
+                    } else if (s.kind == ST_NN) {
+                        if (!panel("nn X", t.x_off, t.x_ld, t.h, t.wx)) return msg;
+                        if (!panel("nn C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
+                        if (!panel("nn Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
+                    } else {
+                        if (t.x_ld < t.h) return "sum ld";
+                        if (!span("sum parts", t.x_off, t.x_off + (int64_t)(t.wx - 1) * t.c_ld + (int64_t)(t.wy - 1) * t.x_ld + t.h - 1, WS)) return msg;
+                        if (!panel("sum Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
+                    }
+                }
+                break;
+            }
+            case ST_CORE: {
+                const CoreTask* T = (const CoreTask*)(b + s.tasks_off);
+                if (s.maxdim > 128 || (s.with_v && s.maxdim > 64)) return "core size";
+                for (int i = 0; i < s.n; ++i) {
+                    const CoreTask& t = T[i];
+                    const int W = P.W;
+                    if (t.mode == CORE_MERGE) {
+                        if (2 * W > s.maxdim) return "merge core exceeds maxdim";
+                        if (!span("core s1", t.s1_off, t.s1_off + W - 1, WS)) return msg;
+                        if (!span("core s2", t.s2_off, t.s2_off + W - 1, WS)) return msg;
+                        if (!panel("core C", t.c_off, t.c_ld, W, W)) return msg;
+                        if (!panel("core R", t.r_off, t.r_ld, W, W)) return msg;
+                        if (!span("core ranks", std::min(t.rank1, t.rank2), std::max(t.rank1, t.rank2), IW)) return msg;
+                        if (!panel("core T", t.t_off, t.t_ld, t.t_ld, t.out_w)) return msg;
+                        if (!panel("core X", t.u_off, t.u_ld, t.u_ld, t.out_w)) return msg;
+                        if (t.t_ld < W || t.u_ld < W) return "merge outputs too short";
+                    } else {
+                        if (t.dim > s.maxdim) return "core dim exceeds maxdim";
+                        if (!panel("core M", t.m_off, t.m_ld, t.dim, t.dim)) return msg;
+                        if (t.rank_in >= IW) return "core rank_in";
+                        if (t.u_off >= 0 && !panel("core U", t.u_off, t.u_ld, t.dim, t.out_w)) return msg;
+                        if (t.v_off >= 0 && (!s.with_v || !panel("core V", t.v_off, t.v_ld, t.dim, t.out_w))) return msg;
+                    }
+                    if (!span("core sigma", t.sig_off, t.sig_off + t.out_w - 1, WS)) return msg;
+                    if (t.rank_out >= IW || t.fixed_rank_slot >= IW) return "core rank slot";
+                }
+                break;
+            }
+        }
+    }
+    if (!panel("out U", P.out.u_off, P.out.u_ld, P.m, P.W)) return msg;
+    if (!panel("out V", P.out.v_off, P.out.v_ld, P.n, P.W)) return msg;
+    if (!span("out signs", P.out.sign_off, P.out.sign_off + P.k - 1, IW)) return msg;
+    if (!span("omega", P.omega_off, P.omega_off + P.omega_count - 1, WS)) return msg;
+    return "";
+}
+
+hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, const void* A, hipStream_t st) {
+    unsigned char* b = (unsigned char*)P.dblob;
+    hipError_t e = hipSuccess;
+    const int fp32 = P.opt.precision == HSVD_FP32;
+    switch (s.kind) {
+        case ST_GEMM:
+            e = launch_gemm(s.op, fp32, A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
+                            (const TileRef*)(b + s.refs_off), s.n, s.N, st);
+            break;
+        case ST_TSQR_F:
+            e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
+                                   (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
+            break;
+        case ST_TSQR_A:
+            e = launch_tsqr_apply(P.ws, (const TsqrTask*)(b + s.tsqr_off),
+                                  (const ApplyTask*)(b + s.tasks_off),
+                                  (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, s.c, st);
+            break;
+        case ST_GRAM:
+            e = launch_thin_gram(P.ws, (const ThinTask*)(b + s.tasks_off),
+                                 (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+            break;
+        case ST_REDUCE:
+            e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, st);
+            break;
+        case ST_NN:
+            e = launch_thin_nn(P.ws, (const ThinTask*)(b + s.tasks_off),
+                               (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+            break;
+        case ST_SUM:
+            e = launch_thin_sum(P.ws, (const ThinTask*)(b + s.tasks_off),
+                                (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+            break;
+        case ST_CORE:
+            e = launch_core(P.ws, P.iws, (const CoreTask*)(b + s.tasks_off), s.n, s.maxdim,
+                            P.opt.max_sweeps, P.flags, s.with_v, st);
+            break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return HSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hsvd_status hsvd_default_options(hsvd_options* opt) {
+    if (!opt) return fail(HSVD_ERR_INVALID, "opt is NULL");
+    opt->precision = HSVD_FP64;
+    opt->rule = HSVD_RULE_GAMMA;
+    opt->oversample = 14;
+    opt->power_steps = 1;
+    opt->refine_steps = 0;
+    opt->max_sweeps = 40;
+    opt->seed = 0;
+    return HSVD_OK;
+}
+
+static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
+                             int32_t k, double tol, const hsvd_options* opt, size_t* check_only) {
+    if (!out && !check_only) return fail(HSVD_ERR_INVALID, "out is NULL");
+    if (out) *out = nullptr;
+    if (m < 1 || n < 1) return fail(HSVD_ERR_INVALID, "m and n must be >= 1");
+    if (p < 1 || p > m) return fail(HSVD_ERR_INVALID, "need 1 <= p <= m");
+    if (q < 1 || q > n) return fail(HSVD_ERR_INVALID, "need 1 <= q <= n");
+    if (k < 1 || k > std::min(m, n)) return fail(HSVD_ERR_INVALID, "need 1 <= k <= min(m, n)");
+    if (!(tol >= 0.0 && tol < 1.0)) return fail(HSVD_ERR_INVALID, "need 0 <= tol < 1");
+    if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
+        return fail(HSVD_ERR_UNSUPPORTED, "m and n must be below 2^30");
+    hsvd_options o;
+    hsvd_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != HSVD_FP64 && o.precision != HSVD_FP32)
+        return fail(HSVD_ERR_INVALID, "unknown precision");
+    if (o.rule != HSVD_RULE_GAMMA && o.rule != HSVD_RULE_FROB)
+        return fail(HSVD_ERR_INVALID, "unknown rule");
+    if (o.oversample < 0 || o.power_steps < 0 || o.refine_steps < 0 || o.max_sweeps < 1)
+        return fail(HSVD_ERR_INVALID, "negative option");
+    if (k > 64) return fail(HSVD_ERR_UNSUPPORTED, "k > 64 is not supported by this build");
+
+    hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
+    if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
+    P->m = m; P->n = n; P->p = p; P->q = q; P->k = k; P->tol = tol; P->opt = o;
+    P->rs.resize(p + 1);
+    P->cs.resize(q + 1);
+    for (int i = 0; i <= p; ++i) P->rs[i] = (m / p) * i + std::min<int64_t>(i, m % p);
+    for (int j = 0; j <= q; ++j) P->cs[j] = (n / q) * j + std::min<int64_t>(j, n % q);
+    const int64_t bmin = std::min(m / p, n / q);
+    P->W = k;
+    P->L = (int)std::min<int64_t>(k + o.oversample, bmin);
+    if (P->L < 1) P->L = 1;
+    if (P->L > 96) P->L = 96;
+    P->g = 2 + o.power_steps;
+
+    build_plan(*P);
+    const std::string verr = validate_plan(*P);
+    if (!verr.empty()) { delete P; return fail(HSVD_ERR_INVALID, "plan validation: " + verr); }
+    if (check_only) {
+        *check_only = sizeof(double) * (size_t)P->ws_elems;
+        delete P;
+        return HSVD_OK;
+    }
+
+    hipError_t e = hipGetDevice(&P->device);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice"); }
+    e = hipMalloc(&P->ws, sizeof(double) * (size_t)std::max<int64_t>(P->ws_elems, 32));
+    if (e != hipSuccess) { delete P; return fail(HSVD_ERR_ALLOC, "workspace allocation failed"); }
+    e = hipMalloc(&P->iws, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
+    if (e == hipSuccess) e = hipMalloc(&P->flags, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = hipMalloc(&P->dblob, std::max<size_t>(P->blob.size(), 256));
+    if (e != hipSuccess) { hsvd_destroy(P); return fail(HSVD_ERR_ALLOC, "allocation failed"); }
+    e = hipMemcpy(P->dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(P->iws, 0, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
+    if (e == hipSuccess) e = hipMemset(P->flags, 0, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = hipMemset(P->ws, 0, sizeof(double) * (size_t)P->ws_elems);
+    for (auto& c : P->ws_init)
+        if (e == hipSuccess)
+            e = hipMemcpy(P->ws + c.first, c.second.data(), c.second.size() * sizeof(double),
+                          hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_gaussian(P->ws + P->omega_off, P->omega_count, o.seed, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { hsvd_destroy(P); return hip_fail(e, "plan initialisation"); }
+    *out = P;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                         double tol, const hsvd_options* opt) {
+    return plan_impl(out, m, n, p, q, k, tol, opt, nullptr);
+}
+
+hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k, double tol,
+                                  const hsvd_options* opt, size_t* workspace_bytes) {
+    size_t bytes = 0;
+    hsvd_status st = plan_impl(nullptr, m, n, p, q, k, tol, opt, &bytes);
+    if (workspace_bytes) *workspace_bytes = bytes;
+    return st;
+}
+
+hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                      double tol) {
+    return hsvd_plan_ex(out, m, n, p, q, k, tol, nullptr);
+}
+
+hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
+                         hipStream_t stream) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL data pointer");
+    hsvd_plan_st& P = *plan;
+    hipError_t e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * 4, stream);
+    if (e != hipSuccess) return hip_fail(e, "flags reset");
+    for (const Stage& s : P.stages) {
+        hsvd_status st = run_stage(P, s, A, stream);
+        if (st != HSVD_OK) return st;
+    }
+    e = launch_output(P.opt.precision == HSVD_FP32, P.ws, P.iws, P.out, U, S, Vt, stream);
+    if (e != hipSuccess) return hip_fail(e, "output launch");
+    P.last_stream = stream;
+    P.executed = true;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_destroy(hsvd_plan_t plan) {
+    if (!plan) return HSVD_OK;
+    if (plan->executed) hipStreamSynchronize(plan->last_stream);
+    if (plan->ws) hipFree(plan->ws);
+    if (plan->iws) hipFree(plan->iws);
+    if (plan->flags) hipFree(plan->flags);
+    if (plan->dblob) hipFree(plan->dblob);
+    delete plan;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host) {
+    if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(r_host, plan->iws + plan->rank_slot, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_get_rank");
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
+    if (!plan || !flags_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(flags_host, plan->flags, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_get_status");
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host) {
+    if (!plan || !bytes_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    *bytes_host = sizeof(double) * (size_t)plan->ws_elems + sizeof(int) * (size_t)plan->iws_elems +
+                  plan->blob.size();
+    return HSVD_OK;
+}
+
+const char* hsvd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

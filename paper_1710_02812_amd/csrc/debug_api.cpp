@@ -1,0 +1,160 @@
+// Kernel-level entry points (hsvd_debug.h): run the Jacobi core or the TSQR
+// factor/apply kernels on caller data, with a private scratch arena.
+#include "../../include/hsvd_debug.h"
+#include "hsvd_internal.hpp"
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+using namespace hsvd;
+
+extern "C" const char* hsvd_last_error(void);
+namespace hsvd_detail {
+hsvd_status set_error(hsvd_status st, const std::string& msg);
+}
+
+namespace {
+
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch() {
+        for (void* p : ptrs) hipFree(p);
+    }
+    template <typename T>
+    T* get(size_t count) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+};
+
+int pow2floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+}  // namespace
+
+extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double* U,
+                                         double* S, double* V, int32_t max_sweeps,
+                                         uint32_t* flags_host, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    if (!M || !U || !S || batch < 1 || n < 1 || n > 128 || (V && n > 64) || max_sweeps < 1)
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_jacobi: bad argument");
+    Scratch sc;
+    const int64_t nn = (int64_t)n * n;
+    // arena: copies of M | U | V | S
+    const int64_t offM = 0, offU = offM + batch * nn, offV = offU + batch * nn,
+                  offS = offV + batch * nn, tot = offS + (int64_t)batch * n;
+    double* ws = sc.get<double>(tot);
+    int* iws = sc.get<int>(batch);
+    unsigned* flags = sc.get<unsigned>(1);
+    CoreTask* dt = sc.get<CoreTask>(batch);
+    if (!ws || !iws || !flags || !dt) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    std::vector<CoreTask> tasks(batch);
+    for (int b = 0; b < batch; ++b) {
+        CoreTask c{};
+        c.mode = CORE_DENSE;
+        c.dim = n;
+        c.m_off = offM + b * nn;
+        c.m_ld = n;
+        c.rank_in = -1;
+        c.rank1 = c.rank2 = -1;
+        c.u_off = offU + b * nn;
+        c.u_ld = n;
+        c.t_off = -1;
+        c.v_off = V ? offV + b * nn : -1;
+        c.v_ld = n;
+        c.sig_off = offS + (int64_t)b * n;
+        c.out_w = n;
+        c.rank_out = b;
+        c.kcap = n;
+        c.rule = 0;
+        c.tol = 0.0;
+        c.floor_rows = 0;
+        c.floor_cols = -1;
+        c.fixed_rank_slot = -1;
+        // keep every nonzero column: rank = count above a zero floor of 0
+        tasks[b] = c;
+    }
+    hipError_t e = hipMemcpyAsync(ws + offM, M, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tasks.data(), sizeof(CoreTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(unsigned), stream);
+    if (e == hipSuccess) e = launch_core(ws, iws, dt, batch, n, max_sweeps, flags, V ? 1 : 0, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(U, ws + offU, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(S, ws + offS, sizeof(double) * batch * n, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && V) e = hipMemcpyAsync(V, ws + offV, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
+    unsigned fl = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&fl, flags, sizeof(unsigned), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_jacobi: ") + hipGetErrorString(e));
+    if (flags_host) *flags_host = fl;
+    return HSVD_OK;
+}
+
+extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w,
+                                       double* Q, double* R, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    if (!P || !Q || !R || batch < 1 || h < 1 || w < 1 || w > 96 || h > (1 << 26))
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_tsqr: bad argument");
+    Scratch sc;
+    int ch = std::min(1024, pow2floor(std::max(1, 16384 / w)));
+    if (ch < w) ch = w;
+    const int nch = (int)((h + ch - 1) / ch);
+    int nodes = 0;
+    for (int nn = nch;; nn = (nn + 1) >> 1) {
+        nodes += nn;
+        if (nn == 1) break;
+    }
+    const int64_t hw = h * w, slot = 3LL * w * w + w;
+    const int64_t offP = 0, offI = offP + batch * hw, offQ = offI + (int64_t)w * w,
+                  offS = offQ + batch * hw, offR = offS + (int64_t)batch * nodes * slot,
+                  tot = offR + (int64_t)batch * w * w;
+    double* ws = sc.get<double>(tot);
+    int* iws = sc.get<int>((size_t)batch * nodes);
+    TsqrTask* dt = sc.get<TsqrTask>(batch);
+    ApplyTask* da = sc.get<ApplyTask>(batch);
+    ChunkRef* dc = sc.get<ChunkRef>((size_t)batch * nch);
+    if (!ws || !iws || !dt || !da || !dc) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    std::vector<TsqrTask> tt(batch);
+    std::vector<ApplyTask> at(batch);
+    std::vector<ChunkRef> cr;
+    for (int b = 0; b < batch; ++b) {
+        TsqrTask t{};
+        t.p_off = offP + b * hw;
+        t.store_off = offS + (int64_t)b * nodes * slot;
+        t.r_out = offR + (int64_t)b * w * w;
+        t.h = (int)h;
+        t.p_ld = (int)h;
+        t.nch = nch;
+        t.chunk0 = b * nch;
+        t.cnt_off = b * nodes;
+        tt[b] = t;
+        ApplyTask a{};
+        a.tsqr = b;
+        a.x_off = offI;
+        a.out_off = offQ + b * hw;
+        a.out_ld = (int)h;
+        a.add_u_off = -1;
+        at[b] = a;
+        for (int c = 0; c < nch; ++c) cr.push_back({b, c});
+    }
+    std::vector<double> I((size_t)w * w, 0.0);
+    for (int i = 0; i < w; ++i) I[(size_t)i * w + i] = 1.0;
+    hipError_t e = hipMemcpyAsync(ws + offP, P, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + offI, I.data(), sizeof(double) * w * w, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(iws, 0, sizeof(int) * batch * nodes, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tt.data(), sizeof(TsqrTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(da, at.data(), sizeof(ApplyTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, cr.data(), sizeof(ChunkRef) * cr.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_tsqr_factor(ws, iws, dt, dc, (int)cr.size(), w, ch, stream);
+    if (e == hipSuccess) e = launch_tsqr_apply(ws, dt, da, dc, (int)cr.size(), w, ch, w, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Q, ws + offQ, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(R, ws + offR, sizeof(double) * batch * w * w, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_tsqr: ") + hipGetErrorString(e));
+    return HSVD_OK;
+}

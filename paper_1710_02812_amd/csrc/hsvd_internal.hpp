@@ -1,0 +1,139 @@
+// Internal task descriptors shared by the host plan and the gfx950 kernels.
+//
+// Every device buffer lives in one plan-owned arena of doubles (offsets are in
+// elements of that arena) plus a small int arena (ranks, tree counters, flags).
+// The input A is addressed by element offsets from the pointer passed to execute.
+// Panels are column-major with an explicit leading dimension; A is row-major.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsvd {
+
+constexpr double kEps = 2.220446049250313e-16;   // 2^-52
+
+// ---------------------------------------------------------------- big products with A
+// op 0: Y (rows x N) = A_blk (rows x cols) * X (cols x N)
+// op 1: Y (cols x N) = A_blk^T * X (rows x N)
+struct GemmTask {
+    int64_t a_off;        // offset of A_blk[0][0] in A (row-major, leading dim lda)
+    int64_t x_off, y_off; // arena offsets (col-major panels)
+    int32_t rows, cols;   // A_blk shape as stored
+    int32_t x_ld, y_ld;
+    int32_t tiles;        // output row tiles of this task
+    int32_t pad;
+};
+struct TileRef { int32_t task; int32_t tile; };
+
+// ---------------------------------------------------------------- tall-skinny QR (TSQR)
+// Panel P (h x w, col-major, ld) split into nch row chunks of `ch` rows; each chunk
+// gets a Householder QR in LDS, then R factors are merged pairwise up a binary tree
+// (the last work-group to finish a pair merges it).  Tree node (level L, index i)
+// has children (2i, 2i+1) at level L-1; an odd last node passes straight up.
+struct TsqrTask {
+    int64_t p_off;        // panel, overwritten by the chunk reflectors
+    int64_t store_off;    // per-node storage: R (w*w) | V (2w*w) | tau (w)
+    int64_t r_out;        // final R (w x w, col-major, ld w), upper triangular
+    int32_t h, p_ld;
+    int32_t nch;          // chunks
+    int32_t chunk0;       // first flat chunk index of this task
+    int32_t cnt_off;      // int arena: one counter per tree node
+    int32_t levels;       // tree levels above the chunks
+};
+struct ChunkRef { int32_t task; int32_t chunk; };
+
+// out (h x c) = Q * X  (+ U1 * T when add_u_off >= 0), Q the explicit thin factor of a
+// TsqrTask, X (w x c).  One work-group per chunk.
+struct ApplyTask {
+    int32_t tsqr;         // index into the TsqrTask array of the same launch family
+    int32_t out_ld;
+    int64_t x_off;        // X, col-major, ld w
+    int64_t out_off;
+    int64_t add_u_off;    // U1 panel (h x w1, ld add_u_ld) or -1
+    int64_t add_t_off;    // T (w1 x c, col-major, ld w1)
+    int32_t add_u_ld, add_w;
+};
+
+// ---------------------------------------------------------------- thin panel algebra
+// Row-chunked ops on col-major panels of height h:
+//   gram:  part[c] = X_c^T Y_c           (wx x wy), per chunk c
+//   reduce:C = sum_c part[c]; Cacc (+)= C  (one group per task)
+//   sub:   Y_c -= X_c * C
+//   nn:    O_c (+)= X_c * T
+struct ThinTask {
+    int64_t x_off, y_off, c_off, part_off, acc_off;
+    int32_t h, x_ld, y_ld, c_ld;
+    int32_t wx, wy;       // widths
+    int32_t nch, chunk0;
+    int32_t accumulate;   // reduce: 0 -> Cacc = C, 1 -> Cacc += C; nn: 0 set, 1 add
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------- Jacobi cores
+enum CoreMode : int32_t {
+    CORE_UPPER = 0,       // M = R (dim x dim) read from m_off (ld m_ld)
+    CORE_UPPER_T = 1,     // M = R^T
+    CORE_MERGE = 2,       // M = E = [[S1, C S2], [0, R S2]] (compact r1 + r2)
+    CORE_DENSE = 3        // M = a dense dim x dim matrix (kernel-level tests)
+};
+struct CoreTask {
+    int32_t mode;
+    int32_t dim;          // UPPER modes: dimension of R as stored (panel width)
+    int64_t m_off; int32_t m_ld;
+    int32_t rank_in;      // UPPER modes: int-arena slot holding the active size, or -1 (= dim)
+    // merge inputs
+    int64_t s1_off, s2_off, c_off, r_off;
+    int32_t c_ld, r_ld;
+    int32_t rank1, rank2; // int-arena slots
+    // outputs
+    int64_t u_off; int32_t u_ld;   // left vectors: UPPER -> rows 0..dim-1; MERGE -> rows r1..r1+r2-1
+    int64_t t_off; int32_t t_ld;   // MERGE: left-vector rows 0..r1-1
+    int64_t v_off; int32_t v_ld;   // accumulated right rotations (or -1)
+    int64_t sig_off;               // kcap values, zero padded
+    int32_t out_w;                 // columns written to u/t/v outputs (zero padded past r)
+    int32_t rank_out;              // int-arena slot for r
+    int32_t kcap, rule;
+    double tol;
+    int32_t floor_rows;            // zero-floor shape: max(floor_rows, floor_cols or r1+r2)
+    int32_t floor_cols;            // < 0: use the active core size
+    int32_t fixed_rank_slot;       // >= 0: rank = min(zero-floor count, ranks[slot])
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------- output
+struct OutputArgs {
+    int64_t u_off, v_off, sig_off;  // final U (m x W), V (n x W) panels, sigma
+    int32_t u_ld, v_ld;
+    int32_t m, n, k;
+    int32_t rank_slot;
+    int32_t sign_off;               // int arena: k signs
+};
+
+// ---------------------------------------------------------------- launches
+// All launchers enqueue on `s` and return the hipError_t of the launch.
+hipError_t launch_gemm(int op, int fp32, const void* A, int64_t lda, double* ws,
+                       const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
+                       hipStream_t s);
+hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
+                              const ChunkRef* chunks, int nchunks, int w, int ch,
+                              hipStream_t s);
+hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
+                             const ChunkRef* chunks, int nchunks, int w, int ch, int c,
+                             hipStream_t s);
+hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks,
+                            int nchunks, int chh, hipStream_t s);
+hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, hipStream_t s);
+hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks,
+                           int nchunks, int chh, hipStream_t s);
+hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks,
+                          int nchunks, int chh, hipStream_t s);
+hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks,
+                           int nchunks, int chh, hipStream_t s);
+hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
+                       int max_sweeps, unsigned* flags, int with_v, hipStream_t s);
+hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_output(int fp32, const double* ws, const int* iws, OutputArgs a,
+                         void* U, void* S, void* Vt, hipStream_t s);
+
+}  // namespace hsvd

@@ -1,0 +1,149 @@
+// Gaussian test matrices, fills, and the final sign-normalised output write.
+#include "hsvd_internal.hpp"
+#include "device_common.hpp"
+
+namespace hsvd {
+
+// Philox-4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, "Parallel
+// random numbers: as easy as 1, 2, 3", SC 2011): ten rounds of two 32x32->64-bit
+// multiplies with the round constants and Weyl key increments published there.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 53-bit uniform in the open interval (0, 1) from two 32-bit words.
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// out[e] ~ N(0, 1): Box-Muller on the Philox block of counter e/2.
+__global__ void k_gaussian(double* out, int64_t count, uint64_t seed) {
+    const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * pair >= count) return;
+    const uint4 c = make_uint4((uint32_t)pair, (uint32_t)(pair >> 32), 0x5eedu, 0u);
+    const uint2 k = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint4 x = philox4x32_10(c, k);
+    const double u1 = u53(x.x, x.y), u2 = u53(x.z, x.w);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    out[2 * pair] = rad * cs;
+    if (2 * pair + 1 < count) out[2 * pair + 1] = rad * sn;
+}
+
+__global__ void k_fill(double* p, int64_t count, double v) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+// Column signs: flip so the largest-magnitude entry of u_j is positive (ties: lowest row).
+__global__ __launch_bounds__(256) void k_colsign(const double* __restrict__ ws, int* __restrict__ iws,
+                                                 OutputArgs a) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int j = blockIdx.x;
+    const int r = iws[a.rank_slot];
+    const double* u = ws + a.u_off + (int64_t)j * a.u_ld;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    if (j < r)
+        for (int i = threadIdx.x; i < a.m; i += blockDim.x) {
+            const double v = fabs(u[i]);
+            if (v > best) { best = v; bi = i; }       // first hit per thread is the lowest row
+        }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v2 = sv[threadIdx.x + o];
+            const int i2 = si[threadIdx.x + o];
+            if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) iws[a.sign_off + j] = (j < r && si[0] < a.m && u[si[0]] < 0.0) ? -1 : 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_write_u(const double* __restrict__ ws, const int* __restrict__ iws,
+                                                 OutputArgs a, T* __restrict__ U) {
+    __shared__ double tile[64][129];
+    const int r = iws[a.rank_slot];
+    const int row0 = blockIdx.x * 64;
+    const int rows = min(64, a.m - row0);
+    for (int j0 = 0; j0 < a.k; j0 += 128) {
+        const int cols = min(128, a.k - j0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * cols; e += blockDim.x) {
+            const int jj = e / 64, i = e - jj * 64;
+            const int j = j0 + jj;
+            double v = 0.0;
+            if (i < rows && j < r) v = iws[a.sign_off + j] * ws[a.u_off + (int64_t)j * a.u_ld + row0 + i];
+            tile[i][jj] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+            const int i = e / cols, jj = e - i * cols;
+            U[(int64_t)(row0 + i) * a.k + j0 + jj] = (T)tile[i][jj];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ ws, const int* __restrict__ iws,
+                                                 OutputArgs a, T* __restrict__ S, T* __restrict__ Vt) {
+    const int r = iws[a.rank_slot];
+    const int j = blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double sg = (j < r) ? (double)iws[a.sign_off + j] : 0.0;
+    if (c < a.n) Vt[(int64_t)j * a.n + c] = (T)(sg * ws[a.v_off + (int64_t)j * a.v_ld + c]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S[j] = (T)((j < r) ? ws[a.sig_off + j] : 0.0);
+}
+
+hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t pairs = (count + 1) / 2;
+    hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out,
+                       count, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(int fp32, const double* ws, const int* iws, OutputArgs a, void* U,
+                         void* S, void* Vt, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsign, dim3(a.k), dim3(256), 0, s, ws, (int*)iws, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 gu((a.m + 63) / 64), gv((a.n + 255) / 256, a.k);
+    if (fp32) {
+        hipLaunchKernelGGL(k_write_u<float>, gu, dim3(256), 0, s, ws, iws, a, (float*)U);
+        hipLaunchKernelGGL(k_write_v<float>, gv, dim3(256), 0, s, ws, iws, a, (float*)S, (float*)Vt);
+    } else {
+        hipLaunchKernelGGL(k_write_u<double>, gu, dim3(256), 0, s, ws, iws, a, (double*)U);
+        hipLaunchKernelGGL(k_write_v<double>, gv, dim3(256), 0, s, ws, iws, a, (double*)S, (double*)Vt);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hsvd

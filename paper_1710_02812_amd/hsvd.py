@@ -1,0 +1,211 @@
+"""ctypes binding of libhsvd.so (include/hsvd.h, include/hsvd_debug.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Tensors are PyTorch-ROCm device tensors; the current torch stream is passed as
+the hipStream_t.  The library is loaded on first use and a missing or stale
+build raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsvd.so")
+
+HSVD_OK = 0
+STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_NONFINITE",
+                5: "ERR_NOCONV", 6: "ERR_UNSUPPORTED"}
+FP64, FP32 = 0, 1
+RULE_GAMMA, RULE_FROB = 0, 1
+FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
+
+EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
+            "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
+            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check"]
+
+
+class HsvdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("power_steps", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libhsvd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1710_02812_amd.build.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.hsvd_default_options.argtypes = [P(Options)]
+    L.hsvd_plan.argtypes = [P(vp), i64, i64, i32, i32, i32, f64]
+    L.hsvd_plan_ex.argtypes = [P(vp), i64, i64, i32, i32, i32, f64, P(Options)]
+    L.hsvd_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.hsvd_destroy.argtypes = [vp]
+    L.hsvd_get_rank.argtypes = [vp, P(i32)]
+    L.hsvd_get_status.argtypes = [vp, P(ctypes.c_uint32)]
+    L.hsvd_workspace_bytes.argtypes = [vp, P(ctypes.c_size_t)]
+    L.hsvd_last_error.restype = ctypes.c_char_p
+    L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, P(ctypes.c_uint32), vp]
+    L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
+    L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
+                                        P(ctypes.c_size_t)]
+    for name in EXPORTED:
+        if name != "hsvd_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != HSVD_OK:
+        raise HsvdError(status, lib().hsvd_last_error().decode())
+
+
+def default_options() -> Options:
+    o = Options()
+    _check(lib().hsvd_default_options(ctypes.byref(o)))
+    return o
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """Owns an hsvd_plan_t.  Create once per shape; execute many times."""
+
+    def __init__(self, m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, *,
+                 precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
+                 power_steps: int | None = None, refine_steps: int = 0,
+                 max_sweeps: int | None = None, seed: int = 0):
+        o = default_options()
+        o.precision = precision
+        o.rule = rule
+        if oversample is not None:
+            o.oversample = oversample
+        if power_steps is not None:
+            o.power_steps = power_steps
+        o.refine_steps = refine_steps
+        if max_sweeps is not None:
+            o.max_sweeps = max_sweeps
+        o.seed = seed
+        h = ctypes.c_void_p()
+        _check(lib().hsvd_plan_ex(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
+        self._h = h
+        self.m, self.n, self.p, self.q, self.k, self.tol = m, n, p, q, k, tol
+        self.precision = precision
+
+    def execute(self, A, U, S, Vt, stream=None):
+        """Enqueues the method on A (torch device tensors; no synchronisation)."""
+        import torch
+        dt = torch.float64 if self.precision == FP64 else torch.float32
+        for name, t, shape in (("A", A, (self.m, self.n)), ("U", U, (self.m, self.k)),
+                               ("S", S, (self.k,)), ("Vt", Vt, (self.k, self.n))):
+            if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name}: need a contiguous {dt} device tensor of shape {shape}")
+        _check(lib().hsvd_execute(self._h, A.data_ptr(), U.data_ptr(), S.data_ptr(),
+                                  Vt.data_ptr(), _stream_handle(stream)))
+
+    def rank(self) -> int:
+        r = ctypes.c_int32()
+        _check(lib().hsvd_get_rank(self._h, ctypes.byref(r)))
+        return r.value
+
+    def status(self) -> int:
+        f = ctypes.c_uint32()
+        _check(lib().hsvd_get_status(self._h, ctypes.byref(f)))
+        return f.value
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().hsvd_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsvd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def svd(A, p: int, q: int, k: int, tol: float = 0.0, **opts):
+    """Hierarchical MAT truncated SVD of a torch device matrix A (float64 or float32).
+
+    Returns (U [m x k], S [k], Vt [k x n], r); entries past the rank r are zero.
+    """
+    import torch
+    if A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A must be float64 or float32")
+    prec = FP64 if A.dtype == torch.float64 else FP32
+    A = A.contiguous()
+    m, n = A.shape
+    plan = Plan(m, n, p, q, k, tol, precision=prec, **opts)
+    U = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    S = torch.empty((k,), dtype=A.dtype, device=A.device)
+    Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
+    plan.execute(A, U, S, Vt)
+    r = plan.rank()
+    flags = plan.status()
+    plan.close()
+    if flags:
+        raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
+    return U, S, Vt, r
+
+
+def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True):
+    """Jacobi SVD of a batch of dense square float64 matrices M (batch, n, n)."""
+    import torch
+    b, n, _ = M.shape
+    Mc = M.transpose(1, 2).contiguous()       # col-major storage
+    U = torch.empty_like(Mc)
+    S = torch.empty((b, n), dtype=torch.float64, device=M.device)
+    V = torch.empty_like(Mc) if with_v else None
+    fl = ctypes.c_uint32()
+    _check(lib().hsvd_debug_jacobi(Mc.data_ptr(), b, n, U.data_ptr(), S.data_ptr(),
+                                   V.data_ptr() if with_v else None, max_sweeps,
+                                   ctypes.byref(fl), _stream_handle()))
+    return (U.transpose(1, 2), S, V.transpose(1, 2) if with_v else None, fl.value)
+
+
+def plan_check(m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, **opts) -> int:
+    """Builds and bounds-checks a plan on the host only; returns the arena bytes."""
+    o = default_options()
+    for key, v in opts.items():
+        setattr(o, key, v)
+    b = ctypes.c_size_t()
+    _check(lib().hsvd_debug_plan_check(m, n, p, q, k, float(tol), ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+def debug_tsqr(P):
+    """TSQR of a batch of float64 panels P (batch, h, w) -> (Q (batch,h,w), R (batch,w,w))."""
+    import torch
+    b, h, w = P.shape
+    Pc = P.transpose(1, 2).contiguous()
+    Q = torch.empty_like(Pc)
+    R = torch.empty((b, w, w), dtype=torch.float64, device=P.device)
+    _check(lib().hsvd_debug_tsqr(Pc.data_ptr(), b, h, w, Q.data_ptr(), R.data_ptr(),
+                                 _stream_handle()))
+    return Q.transpose(1, 2), R.transpose(1, 2)

@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the headers declare, and rejects bad arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1710_02812_amd import hsvd as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for hdr in ("hsvd.h", "hsvd_debug.h"):
+        with open(os.path.join(ROOT, "include", hdr)) as f:
+            txt = f.read()
+        names += re.findall(r"^(?:hsvd_status|const char\*)\s+(hsvd_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = H.lib()
+    declared = _declared()
+    assert len(declared) >= 11
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(H.EXPORTED) == declared
+
+
+def test_default_options():
+    o = H.default_options()
+    assert (o.precision, o.rule, o.oversample, o.power_steps, o.refine_steps, o.max_sweeps,
+            o.seed) == (0, 0, 14, 1, 0, 40, 0)
+
+
+@pytest.mark.parametrize("args", [
+    (0, 10, 1, 1, 1, 0.0), (10, 0, 1, 1, 1, 0.0), (10, 10, 0, 1, 1, 0.0),
+    (10, 10, 11, 1, 1, 0.0), (10, 10, 1, 0, 1, 0.0), (10, 10, 1, 11, 1, 0.0),
+    (10, 10, 1, 1, 0, 0.0), (10, 10, 1, 1, 11, 0.0), (10, 12, 1, 1, 11, 0.0),
+    (10, 10, 1, 1, 1, -0.1), (10, 10, 1, 1, 1, 1.0), (10, 10, 1, 1, 1, float("nan")),
+])
+def test_plan_rejects_bad_arguments(args):
+    lib = H.lib()
+    h = ctypes.c_void_p(1234)
+    st = lib.hsvd_plan(ctypes.byref(h), *args)
+    assert st == 1
+    assert h.value is None
+    assert lib.hsvd_last_error().decode()
+
+
+def test_plan_rejects_bad_options_and_unsupported_rank():
+    lib = H.lib()
+    h = ctypes.c_void_p()
+    o = H.default_options()
+    o.precision = 7
+    assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
+    o = H.default_options()
+    o.max_sweeps = 0
+    assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
+    assert lib.hsvd_plan(ctypes.byref(h), 1000, 1000, 2, 2, 65, 0.0) == 6
+    assert lib.hsvd_plan(None, 100, 100, 2, 2, 5, 0.0) == 1
+
+
+def test_null_handles():
+    lib = H.lib()
+    assert lib.hsvd_destroy(None) == 0
+    assert lib.hsvd_execute(None, None, None, None, None, None) == 1
+    r = ctypes.c_int32()
+    assert lib.hsvd_get_rank(None, ctypes.byref(r)) == 1
+    assert lib.hsvd_get_status(None, None) == 1
+    assert lib.hsvd_debug_jacobi(None, 1, 4, None, None, None, 10, None, None) == 1
+    assert lib.hsvd_debug_tsqr(None, 1, 4, 4, None, None, None) == 1
+
+
+@pytest.mark.parametrize("shape", [
+    (512, 512, 2, 2, 20, {}),
+    (8192, 8192, 8, 8, 50, {"precision": 1}),
+    (1000, 900, 3, 4, 20, {}),
+    (1000, 900, 3, 4, 20, {"power_steps": 0}),
+    (1000, 900, 3, 4, 20, {"power_steps": 2, "refine_steps": 2}),
+    (777, 333, 5, 3, 17, {"rule": 1}),
+    (300, 200, 1, 1, 7, {}),
+    (10, 7, 10, 7, 1, {}),
+    (16384, 16384, 16, 16, 64, {"precision": 1}),
+    (2049, 4097, 3, 9, 64, {"oversample": 40}),
+])
+def test_plan_footprint_is_in_bounds(shape):
+    """Every task of every launch stays inside the plan's buffers (host-side check)."""
+    m, n, p, q, k, opts = shape
+    b = H.plan_check(m, n, p, q, k, 0.0, **opts)
+    assert b > 0

@@ -1,0 +1,84 @@
+"""Kernel-level parity on the GPU: the Jacobi core and the TSQR kernels through
+the C ABI's debug entry points, against LAPACK on the host."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1710_02812_amd import hsvd as H  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 100, 128])
+def test_jacobi_dense_random(n):
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((3, n, n))
+    M[1] *= np.exp(-np.arange(n) / 3.0)[None, :]          # graded columns
+    print(f"jacobi n={n}", flush=True)
+    U, S, V, flags = H.debug_jacobi(_t(M), with_v=(n <= 64))
+    assert flags == 0
+    U, S = U.cpu().numpy(), S.cpu().numpy()
+    for b in range(3):
+        s_ref = np.linalg.svd(M[b], compute_uv=False)
+        assert np.max(np.abs(S[b] - s_ref)) <= 1e-13 * s_ref[0] * max(1, n / 8)
+        assert np.all(np.diff(S[b]) <= 0)
+        nz = S[b] > 1e-12 * S[b][0]
+        Ub = U[b][:, nz]
+        assert np.linalg.norm(Ub.T @ Ub - np.eye(nz.sum())) <= 1e-13 * n
+        if n <= 64:
+            Vb = V.cpu().numpy()[b]
+            assert np.linalg.norm(Vb.T @ Vb - np.eye(n)) <= 1e-13 * n
+            rec = (U[b] * S[b]) @ Vb.T
+            assert np.linalg.norm(rec - M[b]) <= 1e-13 * n * np.linalg.norm(M[b])
+
+
+def test_jacobi_rank_deficient_and_zero():
+    rng = np.random.default_rng(5)
+    n = 40
+    A = rng.standard_normal((n, 6)) @ rng.standard_normal((6, n))
+    Z = np.zeros((n, n))
+    U, S, V, flags = H.debug_jacobi(_t(np.stack([A, Z])), with_v=True)
+    S = S.cpu().numpy()
+    assert flags == 0
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(S[0] - s_ref)) <= 1e-12 * s_ref[0]
+    assert np.all(S[1] == 0.0)
+    assert np.all(U.cpu().numpy()[1] == 0.0)
+
+
+def test_jacobi_sweep_cap_flag():
+    """A cap of one sweep on a random 64 x 64 matrix is reported, not hidden."""
+    rng = np.random.default_rng(6)
+    M = rng.standard_normal((1, 64, 64))
+    _, _, _, flags = H.debug_jacobi(_t(M), max_sweeps=1, with_v=False)
+    assert flags & H.FLAG_NOCONV
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (5, 7), (64, 64), (100, 20), (1000, 50), (1024, 64),
+                                 (257, 64), (3000, 96), (8192, 50), (20000, 17)])
+def test_tsqr_random_panels(h, w):
+    rng = np.random.default_rng(h + w)
+    P = rng.standard_normal((2, h, w))
+    P[1, :, -1] = P[1, :, 0]                                # rank-deficient panel
+    print(f"tsqr h={h} w={w}", flush=True)
+    Q, R = H.debug_tsqr(_t(P))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    kk = min(h, w)
+    for b in range(2):
+        assert np.allclose(np.tril(R[b], -1), 0.0)
+        assert np.linalg.norm(Q[b] @ R[b] - P[b]) <= 1e-13 * np.sqrt(h * w) * np.linalg.norm(P[b])
+        G = Q[b][:, :kk].T @ Q[b][:, :kk]
+        assert np.linalg.norm(G - np.eye(kk)) <= 1e-13 * np.sqrt(h) * w
+        if b == 0:
+            Rref = np.linalg.qr(P[b], mode="r")
+            assert np.allclose(np.abs(np.diag(R[b])[:kk]), np.abs(np.diag(Rref)[:kk]),
+                               rtol=1e-11, atol=1e-12 * np.abs(Rref).max())
