@@ -119,6 +119,32 @@ hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
 /* Device workspace owned by the plan, in bytes. */
 hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host);
 
+/* Launch kinds reported by hsvd_launch_times. */
+typedef enum {
+    HSVD_LAUNCH_GEMM_AX = 0,       /* Y = A_blk X   (passes over A)                      */
+    HSVD_LAUNCH_GEMM_ATX = 1,      /* Y = A_blk^T X (passes over A)                      */
+    HSVD_LAUNCH_TSQR_FACTOR = 2,   /* Householder TSQR of panels                         */
+    HSVD_LAUNCH_TSQR_APPLY = 3,    /* Q X from the TSQR factors                          */
+    HSVD_LAUNCH_GRAM = 4,          /* projection coefficients X^T Y (row-chunk partials) */
+    HSVD_LAUNCH_REDUCE = 5,        /* sum of the partials                                */
+    HSVD_LAUNCH_THIN_NN = 6,       /* Y (+/-)= X C                                       */
+    HSVD_LAUNCH_SUM = 7,           /* sum of split products                              */
+    HSVD_LAUNCH_CORE = 8,          /* Jacobi SVD cores                                   */
+    HSVD_LAUNCH_OUTPUT = 9         /* signs and the U, S, Vt writes                      */
+} hsvd_launch_kind;
+
+/* Turns per-launch timing on (1) or off (0) for later executes of this plan.
+ * When on, execute records a HIP event on its stream after every launch. */
+hsvd_status hsvd_set_profiling(hsvd_plan_t plan, int32_t enable);
+
+/* Per-launch durations (ms) of the last profiled execute, in launch order:
+ * kinds_host[i] (hsvd_launch_kind) and ms_host[i] for i < min(cap, count).
+ * *count_host receives the number of launches of one execute; with
+ * kinds_host == NULL or ms_host == NULL only the count is returned.
+ * Synchronises on the last event. */
+hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_host, int32_t cap,
+                              int32_t* count_host);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hsvd_last_error(void);
 

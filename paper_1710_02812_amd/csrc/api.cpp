@@ -111,6 +111,11 @@ struct hsvd_plan_st {
     OutputArgs out{};
     int rank_slot = -1;
 
+    // optional per-launch timing: events[i] .. events[i+1] bracket launch i
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> event_kind;
+
     int64_t alloc(int64_t elems) {
         const int64_t off = ws_elems;
         ws_elems += (elems + 31) / 32 * 32;
@@ -1037,20 +1042,72 @@ hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void
     hsvd_plan_st& P = *plan;
     hipError_t e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * 4, stream);
     if (e != hipSuccess) return hip_fail(e, "flags reset");
-    for (const Stage& s : P.stages) {
-        hsvd_status st = run_stage(P, s, A, stream);
+    const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
+    if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
+    for (size_t i = 0; i < P.stages.size(); ++i) {
+        hsvd_status st = run_stage(P, P.stages[i], A, stream);
         if (st != HSVD_OK) return st;
+        if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
     }
     e = launch_output(P.opt.precision == HSVD_FP32, P.ws, P.iws, P.out, U, S, Vt, stream);
     if (e != hipSuccess) return hip_fail(e, "output launch");
+    if (prof && (e = hipEventRecord(P.events.back(), stream)) != hipSuccess) return hip_fail(e, "event");
     P.last_stream = stream;
     P.executed = true;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_set_profiling(hsvd_plan_t plan, int32_t enable) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (enable && plan->events.empty()) {
+        plan->events.resize(plan->stages.size() + 2);
+        for (auto& ev : plan->events) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+    }
+    plan->profiling = enable != 0;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_host, int32_t cap,
+                              int32_t* count_host) {
+    if (!plan || !count_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    const int n = (int)plan->stages.size() + 1;
+    *count_host = n;
+    if (!kinds_host || !ms_host) return HSVD_OK;
+    if (!plan->profiling || plan->events.size() != (size_t)n + 1 || !plan->executed)
+        return fail(HSVD_ERR_INVALID, "profiling was not enabled for the last execute");
+    hipError_t e = hipEventSynchronize(plan->events.back());
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int i = 0; i < n && i < cap; ++i) {
+        int kind = HSVD_LAUNCH_OUTPUT;
+        if (i < (int)plan->stages.size()) {
+            const Stage& s = plan->stages[i];
+            switch (s.kind) {
+                case ST_GEMM: kind = s.op == 0 ? HSVD_LAUNCH_GEMM_AX : HSVD_LAUNCH_GEMM_ATX; break;
+                case ST_TSQR_F: kind = HSVD_LAUNCH_TSQR_FACTOR; break;
+                case ST_TSQR_A: kind = HSVD_LAUNCH_TSQR_APPLY; break;
+                case ST_GRAM: kind = HSVD_LAUNCH_GRAM; break;
+                case ST_REDUCE: kind = HSVD_LAUNCH_REDUCE; break;
+                case ST_NN: kind = HSVD_LAUNCH_THIN_NN; break;
+                case ST_SUM: kind = HSVD_LAUNCH_SUM; break;
+                case ST_CORE: kind = HSVD_LAUNCH_CORE; break;
+            }
+        }
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, plan->events[i], plan->events[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        kinds_host[i] = kind;
+        ms_host[i] = ms;
+    }
     return HSVD_OK;
 }
 
 hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (!plan) return HSVD_OK;
     if (plan->executed) hipStreamSynchronize(plan->last_stream);
+    for (auto& ev : plan->events) hipEventDestroy(ev);
     if (plan->ws) hipFree(plan->ws);
     if (plan->iws) hipFree(plan->iws);
     if (plan->flags) hipFree(plan->flags);
