@@ -80,14 +80,20 @@ def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
     per_kind = {}
     counts = {}
     reps = 3
+    per_launch = None
     for _ in range(reps):
         plan.execute(A, U, S, Vt)
-        for kind, t in plan.launch_times():
+        lt = plan.launch_times()
+        if per_launch is None:
+            per_launch = [[kk, 0.0] for kk, _ in lt]
+        for i, (kind, t) in enumerate(lt):
             per_kind[kind] = per_kind.get(kind, 0.0) + t / reps
             counts[kind] = counts.get(kind, 0) + 1
+            per_launch[i][1] += t / reps
     counts = {kk: v // reps for kk, v in counts.items()}
     plan.set_profiling(False)
     plan.close()
+    time_path.last_launches = [(i, kk, round(t, 4)) for i, (kk, t) in enumerate(per_launch)]
     return ms, flags, out, per_kind, counts
 
 
@@ -112,6 +118,7 @@ def main():
     torch.cuda.synchronize()
 
     ms32, fl32, out32, kinds32, cnt32 = time_path(H, torch, A32, H.FP32, args, k, p, q)
+    launches32 = time_path.last_launches
     if args.profile_only:
         print(json.dumps({"profile_only": True, "ms_fp32": ms32}))
         return
@@ -190,10 +197,12 @@ def main():
                    "parallelism": "single GPU"},
         "fp64_path_ms": round(ms64, 4),
         "fp32_storage_speedup_vs_fp64": round(ms64 / ms32, 3),
-        "status_flags": {"fp32": fl32, "fp64": fl64},
+        "status_flags": {"fp32": fl32 & 0xFFFF, "fp64": fl64 & 0xFFFF},
+        "max_jacobi_sweeps": {"fp32": fl32 >> 16, "fp64": fl64 >> 16},
         "launch_ms_per_step": {"fp32": {kk: round(v, 4) for kk, v in kinds32.items()},
                                "fp64": {kk: round(v, 4) for kk, v in kinds64.items()}},
         "launch_counts": cnt32,
+        "launches_fp32": launches32,
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": acc,

@@ -113,7 +113,9 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan);
  * execute's stream). */
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host);
 
-/* Copies the status flags of the last execute to *flags_host (synchronises). */
+/* Copies the status of the last execute to *flags_host (synchronises): bits 0..15
+ * hold the HSVD_FLAG_* conditions, bits 16..31 the largest number of Jacobi sweeps
+ * any core of that execute ran. */
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
 
 /* Device workspace owned by the plan, in bytes. */

@@ -19,7 +19,8 @@ extern "C" {
  * Writes the left singular vectors U (n x n, columns by descending sigma),
  * S (n, descending) and, when V != NULL (then n <= 64), the right singular
  * vectors V (n x n), so that M = U diag(S) V^T.  Columns with sigma = 0 are 0.
- * *flags_host (may be NULL) receives the status flags (HSVD_FLAG_*).          */
+ * *flags_host (may be NULL) receives the status flags (HSVD_FLAG_*) in bits 0..15
+ * and the largest number of sweeps any core ran in bits 16..31.              */
 hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double* U, double* S,
                               double* V, int32_t max_sweeps, uint32_t* flags_host,
                               hipStream_t stream);
@@ -31,7 +32,7 @@ hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double*
 hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
                                   double tol, const hsvd_options* opt, size_t* workspace_bytes);
 
-/* Householder TSQR of `batch` h x w panels P (w <= 96): Q (h x w, orthonormal
+/* Householder TSQR of `batch` h x w panels P (w <= 80): Q (h x w, orthonormal
  * columns) and R (w x w upper triangular) with P = Q R.  P is not modified.   */
 hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
                             double* R, hipStream_t stream);

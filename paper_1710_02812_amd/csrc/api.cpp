@@ -69,12 +69,7 @@ int pow2floor(int x) {
     return p;
 }
 
-int tsqr_chunk(int w, int c) {
-    const int mx = std::max(w, c);
-    int ch = std::min(1024, pow2floor(std::max(1, 16384 / std::max(mx, 1))));
-    if (ch < mx) ch = mx;
-    return ch;
-}
+int tsqr_chunk(int w, int /*c*/) { return tsqr_chunk_rows(w); }
 
 constexpr int THIN_CH = 256;
 
@@ -165,7 +160,7 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
         ++levels;
     }
     t.levels = levels;
-    t.store_off = P.alloc((int64_t)nodes * (3LL * w * w + w));
+    t.store_off = P.alloc((int64_t)nodes * tsqr_slot_size(w));
     t.cnt_off = P.ialloc(nodes);
     t.r_out = P.alloc((int64_t)w * w);
     for (int c = 0; c < t.nch; ++c) tb.chunks.push_back({(int)tb.tasks.size(), c});
@@ -795,14 +790,14 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 const ChunkRef* R = (const ChunkRef*)(b + s.refs_off);
                 int ntask = 0;
                 for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
-                if (s.w > 96 || s.ch < s.w || s.ch < s.c) return "tsqr geometry";
+                if (s.w > kTsqrMaxW || s.c > kTsqrMaxW || s.ch < s.w || s.ch != tsqr_chunk_rows(s.w)) return "tsqr geometry";
                 for (int i = 0; i < ntask; ++i) {
                     const TsqrTask& t = T[i];
                     int nodes = 0;
                     for (int nn = t.nch;; nn = (nn + 1) >> 1) { nodes += nn; if (nn == 1) break; }
                     if (t.nch != (t.h + s.ch - 1) / s.ch) return "tsqr chunk count";
                     if (!panel("tsqr panel", t.p_off, t.p_ld, t.h, s.w)) return msg;
-                    if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * (3LL * s.w * s.w + s.w) - 1, WS)) return msg;
+                    if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * tsqr_slot_size(s.w) - 1, WS)) return msg;
                     if (!span("tsqr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
                     if (!span("tsqr counters", t.cnt_off, t.cnt_off + nodes - 1, IW)) return msg;
                     if (s.kind == ST_TSQR_A) {
@@ -982,7 +977,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, 
     P->W = k;
     P->L = (int)std::min<int64_t>(k + o.oversample, bmin);
     if (P->L < 1) P->L = 1;
-    if (P->L > 96) P->L = 96;
+    if (P->L > kTsqrMaxW) P->L = kTsqrMaxW;
     P->g = 2 + o.power_steps;
 
     build_plan(*P);
@@ -1130,9 +1125,10 @@ hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
     if (!plan || !flags_host) return fail(HSVD_ERR_INVALID, "NULL argument");
     hipError_t e = hipSuccess;
     if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
-    if (e == hipSuccess)
-        e = hipMemcpy(flags_host, plan->flags, sizeof(unsigned), hipMemcpyDeviceToHost);
+    unsigned fl[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpy(fl, plan->flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hsvd_get_status");
+    *flags_host = (fl[0] & 0xFFFFu) | (std::min(fl[1], 0xFFFFu) << 16);
     return HSVD_OK;
 }
 

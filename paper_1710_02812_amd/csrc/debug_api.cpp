@@ -51,7 +51,7 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
                   offS = offV + batch * nn, tot = offS + (int64_t)batch * n;
     double* ws = sc.get<double>(tot);
     int* iws = sc.get<int>(batch);
-    unsigned* flags = sc.get<unsigned>(1);
+    unsigned* flags = sc.get<unsigned>(2);
     CoreTask* dt = sc.get<CoreTask>(batch);
     if (!ws || !iws || !flags || !dt) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
     std::vector<CoreTask> tasks(batch);
@@ -82,34 +82,33 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
     }
     hipError_t e = hipMemcpyAsync(ws + offM, M, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dt, tasks.data(), sizeof(CoreTask) * batch, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(unsigned), stream);
+    if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(unsigned), stream);
     if (e == hipSuccess) e = launch_core(ws, iws, dt, batch, n, max_sweeps, flags, V ? 1 : 0, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(U, ws + offU, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(S, ws + offS, sizeof(double) * batch * n, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess && V) e = hipMemcpyAsync(V, ws + offV, sizeof(double) * batch * nn, hipMemcpyDeviceToDevice, stream);
-    unsigned fl = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&fl, flags, sizeof(unsigned), hipMemcpyDeviceToHost, stream);
+    unsigned fl[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(fl, flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_jacobi: ") + hipGetErrorString(e));
-    if (flags_host) *flags_host = fl;
+    if (flags_host) *flags_host = (fl[0] & 0xFFFFu) | (std::min(fl[1], 0xFFFFu) << 16);
     return HSVD_OK;
 }
 
 extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w,
                                        double* Q, double* R, hipStream_t stream) {
     using hsvd_detail::set_error;
-    if (!P || !Q || !R || batch < 1 || h < 1 || w < 1 || w > 96 || h > (1 << 26))
+    if (!P || !Q || !R || batch < 1 || h < 1 || w < 1 || w > kTsqrMaxW || h > (1 << 26))
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_tsqr: bad argument");
     Scratch sc;
-    int ch = std::min(1024, pow2floor(std::max(1, 16384 / w)));
-    if (ch < w) ch = w;
+    const int ch = tsqr_chunk_rows(w);
     const int nch = (int)((h + ch - 1) / ch);
     int nodes = 0;
     for (int nn = nch;; nn = (nn + 1) >> 1) {
         nodes += nn;
         if (nn == 1) break;
     }
-    const int64_t hw = h * w, slot = 3LL * w * w + w;
+    const int64_t hw = h * w, slot = tsqr_slot_size(w);
     const int64_t offP = 0, offI = offP + batch * hw, offQ = offI + (int64_t)w * w,
                   offS = offQ + batch * hw, offR = offS + (int64_t)batch * nodes * slot,
                   tot = offR + (int64_t)batch * w * w;

@@ -42,6 +42,14 @@ struct TsqrTask {
 };
 struct ChunkRef { int32_t task; int32_t chunk; };
 
+constexpr int kTsqrMaxW = 80;
+// Per-node storage: R (w*w) | V (2w*w) | tau (w) | T (w*w).
+__host__ __device__ inline int64_t tsqr_slot_size(int w) { return 4LL * w * w + w; }
+// Rows per chunk: the factor kernel holds a chunk (or a stacked 2w x w pair of R
+// factors) in registers: 16 lanes x 16 rows per column (w <= 64) or 8 lanes x 20
+// rows (w <= 80; a stacked pair needs 2w <= 160 rows).
+inline int tsqr_chunk_rows(int w) { return w <= 64 ? 256 : 160; }
+
 // out (h x c) = Q * X  (+ U1 * T when add_u_off >= 0), Q the explicit thin factor of a
 // TsqrTask, X (w x c).  One work-group per chunk.
 struct ApplyTask {

@@ -10,7 +10,12 @@
 // round-robin tournament, so each round rotates nc/2 disjoint pairs in parallel,
 // one lane group per pair (dot product by shuffle reduction, rotation in LDS).
 // A pair is rotated when |g_a . g_b| > tol * |g_a| |g_b|; sweeps stop after a sweep
-// without rotations.  At convergence G = U S (V not needed for merges, which
+// without rotations.  Pairs whose two columns both had a squared norm below
+// 1e-12 of the largest at the start of the sweep are skipped: such columns can
+// only matter through their rotations against larger columns, which still run.
+// Once converged, the skip is accepted only if the kept columns are all large,
+// exceed the Frobenius norm of the small ones, and the rank rule provably
+// excludes the small part; otherwise full sweeps continue from that state.  At convergence G = U S (V not needed for merges, which
 // drop the right factors); the optional accumulated rotations give V.
 // Columns are then sorted by norm, the truncation rule picks the rank r, and the
 // normalised left vectors, singular values and (optionally) V are written.
@@ -70,7 +75,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     double* d = V + (with_v ? (int64_t)maxdim * ldg : 0);
     double* sig = d + maxdim + 1;
     int* perm = (int*)(sig + maxdim);
-    __shared__ int s_nr, s_nc, s_r1, s_r2, s_rot, s_bad, s_rank;
+    __shared__ int s_nr, s_nc, s_r1, s_r2, s_rot, s_bad, s_rank, s_safe;
+    __shared__ unsigned char sflag[128];
+    __shared__ double s_dmax;
 
     if (tid == 0) {
         int nr, nc, r1 = 0, r2 = 0;
@@ -124,14 +131,22 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     __syncthreads();
 
     // ---- one-sided Jacobi sweeps
+    // Round-robin tournament on N = nc rounded up to even players (player N-1 fixed):
+    // in round r group g pairs a = (r + g) mod (N-1) (a = r for g = 0) with
+    // b = (r - g) mod (N-1) (b = N-1 for g = 0); indices advance by one per round.
     const int N = nc + (nc & 1);
     const int npairs = N >> 1;
     int gsz = 64;
-    while (gsz > 1 && gsz * npairs > nth) gsz >>= 1;
+    while (gsz > 16 && gsz * npairs > nth) gsz >>= 1;
     const int grp = tid / gsz, gl = tid - grp * gsz;
+    constexpr int TMAX = 8;                         // rows per lane: nr <= 128, gsz >= 16
     const double tol = (double)(nr > 1 ? nr : 1) * kEps;
+    const double tol2 = tol * tol;
+    constexpr double kSkip2 = 1e-12;               // (1e-6)^2 relative squared norm
     bool converged = (nc <= 1) || s_bad;
+    bool skip = true;
     int sweep = 0;
+  resume:
     for (; sweep < max_sweeps && !converged; ++sweep) {
         for (int j = wave; j < nc; j += nw) {
             double s = 0.0;
@@ -144,33 +159,59 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         }
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        if (wave == 0) {
+            double mx = 0.0;
+            for (int j = lane64; j < nc; j += 64) mx = fmax(mx, d[j]);
+            mx = wave_max(mx);
+            for (int j = lane64; j < nc; j += 64) sflag[j] = skip && (d[j] <= kSkip2 * mx);
+        }
+        __syncthreads();
+        int a = (grp == 0) ? 0 : grp;
+        int b = (grp == 0) ? N - 1 : N - 1 - grp;
         for (int round = 0; round < N - 1; ++round) {
             if (grp < npairs) {
-                int a, b;
-                if (grp == 0) { a = round; b = N - 1; }
-                else { a = (round + grp) % (N - 1); b = (round + N - 1 - grp) % (N - 1); }
-                const bool valid = (a < nc) && (b < nc);
-                double c = 0.0;
-                if (valid)
-                    for (int i = gl; i < nr; i += gsz)
-                        c = fma(G[(int64_t)a * ldg + i], G[(int64_t)b * ldg + i], c);
-                c = group_sum(c, gsz);
+                const bool valid = (a < nc) && (b < nc) && !(sflag[a] && sflag[b]);
+                double ra[TMAX], rb[TMAX];
+                double c0 = 0.0, c1 = 0.0;
+                double* ga = G + (int64_t)(valid ? a : 0) * ldg;
+                double* gb = G + (int64_t)(valid ? b : 0) * ldg;
+#pragma unroll
+                for (int t = 0; t < TMAX; ++t) {
+                    const int i = gl + t * gsz;
+                    ra[t] = (valid && i < nr) ? ga[i] : 0.0;
+                    rb[t] = (valid && i < nr) ? gb[i] : 0.0;
+                    if (t & 1) c1 = fma(ra[t], rb[t], c1);
+                    else c0 = fma(ra[t], rb[t], c0);
+                }
+                const double c = group_sum(c0 + c1, gsz);
                 if (valid) {
                     const double da = d[a], db = d[b];
-                    const double na = sqrt(da), nb = sqrt(db);
-                    if (na > 0.0 && nb > 0.0 && fabs(c) > tol * na * nb) {
-                        const double zeta = (db - da) / (2.0 * c);
-                        const double az = fabs(zeta);
-                        const double tt = (az > 1e150) ? 0.5 / zeta
-                                                       : copysign(1.0 / (az + sqrt(1.0 + zeta * zeta)), zeta);
-                        const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                    if (da > 0.0 && db > 0.0 && c * c > tol2 * da * db) {
+                        // tan of the rotation angle: t = sign(dd) g / (|dd| + sqrt(dd^2 + g^2)),
+                        // dd = |g_b|^2 - |g_a|^2, g = 2 g_a.g_b (the smaller root of
+                        // t^2 + 2 (dd/g) t - 1 = 0).
+                        const double dd = db - da, gg = 2.0 * c;
+                        double tt;
+                        if (fmax(fabs(dd), fabs(gg)) < 1e150) {
+                            // the angle only steers convergence: hardware estimates suffice;
+                            // orthogonality comes from the refined cs below
+                            const double x = fma(dd, dd, gg * gg);
+                            const double hyp = x * __builtin_amdgcn_rsq(x);
+                            tt = copysign(1.0, dd) * gg * __builtin_amdgcn_rcp(fabs(dd) + hyp);
+                        } else {
+                            const double zeta = dd / gg, az = fabs(zeta);
+                            tt = (az > 1e150) ? 0.5 / zeta
+                                              : copysign(1.0 / (az + sqrt(1.0 + zeta * zeta)), zeta);
+                        }
+                        const double cs = rsqrt_nr(fma(tt, tt, 1.0));
                         const double sn = cs * tt;
-                        double* ga = G + (int64_t)a * ldg;
-                        double* gb = G + (int64_t)b * ldg;
-                        for (int i = gl; i < nr; i += gsz) {
-                            const double x = ga[i], y = gb[i];
-                            ga[i] = cs * x - sn * y;
-                            gb[i] = sn * x + cs * y;
+#pragma unroll
+                        for (int t = 0; t < TMAX; ++t) {
+                            const int i = gl + t * gsz;
+                            if (i < nr) {
+                                ga[i] = cs * ra[t] - sn * rb[t];
+                                gb[i] = sn * ra[t] + cs * rb[t];
+                            }
                         }
                         if (accv) {
                             double* va = V + (int64_t)a * ldg;
@@ -189,6 +230,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                     }
                 }
             }
+            // advance the tournament
+            if (grp == 0) a = a + 1;
+            else { a = (a + 1 == N - 1) ? 0 : a + 1; b = (b + 1 == N - 1) ? 0 : b + 1; }
             __syncthreads();
         }
         converged = (s_rot == 0);
@@ -199,6 +243,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         if (s_bad) f |= 1u;
         if (!converged) f |= 2u;
         if (f) atomicOr(flags, f);
+        atomicMax(flags + 1, (unsigned)sweep);
     }
 
     // ---- singular values (exact column norms), sort descending
@@ -226,9 +271,45 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     if (tid == 0) {
         const int r = s_bad ? 0 : select_rank(sig, nc, t, iws, nr);
         s_rank = r;
-        if (t.rank_out >= 0) iws[t.rank_out] = r;
+        // accept the skipped small-small rotations only if they cannot change the result
+        int safe = 1;
+        if (skip && r > 0 && nc > 1) {
+            const double dmax = sig[0] * sig[0];
+            double small2 = 0.0;
+            int any_small = 0;
+            for (int j = 0; j < nc; ++j)
+                if (d[j] * d[j] <= kSkip2 * dmax) { small2 += d[j] * d[j]; any_small = 1; }
+            if (any_small) {
+                for (int i = 0; i < r; ++i)
+                    if (sig[i] * sig[i] <= kSkip2 * dmax) safe = 0;
+                const double sm = sqrt(small2);
+                if (!(sm < sig[r - 1])) safe = 0;
+                int cap = t.kcap;
+                if (t.fixed_rank_slot >= 0) cap = min(cap, iws[t.fixed_rank_slot]);
+                if (r < cap) {
+                    const int fr = t.floor_rows, fc = t.floor_cols < 0 ? nc : t.floor_cols;
+                    const double floor = (double)(fr > fc ? fr : fc) * kEps * sig[0];
+                    bool excluded = sm <= floor;
+                    if (t.fixed_rank_slot < 0 && t.rule == 0) excluded = excluded || sm < t.tol * sig[0];
+                    if (t.fixed_rank_slot < 0 && t.rule == 1) {
+                        double total = 0.0;
+                        for (int i = nc - 1; i >= 0; --i) total += sig[i] * sig[i];
+                        excluded = excluded || small2 <= t.tol * t.tol * total;
+                    }
+                    if (!excluded) safe = 0;
+                }
+            }
+        }
+        s_safe = safe;
+        if (safe && t.rank_out >= 0) iws[t.rank_out] = r;
     }
     __syncthreads();
+    if (!s_safe) {                 // redo with full sweeps from the current state
+        skip = false;
+        converged = false;
+        __syncthreads();
+        goto resume;
+    }
     const int r = s_rank;
 
     // ---- outputs

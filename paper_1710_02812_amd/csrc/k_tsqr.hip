@@ -1,26 +1,32 @@
-// Tall-skinny Householder QR (TSQR) for h x w panels, w <= 96.
+// Tall-skinny Householder QR (TSQR) for h x w panels, w <= 80, chunks of 256 rows
+// (w <= 64) or 160 rows (w <= 80).
 //
 // Factor: each row chunk of `ch` rows is loaded into LDS and reduced by w
 // Householder reflectors (LAPACK dlarfg convention: H = I - tau v v^T, v_j = 1,
-// R_jj = beta).  The chunk's reflectors go back into the panel and its R into the
-// tree storage.  R factors are then merged pairwise up a binary tree by QR of the
-// stacked [R_left; R_right] (2w x w); the work-group that finishes second on a
-// pair performs the merge (an atomic counter per node, reset by that group), so
-// the whole tree runs in one launch without any group waiting on another.  An
-// odd last node is "merged" with a zero sibling, which yields tau = 0 (identity).
+// R_jj = beta).  The chunk's reflectors go back into the panel; its R, tau and the
+// compact-WY factor T (w x w upper triangular, Q = H_0 ... H_{w-1} = I - V T V^T,
+// dlarft forward/columnwise) go into the tree storage.  R factors are then merged
+// pairwise up a binary tree by QR of the stacked [R_left; R_right] (2w x w); the
+// work-group that finishes second on a pair performs the merge (an atomic counter
+// per node, reset by that group), so the whole tree runs in one launch and no
+// group waits on another.  An odd last node is merged with a zero sibling, which
+// gives tau = 0 (identity).
 //
 // Apply: out = Q [X; 0] for the explicit thin factor Q (h x w).  Each chunk's
-// group walks from the root to its chunk, applying every node's reflectors to
-// [X; 0] and keeping the half that belongs to its child, then applies the chunk
-// reflectors.  Optionally adds U1 * T (the merge's U1 U_E,top term).
+// group walks from the root to its chunk; at every node [X; 0] - V (T (V_top^T X))
+// gives the node's 2w rows, of which the half belonging to the child is kept;
+// at the chunk the same three small products give the output rows.  Optionally
+// adds U1 * Tm (the merge's U1 U_E,top term).
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
 
 namespace hsvd {
 
-constexpr int TSQR_THREADS = 256;
+constexpr int TSQR_THREADS = 1024;
 
-__device__ __forceinline__ int64_t node_slot_size(int w) { return 3LL * w * w + w; }
+// Node slot layout: R (w*w) | V (2w*w) | tau (w) | T (w*w)
+__device__ __forceinline__ int64_t slot_tau(int w) { return 3LL * w * w; }
+__device__ __forceinline__ int64_t slot_T(int w) { return 3LL * w * w + w; }
 
 // Slot index of tree node (level, idx) given the chunk count.
 __device__ __forceinline__ int node_slot(int nch, int level, int idx) {
@@ -29,82 +35,195 @@ __device__ __forceinline__ int node_slot(int nch, int level, int idx) {
     return off + idx;
 }
 
-// Householder QR of the rows x w matrix in LDS (column stride lds), in place.
-__device__ void house_qr_lds(double* A, int lds, int rows, int w, double* tau, double* red) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
-    const int kmax = rows < w ? rows : w;
-    for (int j = 0; j < kmax; ++j) {
-        double* aj = A + (int64_t)j * lds;
-        double s = 0.0;
-        for (int i = j + 1 + tid; i < rows; i += nth) s += aj[i] * aj[i];
-        s = block_sum(s, red);
-        const double alpha = aj[j];
-        double beta = alpha, tj = 0.0, scal = 0.0;
-        if (s > 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + s), alpha);
-            tj = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
+// Element (i, l) of the reflector block V whose strictly-lower part is stored in
+// the column-major array A (ld) with the unit diagonal implicit.
+__device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l) {
+    return i == l ? 1.0 : (i > l ? A[(int64_t)l * ld + i] : 0.0);
+}
+
+// Register-resident Householder QR of one rows x w block (rows <= LANES * RMAX,
+// w <= 1024 / LANES) with 1024 threads = groups of LANES lanes.  Column c lives in
+// the registers of group c, row r in lane r % LANES (index r / LANES), so the
+// trailing matrix never travels through LDS; per step only the pivot reflector is
+// broadcast through LDS.
+//
+// Step j, phase 1: the owner of column j takes alpha = A_jj and the below-diagonal
+// norm (left in LDS by step j-1), forms beta, tau_j and v_j (dlarfg convention:
+// H = I - tau v v^T, v_j = 1, R_jj = beta) and publishes v_j; meanwhile the other
+// groups finish column j-1 of the compact-WY factor T (dlarft forward/columnwise:
+// T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] z with z = V[:, 0:j]^T v_j).
+// Phase 2: every other column c forms v_j^T a_c; c > j is updated (c = j + 1 also
+// leaves its next norm), c < j yields z_c.  Two barriers per step.
+template <int LANES, int RMAX>
+struct HouseQR {
+    static constexpr int NG = 1024 / LANES;
+    double x[RMAX];
+
+    __device__ static double gsum(double v) { return LANES == 16 ? sum16(v) : sum8(v); }
+
+    __device__ void load(const double* src, int64_t ld, int rows, int w) {
+        const int c = threadIdx.x / LANES, gl = threadIdx.x % LANES;
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+            const int r = gl + LANES * t;
+            x[t] = (c < w && r < rows) ? src[(int64_t)c * ld + r] : 0.0;
         }
-        __syncthreads();
-        if (s > 0.0)
-            for (int i = j + 1 + tid; i < rows; i += nth) aj[i] *= scal;
-        if (tid == 0) { aj[j] = beta; tau[j] = tj; }
-        __syncthreads();
-        if (tj != 0.0) {
-            for (int c = j + 1 + wave; c < w; c += nw) {
-                double* ac = A + (int64_t)c * lds;
-                double d = (lane == 0) ? ac[j] : 0.0;
-                for (int i = j + 1 + lane; i < rows; i += 64) d += aj[i] * ac[i];
-                d = wave_sum(d);
-                const double f = tj * d;
-                if (lane == 0) ac[j] -= f;
-                for (int i = j + 1 + lane; i < rows; i += 64) ac[i] -= f * aj[i];
+    }
+
+    // writes the factored block (R above/on the diagonal, reflectors below)
+    __device__ void store(double* dst, int64_t ld, int rows, int w) const {
+        const int c = threadIdx.x / LANES, gl = threadIdx.x % LANES;
+        if (c >= w) return;
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+            const int r = gl + LANES * t;
+            if (r < rows) dst[(int64_t)c * ld + r] = x[t];
+        }
+    }
+
+    // R (w x w, col-major ld w): upper triangle of the first min(rows, w) rows
+    __device__ void store_r(double* R, int rows, int w) const {
+        const int c = threadIdx.x / LANES, gl = threadIdx.x % LANES;
+        if (c >= w) return;
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+            const int r = gl + LANES * t;
+            if (r < w) R[(int64_t)c * w + r] = (r <= c && r < rows) ? x[t] : 0.0;
+        }
+    }
+
+    // T column j (rows i < j from z in ztmp; T_jj = tau_j).  The calling groups
+    // number themselves vg = 0..ng-1 and stride over the rows.
+    __device__ static void t_column(double* T, int ldt, int j, const double* ztmp, double tj,
+                                    int vg, int ng) {
+        const int gl = threadIdx.x % LANES;
+        for (int i = vg; i < j; i += ng) {
+            double d = 0.0;
+            for (int l = i + gl; l < j; l += LANES) d = fma(T[(int64_t)l * ldt + i], ztmp[l], d);
+            d = gsum(d);
+            if (gl == 0) T[(int64_t)j * ldt + i] = -tj * d;
+        }
+        if (vg == 0 && gl == 0) T[(int64_t)j * ldt + j] = tj;
+    }
+
+    // lds scratch: T (w x (w+1)), tau (w), nrm (w), z (2w), vbuf (16 * RMAX)
+    __device__ void factor(int rows, int w, double* T, double* tau, double* nrm, double* z,
+                           double* vbuf) {
+        const int tid = threadIdx.x, nth = blockDim.x;
+        const int grp = tid / LANES, gl = tid % LANES;
+        const int kmax = rows < w ? rows : w;
+        const int ldt = w + 1;
+        for (int e = tid; e < w * ldt; e += nth) T[e] = 0.0;
+        if (grp == 0) {                                // norm of column 0 below the diagonal
+            double s2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < RMAX; ++t) {
+                const int r = gl + LANES * t;
+                if (r > 0) s2 = fma(x[t], x[t], s2);
             }
+            s2 = gsum(s2);
+            if (gl == 0) nrm[0] = s2;
         }
         __syncthreads();
-    }
-    for (int j = kmax + tid; j < w; j += nth) tau[j] = 0.0;
-    __syncthreads();
-}
-
-// Y (rows x c in LDS, stride ldy) <- H_0 ... H_{w-1} Y with reflectors v_j taken from
-// `V` (column j at V + j*ldv, rows j+1.. below the implicit unit) and tau.
-// `V` may be global or LDS memory.
-__device__ void apply_q_lds(const double* V, int64_t ldv, const double* tau, int rows, int w,
-                            double* Y, int ldy, int c) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int kmax = rows < w ? rows : w;
-    for (int j = kmax - 1; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj == 0.0) continue;                    // uniform across the group
-        const double* vj = V + (int64_t)j * ldv;
-        for (int cc = wave; cc < c; cc += nw) {
-            double* yc = Y + (int64_t)cc * ldy;
-            double d = (lane == 0) ? yc[j] : 0.0;
-            for (int i = j + 1 + lane; i < rows; i += 64) d += vj[i] * yc[i];
-            d = wave_sum(d);
-            const double f = tj * d;
-            if (lane == 0) yc[j] -= f;
-            for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= f * vj[i];
+        for (int j = 0; j < kmax; ++j) {
+            const int og = j;
+            // ---- phase 1
+            if (grp == og) {
+                double a = 0.0;
+#pragma unroll
+                for (int t = 0; t < RMAX; ++t)
+                    if (gl + LANES * t == j) a = x[t];
+                const double alpha = gsum(a);
+                const double sq = nrm[j];
+                double beta = alpha, tj = 0.0, scal = 0.0;
+                if (sq > 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + sq), alpha);
+                    tj = (beta - alpha) / beta;
+                    scal = 1.0 / (alpha - beta);
+                }
+#pragma unroll
+                for (int t = 0; t < RMAX; ++t) {
+                    const int r = gl + LANES * t;
+                    double v = 0.0;
+                    if (r == j) { x[t] = beta; v = 1.0; }
+                    else if (r > j) { if (sq > 0.0) x[t] *= scal; v = x[t]; }
+                    if (r < rows) vbuf[r] = v;
+                }
+                if (gl == 0) tau[j] = tj;
+            } else if (j > 0) {                        // the 63 other groups, renumbered
+                t_column(T, ldt, j - 1, z + ((j - 1) & 1) * w, tau[j - 1], grp < og ? grp : grp - 1, NG - 1);
+            }
+            __syncthreads();
+            // ---- phase 2
+            const double tj = tau[j];
+            double* zj = z + (j & 1) * w;
+            const int c = grp;
+            if (c < w && c != j) {
+                if (tj == 0.0) {
+                    if (c == j + 1) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int t = 0; t < RMAX; ++t) {
+                            const int r = gl + LANES * t;
+                            if (r > j + 1 && r < rows) s2 = fma(x[t], x[t], s2);
+                        }
+                        s2 = gsum(s2);
+                        if (gl == 0) nrm[j + 1] = s2;
+                    }
+                    if (c < j && gl == 0) zj[c] = 0.0;
+                } else {
+                    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < RMAX; ++t) {
+                        const int r = gl + LANES * t;
+                        if (r >= j && r < rows) {
+                            if (t & 1) d1 = fma(vbuf[r], x[t], d1);
+                            else d0 = fma(vbuf[r], x[t], d0);
+                        }
+                    }
+                    const double d = gsum(d0 + d1);
+                    if (c < j) {
+                        if (gl == 0) zj[c] = d;
+                    } else {
+                        const double f = tj * d;
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int t = 0; t < RMAX; ++t) {
+                            const int r = gl + LANES * t;
+                            if (r >= j && r < rows) {
+                                x[t] = fma(-f, vbuf[r], x[t]);
+                                if (r > j + 1) s2 = fma(x[t], x[t], s2);
+                            }
+                        }
+                        if (c == j + 1) {
+                            s2 = gsum(s2);
+                            if (gl == 0) nrm[j + 1] = s2;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
         }
+        if (kmax > 0) t_column(T, ldt, kmax - 1, z + ((kmax - 1) & 1) * w, tau[kmax - 1], grp, NG);
+        for (int j = kmax + tid; j < w; j += nth) tau[j] = 0.0;
         __syncthreads();
     }
-    __syncthreads();
-}
+};
 
+template <int LANES, int RMAX>
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
                                                               const TsqrTask* __restrict__ tasks,
                                                               const ChunkRef* __restrict__ chunks,
                                                               int w, int ch) {
     extern __shared__ double sm[];
-    const int lds = (ch > 2 * w ? ch : 2 * w) + 1;
-    double* A = sm;
-    double* tau = A + (int64_t)w * lds;
-    double* red = tau + w + 1;
+    double* T = sm;                                  // w x (w + 1)
+    double* tau = T + (int64_t)w * (w + 1);
+    double* nrm = tau + w;
+    double* z = nrm + w;                             // 2w
+    double* vbuf = z + 2 * w;                        // 16 * RMAX
     __shared__ int s_go;
+    HouseQR<LANES, RMAX> q;
 
     const ChunkRef cr = chunks[blockIdx.x];
     const TsqrTask t = tasks[cr.task];
@@ -113,30 +232,22 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
     const int rows = min(ch, t.h - row0);
     double* P = ws + t.p_off;
     double* store = ws + t.store_off;
-    const int64_t S = node_slot_size(w);
+    const int64_t S = tsqr_slot_size(w);
 
-    for (int e = tid; e < rows * w; e += nth) {
-        const int j = e / rows, i = e - j * rows;
-        A[(int64_t)j * lds + i] = P[(int64_t)j * t.p_ld + row0 + i];
-    }
-    __syncthreads();
-    house_qr_lds(A, lds, rows, w, tau, red);
-
-    // chunk reflectors back into the panel, R and tau into the node slot
-    for (int e = tid; e < rows * w; e += nth) {
-        const int j = e / rows, i = e - j * rows;
-        P[(int64_t)j * t.p_ld + row0 + i] = A[(int64_t)j * lds + i];
-    }
+    q.load(P + row0, t.p_ld, rows, w);
+    q.factor(rows, w, T, tau, nrm, z, vbuf);
+    q.store(P + row0, t.p_ld, rows, w);
     {
         double* slot = store + S * node_slot(t.nch, 0, cr.chunk);
+        q.store_r(slot, rows, w);
         for (int e = tid; e < w * w; e += nth) {
             const int j = e / w, i = e - j * w;
-            slot[e] = (i <= j && i < rows) ? A[(int64_t)j * lds + i] : 0.0;
+            slot[slot_T(w) + e] = T[(int64_t)j * (w + 1) + i];
         }
-        for (int j = tid; j < w; j += nth) slot[3 * w * w + j] = tau[j];
+        for (int j = tid; j < w; j += nth) slot[slot_tau(w) + j] = tau[j];
     }
-
     int level = 0, idx = cr.chunk, n = t.nch;
+    int last_rows = rows;
     while (n > 1) {
         const int parent = idx >> 1;
         const bool has_sib = ((idx ^ 1) < n);
@@ -153,40 +264,74 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
             if (!s_go) return;
         }
         __threadfence();
-        // stack [R_left; R_right (or 0)] -> 2w x w
-        const int left = parent * 2, right = left + 1;
+        // stack [R_left; R_right (or 0)] -> 2w x w, straight into registers
+        const int left = parent * 2;
         const double* Rl = store + S * node_slot(t.nch, level, left);
-        const double* Rr = has_sib ? store + S * node_slot(t.nch, level, right) : nullptr;
-        for (int e = tid; e < 2 * w * w; e += nth) {
-            const int j = e / (2 * w), i = e - j * (2 * w);
-            double v;
-            if (i < w) v = Rl[(int64_t)j * w + i];
-            else v = Rr ? Rr[(int64_t)j * w + (i - w)] : 0.0;
-            A[(int64_t)j * lds + i] = v;
+        const double* Rr = has_sib ? store + S * node_slot(t.nch, level, left + 1) : nullptr;
+        {
+            const int c = tid / LANES, gl = tid % LANES;
+#pragma unroll
+            for (int tt = 0; tt < RMAX; ++tt) {
+                const int r = gl + LANES * tt;
+                double v = 0.0;
+                if (c < w && r < 2 * w) {
+                    if (r < w) v = Rl[(int64_t)c * w + r];
+                    else if (Rr) v = Rr[(int64_t)c * w + (r - w)];
+                }
+                q.x[tt] = v;
+            }
         }
-        __syncthreads();
-        house_qr_lds(A, lds, 2 * w, w, tau, red);
+        q.factor(2 * w, w, T, tau, nrm, z, vbuf);
         double* slot = store + S * node_slot(t.nch, level + 1, parent);
+        q.store_r(slot, 2 * w, w);
+        q.store(slot + w * w, 2 * w, 2 * w, w);
         for (int e = tid; e < w * w; e += nth) {
             const int j = e / w, i = e - j * w;
-            slot[e] = (i <= j) ? A[(int64_t)j * lds + i] : 0.0;
+            slot[slot_T(w) + e] = T[(int64_t)j * (w + 1) + i];
         }
-        for (int e = tid; e < 2 * w * w; e += nth) {
-            const int j = e / (2 * w), i = e - j * (2 * w);
-            slot[w * w + e] = A[(int64_t)j * lds + i];
-        }
-        for (int j = tid; j < w; j += nth) slot[3 * w * w + j] = tau[j];
+        for (int j = tid; j < w; j += nth) slot[slot_tau(w) + j] = tau[j];
+        last_rows = 2 * w;
         ++level;
         idx = parent;
         n = (n + 1) >> 1;
     }
-    // root: its factorisation is the last one this group ran, still in LDS
-    double* R = ws + t.r_out;
-    const int rr = (t.nch == 1) ? rows : 2 * w;
-    for (int e = tid; e < w * w; e += nth) {
-        const int j = e / w, i = e - j * w;
-        R[e] = (i <= j && i < rr) ? A[(int64_t)j * lds + i] : 0.0;
+    q.store_r(ws + t.r_out, last_rows, w);
+}
+
+// Dense copy of rows [r0, r0 + nrows) of the reflector block V (unit diagonal,
+// zeros above) into LDS as Vs[l * ldvs + (i - r0)].
+__device__ void stage_v(const double* V, int64_t ldv, int r0, int nrows, int w, double* Vs,
+                        int ldvs) {
+    for (int e = threadIdx.x; e < nrows * w; e += blockDim.x) {
+        const int l = e / nrows, i = e - l * nrows;
+        Vs[(int64_t)l * ldvs + i] = vref(V, ldv, r0 + i, l);
     }
+}
+
+// One compact-WY level on LDS operands: W1 = V_top^T X (V_top staged in Vs, ld w),
+// then W2 = T W1 (T from global, col-major ld w) written back over W1
+// (w * c <= 8 * blockDim.x).
+__device__ void wy_w(const double* Vs, const double* Tg, const double* X, double* W, int w, int c) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int e = tid; e < w * c; e += nth) {
+        const int cc = e / w, l = e - cc * w;
+        double d = 0.0;
+        for (int i = l; i < w; ++i) d = fma(Vs[(int64_t)l * w + i], X[(int64_t)cc * w + i], d);
+        W[e] = d;
+    }
+    __syncthreads();
+    double r[8];
+    int cnt = 0;
+    for (int e = tid; e < w * c; e += nth, ++cnt) {
+        const int cc = e / w, i = e - cc * w;
+        double d = 0.0;
+        for (int l = i; l < w; ++l) d = fma(Tg[(int64_t)l * w + i], W[(int64_t)cc * w + l], d);
+        r[cnt] = d;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < w * c; e += nth, ++cnt) W[e] = r[cnt];
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict__ ws,
@@ -195,102 +340,111 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                                                              const ChunkRef* __restrict__ chunks,
                                                              int w, int ch, int c) {
     extern __shared__ double sm[];
-    const int ldy = (ch > 2 * w ? ch : 2 * w) + 1;
-    double* Y = sm;                                  // ldy x c
-    double* taus = Y + (int64_t)c * ldy;             // w
+    double* X = sm;                                  // w x c (ld w)
+    double* W = X + (int64_t)w * c;                  // w x c
+    double* Vs = W + (int64_t)w * c;                 // w x w staged reflector rows
     const ChunkRef cr = chunks[blockIdx.x];
     const ApplyTask a = tasks[cr.task];
     const TsqrTask t = tsqr[a.tsqr];
     const int tid = threadIdx.x, nth = blockDim.x;
     const double* store = ws + t.store_off;
-    const int64_t S = node_slot_size(w);
+    const int64_t S = tsqr_slot_size(w);
 
-    // X -> top of Y
-    const double* X = ws + a.x_off;
-    for (int e = tid; e < w * c; e += nth) {
-        const int j = e / w, i = e - j * w;
-        Y[(int64_t)j * ldy + i] = X[(int64_t)j * w + i];
-    }
-    // levels: count
+    const double* Xg = ws + a.x_off;
+    for (int e = tid; e < w * c; e += nth) X[e] = Xg[e];
     int levels = 0;
     for (int n = t.nch; n > 1; n = (n + 1) >> 1) ++levels;
     for (int level = levels; level >= 1; --level) {
         const int idx = cr.chunk >> level;
-        const int child = cr.chunk >> (level - 1);
+        const bool right = (cr.chunk >> (level - 1)) & 1;
         const double* slot = store + S * node_slot(t.nch, level, idx);
-        for (int e = tid; e < w * c; e += nth) {
-            const int j = e / w, i = e - j * w;
-            Y[(int64_t)j * ldy + w + i] = 0.0;
-        }
-        for (int j = tid; j < w; j += nth) taus[j] = slot[3 * w * w + j];
+        const double* V = slot + w * w;              // 2w x w, ld 2w
+        stage_v(V, 2 * w, 0, w, w, Vs, w);
         __syncthreads();
-        apply_q_lds(slot + w * w, 2 * w, taus, 2 * w, w, Y, ldy, c);
-        if (child & 1) {   // keep the bottom half
-            for (int e = tid; e < w * c; e += nth) {   // disjoint rows: no hazard
-                const int j = e / w, i = e - j * w;
-                Y[(int64_t)j * ldy + i] = Y[(int64_t)j * ldy + w + i];
-            }
+        wy_w(Vs, slot + slot_T(w), X, W, w, c);
+        if (right) {
+            stage_v(V, 2 * w, w, w, w, Vs, w);
+            __syncthreads();
+        }
+        for (int e = tid; e < w * c; e += nth) {
+            const int cc = e / w, i = e - cc * w;
+            double d = right ? 0.0 : X[e];
+            for (int l = 0; l < w; ++l) d = fma(-Vs[(int64_t)l * w + i], W[(int64_t)cc * w + l], d);
+            X[e] = d;                                  // each entry reads only itself from X
         }
         __syncthreads();
     }
-    // chunk level
+    // chunk level: out = [X; 0] - V (T (V_top^T X)) over the chunk rows
     const int row0 = cr.chunk * ch;
     const int rows = min(ch, t.h - row0);
-    for (int e = tid; e < (rows - w > 0 ? rows - w : 0) * c; e += nth) {
-        const int span = rows - w;
-        const int j = e / span, i = e - j * span;
-        Y[(int64_t)j * ldy + w + i] = 0.0;
-    }
-    {
-        const double* cslot = store + S * node_slot(t.nch, 0, cr.chunk);
-        for (int j = tid; j < w; j += nth) taus[j] = cslot[3 * w * w + j];
-    }
-    __syncthreads();
     const double* Vc = ws + t.p_off + row0;
-    apply_q_lds(Vc, t.p_ld, taus, rows, w, Y, ldy, c);
+    const double* cslot = store + S * node_slot(t.nch, 0, cr.chunk);
+    const int vtop = rows < w ? rows : w;
+    stage_v(Vc, t.p_ld, 0, vtop, w, Vs, w);
+    for (int e = tid; e < (w - vtop) * w; e += nth) {     // rows past a short chunk: zero
+        const int l = e / (w - vtop), i = vtop + e - l * (w - vtop);
+        Vs[(int64_t)l * w + i] = 0.0;
+    }
     __syncthreads();
+    wy_w(Vs, cslot + slot_T(w), X, W, w, c);
     double* out = ws + a.out_off;
-    if (a.add_u_off >= 0) {
-        const double* U1 = ws + a.add_u_off;
-        const double* T = ws + a.add_t_off;
-        for (int e = tid; e < rows * c; e += nth) {
-            const int j = e / rows, i = e - j * rows;
-            double v = Y[(int64_t)j * ldy + i];
-            for (int l = 0; l < a.add_w; ++l)
-                v = fma(U1[(int64_t)l * a.add_u_ld + row0 + i], T[(int64_t)j * a.add_w + l], v);
-            out[(int64_t)j * a.out_ld + row0 + i] = v;
+    const double* U1 = a.add_u_off >= 0 ? ws + a.add_u_off : nullptr;
+    const double* Tm = a.add_u_off >= 0 ? ws + a.add_t_off : nullptr;
+    for (int r0 = 0; r0 < rows; r0 += w) {
+        const int nrow = min(w, rows - r0);
+        if (r0 > 0) {
+            __syncthreads();
+            stage_v(Vc, t.p_ld, r0, nrow, w, Vs, w);
+            __syncthreads();
         }
-    } else {
-        for (int e = tid; e < rows * c; e += nth) {
-            const int j = e / rows, i = e - j * rows;
-            out[(int64_t)j * a.out_ld + row0 + i] = Y[(int64_t)j * ldy + i];
+        for (int e = tid; e < nrow * c; e += nth) {
+            const int cc = e / nrow, ii = e - cc * nrow;
+            const int i = r0 + ii;
+            double d = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
+            for (int l = 0; l < w; ++l) d = fma(-Vs[(int64_t)l * w + ii], W[(int64_t)cc * w + l], d);
+            if (U1)
+                for (int l = 0; l < a.add_w; ++l)
+                    d = fma(U1[(int64_t)l * a.add_u_ld + row0 + i], Tm[(int64_t)cc * a.add_w + l], d);
+            out[(int64_t)cc * a.out_ld + row0 + i] = d;
         }
     }
 }
 
-static size_t tsqr_lds_bytes(int w, int ch, int c) {
-    const int ld = (ch > 2 * w ? ch : 2 * w) + 1;
-    const int cols = c > w ? c : w;
-    return sizeof(double) * ((size_t)cols * ld + w + 1 + 16);
+static size_t factor_lds_bytes(int w, int rmax) {
+    return sizeof(double) * ((size_t)w * (w + 1) + 4 * (size_t)w + 16 * (size_t)rmax + 32);
+}
+
+template <int LANES, int RMAX>
+static hipError_t launch_factor_t(double* ws, int* iws, const TsqrTask* tasks,
+                                  const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s) {
+    const size_t lds = factor_lds_bytes(w, RMAX);
+    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX>), dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws,
+                       iws, tasks, chunks, w, ch);
+    return hipGetLastError();
 }
 
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const ChunkRef* chunks,
                               int nchunks, int w, int ch, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    const size_t lds = tsqr_lds_bytes(w, ch, w);
-    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tsqr_factor, dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws, iws, tasks,
-                       chunks, w, ch);
-    return hipGetLastError();
+    if (w < 1 || w > kTsqrMaxW || ch != tsqr_chunk_rows(w)) return hipErrorInvalidValue;
+    // a chunk and a stacked pair of R factors must fit the register block
+    if (w <= 64) {
+        if (ch > 16 * 16 || 2 * w > 16 * 16) return hipErrorInvalidValue;
+        return launch_factor_t<16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+    }
+    if (ch > 8 * 20 || 2 * w > 8 * 20) return hipErrorInvalidValue;
+    return launch_factor_t<8, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
 hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    const size_t lds = tsqr_lds_bytes(w, ch, c);
+    const size_t lds = sizeof(double) * (2 * (size_t)w * c + (size_t)w * w + 32);
+    if (w * c > 8 * TSQR_THREADS) return hipErrorInvalidValue;   // wy_w keeps 8 values per thread
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_apply,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

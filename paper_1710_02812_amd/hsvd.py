@@ -186,6 +186,7 @@ def svd(A, p: int, q: int, k: int, tol: float = 0.0, **opts):
     r = plan.rank()
     flags = plan.status()
     plan.close()
+    flags &= 0xFFFF
     if flags:
         raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
     return U, S, Vt, r
@@ -203,7 +204,8 @@ def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True):
     _check(lib().hsvd_debug_jacobi(Mc.data_ptr(), b, n, U.data_ptr(), S.data_ptr(),
                                    V.data_ptr() if with_v else None, max_sweeps,
                                    ctypes.byref(fl), _stream_handle()))
-    return (U.transpose(1, 2), S, V.transpose(1, 2) if with_v else None, fl.value)
+    return (U.transpose(1, 2), S, V.transpose(1, 2) if with_v else None, fl.value & 0xFFFF,
+            fl.value >> 16)
 
 
 def plan_check(m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, **opts) -> int:
