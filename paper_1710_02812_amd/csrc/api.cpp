@@ -323,6 +323,7 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         c.rank_out = o.rank;
         c.floor_rows = h;
         c.floor_cols = -1;
+        c.precond = 1;
         cores.push_back(c);
         ApplyTask ap{};
         ap.tsqr = ti;

@@ -40,9 +40,11 @@ int pow2floor(int x) {
 
 extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double* U,
                                          double* S, double* V, int32_t max_sweeps,
-                                         uint32_t* flags_host, hipStream_t stream) {
+                                         int32_t precondition, uint32_t* flags_host,
+                                         hipStream_t stream) {
     using hsvd_detail::set_error;
-    if (!M || !U || !S || batch < 1 || n < 1 || n > 128 || (V && n > 64) || max_sweeps < 1)
+    if (!M || !U || !S || batch < 1 || n < 1 || n > 128 || (V && n > 64) || max_sweeps < 1 ||
+        (precondition != 0 && precondition != 1) || (precondition && V))
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_jacobi: bad argument");
     Scratch sc;
     const int64_t nn = (int64_t)n * n;
@@ -77,6 +79,7 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
         c.floor_rows = 0;
         c.floor_cols = -1;
         c.fixed_rank_slot = -1;
+        c.precond = precondition;
         // keep every nonzero column: rank = count above a zero floor of 0
         tasks[b] = c;
     }

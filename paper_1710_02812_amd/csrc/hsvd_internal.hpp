@@ -46,7 +46,7 @@ constexpr int kTsqrMaxW = 80;
 // Per-node storage: R (w*w) | V (2w*w) | tau (w) | T (w*w).
 __host__ __device__ inline int64_t tsqr_slot_size(int w) { return 4LL * w * w + w; }
 // Rows per chunk: the factor kernel holds a chunk (or a stacked 2w x w pair of R
-// factors) in registers: 16 lanes x 16 rows per column (w <= 64) or 8 lanes x 20
+// factors) in registers: 16 lanes x 12 rows per column (w <= 64) or 8 lanes x 20
 // rows (w <= 80; a stacked pair needs 2w <= 160 rows).
 inline int tsqr_chunk_rows(int w) { return w <= 64 ? 256 : 160; }
 
@@ -105,7 +105,7 @@ struct CoreTask {
     int32_t floor_rows;            // zero-floor shape: max(floor_rows, floor_cols or r1+r2)
     int32_t floor_cols;            // < 0: use the active core size
     int32_t fixed_rank_slot;       // >= 0: rank = min(zero-floor count, ranks[slot])
-    int32_t pad;
+    int32_t precond;               // 1: LQ-precondition (left vectors only; needs v_off < 0)
 };
 
 // ---------------------------------------------------------------- output

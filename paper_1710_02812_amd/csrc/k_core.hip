@@ -15,12 +15,20 @@
 // only matter through their rotations against larger columns, which still run.
 // Once converged, the skip is accepted only if the kept columns are all large,
 // exceed the Frobenius norm of the small ones, and the rank rule provably
-// excludes the small part; otherwise full sweeps continue from that state.  At convergence G = U S (V not needed for merges, which
-// drop the right factors); the optional accumulated rotations give V.
+// excludes the small part; otherwise full sweeps continue from that state.  At
+// convergence G = U S (V not needed for merges, which drop the right factors);
+// the optional accumulated rotations give V.
+//
+// Preconditioning (when only left vectors are wanted): G is first replaced by L
+// of G = L Q (a Householder QR of G^T held in registers).  L has the left singular
+// pairs of G, and its columns are far closer to orthogonal than those of a merge
+// matrix E, whose two halves hold nearly parallel copies of shared directions:
+// on merge cores this halves the number of sweeps.
 // Columns are then sorted by norm, the truncation rule picks the rank r, and the
 // normalised left vectors, singular values and (optionally) V are written.
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
+#include "house_qr.hpp"
 
 namespace hsvd {
 
@@ -69,7 +77,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     const CoreTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane64 = tid & 63, wave = tid >> 6, nw = nth >> 6;
-    const int ldg = maxdim + 1;
+    constexpr int ROWS = 128;                 // every column padded with zeros to 128 rows
+    const int ldg = ROWS + 1;
     double* G = sm;
     double* V = G + (int64_t)maxdim * ldg;
     double* d = V + (with_v ? (int64_t)maxdim * ldg : 0);
@@ -122,13 +131,39 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         if (!finite_d(v)) bad = 1;
         G[(int64_t)j * ldg + i] = v;
     }
+    for (int e = tid; e < nc * (ROWS - nr); e += nth) {
+        const int j = e / (ROWS - nr), i = nr + e - j * (ROWS - nr);
+        G[(int64_t)j * ldg + i] = 0.0;
+    }
     if (accv)
-        for (int e = tid; e < nc * nc; e += nth) {
-            const int j = e / nc, i = e - j * nc;
+        for (int e = tid; e < nc * ROWS; e += nth) {
+            const int j = e / ROWS, i = e - j * ROWS;
             V[(int64_t)j * ldg + i] = (i == j) ? 1.0 : 0.0;
         }
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
+
+    // ---- LQ preconditioning: G = L Q by Householder QR of G^T; the sweeps then
+    // run on L (same left singular pairs).  Group c (8 lanes) holds row c of G as
+    // column c of G^T, lane rows are G's columns; Q is not formed.
+    if (t.precond && !accv && !s_bad && nc > 1) {
+        HouseQR<8, 16, false> q;
+        const int c = tid >> 3, gl = tid & 7;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int r = gl + 8 * s;
+            q.x[s] = (c < nr && r < nc) ? G[(int64_t)r * ldg + c] : 0.0;
+        }
+        // scratch: tau -> sig, norms -> d, pivot broadcast -> the first 128 entries
+        // of G (all of G is in registers by the first barrier inside factor)
+        q.factor(nc, nr, G, sig, d, d, G);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int r = gl + 8 * s;
+            if (r < nc) G[(int64_t)r * ldg + c] = (r <= c) ? q.x[s] : 0.0;
+        }
+        __syncthreads();
+    }
 
     // ---- one-sided Jacobi sweeps
     // Round-robin tournament on N = nc rounded up to even players (player N-1 fixed):
@@ -136,10 +171,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     // b = (r - g) mod (N-1) (b = N-1 for g = 0); indices advance by one per round.
     const int N = nc + (nc & 1);
     const int npairs = N >> 1;
-    int gsz = 64;
-    while (gsz > 16 && gsz * npairs > nth) gsz >>= 1;
+    constexpr int gsz = 16;                         // lanes per pair: 64 groups cover nc <= 128
     const int grp = tid / gsz, gl = tid - grp * gsz;
-    constexpr int TMAX = 8;                         // rows per lane: nr <= 128, gsz >= 16
+    constexpr int TMAX = ROWS / gsz;                // rows per lane, unconditional (zero padded)
     const double tol = (double)(nr > 1 ? nr : 1) * kEps;
     const double tol2 = tol * tol;
     constexpr double kSkip2 = 1e-12;               // (1e-6)^2 relative squared norm
@@ -175,13 +209,17 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 double c0 = 0.0, c1 = 0.0;
                 double* ga = G + (int64_t)(valid ? a : 0) * ldg;
                 double* gb = G + (int64_t)(valid ? b : 0) * ldg;
+                if (valid) {
 #pragma unroll
-                for (int t = 0; t < TMAX; ++t) {
-                    const int i = gl + t * gsz;
-                    ra[t] = (valid && i < nr) ? ga[i] : 0.0;
-                    rb[t] = (valid && i < nr) ? gb[i] : 0.0;
-                    if (t & 1) c1 = fma(ra[t], rb[t], c1);
-                    else c0 = fma(ra[t], rb[t], c0);
+                    for (int t = 0; t < TMAX; ++t) {
+                        ra[t] = ga[gl + t * gsz];
+                        rb[t] = gb[gl + t * gsz];
+                    }
+#pragma unroll
+                    for (int t = 0; t < TMAX; t += 2) {
+                        c0 = fma(ra[t], rb[t], c0);
+                        c1 = fma(ra[t + 1], rb[t + 1], c1);
+                    }
                 }
                 const double c = group_sum(c0 + c1, gsz);
                 if (valid) {
@@ -207,19 +245,22 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                         const double sn = cs * tt;
 #pragma unroll
                         for (int t = 0; t < TMAX; ++t) {
-                            const int i = gl + t * gsz;
-                            if (i < nr) {
-                                ga[i] = cs * ra[t] - sn * rb[t];
-                                gb[i] = sn * ra[t] + cs * rb[t];
-                            }
+                            ga[gl + t * gsz] = cs * ra[t] - sn * rb[t];
+                            gb[gl + t * gsz] = sn * ra[t] + cs * rb[t];
                         }
                         if (accv) {
                             double* va = V + (int64_t)a * ldg;
                             double* vb = V + (int64_t)b * ldg;
-                            for (int i = gl; i < nc; i += gsz) {
-                                const double x = va[i], y = vb[i];
-                                va[i] = cs * x - sn * y;
-                                vb[i] = sn * x + cs * y;
+                            double xa[TMAX], xb[TMAX];
+#pragma unroll
+                            for (int t = 0; t < TMAX; ++t) {
+                                xa[t] = va[gl + t * gsz];
+                                xb[t] = vb[gl + t * gsz];
+                            }
+#pragma unroll
+                            for (int t = 0; t < TMAX; ++t) {
+                                va[gl + t * gsz] = cs * xa[t] - sn * xb[t];
+                                vb[gl + t * gsz] = sn * xa[t] + cs * xb[t];
                             }
                         }
                         if (gl == 0) {
@@ -346,7 +387,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                          int max_sweeps, unsigned* flags, int with_v, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * ((size_t)maxdim * (maxdim + 1) * (with_v ? 2 : 1) +
+    if (maxdim > 128 || (with_v && maxdim > 64)) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * ((size_t)maxdim * 129 * (with_v ? 2 : 1) +
                                          2 * (size_t)maxdim + 1) + sizeof(int) * maxdim + 64;
     hipError_t e = hipFuncSetAttribute((const void*)k_core,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

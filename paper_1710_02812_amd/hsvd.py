@@ -65,7 +65,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
     L.hsvd_launch_times.argtypes = [vp, P(i32), P(ctypes.c_float), i32, P(i32)]
-    L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, P(ctypes.c_uint32), vp]
+    L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
     L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
                                         P(ctypes.c_size_t)]
@@ -192,8 +192,9 @@ def svd(A, p: int, q: int, k: int, tol: float = 0.0, **opts):
     return U, S, Vt, r
 
 
-def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True):
-    """Jacobi SVD of a batch of dense square float64 matrices M (batch, n, n)."""
+def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True, precondition: bool = False):
+    """Jacobi SVD of a batch of dense square float64 matrices M (batch, n, n);
+    precondition=True runs the sweeps on L of M = L Q (left pairs only)."""
     import torch
     b, n, _ = M.shape
     Mc = M.transpose(1, 2).contiguous()       # col-major storage
@@ -203,7 +204,7 @@ def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True):
     fl = ctypes.c_uint32()
     _check(lib().hsvd_debug_jacobi(Mc.data_ptr(), b, n, U.data_ptr(), S.data_ptr(),
                                    V.data_ptr() if with_v else None, max_sweeps,
-                                   ctypes.byref(fl), _stream_handle()))
+                                   int(precondition), ctypes.byref(fl), _stream_handle()))
     return (U.transpose(1, 2), S, V.transpose(1, 2) if with_v else None, fl.value & 0xFFFF,
             fl.value >> 16)
 

@@ -71,7 +71,7 @@ def test_null_handles():
     r = ctypes.c_int32()
     assert lib.hsvd_get_rank(None, ctypes.byref(r)) == 1
     assert lib.hsvd_get_status(None, None) == 1
-    assert lib.hsvd_debug_jacobi(None, 1, 4, None, None, None, 10, None, None) == 1
+    assert lib.hsvd_debug_jacobi(None, 1, 4, None, None, None, 10, 0, None, None) == 1
     assert lib.hsvd_debug_tsqr(None, 1, 4, 4, None, None, None) == 1
 
 

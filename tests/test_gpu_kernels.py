@@ -42,6 +42,71 @@ def test_jacobi_dense_random(n):
             assert np.linalg.norm(rec - M[b]) <= 1e-13 * n * np.linalg.norm(M[b])
 
 
+def _merge_matrix(rng, k, h=600, noise=1e-6):
+    """E = [[S1, C S2], [0, R S2]] of a merge of two nodes that share most of
+    their directions (Section 3, eq. orthmerge1), as the merge cores see it."""
+    base = np.linalg.qr(rng.standard_normal((h, k)))[0]
+    mix = np.linalg.qr(rng.standard_normal((k, k)))[0]
+    U1 = base
+    U2 = np.linalg.qr(base @ mix + noise * rng.standard_normal((h, k)))[0]
+    s1 = np.exp(-np.arange(k) / 8.0)
+    s2 = np.exp(-np.arange(k) / 8.0) * 0.9
+    C = U1.T @ U2
+    Q = U2 - U1 @ C
+    C2 = U1.T @ Q
+    Q -= U1 @ C2
+    C += C2
+    R = np.linalg.qr(Q, mode="r")
+    E = np.zeros((2 * k, 2 * k))
+    E[:k, :k] = np.diag(s1)
+    E[:k, k:] = C * s2
+    E[k:, k:] = R * s2
+    return E
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 100, 128])
+def test_jacobi_preconditioned(n):
+    """LQ-preconditioned sweeps: same singular values, orthonormal left vectors,
+    U^T M has orthogonal rows of norms S (M M^T = U S^2 U^T)."""
+    rng = np.random.default_rng(1000 + n)
+    M = rng.standard_normal((3, n, n))
+    M[1] *= np.exp(-np.arange(n) / 3.0)[None, :]
+    M[2] = np.triu(M[2])
+    print(f"jacobi lq n={n}", flush=True)
+    U, S, _, flags, sweeps = H.debug_jacobi(_t(M), with_v=False, precondition=True)
+    print(f"sweeps {sweeps}", flush=True)
+    assert flags == 0
+    U, S = U.cpu().numpy(), S.cpu().numpy()
+    for b in range(3):
+        s_ref = np.linalg.svd(M[b], compute_uv=False)
+        assert np.max(np.abs(S[b] - s_ref)) <= 1e-13 * s_ref[0] * max(1, n / 8)
+        nz = S[b] > 1e-12 * S[b][0]
+        Ub = U[b][:, nz]
+        assert np.linalg.norm(Ub.T @ Ub - np.eye(nz.sum())) <= 1e-13 * n
+        B = Ub.T @ M[b]
+        assert np.linalg.norm(B @ B.T - np.diag(S[b][nz] ** 2)) <= 1e-13 * n * s_ref[0] ** 2
+
+
+@pytest.mark.parametrize("k", [20, 50, 64])
+def test_jacobi_merge_matrix_preconditioned(k):
+    """Merge-shaped cores: preconditioning gives the same pairs in fewer sweeps."""
+    rng = np.random.default_rng(k)
+    E = _merge_matrix(rng, k)[None]
+    print(f"merge core k={k}", flush=True)
+    U0, S0, _, f0, sw0 = H.debug_jacobi(_t(E), with_v=False)
+    U1, S1, _, f1, sw1 = H.debug_jacobi(_t(E), with_v=False, precondition=True)
+    print(f"sweeps plain {sw0} lq {sw1}", flush=True)
+    assert f0 == 0 and f1 == 0
+    s_ref = np.linalg.svd(E[0], compute_uv=False)
+    S1 = S1.cpu().numpy()[0]
+    assert np.max(np.abs(S1 - s_ref)) <= 1e-13 * s_ref[0] * 2 * k / 8
+    assert sw1 < sw0
+    # top-k left subspace against LAPACK (a gap separates it from the noise part)
+    Ur = np.linalg.svd(E[0])[0][:, :k]
+    Uk = U1.cpu().numpy()[0][:, :k]
+    assert np.linalg.norm(Uk - Ur @ (Ur.T @ Uk), 2) <= 1e-11
+
+
 def test_jacobi_rank_deficient_and_zero():
     rng = np.random.default_rng(5)
     n = 40
