@@ -9,16 +9,24 @@ resident in HBM (all stages: leaves, column tree, re-projection, row tree,
 projection, output).  Both the float32-storage and the float64 paths are
 timed; `value` is the float32-storage path, the float64 figures sit beside it.
 
-The roofline object is for the launch kind that takes most of a step, timed
-live with HIP events recorded by the library between its launches on the
-execution stream.  cpu_baseline is the NumPy float64 oracle on the host cores.
-Prints one JSON line.
+The roofline object is for the launch kind that takes most of a step.  Its
+launches are timed live with HIP events that the library records between its
+launches on the execution stream; their algorithmic flops and bytes come from
+the plan (hsvd_launch_work).  `traffic` is the measured HBM traffic per launch
+from the committed rocprofv3 counter summary, used only while the kernel's
+sources are unchanged since the counters were taken.  cpu_baseline is the
+NumPy float64 oracle on the host cores.  Prints one JSON line.
+
+--copy-probe runs a plain device copy (torch.mul by 1.0, one read and one write
+of a known size) for scaling the FETCH_SIZE / WRITE_SIZE counters.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,6 +36,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c1_8192.md")
+CSRC = os.path.join(ROOT, "paper_1710_02812_amd", "csrc")
+# sources each launch kind's kernel is built from (hash guards the traffic figure)
+KIND_SOURCES = {
+    "gemm_ax": ["k_gemm.hip"], "gemm_atx": ["k_gemm.hip"],
+    "tsqr_factor": ["k_tsqr.hip", "house_qr.hpp"], "tsqr_apply": ["k_tsqr.hip"],
+    "gram": ["k_thin.hip"], "reduce": ["k_thin.hip"], "thin_nn": ["k_thin.hip"],
+    "sum": ["k_thin.hip"], "core": ["k_core.hip", "house_qr.hpp"], "output": ["k_misc.hip"],
+}
+COMMON_SOURCES = ["device_common.hpp", "hsvd_internal.hpp"]
 
 
 def parse():
@@ -40,18 +58,42 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the fp32 path only (for rocprofv3)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain copies of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
-def algorithmic(plan_kind: str, m: int, n: int, p: int, q: int, k: int, L: int, elem: int):
-    """Algorithmic work of one launch of the dominant kinds for this workload.
+def kind_hash(kind: str) -> str:
+    h = hashlib.sha1()
+    for f in KIND_SOURCES[kind] + COMMON_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
-    gemm_ax / gemm_atx (passes over A): flops = 2 * (elements of A touched) * N,
-    bytes = elements of A touched * elem + panel reads and writes (8-byte).
-    core: the paper's cost model counts 176 k^3 for the SVD of a 2k x 2k merge
-    core (Section 3.1) and 6 s^3 + 16 s^3 = 22 s^3 for an s x s block SVD.
-    """
+
+def measured_traffic(kind: str):
+    """Bytes per launch from the counter summary, or None when absent or stale."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = kind_hash(kind)
+    for line in open(TRAFFIC_FILE):
+        m = re.match(r"\|\s*(\w+)\s*\|\s*([0-9a-f]{12})\s*\|.*\|\s*([0-9.eE+]+)\s*\|\s*$", line)
+        if m and m.group(1) == kind:
+            return float(m.group(3)) if m.group(2) == want else None
     return None
+
+
+def copy_probe(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": 5}))
 
 
 def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
@@ -74,11 +116,23 @@ def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
     ms = t0.elapsed_time(t1) / args.steps
     flags = plan.status()
     r = plan.rank()
-    out = (U.double().cpu().numpy(), S.double().cpu().numpy(), Vt.double().cpu().numpy(), r)
-    # live per-launch timing (separate executes; events between launches)
+    res = {"ms": ms, "flags": flags, "out": (U.double().cpu().numpy(), S.double().cpu().numpy(),
+                                             Vt.double().cpu().numpy(), r)}
+    if args.profile_only:
+        plan.close()
+        return res
+    # per-step spread (each execute bracketed by its own events)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for i in range(args.steps):
+        plan.execute(A, U, S, Vt)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    res["per_step"] = {"median": float(np.median(per)), "min": float(per.min()),
+                       "p90": float(np.percentile(per, 90))}
+    # live per-launch timing: events recorded by the library between its launches
     plan.set_profiling(True)
-    per_kind = {}
-    counts = {}
     reps = 3
     per_launch = None
     for _ in range(reps):
@@ -87,14 +141,43 @@ def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
         if per_launch is None:
             per_launch = [[kk, 0.0] for kk, _ in lt]
         for i, (kind, t) in enumerate(lt):
-            per_kind[kind] = per_kind.get(kind, 0.0) + t / reps
-            counts[kind] = counts.get(kind, 0) + 1
             per_launch[i][1] += t / reps
-    counts = {kk: v // reps for kk, v in counts.items()}
     plan.set_profiling(False)
+    work = plan.launch_work()
     plan.close()
-    time_path.last_launches = [(i, kk, round(t, 4)) for i, (kk, t) in enumerate(per_launch)]
-    return ms, flags, out, per_kind, counts
+    kinds = {}
+    for (kind, t), (f, b) in zip(per_launch, work):
+        e = kinds.setdefault(kind, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        e["launches"] += 1
+        e["ms"] += t
+        e["flops"] += f
+        e["bytes"] += b
+    res["kinds"] = kinds
+    res["launches"] = [(i, kk, round(t, 4)) for i, (kk, t) in enumerate(per_launch)]
+    res["work_total"] = (sum(f for f, _ in work), sum(b for _, b in work))
+    return res
+
+
+def roofline_of(kind: str, e: dict) -> dict:
+    """Roofline of one launch kind: achieved = algorithmic work per launch / mean
+    launch duration (= summed work / summed time over the kind's launches)."""
+    ridge = PEAK["fp64_TF"] * 1e12 / (PEAK["hbm_GBs"] * 1e9)     # flop / byte
+    secs = e["ms"] * 1e-3
+    intensity = e["flops"] / e["bytes"] if e["bytes"] > 0 else float("inf")
+    if intensity >= ridge:
+        ach = e["flops"] / secs / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s"}
+    else:
+        ach = e["bytes"] / secs / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(kind)
+    roof.update({"kernel": kind, "launches_per_step": e["launches"],
+                 "avg_launch_ms": e["ms"] / e["launches"],
+                 "alg_flops_per_launch": e["flops"] / e["launches"],
+                 "alg_bytes_per_launch": e["bytes"] / e["launches"],
+                 "intensity_flop_per_byte": intensity, "source_hash": kind_hash(kind)})
+    return roof
 
 
 def main():
@@ -104,10 +187,11 @@ def main():
               "sharding of the method is described in DESIGN.md and not run here.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     from paper_1710_02812_amd import hsvd as H, synth
 
-    if "LOCAL_RANK" in os.environ:
-        torch.cuda.set_device(int(os.environ["LOCAL_RANK"]))
     size = args.size
     t = time.time()
     w = synth.config1(1, m=size, n=size, block=1024)
@@ -117,42 +201,21 @@ def main():
     A32 = A64.float()
     torch.cuda.synchronize()
 
-    ms32, fl32, out32, kinds32, cnt32 = time_path(H, torch, A32, H.FP32, args, k, p, q)
-    launches32 = time_path.last_launches
+    r32 = time_path(H, torch, A32, H.FP32, args, k, p, q)
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_fp32": ms32}))
+        print(json.dumps({"profile_only": True, "ms_fp32": r32["ms"]}))
         return
-    ms64, fl64, out64, kinds64, cnt64 = time_path(H, torch, A64, H.FP64, args, k, p, q)
-
-    # dominant launch kind of the headline path
-    dom = max(kinds32, key=kinds32.get)
-    dom_ms = kinds32[dom] / cnt32[dom]
+    r64 = time_path(H, torch, A64, H.FP64, args, k, p, q)
     m, n = w.A.shape
-    L = min(k + 14, m // p, n // q)
-    N = k
-    if dom in ("gemm_ax", "gemm_atx"):
-        # per launch of this kind: the leaf products touch all of A once (N = L),
-        # the re-projection / projection products touch all of A once (N = k)
-        # -> report the leaf-pass launch (the most frequent)
-        flops = 2.0 * m * n * L
-        bytes_ = 4.0 * m * n + 8.0 * (p * n * L + q * m * L)
-        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": PEAK["fp64_TF"],
-                "unit": "TFLOP/s"}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
-        roof["algorithmic_bytes"] = bytes_
-    elif dom == "core":
-        # average core launch: count the paper's 176 k^3 per merge core
-        flops = 176.0 * k ** 3
-        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": PEAK["fp64_TF"],
-                "unit": "TFLOP/s", "traffic": None}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s",
-                "frac": None, "traffic": None}
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = dom_ms
-    roof["launches_per_step"] = cnt32[dom]
+
+    kinds = r32["kinds"]
+    dom = max(kinds, key=lambda kk: kinds[kk]["ms"])
+    roof = roofline_of(dom, kinds[dom])
+    tf, tb = r32["work_total"]
+    t_roof = max(tf / (PEAK["fp64_TF"] * 1e12), tb / (PEAK["hbm_GBs"] * 1e9)) * 1e3
+    whole = {"alg_flops": tf, "alg_bytes": tb, "t_roof_ms": t_roof,
+             "frac": t_roof / r32["ms"],
+             "binding": "fp64" if tf / (PEAK["fp64_TF"] * 1e12) >= tb / (PEAK["hbm_GBs"] * 1e9) else "hbm"}
 
     acc = None
     cpu = None
@@ -161,50 +224,58 @@ def main():
         from oracle import metrics
         try:
             from threadpoolctl import threadpool_info
-            threads = max(i.get("num_threads", 1) for i in threadpool_info()) if threadpool_info() else 1
+            info = threadpool_info()
+            threads = max(i.get("num_threads", 1) for i in info) if info else 1
         except Exception:
             threads = os.cpu_count()
         t = time.time()
         Uo, so, Vto, ro = oracle.hsvd(w.A, p, q, k, 0.0)
         cpu_s = time.time() - t
-        cpu = {"value": cpu_s * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
-               "sample": f"whole workload ({m}x{n}, {p}x{q} grid, k={k}), one run, float64 "
-                         "NumPy/LAPACK, exact leaf SVDs"}
+        cpu = {"value": round(cpu_s * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+               "sample": f"the whole workload once ({m}x{n}, {p}x{q} grid, k={k}; float64 NumPy/LAPACK "
+                         "with exact leaf SVDs), generation excluded"}
         if not args.no_accuracy:
             acc = {}
-            for name, o in (("fp32", out32), ("fp64", out64)):
+            for name, o in (("fp32", r32["out"]), ("fp64", r64["out"])):
                 c = metrics.compare(o[0], o[1], o[2], o[3], Uo, so, Vto, ro)
                 acc[name] = {kk: (float(v) if isinstance(v, float) else v) for kk, v in c.items()}
         if args.no_cpu_baseline:
             cpu = None
 
+    def kind_table(ks):
+        return {kk: {"launches": e["launches"], "ms": round(e["ms"], 4),
+                     "gflop": round(e["flops"] / 1e9, 3), "mbyte": round(e["bytes"] / 1e6, 2)}
+                for kk, e in ks.items()}
+
     res = {
         "metric": "time-to-rank-k SVD (ms) + MFMA/HBM roofline %, mixed vs FP64 at <=1e-3 err",
-        "value": round(ms32, 4),
+        "value": round(r32["ms"], 4),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms32, 4),
+        "ms_per_step": round(r32["ms"], 4),
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"snapshot-like {m}x{n}, 50 modes + 1e-6 noise, {p}x{q} grid of "
-                               f"{m // p}x{n // q} blocks, k=50, tol=0, A stored float32",
-                   "m": m, "n": n, "p": p, "q": q, "k": k, "storage": "f32",
-                   "parallelism": "single GPU"},
-        "fp64_path_ms": round(ms64, 4),
-        "fp32_storage_speedup_vs_fp64": round(ms64 / ms32, 3),
-        "status_flags": {"fp32": fl32 & 0xFFFF, "fp64": fl64 & 0xFFFF},
-        "max_jacobi_sweeps": {"fp32": fl32 >> 16, "fp64": fl64 >> 16},
-        "launch_ms_per_step": {"fp32": {kk: round(v, 4) for kk, v in kinds32.items()},
-                               "fp64": {kk: round(v, 4) for kk, v in kinds64.items()}},
-        "launch_counts": cnt32,
-        "launches_fp32": launches32,
+                               f"{m // p}x{n // q} blocks, k=50, tol=0, A stored float32, "
+                               "float64 arithmetic",
+                   "m": m, "n": n, "p": p, "q": q, "k": k, "storage": "f32"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "per_step_ms": r32["per_step"],
+        "whole_call_roofline": whole,
+        "fp64_path_ms": round(r64["ms"], 4),
+        "fp64_per_step_ms": r64["per_step"],
+        "fp32_storage_speedup_vs_fp64": round(r64["ms"] / r32["ms"], 3),
+        "status_flags": {"fp32": r32["flags"] & 0xFFFF, "fp64": r64["flags"] & 0xFFFF},
+        "max_jacobi_sweeps": {"fp32": r32["flags"] >> 16, "fp64": r64["flags"] >> 16},
+        "launch_kinds_fp32": kind_table(kinds),
+        "launch_kinds_fp64": kind_table(r64["kinds"]),
+        "launches_fp32": r32["launches"],
         "accuracy_vs_oracle": acc,
         "generate_s": round(gen_s, 2),
     }

@@ -147,6 +147,23 @@ hsvd_status hsvd_set_profiling(hsvd_plan_t plan, int32_t enable);
 hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_host, int32_t cap,
                               int32_t* count_host);
 
+/* Algorithmic work of every launch of one execute, in the order of
+ * hsvd_launch_times (host only, no device work): flops_host[i] and the minimal
+ * HBM bytes bytes_host[i] (each operand read once, each result written once) for
+ * i < min(cap, count).  Counts at the plan's rank caps (data-dependent ranks
+ * can only lower them):
+ *   passes over A        2 rows cols N flops per block and product width N;
+ *   Householder TSQR     2 h w^2 - 2 w^3 / 3 per h x w panel;
+ *   applying Q           4 h w c per panel and c columns;
+ *   thin products        2 h wx wy;  sums of partials one flop per addend;
+ *   SVD cores            22 n^3 per n x n core, the cost the paper's complexity
+ *                        analysis gives a dense SVD (Section 3.1: 6 m n^2 + 16 n^3
+ *                        at m = n, i.e. 176 k^3 for a 2k x 2k merge core).
+ * *count_host receives the number of launches; with flops_host == NULL or
+ * bytes_host == NULL only the count is returned. */
+hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes_host, int32_t cap,
+                             int32_t* count_host);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hsvd_last_error(void);
 

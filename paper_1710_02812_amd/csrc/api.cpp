@@ -1100,6 +1100,108 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
     return HSVD_OK;
 }
 
+hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes_host, int32_t cap,
+                             int32_t* count_host) {
+    if (!plan || !count_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    const hsvd_plan_st& P = *plan;
+    const int n = (int)P.stages.size() + 1;
+    *count_host = n;
+    if (!flops_host || !bytes_host) return HSVD_OK;
+    const unsigned char* b = P.blob.data();
+    const double eA = P.opt.precision == HSVD_FP32 ? 4.0 : 8.0, e8 = 8.0;
+    for (int i = 0; i < n && i < cap; ++i) {
+        double f = 0.0, by = 0.0;
+        if (i == n - 1) {                                   // output: U, Vt from the panels
+            by = (double)(P.m + P.n) * P.W * e8 + (double)(P.m + P.n) * P.k * eA + P.k * eA;
+        } else {
+            const Stage& s = P.stages[i];
+            switch (s.kind) {
+                case ST_GEMM: {
+                    const GemmTask* T = (const GemmTask*)(b + s.tasks_off);
+                    int ntask = 0;
+                    const TileRef* R = (const TileRef*)(b + s.refs_off);
+                    for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, R[t].task + 1);
+                    for (int t = 0; t < ntask; ++t) {
+                        const double r = T[t].rows, c = T[t].cols, N = s.N;
+                        f += 2.0 * r * c * N;
+                        by += r * c * eA + (r + c) * N * e8;
+                    }
+                    break;
+                }
+                case ST_TSQR_F: {
+                    const ChunkRef* C = (const ChunkRef*)(b + s.refs_off);
+                    const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
+                    int ntask = 0;
+                    for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
+                    for (int t = 0; t < ntask; ++t) {
+                        const double h = T[t].h, w = s.w, mn = std::min(h, w), mx = std::max(h, w);
+                        f += 2.0 * mx * mn * mn - 2.0 * mn * mn * mn / 3.0;
+                        by += 2.0 * h * w * e8;
+                    }
+                    break;
+                }
+                case ST_TSQR_A: {
+                    const ChunkRef* C = (const ChunkRef*)(b + s.refs_off);
+                    const TsqrTask* T = (const TsqrTask*)(b + s.tsqr_off);
+                    const ApplyTask* A = (const ApplyTask*)(b + s.tasks_off);
+                    int ntask = 0;
+                    for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
+                    for (int t = 0; t < ntask; ++t) {
+                        const double h = T[A[t].tsqr].h, w = s.w, c = s.c;
+                        f += 4.0 * h * w * c;
+                        by += (h * w + h * c) * e8;
+                        if (A[t].add_u_off >= 0) {
+                            f += 2.0 * h * A[t].add_w * c;
+                            by += h * A[t].add_w * e8;
+                        }
+                    }
+                    break;
+                }
+                case ST_GRAM: case ST_NN: case ST_REDUCE: case ST_SUM: {
+                    const ThinTask* T = (const ThinTask*)(b + s.tasks_off);
+                    int ntask = s.n;
+                    if (s.kind != ST_REDUCE) {
+                        const ChunkRef* C = (const ChunkRef*)(b + s.refs_off);
+                        ntask = 0;
+                        for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
+                    }
+                    for (int t = 0; t < ntask; ++t) {
+                        const ThinTask& x = T[t];
+                        const double h = x.h, wx = x.wx, wy = x.wy;
+                        if (s.kind == ST_GRAM) {
+                            f += 2.0 * h * wx * wy;
+                            by += h * (wx + wy) * e8;
+                        } else if (s.kind == ST_NN) {
+                            f += 2.0 * h * wx * wy;
+                            by += h * (wx + 2.0 * wy) * e8;
+                        } else if (s.kind == ST_REDUCE) {
+                            const double nch = (x.h + THIN_CH - 1) / THIN_CH;
+                            f += nch * wx * wy;
+                            by += (nch + 1.0) * wx * wy * e8;
+                        } else {                              // wx partial products of h x wy
+                            f += (wx - 1.0) * h * wy;
+                            by += (wx + 1.0) * h * wy * e8;
+                        }
+                    }
+                    break;
+                }
+                case ST_CORE: {
+                    const CoreTask* T = (const CoreTask*)(b + s.tasks_off);
+                    for (int t = 0; t < s.n; ++t) {
+                        const double d = (T[t].mode == CORE_MERGE) ? 2.0 * P.W : (double)T[t].dim;
+                        f += 22.0 * d * d * d;
+                        by += (d * d + d * T[t].out_w + T[t].out_w) * e8;
+                    }
+                    break;
+                }
+            }
+        }
+        flops_host[i] = f;
+        bytes_host[i] = by;
+    }
+    return HSVD_OK;
+}
+
 hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (!plan) return HSVD_OK;
     if (plan->executed) hipStreamSynchronize(plan->last_stream);

@@ -22,7 +22,7 @@ FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 
 EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
             "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
-            "hsvd_set_profiling", "hsvd_launch_times",
+            "hsvd_set_profiling", "hsvd_launch_times", "hsvd_launch_work",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output"]
@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
     L.hsvd_launch_times.argtypes = [vp, P(i32), P(ctypes.c_float), i32, P(i32)]
+    L.hsvd_launch_work.argtypes = [vp, P(f64), P(f64), i32, P(i32)]
     L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
     L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
@@ -149,6 +150,16 @@ class Plan:
         ms = (ctypes.c_float * n.value)()
         _check(lib().hsvd_launch_times(self._h, kinds, ms, n.value, ctypes.byref(n)))
         return [(LAUNCH_KINDS[kinds[i]], float(ms[i])) for i in range(n.value)]
+
+    def launch_work(self):
+        """[(flops, bytes)]: algorithmic work of every launch of one execute, in the
+        order of launch_times (host only)."""
+        n = ctypes.c_int32()
+        _check(lib().hsvd_launch_work(self._h, None, None, 0, ctypes.byref(n)))
+        f = (ctypes.c_double * n.value)()
+        b = (ctypes.c_double * n.value)()
+        _check(lib().hsvd_launch_work(self._h, f, b, n.value, ctypes.byref(n)))
+        return [(float(f[i]), float(b[i])) for i in range(n.value)]
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
