@@ -9,21 +9,26 @@ namespace hsvd {
 // w <= 1024 / LANES) with 1024 threads = groups of LANES lanes.  Column c lives in
 // the registers of group c, row r in lane r % LANES (index r / LANES), so the
 // trailing matrix never travels through LDS; per step only the pivot reflector is
-// broadcast through LDS.
+// broadcast through LDS.  Reflectors follow the dlarfg convention (H = I - tau v v^T,
+// v_j = 1, R_jj = beta); with WITH_T the compact-WY factor T of Q = H_0 ... H_{w-1}
+// = I - V T V^T is built alongside (dlarft forward/columnwise: T_jj = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] z, z = V[:, 0:j]^T v_j).
 //
-// Step j, phase 1: the owner of column j takes alpha = A_jj and the below-diagonal
-// norm (left in LDS by step j-1), forms beta, tau_j and v_j (dlarfg convention:
-// H = I - tau v v^T, v_j = 1, R_jj = beta) and publishes v_j; meanwhile the other
-// groups finish column j-1 of the compact-WY factor T (dlarft forward/columnwise:
-// T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] z with z = V[:, 0:j]^T v_j).
-// Phase 2: every other column c forms v_j^T a_c; c > j is updated (c = j + 1 also
-// leaves its next norm), c < j yields z_c.  Two barriers per step.  Without T
-// (WITH_T = false) only R and the reflectors are produced: columns left of the
-// pivot sit idle and T, z are not touched.
+// One barrier per step, with look-ahead: in step j every column c > j is updated
+// with v_j, and the group of column j + 1, right after its own update, forms v_{j+1}
+// into the other half of a double buffer.  Columns c < j meanwhile form
+// z_c = v_c^T v_j and, from the z of step j - 1, their row of T column j - 1 (each
+// group owns one row of T, so T never needs a barrier of its own).
 template <int LANES, int RMAX, bool WITH_T = true>
 struct HouseQR {
     static constexpr int NG = 1024 / LANES;
+    static constexpr int VB = LANES * RMAX;      // rows one column can hold
     double x[RMAX];
+
+    // LDS doubles factor() needs: T (w x (w + 1)), tau (w), z (2w), two pivot buffers
+    __host__ __device__ static constexpr size_t lds_doubles(int w) {
+        return (size_t)w * (w + 1) + 3 * (size_t)w + 2 * (size_t)VB;
+    }
 
     __device__ static double gsum(double v) { return LANES == 16 ? sum16(v) : sum8(v); }
 
@@ -58,120 +63,131 @@ struct HouseQR {
         }
     }
 
-    // T column j (rows i < j from z in ztmp; T_jj = tau_j).  The calling groups
-    // number themselves vg = 0..ng-1 and stride over the rows.
-    __device__ static void t_column(double* T, int ldt, int j, const double* ztmp, double tj,
-                                    int vg, int ng) {
+    // Squared norm of the rows r > j of this group's column (registers t < NT;
+    // rows past the block hold zeros).
+    template <int NT>
+    __device__ double norm_below(int j) const {
         const int gl = threadIdx.x % LANES;
-        for (int i = vg; i < j; i += ng) {
-            double d = 0.0;
-            for (int l = i + gl; l < j; l += LANES) d = fma(T[(int64_t)l * ldt + i], ztmp[l], d);
-            d = gsum(d);
-            if (gl == 0) T[(int64_t)j * ldt + i] = -tj * d;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int r = gl + LANES * t;
+            const double m = (r > j) ? x[t] : 0.0;
+            if (t & 1) s1 = fma(m, m, s1);
+            else s0 = fma(m, m, s0);
         }
-        if (vg == 0 && gl == 0) T[(int64_t)j * ldt + j] = tj;
+        return gsum(s0 + s1);
     }
 
-    // lds scratch: T (w x (w+1)), tau (w), nrm (w), z (2w), vbuf (LANES * RMAX);
-    // T and z are unused without T
-    __device__ void factor(int rows, int w, double* T, double* tau, double* nrm, double* z,
-                           double* vbuf) {
+    // Reflector of column j, formed by the group that owns it: alpha = A_jj sits in
+    // register j / LANES of the group's lane j % LANES, s2 is the squared norm below
+    // the diagonal.  Leaves beta at row j and v below it in the registers, writes v_j
+    // (0 above row j) into vb and tau_j into tau[j].  The square root and the
+    // reciprocals come from the hardware estimates refined by Newton steps.
+    template <int NT>
+    __device__ void reflect(int j, double s2, double* vb, double* tau) {
+        const int gl = threadIdx.x % LANES;
+        const int tj = j / LANES;
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t == tj) a = x[t];
+        const int src = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & 63) - gl) + (j % LANES);
+        const double alpha = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), src),
+                                              __builtin_amdgcn_readlane(__double2loint(a), src));
+        double beta = alpha, tau_j = 0.0, scal = 0.0;
+        if (s2 > 0.0) {
+            beta = -copysign(sqrt_nr(fma(alpha, alpha, s2)), alpha);
+            tau_j = fma(-alpha, rcp_nr(beta), 1.0);           // (beta - alpha) / beta
+            scal = rcp_nr(alpha - beta);                      // |alpha - beta| >= |beta| > 0
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int r = gl + LANES * t;
+            double v = 0.0;
+            if (r == j) { x[t] = beta; v = 1.0; }
+            else if (r > j) { if (s2 > 0.0) x[t] *= scal; v = x[t]; }
+            vb[r] = v;                                         // zeros above row j
+        }
+        if (gl == 0) tau[j] = tau_j;
+    }
+
+    // Row i of T column jj: -tau_jj sum_{l=i}^{jj-1} T[i][l] zz[l], by the group of row i.
+    __device__ static void t_row(double* T, int ldt, int i, int jj, const double* zz, double tjj) {
+        const int gl = threadIdx.x % LANES;
+        double d = 0.0;
+        for (int l = i + gl; l < jj; l += LANES) d = fma(T[(int64_t)l * ldt + i], zz[l], d);
+        d = gsum(d);
+        if (gl == 0) T[(int64_t)jj * ldt + i] = -tjj * d;
+    }
+
+    // lds scratch (lds_doubles(w)): T (w x (w+1)), tau (w), z (2w), vbuf (2 * VB);
+    // T and z are unused without T.  Registers t >= NT must hold zeros and rows past
+    // the block zeros (rows <= LANES * NT); loops run over the NT registers without
+    // branches so that their LDS reads issue back to back.  All 1024 threads call
+    // it; it ends on a barrier.
+    template <int NT = RMAX>
+    __device__ void factor(int rows, int w, double* T, double* tau, double* z, double* vbuf) {
+        static_assert(NT >= 1 && NT <= RMAX, "NT out of range");
         const int tid = threadIdx.x, nth = blockDim.x;
         const int grp = tid / LANES, gl = tid % LANES;
         const int kmax = rows < w ? rows : w;
         const int ldt = w + 1;
         if constexpr (WITH_T)
             for (int e = tid; e < w * ldt; e += nth) T[e] = 0.0;
-        if (grp == 0) {                                // norm of column 0 below the diagonal
-            double s2 = 0.0;
-#pragma unroll
-            for (int t = 0; t < RMAX; ++t) {
-                const int r = gl + LANES * t;
-                if (r > 0) s2 = fma(x[t], x[t], s2);
-            }
-            s2 = gsum(s2);
-            if (gl == 0) nrm[0] = s2;
+        for (int j = kmax + tid; j < w; j += nth) tau[j] = 0.0;
+        if (kmax > 0 && grp == 0) {
+            const double s2 = norm_below<NT>(0);
+            reflect<NT>(0, s2, vbuf, tau);
         }
         __syncthreads();
         for (int j = 0; j < kmax; ++j) {
-            const int og = j;
-            // ---- phase 1
-            if (grp == og) {
-                double a = 0.0;
-#pragma unroll
-                for (int t = 0; t < RMAX; ++t)
-                    if (gl + LANES * t == j) a = x[t];
-                const double alpha = gsum(a);
-                const double sq = nrm[j];
-                double beta = alpha, tj = 0.0, scal = 0.0;
-                if (sq > 0.0) {
-                    beta = -copysign(sqrt(alpha * alpha + sq), alpha);
-                    tj = (beta - alpha) / beta;
-                    scal = 1.0 / (alpha - beta);
-                }
-#pragma unroll
-                for (int t = 0; t < RMAX; ++t) {
-                    const int r = gl + LANES * t;
-                    double v = 0.0;
-                    if (r == j) { x[t] = beta; v = 1.0; }
-                    else if (r > j) { if (sq > 0.0) x[t] *= scal; v = x[t]; }
-                    vbuf[r] = v;                       // zero above row j and past the rows
-                }
-                if (gl == 0) tau[j] = tj;
-            } else if (WITH_T && j > 0) {              // the other groups, renumbered
-                t_column(T, ldt, j - 1, z + ((j - 1) & 1) * w, tau[j - 1], grp < og ? grp : grp - 1, NG - 1);
-            }
-            __syncthreads();
-            // ---- phase 2
-            const double tj = tau[j];
-            double* zj = z + (j & 1) * w;
+            const double* vj = vbuf + (j & 1) * VB;
             const int c = grp;
-            if (c < w && (WITH_T ? c != j : c > j)) {
-                if (tj == 0.0) {
-                    if (c == j + 1) {
-                        double s2 = 0.0;
-#pragma unroll
-                        for (int t = 0; t < RMAX; ++t) {
-                            const int r = gl + LANES * t;
-                            if (r > j + 1 && r < rows) s2 = fma(x[t], x[t], s2);
-                        }
-                        s2 = gsum(s2);
-                        if (gl == 0) nrm[j + 1] = s2;
-                    }
-                    if (WITH_T && c < j && gl == 0) zj[c] = 0.0;
-                } else {
+            if (c < w && c > j) {
+                const double tj = tau[j];
+                if (tj != 0.0) {
+                    // up to 16 pivot values stay in registers between the two passes;
+                    // beyond that they are read again (no spills)
+                    constexpr int KV = NT <= 16 ? NT : 1;
+                    double v[KV];
                     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-                    for (int t = 0; t < RMAX; ++t) {
-                        const double v = vbuf[gl + LANES * t];   // broadcast read within the wave
-                        if (t & 1) d1 = fma(v, x[t], d1);
-                        else d0 = fma(v, x[t], d0);
+                    for (int t = 0; t < NT; ++t) {
+                        const double vt = vj[gl + LANES * t];             // broadcast reads
+                        if (NT <= 16) v[t < KV ? t : 0] = vt;
+                        if (t & 1) d1 = fma(vt, x[t], d1);
+                        else d0 = fma(vt, x[t], d0);
                     }
-                    const double d = gsum(d0 + d1);
-                    if (c < j) {
-                        if (WITH_T && gl == 0) zj[c] = d;
-                    } else {
-                        const double f = tj * d;
-                        double s2 = 0.0;
+                    const double f = tj * gsum(d0 + d1);
 #pragma unroll
-                        for (int t = 0; t < RMAX; ++t) {
-                            const int r = gl + LANES * t;
-                            x[t] = fma(-f, vbuf[r], x[t]);
-                            const double m = (r > j + 1) ? x[t] : 0.0;
-                            s2 = fma(m, m, s2);
-                        }
-                        if (c == j + 1) {
-                            s2 = gsum(s2);
-                            if (gl == 0) nrm[j + 1] = s2;
-                        }
-                    }
+                    for (int t = 0; t < NT; ++t)
+                        x[t] = fma(-f, NT <= 16 ? v[t < KV ? t : 0] : vj[gl + LANES * t], x[t]);
                 }
+                if (c == j + 1 && j + 1 < kmax) {                  // look-ahead reflector
+                    const double s2 = norm_below<NT>(j + 1);
+                    reflect<NT>(j + 1, s2, vbuf + ((j + 1) & 1) * VB, tau);
+                }
+            } else if (WITH_T && c < j) {
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double v = vj[gl + LANES * t];
+                    if (t & 1) d1 = fma(v, x[t], d1);
+                    else d0 = fma(v, x[t], d0);
+                }
+                const double d = gsum(d0 + d1);
+                if (gl == 0) z[(j & 1) * w + c] = d;              // z_c = v_c^T v_j
+                if (c < j - 1) t_row(T, ldt, c, j - 1, z + ((j - 1) & 1) * w, tau[j - 1]);
+                else if (gl == 0) T[(int64_t)(j - 1) * ldt + (j - 1)] = tau[j - 1];
             }
             __syncthreads();
         }
-        if (WITH_T && kmax > 0)
-            t_column(T, ldt, kmax - 1, z + ((kmax - 1) & 1) * w, tau[kmax - 1], grp, NG);
-        for (int j = kmax + tid; j < w; j += nth) tau[j] = 0.0;
+        if (WITH_T && kmax > 0) {
+            const int J = kmax - 1;
+            if (grp < J) t_row(T, ldt, grp, J, z + (J & 1) * w, tau[J]);
+            else if (grp == J && gl == 0) T[(int64_t)J * ldt + J] = tau[J];
+        }
         __syncthreads();
     }
 };

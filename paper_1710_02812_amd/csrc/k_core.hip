@@ -154,9 +154,10 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             const int r = gl + 8 * s;
             q.x[s] = (c < nr && r < nc) ? G[(int64_t)r * ldg + c] : 0.0;
         }
-        // scratch: tau -> sig, norms -> d, pivot broadcast -> the first 128 entries
-        // of G (all of G is in registers by the first barrier inside factor)
-        q.factor(nc, nr, G, sig, d, d, G);
+        // scratch: tau -> sig, the two pivot buffers -> the first 256 entries of G
+        // (maxdim >= 2 here, so G holds >= 258); T and z are not used
+        __syncthreads();                          // all of G is in registers
+        q.factor(nc, nr, G, sig, d, G);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int r = gl + 8 * s;

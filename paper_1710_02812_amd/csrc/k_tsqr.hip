@@ -42,7 +42,8 @@ __device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l
     return i == l ? 1.0 : (i > l ? A[(int64_t)l * ld + i] : 0.0);
 }
 
-template <int LANES, int RMAX>
+// MT: registers live in a tree merge (2w <= LANES * MT rows)
+template <int LANES, int RMAX, int MT>
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
                                                               const TsqrTask* __restrict__ tasks,
@@ -51,9 +52,8 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
     extern __shared__ double sm[];
     double* T = sm;                                  // w x (w + 1)
     double* tau = T + (int64_t)w * (w + 1);
-    double* nrm = tau + w;
-    double* z = nrm + w;                             // 2w
-    double* vbuf = z + 2 * w;                        // 16 * RMAX
+    double* z = tau + w;                             // 2w
+    double* vbuf = z + 2 * w;                        // 2 * LANES * RMAX
     __shared__ int s_go;
     HouseQR<LANES, RMAX> q;
 
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
     const int64_t S = tsqr_slot_size(w);
 
     q.load(P + row0, t.p_ld, rows, w);
-    q.factor(rows, w, T, tau, nrm, z, vbuf);
+    q.factor(rows, w, T, tau, z, vbuf);
     q.store(P + row0, t.p_ld, rows, w);
     {
         double* slot = store + S * node_slot(t.nch, 0, cr.chunk);
@@ -113,7 +113,8 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
                 q.x[tt] = v;
             }
         }
-        q.factor(2 * w, w, T, tau, nrm, z, vbuf);
+        // the stacked pair has 2w rows: only the first MT registers are live
+        q.template factor<MT>(2 * w, w, T, tau, z, vbuf);
         double* slot = store + S * node_slot(t.nch, level + 1, parent);
         q.store_r(slot, 2 * w, w);
         q.store(slot + w * w, 2 * w, 2 * w, w);
@@ -242,18 +243,14 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     }
 }
 
-static size_t factor_lds_bytes(int w, int rmax) {
-    return sizeof(double) * ((size_t)w * (w + 1) + 4 * (size_t)w + 16 * (size_t)rmax + 32);   // LANES <= 16
-}
-
-template <int LANES, int RMAX>
+template <int LANES, int RMAX, int MT>
 static hipError_t launch_factor_t(double* ws, int* iws, const TsqrTask* tasks,
                                   const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s) {
-    const size_t lds = factor_lds_bytes(w, RMAX);
-    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX>,
+    const size_t lds = sizeof(double) * (HouseQR<LANES, RMAX>::lds_doubles(w) + 32);
+    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX, MT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX>), dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws,
+    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX, MT>), dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws,
                        iws, tasks, chunks, w, ch);
     return hipGetLastError();
 }
@@ -264,11 +261,11 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const
     if (w < 1 || w > kTsqrMaxW || ch != tsqr_chunk_rows(w)) return hipErrorInvalidValue;
     // a chunk and a stacked pair of R factors must fit the register block
     if (w <= 64) {
-        if (ch > 16 * 16 || 2 * w > 16 * 16) return hipErrorInvalidValue;
-        return launch_factor_t<16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+        if (ch > 16 * 16 || 2 * w > 16 * 8) return hipErrorInvalidValue;
+        return launch_factor_t<16, 16, 8>(ws, iws, tasks, chunks, nchunks, w, ch, s);
     }
     if (ch > 8 * 20 || 2 * w > 8 * 20) return hipErrorInvalidValue;
-    return launch_factor_t<8, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+    return launch_factor_t<8, 20, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
 hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
