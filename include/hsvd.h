@@ -51,9 +51,16 @@ typedef enum {
 
 /* Storage and arithmetic of the passes over A.
  *   FP64: A, U, S, Vt are double; all arithmetic float64.
- *   FP32: A, U, S, Vt are float; the products with A run in float32 with float32
- *         accumulation; factor panels, QR and the Jacobi cores are float64.      */
-typedef enum { HSVD_FP64 = 0, HSVD_FP32 = 1 } hsvd_precision;
+ *   FP32: A, U, S, Vt are float (float32 storage); the products with A read
+ *         float32 and run in float64 arithmetic, as does everything else.
+ *   MIXED_BF16: A, U, S, Vt are float.  The leaf passes and the slab
+ *         re-projection run on the matrix cores with A and the panels rounded to
+ *         bfloat16 and float32 sums; the projection and one iteration of
+ *         Algorithm 2 (always added; refine_steps counts further ones) read the
+ *         float32 A with float64 arithmetic, so S and the subspaces are refined
+ *         against the unrounded input.  Factor panels, QR and the Jacobi cores
+ *         are float64 throughout.                                               */
+typedef enum { HSVD_FP64 = 0, HSVD_FP32 = 1, HSVD_MIXED_BF16 = 2 } hsvd_precision;
 
 /* Truncation rule (Section 3): GAMMA keeps s_i >= tol * s_1 of the matrix being
  * truncated; FROB keeps the shortest prefix whose discarded energy
@@ -132,7 +139,9 @@ typedef enum {
     HSVD_LAUNCH_THIN_NN = 6,       /* Y (+/-)= X C                                       */
     HSVD_LAUNCH_SUM = 7,           /* sum of split products                              */
     HSVD_LAUNCH_CORE = 8,          /* Jacobi SVD cores                                   */
-    HSVD_LAUNCH_OUTPUT = 9         /* signs and the U, S, Vt writes                      */
+    HSVD_LAUNCH_OUTPUT = 9,        /* signs and the U, S, Vt writes                      */
+    HSVD_LAUNCH_GEMM_AX_BF16 = 10, /* Y = A_blk X on the bfloat16 matrix cores           */
+    HSVD_LAUNCH_GEMM_ATX_BF16 = 11 /* Y = A_blk^T X on the bfloat16 matrix cores         */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

@@ -60,6 +60,7 @@ struct Stage {
     int n = 0;           // tiles / chunks / tasks
     int w = 0, ch = 0, c = 0, N = 0;
     int maxdim = 0, with_v = 0;
+    int bf16 = 0;        // gemm on the bfloat16 matrix cores
     size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
 };
 
@@ -194,16 +195,20 @@ void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<App
     P.stages.push_back(s);
 }
 
-void push_gemm(hsvd_plan_st& P, int op, const std::vector<GemmTask>& tasks, int N) {
+// A pass over A; bf16 selects the bfloat16 matrix-core kernel (128-row tiles).
+void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, bool bf16 = false) {
     std::vector<TileRef> tiles;
     const int nct = (N + 63) / 64;
+    const int th = bf16 ? kBf16TileRows : 64;
     for (size_t t = 0; t < tasks.size(); ++t) {
         const int out_rows = (op == 0) ? tasks[t].rows : tasks[t].cols;
-        const int nrt = (out_rows + 63) / 64;
+        const int nrt = (out_rows + th - 1) / th;
+        tasks[t].tiles = nrt;
         for (int i = 0; i < nrt * nct; ++i) tiles.push_back({(int)t, i});
     }
     Stage s{};
     s.kind = ST_GEMM;
+    s.bf16 = bf16 ? 1 : 0;
     s.op = op;
     s.n = (int)tiles.size();
     s.N = N;
@@ -413,7 +418,7 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
             t.y_off = l.Y; t.y_ld = (int)brmax;
             gt.push_back(t);
         }
-        push_gemm(P, 0, gt, L);
+        push_gemm(P, 0, gt, L, P.opt.precision == HSVD_MIXED_BF16);
     }
     const int ch = tsqr_chunk(L, std::max(L, W));
     std::vector<int> last_tsqr(leaves.size());
@@ -453,7 +458,7 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
             }
             gt.push_back(x);
         }
-        push_gemm(P, prev_is_y ? 1 : 0, gt, L);
+        push_gemm(P, prev_is_y ? 1 : 0, gt, L, P.opt.precision == HSVD_MIXED_BF16);
     }
     // core of the last product
     const bool last_is_y = ((g - 1) % 2 == 0);
@@ -533,7 +538,7 @@ std::vector<Node> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& r
         t.y_off = Zs[i]; t.y_ld = n;
         gt.push_back(t);
     }
-    push_gemm(P, 1, gt, W);
+    push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16);
     for (size_t i = 0; i < roots.size(); ++i) add_tsqr(P, tb, Zs[i], n, n, W, ch);
     push_tsqr_factor(P, tb, W, ch);
     std::vector<CoreTask> cores;
@@ -728,9 +733,10 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     auto slab_nodes = build_reprojection(P, col_roots);
     auto row_root = merge_forest(P, {slab_nodes})[0];
     Factors f = build_projection(P, row_root.panel, row_root.ld, row_root.rank);
-    for (int it = 0; it < P.opt.refine_steps; ++it) {
+    const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
+    for (int it = 0; it < steps; ++it) {
         f = build_refine_step(P, f);
-        if (it + 1 < P.opt.refine_steps) f = build_projection(P, f.V, (int)P.n, f.rank);
+        if (it + 1 < steps) f = build_projection(P, f.V, (int)P.n, f.rank);
     }
     P.out.u_off = f.U;
     P.out.v_off = f.V;
@@ -782,7 +788,12 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const int xr = s.op == 0 ? t.cols : t.rows, yr = s.op == 0 ? t.rows : t.cols;
                     if (!panel("gemm X", t.x_off, t.x_ld, xr, s.N)) return msg;
                     if (!panel("gemm Y", t.y_off, t.y_ld, yr, s.N)) return msg;
+                    const int th = s.bf16 ? kBf16TileRows : 64;
+                    if (t.tiles != (yr + th - 1) / th) return "gemm tile count";
                 }
+                for (int i = 0; i < s.n; ++i)
+                    if (R[i].tile < 0 || R[i].tile >= T[R[i].task].tiles * ((s.N + 63) / 64)) return "gemm tile ref";
+                if (s.bf16 && P.opt.precision == HSVD_FP64) return "bf16 pass on a float64 plan";
                 break;
             }
             case ST_TSQR_F:
@@ -890,11 +901,15 @@ std::string validate_plan(const hsvd_plan_st& P) {
 hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, const void* A, hipStream_t st) {
     unsigned char* b = (unsigned char*)P.dblob;
     hipError_t e = hipSuccess;
-    const int fp32 = P.opt.precision == HSVD_FP32;
+    const int fp32 = P.opt.precision != HSVD_FP64;
     switch (s.kind) {
         case ST_GEMM:
-            e = launch_gemm(s.op, fp32, A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
-                            (const TileRef*)(b + s.refs_off), s.n, s.N, st);
+            if (s.bf16)
+                e = launch_gemm_bf16(s.op, (const float*)A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
+                                     (const TileRef*)(b + s.refs_off), s.n, s.N, st);
+            else
+                e = launch_gemm(s.op, fp32, A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
+                                (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             break;
         case ST_TSQR_F:
             e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
@@ -959,7 +974,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, 
     hsvd_options o;
     hsvd_default_options(&o);
     if (opt) o = *opt;
-    if (o.precision != HSVD_FP64 && o.precision != HSVD_FP32)
+    if (o.precision != HSVD_FP64 && o.precision != HSVD_FP32 && o.precision != HSVD_MIXED_BF16)
         return fail(HSVD_ERR_INVALID, "unknown precision");
     if (o.rule != HSVD_RULE_GAMMA && o.rule != HSVD_RULE_FROB)
         return fail(HSVD_ERR_INVALID, "unknown rule");
@@ -1045,7 +1060,7 @@ hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void
         if (st != HSVD_OK) return st;
         if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
     }
-    e = launch_output(P.opt.precision == HSVD_FP32, P.ws, P.iws, P.out, U, S, Vt, stream);
+    e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws, P.out, U, S, Vt, stream);
     if (e != hipSuccess) return hip_fail(e, "output launch");
     if (prof && (e = hipEventRecord(P.events.back(), stream)) != hipSuccess) return hip_fail(e, "event");
     P.last_stream = stream;
@@ -1081,7 +1096,10 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
         if (i < (int)plan->stages.size()) {
             const Stage& s = plan->stages[i];
             switch (s.kind) {
-                case ST_GEMM: kind = s.op == 0 ? HSVD_LAUNCH_GEMM_AX : HSVD_LAUNCH_GEMM_ATX; break;
+                case ST_GEMM:
+                    kind = s.bf16 ? (s.op == 0 ? HSVD_LAUNCH_GEMM_AX_BF16 : HSVD_LAUNCH_GEMM_ATX_BF16)
+                                  : (s.op == 0 ? HSVD_LAUNCH_GEMM_AX : HSVD_LAUNCH_GEMM_ATX);
+                    break;
                 case ST_TSQR_F: kind = HSVD_LAUNCH_TSQR_FACTOR; break;
                 case ST_TSQR_A: kind = HSVD_LAUNCH_TSQR_APPLY; break;
                 case ST_GRAM: kind = HSVD_LAUNCH_GRAM; break;
@@ -1108,7 +1126,7 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
     *count_host = n;
     if (!flops_host || !bytes_host) return HSVD_OK;
     const unsigned char* b = P.blob.data();
-    const double eA = P.opt.precision == HSVD_FP32 ? 4.0 : 8.0, e8 = 8.0;
+    const double eA = P.opt.precision != HSVD_FP64 ? 4.0 : 8.0, e8 = 8.0;
     for (int i = 0; i < n && i < cap; ++i) {
         double f = 0.0, by = 0.0;
         if (i == n - 1) {                                   // output: U, Vt from the panels

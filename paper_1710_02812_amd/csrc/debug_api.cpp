@@ -98,6 +98,45 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
     return HSVD_OK;
 }
 
+extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32, const void* A,
+                                       int64_t rows, int64_t cols, int64_t lda, const double* X,
+                                       int32_t N, double* Y, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    if (!A || !X || !Y || (op != 0 && op != 1) || (kind != 0 && kind != 1) || rows < 1 || cols < 1 ||
+        lda < cols || N < 1 || N > 1024 || (kind == 1 && !a_fp32) || rows > (1 << 20) || cols > (1 << 20))
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_gemm: bad argument");
+    const int64_t xr = op == 0 ? cols : rows, yr = op == 0 ? rows : cols;
+    Scratch sc;
+    double* ws = sc.get<double>(xr * N + yr * N);
+    GemmTask* dt = sc.get<GemmTask>(1);
+    const int tile_rows = kind == 1 ? kBf16TileRows : 64;
+    const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = (N + 63) / 64;
+    TileRef* dtiles = sc.get<TileRef>((size_t)nrt * nct);
+    if (!ws || !dt || !dtiles) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    GemmTask t{};
+    t.a_off = 0;
+    t.x_off = 0;
+    t.y_off = xr * N;
+    t.rows = (int32_t)rows;
+    t.cols = (int32_t)cols;
+    t.x_ld = (int32_t)xr;
+    t.y_ld = (int32_t)yr;
+    t.tiles = nrt;
+    std::vector<TileRef> tiles((size_t)nrt * nct);
+    for (int i = 0; i < nrt * nct; ++i) tiles[i] = {0, i};
+    hipError_t e = hipMemcpyAsync(ws, X, sizeof(double) * xr * N, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dtiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = kind == 1 ? launch_gemm_bf16(op, (const float*)A, lda, ws, dt, dtiles, nrt * nct, N, stream)
+                      : launch_gemm(op, a_fp32, A, lda, ws, dt, dtiles, nrt * nct, N, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Y, ws + xr * N, sizeof(double) * yr * N, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_gemm: ") + hipGetErrorString(e));
+    return HSVD_OK;
+}
+
 extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w,
                                        double* Q, double* R, hipStream_t stream) {
     using hsvd_detail::set_error;

@@ -119,6 +119,10 @@ struct OutputArgs {
 
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return the hipError_t of the launch.
+// bfloat16 matrix-core passes: 128 x 64 output tiles (TileRef.tile = row tile * ceil(N / 64) + col tile)
+constexpr int kBf16TileRows = 128;
+hipError_t launch_gemm_bf16(int op, const float* A, int64_t lda, double* ws, const GemmTask* tasks,
+                            const TileRef* tiles, int ntiles, int N, hipStream_t s);
 hipError_t launch_gemm(int op, int fp32, const void* A, int64_t lda, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s);

@@ -16,16 +16,16 @@ LIB_PATH = os.path.join(HERE, "libhsvd.so")
 HSVD_OK = 0
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_NONFINITE",
                 5: "ERR_NOCONV", 6: "ERR_UNSUPPORTED"}
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED_BF16 = 0, 1, 2
 RULE_GAMMA, RULE_FROB = 0, 1
 FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 
 EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
             "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
             "hsvd_set_profiling", "hsvd_launch_times", "hsvd_launch_work",
-            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check"]
+            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check", "hsvd_debug_gemm"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
-                "sum", "core", "output"]
+                "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16"]
 
 
 class HsvdError(RuntimeError):
@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_launch_work.argtypes = [vp, P(f64), P(f64), i32, P(i32)]
     L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
     L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
+    L.hsvd_debug_gemm.argtypes = [i32, i32, i32, vp, i64, i64, i64, vp, i32, vp, vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
                                         P(ctypes.c_size_t)]
     for name in EXPORTED:
@@ -178,15 +179,18 @@ class Plan:
             pass
 
 
-def svd(A, p: int, q: int, k: int, tol: float = 0.0, **opts):
-    """Hierarchical MAT truncated SVD of a torch device matrix A (float64 or float32).
+def svd(A, p: int, q: int, k: int, tol: float = 0.0, mixed: bool = False, **opts):
+    """Hierarchical MAT truncated SVD of a torch device matrix A (float64 or float32;
+    mixed=True selects the bfloat16 matrix-core passes for a float32 A).
 
     Returns (U [m x k], S [k], Vt [k x n], r); entries past the rank r are zero.
     """
     import torch
     if A.dtype not in (torch.float64, torch.float32):
         raise ValueError("A must be float64 or float32")
-    prec = FP64 if A.dtype == torch.float64 else FP32
+    if mixed and A.dtype != torch.float32:
+        raise ValueError("the mixed path takes a float32 A")
+    prec = FP64 if A.dtype == torch.float64 else (MIXED_BF16 if mixed else FP32)
     A = A.contiguous()
     m, n = A.shape
     plan = Plan(m, n, p, q, k, tol, precision=prec, **opts)
@@ -228,6 +232,22 @@ def plan_check(m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, **opts)
     b = ctypes.c_size_t()
     _check(lib().hsvd_debug_plan_check(m, n, p, q, k, float(tol), ctypes.byref(o), ctypes.byref(b)))
     return b.value
+
+
+def debug_gemm(A, X, op: int = 0, bf16: bool = False):
+    """One pass product on a single block: op 0 -> A @ X, op 1 -> A.T @ X (float64 result).
+    A: (rows, cols) float32/float64 device tensor (row-major); X: float64 (K, N)."""
+    import torch
+    rows, cols = A.shape
+    K, N = X.shape
+    assert K == (cols if op == 0 else rows)
+    Ac = A.contiguous()
+    Xc = X.t().contiguous()                  # col-major storage
+    yr = rows if op == 0 else cols
+    Y = torch.empty((N, yr), dtype=torch.float64, device=A.device)
+    _check(lib().hsvd_debug_gemm(op, int(bf16), int(Ac.dtype == torch.float32), Ac.data_ptr(),
+                                 rows, cols, cols, Xc.data_ptr(), N, Y.data_ptr(), _stream_handle()))
+    return Y.t()
 
 
 def debug_tsqr(P):

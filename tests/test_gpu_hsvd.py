@@ -152,3 +152,35 @@ def test_plan_reuse_and_repeatability():
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
     plan.close()
+
+
+@pytest.mark.parametrize("seed", [0, 100])
+def test_mixed_bf16_config0(seed):
+    """Mixed path (bfloat16 matrix-core passes + float32-accurate projection and
+    refinement) against the oracle on the same float32 input: e_frob <= 1e-3."""
+    w = synth.config0(seed)
+    A32 = w.A.astype(np.float32)
+    Ao = A32.astype(np.float64)
+    Uo, so, Vto, ro = oracle.hsvd(Ao, w.p, w.q, w.k, w.tol)
+    At = torch.tensor(A32, device=DEV)
+    U, S, Vt, r = H.svd(At, w.p, w.q, w.k, w.tol, mixed=True)
+    torch.cuda.synchronize()
+    c = metrics.compare(U.double().cpu().numpy(), S.double().cpu().numpy(), Vt.double().cpu().numpy(), r,
+                        Uo, so, Vto, ro)
+    print("mixed C0", c, flush=True)
+    assert r == ro
+    assert c["e_frob"] <= 1e-3 and c["e_sigma"] <= 1e-3
+
+
+def test_mixed_bf16_snapshot_2048():
+    """Mixed path on a 2048^2 snapshot-like matrix (4 x 4 grid of 512^2, k = 50)."""
+    w = synth.config1(1, m=2048, n=2048, block=512)
+    A32 = w.A.astype(np.float32)
+    Uo, so, Vto, ro = oracle.hsvd(A32.astype(np.float64), w.p, w.q, w.k, 0.0)
+    U, S, Vt, r = H.svd(torch.tensor(A32, device=DEV), w.p, w.q, w.k, 0.0, mixed=True)
+    torch.cuda.synchronize()
+    c = metrics.compare(U.double().cpu().numpy(), S.double().cpu().numpy(), Vt.double().cpu().numpy(), r,
+                        Uo, so, Vto, ro)
+    print("mixed 2048", c, flush=True)
+    assert r == ro
+    assert c["e_frob"] <= 1e-3 and c["e_sigma"] <= 1e-3

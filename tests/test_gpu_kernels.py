@@ -149,3 +149,34 @@ def test_tsqr_random_panels(h, w):
             Rref = np.linalg.qr(P[b], mode="r")
             assert np.allclose(np.abs(np.diag(R[b])[:kk]), np.abs(np.diag(Rref)[:kk]),
                                rtol=1e-11, atol=1e-12 * np.abs(Rref).max())
+
+
+def _bf16(x):
+    """Round to bfloat16 (nearest even) through float32, as the matrix-core passes do."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("rows,cols,op,N", [(300, 200, 0, 50), (1024, 1024, 0, 64), (1000, 130, 1, 17),
+                                            (129, 257, 1, 64), (1024, 1024, 1, 50), (77, 33, 0, 100)])
+def test_gemm_bf16_matrix_cores(rows, cols, op, N):
+    """bfloat16 MFMA pass: equals the float64 product of the bfloat16-rounded operands
+    up to float32 summation error (this also fixes the MFMA lane layout)."""
+    rng = np.random.default_rng(rows + cols + N)
+    A = rng.standard_normal((rows, cols)).astype(np.float32)
+    K = cols if op == 0 else rows
+    X = rng.standard_normal((K, N))
+    print(f"gemm bf16 {rows}x{cols} op{op} N={N}", flush=True)
+    At = torch.tensor(A, device=DEV)
+    Y = H.debug_gemm(At, _t(X), op=op, bf16=True).cpu().numpy()
+    Ab, Xb = _bf16(A), _bf16(X)
+    ref = (Ab @ Xb) if op == 0 else (Ab.T @ Xb)
+    bound = (np.abs(Ab) @ np.abs(Xb)) if op == 0 else (np.abs(Ab).T @ np.abs(Xb))
+    assert np.all(np.abs(Y - ref) <= 2.0 * K * 2.0 ** -24 * bound + 1e-30)
+    # and the float64-arithmetic kernel on the same float32 A is exact to float64 rounding
+    Y64 = H.debug_gemm(At, _t(X), op=op, bf16=False).cpu().numpy()
+    A64 = A.astype(np.float64)
+    ref64 = (A64 @ X) if op == 0 else (A64.T @ X)
+    assert np.max(np.abs(Y64 - ref64)) <= 1e-13 * np.max(np.abs(ref64)) * np.sqrt(K)
