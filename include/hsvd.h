@@ -111,14 +111,37 @@ hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int3
  *   A, U, S, Vt must not overlap.                                               */
 hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
                          hipStream_t stream);
+/* (A plan from hsvd_plan_batched takes hsvd_execute_batched instead.) */
+
+/* Plan over `count` matrices of arbitrary shapes (Section 3: the leaves and the
+ * merges of different matrices are independent), executed together: every launch
+ * of an execute covers the same stage of all matrices.  m[i], n[i], p[i], q[i],
+ * k[i] (host arrays) describe matrix i with the same constraints as hsvd_plan_ex;
+ * tol and opt apply to all.  The panels of the batch share one width (max k) and
+ * one sketch width; each matrix keeps its own rank cap k[i].
+ * HSVD_ERR_INVALID names the first bad matrix; count must be 1..65535.         */
+hsvd_status hsvd_plan_batched(hsvd_plan_t* out, int32_t count, const int64_t* m, const int64_t* n,
+                              const int32_t* p, const int32_t* q, const int32_t* k, double tol,
+                              const hsvd_options* opt);
+
+/* Execute of a plan from hsvd_plan_batched: A[i], U[i], S[i], Vt[i] (host arrays
+ * of device pointers) are the operands of matrix i, laid out as in hsvd_execute.
+ * Asynchronous on `stream`; when the pointers differ from the previous execute's,
+ * the call first waits for the previous execute and uploads the new pointers.   */
+hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* const* U,
+                                 void* const* S, void* const* Vt, hipStream_t stream);
 
 /* Frees the plan and its workspace after synchronising its last stream.
  * plan == NULL is accepted and does nothing. */
 hsvd_status hsvd_destroy(hsvd_plan_t plan);
 
 /* Copies the effective rank of the last execute to *r_host (synchronises that
- * execute's stream). */
+ * execute's stream).  Single-matrix plans only. */
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host);
+
+/* Effective ranks of all `count` matrices of the last execute (count must equal
+ * the plan's matrix count; synchronises). */
+hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count);
 
 /* Copies the status of the last execute to *flags_host (synchronises): bits 0..15
  * hold the HSVD_FLAG_* conditions, bits 16..31 the largest number of Jacobi sweeps

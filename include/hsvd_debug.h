@@ -49,6 +49,12 @@ hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32, const void
 hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
                                   double tol, const hsvd_options* opt, size_t* workspace_bytes);
 
+/* hsvd_debug_plan_check for a plan over `count` matrices (hsvd_plan_batched). */
+hsvd_status hsvd_debug_plan_check_batched(int32_t count, const int64_t* m, const int64_t* n,
+                                          const int32_t* p, const int32_t* q, const int32_t* k,
+                                          double tol, const hsvd_options* opt,
+                                          size_t* workspace_bytes);
+
 /* Householder TSQR of `batch` h x w panels P (w <= 80): Q (h x w, orthonormal
  * columns) and R (w x w upper triangular) with P = Q R.  P is not modified.   */
 hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,

@@ -4,5 +4,5 @@ The compute path is the HIP library ``libhsvd.so`` built from ``csrc/``; the
 ``hsvd`` module only marshals arguments to its C ABI.  ``synth`` holds the
 seeded synthetic workloads.
 """
-from .hsvd import (Plan, svd, HsvdError, FP64, FP32, MIXED_BF16, RULE_GAMMA, RULE_FROB,  # noqa: F401
-                   FLAG_NONFINITE, FLAG_NOCONV)
+from .hsvd import (Plan, BatchPlan, svd, svd_batched, HsvdError, FP64, FP32, MIXED_BF16,  # noqa: F401
+                   RULE_GAMMA, RULE_FROB, FLAG_NONFINITE, FLAG_NOCONV)

@@ -76,13 +76,20 @@ constexpr int THIN_CH = 256;
 
 }  // namespace
 
-struct hsvd_plan_st {
+// One matrix of a plan: shape, grid, rank cap and the balanced split points.
+struct MatDesc {
     int64_t m = 0, n = 0;
     int p = 0, q = 0, k = 0;
+    std::vector<int64_t> rs, cs;
+    int64_t brow(int i) const { return rs[i + 1] - rs[i]; }
+    int64_t bcol(int j) const { return cs[j + 1] - cs[j]; }
+};
+
+struct hsvd_plan_st {
+    std::vector<MatDesc> mats;     // one for hsvd_plan, count for hsvd_plan_batched
     double tol = 0.0;
     hsvd_options opt{};
-    int W = 0, L = 0, g = 0;
-    std::vector<int64_t> rs, cs;   // split points
+    int W = 0, L = 0, g = 0;       // panel width (max k), leaf sketch width, products per leaf
 
     // arenas (host-side bookkeeping)
     int64_t ws_elems = 0;
@@ -100,12 +107,16 @@ struct hsvd_plan_st {
     int* iws = nullptr;
     unsigned* flags = nullptr;
     void* dblob = nullptr;
+    void** dptrs = nullptr;        // pointer table: A, U, S, Vt per matrix
+    std::vector<void*> host_ptrs;  // its last uploaded contents
     hipStream_t last_stream = nullptr;
     bool executed = false;
 
     // final
-    OutputArgs out{};
-    int rank_slot = -1;
+    std::vector<OutputArgs> outs;  // per matrix
+    std::vector<int> rank_slots;   // per matrix
+    size_t outs_off = 0;           // OutputArgs array in the task blob
+    int kmax = 0, mmax = 0, nmax = 0;
 
     // optional per-launch timing: events[i] .. events[i+1] bracket launch i
     bool profiling = false;
@@ -129,8 +140,6 @@ struct hsvd_plan_st {
         if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
         return off;
     }
-    int64_t brow(int i) const { return rs[i + 1] - rs[i]; }
-    int64_t bcol(int j) const { return cs[j + 1] - cs[j]; }
 };
 
 namespace {
@@ -139,6 +148,7 @@ namespace {
 struct Node {            // a factor node: panel (h x W, ld), sigma (W), rank slot
     int64_t panel, sig;
     int ld, h, rank;
+    int mat;             // matrix of the batch
 };
 
 struct TsqrBuild {
@@ -244,12 +254,12 @@ void push_core(hsvd_plan_st& P, const std::vector<CoreTask>& tasks, int maxdim, 
     P.stages.push_back(s);
 }
 
-CoreTask core_defaults(const hsvd_plan_st& P) {
+CoreTask core_defaults(const hsvd_plan_st& P, int k) {
     CoreTask c{};
     c.rank_in = -1;
     c.u_off = c.t_off = c.v_off = -1;
     c.rank1 = c.rank2 = -1;
-    c.kcap = P.k;
+    c.kcap = k;
     c.rule = P.opt.rule;
     c.tol = P.tol;
     c.floor_cols = -1;
@@ -264,6 +274,16 @@ int64_t identity_panel(hsvd_plan_st& P, int w) {
     for (int i = 0; i < w; ++i) I[(size_t)i * w + i] = 1.0;
     P.ws_init.push_back({off, I});
     return off;
+}
+
+GemmTask gemm_task(const hsvd_plan_st& P, int mat, int64_t a_off, int64_t rows, int64_t cols) {
+    GemmTask t{};
+    t.mat = mat;
+    t.lda = P.mats[mat].n;
+    t.a_off = a_off;
+    t.rows = (int)rows;
+    t.cols = (int)cols;
+    return t;
 }
 
 // One level of merges (all pairs of all trees at this level), in place of the
@@ -309,13 +329,14 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
 
         const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq);
         Node o{};
+        o.mat = a.mat;
         o.h = h;
         o.ld = a.ld;
         o.panel = P.alloc((int64_t)o.ld * W);
         o.sig = P.alloc(W);
         o.rank = P.ialloc(1);
         const int64_t T = P.alloc((int64_t)W * W), X = P.alloc((int64_t)W * W);
-        CoreTask c = core_defaults(P);
+        CoreTask c = core_defaults(P, P.mats[a.mat].k);
         c.mode = CORE_MERGE;
         c.s1_off = a.sig; c.s2_off = b.sig;
         c.c_off = Cacc; c.c_ld = W;
@@ -384,52 +405,57 @@ std::vector<Node> merge_forest(hsvd_plan_st& P, std::vector<std::vector<Node>> t
     return roots;
 }
 
-// Leaves: randomised range finder with power steps, per block.
+// Leaves: randomised range finder with power steps, per block of every matrix.
+// Returns one forest per (matrix, row slab), matrices in order, slabs top to bottom.
 std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
     const int L = P.L, W = P.W, g = P.g;
-    const int p = P.p, q = P.q;
-    const int64_t brmax = P.brow(0), bcmax = P.bcol(0);
+    int64_t bcmax = 1;
+    for (const auto& M : P.mats)
+        for (int j = 0; j < M.q; ++j) bcmax = std::max(bcmax, M.bcol(j));
     P.omega_count = bcmax * L;
     P.omega_off = P.alloc(P.omega_count);
     const int64_t I_L = identity_panel(P, L);
+    const bool bf16 = P.opt.precision == HSVD_MIXED_BF16;
 
-    struct Leaf { int i, j; int64_t rowsz, colsz, aoff; int64_t Y, Z, Qy, Qz; };
+    struct Leaf { int mat, i, j; int64_t rowsz, colsz, aoff; int64_t Y, Z, Qy, Qz; };
     std::vector<Leaf> leaves;
-    for (int i = 0; i < p; ++i)
-        for (int j = 0; j < q; ++j) {
-            Leaf l{};
-            l.i = i; l.j = j;
-            l.rowsz = P.brow(i);
-            l.colsz = P.bcol(j);
-            l.aoff = P.rs[i] * P.n + P.cs[j];
-            l.Y = P.alloc(brmax * L);
-            l.Z = P.alloc(bcmax * L);
-            l.Qy = P.alloc(brmax * L);
-            l.Qz = P.alloc(bcmax * L);
-            leaves.push_back(l);
-        }
+    for (int mi = 0; mi < (int)P.mats.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        for (int i = 0; i < M.p; ++i)
+            for (int j = 0; j < M.q; ++j) {
+                Leaf l{};
+                l.mat = mi;
+                l.i = i; l.j = j;
+                l.rowsz = M.brow(i);
+                l.colsz = M.bcol(j);
+                l.aoff = M.rs[i] * M.n + M.cs[j];
+                l.Y = P.alloc(l.rowsz * L);
+                l.Z = P.alloc(l.colsz * L);
+                l.Qy = P.alloc(l.rowsz * L);
+                l.Qz = P.alloc(l.colsz * L);
+                leaves.push_back(l);
+            }
+    }
     // product t = 0: Y = A_b Omega
     {
         std::vector<GemmTask> gt;
         for (auto& l : leaves) {
-            GemmTask t{};
-            t.a_off = l.aoff; t.rows = (int)l.rowsz; t.cols = (int)l.colsz;
+            GemmTask t = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
             t.x_off = P.omega_off; t.x_ld = (int)bcmax;
-            t.y_off = l.Y; t.y_ld = (int)brmax;
+            t.y_off = l.Y; t.y_ld = (int)l.rowsz;
             gt.push_back(t);
         }
-        push_gemm(P, 0, gt, L, P.opt.precision == HSVD_MIXED_BF16);
+        push_gemm(P, 0, gt, L, bf16);
     }
     const int ch = tsqr_chunk(L, std::max(L, W));
-    std::vector<int> last_tsqr(leaves.size());
     TsqrBuild tb_last;
     for (int t = 1; t <= g; ++t) {
         // QR of the previous product (Y if t-1 even, Z if odd)
         const bool prev_is_y = ((t - 1) % 2 == 0);
         TsqrBuild tb;
         for (auto& l : leaves) {
-            if (prev_is_y) add_tsqr(P, tb, l.Y, (int)l.rowsz, (int)brmax, L, ch);
-            else add_tsqr(P, tb, l.Z, (int)l.colsz, (int)bcmax, L, ch);
+            if (prev_is_y) add_tsqr(P, tb, l.Y, (int)l.rowsz, (int)l.rowsz, L, ch);
+            else add_tsqr(P, tb, l.Z, (int)l.colsz, (int)l.colsz, L, ch);
         }
         push_tsqr_factor(P, tb, L, ch);
         if (t == g) { tb_last = tb; break; }
@@ -439,7 +465,7 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
             a.tsqr = (int)b;
             a.x_off = I_L;
             a.out_off = prev_is_y ? leaves[b].Qy : leaves[b].Qz;
-            a.out_ld = prev_is_y ? (int)brmax : (int)bcmax;
+            a.out_ld = prev_is_y ? (int)leaves[b].rowsz : (int)leaves[b].colsz;
             a.add_u_off = -1;
             at.push_back(a);
         }
@@ -447,18 +473,17 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
         // next product
         std::vector<GemmTask> gt;
         for (auto& l : leaves) {
-            GemmTask x{};
-            x.a_off = l.aoff; x.rows = (int)l.rowsz; x.cols = (int)l.colsz;
+            GemmTask x = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
             if (prev_is_y) {            // Z = A_b^T Qy
-                x.x_off = l.Qy; x.x_ld = (int)brmax;
-                x.y_off = l.Z; x.y_ld = (int)bcmax;
+                x.x_off = l.Qy; x.x_ld = (int)l.rowsz;
+                x.y_off = l.Z; x.y_ld = (int)l.colsz;
             } else {                    // Y = A_b Qz
-                x.x_off = l.Qz; x.x_ld = (int)bcmax;
-                x.y_off = l.Y; x.y_ld = (int)brmax;
+                x.x_off = l.Qz; x.x_ld = (int)l.colsz;
+                x.y_off = l.Y; x.y_ld = (int)l.rowsz;
             }
             gt.push_back(x);
         }
-        push_gemm(P, prev_is_y ? 1 : 0, gt, L, P.opt.precision == HSVD_MIXED_BF16);
+        push_gemm(P, prev_is_y ? 1 : 0, gt, L, bf16);
     }
     // core of the last product
     const bool last_is_y = ((g - 1) % 2 == 0);
@@ -468,14 +493,15 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
     for (size_t b = 0; b < leaves.size(); ++b) {
         const Leaf& l = leaves[b];
         Node nd{};
+        nd.mat = l.mat;
         nd.h = (int)l.rowsz;
-        nd.ld = (int)brmax;
-        nd.panel = P.alloc(brmax * W);
+        nd.ld = (int)l.rowsz;
+        nd.panel = P.alloc(l.rowsz * W);
         nd.sig = P.alloc(W);
         nd.rank = P.ialloc(1);
         nodes.push_back(nd);
         ur[b] = P.alloc((int64_t)L * W);
-        CoreTask c = core_defaults(P);
+        CoreTask c = core_defaults(P, P.mats[l.mat].k);
         c.mode = last_is_y ? CORE_UPPER : CORE_UPPER_T;
         c.dim = L;
         c.m_off = tb_last.tasks[b].r_out;
@@ -506,7 +532,7 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
         std::vector<ThinTask> nn;
         for (size_t b = 0; b < leaves.size(); ++b) {
             ThinTask t{};
-            t.x_off = leaves[b].Qy; t.x_ld = (int)brmax;
+            t.x_off = leaves[b].Qy; t.x_ld = (int)leaves[b].rowsz;
             t.c_off = ur[b]; t.c_ld = L;
             t.y_off = nodes[b].panel; t.y_ld = nodes[b].ld;
             t.h = (int)leaves[b].rowsz; t.wx = L; t.wy = W;
@@ -515,44 +541,61 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
         }
         push_thin(P, ST_NN, nn);
     }
-    std::vector<std::vector<Node>> slabs(p);
-    for (size_t b = 0; b < leaves.size(); ++b) slabs[leaves[b].i].push_back(nodes[b]);
+    std::vector<std::vector<Node>> slabs;
+    int prev_mat = -1, prev_i = -1;
+    for (size_t b = 0; b < leaves.size(); ++b) {
+        if (leaves[b].mat != prev_mat || leaves[b].i != prev_i) {
+            slabs.emplace_back();
+            prev_mat = leaves[b].mat;
+            prev_i = leaves[b].i;
+        }
+        slabs.back().push_back(nodes[b]);
+    }
     return slabs;
 }
 
-// Slab re-projection: V_i, s_i = SVD(U_i^T A_i).
-std::vector<Node> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& roots) {
+// Slab re-projection: V_i, s_i = SVD(U_i^T A_i), for the column-tree root of every
+// (matrix, slab) in the order build_leaves produced them.  Returns one row forest
+// per matrix.
+std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& roots) {
     const int W = P.W;
-    const int n = (int)P.n;
     const int ch = tsqr_chunk(W, W);
     std::vector<GemmTask> gt;
     TsqrBuild tb;
     std::vector<int64_t> Zs(roots.size());
+    std::vector<int> slab(roots.size());
     for (size_t i = 0; i < roots.size(); ++i) {
+        const int mi = roots[i].mat;
+        slab[i] = (i > 0 && roots[i - 1].mat == mi) ? slab[i - 1] + 1 : 0;
+        const MatDesc& M = P.mats[mi];
+        const int n = (int)M.n;
         Zs[i] = P.alloc((int64_t)n * W);
-        GemmTask t{};
-        t.a_off = P.rs[i] * P.n;
-        t.rows = (int)P.brow((int)i);
-        t.cols = n;
+        GemmTask t = gemm_task(P, mi, M.rs[slab[i]] * M.n, M.brow(slab[i]), n);
         t.x_off = roots[i].panel; t.x_ld = roots[i].ld;
         t.y_off = Zs[i]; t.y_ld = n;
         gt.push_back(t);
     }
     push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16);
-    for (size_t i = 0; i < roots.size(); ++i) add_tsqr(P, tb, Zs[i], n, n, W, ch);
+    for (size_t i = 0; i < roots.size(); ++i) {
+        const int n = (int)P.mats[roots[i].mat].n;
+        add_tsqr(P, tb, Zs[i], n, n, W, ch);
+    }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<CoreTask> cores;
     std::vector<ApplyTask> at;
-    std::vector<Node> out;
+    std::vector<std::vector<Node>> out(P.mats.size());
     for (size_t i = 0; i < roots.size(); ++i) {
+        const int mi = roots[i].mat;
+        const int n = (int)P.mats[mi].n;
         Node nd{};
+        nd.mat = mi;
         nd.h = n;
         nd.ld = n;
         nd.panel = P.alloc((int64_t)n * W);
         nd.sig = P.alloc(W);
         nd.rank = P.ialloc(1);
         const int64_t X = P.alloc((int64_t)W * W);
-        CoreTask c = core_defaults(P);
+        CoreTask c = core_defaults(P, P.mats[mi].k);
         c.mode = CORE_UPPER;
         c.dim = W;
         c.m_off = tb.tasks[i].r_out;
@@ -573,7 +616,7 @@ std::vector<Node> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& r
         a.out_ld = n;
         a.add_u_off = -1;
         at.push_back(a);
-        out.push_back(nd);
+        out[mi].push_back(nd);
     }
     push_core(P, cores, W, 0);
     push_tsqr_apply(P, tb, at, W, ch, W);
@@ -582,173 +625,226 @@ std::vector<Node> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& r
 
 struct Factors { int64_t U, V, sig; int rank; };
 
-// Left vectors by projection: Y = A V (split over column blocks), TSQR(Y) = Q R,
-// Jacobi on R (with rotations J): U = Q Z, V <- V J.
-Factors build_projection(hsvd_plan_st& P, int64_t Vpanel, int vld, int rank_slot) {
+// Left vectors by projection, for every matrix: Y = A V (split over column
+// blocks), TSQR(Y) = Q R, Jacobi on R (with rotations J): U = Q Z, V <- V J.
+std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& vs) {
     const int W = P.W;
-    const int64_t m = P.m, n = P.n;
     const int ch = tsqr_chunk(W, W);
-    const int64_t parts = P.alloc((int64_t)P.q * m * W);
     std::vector<GemmTask> gt;
-    for (int i = 0; i < P.p; ++i)
-        for (int j = 0; j < P.q; ++j) {
-            GemmTask t{};
-            t.a_off = P.rs[i] * n + P.cs[j];
-            t.rows = (int)P.brow(i);
-            t.cols = (int)P.bcol(j);
-            t.x_off = Vpanel + P.cs[j];
-            t.x_ld = vld;
-            t.y_off = parts + (int64_t)j * m * W + P.rs[i];
-            t.y_ld = (int)m;
-            gt.push_back(t);
-        }
-    push_gemm(P, 0, gt, W);
-    const int64_t Y = P.alloc(m * W);
-    {
+    std::vector<ThinTask> sums;
+    std::vector<int64_t> Ys(vs.size());
+    for (size_t mi = 0; mi < vs.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        const int64_t m = M.m, n = M.n;
+        const int64_t parts = P.alloc((int64_t)M.q * m * W);
+        for (int i = 0; i < M.p; ++i)
+            for (int j = 0; j < M.q; ++j) {
+                GemmTask t = gemm_task(P, (int)mi, M.rs[i] * n + M.cs[j], M.brow(i), M.bcol(j));
+                t.x_off = vs[mi].panel + M.cs[j];
+                t.x_ld = vs[mi].ld;
+                t.y_off = parts + (int64_t)j * m * W + M.rs[i];
+                t.y_ld = (int)m;
+                gt.push_back(t);
+            }
+        Ys[mi] = P.alloc(m * W);
         ThinTask s{};
         s.x_off = parts; s.x_ld = (int)m;
         s.c_ld = (int)(m * W);      // stride between partials
-        s.wx = P.q; s.wy = W;
-        s.y_off = Y; s.y_ld = (int)m;
+        s.wx = M.q; s.wy = W;
+        s.y_off = Ys[mi]; s.y_ld = (int)m;
         s.h = (int)m;
         s.acc_off = -1;
-        push_thin(P, ST_SUM, {s});
+        sums.push_back(s);
     }
+    push_gemm(P, 0, gt, W);
+    push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
-    add_tsqr(P, tb, Y, (int)m, (int)m, W, ch);
+    for (size_t mi = 0; mi < vs.size(); ++mi) {
+        const int m = (int)P.mats[mi].m;
+        add_tsqr(P, tb, Ys[mi], m, m, W, ch);
+    }
     push_tsqr_factor(P, tb, W, ch);
-    Factors f{};
-    f.U = P.alloc(m * W);
-    f.V = P.alloc(n * W);
-    f.sig = P.alloc(W);
-    f.rank = P.ialloc(1);
-    const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
-    CoreTask c = core_defaults(P);
-    c.mode = CORE_UPPER;
-    c.dim = W;
-    c.m_off = tb.tasks[0].r_out;
-    c.m_ld = W;
-    c.rank_in = rank_slot;
-    c.u_off = X; c.u_ld = W;
-    c.v_off = J; c.v_ld = W;
-    c.sig_off = f.sig;
-    c.out_w = W;
-    c.rank_out = f.rank;
-    c.floor_rows = (int)m;
-    c.floor_cols = -1;
-    c.fixed_rank_slot = rank_slot;
-    push_core(P, {c}, W, 1);
-    ApplyTask a{};
-    a.tsqr = 0;
-    a.x_off = X;
-    a.out_off = f.U;
-    a.out_ld = (int)m;
-    a.add_u_off = -1;
-    push_tsqr_apply(P, tb, {a}, W, ch, W);
-    ThinTask nn{};
-    nn.x_off = Vpanel; nn.x_ld = vld;
-    nn.c_off = J; nn.c_ld = W;
-    nn.y_off = f.V; nn.y_ld = (int)n;
-    nn.h = (int)n; nn.wx = W; nn.wy = W;
-    nn.accumulate = 0; nn.acc_off = -1;
-    push_thin(P, ST_NN, {nn});
-    return f;
+    std::vector<Factors> fs(vs.size());
+    std::vector<CoreTask> cores;
+    std::vector<ApplyTask> at;
+    std::vector<ThinTask> nns;
+    for (size_t mi = 0; mi < vs.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        const int64_t m = M.m, n = M.n;
+        Factors& f = fs[mi];
+        f.U = P.alloc(m * W);
+        f.V = P.alloc(n * W);
+        f.sig = P.alloc(W);
+        f.rank = P.ialloc(1);
+        const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
+        CoreTask c = core_defaults(P, M.k);
+        c.mode = CORE_UPPER;
+        c.dim = W;
+        c.m_off = tb.tasks[mi].r_out;
+        c.m_ld = W;
+        c.rank_in = vs[mi].rank;
+        c.u_off = X; c.u_ld = W;
+        c.v_off = J; c.v_ld = W;
+        c.sig_off = f.sig;
+        c.out_w = W;
+        c.rank_out = f.rank;
+        c.floor_rows = (int)m;
+        c.floor_cols = -1;
+        c.fixed_rank_slot = vs[mi].rank;
+        cores.push_back(c);
+        ApplyTask a{};
+        a.tsqr = (int)mi;
+        a.x_off = X;
+        a.out_off = f.U;
+        a.out_ld = (int)m;
+        a.add_u_off = -1;
+        at.push_back(a);
+        ThinTask nn{};
+        nn.x_off = vs[mi].panel; nn.x_ld = vs[mi].ld;
+        nn.c_off = J; nn.c_ld = W;
+        nn.y_off = f.V; nn.y_ld = (int)n;
+        nn.h = (int)n; nn.wx = W; nn.wy = W;
+        nn.accumulate = 0; nn.acc_off = -1;
+        nns.push_back(nn);
+    }
+    push_core(P, cores, W, 1);
+    push_tsqr_apply(P, tb, at, W, ch, W);
+    push_thin(P, ST_NN, nns);
+    return fs;
 }
 
-// One Algorithm 2 step from (U_i = left vectors of A V): W^T = A^T U_i = Q R;
-// Jacobi on R with rotations J: V~ = Q Z, U^ = U_i J, S~.
-Factors build_refine_step(hsvd_plan_st& P, const Factors& in) {
+// One Algorithm 2 step per matrix from (U_i = left vectors of A V):
+// W^T = A^T U_i = Q R; Jacobi on R with rotations J: V~ = Q Z, U^ = U_i J, S~.
+std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factors>& in) {
     const int W = P.W;
-    const int64_t m = P.m, n = P.n;
     const int ch = tsqr_chunk(W, W);
-    const int64_t parts = P.alloc((int64_t)P.p * n * W);
     std::vector<GemmTask> gt;
-    for (int i = 0; i < P.p; ++i) {
-        GemmTask t{};
-        t.a_off = P.rs[i] * n;
-        t.rows = (int)P.brow(i);
-        t.cols = (int)n;
-        t.x_off = in.U + P.rs[i];
-        t.x_ld = (int)m;
-        t.y_off = parts + (int64_t)i * n * W;
-        t.y_ld = (int)n;
-        gt.push_back(t);
-    }
-    push_gemm(P, 1, gt, W);
-    const int64_t Z = P.alloc(n * W);
-    {
+    std::vector<ThinTask> sums;
+    std::vector<int64_t> Zs(in.size());
+    for (size_t mi = 0; mi < in.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        const int64_t m = M.m, n = M.n;
+        const int64_t parts = P.alloc((int64_t)M.p * n * W);
+        for (int i = 0; i < M.p; ++i) {
+            GemmTask t = gemm_task(P, (int)mi, M.rs[i] * n, M.brow(i), n);
+            t.x_off = in[mi].U + M.rs[i];
+            t.x_ld = (int)m;
+            t.y_off = parts + (int64_t)i * n * W;
+            t.y_ld = (int)n;
+            gt.push_back(t);
+        }
+        Zs[mi] = P.alloc(n * W);
         ThinTask s{};
         s.x_off = parts; s.x_ld = (int)n;
         s.c_ld = (int)(n * W);
-        s.wx = P.p; s.wy = W;
-        s.y_off = Z; s.y_ld = (int)n;
+        s.wx = M.p; s.wy = W;
+        s.y_off = Zs[mi]; s.y_ld = (int)n;
         s.h = (int)n;
         s.acc_off = -1;
-        push_thin(P, ST_SUM, {s});
+        sums.push_back(s);
     }
+    push_gemm(P, 1, gt, W);
+    push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
-    add_tsqr(P, tb, Z, (int)n, (int)n, W, ch);
+    for (size_t mi = 0; mi < in.size(); ++mi) {
+        const int n = (int)P.mats[mi].n;
+        add_tsqr(P, tb, Zs[mi], n, n, W, ch);
+    }
     push_tsqr_factor(P, tb, W, ch);
-    Factors f{};
-    f.U = P.alloc(m * W);
-    f.V = P.alloc(n * W);
-    f.sig = P.alloc(W);
-    f.rank = P.ialloc(1);
-    const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
-    CoreTask c = core_defaults(P);
-    c.mode = CORE_UPPER;
-    c.dim = W;
-    c.m_off = tb.tasks[0].r_out;
-    c.m_ld = W;
-    c.rank_in = in.rank;
-    c.u_off = X; c.u_ld = W;
-    c.v_off = J; c.v_ld = W;
-    c.sig_off = f.sig;
-    c.out_w = W;
-    c.rank_out = f.rank;
-    c.floor_rows = (int)n;
-    c.floor_cols = -1;
-    c.fixed_rank_slot = in.rank;
-    push_core(P, {c}, W, 1);
-    ApplyTask a{};
-    a.tsqr = 0;
-    a.x_off = X;
-    a.out_off = f.V;
-    a.out_ld = (int)n;
-    a.add_u_off = -1;
-    push_tsqr_apply(P, tb, {a}, W, ch, W);
-    ThinTask nn{};
-    nn.x_off = in.U; nn.x_ld = (int)m;
-    nn.c_off = J; nn.c_ld = W;
-    nn.y_off = f.U; nn.y_ld = (int)m;
-    nn.h = (int)m; nn.wx = W; nn.wy = W;
-    nn.accumulate = 0; nn.acc_off = -1;
-    push_thin(P, ST_NN, {nn});
-    return f;
+    std::vector<Factors> fs(in.size());
+    std::vector<CoreTask> cores;
+    std::vector<ApplyTask> at;
+    std::vector<ThinTask> nns;
+    for (size_t mi = 0; mi < in.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        const int64_t m = M.m, n = M.n;
+        Factors& f = fs[mi];
+        f.U = P.alloc(m * W);
+        f.V = P.alloc(n * W);
+        f.sig = P.alloc(W);
+        f.rank = P.ialloc(1);
+        const int64_t X = P.alloc((int64_t)W * W), J = P.alloc((int64_t)W * W);
+        CoreTask c = core_defaults(P, M.k);
+        c.mode = CORE_UPPER;
+        c.dim = W;
+        c.m_off = tb.tasks[mi].r_out;
+        c.m_ld = W;
+        c.rank_in = in[mi].rank;
+        c.u_off = X; c.u_ld = W;
+        c.v_off = J; c.v_ld = W;
+        c.sig_off = f.sig;
+        c.out_w = W;
+        c.rank_out = f.rank;
+        c.floor_rows = (int)n;
+        c.floor_cols = -1;
+        c.fixed_rank_slot = in[mi].rank;
+        cores.push_back(c);
+        ApplyTask a{};
+        a.tsqr = (int)mi;
+        a.x_off = X;
+        a.out_off = f.V;
+        a.out_ld = (int)n;
+        a.add_u_off = -1;
+        at.push_back(a);
+        ThinTask nn{};
+        nn.x_off = in[mi].U; nn.x_ld = (int)m;
+        nn.c_off = J; nn.c_ld = W;
+        nn.y_off = f.U; nn.y_ld = (int)m;
+        nn.h = (int)m; nn.wx = W; nn.wy = W;
+        nn.accumulate = 0; nn.acc_off = -1;
+        nns.push_back(nn);
+    }
+    push_core(P, cores, W, 1);
+    push_tsqr_apply(P, tb, at, W, ch, W);
+    push_thin(P, ST_NN, nns);
+    return fs;
 }
 
 hsvd_status build_plan(hsvd_plan_st& P) {
-    auto leaves = build_leaves(P);
-    auto col_roots = merge_forest(P, leaves);
-    auto slab_nodes = build_reprojection(P, col_roots);
-    auto row_root = merge_forest(P, {slab_nodes})[0];
-    Factors f = build_projection(P, row_root.panel, row_root.ld, row_root.rank);
+    auto slabs = build_leaves(P);
+    auto col_roots = merge_forest(P, slabs);
+    auto row_forests = build_reprojection(P, col_roots);
+    auto row_roots = merge_forest(P, row_forests);
+    std::vector<Factors> f = build_projection(P, row_roots);
     const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
     for (int it = 0; it < steps; ++it) {
         f = build_refine_step(P, f);
-        if (it + 1 < steps) f = build_projection(P, f.V, (int)P.n, f.rank);
+        if (it + 1 < steps) {
+            std::vector<Node> vs(f.size());
+            for (size_t mi = 0; mi < f.size(); ++mi) {
+                vs[mi].mat = (int)mi;
+                vs[mi].panel = f[mi].V;
+                vs[mi].ld = (int)P.mats[mi].n;
+                vs[mi].h = (int)P.mats[mi].n;
+                vs[mi].rank = f[mi].rank;
+                vs[mi].sig = f[mi].sig;
+            }
+            f = build_projection(P, vs);
+        }
     }
-    P.out.u_off = f.U;
-    P.out.v_off = f.V;
-    P.out.sig_off = f.sig;
-    P.out.u_ld = (int)P.m;
-    P.out.v_ld = (int)P.n;
-    P.out.m = (int)P.m;
-    P.out.n = (int)P.n;
-    P.out.k = P.k;
-    P.out.rank_slot = f.rank;
-    P.out.sign_off = P.ialloc(P.k);
-    P.rank_slot = f.rank;
+    P.outs.clear();
+    P.rank_slots.clear();
+    P.kmax = P.mmax = P.nmax = 0;
+    for (size_t mi = 0; mi < f.size(); ++mi) {
+        const MatDesc& M = P.mats[mi];
+        OutputArgs o{};
+        o.u_off = f[mi].U;
+        o.v_off = f[mi].V;
+        o.sig_off = f[mi].sig;
+        o.u_ld = (int)M.m;
+        o.v_ld = (int)M.n;
+        o.m = (int)M.m;
+        o.n = (int)M.n;
+        o.k = M.k;
+        o.rank_slot = f[mi].rank;
+        o.sign_off = P.ialloc(M.k);
+        P.outs.push_back(o);
+        P.rank_slots.push_back(f[mi].rank);
+        P.kmax = std::max(P.kmax, M.k);
+        P.mmax = std::max<int>(P.mmax, (int)M.m);
+        P.nmax = std::max<int>(P.nmax, (int)M.n);
+    }
+    P.outs_off = P.put(P.outs);
     return HSVD_OK;
 }
 
@@ -756,7 +852,7 @@ hsvd_status build_plan(hsvd_plan_st& P) {
 // each kernel's index range is recomputed here from the task fields, so a plan
 // whose footprint leaves its buffers is rejected before anything is launched.
 std::string validate_plan(const hsvd_plan_st& P) {
-    const int64_t WS = P.ws_elems, IW = P.iws_elems, AN = P.m * P.n;
+    const int64_t WS = P.ws_elems, IW = P.iws_elems;
     const unsigned char* b = P.blob.data();
     char msg[256];
     auto span = [&](const char* what, int64_t off, int64_t last, int64_t lim) -> bool {
@@ -783,8 +879,11 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
                 for (int i = 0; i < ntask; ++i) {
                     const GemmTask& t = T[i];
-                    if (!span("gemm A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * P.n + t.cols - 1, AN)) return msg;
-                    if (t.cols > P.n || t.a_off % P.n + t.cols > P.n) return "gemm A block crosses a row";
+                    if (t.mat < 0 || t.mat >= (int)P.mats.size()) return "gemm matrix index";
+                    const MatDesc& M = P.mats[t.mat];
+                    if (t.lda != M.n) return "gemm leading dimension";
+                    if (!span("gemm A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * M.n + t.cols - 1, M.m * M.n)) return msg;
+                    if (t.cols > M.n || t.a_off % M.n + t.cols > M.n) return "gemm A block crosses a row";
                     const int xr = s.op == 0 ? t.cols : t.rows, yr = s.op == 0 ? t.rows : t.cols;
                     if (!panel("gemm X", t.x_off, t.x_ld, xr, s.N)) return msg;
                     if (!panel("gemm Y", t.y_off, t.y_ld, yr, s.N)) return msg;
@@ -891,24 +990,32 @@ std::string validate_plan(const hsvd_plan_st& P) {
             }
         }
     }
-    if (!panel("out U", P.out.u_off, P.out.u_ld, P.m, P.W)) return msg;
-    if (!panel("out V", P.out.v_off, P.out.v_ld, P.n, P.W)) return msg;
-    if (!span("out signs", P.out.sign_off, P.out.sign_off + P.k - 1, IW)) return msg;
+    if (P.outs.size() != P.mats.size()) return "output count";
+    for (size_t mi = 0; mi < P.mats.size(); ++mi) {
+        const OutputArgs& o = P.outs[mi];
+        const MatDesc& M = P.mats[mi];
+        if (o.m != M.m || o.n != M.n || o.k != M.k || o.k > P.W) return "output shape";
+        if (!panel("out U", o.u_off, o.u_ld, M.m, P.W)) return msg;
+        if (!panel("out V", o.v_off, o.v_ld, M.n, P.W)) return msg;
+        if (!span("out sigma", o.sig_off, o.sig_off + P.W - 1, WS)) return msg;
+        if (!span("out signs", o.sign_off, o.sign_off + M.k - 1, IW)) return msg;
+        if (o.rank_slot < 0 || o.rank_slot >= IW) return "out rank slot";
+    }
     if (!span("omega", P.omega_off, P.omega_off + P.omega_count - 1, WS)) return msg;
     return "";
 }
 
-hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, const void* A, hipStream_t st) {
+hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
     unsigned char* b = (unsigned char*)P.dblob;
     hipError_t e = hipSuccess;
     const int fp32 = P.opt.precision != HSVD_FP64;
     switch (s.kind) {
         case ST_GEMM:
             if (s.bf16)
-                e = launch_gemm_bf16(s.op, (const float*)A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
+                e = launch_gemm_bf16(s.op, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
                                      (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             else
-                e = launch_gemm(s.op, fp32, A, P.n, P.ws, (const GemmTask*)(b + s.tasks_off),
+                e = launch_gemm(s.op, fp32, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
                                 (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             break;
         case ST_TSQR_F:
@@ -960,17 +1067,27 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     return HSVD_OK;
 }
 
-static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
-                             int32_t k, double tol, const hsvd_options* opt, size_t* check_only) {
+static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
+                             const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
+                             const hsvd_options* opt, size_t* check_only) {
     if (!out && !check_only) return fail(HSVD_ERR_INVALID, "out is NULL");
     if (out) *out = nullptr;
-    if (m < 1 || n < 1) return fail(HSVD_ERR_INVALID, "m and n must be >= 1");
-    if (p < 1 || p > m) return fail(HSVD_ERR_INVALID, "need 1 <= p <= m");
-    if (q < 1 || q > n) return fail(HSVD_ERR_INVALID, "need 1 <= q <= n");
-    if (k < 1 || k > std::min(m, n)) return fail(HSVD_ERR_INVALID, "need 1 <= k <= min(m, n)");
+    if (count < 1) return fail(HSVD_ERR_INVALID, "count must be >= 1");
+    if (!ms || !ns || !ps || !qs || !ks) return fail(HSVD_ERR_INVALID, "NULL shape array");
+    if (count > 65535) return fail(HSVD_ERR_UNSUPPORTED, "more than 65535 matrices in one plan");
+    for (int i = 0; i < count; ++i) {
+        const int64_t m = ms[i], n = ns[i];
+        const int32_t p = ps[i], q = qs[i], k = ks[i];
+        const std::string at = count > 1 ? " (matrix " + std::to_string(i) + ")" : "";
+        if (m < 1 || n < 1) return fail(HSVD_ERR_INVALID, "m and n must be >= 1" + at);
+        if (p < 1 || p > m) return fail(HSVD_ERR_INVALID, "need 1 <= p <= m" + at);
+        if (q < 1 || q > n) return fail(HSVD_ERR_INVALID, "need 1 <= q <= n" + at);
+        if (k < 1 || k > std::min(m, n)) return fail(HSVD_ERR_INVALID, "need 1 <= k <= min(m, n)" + at);
+        if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
+            return fail(HSVD_ERR_UNSUPPORTED, "m and n must be below 2^30" + at);
+        if (k > 64) return fail(HSVD_ERR_UNSUPPORTED, "k > 64 is not supported by this build" + at);
+    }
     if (!(tol >= 0.0 && tol < 1.0)) return fail(HSVD_ERR_INVALID, "need 0 <= tol < 1");
-    if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
-        return fail(HSVD_ERR_UNSUPPORTED, "m and n must be below 2^30");
     hsvd_options o;
     hsvd_default_options(&o);
     if (opt) o = *opt;
@@ -980,18 +1097,29 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, 
         return fail(HSVD_ERR_INVALID, "unknown rule");
     if (o.oversample < 0 || o.power_steps < 0 || o.refine_steps < 0 || o.max_sweeps < 1)
         return fail(HSVD_ERR_INVALID, "negative option");
-    if (k > 64) return fail(HSVD_ERR_UNSUPPORTED, "k > 64 is not supported by this build");
 
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
-    P->m = m; P->n = n; P->p = p; P->q = q; P->k = k; P->tol = tol; P->opt = o;
-    P->rs.resize(p + 1);
-    P->cs.resize(q + 1);
-    for (int i = 0; i <= p; ++i) P->rs[i] = (m / p) * i + std::min<int64_t>(i, m % p);
-    for (int j = 0; j <= q; ++j) P->cs[j] = (n / q) * j + std::min<int64_t>(j, n % q);
-    const int64_t bmin = std::min(m / p, n / q);
-    P->W = k;
-    P->L = (int)std::min<int64_t>(k + o.oversample, bmin);
+    P->tol = tol;
+    P->opt = o;
+    int kmax = 0, lwant = 1;
+    int64_t bmin = INT64_MAX;
+    for (int i = 0; i < count; ++i) {
+        MatDesc M;
+        M.m = ms[i]; M.n = ns[i]; M.p = ps[i]; M.q = qs[i]; M.k = ks[i];
+        M.rs.resize(M.p + 1);
+        M.cs.resize(M.q + 1);
+        for (int r = 0; r <= M.p; ++r) M.rs[r] = (M.m / M.p) * r + std::min<int64_t>(r, M.m % M.p);
+        for (int c = 0; c <= M.q; ++c) M.cs[c] = (M.n / M.q) * c + std::min<int64_t>(c, M.n % M.q);
+        bmin = std::min(bmin, std::min(M.m / M.p, M.n / M.q));
+        kmax = std::max(kmax, M.k);
+        lwant = std::max(lwant, M.k + o.oversample);
+        P->mats.push_back(std::move(M));
+    }
+    // one panel width and one sketch width for the whole batch (per-matrix rank caps
+    // stay in the tasks)
+    P->W = kmax;
+    P->L = (int)std::min<int64_t>(lwant, bmin);
     if (P->L < 1) P->L = 1;
     if (P->L > kTsqrMaxW) P->L = kTsqrMaxW;
     P->g = 2 + o.power_steps;
@@ -1012,11 +1140,13 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, 
     e = hipMalloc(&P->iws, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
     if (e == hipSuccess) e = hipMalloc(&P->flags, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMalloc(&P->dblob, std::max<size_t>(P->blob.size(), 256));
+    if (e == hipSuccess) e = hipMalloc((void**)&P->dptrs, sizeof(void*) * 4 * (size_t)count);
     if (e != hipSuccess) { hsvd_destroy(P); return fail(HSVD_ERR_ALLOC, "allocation failed"); }
     e = hipMemcpy(P->dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(P->iws, 0, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
     if (e == hipSuccess) e = hipMemset(P->flags, 0, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMemset(P->ws, 0, sizeof(double) * (size_t)P->ws_elems);
+    if (e == hipSuccess) e = hipMemset(P->dptrs, 0, sizeof(void*) * 4 * (size_t)count);
     for (auto& c : P->ws_init)
         if (e == hipSuccess)
             e = hipMemcpy(P->ws + c.first, c.second.data(), c.second.size() * sizeof(double),
@@ -1030,13 +1160,28 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, 
 
 hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
                          double tol, const hsvd_options* opt) {
-    return plan_impl(out, m, n, p, q, k, tol, opt, nullptr);
+    return plan_impl(out, 1, &m, &n, &p, &q, &k, tol, opt, nullptr);
+}
+
+hsvd_status hsvd_plan_batched(hsvd_plan_t* out, int32_t count, const int64_t* m, const int64_t* n,
+                              const int32_t* p, const int32_t* q, const int32_t* k, double tol,
+                              const hsvd_options* opt) {
+    return plan_impl(out, count, m, n, p, q, k, tol, opt, nullptr);
 }
 
 hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k, double tol,
                                   const hsvd_options* opt, size_t* workspace_bytes) {
     size_t bytes = 0;
-    hsvd_status st = plan_impl(nullptr, m, n, p, q, k, tol, opt, &bytes);
+    hsvd_status st = plan_impl(nullptr, 1, &m, &n, &p, &q, &k, tol, opt, &bytes);
+    if (workspace_bytes) *workspace_bytes = bytes;
+    return st;
+}
+
+hsvd_status hsvd_debug_plan_check_batched(int32_t count, const int64_t* m, const int64_t* n,
+                                          const int32_t* p, const int32_t* q, const int32_t* k,
+                                          double tol, const hsvd_options* opt, size_t* workspace_bytes) {
+    size_t bytes = 0;
+    hsvd_status st = plan_impl(nullptr, count, m, n, p, q, k, tol, opt, &bytes);
     if (workspace_bytes) *workspace_bytes = bytes;
     return st;
 }
@@ -1046,26 +1191,59 @@ hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t
     return hsvd_plan_ex(out, m, n, p, q, k, tol, nullptr);
 }
 
-hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
-                         hipStream_t stream) {
-    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
-    if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL data pointer");
-    hsvd_plan_st& P = *plan;
-    hipError_t e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * 4, stream);
+static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* const* U, void* const* S,
+                                void* const* Vt, hipStream_t stream) {
+    const size_t cnt = P.mats.size();
+    std::vector<void*> tab(4 * cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+        if (!A[i] || !U[i] || !S[i] || !Vt[i]) return fail(HSVD_ERR_INVALID, "NULL data pointer");
+        tab[4 * i] = const_cast<void*>(A[i]);
+        tab[4 * i + 1] = U[i];
+        tab[4 * i + 2] = S[i];
+        tab[4 * i + 3] = Vt[i];
+    }
+    hipError_t e = hipSuccess;
+    if (tab != P.host_ptrs) {
+        // the table is read by the launches of earlier executes on this stream:
+        // replace it only once they are done (then the copy is stream-ordered)
+        if (P.executed && (e = hipStreamSynchronize(P.last_stream)) != hipSuccess)
+            return hip_fail(e, "pointer table");
+        e = hipMemcpyAsync(P.dptrs, tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "pointer table");
+        P.host_ptrs = tab;
+    }
+    e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * 4, stream);
     if (e != hipSuccess) return hip_fail(e, "flags reset");
     const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
     if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
     for (size_t i = 0; i < P.stages.size(); ++i) {
-        hsvd_status st = run_stage(P, P.stages[i], A, stream);
+        hsvd_status st = run_stage(P, P.stages[i], stream);
         if (st != HSVD_OK) return st;
         if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
     }
-    e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws, P.out, U, S, Vt, stream);
+    e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws,
+                      (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)cnt, P.kmax, P.mmax,
+                      P.nmax, (void* const*)P.dptrs, stream);
     if (e != hipSuccess) return hip_fail(e, "output launch");
     if (prof && (e = hipEventRecord(P.events.back(), stream)) != hipSuccess) return hip_fail(e, "event");
     P.last_stream = stream;
     P.executed = true;
     return HSVD_OK;
+}
+
+hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
+                         hipStream_t stream) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_execute_batched");
+    return execute_impl(*plan, &A, &U, &S, &Vt, stream);
+}
+
+hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* const* U, void* const* S,
+                                 void* const* Vt, hipStream_t stream) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL pointer array");
+    return execute_impl(*plan, A, U, S, Vt, stream);
 }
 
 hsvd_status hsvd_set_profiling(hsvd_plan_t plan, int32_t enable) {
@@ -1130,7 +1308,8 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
     for (int i = 0; i < n && i < cap; ++i) {
         double f = 0.0, by = 0.0;
         if (i == n - 1) {                                   // output: U, Vt from the panels
-            by = (double)(P.m + P.n) * P.W * e8 + (double)(P.m + P.n) * P.k * eA + P.k * eA;
+            for (const MatDesc& M : P.mats)
+                by += (double)(M.m + M.n) * P.W * e8 + (double)(M.m + M.n) * M.k * eA + M.k * eA;
         } else {
             const Stage& s = P.stages[i];
             switch (s.kind) {
@@ -1228,18 +1407,28 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (plan->iws) hipFree(plan->iws);
     if (plan->flags) hipFree(plan->flags);
     if (plan->dblob) hipFree(plan->dblob);
+    if (plan->dptrs) hipFree(plan->dptrs);
     delete plan;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count) {
+    if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    if (count != (int32_t)plan->mats.size()) return fail(HSVD_ERR_INVALID, "count does not match the plan");
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    std::vector<int> all((size_t)plan->iws_elems);
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpy(all.data(), plan->iws, sizeof(int) * all.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_get_ranks");
+    for (int32_t i = 0; i < count; ++i) r_host[i] = all[(size_t)plan->rank_slots[i]];
     return HSVD_OK;
 }
 
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host) {
     if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
-    hipError_t e = hipSuccess;
-    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
-    if (e == hipSuccess)
-        e = hipMemcpy(r_host, plan->iws + plan->rank_slot, sizeof(int), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hsvd_get_rank");
-    return HSVD_OK;
+    if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_get_ranks");
+    return hsvd_get_ranks(plan, r_host, 1);
 }
 
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {

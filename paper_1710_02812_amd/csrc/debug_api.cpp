@@ -109,12 +109,15 @@ extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32,
     Scratch sc;
     double* ws = sc.get<double>(xr * N + yr * N);
     GemmTask* dt = sc.get<GemmTask>(1);
+    void** dptrs = sc.get<void*>(4);
     const int tile_rows = kind == 1 ? kBf16TileRows : 64;
     const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = (N + 63) / 64;
     TileRef* dtiles = sc.get<TileRef>((size_t)nrt * nct);
-    if (!ws || !dt || !dtiles) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    if (!ws || !dt || !dtiles || !dptrs) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
     GemmTask t{};
     t.a_off = 0;
+    t.lda = lda;
+    t.mat = 0;
     t.x_off = 0;
     t.y_off = xr * N;
     t.rows = (int32_t)rows;
@@ -124,13 +127,15 @@ extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32,
     t.tiles = nrt;
     std::vector<TileRef> tiles((size_t)nrt * nct);
     for (int i = 0; i < nrt * nct; ++i) tiles[i] = {0, i};
+    void* tab[4] = {const_cast<void*>(A), nullptr, nullptr, nullptr};
     hipError_t e = hipMemcpyAsync(ws, X, sizeof(double) * xr * N, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dptrs, tab, sizeof(tab), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dtiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = kind == 1 ? launch_gemm_bf16(op, (const float*)A, lda, ws, dt, dtiles, nrt * nct, N, stream)
-                      : launch_gemm(op, a_fp32, A, lda, ws, dt, dtiles, nrt * nct, N, stream);
+        e = kind == 1 ? launch_gemm_bf16(op, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream)
+                      : launch_gemm(op, a_fp32, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(Y, ws + xr * N, sizeof(double) * yr * N, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_gemm: ") + hipGetErrorString(e));

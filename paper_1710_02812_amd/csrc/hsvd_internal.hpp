@@ -16,12 +16,13 @@ constexpr double kEps = 2.220446049250313e-16;   // 2^-52
 // op 0: Y (rows x N) = A_blk (rows x cols) * X (cols x N)
 // op 1: Y (cols x N) = A_blk^T * X (rows x N)
 struct GemmTask {
-    int64_t a_off;        // offset of A_blk[0][0] in A (row-major, leading dim lda)
+    int64_t a_off;        // offset of A_blk[0][0] in its matrix (row-major, leading dim lda)
     int64_t x_off, y_off; // arena offsets (col-major panels)
+    int64_t lda;          // leading dimension (columns) of the task's matrix
     int32_t rows, cols;   // A_blk shape as stored
     int32_t x_ld, y_ld;
     int32_t tiles;        // output row tiles of this task
-    int32_t pad;
+    int32_t mat;          // matrix index: A = Aptrs[mat]
 };
 struct TileRef { int32_t task; int32_t tile; };
 
@@ -115,15 +116,18 @@ struct OutputArgs {
     int32_t m, n, k;
     int32_t rank_slot;
     int32_t sign_off;               // int arena: k signs
+    int32_t pad;
 };
+// Per-execute pointer table of a plan over `count` matrices: entries
+// [4 i .. 4 i + 3] are A, U, S, Vt of matrix i (device pointers).
 
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // bfloat16 matrix-core passes: 128 x 64 output tiles (TileRef.tile = row tile * ceil(N / 64) + col tile)
 constexpr int kBf16TileRows = 128;
-hipError_t launch_gemm_bf16(int op, const float* A, int64_t lda, double* ws, const GemmTask* tasks,
+hipError_t launch_gemm_bf16(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
                             const TileRef* tiles, int ntiles, int N, hipStream_t s);
-hipError_t launch_gemm(int op, int fp32, const void* A, int64_t lda, double* ws,
+hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s);
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
@@ -145,7 +149,9 @@ hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, 
                        int max_sweeps, unsigned* flags, int with_v, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
-hipError_t launch_output(int fp32, const double* ws, const int* iws, OutputArgs a,
-                         void* U, void* S, void* Vt, hipStream_t s);
+// Output of `count` matrices (args: device array; ptrs: the pointer table);
+// kmax, mmax, nmax bound k, m, n over the batch (grid sizes).
+hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,
+                         int kmax, int mmax, int nmax, void* const* ptrs, hipStream_t s);
 
 }  // namespace hsvd

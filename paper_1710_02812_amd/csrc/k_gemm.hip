@@ -1,7 +1,8 @@
 // Products of blocks of the input A with thin panels (the passes over A):
 //   op 0: Y = A_blk * X      (leaf sketch / power step / projection Y = A V)
 //   op 1: Y = A_blk^T * X    (leaf power step / slab re-projection W^T = A_i^T U_i)
-// A is row-major (float64 or float32); X and Y are float64 col-major panels.
+// A is row-major (float64 or float32), taken from the plan's pointer table by the
+// task's matrix index; X and Y are float64 col-major panels.
 // One 256-thread work-group computes a 64 x 64 output tile; the reduction
 // dimension streams through LDS in slabs of 32 with coalesced row reads of A.
 #include "hsvd_internal.hpp"
@@ -12,7 +13,7 @@ constexpr int GT = 64;   // output tile (rows and columns)
 constexpr int GK = 32;   // reduction slab
 
 template <typename TA>
-__global__ __launch_bounds__(256) void k_gemm_ax(const TA* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void k_gemm_ax(const void* const* __restrict__ ptrs,
                                                  double* __restrict__ ws,
                                                  const GemmTask* __restrict__ tasks,
                                                  const TileRef* __restrict__ tiles, int N) {
@@ -23,7 +24,8 @@ __global__ __launch_bounds__(256) void k_gemm_ax(const TA* __restrict__ A, int64
     const int nct = (N + GT - 1) / GT;
     const int r0 = (tr.tile / nct) * GT, c0 = (tr.tile % nct) * GT;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const TA* Ab = A + t.a_off;
+    const TA* Ab = (const TA*)ptrs[4 * t.mat] + t.a_off;
+    const int64_t lda = t.lda;
     const double* X = ws + t.x_off;
     double acc[4][4];
 #pragma unroll
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gemm_ax(const TA* __restrict__ A, int64
 }
 
 template <typename TA>
-__global__ __launch_bounds__(256) void k_gemm_atx(const TA* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void k_gemm_atx(const void* const* __restrict__ ptrs,
                                                   double* __restrict__ ws,
                                                   const GemmTask* __restrict__ tasks,
                                                   const TileRef* __restrict__ tiles, int N) {
@@ -82,7 +84,8 @@ __global__ __launch_bounds__(256) void k_gemm_atx(const TA* __restrict__ A, int6
     const int nct = (N + GT - 1) / GT;
     const int r0 = (tr.tile / nct) * GT, c0 = (tr.tile % nct) * GT;  // r0: A column
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const TA* Ab = A + t.a_off;
+    const TA* Ab = (const TA*)ptrs[4 * t.mat] + t.a_off;
+    const int64_t lda = t.lda;
     const double* X = ws + t.x_off;
     double acc[4][4];
 #pragma unroll
@@ -129,21 +132,21 @@ __global__ __launch_bounds__(256) void k_gemm_atx(const TA* __restrict__ A, int6
     }
 }
 
-hipError_t launch_gemm(int op, int fp32, const void* A, int64_t lda, double* ws,
+hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     dim3 g(ntiles), b(256);
     if (op == 0) {
         if (fp32)
-            hipLaunchKernelGGL(k_gemm_ax<float>, g, b, 0, s, (const float*)A, lda, ws, tasks, tiles, N);
+            hipLaunchKernelGGL(k_gemm_ax<float>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
         else
-            hipLaunchKernelGGL(k_gemm_ax<double>, g, b, 0, s, (const double*)A, lda, ws, tasks, tiles, N);
+            hipLaunchKernelGGL(k_gemm_ax<double>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
     } else {
         if (fp32)
-            hipLaunchKernelGGL(k_gemm_atx<float>, g, b, 0, s, (const float*)A, lda, ws, tasks, tiles, N);
+            hipLaunchKernelGGL(k_gemm_atx<float>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
         else
-            hipLaunchKernelGGL(k_gemm_atx<double>, g, b, 0, s, (const double*)A, lda, ws, tasks, tiles, N);
+            hipLaunchKernelGGL(k_gemm_atx<double>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
     }
     return hipGetLastError();
 }

@@ -26,7 +26,7 @@ constexpr int BM = 128, BN = 64, BK = 32;
 constexpr int PITCH = BK + 8;   // bf16 per LDS row: 80 bytes, keeps 16-byte alignment
 
 template <int OP>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void k_gemm_bf16(const void* const* __restrict__ ptrs,
                                                    double* __restrict__ ws,
                                                    const GemmTask* __restrict__ tasks,
                                                    const TileRef* __restrict__ tiles, int N) {
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
     const int out_rows = OP == 0 ? t.rows : t.cols;
     const int K = OP == 0 ? t.cols : t.rows;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float* Ab = A + t.a_off;
+    const float* Ab = (const float*)ptrs[4 * t.mat] + t.a_off;
+    const int64_t lda = t.lda;
     const double* X = ws + t.x_off;
 
     float ra[16];
@@ -118,14 +119,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
     }
 }
 
-hipError_t launch_gemm_bf16(int op, const float* A, int64_t lda, double* ws, const GemmTask* tasks,
+hipError_t launch_gemm_bf16(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
                             const TileRef* tiles, int ntiles, int N, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     dim3 g(ntiles), b(256);
     if (op == 0)
-        hipLaunchKernelGGL(k_gemm_bf16<0>, g, b, 0, s, A, lda, ws, tasks, tiles, N);
+        hipLaunchKernelGGL(k_gemm_bf16<0>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
     else
-        hipLaunchKernelGGL(k_gemm_bf16<1>, g, b, 0, s, A, lda, ws, tasks, tiles, N);
+        hipLaunchKernelGGL(k_gemm_bf16<1>, g, b, 0, s, ptrs, ws, tasks, tiles, N);
     return hipGetLastError();
 }
 

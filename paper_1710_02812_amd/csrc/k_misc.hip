@@ -47,11 +47,14 @@ __global__ void k_fill(double* p, int64_t count, double v) {
 }
 
 // Column signs: flip so the largest-magnitude entry of u_j is positive (ties: lowest row).
+// Matrix blockIdx.y of the batch, column blockIdx.x (blocks past its k return).
 __global__ __launch_bounds__(256) void k_colsign(const double* __restrict__ ws, int* __restrict__ iws,
-                                                 OutputArgs a) {
+                                                 const OutputArgs* __restrict__ args) {
     __shared__ double sv[256];
     __shared__ int si[256];
+    const OutputArgs a = args[blockIdx.y];
     const int j = blockIdx.x;
+    if (j >= a.k) return;
     const int r = iws[a.rank_slot];
     const double* u = ws + a.u_off + (int64_t)j * a.u_ld;
     double best = -1.0;
@@ -80,10 +83,14 @@ __global__ __launch_bounds__(256) void k_colsign(const double* __restrict__ ws, 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_write_u(const double* __restrict__ ws, const int* __restrict__ iws,
-                                                 OutputArgs a, T* __restrict__ U) {
+                                                 const OutputArgs* __restrict__ args,
+                                                 void* const* __restrict__ ptrs) {
     __shared__ double tile[64][129];
-    const int r = iws[a.rank_slot];
+    const OutputArgs a = args[blockIdx.y];
+    T* __restrict__ U = (T*)ptrs[4 * blockIdx.y + 1];
     const int row0 = blockIdx.x * 64;
+    if (row0 >= a.m) return;
+    const int r = iws[a.rank_slot];
     const int rows = min(64, a.m - row0);
     for (int j0 = 0; j0 < a.k; j0 += 128) {
         const int cols = min(128, a.k - j0);
@@ -105,9 +112,14 @@ __global__ __launch_bounds__(256) void k_write_u(const double* __restrict__ ws, 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ ws, const int* __restrict__ iws,
-                                                 OutputArgs a, T* __restrict__ S, T* __restrict__ Vt) {
-    const int r = iws[a.rank_slot];
+                                                 const OutputArgs* __restrict__ args,
+                                                 void* const* __restrict__ ptrs) {
+    const OutputArgs a = args[blockIdx.z];
+    T* __restrict__ S = (T*)ptrs[4 * blockIdx.z + 2];
+    T* __restrict__ Vt = (T*)ptrs[4 * blockIdx.z + 3];
     const int j = blockIdx.y;
+    if (j >= a.k) return;
+    const int r = iws[a.rank_slot];
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double sg = (j < r) ? (double)iws[a.sign_off + j] : 0.0;
     if (c < a.n) Vt[(int64_t)j * a.n + c] = (T)(sg * ws[a.v_off + (int64_t)j * a.v_ld + c]);
@@ -130,18 +142,19 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_output(int fp32, const double* ws, const int* iws, OutputArgs a, void* U,
-                         void* S, void* Vt, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsign, dim3(a.k), dim3(256), 0, s, ws, (int*)iws, a);
+hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,
+                         int kmax, int mmax, int nmax, void* const* ptrs, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colsign, dim3(kmax, count), dim3(256), 0, s, ws, iws, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 gu((a.m + 63) / 64), gv((a.n + 255) / 256, a.k);
+    const dim3 gu((mmax + 63) / 64, count), gv((nmax + 255) / 256, kmax, count);
     if (fp32) {
-        hipLaunchKernelGGL(k_write_u<float>, gu, dim3(256), 0, s, ws, iws, a, (float*)U);
-        hipLaunchKernelGGL(k_write_v<float>, gv, dim3(256), 0, s, ws, iws, a, (float*)S, (float*)Vt);
+        hipLaunchKernelGGL(k_write_u<float>, gu, dim3(256), 0, s, ws, iws, args, ptrs);
+        hipLaunchKernelGGL(k_write_v<float>, gv, dim3(256), 0, s, ws, iws, args, ptrs);
     } else {
-        hipLaunchKernelGGL(k_write_u<double>, gu, dim3(256), 0, s, ws, iws, a, (double*)U);
-        hipLaunchKernelGGL(k_write_v<double>, gv, dim3(256), 0, s, ws, iws, a, (double*)S, (double*)Vt);
+        hipLaunchKernelGGL(k_write_u<double>, gu, dim3(256), 0, s, ws, iws, args, ptrs);
+        hipLaunchKernelGGL(k_write_v<double>, gv, dim3(256), 0, s, ws, iws, args, ptrs);
     }
     return hipGetLastError();
 }

@@ -23,7 +23,9 @@ FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
             "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
             "hsvd_set_profiling", "hsvd_launch_times", "hsvd_launch_work",
-            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check", "hsvd_debug_gemm"]
+            "hsvd_plan_batched", "hsvd_execute_batched", "hsvd_get_ranks",
+            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check", "hsvd_debug_gemm",
+            "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16"]
 
@@ -66,6 +68,11 @@ def lib() -> ctypes.CDLL:
     L.hsvd_set_profiling.argtypes = [vp, i32]
     L.hsvd_launch_times.argtypes = [vp, P(i32), P(ctypes.c_float), i32, P(i32)]
     L.hsvd_launch_work.argtypes = [vp, P(f64), P(f64), i32, P(i32)]
+    L.hsvd_plan_batched.argtypes = [P(vp), i32, P(i64), P(i64), P(i32), P(i32), P(i32), f64, P(Options)]
+    L.hsvd_execute_batched.argtypes = [vp, P(vp), P(vp), P(vp), P(vp), vp]
+    L.hsvd_get_ranks.argtypes = [vp, P(i32), i32]
+    L.hsvd_debug_plan_check_batched.argtypes = [i32, P(i64), P(i64), P(i32), P(i32), P(i32), f64,
+                                                P(Options), P(ctypes.c_size_t)]
     L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
     L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
     L.hsvd_debug_gemm.argtypes = [i32, i32, i32, vp, i64, i64, i64, vp, i32, vp, vp]
@@ -93,6 +100,21 @@ def _stream_handle(stream=None) -> int:
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return int(s.cuda_stream)
+
+
+def _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed) -> Options:
+    o = default_options()
+    o.precision = precision
+    o.rule = rule
+    if oversample is not None:
+        o.oversample = oversample
+    if power_steps is not None:
+        o.power_steps = power_steps
+    o.refine_steps = refine_steps
+    if max_sweeps is not None:
+        o.max_sweeps = max_sweeps
+    o.seed = seed
+    return o
 
 
 class Plan:
@@ -179,6 +201,101 @@ class Plan:
             pass
 
 
+class BatchPlan:
+    """Owns an hsvd_plan_t over several matrices of different shapes
+    (hsvd_plan_batched): one execute runs every stage of all of them together."""
+
+    def __init__(self, shapes, tol: float = 0.0, *, precision: int = FP64, rule: int = RULE_GAMMA,
+                 oversample: int | None = None, power_steps: int | None = None,
+                 refine_steps: int = 0, max_sweeps: int | None = None, seed: int = 0):
+        """shapes: list of (m, n, p, q, k)."""
+        c = len(shapes)
+        i64a, i32a = ctypes.c_int64 * c, ctypes.c_int32 * c
+        ms = i64a(*[s[0] for s in shapes])
+        ns = i64a(*[s[1] for s in shapes])
+        ps = i32a(*[s[2] for s in shapes])
+        qs = i32a(*[s[3] for s in shapes])
+        ks = i32a(*[s[4] for s in shapes])
+        o = _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed)
+        h = ctypes.c_void_p()
+        _check(lib().hsvd_plan_batched(ctypes.byref(h), c, ms, ns, ps, qs, ks, float(tol), ctypes.byref(o)))
+        self._h = h
+        self.shapes = [tuple(s) for s in shapes]
+        self.precision = precision
+
+    def execute(self, As, Us, Ss, Vts, stream=None):
+        """Enqueues the method on every matrix (lists of torch device tensors)."""
+        import torch
+        dt = torch.float64 if self.precision == FP64 else torch.float32
+        c = len(self.shapes)
+        if not (len(As) == len(Us) == len(Ss) == len(Vts) == c):
+            raise ValueError("one A, U, S, Vt per matrix")
+        for i, (m, n, _, _, k) in enumerate(self.shapes):
+            for name, t, shape in (("A", As[i], (m, n)), ("U", Us[i], (m, k)), ("S", Ss[i], (k,)),
+                                   ("Vt", Vts[i], (k, n))):
+                if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
+                    raise ValueError(f"{name}[{i}]: need a contiguous {dt} device tensor of shape {shape}")
+        arr = ctypes.c_void_p * c
+        _check(lib().hsvd_execute_batched(self._h, arr(*[t.data_ptr() for t in As]),
+                                          arr(*[t.data_ptr() for t in Us]), arr(*[t.data_ptr() for t in Ss]),
+                                          arr(*[t.data_ptr() for t in Vts]), _stream_handle(stream)))
+
+    def ranks(self):
+        c = len(self.shapes)
+        r = (ctypes.c_int32 * c)()
+        _check(lib().hsvd_get_ranks(self._h, r, c))
+        return list(r)
+
+    def status(self) -> int:
+        f = ctypes.c_uint32()
+        _check(lib().hsvd_get_status(self._h, ctypes.byref(f)))
+        return f.value
+
+    def set_profiling(self, enable: bool = True):
+        _check(lib().hsvd_set_profiling(self._h, 1 if enable else 0))
+
+    def launch_times(self):
+        return Plan.launch_times(self)
+
+    def launch_work(self):
+        return Plan.launch_work(self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsvd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def svd_batched(As, ps, qs, ks, tol: float = 0.0, mixed: bool = False, **opts):
+    """Hierarchical MAT truncated SVDs of a list of torch device matrices in one
+    batched plan.  Returns a list of (U, S, Vt, r)."""
+    import torch
+    dt = As[0].dtype
+    if any(A.dtype != dt for A in As) or dt not in (torch.float64, torch.float32):
+        raise ValueError("all matrices must share a float64 or float32 dtype")
+    prec = FP64 if dt == torch.float64 else (MIXED_BF16 if mixed else FP32)
+    As = [A.contiguous() for A in As]
+    shapes = [(A.shape[0], A.shape[1], p, q, k) for A, p, q, k in zip(As, ps, qs, ks)]
+    plan = BatchPlan(shapes, tol, precision=prec, **opts)
+    Us = [torch.empty((m, k), dtype=dt, device=As[0].device) for (m, n, _, _, k) in shapes]
+    Ss = [torch.empty((k,), dtype=dt, device=As[0].device) for (m, n, _, _, k) in shapes]
+    Vts = [torch.empty((k, n), dtype=dt, device=As[0].device) for (m, n, _, _, k) in shapes]
+    plan.execute(As, Us, Ss, Vts)
+    rs = plan.ranks()
+    flags = plan.status()
+    plan.close()
+    flags &= 0xFFFF
+    if flags:
+        raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
+    return [(U, S, Vt, r) for U, S, Vt, r in zip(Us, Ss, Vts, rs)]
+
+
 def svd(A, p: int, q: int, k: int, tol: float = 0.0, mixed: bool = False, **opts):
     """Hierarchical MAT truncated SVD of a torch device matrix A (float64 or float32;
     mixed=True selects the bfloat16 matrix-core passes for a float32 A).
@@ -248,6 +365,21 @@ def debug_gemm(A, X, op: int = 0, bf16: bool = False):
     _check(lib().hsvd_debug_gemm(op, int(bf16), int(Ac.dtype == torch.float32), Ac.data_ptr(),
                                  rows, cols, cols, Xc.data_ptr(), N, Y.data_ptr(), _stream_handle()))
     return Y.t()
+
+
+def plan_check_batched(shapes, tol: float = 0.0, **opts) -> int:
+    """Builds and bounds-checks a batched plan on the host only; returns the arena bytes."""
+    c = len(shapes)
+    i64a, i32a = ctypes.c_int64 * c, ctypes.c_int32 * c
+    o = default_options()
+    for key, v in opts.items():
+        setattr(o, key, v)
+    b = ctypes.c_size_t()
+    _check(lib().hsvd_debug_plan_check_batched(
+        c, i64a(*[s[0] for s in shapes]), i64a(*[s[1] for s in shapes]), i32a(*[s[2] for s in shapes]),
+        i32a(*[s[3] for s in shapes]), i32a(*[s[4] for s in shapes]), float(tol), ctypes.byref(o),
+        ctypes.byref(b)))
+    return b.value
 
 
 def debug_tsqr(P):

@@ -108,8 +108,8 @@ def config2(seed: int = 2, m: int = 16384, block: int = 1024) -> Workload:
 
 
 def config3(seed: int = 3, count: int = 200, lo: int = 256, hi: int = 4096,
-            block: int = 512) -> list[Workload]:
-    """Uneven batch: m, n ~ U{lo..hi}, rank ~ U{5..80}, sigma_i = exp(-i/6), no noise.
+            block: int = 512, rank_hi: int = 80) -> list[Workload]:
+    """Uneven batch: m, n ~ U{lo..hi}, rank ~ U{5..rank_hi}, sigma_i = exp(-i/6), no noise.
 
     Grids p = ceil(m/block), q = ceil(n/block) (balanced split), k = rank.
     Draw order per matrix: m, n, rank, U, V.
@@ -119,7 +119,7 @@ def config3(seed: int = 3, count: int = 200, lo: int = 256, hi: int = 4096,
     for j in range(count):
         m = int(rng.integers(lo, hi + 1))
         n = int(rng.integers(lo, hi + 1))
-        rank = int(rng.integers(5, 81))
+        rank = int(rng.integers(5, rank_hi + 1))
         sigma = np.exp(-np.arange(rank) / 6.0)
         A, U, s, V = low_rank(rng, m, n, sigma)
         out.append(Workload(f"C3_{j}_{m}x{n}_r{rank}", A, -(-m // block), -(-n // block),

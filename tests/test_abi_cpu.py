@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1710_02812_amd import hsvd as H
@@ -86,9 +87,50 @@ def test_null_handles():
     (10, 7, 10, 7, 1, {}),
     (16384, 16384, 16, 16, 64, {"precision": 1}),
     (2049, 4097, 3, 9, 64, {"oversample": 40}),
+    (8192, 8192, 8, 8, 50, {"precision": 2}),
+    (1000, 900, 3, 4, 20, {"precision": 2, "refine_steps": 1}),
 ])
 def test_plan_footprint_is_in_bounds(shape):
     """Every task of every launch stays inside the plan's buffers (host-side check)."""
     m, n, p, q, k, opts = shape
     b = H.plan_check(m, n, p, q, k, 0.0, **opts)
     assert b > 0
+
+
+def _arr(t, v):
+    return (t * len(v))(*v)
+
+
+def test_batched_plan_rejects_bad_arguments():
+    lib = H.lib()
+    h = ctypes.c_void_p(1234)
+    assert lib.hsvd_plan_batched(ctypes.byref(h), 0, None, None, None, None, None, 0.0, None) == 1
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    ms, ns = _arr(i64, [100, 10]), _arr(i64, [100, 50])
+    ps, qs, ks = _arr(i32, [2, 20]), _arr(i32, [2, 2]), _arr(i32, [5, 5])
+    assert lib.hsvd_plan_batched(ctypes.byref(h), 2, ms, ns, ps, qs, ks, 0.0, None) == 1
+    assert "matrix 1" in lib.hsvd_last_error().decode()
+    ks = _arr(i32, [5, 65])
+    ms, ns = _arr(i64, [100, 100]), _arr(i64, [100, 100])
+    assert lib.hsvd_plan_batched(ctypes.byref(h), 2, ms, ns, _arr(i32, [2, 2]), qs, ks, 0.0, None) == 6
+    assert lib.hsvd_execute_batched(None, None, None, None, None, None) == 1
+    assert lib.hsvd_get_ranks(None, None, 1) == 1
+
+
+def test_batched_plan_footprint_uneven_batch():
+    """The 200-matrix uneven batch (shapes and grids of the uneven workload, ranks
+    capped at 64): every task of every launch stays inside its buffers."""
+    from paper_1710_02812_amd import synth
+    rng = np.random.default_rng(3)
+    shapes = []
+    for _ in range(200):
+        m, n = int(rng.integers(256, 4097)), int(rng.integers(256, 4097))
+        k = int(rng.integers(5, 65))
+        shapes.append((m, n, -(-m // 512), -(-n // 512), k))
+    b = H.plan_check_batched(shapes)
+    assert b > 0
+    b2 = H.plan_check_batched(shapes[:7], precision=2)
+    assert b2 > 0
+    single = H.plan_check(*shapes[0])
+    assert H.plan_check_batched(shapes[:1]) == single
+    assert synth is not None

@@ -184,3 +184,70 @@ def test_mixed_bf16_snapshot_2048():
     print("mixed 2048", c, flush=True)
     assert r == ro
     assert c["e_frob"] <= 1e-3 and c["e_sigma"] <= 1e-3
+
+
+def _uneven(count, hi, rank_hi, seed=3):
+    return synth.config3(seed=seed, count=count, lo=256, hi=hi, rank_hi=rank_hi)
+
+
+def test_batched_uneven_fp64():
+    """One batched plan over uneven matrices (exact low rank): every matrix matches
+    the oracle at the float64 gate and recovers its rank."""
+    ws = _uneven(12, 1300, 40)
+    print("batched fp64", [w.A.shape for w in ws], flush=True)
+    As = [torch.tensor(w.A, device=DEV) for w in ws]
+    outs = H.svd_batched(As, [w.p for w in ws], [w.q for w in ws], [w.k for w in ws])
+    torch.cuda.synchronize()
+    for w, (U, S, Vt, r) in zip(ws, outs):
+        Uo, so, Vto, ro = oracle.hsvd(w.A, w.p, w.q, w.k, 0.0)
+        assert r == ro == w.k
+        c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), r, Uo, so, Vto, ro)
+        assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10, (w.name, c)
+        assert np.max(np.abs(S.cpu().numpy()[:r] - w.meta["sigma"])) <= 1e-12
+
+
+def test_batched_uneven_fp32_and_mixed():
+    ws = _uneven(8, 1500, 48, seed=5)
+    As = [torch.tensor(w.A.astype(np.float32), device=DEV) for w in ws]
+    ref = [oracle.hsvd(w.A.astype(np.float32).astype(np.float64), w.p, w.q, w.k, 0.0) for w in ws]
+    for mixed, gate in ((False, 1e-5), (True, 1e-3)):
+        print("batched f32 mixed" if mixed else "batched f32", flush=True)
+        outs = H.svd_batched(As, [w.p for w in ws], [w.q for w in ws], [w.k for w in ws], mixed=mixed)
+        torch.cuda.synchronize()
+        for w, (U, S, Vt, r), (Uo, so, Vto, ro) in zip(ws, outs, ref):
+            assert r == ro
+            c = metrics.compare(U.double().cpu().numpy(), S.double().cpu().numpy(),
+                                Vt.double().cpu().numpy(), r, Uo, so, Vto, ro)
+            assert c["e_frob"] <= gate and c["e_sigma"] <= gate, (w.name, mixed, c)
+
+
+def test_batch_of_one_equals_single_plan():
+    """A batched plan over one matrix is the single-matrix plan, bit for bit."""
+    w = synth.config0(0)
+    A = torch.tensor(w.A, device=DEV)
+    U1, S1, Vt1, r1 = H.svd(A, w.p, w.q, w.k)
+    ((U2, S2, Vt2, r2),) = H.svd_batched([A], [w.p], [w.q], [w.k])
+    torch.cuda.synchronize()
+    assert r1 == r2
+    for a, b in ((U1, U2), (S1, S2), (Vt1, Vt2)):
+        assert torch.equal(a, b)
+
+
+def test_batched_plan_reuse_with_new_pointers():
+    """Re-executing a batched plan on other buffers (pointer table re-upload)."""
+    ws = _uneven(3, 700, 20, seed=8)
+    shapes = [(w.A.shape[0], w.A.shape[1], w.p, w.q, w.k) for w in ws]
+    plan = H.BatchPlan(shapes)
+    res = []
+    for scale in (1.0, 2.0):
+        As = [torch.tensor(scale * w.A, device=DEV) for w in ws]
+        Us = [torch.empty((m, k), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+        Ss = [torch.empty((k,), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+        Vts = [torch.empty((k, n), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+        plan.execute(As, Us, Ss, Vts)
+        torch.cuda.synchronize()
+        res.append([s.cpu().numpy() for s in Ss])
+        assert plan.ranks() == [w.k for w in ws]
+    for s1, s2 in zip(res[0], res[1]):
+        assert np.allclose(2.0 * s1, s2, rtol=1e-12, atol=0)
+    plan.close()
