@@ -128,11 +128,12 @@ def config3(seed: int = 3, count: int = 200, lo: int = 256, hi: int = 4096,
 
 
 def config4(seed: int = 4, p: int = 32, q: int = 8, block: int = 1024,
-            base_rank: int = 128) -> Workload:
+            base_rank: int = 128, max_class: int = 5, k: int = 256) -> Workload:
     """Per-block local ranks from a smooth seeded field over shared orthonormal bases.
 
     phi1, phi2 ~ U(0, 2 pi); f(I,J) = 1/2 + 1/2 sin(2 pi I/p + phi1) cos(2 pi J/q + phi2);
-    class c = min(5, floor(6 f)); r_IJ = 4 * 2^c.  Shared bases Ubar (m x 128),
+    class c = min(max_class, floor((max_class + 1) f)); r_IJ = 4 * 2^c (max_class = 5
+    gives ranks 4..128; 3 gives 4..32, whose leaf ranks fit a rank cap of 64).  Shared bases Ubar (m x 128),
     Vbar (n x 128); block (I,J) = Ubar_I diag(exp(-4 i / r_IJ)) Vbar_J^T.  Frobenius
     rule with tol = 1e-3.  Draw order: phi1, phi2, Ubar, Vbar.
     """
@@ -144,7 +145,7 @@ def config4(seed: int = 4, p: int = 32, q: int = 8, block: int = 1024,
     I = np.arange(p)[:, None]
     J = np.arange(q)[None, :]
     f = 0.5 + 0.5 * np.sin(2 * np.pi * I / p + phi1) * np.cos(2 * np.pi * J / q + phi2)
-    cls = np.minimum(5, np.floor(6 * f)).astype(int)
+    cls = np.minimum(max_class, np.floor((max_class + 1) * f)).astype(int)
     ranks = 4 * (2 ** cls)
     A = np.empty((m, n))
     i = np.arange(base_rank, dtype=np.float64)
@@ -153,5 +154,5 @@ def config4(seed: int = 4, p: int = 32, q: int = 8, block: int = 1024,
             d = np.exp(-4.0 * i / ranks[bi, bj])
             A[bi * block:(bi + 1) * block, bj * block:(bj + 1) * block] = \
                 (Ub[bi * block:(bi + 1) * block] * d) @ Vb[bj * block:(bj + 1) * block].T
-    return Workload(f"C4_{m}x{n}_field_grid{p}x{q}", A, p, q, 256, 1e-3, rule="frob",
+    return Workload(f"C4_{m}x{n}_field_grid{p}x{q}", A, p, q, k, 1e-3, rule="frob",
                     dtype="f32", meta={"block_ranks": ranks})

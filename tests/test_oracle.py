@@ -383,3 +383,71 @@ def test_planted_mistakes_are_caught(mutant):
     """Each plausible slip in a merge fails the merge pin or the pipeline pin."""
     assert _pipeline_pin(oracle.merge)
     assert not (_merge_pin(mutant) and _pipeline_pin(mutant))
+
+
+# ---------------------------------------------------------------- learned-rank oracle
+from oracle import mlp_oracle as mlp  # noqa: E402
+
+
+def test_mlp_gradient_matches_finite_differences():
+    """Analytic backward pass against central differences of the loss (float64)."""
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(3).astype(np.float64) + 0.01 * rng.standard_normal(mlp.N_PARAMS)
+    X = rng.standard_normal((24, mlp.N_IN))
+    t = rng.uniform(1.0, 6.0, 24)
+    L, g = mlp.grad(theta, X, t)
+    assert abs(L - mlp.loss(theta, X, t)) <= 1e-14 * max(1.0, L)
+    h = 1e-6
+    idx = rng.choice(mlp.N_PARAMS, 300, replace=False)
+    idx = np.concatenate([idx, [mlp.N_PARAMS - 1, 0, 1024, 1088, 5248]])   # each layer's first entry
+    for i in idx:
+        e = np.zeros(mlp.N_PARAMS)
+        e[i] = h
+        fd = (mlp.loss(theta + e, X, t) - mlp.loss(theta - e, X, t)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.max(np.abs(g))), (i, fd, g[i])
+
+
+def test_mlp_planted_backward_errors_are_caught():
+    """A dropped ReLU mask or a transposed weight in the backward pass breaks the pin."""
+    rng = np.random.default_rng(1)
+    theta = mlp.init_params(4).astype(np.float64)
+    X = rng.standard_normal((16, mlp.N_IN))
+    t = rng.uniform(1.0, 6.0, 16)
+    _, g = mlp.grad(theta, X, t)
+    p = mlp.unpack(theta)
+    y, (X_, z1, h1, z2, h2) = mlp.forward(theta, X)
+    dy = (y - t) / X.shape[0]
+    dz2 = np.outer(dy, p["w3"])                                   # mask dropped
+    bad = dz2.T @ h1
+    good = mlp.unpack(g)["W2"]
+    assert np.max(np.abs(bad - good)) > 1e-3 * np.max(np.abs(good))
+    dz2 = np.outer(dy, p["w3"]) * (z2 > 0)
+    dz1_bad = (dz2 @ p["W2"].T) * (z1 > 0)                        # transposed weight
+    assert np.max(np.abs(dz1_bad.T @ X - mlp.unpack(g)["W1"])) > 1e-6
+
+
+def test_mlp_features_closed_form():
+    """Features of a sketch with known singular values."""
+    s = 10.0 ** -np.arange(16.0)
+    f = mlp.features(s, energy=np.sum(s * s) / 16.0)
+    assert np.allclose(f[:15], -np.arange(1.0, 16.0))
+    assert abs(f[15]) <= 1e-15
+    s2 = np.zeros(16)
+    s2[:3] = [2.0, 1.0, 0.5]
+    f2 = mlp.features(s2, energy=2.0)
+    assert np.allclose(f2[:2], np.log10([0.5, 0.25])) and np.all(f2[2:15] == -16.0)
+    assert np.allclose(f2[15], np.log10(2.0 * 16.0 / 5.25))
+    assert np.all(mlp.features(np.zeros(16), 0.0) == 0.0)
+
+
+def test_mlp_training_fits_a_rank_map():
+    """Adam training on a learnable map (log2 rank from the feature that marks the
+    spectrum's drop) drives the loss down by orders of magnitude."""
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((256, mlp.N_IN))
+    t = 3.0 + 1.5 * np.tanh(X[:, 0]) + 0.5 * X[:, 3]
+    theta0 = mlp.init_params(5)
+    L0 = mlp.loss(mlp.fp16(theta0), X, t)
+    theta, losses = mlp.train(theta0, X, t, steps=600, lr=3e-3)
+    L1 = mlp.loss(mlp.fp16(theta), X, t)
+    assert L1 < 0.02 * L0 and L1 < 0.05, (L0, L1)
