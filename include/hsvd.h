@@ -83,6 +83,9 @@ typedef struct {
 /* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
 #define HSVD_FLAG_NONFINITE 0x1u   /* a core matrix held NaN or Inf                        */
 #define HSVD_FLAG_NOCONV    0x2u   /* a Jacobi core hit max_sweeps before convergence      */
+#define HSVD_FLAG_RANK_FALLBACK 0x4u /* a leaf of a width plan left more than tol^2 of its
+                                       block's energy outside its sketch (see
+                                       hsvd_get_leaf_info)                               */
 
 /* Fills *opt with the defaults listed above. */
 hsvd_status hsvd_default_options(hsvd_options* opt);
@@ -164,7 +167,9 @@ typedef enum {
     HSVD_LAUNCH_CORE = 8,          /* Jacobi SVD cores                                   */
     HSVD_LAUNCH_OUTPUT = 9,        /* signs and the U, S, Vt writes                      */
     HSVD_LAUNCH_GEMM_AX_BF16 = 10, /* Y = A_blk X on the bfloat16 matrix cores           */
-    HSVD_LAUNCH_GEMM_ATX_BF16 = 11 /* Y = A_blk^T X on the bfloat16 matrix cores         */
+    HSVD_LAUNCH_GEMM_ATX_BF16 = 11,/* Y = A_blk^T X on the bfloat16 matrix cores         */
+    HSVD_LAUNCH_ENERGY = 12,       /* squared Frobenius norms of the blocks              */
+    HSVD_LAUNCH_FEATURES = 13      /* block features of a feature plan                   */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.
@@ -195,6 +200,68 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
  * bytes_host == NULL only the count is returned. */
 hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes_host, int32_t cap,
                              int32_t* count_host);
+
+/* ---------------------------------------------------------------- learned rank
+ * A small network predicts, from a cheap sketch of each block, the rank the
+ * tolerance rule would keep there, so that a leaf computes only the sketch columns
+ * it needs (widths of a width plan).  The tolerance rule stays the judge: each
+ * leaf of a width plan checks the energy its sketch missed and reports it.
+ *
+ * Features of block b (16 floats): with s_1 >= ... >= s_16 the singular values of
+ * Y = A_b Omega (Omega a 16-column Gaussian test matrix) and E = ||A_b||_F^2:
+ *   f_j = max(log10(s_{j+1} / s_1), -16) for j = 1..15,  f_16 = log10(16 E / sum s^2);
+ * all zero for a zero block.
+ * Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2) (64 units each),
+ * y = w3 . h2 + b3 = predicted log2(rank); weights used rounded to float16,
+ * float32 arithmetic.  Parameters (HSVD_RANK_MODEL_PARAMS floats): W1 (64 x 16
+ * row-major) | b1 (64) | W2 (64 x 64 row-major) | b2 (64) | w3 (64) | b3 (1).     */
+#define HSVD_RANK_FEATURES 16
+#define HSVD_RANK_MODEL_PARAMS 5313
+typedef struct hsvd_rank_model_st* hsvd_rank_model_t;
+
+/* Feature plan for an m x n matrix on a p x q grid (precision FP64 or FP32 for A;
+ * seed fixes Omega).  Execute with hsvd_features_execute only.                   */
+hsvd_status hsvd_features_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
+                               int32_t precision, uint64_t seed);
+/* features: device float array of p * q * 16, block (i, j) at row i * q + j. */
+hsvd_status hsvd_features_execute(hsvd_plan_t plan, const void* A, float* features,
+                                  hipStream_t stream);
+
+/* A plan like hsvd_plan_ex whose leaves use per-block sketch widths:
+ * leaf_width[i * q + j] (host array, each in 1..80) columns for block (i, j)
+ * instead of k + oversample.  Its leaves also check the energy their sketch
+ * missed (status bit HSVD_FLAG_RANK_FALLBACK, per block via hsvd_get_leaf_info):
+ * a block whose missed share exceeds tol^2 (tol with the FROB rule) needs a wider
+ * sketch.                                                                        */
+hsvd_status hsvd_plan_widths(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                             double tol, const hsvd_options* opt, const int32_t* leaf_width);
+
+/* Per-block leaf ranks and fallback flags (1 = the sketch missed too much energy;
+ * always 0 outside width plans) of the last execute of a single-matrix plan;
+ * count = p * q; either output may be NULL.  Synchronises.                      */
+hsvd_status hsvd_get_leaf_info(hsvd_plan_t plan, int32_t* ranks, int32_t* fallback, int32_t count);
+
+/* Network with He-initialised weights (seeded) and a fresh Adam state. */
+hsvd_status hsvd_rank_model_create(hsvd_rank_model_t* out, uint64_t seed);
+hsvd_status hsvd_rank_model_destroy(hsvd_rank_model_t model);
+/* Host copies of the float32 master parameters (count = HSVD_RANK_MODEL_PARAMS);
+ * set also resets the Adam state and the minibatch counter.                     */
+hsvd_status hsvd_rank_model_set_params(hsvd_rank_model_t model, const float* params_host, int32_t count);
+hsvd_status hsvd_rank_model_get_params(hsvd_rank_model_t model, float* params_host, int32_t count);
+/* `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8, rate lr) on the mean of
+ * (y - t)^2 / 2 over minibatches of 64: step s of the model's life takes samples
+ * (s * 64 + i) mod count.  X: count x 16 features, T: count log2-rank targets
+ * (device).  losses (device, may be NULL) receives each step's minibatch loss.
+ * Runs on the GPU in one work-group; asynchronous.                              */
+hsvd_status hsvd_rank_model_train(hsvd_rank_model_t model, const float* X, const float* T, int32_t count,
+                                  int32_t steps, float lr, float* losses, hipStream_t stream);
+/* Gradient (device, HSVD_RANK_MODEL_PARAMS) and loss (device, 1) of minibatch
+ * batch_index at the current weights, without updating anything.                 */
+hsvd_status hsvd_rank_model_grad(hsvd_rank_model_t model, const float* X, const float* T, int32_t count,
+                                 int32_t batch_index, float* grad, float* loss, hipStream_t stream);
+/* out[i] = predicted log2(rank) of feature row i (device arrays). */
+hsvd_status hsvd_rank_model_predict(hsvd_rank_model_t model, const float* X, int32_t count, float* out,
+                                    hipStream_t stream);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hsvd_last_error(void);

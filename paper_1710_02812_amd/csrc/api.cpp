@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <random>
 #include <vector>
 
 using namespace hsvd;
@@ -52,7 +53,8 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
     return fail(HSVD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE };
+enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY,
+                 ST_FEAT };
 
 struct Stage {
     StageKind kind;
@@ -61,6 +63,7 @@ struct Stage {
     int w = 0, ch = 0, c = 0, N = 0;
     int maxdim = 0, with_v = 0;
     int bf16 = 0;        // gemm on the bfloat16 matrix cores
+    int64_t off = 0, off2 = 0;   // energy: output offset; features: sigma and energy offsets
     size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
 };
 
@@ -87,6 +90,10 @@ struct MatDesc {
 
 struct hsvd_plan_st {
     std::vector<MatDesc> mats;     // one for hsvd_plan, count for hsvd_plan_batched
+    int kind = 0;                  // 0: SVD plan, 1: block-feature plan
+    std::vector<int> leaf_width;   // per-block sketch widths (width plans), else empty
+    std::vector<int> leaf_rank_slots, leaf_flag_slots;   // per block of matrix 0
+    int64_t energy_off = -1;       // block energies (width and feature plans)
     double tol = 0.0;
     hsvd_options opt{};
     int W = 0, L = 0, g = 0;       // panel width (max k), leaf sketch width, products per leaf
@@ -264,6 +271,8 @@ CoreTask core_defaults(const hsvd_plan_st& P, int k) {
     c.tol = P.tol;
     c.floor_cols = -1;
     c.fixed_rank_slot = -1;
+    c.energy_off = -1;
+    c.flag_slot = -1;
     return c;
 }
 
@@ -405,19 +414,140 @@ std::vector<Node> merge_forest(hsvd_plan_st& P, std::vector<std::vector<Node>> t
     return roots;
 }
 
-// Leaves: randomised range finder with power steps, per block of every matrix.
+// Leaf pipeline for one class of leaves sharing the sketch width w: randomised range
+// finder with power steps (Y = A_b Omega_w, then alternately QR and products with
+// A_b^T / A_b), QR of the last product, Jacobi core -> (U_b, s_b, r_b).
+struct Leaf { int mat, i, j, w; int64_t rowsz, colsz, aoff; };
+
+void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::vector<int>& ids, int w,
+                   int64_t omega_ld, std::vector<Node>& nodes) {
+    const int W = P.W, g = P.g;
+    const bool bf16 = P.opt.precision == HSVD_MIXED_BF16;
+    const int64_t I_w = identity_panel(P, w);
+    struct Pan { int64_t Y, Z, Qy, Qz; };
+    std::vector<Pan> pan(ids.size());
+    for (size_t u = 0; u < ids.size(); ++u) {
+        const Leaf& l = leaves[ids[u]];
+        pan[u] = {P.alloc(l.rowsz * w), P.alloc(l.colsz * w), P.alloc(l.rowsz * w), P.alloc(l.colsz * w)};
+    }
+    {
+        std::vector<GemmTask> gt;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const Leaf& l = leaves[ids[u]];
+            GemmTask t = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
+            t.x_off = P.omega_off; t.x_ld = (int)omega_ld;
+            t.y_off = pan[u].Y; t.y_ld = (int)l.rowsz;
+            gt.push_back(t);
+        }
+        push_gemm(P, 0, gt, w, bf16);
+    }
+    const int ch = tsqr_chunk(w, std::max(w, W));
+    TsqrBuild tb_last;
+    for (int t = 1; t <= g; ++t) {
+        const bool prev_is_y = ((t - 1) % 2 == 0);
+        TsqrBuild tb;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const Leaf& l = leaves[ids[u]];
+            if (prev_is_y) add_tsqr(P, tb, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch);
+            else add_tsqr(P, tb, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch);
+        }
+        push_tsqr_factor(P, tb, w, ch);
+        if (t == g) { tb_last = tb; break; }
+        std::vector<ApplyTask> at;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const Leaf& l = leaves[ids[u]];
+            ApplyTask a{};
+            a.tsqr = (int)u;
+            a.x_off = I_w;
+            a.out_off = prev_is_y ? pan[u].Qy : pan[u].Qz;
+            a.out_ld = prev_is_y ? (int)l.rowsz : (int)l.colsz;
+            a.add_u_off = -1;
+            at.push_back(a);
+        }
+        push_tsqr_apply(P, tb, at, w, ch, w);
+        std::vector<GemmTask> gt;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const Leaf& l = leaves[ids[u]];
+            GemmTask x = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
+            if (prev_is_y) {            // Z = A_b^T Qy
+                x.x_off = pan[u].Qy; x.x_ld = (int)l.rowsz;
+                x.y_off = pan[u].Z; x.y_ld = (int)l.colsz;
+            } else {                    // Y = A_b Qz
+                x.x_off = pan[u].Qz; x.x_ld = (int)l.colsz;
+                x.y_off = pan[u].Y; x.y_ld = (int)l.rowsz;
+            }
+            gt.push_back(x);
+        }
+        push_gemm(P, prev_is_y ? 1 : 0, gt, w, bf16);
+    }
+    const bool last_is_y = ((g - 1) % 2 == 0);
+    std::vector<CoreTask> cores;
+    std::vector<int64_t> ur(ids.size());
+    for (size_t u = 0; u < ids.size(); ++u) {
+        const int b = ids[u];
+        const Leaf& l = leaves[b];
+        Node& nd = nodes[b];
+        nd.mat = l.mat;
+        nd.h = (int)l.rowsz;
+        nd.ld = (int)l.rowsz;
+        nd.panel = P.alloc(l.rowsz * W);
+        nd.sig = P.alloc(W);
+        nd.rank = P.ialloc(1);
+        ur[u] = P.alloc((int64_t)w * W);
+        CoreTask c = core_defaults(P, P.mats[l.mat].k);
+        c.mode = last_is_y ? CORE_UPPER : CORE_UPPER_T;
+        c.dim = w;
+        c.m_off = tb_last.tasks[u].r_out;
+        c.m_ld = w;
+        c.u_off = ur[u];
+        c.u_ld = w;
+        c.sig_off = nd.sig;
+        c.out_w = W;
+        c.rank_out = nd.rank;
+        c.floor_rows = (int)l.rowsz;
+        c.floor_cols = (int)l.colsz;
+        if (P.energy_off >= 0 && l.mat == 0) {
+            c.energy_off = P.energy_off + b;
+            c.flag_slot = P.ialloc(1);
+            P.leaf_flag_slots[b] = c.flag_slot;
+        }
+        if (l.mat == 0) P.leaf_rank_slots[b] = nd.rank;
+        cores.push_back(c);
+    }
+    push_core(P, cores, w, 0);
+    if (last_is_y) {
+        std::vector<ApplyTask> at;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            ApplyTask a{};
+            a.tsqr = (int)u;
+            a.x_off = ur[u];
+            a.out_off = nodes[ids[u]].panel;
+            a.out_ld = nodes[ids[u]].ld;
+            a.add_u_off = -1;
+            at.push_back(a);
+        }
+        push_tsqr_apply(P, tb_last, at, w, ch, W);
+    } else {
+        std::vector<ThinTask> nn;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const Leaf& l = leaves[ids[u]];
+            ThinTask t{};
+            t.x_off = pan[u].Qy; t.x_ld = (int)l.rowsz;
+            t.c_off = ur[u]; t.c_ld = w;
+            t.y_off = nodes[ids[u]].panel; t.y_ld = nodes[ids[u]].ld;
+            t.h = (int)l.rowsz; t.wx = w; t.wy = W;
+            t.accumulate = 0; t.acc_off = -1;
+            nn.push_back(t);
+        }
+        push_thin(P, ST_NN, nn);
+    }
+}
+
+// Leaves of every block of every matrix.  Sketch width P.L for all, or the
+// per-block widths of a width plan (leaves grouped by width: one pipeline per
+// class).  Width plans first compute every block's energy for the leaf check.
 // Returns one forest per (matrix, row slab), matrices in order, slabs top to bottom.
 std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
-    const int L = P.L, W = P.W, g = P.g;
-    int64_t bcmax = 1;
-    for (const auto& M : P.mats)
-        for (int j = 0; j < M.q; ++j) bcmax = std::max(bcmax, M.bcol(j));
-    P.omega_count = bcmax * L;
-    P.omega_off = P.alloc(P.omega_count);
-    const int64_t I_L = identity_panel(P, L);
-    const bool bf16 = P.opt.precision == HSVD_MIXED_BF16;
-
-    struct Leaf { int mat, i, j; int64_t rowsz, colsz, aoff; int64_t Y, Z, Qy, Qz; };
     std::vector<Leaf> leaves;
     for (int mi = 0; mi < (int)P.mats.size(); ++mi) {
         const MatDesc& M = P.mats[mi];
@@ -429,117 +559,41 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
                 l.rowsz = M.brow(i);
                 l.colsz = M.bcol(j);
                 l.aoff = M.rs[i] * M.n + M.cs[j];
-                l.Y = P.alloc(l.rowsz * L);
-                l.Z = P.alloc(l.colsz * L);
-                l.Qy = P.alloc(l.rowsz * L);
-                l.Qz = P.alloc(l.colsz * L);
+                l.w = P.leaf_width.empty() ? P.L : P.leaf_width[(size_t)i * M.q + j];
                 leaves.push_back(l);
             }
     }
-    // product t = 0: Y = A_b Omega
-    {
-        std::vector<GemmTask> gt;
-        for (auto& l : leaves) {
-            GemmTask t = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
-            t.x_off = P.omega_off; t.x_ld = (int)bcmax;
-            t.y_off = l.Y; t.y_ld = (int)l.rowsz;
-            gt.push_back(t);
-        }
-        push_gemm(P, 0, gt, L, bf16);
+    int64_t bcmax = 1;
+    int wmax = 1;
+    for (const Leaf& l : leaves) {
+        bcmax = std::max(bcmax, l.colsz);
+        wmax = std::max(wmax, l.w);
     }
-    const int ch = tsqr_chunk(L, std::max(L, W));
-    TsqrBuild tb_last;
-    for (int t = 1; t <= g; ++t) {
-        // QR of the previous product (Y if t-1 even, Z if odd)
-        const bool prev_is_y = ((t - 1) % 2 == 0);
-        TsqrBuild tb;
-        for (auto& l : leaves) {
-            if (prev_is_y) add_tsqr(P, tb, l.Y, (int)l.rowsz, (int)l.rowsz, L, ch);
-            else add_tsqr(P, tb, l.Z, (int)l.colsz, (int)l.colsz, L, ch);
-        }
-        push_tsqr_factor(P, tb, L, ch);
-        if (t == g) { tb_last = tb; break; }
-        std::vector<ApplyTask> at;
-        for (size_t b = 0; b < leaves.size(); ++b) {
-            ApplyTask a{};
-            a.tsqr = (int)b;
-            a.x_off = I_L;
-            a.out_off = prev_is_y ? leaves[b].Qy : leaves[b].Qz;
-            a.out_ld = prev_is_y ? (int)leaves[b].rowsz : (int)leaves[b].colsz;
-            a.add_u_off = -1;
-            at.push_back(a);
-        }
-        push_tsqr_apply(P, tb, at, L, ch, L);
-        // next product
-        std::vector<GemmTask> gt;
-        for (auto& l : leaves) {
-            GemmTask x = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
-            if (prev_is_y) {            // Z = A_b^T Qy
-                x.x_off = l.Qy; x.x_ld = (int)l.rowsz;
-                x.y_off = l.Z; x.y_ld = (int)l.colsz;
-            } else {                    // Y = A_b Qz
-                x.x_off = l.Qz; x.x_ld = (int)l.colsz;
-                x.y_off = l.Y; x.y_ld = (int)l.rowsz;
-            }
-            gt.push_back(x);
-        }
-        push_gemm(P, prev_is_y ? 1 : 0, gt, L, bf16);
+    P.omega_count = bcmax * wmax;
+    P.omega_off = P.alloc(P.omega_count);
+    P.leaf_rank_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
+    P.leaf_flag_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
+    if (!P.leaf_width.empty()) {
+        P.energy_off = P.alloc((int64_t)leaves.size());
+        std::vector<GemmTask> et;
+        for (const Leaf& l : leaves) et.push_back(gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz));
+        Stage s{};
+        s.kind = ST_ENERGY;
+        s.n = (int)et.size();
+        s.off = P.energy_off;
+        s.tasks_off = P.put(et);
+        P.stages.push_back(s);
     }
-    // core of the last product
-    const bool last_is_y = ((g - 1) % 2 == 0);
-    std::vector<CoreTask> cores;
-    std::vector<Node> nodes;
-    std::vector<int64_t> ur(leaves.size());
-    for (size_t b = 0; b < leaves.size(); ++b) {
-        const Leaf& l = leaves[b];
-        Node nd{};
-        nd.mat = l.mat;
-        nd.h = (int)l.rowsz;
-        nd.ld = (int)l.rowsz;
-        nd.panel = P.alloc(l.rowsz * W);
-        nd.sig = P.alloc(W);
-        nd.rank = P.ialloc(1);
-        nodes.push_back(nd);
-        ur[b] = P.alloc((int64_t)L * W);
-        CoreTask c = core_defaults(P, P.mats[l.mat].k);
-        c.mode = last_is_y ? CORE_UPPER : CORE_UPPER_T;
-        c.dim = L;
-        c.m_off = tb_last.tasks[b].r_out;
-        c.m_ld = L;
-        c.u_off = ur[b];
-        c.u_ld = L;
-        c.sig_off = nd.sig;
-        c.out_w = W;
-        c.rank_out = nd.rank;
-        c.floor_rows = (int)l.rowsz;
-        c.floor_cols = (int)l.colsz;
-        cores.push_back(c);
-    }
-    push_core(P, cores, L, 0);
-    if (last_is_y) {
-        std::vector<ApplyTask> at;
-        for (size_t b = 0; b < leaves.size(); ++b) {
-            ApplyTask a{};
-            a.tsqr = (int)b;
-            a.x_off = ur[b];
-            a.out_off = nodes[b].panel;
-            a.out_ld = nodes[b].ld;
-            a.add_u_off = -1;
-            at.push_back(a);
-        }
-        push_tsqr_apply(P, tb_last, at, L, ch, W);
-    } else {
-        std::vector<ThinTask> nn;
-        for (size_t b = 0; b < leaves.size(); ++b) {
-            ThinTask t{};
-            t.x_off = leaves[b].Qy; t.x_ld = (int)leaves[b].rowsz;
-            t.c_off = ur[b]; t.c_ld = L;
-            t.y_off = nodes[b].panel; t.y_ld = nodes[b].ld;
-            t.h = (int)leaves[b].rowsz; t.wx = L; t.wy = W;
-            t.accumulate = 0; t.acc_off = -1;
-            nn.push_back(t);
-        }
-        push_thin(P, ST_NN, nn);
+    std::vector<int> widths;
+    for (const Leaf& l : leaves)
+        if (std::find(widths.begin(), widths.end(), l.w) == widths.end()) widths.push_back(l.w);
+    std::sort(widths.begin(), widths.end());
+    std::vector<Node> nodes(leaves.size());
+    for (int w : widths) {
+        std::vector<int> ids;
+        for (size_t b = 0; b < leaves.size(); ++b)
+            if (leaves[b].w == w) ids.push_back((int)b);
+        leaf_pipeline(P, leaves, ids, w, bcmax, nodes);
     }
     std::vector<std::vector<Node>> slabs;
     int prev_mat = -1, prev_i = -1;
@@ -848,6 +902,70 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     return HSVD_OK;
 }
 
+// Block features (learned rank): energy of every block, a 16-column Gaussian sketch
+// Y = A_b Omega_16, its TSQR and the singular values of R, then the 16 features.
+void build_features(hsvd_plan_st& P) {
+    const MatDesc& M = P.mats[0];
+    const int nb = M.p * M.q;
+    int64_t bcmax = 1;
+    for (int j = 0; j < M.q; ++j) bcmax = std::max(bcmax, M.bcol(j));
+    P.omega_count = bcmax * 16;
+    P.omega_off = P.alloc(P.omega_count);
+    P.energy_off = P.alloc(nb);
+    const int64_t sigs = P.alloc(16LL * nb);
+    std::vector<GemmTask> et, gt;
+    std::vector<int64_t> Ys(nb);
+    for (int i = 0; i < M.p; ++i)
+        for (int j = 0; j < M.q; ++j) {
+            const int b = i * M.q + j;
+            GemmTask t = gemm_task(P, 0, M.rs[i] * M.n + M.cs[j], M.brow(i), M.bcol(j));
+            et.push_back(t);
+            Ys[b] = P.alloc(M.brow(i) * 16);
+            t.x_off = P.omega_off; t.x_ld = (int)bcmax;
+            t.y_off = Ys[b]; t.y_ld = (int)M.brow(i);
+            gt.push_back(t);
+        }
+    Stage se{};
+    se.kind = ST_ENERGY;
+    se.n = nb;
+    se.off = P.energy_off;
+    se.tasks_off = P.put(et);
+    P.stages.push_back(se);
+    push_gemm(P, 0, gt, 16);
+    const int ch = tsqr_chunk(16, 16);
+    TsqrBuild tb;
+    for (int b = 0; b < nb; ++b) {
+        const int h = (int)M.brow(b / M.q);
+        add_tsqr(P, tb, Ys[b], h, h, 16, ch);
+    }
+    push_tsqr_factor(P, tb, 16, ch);
+    std::vector<CoreTask> cores;
+    for (int b = 0; b < nb; ++b) {
+        CoreTask c = core_defaults(P, 16);
+        c.rule = 0;
+        c.tol = 0.0;
+        c.mode = CORE_UPPER;
+        c.dim = 16;
+        c.m_off = tb.tasks[b].r_out;
+        c.m_ld = 16;
+        c.sig_off = sigs + 16LL * b;
+        c.out_w = 16;
+        c.rank_out = P.ialloc(1);
+        c.floor_rows = (int)M.brow(b / M.q);
+        c.floor_cols = 16;
+        cores.push_back(c);
+    }
+    push_core(P, cores, 16, 0);
+    Stage sf{};
+    sf.kind = ST_FEAT;
+    sf.n = nb;
+    sf.off = sigs;
+    sf.off2 = P.energy_off;
+    P.stages.push_back(sf);
+    P.kmax = P.mmax = P.nmax = 0;
+    P.outs_off = P.put(P.outs);
+}
+
 // Host-side bounds check of every task in every stage against the arenas and A:
 // each kernel's index range is recomputed here from the task fields, so a plan
 // whose footprint leaves its buffers is rejected before anything is launched.
@@ -960,6 +1078,23 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 }
                 break;
             }
+            case ST_ENERGY: {
+                const GemmTask* T = (const GemmTask*)(b + s.tasks_off);
+                if (!span("energy out", s.off, s.off + s.n - 1, WS)) return msg;
+                for (int i = 0; i < s.n; ++i) {
+                    const GemmTask& t = T[i];
+                    if (t.mat < 0 || t.mat >= (int)P.mats.size()) return "energy matrix index";
+                    const MatDesc& M = P.mats[t.mat];
+                    if (t.lda != M.n || t.cols > M.n || t.a_off % M.n + t.cols > M.n) return "energy block";
+                    if (!span("energy A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * M.n + t.cols - 1, M.m * M.n)) return msg;
+                }
+                break;
+            }
+            case ST_FEAT: {
+                if (!span("feature sigma", s.off, s.off + 16LL * s.n - 1, WS)) return msg;
+                if (!span("feature energy", s.off2, s.off2 + s.n - 1, WS)) return msg;
+                break;
+            }
             case ST_CORE: {
                 const CoreTask* T = (const CoreTask*)(b + s.tasks_off);
                 if (s.maxdim > 128 || (s.with_v && s.maxdim > 64)) return "core size";
@@ -984,14 +1119,16 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         if (t.v_off >= 0 && (!s.with_v || !panel("core V", t.v_off, t.v_ld, t.dim, t.out_w))) return msg;
                     }
                     if (!span("core sigma", t.sig_off, t.sig_off + t.out_w - 1, WS)) return msg;
+                    if (t.energy_off >= 0 && (t.energy_off >= WS || t.flag_slot < 0 || t.flag_slot >= IW))
+                        return "core energy check";
                     if (t.rank_out >= IW || t.fixed_rank_slot >= IW) return "core rank slot";
                 }
                 break;
             }
         }
     }
-    if (P.outs.size() != P.mats.size()) return "output count";
-    for (size_t mi = 0; mi < P.mats.size(); ++mi) {
+    if (P.outs.size() != (P.kind == 0 ? P.mats.size() : 0)) return "output count";
+    for (size_t mi = 0; mi < P.outs.size(); ++mi) {
         const OutputArgs& o = P.outs[mi];
         const MatDesc& M = P.mats[mi];
         if (o.m != M.m || o.n != M.n || o.k != M.k || o.k > P.W) return "output shape";
@@ -1046,6 +1183,13 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             e = launch_core(P.ws, P.iws, (const CoreTask*)(b + s.tasks_off), s.n, s.maxdim,
                             P.opt.max_sweeps, P.flags, s.with_v, st);
             break;
+        case ST_ENERGY:
+            e = launch_block_energy((const void* const*)P.dptrs, fp32, (const GemmTask*)(b + s.tasks_off),
+                                    s.n, P.ws, s.off, st);
+            break;
+        case ST_FEAT:
+            e = launch_block_features(P.ws, s.off, s.off2, s.n, (float*)P.host_ptrs[1], st);
+            break;
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return HSVD_OK;
@@ -1069,7 +1213,8 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
 
 static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
                              const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
-                             const hsvd_options* opt, size_t* check_only) {
+                             const hsvd_options* opt, size_t* check_only,
+                             const int32_t* leaf_width = nullptr, int kind = 0) {
     if (!out && !check_only) return fail(HSVD_ERR_INVALID, "out is NULL");
     if (out) *out = nullptr;
     if (count < 1) return fail(HSVD_ERR_INVALID, "count must be >= 1");
@@ -1123,8 +1268,24 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     if (P->L < 1) P->L = 1;
     if (P->L > kTsqrMaxW) P->L = kTsqrMaxW;
     P->g = 2 + o.power_steps;
+    P->kind = kind;
+    if (leaf_width) {
+        const MatDesc& M = P->mats[0];
+        int wmax = 1;
+        for (int b = 0; b < M.p * M.q; ++b) {
+            const int w = leaf_width[b];
+            if (w < 1 || w > kTsqrMaxW) {
+                delete P;
+                return fail(HSVD_ERR_INVALID, "leaf widths must be in 1.." + std::to_string(kTsqrMaxW));
+            }
+            wmax = std::max(wmax, w);
+        }
+        P->leaf_width.assign(leaf_width, leaf_width + M.p * M.q);
+        P->L = wmax;
+    }
 
-    build_plan(*P);
+    if (kind == 1) build_features(*P);
+    else build_plan(*P);
     const std::string verr = validate_plan(*P);
     if (!verr.empty()) { delete P; return fail(HSVD_ERR_INVALID, "plan validation: " + verr); }
     if (check_only) {
@@ -1177,6 +1338,23 @@ hsvd_status hsvd_debug_plan_check(int64_t m, int64_t n, int32_t p, int32_t q, in
     return st;
 }
 
+hsvd_status hsvd_plan_widths(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                             double tol, const hsvd_options* opt, const int32_t* leaf_width) {
+    if (!leaf_width) return fail(HSVD_ERR_INVALID, "leaf_width is NULL");
+    return plan_impl(out, 1, &m, &n, &p, &q, &k, tol, opt, nullptr, leaf_width, 0);
+}
+
+hsvd_status hsvd_features_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
+                               int32_t precision, uint64_t seed) {
+    hsvd_options o;
+    hsvd_default_options(&o);
+    o.precision = precision;
+    o.seed = seed;
+    if (precision == HSVD_MIXED_BF16) return fail(HSVD_ERR_INVALID, "feature plans take FP64 or FP32");
+    const int32_t k = 1;
+    return plan_impl(out, 1, &m, &n, &p, &q, &k, 0.0, &o, nullptr, nullptr, 1);
+}
+
 hsvd_status hsvd_debug_plan_check_batched(int32_t count, const int64_t* m, const int64_t* n,
                                           const int32_t* p, const int32_t* q, const int32_t* k,
                                           double tol, const hsvd_options* opt, size_t* workspace_bytes) {
@@ -1223,7 +1401,7 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
         if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
     }
     e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws,
-                      (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)cnt, P.kmax, P.mmax,
+                      (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)P.outs.size(), P.kmax, P.mmax,
                       P.nmax, (void* const*)P.dptrs, stream);
     if (e != hipSuccess) return hip_fail(e, "output launch");
     if (prof && (e = hipEventRecord(P.events.back(), stream)) != hipSuccess) return hip_fail(e, "event");
@@ -1235,13 +1413,22 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
 hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void* Vt,
                          hipStream_t stream) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan: use hsvd_features_execute");
     if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_execute_batched");
     return execute_impl(*plan, &A, &U, &S, &Vt, stream);
+}
+
+hsvd_status hsvd_features_execute(hsvd_plan_t plan, const void* A, float* features, hipStream_t stream) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->kind != 1) return fail(HSVD_ERR_INVALID, "not a feature plan");
+    void* f = features;
+    return execute_impl(*plan, &A, &f, &f, &f, stream);
 }
 
 hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* const* U, void* const* S,
                                  void* const* Vt, hipStream_t stream) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan: use hsvd_features_execute");
     if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL pointer array");
     return execute_impl(*plan, A, U, S, Vt, stream);
 }
@@ -1285,6 +1472,8 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_NN: kind = HSVD_LAUNCH_THIN_NN; break;
                 case ST_SUM: kind = HSVD_LAUNCH_SUM; break;
                 case ST_CORE: kind = HSVD_LAUNCH_CORE; break;
+                case ST_ENERGY: kind = HSVD_LAUNCH_ENERGY; break;
+                case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
             }
         }
         float ms = 0.f;
@@ -1391,6 +1580,18 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     }
                     break;
                 }
+                case ST_ENERGY: {
+                    const GemmTask* T = (const GemmTask*)(b + s.tasks_off);
+                    for (int t = 0; t < s.n; ++t) {
+                        f += 2.0 * T[t].rows * (double)T[t].cols;
+                        by += (double)T[t].rows * T[t].cols * eA + e8;
+                    }
+                    break;
+                }
+                case ST_FEAT:
+                    f = 40.0 * s.n;
+                    by = s.n * (17.0 * e8 + 16.0 * 4.0);
+                    break;
             }
         }
         flops_host[i] = f;
@@ -1425,6 +1626,23 @@ hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count) {
     return HSVD_OK;
 }
 
+hsvd_status hsvd_get_leaf_info(hsvd_plan_t plan, int32_t* ranks, int32_t* fallback, int32_t count) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->kind != 0 || count != (int32_t)plan->leaf_rank_slots.size())
+        return fail(HSVD_ERR_INVALID, "count must be p * q of the plan's (first) matrix");
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    std::vector<int> all((size_t)plan->iws_elems);
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpy(all.data(), plan->iws, sizeof(int) * all.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_get_leaf_info");
+    for (int32_t b = 0; b < count; ++b) {
+        if (ranks) ranks[b] = all[(size_t)plan->leaf_rank_slots[b]];
+        if (fallback) fallback[b] = plan->leaf_flag_slots[b] >= 0 ? all[(size_t)plan->leaf_flag_slots[b]] : 0;
+    }
+    return HSVD_OK;
+}
+
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host) {
     if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
     if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_get_ranks");
@@ -1450,5 +1668,101 @@ hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host) {
 }
 
 const char* hsvd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned rank model
+struct hsvd_rank_model_st {
+    float* params = nullptr;   // float32 masters (the network uses them rounded to float16)
+    float* m1 = nullptr;       // Adam moments
+    float* m2 = nullptr;
+    int steps_done = 0;        // Adam step counter
+    int batches_done = 0;      // minibatch counter (which samples the next step takes)
+};
+
+extern "C" {
+
+hsvd_status hsvd_rank_model_create(hsvd_rank_model_t* out, uint64_t seed) {
+    if (!out) return fail(HSVD_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    hsvd_rank_model_st* M = new (std::nothrow) hsvd_rank_model_st();
+    if (!M) return fail(HSVD_ERR_ALLOC, "host allocation failed");
+    hipError_t e = hipMalloc(&M->params, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMalloc(&M->m1, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMalloc(&M->m2, sizeof(float) * kMlpParams);
+    if (e != hipSuccess) { hsvd_rank_model_destroy(M); return fail(HSVD_ERR_ALLOC, "allocation failed"); }
+    // He initialisation: W1 ~ N(0, 2/16), W2 ~ N(0, 2/64), w3 ~ N(0, 1/64), biases 0,
+    // output bias 3 (log2 of a middling rank)
+    std::vector<float> h(kMlpParams, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int i = 0; i < 64 * 16; ++i) h[i] = (float)(nd(rng) * std::sqrt(2.0 / 16.0));
+    for (int i = 0; i < 64 * 64; ++i) h[1088 + i] = (float)(nd(rng) * std::sqrt(2.0 / 64.0));
+    for (int i = 0; i < 64; ++i) h[5248 + i] = (float)(nd(rng) * std::sqrt(1.0 / 64.0));
+    h[kMlpParams - 1] = 3.0f;
+    e = hipMemcpy(M->params, h.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(M->m1, 0, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMemset(M->m2, 0, sizeof(float) * kMlpParams);
+    if (e != hipSuccess) { hsvd_rank_model_destroy(M); return hip_fail(e, "rank model init"); }
+    *out = M;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_destroy(hsvd_rank_model_t model) {
+    if (!model) return HSVD_OK;
+    hipDeviceSynchronize();
+    if (model->params) hipFree(model->params);
+    if (model->m1) hipFree(model->m1);
+    if (model->m2) hipFree(model->m2);
+    delete model;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_set_params(hsvd_rank_model_t model, const float* params_host, int32_t count) {
+    if (!model || !params_host || count != kMlpParams) return fail(HSVD_ERR_INVALID, "bad argument");
+    hipError_t e = hipMemcpy(model->params, params_host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(model->m1, 0, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMemset(model->m2, 0, sizeof(float) * kMlpParams);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_rank_model_set_params");
+    model->steps_done = model->batches_done = 0;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_get_params(hsvd_rank_model_t model, float* params_host, int32_t count) {
+    if (!model || !params_host || count != kMlpParams) return fail(HSVD_ERR_INVALID, "bad argument");
+    hipError_t e = hipMemcpy(params_host, model->params, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_rank_model_get_params");
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_train(hsvd_rank_model_t model, const float* X, const float* T, int32_t count,
+                                  int32_t steps, float lr, float* losses, hipStream_t stream) {
+    if (!model || !X || !T || count < 1 || steps < 1 || !(lr > 0.0f))
+        return fail(HSVD_ERR_INVALID, "bad argument");
+    hipError_t e = launch_mlp_train(model->params, model->m1, model->m2, X, T, count, steps,
+                                    model->batches_done, model->steps_done, lr, nullptr, losses, stream);
+    if (e != hipSuccess) return hip_fail(e, "rank model training launch");
+    model->steps_done += steps;
+    model->batches_done += steps;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_grad(hsvd_rank_model_t model, const float* X, const float* T, int32_t count,
+                                 int32_t batch_index, float* grad, float* loss, hipStream_t stream) {
+    if (!model || !X || !T || !grad || !loss || count < 1 || batch_index < 0)
+        return fail(HSVD_ERR_INVALID, "bad argument");
+    hipError_t e = launch_mlp_train(model->params, model->m1, model->m2, X, T, count, 0, batch_index, 0,
+                                    0.0f, grad, loss, stream);
+    if (e != hipSuccess) return hip_fail(e, "rank model gradient launch");
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_rank_model_predict(hsvd_rank_model_t model, const float* X, int32_t count, float* out,
+                                    hipStream_t stream) {
+    if (!model || !X || !out || count < 0) return fail(HSVD_ERR_INVALID, "bad argument");
+    hipError_t e = launch_mlp_predict(model->params, X, count, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "rank model prediction launch");
+    return HSVD_OK;
+}
 
 }  // extern "C"

@@ -80,6 +80,8 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
         c.floor_cols = -1;
         c.fixed_rank_slot = -1;
         c.precond = precondition;
+        c.energy_off = -1;
+        c.flag_slot = -1;
         // keep every nonzero column: rank = count above a zero floor of 0
         tasks[b] = c;
     }

@@ -107,6 +107,11 @@ struct CoreTask {
     int32_t floor_cols;            // < 0: use the active core size
     int32_t fixed_rank_slot;       // >= 0: rank = min(zero-floor count, ranks[slot])
     int32_t precond;               // 1: LQ-precondition (left vectors only; needs v_off < 0)
+    // a-posteriori check of a leaf whose block energy E is known (energy_off >= 0):
+    // iws[flag_slot] = 1 (and status bit 4) when E - sum(sigma^2) > tol^2 E
+    int64_t energy_off;
+    int32_t flag_slot;
+    int32_t pad2;
 };
 
 // ---------------------------------------------------------------- output
@@ -120,6 +125,10 @@ struct OutputArgs {
 };
 // Per-execute pointer table of a plan over `count` matrices: entries
 // [4 i .. 4 i + 3] are A, U, S, Vt of matrix i (device pointers).
+
+// ---------------------------------------------------------------- learned block rank
+constexpr int kMlpParams = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1;   // 5313
+constexpr int kMlpBatch = 64;
 
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return the hipError_t of the launch.
@@ -147,6 +156,14 @@ hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks
                            int nchunks, int chh, hipStream_t s);
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                        int max_sweeps, unsigned* flags, int with_v, hipStream_t s);
+hipError_t launch_mlp_train(float* master, float* m1, float* m2, const float* X, const float* T,
+                            int count, int steps, int s0, int t0, float lr, float* grad_out,
+                            float* loss_out, hipStream_t s);
+hipError_t launch_mlp_predict(const float* master, const float* X, int count, float* out, hipStream_t s);
+hipError_t launch_block_energy(const void* const* ptrs, int fp32, const GemmTask* tasks, int ntasks,
+                               double* ws, int64_t out_off, hipStream_t s);
+hipError_t launch_block_features(const double* ws, int64_t sig_off, int64_t energy_off, int nblocks,
+                                 float* out, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // Output of `count` matrices (args: device array; ptrs: the pointer table);

@@ -10,9 +10,13 @@
 // round-robin tournament, so each round rotates nc/2 disjoint pairs in parallel,
 // one lane group per pair (dot product by shuffle reduction, rotation in LDS).
 // A pair is rotated when |g_a . g_b| > tol * |g_a| |g_b|; sweeps stop after a sweep
-// without rotations.  Pairs whose two columns both had a squared norm below
-// 1e-12 of the largest at the start of the sweep are skipped: such columns can
-// only matter through their rotations against larger columns, which still run.
+// without rotations.  When the core has more columns than the rank cap, pairs
+// whose two columns both had a norm below 1e-3 of the cap-th largest at the start
+// of the first sweep are skipped in every sweep: the cap drops such columns
+// whatever their mutual rotations, and their rotations against larger columns
+// still run.  The set is fixed once: re-deciding it every sweep lets columns of a
+// spectrum that decays through the threshold drift in and out of it, which stalls
+// convergence.
 // Once converged, the skip is accepted only if the kept columns are all large,
 // exceed the Frobenius norm of the small ones, and the rank rule provably
 // excludes the small part; otherwise full sweeps continue from that state.  At
@@ -140,6 +144,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             const int j = e / ROWS, i = e - j * ROWS;
             V[(int64_t)j * ldg + i] = (i == j) ? 1.0 : 0.0;
         }
+    for (int j = tid; j < 128; j += nth) sflag[j] = 0;
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
 
@@ -177,9 +182,12 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     constexpr int TMAX = ROWS / gsz;                // rows per lane, unconditional (zero padded)
     const double tol = (double)(nr > 1 ? nr : 1) * kEps;
     const double tol2 = tol * tol;
-    constexpr double kSkip2 = 1e-12;               // (1e-6)^2 relative squared norm
+    // skip threshold: squared norm <= (1e-3)^2 of the cap-th largest squared norm
+    constexpr double kSkip2 = 1e-6;
+    const int cap_all = (t.fixed_rank_slot >= 0) ? min(t.kcap, iws[t.fixed_rank_slot]) : t.kcap;
     bool converged = (nc <= 1) || s_bad;
     bool skip = true;
+    bool classify = true;       // the skipped set is fixed at the first sweep of a phase
     int sweep = 0;
   resume:
     for (; sweep < max_sweeps && !converged; ++sweep) {
@@ -194,12 +202,25 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         }
         if (tid == 0) s_rot = 0;
         __syncthreads();
-        if (wave == 0) {
-            double mx = 0.0;
-            for (int j = lane64; j < nc; j += 64) mx = fmax(mx, d[j]);
-            mx = wave_max(mx);
-            for (int j = lane64; j < nc; j += 64) sflag[j] = skip && (d[j] <= kSkip2 * mx);
+        if (classify && wave == 0) {
+            // only columns far below the cap-th largest can be left unrotated among
+            // themselves: the rank cap drops them whatever their mutual rotations
+            double dk = -1.0;
+            if (skip && nc > cap_all && cap_all >= 1) {
+                for (int j = lane64; j < nc; j += 64) {
+                    const double dj = d[j];
+                    int pos = 0;
+                    for (int i = 0; i < nc; ++i) {
+                        const double di = d[i];
+                        pos += (di > dj) || (di == dj && i < j);
+                    }
+                    if (pos == cap_all - 1) dk = dj;
+                }
+                dk = wave_max(dk);
+            }
+            for (int j = lane64; j < nc; j += 64) sflag[j] = (dk >= 0.0) && (d[j] <= kSkip2 * dk);
         }
+        classify = false;
         __syncthreads();
         int a = (grp == 0) ? 0 : grp;
         int b = (grp == 0) ? N - 1 : N - 1 - grp;
@@ -310,20 +331,32 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         sig[pos] = sj;
     }
     __syncthreads();
+    if (tid == 0 && t.energy_off >= 0) {
+        // captured energy of the sketch against the block's: the leaf keeps too few
+        // columns when the part it cannot see exceeds the tolerance
+        double cap = 0.0;
+        for (int j = 0; j < nc; ++j) cap = fma(sig[j], sig[j], cap);
+        const double E = ws[t.energy_off];
+        const int miss = (E - cap > t.tol * t.tol * E * (1.0 + 1e-9)) ? 1 : 0;
+        iws[t.flag_slot] = miss;
+        if (miss && flags) atomicOr(flags, 4u);
+    }
     if (tid == 0) {
         const int r = s_bad ? 0 : select_rank(sig, nc, t, iws, nr);
         s_rank = r;
         // accept the skipped small-small rotations only if they cannot change the result
         int safe = 1;
-        if (skip && r > 0 && nc > 1) {
-            const double dmax = sig[0] * sig[0];
+        if (skip && r > 0) {
+            // the skipped set (fixed at the first sweep) is S; at convergence every
+            // other pair is orthogonal, so the kept columns are exact if none of them
+            // is in S and S cannot hold a singular value as large as the r-th
             double small2 = 0.0;
             int any_small = 0;
             for (int j = 0; j < nc; ++j)
-                if (d[j] * d[j] <= kSkip2 * dmax) { small2 += d[j] * d[j]; any_small = 1; }
+                if (sflag[j]) { small2 += d[j] * d[j]; any_small = 1; }
             if (any_small) {
                 for (int i = 0; i < r; ++i)
-                    if (sig[i] * sig[i] <= kSkip2 * dmax) safe = 0;
+                    if (sflag[perm[i]]) safe = 0;
                 const double sm = sqrt(small2);
                 if (!(sm < sig[r - 1])) safe = 0;
                 int cap = t.kcap;
@@ -348,6 +381,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     __syncthreads();
     if (!s_safe) {                 // redo with full sweeps from the current state
         skip = false;
+        classify = true;
         converged = false;
         __syncthreads();
         goto resume;

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsvd.so")
 
@@ -18,16 +20,21 @@ STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR
                 5: "ERR_NOCONV", 6: "ERR_UNSUPPORTED"}
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 RULE_GAMMA, RULE_FROB = 0, 1
+FLAG_RANK_FALLBACK = 4
 FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 
 EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
             "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
             "hsvd_set_profiling", "hsvd_launch_times", "hsvd_launch_work",
             "hsvd_plan_batched", "hsvd_execute_batched", "hsvd_get_ranks",
+            "hsvd_features_plan", "hsvd_features_execute", "hsvd_plan_widths", "hsvd_get_leaf_info",
+            "hsvd_rank_model_create", "hsvd_rank_model_destroy", "hsvd_rank_model_set_params",
+            "hsvd_rank_model_get_params", "hsvd_rank_model_train", "hsvd_rank_model_grad",
+            "hsvd_rank_model_predict",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_plan_check", "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
-                "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16"]
+                "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features"]
 
 
 class HsvdError(RuntimeError):
@@ -71,6 +78,18 @@ def lib() -> ctypes.CDLL:
     L.hsvd_plan_batched.argtypes = [P(vp), i32, P(i64), P(i64), P(i32), P(i32), P(i32), f64, P(Options)]
     L.hsvd_execute_batched.argtypes = [vp, P(vp), P(vp), P(vp), P(vp), vp]
     L.hsvd_get_ranks.argtypes = [vp, P(i32), i32]
+    u64 = ctypes.c_uint64
+    L.hsvd_features_plan.argtypes = [P(vp), i64, i64, i32, i32, i32, u64]
+    L.hsvd_features_execute.argtypes = [vp, vp, vp, vp]
+    L.hsvd_plan_widths.argtypes = [P(vp), i64, i64, i32, i32, i32, f64, P(Options), P(i32)]
+    L.hsvd_get_leaf_info.argtypes = [vp, P(i32), P(i32), i32]
+    L.hsvd_rank_model_create.argtypes = [P(vp), u64]
+    L.hsvd_rank_model_destroy.argtypes = [vp]
+    L.hsvd_rank_model_set_params.argtypes = [vp, P(ctypes.c_float), i32]
+    L.hsvd_rank_model_get_params.argtypes = [vp, P(ctypes.c_float), i32]
+    L.hsvd_rank_model_train.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, vp, vp]
+    L.hsvd_rank_model_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    L.hsvd_rank_model_predict.argtypes = [vp, vp, i32, vp, vp]
     L.hsvd_debug_plan_check_batched.argtypes = [i32, P(i64), P(i64), P(i32), P(i32), P(i32), f64,
                                                 P(Options), P(ctypes.c_size_t)]
     L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
@@ -123,7 +142,8 @@ class Plan:
     def __init__(self, m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, *,
                  precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
                  power_steps: int | None = None, refine_steps: int = 0,
-                 max_sweeps: int | None = None, seed: int = 0):
+                 max_sweeps: int | None = None, seed: int = 0, leaf_widths=None):
+        """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths)."""
         o = default_options()
         o.precision = precision
         o.rule = rule
@@ -136,7 +156,14 @@ class Plan:
             o.max_sweeps = max_sweeps
         o.seed = seed
         h = ctypes.c_void_p()
-        _check(lib().hsvd_plan_ex(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
+        if leaf_widths is None:
+            _check(lib().hsvd_plan_ex(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
+        else:
+            wv = [int(x) for x in list(np.asarray(leaf_widths).reshape(-1))]
+            if len(wv) != p * q:
+                raise ValueError("leaf_widths needs p * q entries")
+            _check(lib().hsvd_plan_widths(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o),
+                                          (ctypes.c_int32 * (p * q))(*wv)))
         self._h = h
         self.m, self.n, self.p, self.q, self.k, self.tol = m, n, p, q, k, tol
         self.precision = precision
@@ -156,6 +183,15 @@ class Plan:
         r = ctypes.c_int32()
         _check(lib().hsvd_get_rank(self._h, ctypes.byref(r)))
         return r.value
+
+    def leaf_info(self):
+        """(ranks, fallback flags) of the leaves, p x q int arrays."""
+        c = self.p * self.q
+        r = (ctypes.c_int32 * c)()
+        f = (ctypes.c_int32 * c)()
+        _check(lib().hsvd_get_leaf_info(self._h, r, f, c))
+        return (np.array(list(r), dtype=np.int32).reshape(self.p, self.q),
+                np.array(list(f), dtype=np.int32).reshape(self.p, self.q))
 
     def status(self) -> int:
         f = ctypes.c_uint32()
@@ -199,6 +235,131 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def block_features(A, p: int, q: int, seed: int = 0):
+    """Learned-rank features of every block of a torch device matrix (float64 or
+    float32): a (p * q, 16) float32 device tensor, row i * q + j for block (i, j)."""
+    import torch
+    if A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A must be float64 or float32")
+    A = A.contiguous()
+    m, n = A.shape
+    h = ctypes.c_void_p()
+    _check(lib().hsvd_features_plan(ctypes.byref(h), m, n, p, q, FP64 if A.dtype == torch.float64 else FP32,
+                                    seed))
+    F = torch.empty((p * q, 16), dtype=torch.float32, device=A.device)
+    try:
+        _check(lib().hsvd_features_execute(h, A.data_ptr(), F.data_ptr(), _stream_handle()))
+        torch.cuda.synchronize()
+    finally:
+        lib().hsvd_destroy(h)
+    return F
+
+
+class RankModel:
+    """The learned block-rank network (hsvd_rank_model_*): trained and evaluated on
+    the GPU by the library's own kernels."""
+    N_PARAMS = 5313
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hsvd_rank_model_create(ctypes.byref(h), seed))
+        self._h = h
+
+    def params(self) -> np.ndarray:
+        buf = (ctypes.c_float * self.N_PARAMS)()
+        _check(lib().hsvd_rank_model_get_params(self._h, buf, self.N_PARAMS))
+        return np.array(list(buf), dtype=np.float32)
+
+    def set_params(self, theta):
+        theta = np.asarray(theta, dtype=np.float32).ravel()
+        buf = (ctypes.c_float * self.N_PARAMS)(*theta.tolist())
+        _check(lib().hsvd_rank_model_set_params(self._h, buf, self.N_PARAMS))
+
+    def train(self, X, T, steps: int, lr: float = 3e-3):
+        """Adam steps on (features X (count, 16), targets T (count,)) float32 device
+        tensors; returns the per-step minibatch losses (device tensor)."""
+        import torch
+        X = X.contiguous().float()
+        T = T.contiguous().float()
+        losses = torch.empty((steps,), dtype=torch.float32, device=X.device)
+        _check(lib().hsvd_rank_model_train(self._h, X.data_ptr(), T.data_ptr(), X.shape[0], steps, lr,
+                                           losses.data_ptr(), _stream_handle()))
+        return losses
+
+    def grad(self, X, T, batch_index: int = 0):
+        import torch
+        X = X.contiguous().float()
+        T = T.contiguous().float()
+        g = torch.empty((self.N_PARAMS,), dtype=torch.float32, device=X.device)
+        L = torch.empty((1,), dtype=torch.float32, device=X.device)
+        _check(lib().hsvd_rank_model_grad(self._h, X.data_ptr(), T.data_ptr(), X.shape[0], batch_index,
+                                          g.data_ptr(), L.data_ptr(), _stream_handle()))
+        return g, L
+
+    def predict(self, X):
+        import torch
+        X = X.contiguous().float()
+        out = torch.empty((X.shape[0],), dtype=torch.float32, device=X.device)
+        _check(lib().hsvd_rank_model_predict(self._h, X.data_ptr(), X.shape[0], out.data_ptr(),
+                                             _stream_handle()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsvd_rank_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def widths_from_prediction(pred_log2, margin: int = 8, lmax: int = 80, quantum: int = 8):
+    """Sketch width per block: ceil(2^prediction) + margin, rounded up to a multiple
+    of `quantum` (fewer width classes), clipped to [quantum, lmax]."""
+    k = np.ceil(np.exp2(np.asarray(pred_log2, dtype=np.float64)))
+    w = np.ceil((k + margin) / quantum) * quantum
+    return np.clip(w, quantum, lmax).astype(np.int32)
+
+
+def learned_svd(A, p: int, q: int, k: int, tol: float, model: "RankModel", margin: int = 8,
+                lmax: int = 80, max_refits: int = 3, **opts):
+    """Hierarchical SVD whose leaves take the sketch widths the network predicts.
+    Blocks whose leaf reports missed energy beyond tol^2 get twice the width and
+    the call runs again (at most max_refits times).  Returns (U, S, Vt, r, info)."""
+    import torch
+    A = A.contiguous()
+    m, n = A.shape
+    F = block_features(A, p, q)
+    pred = model.predict(F).cpu().numpy()
+    widths = widths_from_prediction(pred, margin, lmax).reshape(p, q)
+    prec = FP64 if A.dtype == torch.float64 else FP32
+    opts.setdefault("rule", RULE_FROB)
+    refits = 0
+    while True:
+        plan = Plan(m, n, p, q, k, tol, precision=prec, leaf_widths=widths, **opts)
+        U = torch.empty((m, k), dtype=A.dtype, device=A.device)
+        S = torch.empty((k,), dtype=A.dtype, device=A.device)
+        Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
+        plan.execute(A, U, S, Vt)
+        ranks, fb = plan.leaf_info()
+        r = plan.rank()
+        flags = plan.status() & 0xFFFF
+        plan.close()
+        if flags & ~FLAG_RANK_FALLBACK:
+            raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
+        grow = (fb != 0) & (widths < lmax)
+        if not grow.any() or refits >= max_refits:
+            break
+        widths = np.where(grow, np.minimum(2 * widths, lmax), widths).astype(np.int32)
+        refits += 1
+    info = {"widths": widths, "leaf_ranks": ranks, "fallback": fb, "refits": refits,
+            "predicted_log2": pred.reshape(p, q)}
+    return U, S, Vt, r, info
 
 
 class BatchPlan:

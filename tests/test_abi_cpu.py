@@ -134,3 +134,28 @@ def test_batched_plan_footprint_uneven_batch():
     single = H.plan_check(*shapes[0])
     assert H.plan_check_batched(shapes[:1]) == single
     assert synth is not None
+
+
+def _build_or_no_device(st, h):
+    """Plan construction and validation run on the host; without a GPU the call
+    then stops at the device query (status 3)."""
+    lib = H.lib()
+    assert st in (0, 3), lib.hsvd_last_error()
+    if st == 0:
+        lib.hsvd_destroy(h)
+
+
+def test_feature_and_width_plans_build_on_host():
+    lib = H.lib()
+    h = ctypes.c_void_p()
+    _build_or_no_device(lib.hsvd_features_plan(ctypes.byref(h), 512, 768, 2, 3, 0, 0), h)
+    _build_or_no_device(lib.hsvd_features_plan(ctypes.byref(h), 1000, 333, 4, 3, 1, 5), h)
+    assert lib.hsvd_features_plan(ctypes.byref(h), 512, 768, 2, 3, 2, 0) == 1
+    widths = _arr(ctypes.c_int32, [8, 16, 24, 64, 80, 8])
+    o = H.default_options()
+    o.rule = 1
+    _build_or_no_device(lib.hsvd_plan_widths(ctypes.byref(h), 512, 768, 2, 3, 40, 1e-3, ctypes.byref(o),
+                                             widths), h)
+    bad = _arr(ctypes.c_int32, [8, 16, 24, 64, 81, 8])
+    assert lib.hsvd_plan_widths(ctypes.byref(h), 512, 768, 2, 3, 40, 1e-3, ctypes.byref(o), bad) == 1
+    assert lib.hsvd_plan_widths(ctypes.byref(h), 512, 768, 2, 3, 40, 1e-3, ctypes.byref(o), None) == 1
