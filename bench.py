@@ -64,9 +64,10 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the mixed path only (for rocprofv3)")
-    ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven"],
+    ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven", "learned"],
                     help="snapshot: the 8192^2 headline; uneven: 200 matrices of uneven shapes "
-                         "in one batched plan against a loop of per-matrix plans")
+                         "in one batched plan against a loop of per-matrix plans; learned: "
+                         "32768 x 8192 field matrix, learned sketch widths against k + 14")
     ap.add_argument("--count", type=int, default=200, help="uneven: number of matrices")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain copies of MIB MiB (counter calibration)")
@@ -290,6 +291,119 @@ def run_uneven(args, torch):
     print(json.dumps(res))
 
 
+def run_learned(args, torch):
+    """Learned block rank: train the network on the leaf ranks the plain method picks
+    on four seeded field matrices (8192 x 4096, 8 x 4 grid of 1024^2), then time the
+    plain plan and the learned-width plan on the 32768 x 8192 field workload (32 x 8
+    grid of 1024^2, local ranks 4..32, Frobenius rule tol 1e-3, k = 64, float32)."""
+    from paper_1710_02812_amd import hsvd as H, synth
+
+    def field(seed, p, q, block):
+        return synth.config4(seed=seed, p=p, q=q, block=block, base_rank=64, max_class=3, k=64)
+
+    def run_plan(A, w, widths=None, reps=1):
+        m, n = A.shape
+        plan = H.Plan(m, n, w.p, w.q, w.k, w.tol, precision=H.FP32 if A.dtype == torch.float32 else H.FP64,
+                      rule=H.RULE_FROB, max_sweeps=100, leaf_widths=widths)
+        U = torch.empty((m, w.k), dtype=A.dtype, device="cuda")
+        S = torch.empty((w.k,), dtype=A.dtype, device="cuda")
+        Vt = torch.empty((w.k, n), dtype=A.dtype, device="cuda")
+        plan.execute(A, U, S, Vt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.execute(A, U, S, Vt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ranks, fb = plan.leaf_info()
+        r, st = plan.rank(), plan.status()
+        plan.close()
+        return ms, U, S, Vt, r, ranks, fb, st
+
+    t = time.time()
+    Xs, Ts = [], []
+    for seed in (10, 11, 12, 13):
+        w = field(seed, 8, 4, 1024)
+        A = torch.tensor(w.A, dtype=torch.float32, device="cuda")
+        Xs.append(H.block_features(A, w.p, w.q))
+        ranks = run_plan(A, w)[5]
+        Ts.append(torch.tensor(np.log2(np.maximum(ranks.reshape(-1), 1)).astype(np.float32), device="cuda"))
+        del A
+    model = H.RankModel(seed=1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    losses = model.train(torch.cat(Xs), torch.cat(Ts), steps=1500, lr=3e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    prep_s = time.time() - t
+
+    w = field(4, 32, 8, 1024)
+    A = torch.tensor(w.A, dtype=torch.float32, device="cuda")
+    ms_plain, U0, S0, Vt0, r0, ranks0, _, st0 = run_plan(A, w, reps=args.steps)
+    e0.record()
+    F = H.block_features(A, w.p, w.q)
+    pred = model.predict(F)
+    e1.record()
+    torch.cuda.synchronize()
+    feat_ms = e0.elapsed_time(e1)
+    widths = H.widths_from_prediction(pred.cpu().numpy()).reshape(w.p, w.q)
+    ms_learned, U1, S1, Vt1, r1, ranks1, fb, st1 = run_plan(A, w, widths, reps=args.steps)
+    refits = 0
+    while (fb != 0).any() and refits < 3:
+        widths = np.where(fb != 0, np.minimum(2 * widths, 80), widths).astype(np.int32)
+        ms_learned, U1, S1, Vt1, r1, ranks1, fb, st1 = run_plan(A, w, widths, reps=args.steps)
+        refits += 1
+    acc = None
+    cpu = None
+    from oracle import metrics
+    c = metrics.compare(U1.double().cpu().numpy(), S1.double().cpu().numpy(), Vt1.double().cpu().numpy(), r1,
+                        U0.double().cpu().numpy(), S0.double().cpu().numpy(), Vt0.double().cpu().numpy(), r0)
+    if not args.no_accuracy or not args.no_cpu_baseline:
+        import oracle
+        ws_ = field(4, 8, 4, 512)
+        t = time.time()
+        Uo, so, Vto, ro = oracle.hsvd(ws_.A.astype(np.float32).astype(np.float64), ws_.p, ws_.q, ws_.k, ws_.tol, "frob")
+        cpu_s = time.time() - t
+        As = torch.tensor(ws_.A, dtype=torch.float32, device="cuda")
+        Us, Ss, Vts, rs, info = H.learned_svd(As, ws_.p, ws_.q, ws_.k, ws_.tol, model)
+        cs = metrics.compare(Us.double().cpu().numpy(), Ss.double().cpu().numpy(), Vts.double().cpu().numpy(), rs,
+                             Uo, so, Vto, ro)
+        acc = {"learned_vs_plain_full_size": {kk: (float(v) if isinstance(v, float) else v) for kk, v in c.items()},
+               "learned_vs_oracle_4096x2048": {kk: (float(v) if isinstance(v, float) else v) for kk, v in cs.items()}}
+        frac = (4096 * 2048) / w.A.size
+        cpu = {"value": round(cpu_s / frac * 1e3, 1), "unit": "ms", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"the same method on a 4096 x 2048 instance (8 x 4 grid of 512^2), {cpu_s:.1f} s, "
+                         f"scaled by element count ({frac:.4f} of the workload)"}
+        if args.no_cpu_baseline:
+            cpu = None
+    plain_cols = w.p * w.q * min(w.k + 14, 80)
+    res = {
+        "metric": "time-to-rank-k SVD (ms), learned block rank",
+        "value": round(ms_learned + feat_ms, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": round(ms_learned + feat_ms, 4), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "32768 x 8192 field matrix, 32 x 8 grid of 1024^2, local ranks 4..32 over shared "
+                               "bases, Frobenius rule tol 1e-3, k = 64, float32 storage; learned sketch widths "
+                               "(features + prediction + width plan)", "storage": "f32"},
+        "plain_ms": round(ms_plain, 4),
+        "learned_plan_ms": round(ms_learned, 4),
+        "features_and_prediction_ms": round(feat_ms, 4),
+        "learned_speedup_vs_plain": round(ms_plain / (ms_learned + feat_ms), 3),
+        "sketch_columns": {"learned": int(widths.sum()), "plain": plain_cols},
+        "refits": refits,
+        "ranks": {"learned": r1, "plain": r0},
+        "status_flags": {"learned": st1 & 0xFFFF, "plain": st0 & 0xFFFF},
+        "training": {"samples": int(sum(x.shape[0] for x in Xs)), "steps": 1500, "gpu_ms": round(train_ms, 2),
+                     "final_loss": float(losses[-1].item()), "prep_s": round(prep_s, 2)},
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -302,6 +416,9 @@ def main():
         return
     if args.workload == "uneven":
         run_uneven(args, torch)
+        return
+    if args.workload == "learned":
+        run_learned(args, torch)
         return
     from paper_1710_02812_amd import hsvd as H, synth
 

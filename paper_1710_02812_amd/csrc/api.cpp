@@ -171,13 +171,8 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
     t.p_ld = ld;
     t.nch = (h + ch - 1) / ch;
     t.chunk0 = (int)tb.chunks.size();
-    int nodes = 0, levels = 0;
-    for (int nn = t.nch;; nn = (nn + 1) >> 1) {
-        nodes += nn;
-        if (nn == 1) break;
-        ++levels;
-    }
-    t.levels = levels;
+    const int nodes = tsqr_nodes(t.nch, tsqr_fanin(w));
+    t.levels = tsqr_levels(t.nch, tsqr_fanin(w));
     t.store_off = P.alloc((int64_t)nodes * tsqr_slot_size(w));
     t.cnt_off = P.ialloc(nodes);
     t.r_out = P.alloc((int64_t)w * w);
@@ -1022,8 +1017,8 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 if (s.w > kTsqrMaxW || s.c > kTsqrMaxW || s.ch < s.w || s.ch != tsqr_chunk_rows(s.w)) return "tsqr geometry";
                 for (int i = 0; i < ntask; ++i) {
                     const TsqrTask& t = T[i];
-                    int nodes = 0;
-                    for (int nn = t.nch;; nn = (nn + 1) >> 1) { nodes += nn; if (nn == 1) break; }
+                    const int nodes = tsqr_nodes(t.nch, tsqr_fanin(s.w));
+                    if (t.levels != tsqr_levels(t.nch, tsqr_fanin(s.w))) return "tsqr levels";
                     if (t.nch != (t.h + s.ch - 1) / s.ch) return "tsqr chunk count";
                     if (!panel("tsqr panel", t.p_off, t.p_ld, t.h, s.w)) return msg;
                     if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * tsqr_slot_size(s.w) - 1, WS)) return msg;

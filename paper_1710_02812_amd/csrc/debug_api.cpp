@@ -152,11 +152,7 @@ extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h
     Scratch sc;
     const int ch = tsqr_chunk_rows(w);
     const int nch = (int)((h + ch - 1) / ch);
-    int nodes = 0;
-    for (int nn = nch;; nn = (nn + 1) >> 1) {
-        nodes += nn;
-        if (nn == 1) break;
-    }
+    const int nodes = tsqr_nodes(nch, tsqr_fanin(w));
     const int64_t hw = h * w, slot = tsqr_slot_size(w);
     const int64_t offP = 0, offI = offP + batch * hw, offQ = offI + (int64_t)w * w,
                   offS = offQ + batch * hw, offR = offS + (int64_t)batch * nodes * slot,
@@ -180,6 +176,7 @@ extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h
         t.nch = nch;
         t.chunk0 = b * nch;
         t.cnt_off = b * nodes;
+        t.levels = tsqr_levels(nch, tsqr_fanin(w));
         tt[b] = t;
         ApplyTask a{};
         a.tsqr = b;

@@ -147,22 +147,22 @@ struct HouseQR {
             if (c < w && c > j) {
                 const double tj = tau[j];
                 if (tj != 0.0) {
-                    // up to 16 pivot values stay in registers between the two passes;
-                    // beyond that they are read again (no spills)
-                    constexpr int KV = NT <= 16 ? NT : 1;
+                    // up to 8 pivot values stay in registers between the two passes;
+                    // beyond that they are read again from LDS (broadcast reads; no spills)
+                    constexpr int KV = NT <= 8 ? NT : 1;
                     double v[KV];
                     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const double vt = vj[gl + LANES * t];             // broadcast reads
-                        if (NT <= 16) v[t < KV ? t : 0] = vt;
+                        if (NT <= 8) v[t < KV ? t : 0] = vt;
                         if (t & 1) d1 = fma(vt, x[t], d1);
                         else d0 = fma(vt, x[t], d0);
                     }
                     const double f = tj * gsum(d0 + d1);
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
-                        x[t] = fma(-f, NT <= 16 ? v[t < KV ? t : 0] : vj[gl + LANES * t], x[t]);
+                        x[t] = fma(-f, NT <= 8 ? v[t < KV ? t : 0] : vj[gl + LANES * t], x[t]);
                 }
                 if (c == j + 1 && j + 1 < kmax) {                  // look-ahead reflector
                     const double s2 = norm_below<NT>(j + 1);

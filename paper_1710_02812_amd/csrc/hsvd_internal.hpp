@@ -33,7 +33,7 @@ struct TileRef { int32_t task; int32_t tile; };
 // has children (2i, 2i+1) at level L-1; an odd last node passes straight up.
 struct TsqrTask {
     int64_t p_off;        // panel, overwritten by the chunk reflectors
-    int64_t store_off;    // per-node storage: R (w*w) | V (2w*w) | tau (w)
+    int64_t store_off;    // per-node storage: R (w*w) | V (F w * w) | tau (w) | T (w*w)
     int64_t r_out;        // final R (w x w, col-major, ld w), upper triangular
     int32_t h, p_ld;
     int32_t nch;          // chunks
@@ -44,11 +44,27 @@ struct TsqrTask {
 struct ChunkRef { int32_t task; int32_t chunk; };
 
 constexpr int kTsqrMaxW = 80;
-// Per-node storage: R (w*w) | V (2w*w) | tau (w) | T (w*w).
-__host__ __device__ inline int64_t tsqr_slot_size(int w) { return 4LL * w * w + w; }
-// Rows per chunk: the factor kernel holds a chunk (or a stacked 2w x w pair of R
-// factors) in registers: 16 lanes x 12 rows per column (w <= 64) or 8 lanes x 20
-// rows (w <= 80; a stacked pair needs 2w <= 160 rows).
+// Fan-in F of the R-factor tree: up to F stacked w x w factors are merged by one
+// Householder QR held in registers (4w <= 256 rows for w <= 64, 2w <= 160 above).
+__host__ __device__ inline int tsqr_fanin(int w) { return w <= 64 ? 4 : 2; }
+// Tree nodes (chunks included) and levels above the chunks for nch chunks.
+__host__ __device__ inline int tsqr_nodes(int nch, int F) {
+    int nodes = 0;
+    for (int n = nch;; n = (n + F - 1) / F) {
+        nodes += n;
+        if (n == 1) break;
+    }
+    return nodes;
+}
+__host__ __device__ inline int tsqr_levels(int nch, int F) {
+    int l = 0;
+    for (int n = nch; n > 1; n = (n + F - 1) / F) ++l;
+    return l;
+}
+// Per-node storage: R (w*w) | V (F w * w, ld F w) | tau (w) | T (w*w).
+__host__ __device__ inline int64_t tsqr_slot_size(int w) { return (int64_t)(tsqr_fanin(w) + 2) * w * w + w; }
+// Rows per chunk: the factor kernel holds a chunk in registers: 16 lanes x 16 rows
+// per column (w <= 64) or 8 lanes x 20 rows (w <= 80).
 inline int tsqr_chunk_rows(int w) { return w <= 64 ? 256 : 160; }
 
 // out (h x c) = Q * X  (+ U1 * T when add_u_off >= 0), Q the explicit thin factor of a

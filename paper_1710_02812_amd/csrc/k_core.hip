@@ -184,6 +184,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     const double tol2 = tol * tol;
     // skip threshold: squared norm <= (1e-3)^2 of the cap-th largest squared norm
     constexpr double kSkip2 = 1e-6;
+    constexpr double kGap2 = 1e-4;
     const int cap_all = (t.fixed_rank_slot >= 0) ? min(t.kcap, iws[t.fixed_rank_slot]) : t.kcap;
     bool converged = (nc <= 1) || s_bad;
     bool skip = true;
@@ -218,7 +219,18 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 }
                 dk = wave_max(dk);
             }
-            for (int j = lane64; j < nc; j += 64) sflag[j] = (dk >= 0.0) && (d[j] <= kSkip2 * dk);
+            // ... and only when they sit apart from the rest (largest of them at most
+            // 1e-2 of the smallest kept norm): a set cut through a cluster of similar
+            // norms leaves rotations half done and convergence turns linear
+            double mx = 0.0, mn = 1.0e300;
+            for (int j = lane64; j < nc; j += 64) {
+                const bool sm = (dk >= 0.0) && (d[j] <= kSkip2 * dk);
+                if (sm) mx = fmax(mx, d[j]); else mn = fmin(mn, d[j]);
+            }
+            mx = wave_max(mx);
+            mn = -wave_max(-mn);
+            const bool apart = mx <= kGap2 * mn;
+            for (int j = lane64; j < nc; j += 64) sflag[j] = apart && (dk >= 0.0) && (d[j] <= kSkip2 * dk);
         }
         classify = false;
         __syncthreads();

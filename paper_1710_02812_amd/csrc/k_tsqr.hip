@@ -1,22 +1,22 @@
 // Tall-skinny Householder QR (TSQR) for h x w panels, w <= 80, chunks of 256 rows
 // (w <= 64) or 160 rows (w <= 80).
 //
-// Factor: each row chunk of `ch` rows is loaded into LDS and reduced by w
+// Factor: each row chunk of `ch` rows is held in registers and reduced by w
 // Householder reflectors (LAPACK dlarfg convention: H = I - tau v v^T, v_j = 1,
 // R_jj = beta).  The chunk's reflectors go back into the panel; its R, tau and the
 // compact-WY factor T (w x w upper triangular, Q = H_0 ... H_{w-1} = I - V T V^T,
 // dlarft forward/columnwise) go into the tree storage.  R factors are then merged
-// pairwise up a binary tree by QR of the stacked [R_left; R_right] (2w x w); the
-// work-group that finishes second on a pair performs the merge (an atomic counter
-// per node, reset by that group), so the whole tree runs in one launch and no
-// group waits on another.  An odd last node is merged with a zero sibling, which
-// gives tau = 0 (identity).
+// up a tree of fan-in F = 4 (w <= 64; 2 above) by the QR of the stacked children
+// [R_0; ...; R_{F-1}] (F w x w); the work-group that finishes last among a node's
+// children performs the merge (an atomic counter per node, reset by that group), so
+// the whole tree runs in one launch and no group waits on another.  A node with a
+// single child takes that child's R unchanged.
 //
 // Apply: out = Q [X; 0] for the explicit thin factor Q (h x w).  Each chunk's
-// group walks from the root to its chunk; at every node [X; 0] - V (T (V_top^T X))
-// gives the node's 2w rows, of which the half belonging to the child is kept;
-// at the chunk the same three small products give the output rows.  Optionally
-// adds U1 * Tm (the merge's U1 U_E,top term).
+// group walks from the root to its chunk; at every merged node [X; 0] - V (T (V_top^T X))
+// gives the node's F w rows, of which the w rows of the child on the path are kept
+// (single-child nodes are skipped); at the chunk the same three small products give
+// the output rows.  Optionally adds U1 * Tm (the merge's U1 U_E,top term).
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
 #include "house_qr.hpp"
@@ -25,14 +25,14 @@ namespace hsvd {
 
 constexpr int TSQR_THREADS = 1024;
 
-// Node slot layout: R (w*w) | V (2w*w) | tau (w) | T (w*w)
-__device__ __forceinline__ int64_t slot_tau(int w) { return 3LL * w * w; }
-__device__ __forceinline__ int64_t slot_T(int w) { return 3LL * w * w + w; }
+// Node slot layout: R (w*w) | V (F w * w, ld F w) | tau (w) | T (w*w), F = tsqr_fanin(w)
+__device__ __forceinline__ int64_t slot_tau(int w) { return (int64_t)(tsqr_fanin(w) + 1) * w * w; }
+__device__ __forceinline__ int64_t slot_T(int w) { return (int64_t)(tsqr_fanin(w) + 1) * w * w + w; }
 
-// Slot index of tree node (level, idx) given the chunk count.
-__device__ __forceinline__ int node_slot(int nch, int level, int idx) {
+// Slot index of tree node (level, idx) given the chunk count and the fan-in.
+__device__ __forceinline__ int node_slot(int nch, int F, int level, int idx) {
     int off = 0, n = nch;
-    for (int l = 0; l < level; ++l) { off += n; n = (n + 1) >> 1; }
+    for (int l = 0; l < level; ++l) { off += n; n = (n + F - 1) / F; }
     return off + idx;
 }
 
@@ -42,7 +42,7 @@ __device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l
     return i == l ? 1.0 : (i > l ? A[(int64_t)l * ld + i] : 0.0);
 }
 
-// MT: registers live in a tree merge (2w <= LANES * MT rows)
+// MT: registers live in a tree merge (F w <= LANES * MT rows)
 template <int LANES, int RMAX, int MT>
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
@@ -66,69 +66,64 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
     double* store = ws + t.store_off;
     const int64_t S = tsqr_slot_size(w);
 
+    const int F = tsqr_fanin(w);
+    int level = 0, idx = cr.chunk, n = t.nch;
+    int cur_rows = rows;                // rows of the block in registers
+    double* dst = store + S * node_slot(t.nch, F, 0, cr.chunk);
     q.load(P + row0, t.p_ld, rows, w);
-    q.factor(rows, w, T, tau, z, vbuf);
-    q.store(P + row0, t.p_ld, rows, w);
-    {
-        double* slot = store + S * node_slot(t.nch, 0, cr.chunk);
-        q.store_r(slot, rows, w);
+    // One factorization call site (the chunk, then each merge this group performs):
+    // a single inlined copy keeps the register block free of spills.
+    for (;;) {
+        q.factor(cur_rows, w, T, tau, z, vbuf);
+        if (level == 0) q.store(P + row0, t.p_ld, rows, w);      // chunk reflectors
+        else q.store(dst + w * w, F * w, F * w, w);               // rows past the stack are zeros
+        q.store_r(dst, cur_rows, w);
         for (int e = tid; e < w * w; e += nth) {
             const int j = e / w, i = e - j * w;
-            slot[slot_T(w) + e] = T[(int64_t)j * (w + 1) + i];
+            dst[slot_T(w) + e] = T[(int64_t)j * (w + 1) + i];
         }
-        for (int j = tid; j < w; j += nth) slot[slot_tau(w) + j] = tau[j];
-    }
-    int level = 0, idx = cr.chunk, n = t.nch;
-    int last_rows = rows;
-    while (n > 1) {
-        const int parent = idx >> 1;
-        const bool has_sib = ((idx ^ 1) < n);
+        for (int j = tid; j < w; j += nth) dst[slot_tau(w) + j] = tau[j];
+        // climb: single-child parents take the R unchanged; at a merged parent the
+        // last child to arrive stacks the children's R factors and factors them
+        int nsib = 1, parent = 0;
+        while (n > 1) {
+            parent = idx / F;
+            nsib = min(F, n - parent * F);
+            dst = store + S * node_slot(t.nch, F, level + 1, parent);
+            ++level;
+            idx = parent;
+            n = (n + F - 1) / F;
+            if (nsib > 1) break;
+            __syncthreads();
+            q.store_r(dst, cur_rows, w);
+        }
+        if (nsib == 1) break;                                       // reached the root
         __threadfence();
         __syncthreads();
-        if (has_sib) {
-            if (tid == 0) {
-                const int slot = node_slot(t.nch, level + 1, parent);
-                const int old = atomicAdd(&iws[t.cnt_off + slot], 1);
-                s_go = (old == 1);
-                if (old == 1) atomicExch(&iws[t.cnt_off + slot], 0);
-            }
-            __syncthreads();
-            if (!s_go) return;
+        if (tid == 0) {
+            const int cslot = node_slot(t.nch, F, level, parent);
+            const int old = atomicAdd(&iws[t.cnt_off + cslot], 1);
+            s_go = (old == nsib - 1);
+            if (old == nsib - 1) atomicExch(&iws[t.cnt_off + cslot], 0);
         }
+        __syncthreads();
+        if (!s_go) return;                                          // a later sibling merges
         __threadfence();
-        // stack [R_left; R_right (or 0)] -> 2w x w, straight into registers
-        const int left = parent * 2;
-        const double* Rl = store + S * node_slot(t.nch, level, left);
-        const double* Rr = has_sib ? store + S * node_slot(t.nch, level, left + 1) : nullptr;
         {
+            // the children are consecutive slots of the level below
+            const double* c0 = store + S * node_slot(t.nch, F, level - 1, parent * F);
             const int c = tid / LANES, gl = tid % LANES;
+            const int rlim = nsib * w;
 #pragma unroll
             for (int tt = 0; tt < RMAX; ++tt) {
                 const int r = gl + LANES * tt;
-                double v = 0.0;
-                if (c < w && r < 2 * w) {
-                    if (r < w) v = Rl[(int64_t)c * w + r];
-                    else if (Rr) v = Rr[(int64_t)c * w + (r - w)];
-                }
-                q.x[tt] = v;
+                const int ch_i = r / w;
+                q.x[tt] = (c < w && r < rlim) ? c0[S * ch_i + (int64_t)c * w + (r - ch_i * w)] : 0.0;
             }
         }
-        // the stacked pair has 2w rows: only the first MT registers are live
-        q.template factor<MT>(2 * w, w, T, tau, z, vbuf);
-        double* slot = store + S * node_slot(t.nch, level + 1, parent);
-        q.store_r(slot, 2 * w, w);
-        q.store(slot + w * w, 2 * w, 2 * w, w);
-        for (int e = tid; e < w * w; e += nth) {
-            const int j = e / w, i = e - j * w;
-            slot[slot_T(w) + e] = T[(int64_t)j * (w + 1) + i];
-        }
-        for (int j = tid; j < w; j += nth) slot[slot_tau(w) + j] = tau[j];
-        last_rows = 2 * w;
-        ++level;
-        idx = parent;
-        n = (n + 1) >> 1;
+        cur_rows = nsib * w;
     }
-    q.store_r(ws + t.r_out, last_rows, w);
+    q.store_r(ws + t.r_out, cur_rows, w);
 }
 
 // Dense copy of rows [r0, r0 + nrows) of the reflector block V (unit diagonal,
@@ -141,29 +136,74 @@ __device__ void stage_v(const double* V, int64_t ldv, int r0, int nrows, int w, 
     }
 }
 
-// One compact-WY level on LDS operands: W1 = V_top^T X (V_top staged in Vs, ld w),
-// then W2 = T W1 (T from global, col-major ld w) written back over W1
-// (w * c <= 8 * blockDim.x).
+// Register-tiled small product C = sum_k a(i, k) b(k, j) over an M x N output:
+// thread t owns TR x TC tiles t, t + nth, ... (row tiles fastest, so consecutive
+// threads read consecutive rows of column-major operands); each k step loads TR + TC
+// values and issues TR * TC independent FMAs.  out(i0, j0, acc) receives each tile.
+template <int TR, int TC, typename FA, typename FB, typename FO>
+__device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
+    const int tr = (M + TR - 1) / TR, tc = (N + TC - 1) / TC;
+    for (int t = threadIdx.x; t < tr * tc; t += blockDim.x) {
+        const int i0 = (t % tr) * TR, j0 = (t / tr) * TC;
+        double acc[TR][TC];
+#pragma unroll
+        for (int r = 0; r < TR; ++r)
+#pragma unroll
+            for (int s = 0; s < TC; ++s) acc[r][s] = 0.0;
+#pragma unroll 2
+        for (int k = 0; k < K; ++k) {
+            double av[TR], bv[TC];
+#pragma unroll
+            for (int r = 0; r < TR; ++r) av[r] = (i0 + r < M) ? a(i0 + r, k) : 0.0;
+#pragma unroll
+            for (int s = 0; s < TC; ++s) bv[s] = (j0 + s < N) ? b(k, j0 + s) : 0.0;
+#pragma unroll
+            for (int r = 0; r < TR; ++r)
+#pragma unroll
+                for (int s = 0; s < TC; ++s) acc[r][s] = fma(av[r], bv[s], acc[r][s]);
+        }
+        out(i0, j0, acc);
+    }
+}
+
+// One compact-WY level on LDS operands: W = T (V_top^T X) (V_top staged in Vs with
+// leading dimension w; T col-major ld w in global memory), W written over itself
+// through registers (2 x 2 tiles, at most two per thread: w * c <= 8 * 1024).
 __device__ void wy_w(const double* Vs, const double* Tg, const double* X, double* W, int w, int c) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    for (int e = tid; e < w * c; e += nth) {
-        const int cc = e / w, l = e - cc * w;
-        double d = 0.0;
-        for (int i = l; i < w; ++i) d = fma(Vs[(int64_t)l * w + i], X[(int64_t)cc * w + i], d);
-        W[e] = d;
-    }
+    tiled<2, 2>(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * w + i]; },
+                [&](int i, int cc) { return X[(int64_t)cc * w + i]; },
+                [&](int l0, int c0, double (&acc)[2][2]) {
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+                            if (l0 + r < w && c0 + s < c) W[(int64_t)(c0 + s) * w + l0 + r] = acc[r][s];
+                });
     __syncthreads();
-    double r[8];
-    int cnt = 0;
-    for (int e = tid; e < w * c; e += nth, ++cnt) {
-        const int cc = e / w, i = e - cc * w;
-        double d = 0.0;
-        for (int l = i; l < w; ++l) d = fma(Tg[(int64_t)l * w + i], W[(int64_t)cc * w + l], d);
-        r[cnt] = d;
-    }
+    double keep[2][2][2];
+    int nt = 0;
+    tiled<2, 2>(w, c, w, [&](int i, int l) { return Tg[(int64_t)l * w + i]; },
+                [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
+                [&](int, int, double (&acc)[2][2]) {
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) keep[nt & 1][r][s] = acc[r][s];
+                    ++nt;
+                });
     __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < w * c; e += nth, ++cnt) W[e] = r[cnt];
+    {
+        const int tr = (w + 1) / 2, tc = (c + 1) / 2;
+        int u = 0;
+        for (int t = threadIdx.x; t < tr * tc; t += blockDim.x, ++u) {
+            const int i0 = (t % tr) * 2, c0 = (t / tr) * 2;
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    if (i0 + r < w && c0 + s < c) W[(int64_t)(c0 + s) * w + i0 + r] = keep[u & 1][r][s];
+        }
+    }
     __syncthreads();
 }
 
@@ -185,35 +225,48 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
 
     const double* Xg = ws + a.x_off;
     for (int e = tid; e < w * c; e += nth) X[e] = Xg[e];
-    int levels = 0;
-    for (int n = t.nch; n > 1; n = (n + 1) >> 1) ++levels;
+    const int F = tsqr_fanin(w);
+    const int levels = tsqr_levels(t.nch, F);
     for (int level = levels; level >= 1; --level) {
-        const int idx = cr.chunk >> level;
-        const bool right = (cr.chunk >> (level - 1)) & 1;
-        const double* slot = store + S * node_slot(t.nch, level, idx);
-        const double* V = slot + w * w;              // 2w x w, ld 2w
-        stage_v(V, 2 * w, 0, w, w, Vs, w);
+        int span = 1, nbelow = t.nch;                 // chunks per node one level down; nodes there
+        for (int l = 1; l < level; ++l) { span *= F; nbelow = (nbelow + F - 1) / F; }
+        const int idx = cr.chunk / (span * F);
+        const int pos = (cr.chunk / span) % F;        // which child leads towards this chunk
+        if (min(F, nbelow - idx * F) == 1) continue;  // a lone child: the parent is its R
+        const bool right = pos > 0;
+        const double* slot = store + S * node_slot(t.nch, F, level, idx);
+        const double* V = slot + w * w;              // F w x w, ld F w
+        __syncthreads();
+        stage_v(V, F * w, 0, w, w, Vs, w);
         __syncthreads();
         wy_w(Vs, slot + slot_T(w), X, W, w, c);
         if (right) {
-            stage_v(V, 2 * w, w, w, w, Vs, w);
+            stage_v(V, F * w, pos * w, w, w, Vs, w);
             __syncthreads();
         }
-        for (int e = tid; e < w * c; e += nth) {
-            const int cc = e / w, i = e - cc * w;
-            double d = right ? 0.0 : X[e];
-            for (int l = 0; l < w; ++l) d = fma(-Vs[(int64_t)l * w + i], W[(int64_t)cc * w + l], d);
-            X[e] = d;                                  // each entry reads only itself from X
-        }
-        __syncthreads();
+        // X <- (first child: X, others: 0) - V_child W; each tile reads and writes only itself
+        tiled<2, 2>(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * w + i]; },
+                    [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
+                    [&](int i0, int c0, double (&acc)[2][2]) {
+#pragma unroll
+                        for (int r = 0; r < 2; ++r)
+#pragma unroll
+                            for (int s = 0; s < 2; ++s)
+                                if (i0 + r < w && c0 + s < c) {
+                                    double* xp = X + (int64_t)(c0 + s) * w + i0 + r;
+                                    *xp = (right ? 0.0 : *xp) - acc[r][s];
+                                }
+                    });
     }
-    // chunk level: out = [X; 0] - V (T (V_top^T X)) over the chunk rows
+    // chunk level: out = [X; 0] - V (T (V_top^T X)) over the chunk rows (+ U1 Tm)
     const int row0 = cr.chunk * ch;
     const int rows = min(ch, t.h - row0);
     const double* Vc = ws + t.p_off + row0;
-    const double* cslot = store + S * node_slot(t.nch, 0, cr.chunk);
+    const int64_t ldv = t.p_ld;
+    const double* cslot = store + S * node_slot(t.nch, F, 0, cr.chunk);
     const int vtop = rows < w ? rows : w;
-    stage_v(Vc, t.p_ld, 0, vtop, w, Vs, w);
+    __syncthreads();
+    stage_v(Vc, ldv, 0, vtop, w, Vs, w);
     for (int e = tid; e < (w - vtop) * w; e += nth) {     // rows past a short chunk: zero
         const int l = e / (w - vtop), i = vtop + e - l * (w - vtop);
         Vs[(int64_t)l * w + i] = 0.0;
@@ -223,24 +276,43 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     double* out = ws + a.out_off;
     const double* U1 = a.add_u_off >= 0 ? ws + a.add_u_off : nullptr;
     const double* Tm = a.add_u_off >= 0 ? ws + a.add_t_off : nullptr;
-    for (int r0 = 0; r0 < rows; r0 += w) {
-        const int nrow = min(w, rows - r0);
-        if (r0 > 0) {
-            __syncthreads();
-            stage_v(Vc, t.p_ld, r0, nrow, w, Vs, w);
-            __syncthreads();
-        }
-        for (int e = tid; e < nrow * c; e += nth) {
-            const int cc = e / nrow, ii = e - cc * nrow;
-            const int i = r0 + ii;
-            double d = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
-            for (int l = 0; l < w; ++l) d = fma(-Vs[(int64_t)l * w + ii], W[(int64_t)cc * w + l], d);
-            if (U1)
-                for (int l = 0; l < a.add_w; ++l)
-                    d = fma(U1[(int64_t)l * a.add_u_ld + row0 + i], Tm[(int64_t)cc * a.add_w + l], d);
-            out[(int64_t)cc * a.out_ld + row0 + i] = d;
-        }
-    }
+    const int aw = a.add_w;
+    // reflector entries straight from the panel (unit diagonal, zeros above)
+    auto vchunk = [&](int i, int l) {
+        return i == l ? 1.0 : (i > l ? Vc[(int64_t)l * ldv + i] : 0.0);
+    };
+    tiled<4, 4>(rows, c, w, vchunk, [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
+                [&](int i0, int c0, double (&acc)[4][4]) {
+                    double add[4][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) add[r][s] = 0.0;
+                    if (U1) {
+                        for (int l = 0; l < aw; ++l) {
+                            double uv[4], tv[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                uv[r] = (i0 + r < rows) ? U1[(int64_t)l * a.add_u_ld + row0 + i0 + r] : 0.0;
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) tv[s] = (c0 + s < c) ? Tm[(int64_t)(c0 + s) * aw + l] : 0.0;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) add[r][s] = fma(uv[r], tv[s], add[r][s]);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int i = i0 + r, cc = c0 + s;
+                            if (i < rows && cc < c) {
+                                const double x = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
+                                out[(int64_t)cc * a.out_ld + row0 + i] = x - acc[r][s] + add[r][s];
+                            }
+                        }
+                });
 }
 
 template <int LANES, int RMAX, int MT>
@@ -261,10 +333,10 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const
     if (w < 1 || w > kTsqrMaxW || ch != tsqr_chunk_rows(w)) return hipErrorInvalidValue;
     // a chunk and a stacked pair of R factors must fit the register block
     if (w <= 64) {
-        if (ch > 16 * 16 || 2 * w > 16 * 8) return hipErrorInvalidValue;
-        return launch_factor_t<16, 16, 8>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+        if (ch > 16 * 16 || tsqr_fanin(w) * w > 16 * 16) return hipErrorInvalidValue;
+        return launch_factor_t<16, 16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
     }
-    if (ch > 8 * 20 || 2 * w > 8 * 20) return hipErrorInvalidValue;
+    if (ch > 8 * 20 || tsqr_fanin(w) * w > 8 * 20) return hipErrorInvalidValue;
     return launch_factor_t<8, 20, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
@@ -273,7 +345,9 @@ hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* 
                              hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * (2 * (size_t)w * c + (size_t)w * w + 32);
-    if (w * c > 8 * TSQR_THREADS) return hipErrorInvalidValue;   // wy_w keeps 8 values per thread
+    // wy_w keeps at most two 2 x 2 tiles per thread across its barrier
+    if (w * c > 8 * TSQR_THREADS || ((w + 1) / 2) * ((c + 1) / 2) > 2 * TSQR_THREADS)
+        return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_apply,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
