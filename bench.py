@@ -63,7 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run warmup + steps of the mixed path only (for rocprofv3)")
+                    help="run warmup + steps of one path only (for rocprofv3)")
+    ap.add_argument("--path", default="fp32", choices=["mixed", "fp32", "fp64"],
+                    help="the path --profile-only runs")
     ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven", "learned"],
                     help="snapshot: the 8192^2 headline; uneven: 200 matrices of uneven shapes "
                          "in one batched plan against a loop of per-matrix plans; learned: "
@@ -431,10 +433,12 @@ def main():
     A32 = A64.float()
     torch.cuda.synchronize()
 
-    rmx = time_path(H, torch, A32, H.MIXED_BF16, args, k, p, q)
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_mixed": rmx["ms"]}))
+        prec = {"mixed": H.MIXED_BF16, "fp32": H.FP32, "fp64": H.FP64}[args.path]
+        r = time_path(H, torch, A64 if args.path == "fp64" else A32, prec, args, k, p, q)
+        print(json.dumps({"profile_only": True, "path": args.path, "ms": r["ms"]}))
         return
+    rmx = time_path(H, torch, A32, H.MIXED_BF16, args, k, p, q)
     r32 = time_path(H, torch, A32, H.FP32, args, k, p, q)
     r64 = time_path(H, torch, A64, H.FP64, args, k, p, q)
     m, n = w.A.shape
@@ -527,10 +531,11 @@ def main():
                          "fp64": r64["flags"] & 0xFFFF},
         "max_jacobi_sweeps": {"mixed": rmx["flags"] >> 16, "fp32": r32["flags"] >> 16,
                               "fp64": r64["flags"] >> 16},
-        "launch_kinds_mixed": kind_table(kinds),
+        "launch_kinds_mixed": kind_table(rmx["kinds"]),
         "launch_kinds_fp32": kind_table(r32["kinds"]),
         "launch_kinds_fp64": kind_table(r64["kinds"]),
         "launches_mixed": rmx["launches"],
+        "launches_fp32": r32["launches"],
         "accuracy_vs_oracle": acc,
         "generate_s": round(gen_s, 2),
     }
