@@ -241,6 +241,8 @@ void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks) {
     Stage s{};
     s.kind = kind;
     s.n = (kind == ST_REDUCE) ? (int)tasks.size() : (int)chunks.size();
+    if (kind == ST_REDUCE)
+        for (const ThinTask& t : tasks) s.w = std::max(s.w, t.wx * t.wy);
     s.tasks_off = P.put(tasks);
     s.refs_off = P.put(chunks);
     P.stages.push_back(s);
@@ -1058,6 +1060,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         if (!panel("gram Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
                         if (!span("gram part", t.part_off, t.part_off + (int64_t)t.nch * t.wx * t.wy - 1, WS)) return msg;
                     } else if (s.kind == ST_REDUCE) {
+                        if (t.wx * t.wy > s.w) return "reduce grid";
                         if (!span("reduce part", t.part_off, t.part_off + (int64_t)t.nch * t.wx * t.wy - 1, WS)) return msg;
                         if (!panel("reduce C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
                         if (t.acc_off >= 0 && !panel("reduce acc", t.acc_off, t.c_ld, t.wx, t.wy)) return msg;
@@ -1164,7 +1167,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
                                  (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
             break;
         case ST_REDUCE:
-            e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, st);
+            e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, s.w, st);
             break;
         case ST_NN:
             e = launch_thin_nn(P.ws, (const ThinTask*)(b + s.tasks_off),

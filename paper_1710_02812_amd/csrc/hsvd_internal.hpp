@@ -163,7 +163,8 @@ hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* 
                              hipStream_t s);
 hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks,
                             int nchunks, int chh, hipStream_t s);
-hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, hipStream_t s);
+// maxsz: the largest wx * wy over the tasks (grid: task x element slices of 256)
+hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int maxsz, hipStream_t s);
 hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks,
                            int nchunks, int chh, hipStream_t s);
 hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks,

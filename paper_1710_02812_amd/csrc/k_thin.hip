@@ -68,20 +68,28 @@ __global__ __launch_bounds__(256) void k_thin_gram(double* __restrict__ ws,
 
 __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
                                                      const ThinTask* __restrict__ tasks) {
+    // grid: task x (element slices of 256); one thread per element of C, partials
+    // summed in chunk order
     const ThinTask t = tasks[blockIdx.x];
     const int64_t sz = (int64_t)t.wx * t.wy;
-    const double* P = ws + t.part_off;
-    double* C = ws + t.c_off;
-    double* Acc = t.acc_off >= 0 ? ws + t.acc_off : nullptr;
-    for (int64_t e = threadIdx.x; e < sz; e += blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < t.nch; ++c) s += P[c * sz + e];
-        const int j = (int)(e / t.wx), i = (int)(e - (int64_t)j * t.wx);
-        C[(int64_t)j * t.c_ld + i] = s;
-        if (Acc) {
-            double* a = Acc + (int64_t)j * t.c_ld + i;
-            *a = t.accumulate ? *a + s : s;
-        }
+    const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= sz) return;
+    const double* P = ws + t.part_off + e;
+    double s = 0.0;
+    int c = 0;
+    for (; c + 8 <= t.nch; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)(c + u) * sz];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < t.nch; ++c) s += P[(int64_t)c * sz];
+    const int j = (int)(e / t.wx), i = (int)(e - (int64_t)j * t.wx);
+    ws[t.c_off + (int64_t)j * t.c_ld + i] = s;
+    if (t.acc_off >= 0) {
+        double* a = ws + t.acc_off + (int64_t)j * t.c_ld + i;
+        *a = t.accumulate ? *a + s : s;
     }
 }
 
@@ -167,9 +175,9 @@ hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunk
     hipLaunchKernelGGL(k_thin_gram, dim3(nchunks, 2, 2), dim3(256), 0, s, ws, t, chunks, chh);
     return hipGetLastError();
 }
-hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, hipStream_t s) {
-    if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_reduce, dim3(ntasks), dim3(256), 0, s, ws, t);
+hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int maxsz, hipStream_t s) {
+    if (ntasks <= 0 || maxsz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thin_reduce, dim3(ntasks, (maxsz + 255) / 256), dim3(256), 0, s, ws, t);
     return hipGetLastError();
 }
 hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
