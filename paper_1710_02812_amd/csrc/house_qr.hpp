@@ -19,7 +19,9 @@ namespace hsvd {
 // into the other half of a double buffer.  Columns c < j meanwhile form
 // z_c = v_c^T v_j and, from the z of step j - 1, their row of T column j - 1 (each
 // group owns one row of T, so T never needs a barrier of its own).
-template <int LANES, int RMAX, bool WITH_T = true>
+// KVMAX: pivot values kept in registers between the dot and the update when
+// NT <= KVMAX (else read twice from LDS).
+template <int LANES, int RMAX, bool WITH_T = true, int KVMAX = 8>
 struct HouseQR {
     static constexpr int NG = 1024 / LANES;
     static constexpr int VB = LANES * RMAX;      // rows one column can hold
@@ -147,22 +149,23 @@ struct HouseQR {
             if (c < w && c > j) {
                 const double tj = tau[j];
                 if (tj != 0.0) {
-                    // up to 8 pivot values stay in registers between the two passes;
-                    // beyond that they are read again from LDS (broadcast reads; no spills)
-                    constexpr int KV = NT <= 8 ? NT : 1;
+                    // up to KVMAX pivot values stay in registers between the two passes;
+                    // beyond that they are read again from LDS (broadcast reads)
+                    constexpr bool CACHE = NT <= KVMAX;
+                    constexpr int KV = CACHE ? NT : 1;
                     double v[KV];
                     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const double vt = vj[gl + LANES * t];             // broadcast reads
-                        if (NT <= 8) v[t < KV ? t : 0] = vt;
+                        if (CACHE) v[t < KV ? t : 0] = vt;
                         if (t & 1) d1 = fma(vt, x[t], d1);
                         else d0 = fma(vt, x[t], d0);
                     }
                     const double f = tj * gsum(d0 + d1);
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
-                        x[t] = fma(-f, NT <= 8 ? v[t < KV ? t : 0] : vj[gl + LANES * t], x[t]);
+                        x[t] = fma(-f, CACHE ? v[t < KV ? t : 0] : vj[gl + LANES * t], x[t]);
                 }
                 if (c == j + 1 && j + 1 < kmax) {                  // look-ahead reflector
                     const double s2 = norm_below<NT>(j + 1);

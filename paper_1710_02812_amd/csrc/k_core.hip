@@ -73,6 +73,8 @@ __device__ int select_rank(const double* sig, int nc, const CoreTask& t, const i
     return r;
 }
 
+// ROWS: every column is padded with zeros to ROWS >= maxdim rows (a multiple of 16)
+template <int ROWS>
 __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, int* __restrict__ iws,
                                                        const CoreTask* __restrict__ tasks,
                                                        int maxdim, int max_sweeps,
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     const CoreTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane64 = tid & 63, wave = tid >> 6, nw = nth >> 6;
-    constexpr int ROWS = 128;                 // every column padded with zeros to 128 rows
+    static_assert(ROWS % 16 == 0 && ROWS <= 128, "ROWS");
     const int ldg = ROWS + 1;
     double* G = sm;
     double* V = G + (int64_t)maxdim * ldg;
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     int* perm = (int*)(sig + maxdim);
     __shared__ int s_nr, s_nc, s_r1, s_r2, s_rot, s_bad, s_rank, s_safe;
     __shared__ unsigned char sflag[128];
+    __shared__ unsigned long long s_mask[2];      // sflag as bits (columns 0..63, 64..127)
     __shared__ double s_dmax;
 
     if (tid == 0) {
@@ -145,6 +148,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             V[(int64_t)j * ldg + i] = (i == j) ? 1.0 : 0.0;
         }
     for (int j = tid; j < 128; j += nth) sflag[j] = 0;
+    if (tid < 2) s_mask[tid] = 0ull;
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
 
@@ -152,21 +156,23 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     // run on L (same left singular pairs).  Group c (8 lanes) holds row c of G as
     // column c of G^T, lane rows are G's columns; Q is not formed.
     if (t.precond && !accv && !s_bad && nc > 1) {
-        HouseQR<8, 16, false> q;
+        constexpr int RQ = ROWS / 8;              // rows of G^T (columns of G) per lane
+        HouseQR<8, RQ, false, 16> q;
         const int c = tid >> 3, gl = tid & 7;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < RQ; ++s) {
             const int r = gl + 8 * s;
             q.x[s] = (c < nr && r < nc) ? G[(int64_t)r * ldg + c] : 0.0;
         }
-        // scratch: tau -> sig, the two pivot buffers -> the first 256 entries of G
-        // (maxdim >= 2 here, so G holds >= 258); T and z are not used
+        // scratch: tau -> sig, the two pivot buffers -> the first 2 ROWS entries of G
+        // (maxdim >= nc >= 2 here, so G holds >= 2 ROWS + 2); T and z are not used.
+        // Groups c >= nr hold zero columns of G^T; only c < ROWS have a row of G.
         __syncthreads();                          // all of G is in registers
         q.factor(nc, nr, G, sig, d, G);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < RQ; ++s) {
             const int r = gl + 8 * s;
-            if (r < nc) G[(int64_t)r * ldg + c] = (r <= c) ? q.x[s] : 0.0;
+            if (r < nc && c < ROWS) G[(int64_t)r * ldg + c] = (r <= c) ? q.x[s] : 0.0;
         }
         __syncthreads();
     }
@@ -230,34 +236,46 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             mx = wave_max(mx);
             mn = -wave_max(-mn);
             const bool apart = mx <= kGap2 * mn;
-            for (int j = lane64; j < nc; j += 64) sflag[j] = apart && (dk >= 0.0) && (d[j] <= kSkip2 * dk);
+            const bool on = apart && (dk >= 0.0);
+            const bool f0 = on && lane64 < nc && d[lane64] <= kSkip2 * dk;
+            const bool f1 = on && lane64 + 64 < nc && d[lane64 + 64] <= kSkip2 * dk;
+            sflag[lane64] = f0;
+            sflag[lane64 + 64] = f1;
+            const unsigned long long b0 = __ballot(f0), b1 = __ballot(f1);
+            if (lane64 == 0) { s_mask[0] = b0; s_mask[1] = b1; }
         }
         classify = false;
         __syncthreads();
+        const unsigned long long mask0 = s_mask[0], mask1 = s_mask[1];
         int a = (grp == 0) ? 0 : grp;
         int b = (grp == 0) ? N - 1 : N - 1 - grp;
         for (int round = 0; round < N - 1; ++round) {
             if (grp < npairs) {
-                const bool valid = (a < nc) && (b < nc) && !(sflag[a] && sflag[b]);
+                // skip flags from registers, norms issued with the column loads:
+                // no LDS round trip before the loads or after the reduction
+                const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
+                const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
+                const bool valid = (a < nc) && (b < nc) && !(fa && fb);
                 double ra[TMAX], rb[TMAX];
-                double c0 = 0.0, c1 = 0.0;
+                double c0 = 0.0, c1 = 0.0, da = 0.0, db = 0.0;
                 double* ga = G + (int64_t)(valid ? a : 0) * ldg;
                 double* gb = G + (int64_t)(valid ? b : 0) * ldg;
                 if (valid) {
+                    da = d[a];
+                    db = d[b];
 #pragma unroll
                     for (int t = 0; t < TMAX; ++t) {
                         ra[t] = ga[gl + t * gsz];
                         rb[t] = gb[gl + t * gsz];
                     }
 #pragma unroll
-                    for (int t = 0; t < TMAX; t += 2) {
-                        c0 = fma(ra[t], rb[t], c0);
-                        c1 = fma(ra[t + 1], rb[t + 1], c1);
+                    for (int t = 0; t < TMAX; ++t) {          // TMAX may be odd (112 rows)
+                        if (t & 1) c1 = fma(ra[t], rb[t], c1);
+                        else c0 = fma(ra[t], rb[t], c0);
                     }
                 }
                 const double c = group_sum(c0 + c1, gsz);
                 if (valid) {
-                    const double da = d[a], db = d[b];
                     if (da > 0.0 && db > 0.0 && c * c > tol2 * da * db) {
                         // tan of the rotation angle: t = sign(dd) g / (|dd| + sqrt(dd^2 + g^2)),
                         // dd = |g_b|^2 - |g_a|^2, g = 2 g_a.g_b (the smaller root of
@@ -431,18 +449,29 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     }
 }
 
+template <int ROWS>
+hipError_t launch_core_rows(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
+                            int max_sweeps, unsigned* flags, int with_v, hipStream_t s) {
+    const size_t lds = sizeof(double) * ((size_t)maxdim * (ROWS + 1) * (with_v ? 2 : 1) +
+                                         2 * (size_t)maxdim + 1) + sizeof(int) * maxdim + 64;
+    hipError_t e = hipFuncSetAttribute((const void*)k_core<ROWS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_core<ROWS>, dim3(ntasks), dim3(CORE_THREADS), lds, s, ws, iws, tasks, maxdim,
+                       max_sweeps, flags, with_v);
+    return hipGetLastError();
+}
+
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                          int max_sweeps, unsigned* flags, int with_v, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    if (maxdim > 128 || (with_v && maxdim > 64)) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * ((size_t)maxdim * 129 * (with_v ? 2 : 1) +
-                                         2 * (size_t)maxdim + 1) + sizeof(int) * maxdim + 64;
-    hipError_t e = hipFuncSetAttribute((const void*)k_core,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_core, dim3(ntasks), dim3(CORE_THREADS), lds, s, ws, iws, tasks, maxdim,
-                       max_sweeps, flags, with_v);
-    return hipGetLastError();
+    if (maxdim < 1 || maxdim > 128 || (with_v && maxdim > 64)) return hipErrorInvalidValue;
+    // rows padded to the smallest variant that holds the largest core of the launch
+    if (maxdim <= 32) return launch_core_rows<32>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
+    if (maxdim <= 64) return launch_core_rows<64>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
+    if (maxdim <= 96) return launch_core_rows<96>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
+    if (maxdim <= 112) return launch_core_rows<112>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
+    return launch_core_rows<128>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
 }
 
 }  // namespace hsvd

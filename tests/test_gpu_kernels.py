@@ -18,7 +18,7 @@ def _t(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 100, 128])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 90, 100, 128])
 def test_jacobi_dense_random(n):
     rng = np.random.default_rng(n)
     M = rng.standard_normal((3, n, n))
@@ -64,7 +64,7 @@ def _merge_matrix(rng, k, h=600, noise=1e-6):
     return E
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 100, 128])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 90, 100, 128])
 def test_jacobi_preconditioned(n):
     """LQ-preconditioned sweeps: same singular values, orthonormal left vectors,
     U^T M has orthogonal rows of norms S (M M^T = U S^2 U^T)."""
