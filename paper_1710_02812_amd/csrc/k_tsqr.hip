@@ -42,9 +42,16 @@ __device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l
     return i == l ? 1.0 : (i > l ? A[(int64_t)l * ld + i] : 0.0);
 }
 
-// MT: registers live in a tree merge (F w <= LANES * MT rows)
-template <int LANES, int RMAX, int MT>
-__global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict__ ws,
+// Factor work-groups: CPL = 2 columns per lane group on 512 threads (each lane
+// reads a pivot value once for both of its columns; the pivot stays in registers;
+// panels above 64 columns hold 2 x 20 registers per lane and re-read the pivot).
+constexpr int TSQR_CPL = 2;
+constexpr int TSQR_FTHREADS = 1024 / TSQR_CPL;
+template <int LANES, int RMAX>
+using TsqrQR = HouseQR<LANES, RMAX, true, (RMAX <= 16 ? RMAX : 8), TSQR_CPL, TSQR_FTHREADS>;
+
+template <int LANES, int RMAX>
+__global__ __launch_bounds__(TSQR_FTHREADS) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
                                                               const TsqrTask* __restrict__ tasks,
                                                               const ChunkRef* __restrict__ chunks,
@@ -55,7 +62,8 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
     double* z = tau + w;                             // 2w
     double* vbuf = z + 2 * w;                        // 2 * LANES * RMAX
     __shared__ int s_go;
-    HouseQR<LANES, RMAX> q;
+    TsqrQR<LANES, RMAX> q;
+    constexpr int NG = TsqrQR<LANES, RMAX>::NG;
 
     const ChunkRef cr = chunks[blockIdx.x];
     const TsqrTask t = tasks[cr.task];
@@ -112,13 +120,18 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_factor(double* __restrict
         {
             // the children are consecutive slots of the level below
             const double* c0 = store + S * node_slot(t.nch, F, level - 1, parent * F);
-            const int c = tid / LANES, gl = tid % LANES;
+            const int gl = tid % LANES;
             const int rlim = nsib * w;
 #pragma unroll
-            for (int tt = 0; tt < RMAX; ++tt) {
-                const int r = gl + LANES * tt;
-                const int ch_i = r / w;
-                q.x[tt] = (c < w && r < rlim) ? c0[S * ch_i + (int64_t)c * w + (r - ch_i * w)] : 0.0;
+            for (int sl = 0; sl < TSQR_CPL; ++sl) {
+                const int c = tid / LANES + sl * NG;
+#pragma unroll
+                for (int tt = 0; tt < RMAX; ++tt) {
+                    const int r = gl + LANES * tt;
+                    const int ch_i = r / w;
+                    q.x[sl * RMAX + tt] =
+                        (c < w && r < rlim) ? c0[S * ch_i + (int64_t)c * w + (r - ch_i * w)] : 0.0;
+                }
             }
         }
         cur_rows = nsib * w;
@@ -137,14 +150,16 @@ __device__ void stage_v(const double* V, int64_t ldv, int r0, int nrows, int w, 
 }
 
 // Register-tiled small product C = sum_k a(i, k) b(k, j) over an M x N output:
-// thread t owns TR x TC tiles t, t + nth, ... (row tiles fastest, so consecutive
-// threads read consecutive rows of column-major operands); each k step loads TR + TC
-// values and issues TR * TC independent FMAs.  out(i0, j0, acc) receives each tile.
+// thread t owns tiles t, t + nth, ...; a tile has rows i0 + r di (r < TR, di =
+// ceil(M / TR), i0 = t mod di: consecutive threads take consecutive rows, so every
+// load of a column-major operand is contiguous across the wave) and columns j0 + s
+// (s < TC); each k step loads TR + TC values and issues TR * TC independent FMAs.
+// out(i0, di, j0, acc) receives each tile.
 template <int TR, int TC, typename FA, typename FB, typename FO>
 __device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
     const int tr = (M + TR - 1) / TR, tc = (N + TC - 1) / TC;
     for (int t = threadIdx.x; t < tr * tc; t += blockDim.x) {
-        const int i0 = (t % tr) * TR, j0 = (t / tr) * TC;
+        const int i0 = t % tr, j0 = (t / tr) * TC;
         double acc[TR][TC];
 #pragma unroll
         for (int r = 0; r < TR; ++r)
@@ -154,7 +169,7 @@ __device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
         for (int k = 0; k < K; ++k) {
             double av[TR], bv[TC];
 #pragma unroll
-            for (int r = 0; r < TR; ++r) av[r] = (i0 + r < M) ? a(i0 + r, k) : 0.0;
+            for (int r = 0; r < TR; ++r) av[r] = (i0 + r * tr < M) ? a(i0 + r * tr, k) : 0.0;
 #pragma unroll
             for (int s = 0; s < TC; ++s) bv[s] = (j0 + s < N) ? b(k, j0 + s) : 0.0;
 #pragma unroll
@@ -162,7 +177,7 @@ __device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
 #pragma unroll
                 for (int s = 0; s < TC; ++s) acc[r][s] = fma(av[r], bv[s], acc[r][s]);
         }
-        out(i0, j0, acc);
+        out(i0, tr, j0, acc);
     }
 }
 
@@ -172,19 +187,19 @@ __device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
 __device__ void wy_w(const double* Vs, const double* Tg, const double* X, double* W, int w, int c) {
     tiled<2, 2>(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * w + i]; },
                 [&](int i, int cc) { return X[(int64_t)cc * w + i]; },
-                [&](int l0, int c0, double (&acc)[2][2]) {
+                [&](int l0, int dl, int c0, double (&acc)[2][2]) {
 #pragma unroll
                     for (int r = 0; r < 2; ++r)
 #pragma unroll
                         for (int s = 0; s < 2; ++s)
-                            if (l0 + r < w && c0 + s < c) W[(int64_t)(c0 + s) * w + l0 + r] = acc[r][s];
+                            if (l0 + r * dl < w && c0 + s < c) W[(int64_t)(c0 + s) * w + l0 + r * dl] = acc[r][s];
                 });
     __syncthreads();
     double keep[2][2][2];
     int nt = 0;
     tiled<2, 2>(w, c, w, [&](int i, int l) { return Tg[(int64_t)l * w + i]; },
                 [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                [&](int, int, double (&acc)[2][2]) {
+                [&](int, int, int, double (&acc)[2][2]) {
 #pragma unroll
                     for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -196,12 +211,12 @@ __device__ void wy_w(const double* Vs, const double* Tg, const double* X, double
         const int tr = (w + 1) / 2, tc = (c + 1) / 2;
         int u = 0;
         for (int t = threadIdx.x; t < tr * tc; t += blockDim.x, ++u) {
-            const int i0 = (t % tr) * 2, c0 = (t / tr) * 2;
+            const int i0 = t % tr, c0 = (t / tr) * 2;       // the tiles of the product above
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
-                    if (i0 + r < w && c0 + s < c) W[(int64_t)(c0 + s) * w + i0 + r] = keep[u & 1][r][s];
+                    if (i0 + r * tr < w && c0 + s < c) W[(int64_t)(c0 + s) * w + i0 + r * tr] = keep[u & 1][r][s];
         }
     }
     __syncthreads();
@@ -247,13 +262,13 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
         // X <- (first child: X, others: 0) - V_child W; each tile reads and writes only itself
         tiled<2, 2>(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * w + i]; },
                     [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                    [&](int i0, int c0, double (&acc)[2][2]) {
+                    [&](int i0, int di, int c0, double (&acc)[2][2]) {
 #pragma unroll
                         for (int r = 0; r < 2; ++r)
 #pragma unroll
                             for (int s = 0; s < 2; ++s)
-                                if (i0 + r < w && c0 + s < c) {
-                                    double* xp = X + (int64_t)(c0 + s) * w + i0 + r;
+                                if (i0 + r * di < w && c0 + s < c) {
+                                    double* xp = X + (int64_t)(c0 + s) * w + i0 + r * di;
                                     *xp = (right ? 0.0 : *xp) - acc[r][s];
                                 }
                     });
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
         return i == l ? 1.0 : (i > l ? Vc[(int64_t)l * ldv + i] : 0.0);
     };
     tiled<4, 4>(rows, c, w, vchunk, [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                [&](int i0, int c0, double (&acc)[4][4]) {
+                [&](int i0, int di, int c0, double (&acc)[4][4]) {
                     double add[4][4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
@@ -293,7 +308,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                             double uv[4], tv[4];
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                uv[r] = (i0 + r < rows) ? U1[(int64_t)l * a.add_u_ld + row0 + i0 + r] : 0.0;
+                                uv[r] = (i0 + r * di < rows) ? U1[(int64_t)l * a.add_u_ld + row0 + i0 + r * di] : 0.0;
 #pragma unroll
                             for (int s = 0; s < 4; ++s) tv[s] = (c0 + s < c) ? Tm[(int64_t)(c0 + s) * aw + l] : 0.0;
 #pragma unroll
@@ -306,7 +321,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
-                            const int i = i0 + r, cc = c0 + s;
+                            const int i = i0 + r * di, cc = c0 + s;
                             if (i < rows && cc < c) {
                                 const double x = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
                                 out[(int64_t)cc * a.out_ld + row0 + i] = x - acc[r][s] + add[r][s];
@@ -315,14 +330,15 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                 });
 }
 
-template <int LANES, int RMAX, int MT>
+template <int LANES, int RMAX>
 static hipError_t launch_factor_t(double* ws, int* iws, const TsqrTask* tasks,
                                   const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s) {
-    const size_t lds = sizeof(double) * (HouseQR<LANES, RMAX>::lds_doubles(w) + 32);
-    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX, MT>,
+    if (w > TsqrQR<LANES, RMAX>::WMAX) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * (TsqrQR<LANES, RMAX>::lds_doubles(w) + 32);
+    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX, MT>), dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws,
+    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX>), dim3(nchunks), dim3(TSQR_FTHREADS), lds, s, ws,
                        iws, tasks, chunks, w, ch);
     return hipGetLastError();
 }
@@ -334,10 +350,10 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const
     // a chunk and a stacked pair of R factors must fit the register block
     if (w <= 64) {
         if (ch > 16 * 16 || tsqr_fanin(w) * w > 16 * 16) return hipErrorInvalidValue;
-        return launch_factor_t<16, 16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+        return launch_factor_t<16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
     }
     if (ch > 8 * 20 || tsqr_fanin(w) * w > 8 * 20) return hipErrorInvalidValue;
-    return launch_factor_t<8, 20, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+    return launch_factor_t<8, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
 hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
