@@ -181,11 +181,18 @@ __device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
     }
 }
 
-// One compact-WY level on LDS operands: W = T (V_top^T X) (V_top staged in Vs with
-// leading dimension w; T col-major ld w in global memory), W written over itself
-// through registers (2 x 2 tiles, at most two per thread: w * c <= 8 * 1024).
-__device__ void wy_w(const double* Vs, const double* Tg, const double* X, double* W, int w, int c) {
-    tiled<2, 2>(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * w + i]; },
+// One compact-WY level on LDS operands: W = T (V_top^T X).  V_top is staged in Vs
+// with leading dimension w + 1 (the product reads it across its rows: an odd pitch
+// keeps the lanes of a wave on distinct banks); T is col-major with leading dimension
+// w, in LDS (Ts, copied here while the first product runs) or, when it does not fit,
+// read from global memory (Tg).  W is written over itself through registers (2 x 2
+// tiles, at most two per thread).
+__device__ void wy_w(const double* Vs, const double* Tg, double* Ts, const double* X, double* W,
+                     int w, int c) {
+    if (Ts)
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) Ts[e] = Tg[e];
+    const int ldvs = w + 1;
+    tiled<2, 2>(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * ldvs + i]; },
                 [&](int i, int cc) { return X[(int64_t)cc * w + i]; },
                 [&](int l0, int dl, int c0, double (&acc)[2][2]) {
 #pragma unroll
@@ -195,9 +202,10 @@ __device__ void wy_w(const double* Vs, const double* Tg, const double* X, double
                             if (l0 + r * dl < w && c0 + s < c) W[(int64_t)(c0 + s) * w + l0 + r * dl] = acc[r][s];
                 });
     __syncthreads();
+    const double* T = Ts ? Ts : Tg;
     double keep[2][2][2];
     int nt = 0;
-    tiled<2, 2>(w, c, w, [&](int i, int l) { return Tg[(int64_t)l * w + i]; },
+    tiled<2, 2>(w, c, w, [&](int i, int l) { return T[(int64_t)l * w + i]; },
                 [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
                 [&](int, int, int, double (&acc)[2][2]) {
 #pragma unroll
@@ -222,6 +230,18 @@ __device__ void wy_w(const double* Vs, const double* Tg, const double* X, double
     __syncthreads();
 }
 
+// LDS of the apply (doubles): X (w c) | W (w c) | Vs (max(w (w + 1), kApplySlab ch))
+// | Ts (w w, only when the whole fits).
+constexpr int kApplySlab = 16;          // reflector / U1 columns per staged slab
+constexpr size_t kApplyLdsMax = 160 * 1024;
+__host__ __device__ inline size_t apply_buf(int w, int ch) {
+    const size_t a = (size_t)w * (w + 1), b = (size_t)kApplySlab * ch;
+    return a > b ? a : b;
+}
+__host__ __device__ inline bool apply_stage_t(int w, int ch, int c) {
+    return sizeof(double) * (2 * (size_t)w * c + apply_buf(w, ch) + (size_t)w * w + 32) <= kApplyLdsMax;
+}
+
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict__ ws,
                                                              const TsqrTask* __restrict__ tsqr,
                                                              const ApplyTask* __restrict__ tasks,
@@ -230,7 +250,9 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     extern __shared__ double sm[];
     double* X = sm;                                  // w x c (ld w)
     double* W = X + (int64_t)w * c;                  // w x c
-    double* Vs = W + (int64_t)w * c;                 // w x w staged reflector rows
+    double* Vs = W + (int64_t)w * c;                 // staged reflector rows (ld w + 1) / slabs
+    double* Ts = apply_stage_t(w, ch, c) ? Vs + apply_buf(w, ch) : nullptr;   // T (w x w)
+    const int ldvs = w + 1;
     const ChunkRef cr = chunks[blockIdx.x];
     const ApplyTask a = tasks[cr.task];
     const TsqrTask t = tsqr[a.tsqr];
@@ -252,15 +274,15 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
         const double* slot = store + S * node_slot(t.nch, F, level, idx);
         const double* V = slot + w * w;              // F w x w, ld F w
         __syncthreads();
-        stage_v(V, F * w, 0, w, w, Vs, w);
+        stage_v(V, F * w, 0, w, w, Vs, ldvs);
         __syncthreads();
-        wy_w(Vs, slot + slot_T(w), X, W, w, c);
+        wy_w(Vs, slot + slot_T(w), Ts, X, W, w, c);
         if (right) {
-            stage_v(V, F * w, pos * w, w, w, Vs, w);
+            stage_v(V, F * w, pos * w, w, w, Vs, ldvs);
             __syncthreads();
         }
         // X <- (first child: X, others: 0) - V_child W; each tile reads and writes only itself
-        tiled<2, 2>(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * w + i]; },
+        tiled<2, 2>(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * ldvs + i]; },
                     [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
                     [&](int i0, int di, int c0, double (&acc)[2][2]) {
 #pragma unroll
@@ -281,53 +303,82 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     const double* cslot = store + S * node_slot(t.nch, F, 0, cr.chunk);
     const int vtop = rows < w ? rows : w;
     __syncthreads();
-    stage_v(Vc, ldv, 0, vtop, w, Vs, w);
+    stage_v(Vc, ldv, 0, vtop, w, Vs, ldvs);
     for (int e = tid; e < (w - vtop) * w; e += nth) {     // rows past a short chunk: zero
         const int l = e / (w - vtop), i = vtop + e - l * (w - vtop);
-        Vs[(int64_t)l * w + i] = 0.0;
+        Vs[(int64_t)l * ldvs + i] = 0.0;
     }
     __syncthreads();
-    wy_w(Vs, cslot + slot_T(w), X, W, w, c);
+    wy_w(Vs, cslot + slot_T(w), Ts, X, W, w, c);
     double* out = ws + a.out_off;
     const double* U1 = a.add_u_off >= 0 ? ws + a.add_u_off : nullptr;
-    const double* Tm = a.add_u_off >= 0 ? ws + a.add_t_off : nullptr;
-    const int aw = a.add_w;
-    // reflector entries straight from the panel (unit diagonal, zeros above)
-    auto vchunk = [&](int i, int l) {
-        return i == l ? 1.0 : (i > l ? Vc[(int64_t)l * ldv + i] : 0.0);
-    };
-    tiled<4, 4>(rows, c, w, vchunk, [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                [&](int i0, int di, int c0, double (&acc)[4][4]) {
-                    double add[4][4];
+    const int aw = U1 ? a.add_w : 0;
+    const double* Tm = U1 ? ws + a.add_t_off : nullptr;    // aw x c, ld aw
+    if (U1 && Ts && aw * c <= w * w) {                      // T is done with: Tm takes its place
+        for (int e = tid; e < aw * c; e += nth) Ts[e] = Tm[e];
+        Tm = Ts;
+    }
+    // One product over K = w + aw: out = [X; 0] - [V_chunk | U1] [W; -Tm].  The left
+    // operand streams through LDS in slabs of kApplySlab columns, each loaded by all
+    // threads at once (coalesced, one memory round trip per slab); the right operand
+    // is in LDS (W; Tm when it fit).  4 x 4 tiles with interleaved rows.
+    const int K = w + aw;
+    double* Bs = Vs;                                        // slab: Bs[kk * rows + i]
+    const int tr = (rows + 3) / 4, tc = (c + 3) / 4, ntiles = tr * tc;
+    for (int base = 0; base < ntiles; base += nth) {
+        const int tile = base + tid;
+        const bool active = tile < ntiles;
+        const int i0 = active ? tile % tr : 0, j0 = active ? (tile / tr) * 4 : 0;
+        double acc[4][4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) add[r][s] = 0.0;
-                    if (U1) {
-                        for (int l = 0; l < aw; ++l) {
-                            double uv[4], tv[4];
+            for (int s = 0; s < 4; ++s) acc[r][s] = 0.0;
+        for (int k0 = 0; k0 < K; k0 += kApplySlab) {
+            const int ks = min(kApplySlab, K - k0);
+            __syncthreads();                                // the previous slab is consumed
+            for (int e = tid; e < ks * rows; e += nth) {
+                const int kk = e / rows, i = e - kk * rows, k = k0 + kk;
+                double v;
+                if (k < w) v = (i == k) ? 1.0 : (i > k ? Vc[(int64_t)k * ldv + i] : 0.0);
+                else v = U1[(int64_t)(k - w) * a.add_u_ld + row0 + i];
+                Bs[(int64_t)kk * rows + i] = v;
+            }
+            __syncthreads();
+            if (active) {
+                for (int kk = 0; kk < ks; ++kk) {
+                    const int k = k0 + kk;
+                    double av[4], bv[4];
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                uv[r] = (i0 + r * di < rows) ? U1[(int64_t)l * a.add_u_ld + row0 + i0 + r * di] : 0.0;
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + r * tr;
+                        av[r] = i < rows ? Bs[(int64_t)kk * rows + i] : 0.0;
+                    }
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) tv[s] = (c0 + s < c) ? Tm[(int64_t)(c0 + s) * aw + l] : 0.0;
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                                for (int s = 0; s < 4; ++s) add[r][s] = fma(uv[r], tv[s], add[r][s]);
-                        }
+                    for (int s = 0; s < 4; ++s) {
+                        const int j = j0 + s;
+                        bv[s] = j >= c ? 0.0 : (k < w ? W[(int64_t)j * w + k] : -Tm[(int64_t)j * aw + (k - w)]);
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const int i = i0 + r * di, cc = c0 + s;
-                            if (i < rows && cc < c) {
-                                const double x = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
-                                out[(int64_t)cc * a.out_ld + row0 + i] = x - acc[r][s] + add[r][s];
-                            }
-                        }
-                });
+                        for (int s = 0; s < 4; ++s) acc[r][s] = fma(av[r], bv[s], acc[r][s]);
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int i = i0 + r * tr, cc = j0 + s;
+                    if (i < rows && cc < c) {
+                        const double x = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
+                        out[(int64_t)cc * a.out_ld + row0 + i] = x - acc[r][s];
+                    }
+                }
+        }
+    }
 }
 
 template <int LANES, int RMAX>
@@ -360,7 +411,9 @@ hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* 
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (2 * (size_t)w * c + (size_t)w * w + 32);
+    const size_t lds = sizeof(double) * (2 * (size_t)w * c + apply_buf(w, ch) +
+                                         (apply_stage_t(w, ch, c) ? (size_t)w * w : 0) + 32);
+    if (lds > kApplyLdsMax) return hipErrorInvalidValue;
     // wy_w keeps at most two 2 x 2 tiles per thread across its barrier
     if (w * c > 8 * TSQR_THREADS || ((w + 1) / 2) * ((c + 1) / 2) > 2 * TSQR_THREADS)
         return hipErrorInvalidValue;
