@@ -4,66 +4,35 @@
 //   reduce : C = sum_c part[c];  Cacc = C or Cacc += C (one group per task)
 //   nn     : Y_c = X_c C  |  Y_c += X_c C  |  Y_c -= X_c C
 //   sum    : Y_c = sum_j P_j,c (partial products of a split reduction)
-// Widths are at most 128; a group handles a 64-row x 64-column output tile.
+// Widths are at most 128; gram and nn run one 64 x 64 output tile per group on the
+// float64 matrix cores.
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
+#include "mfma_f64.hpp"
 
 namespace hsvd {
 
-constexpr int TT = 64;
+constexpr int TT = MF_T;
 
-// part (wx x wy) = X_c^T Y_c for one chunk; grid: chunk x (wx/64) x (wy/64) tiles.
+// part (wx x wy) = X_c^T Y_c for one chunk on the float64 matrix cores; grid: chunk x
+// (wx / 64) x (wy / 64) tiles.  X_c^T is a row-major wx x rows array (leading
+// dimension x_ld), Y_c a column-major rows x wy panel.
 __global__ __launch_bounds__(256) void k_thin_gram(double* __restrict__ ws,
                                                    const ThinTask* __restrict__ tasks,
                                                    const ChunkRef* __restrict__ chunks, int chh) {
-    __shared__ double Xs[32][TT + 1];
-    __shared__ double Ys[32][TT + 1];
+    __shared__ double As[mfma_lds_a<0>()];
+    __shared__ double Bs[mfma_lds_b()];
     const ChunkRef cr = chunks[blockIdx.x];
     const ThinTask t = tasks[cr.task];
     const int bx = blockIdx.y * TT, by = blockIdx.z * TT;
     if (bx >= t.wx || by >= t.wy) return;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int row0 = cr.chunk * chh;
     const int rows = min(chh, t.h - row0);
-    const double* X = ws + t.x_off + row0;
-    const double* Y = ws + t.y_off + row0;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < rows; k0 += 32) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = tid + 256 * u;
-            const int c = e >> 5, kk = e & 31;
-            const bool ok = (k0 + kk) < rows;
-            Xs[kk][c] = (ok && bx + c < t.wx) ? X[(int64_t)(bx + c) * t.x_ld + k0 + kk] : 0.0;
-            Ys[kk][c] = (ok && by + c < t.wy) ? Y[(int64_t)(by + c) * t.y_ld + k0 + kk] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = Xs[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Ys[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
+    v4d acc[2][2];
+    mfma_tile<double, 0>(ws + t.x_off + row0, t.x_ld, ws + t.y_off + row0, t.y_ld, t.wx, t.wy, rows,
+                         bx, by, As, Bs, acc);
     double* P = ws + t.part_off + (int64_t)cr.chunk * t.wx * t.wy;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = bx + ty + 16 * i, c = by + tx + 16 * j;
-            if (r < t.wx && c < t.wy) P[(int64_t)c * t.wx + r] = acc[i][j];
-        }
+    mfma_tile_out(t.wx, t.wy, bx, by, acc, [&](int r, int c, double v) { P[(int64_t)c * t.wx + r] = v; });
 }
 
 __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
@@ -93,62 +62,31 @@ __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
     }
 }
 
-// Y_c (op)= X_c * C  with C (wx x wy, ld c_ld); grid: chunk x (wy/64) column tiles.
+// Y_c (op)= X_c * C with C (wx x wy, ld c_ld) on the float64 matrix cores; grid: chunk
+// x (chh / 64) row tiles x (wy / 64) column tiles.  X_c (rows x wx, column-major) is the
+// transpose of a row-major wx x rows array.
 __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws,
                                                  const ThinTask* __restrict__ tasks,
                                                  const ChunkRef* __restrict__ chunks, int chh) {
-    __shared__ double Cs[128][TT + 1];   // [l][col]
-    __shared__ double Xs[TT][129];       // [row][l]
+    __shared__ double As[mfma_lds_a<1>()];
+    __shared__ double Bs[mfma_lds_b()];
     const ChunkRef cr = chunks[blockIdx.x];
     const ThinTask t = tasks[cr.task];
-    const int by = blockIdx.y * TT;
-    if (by >= t.wy) return;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int rt = blockIdx.y * TT, by = blockIdx.z * TT;
     const int row0 = cr.chunk * chh;
     const int rows = min(chh, t.h - row0);
-    const double* C = ws + t.c_off;
-    for (int e = tid; e < t.wx * TT; e += 256) {
-        const int c = e / t.wx, l = e - c * t.wx;
-        Cs[l][c] = (by + c < t.wy) ? C[(int64_t)(by + c) * t.c_ld + l] : 0.0;
-    }
-    const double* X = ws + t.x_off;
-    double* Y = ws + t.y_off;
-    for (int r0 = 0; r0 < rows; r0 += TT) {
-        __syncthreads();
-        for (int e = tid; e < t.wx * TT; e += 256) {
-            const int l = e / TT, r = e - l * TT;
-            Xs[r][l] = (r0 + r < rows) ? X[(int64_t)l * t.x_ld + row0 + r0 + r] : 0.0;
-        }
-        __syncthreads();
-        double acc[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-        for (int l = 0; l < t.wx; ++l) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = Xs[ty + 16 * i][l];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Cs[l][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = r0 + ty + 16 * i, c = by + tx + 16 * j;
-                if (r < rows && c < t.wy) {
-                    double* y = Y + (int64_t)c * t.y_ld + row0 + r;
-                    if (t.accumulate == 0) *y = acc[i][j];
-                    else if (t.accumulate == 1) *y += acc[i][j];
-                    else *y -= acc[i][j];
-                }
-            }
-    }
+    if (rt >= rows || by >= t.wy) return;
+    v4d acc[2][2];
+    mfma_tile<double, 1>(ws + t.x_off + row0, t.x_ld, ws + t.c_off, t.c_ld, rows, t.wy, t.wx, rt, by,
+                         As, Bs, acc);
+    double* Y = ws + t.y_off + row0;
+    const int mode = t.accumulate;
+    mfma_tile_out(rows, t.wy, rt, by, acc, [&](int r, int c, double v) {
+        double* y = Y + (int64_t)c * t.y_ld + r;
+        if (mode == 0) *y = v;
+        else if (mode == 1) *y += v;
+        else *y -= v;
+    });
 }
 
 // Y_c = sum_{j < wx} P_j,c with P_j = X + j * c_ld (each ld x_ld), width wy.
@@ -183,7 +121,7 @@ hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int max
 hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
                           int chh, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, 2), dim3(256), 0, s, ws, t, chunks, chh);
+    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, (chh + TT - 1) / TT, 2), dim3(256), 0, s, ws, t, chunks, chh);
     return hipGetLastError();
 }
 hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,

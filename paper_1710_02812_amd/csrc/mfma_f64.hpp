@@ -1,0 +1,118 @@
+// One 64 x 64 output tile of a float64 product on the matrix cores
+// (v_mfma_f64_16x16x4_f64), for 256-thread work-groups.  Shared by the passes over
+// the input and the thin-panel kernels.
+//
+// C[r0 + i][c0 + j] = sum_k A(r0 + i, k) B(k, c0 + j), i, j < 64, k < K, with
+//   OP 0: A row-major M x K   (A(i, k) = A[i * lda + k]),
+//   OP 1: A stored K x M      (A(i, k) = A[k * lda + i], the transpose of a row-major array),
+//   B column-major K x N      (B(k, j) = B[j * ldb + k]).
+// Wave w owns the 32 x 32 quarter (rows 32 (w & 1), columns 32 (w >> 1)) as 2 x 2
+// blocks of 16 x 16.  Per 4-deep step lane l holds A[i = l % 16][k = l / 16] and
+// B[k = l / 16][j = l % 16]; accumulator element v holds C[i = l / 16 + 4 v][j = l % 16].
+// Slabs of 32 along K are staged through LDS in the order they are read from memory
+// (conflict-free stores) while the next slab is fetched into registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsvd {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int MF_T = 64;        // tile rows and columns
+constexpr int MF_K = 32;        // reduction slab
+
+// LDS doubles of the staging buffers: A slab then B slab
+template <int OP>
+__host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (MF_K + 1) : MF_K * (MF_T + 1); }
+__host__ __device__ constexpr int mfma_lds_b() { return MF_T * (MF_K + 1); }
+
+template <typename TA, int OP>
+__device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
+                                          const double* __restrict__ B, int64_t ldb,
+                                          int M, int N, int K, int r0, int c0, double* As, double* Bs,
+                                          v4d (&acc)[2][2]) {
+    constexpr int AP = OP == 0 ? MF_K + 1 : MF_T + 1;
+    constexpr int BP = MF_K + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    TA pa[8];
+    double pb[8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            if (OP == 0) {
+                const int r = e >> 5, kk = e & 31;            // A(r0 + r, k0 + kk)
+                const int gr = r0 + r, gk = k0 + kk;
+                pa[u] = (gr < M && gk < K) ? A[(int64_t)gr * lda + gk] : (TA)0;
+            } else {
+                const int kk = e >> 6, c = e & 63;            // A(r0 + c, k0 + kk)
+                const int gk = k0 + kk, gc = r0 + c;
+                pa[u] = (gk < K && gc < M) ? A[(int64_t)gk * lda + gc] : (TA)0;
+            }
+            const int bc = e >> 5, bk = e & 31;                // B(k0 + bk, c0 + bc)
+            const int gbc = c0 + bc, gbk = k0 + bk;
+            pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : 0.0;
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            if (OP == 0) As[(e >> 5) * AP + (e & 31)] = (double)pa[u];
+            else As[(e >> 6) * AP + (e & 63)] = (double)pa[u];
+            Bs[(e >> 5) * BP + (e & 31)] = pb[u];
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += MF_K) {
+        stage();
+        __syncthreads();
+        if (k0 + MF_K < K) fetch(k0 + MF_K);                  // in flight during the products
+#pragma unroll
+        for (int q = 0; q < MF_K / 4; ++q) {
+            const int kk = 4 * q + lk;
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = wr + 16 * i + li;
+                a[i] = OP == 0 ? As[row * AP + kk] : As[kk * AP + row];
+                b[i] = Bs[(wc + 16 * i + li) * BP + kk];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+}
+
+// Visits the tile's outputs: f(row, col, value) for rows < M, columns < N.
+template <typename F>
+__device__ __forceinline__ void mfma_tile_out(int M, int N, int r0, int c0, const v4d (&acc)[2][2], F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int gc = c0 + wc + 16 * j + li;
+        if (gc >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = r0 + wr + 16 * i + lk + 4 * v;
+                if (gr < M) f(gr, gc, acc[i][j][v]);
+            }
+    }
+}
+
+}  // namespace hsvd
