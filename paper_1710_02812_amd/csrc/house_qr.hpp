@@ -204,6 +204,10 @@ struct HouseQR {
                 __syncthreads();
             }
         } else {
+            // A wave's lane groups share one instruction stream, so the step runs in
+            // three phases: the updates of every column c > j (both slots), then the
+            // look-ahead reflector of column j + 1 (the step's critical path), then z
+            // and the T rows of the columns c < j.
             for (int j = 0; j < kmax; ++j) {
                 const double* vj = vbuf + (j & 1) * VB;
                 const double tj = tau[j];
@@ -219,18 +223,7 @@ struct HouseQR {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) v[t < KV ? t : 0] = vj[gl + LANES * t];   // broadcast reads
                 }
-#pragma unroll
-                for (int s = 0; s < CPL; ++s) {
-                    const int c = grp + s * NG;
-                    if (c >= w || c == j) continue;
-                    if (c > j && tj == 0.0) {
-                        if (c == j + 1 && j + 1 < kmax) {             // look-ahead reflector
-                            const double s2 = norm_below<NT>(s, j + 1);
-                            reflect<NT>(s, j + 1, s2, vbuf + ((j + 1) & 1) * VB, tau);
-                        }
-                        continue;
-                    }
-                    if (c < j && !WITH_T) continue;
+                auto dot_v = [&](int s) {
                     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
@@ -238,21 +231,37 @@ struct HouseQR {
                         if (t & 1) d1 = fma(vt, x[s * RMAX + t], d1);
                         else d0 = fma(vt, x[s * RMAX + t], d0);
                     }
-                    const double d = gsum(d0 + d1);
-                    if (c > j) {
-                        const double f = tj * d;
+                    return gsum(d0 + d1);
+                };
+#pragma unroll
+                for (int s = 0; s < CPL; ++s) {                     // updates
+                    const int c = grp + s * NG;
+                    if (c < w && c > j && tj != 0.0) {
+                        const double f = tj * dot_v(s);
 #pragma unroll
                         for (int t = 0; t < NT; ++t)
                             x[s * RMAX + t] = fma(-f, CACHE ? v[t < KV ? t : 0] : vj[gl + LANES * t],
                                                   x[s * RMAX + t]);
-                        if (c == j + 1 && j + 1 < kmax) {             // look-ahead reflector
-                            const double s2 = norm_below<NT>(s, j + 1);
-                            reflect<NT>(s, j + 1, s2, vbuf + ((j + 1) & 1) * VB, tau);
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < CPL; ++s) {                     // look-ahead reflector
+                    const int c = grp + s * NG;
+                    if (c == j + 1 && j + 1 < kmax) {
+                        const double s2 = norm_below<NT>(s, j + 1);
+                        reflect<NT>(s, j + 1, s2, vbuf + ((j + 1) & 1) * VB, tau);
+                    }
+                }
+                if (WITH_T) {
+#pragma unroll
+                    for (int s = 0; s < CPL; ++s) {                 // z and T rows
+                        const int c = grp + s * NG;
+                        if (c < j) {
+                            const double d = dot_v(s);
+                            if (gl == 0) z[(j & 1) * w + c] = d;      // z_c = v_c^T v_j
+                            if (c < j - 1) t_row(T, ldt, c, j - 1, z + ((j - 1) & 1) * w, tau[j - 1]);
+                            else if (gl == 0) T[(int64_t)(j - 1) * ldt + (j - 1)] = tau[j - 1];
                         }
-                    } else if (WITH_T) {
-                        if (gl == 0) z[(j & 1) * w + c] = d;          // z_c = v_c^T v_j
-                        if (c < j - 1) t_row(T, ldt, c, j - 1, z + ((j - 1) & 1) * w, tau[j - 1]);
-                        else if (gl == 0) T[(int64_t)(j - 1) * ldt + (j - 1)] = tau[j - 1];
                     }
                 }
                 __syncthreads();
