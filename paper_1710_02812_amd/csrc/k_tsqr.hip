@@ -20,6 +20,7 @@
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
 #include "house_qr.hpp"
+#include "mfma_f64.hpp"
 
 namespace hsvd {
 
@@ -149,97 +150,42 @@ __device__ void stage_v(const double* V, int64_t ldv, int r0, int nrows, int w, 
     }
 }
 
-// Register-tiled small product C = sum_k a(i, k) b(k, j) over an M x N output:
-// thread t owns tiles t, t + nth, ...; a tile has rows i0 + r di (r < TR, di =
-// ceil(M / TR), i0 = t mod di: consecutive threads take consecutive rows, so every
-// load of a column-major operand is contiguous across the wave) and columns j0 + s
-// (s < TC); each k step loads TR + TC values and issues TR * TC independent FMAs.
-// out(i0, di, j0, acc) receives each tile.
-template <int TR, int TC, typename FA, typename FB, typename FO>
-__device__ __forceinline__ void tiled(int M, int N, int K, FA a, FB b, FO out) {
-    const int tr = (M + TR - 1) / TR, tc = (N + TC - 1) / TC;
-    for (int t = threadIdx.x; t < tr * tc; t += blockDim.x) {
-        const int i0 = t % tr, j0 = (t / tr) * TC;
-        double acc[TR][TC];
-#pragma unroll
-        for (int r = 0; r < TR; ++r)
-#pragma unroll
-            for (int s = 0; s < TC; ++s) acc[r][s] = 0.0;
-#pragma unroll 2
-        for (int k = 0; k < K; ++k) {
-            double av[TR], bv[TC];
-#pragma unroll
-            for (int r = 0; r < TR; ++r) av[r] = (i0 + r * tr < M) ? a(i0 + r * tr, k) : 0.0;
-#pragma unroll
-            for (int s = 0; s < TC; ++s) bv[s] = (j0 + s < N) ? b(k, j0 + s) : 0.0;
-#pragma unroll
-            for (int r = 0; r < TR; ++r)
-#pragma unroll
-                for (int s = 0; s < TC; ++s) acc[r][s] = fma(av[r], bv[s], acc[r][s]);
-        }
-        out(i0, tr, j0, acc);
-    }
-}
-
-// One compact-WY level on LDS operands: W = T (V_top^T X).  V_top is staged in Vs
-// with leading dimension w + 1 (the product reads it across its rows: an odd pitch
-// keeps the lanes of a wave on distinct banks); T is col-major with leading dimension
-// w, in LDS (Ts, copied here while the first product runs) or, when it does not fit,
-// read from global memory (Tg).  W is written over itself through registers (2 x 2
-// tiles, at most two per thread).
+// One compact-WY level on LDS operands: W = T (V_top^T X), on the matrix cores.  V_top
+// is staged in Vs with leading dimension w + 1; X and W have leading dimension w + 1
+// (odd pitches keep a fragment's 16 lanes on distinct banks); T is col-major with
+// leading dimension w, in LDS (Ts, copied here while the first product runs) or, when
+// it does not fit, read from global memory (Tg).  W = T W runs through registers: a
+// wave keeps its (at most kApplyKeep) 16 x 16 tiles across the barrier.
+constexpr int kApplyKeep = 2;
 __device__ void wy_w(const double* Vs, const double* Tg, double* Ts, const double* X, double* W,
                      int w, int c) {
     if (Ts)
         for (int e = threadIdx.x; e < w * w; e += blockDim.x) Ts[e] = Tg[e];
-    const int ldvs = w + 1;
-    tiled<2, 2>(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * ldvs + i]; },
-                [&](int i, int cc) { return X[(int64_t)cc * w + i]; },
-                [&](int l0, int dl, int c0, double (&acc)[2][2]) {
-#pragma unroll
-                    for (int r = 0; r < 2; ++r)
-#pragma unroll
-                        for (int s = 0; s < 2; ++s)
-                            if (l0 + r * dl < w && c0 + s < c) W[(int64_t)(c0 + s) * w + l0 + r * dl] = acc[r][s];
-                });
+    const int ld = w + 1;
+    mfma_small(w, c, w, [&](int l, int i) { return Vs[(int64_t)l * ld + i]; },
+               [&](int i, int cc) { return X[(int64_t)cc * ld + i]; },
+               [&](int l, int cc, double v) { W[(int64_t)cc * ld + l] = v; });
     __syncthreads();
     const double* T = Ts ? Ts : Tg;
-    double keep[2][2][2];
-    int nt = 0;
-    tiled<2, 2>(w, c, w, [&](int i, int l) { return T[(int64_t)l * w + i]; },
-                [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                [&](int, int, int, double (&acc)[2][2]) {
-#pragma unroll
-                    for (int r = 0; r < 2; ++r)
-#pragma unroll
-                        for (int s = 0; s < 2; ++s) keep[nt & 1][r][s] = acc[r][s];
-                    ++nt;
-                });
+    v4d keep[kApplyKeep];
+    mfma_small_keep(w, c, w, [&](int i, int l) { return T[(int64_t)l * w + i]; },
+                    [&](int l, int cc) { return W[(int64_t)cc * ld + l]; }, keep);
     __syncthreads();
-    {
-        const int tr = (w + 1) / 2, tc = (c + 1) / 2;
-        int u = 0;
-        for (int t = threadIdx.x; t < tr * tc; t += blockDim.x, ++u) {
-            const int i0 = t % tr, c0 = (t / tr) * 2;       // the tiles of the product above
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    if (i0 + r * tr < w && c0 + s < c) W[(int64_t)(c0 + s) * w + i0 + r * tr] = keep[u & 1][r][s];
-        }
-    }
+    mfma_small_store(w, c, keep, [&](int i, int cc, double v) { W[(int64_t)cc * ld + i] = v; });
     __syncthreads();
 }
 
-// LDS of the apply (doubles): X (w c) | W (w c) | Vs (max(w (w + 1), kApplySlab ch))
-// | Ts (w w, only when the whole fits).
+// LDS of the apply (doubles): X ((w + 1) c) | W ((w + 1) c) | Vs (max(w (w + 1),
+// kApplySlab ch)) | Ts (w w, only when the whole fits).
 constexpr int kApplySlab = 16;          // reflector / U1 columns per staged slab
+constexpr int kApplyTiles = 5;          // 16 x 16 chunk-output tiles per wave (ch c <= 5 * 16 * 256)
 constexpr size_t kApplyLdsMax = 160 * 1024;
 __host__ __device__ inline size_t apply_buf(int w, int ch) {
     const size_t a = (size_t)w * (w + 1), b = (size_t)kApplySlab * ch;
     return a > b ? a : b;
 }
 __host__ __device__ inline bool apply_stage_t(int w, int ch, int c) {
-    return sizeof(double) * (2 * (size_t)w * c + apply_buf(w, ch) + (size_t)w * w + 32) <= kApplyLdsMax;
+    return sizeof(double) * (2 * (size_t)(w + 1) * c + apply_buf(w, ch) + (size_t)w * w + 32) <= kApplyLdsMax;
 }
 
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict__ ws,
@@ -248,11 +194,11 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                                                              const ChunkRef* __restrict__ chunks,
                                                              int w, int ch, int c) {
     extern __shared__ double sm[];
-    double* X = sm;                                  // w x c (ld w)
-    double* W = X + (int64_t)w * c;                  // w x c
-    double* Vs = W + (int64_t)w * c;                 // staged reflector rows (ld w + 1) / slabs
+    const int ld = w + 1;
+    double* X = sm;                                  // w x c (ld w + 1)
+    double* W = X + (int64_t)ld * c;                 // w x c (ld w + 1)
+    double* Vs = W + (int64_t)ld * c;                // staged reflector rows (ld w + 1) / slabs
     double* Ts = apply_stage_t(w, ch, c) ? Vs + apply_buf(w, ch) : nullptr;   // T (w x w)
-    const int ldvs = w + 1;
     const ChunkRef cr = chunks[blockIdx.x];
     const ApplyTask a = tasks[cr.task];
     const TsqrTask t = tsqr[a.tsqr];
@@ -261,7 +207,10 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     const int64_t S = tsqr_slot_size(w);
 
     const double* Xg = ws + a.x_off;
-    for (int e = tid; e < w * c; e += nth) X[e] = Xg[e];
+    for (int e = tid; e < w * c; e += nth) {
+        const int cc = e / w, i = e - cc * w;
+        X[(int64_t)cc * ld + i] = Xg[e];
+    }
     const int F = tsqr_fanin(w);
     const int levels = tsqr_levels(t.nch, F);
     for (int level = levels; level >= 1; --level) {
@@ -274,26 +223,21 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
         const double* slot = store + S * node_slot(t.nch, F, level, idx);
         const double* V = slot + w * w;              // F w x w, ld F w
         __syncthreads();
-        stage_v(V, F * w, 0, w, w, Vs, ldvs);
+        stage_v(V, F * w, 0, w, w, Vs, ld);
         __syncthreads();
         wy_w(Vs, slot + slot_T(w), Ts, X, W, w, c);
         if (right) {
-            stage_v(V, F * w, pos * w, w, w, Vs, ldvs);
+            stage_v(V, F * w, pos * w, w, w, Vs, ld);
             __syncthreads();
         }
-        // X <- (first child: X, others: 0) - V_child W; each tile reads and writes only itself
-        tiled<2, 2>(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * ldvs + i]; },
-                    [&](int l, int cc) { return W[(int64_t)cc * w + l]; },
-                    [&](int i0, int di, int c0, double (&acc)[2][2]) {
-#pragma unroll
-                        for (int r = 0; r < 2; ++r)
-#pragma unroll
-                            for (int s = 0; s < 2; ++s)
-                                if (i0 + r * di < w && c0 + s < c) {
-                                    double* xp = X + (int64_t)(c0 + s) * w + i0 + r * di;
-                                    *xp = (right ? 0.0 : *xp) - acc[r][s];
-                                }
-                    });
+        // X <- (first child: X, others: 0) - V_child W; each element is read and written
+        // by the lane that computes it
+        mfma_small(w, c, w, [&](int i, int l) { return Vs[(int64_t)l * ld + i]; },
+                   [&](int l, int cc) { return W[(int64_t)cc * ld + l]; },
+                   [&](int i, int cc, double v) {
+                       double* xp = X + (int64_t)cc * ld + i;
+                       *xp = (right ? 0.0 : *xp) - v;
+                   });
     }
     // chunk level: out = [X; 0] - V (T (V_top^T X)) over the chunk rows (+ U1 Tm)
     const int row0 = cr.chunk * ch;
@@ -303,10 +247,10 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     const double* cslot = store + S * node_slot(t.nch, F, 0, cr.chunk);
     const int vtop = rows < w ? rows : w;
     __syncthreads();
-    stage_v(Vc, ldv, 0, vtop, w, Vs, ldvs);
+    stage_v(Vc, ldv, 0, vtop, w, Vs, ld);
     for (int e = tid; e < (w - vtop) * w; e += nth) {     // rows past a short chunk: zero
         const int l = e / (w - vtop), i = vtop + e - l * (w - vtop);
-        Vs[(int64_t)l * ldvs + i] = 0.0;
+        Vs[(int64_t)l * ld + i] = 0.0;
     }
     __syncthreads();
     wy_w(Vs, cslot + slot_T(w), Ts, X, W, w, c);
@@ -321,62 +265,60 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     // One product over K = w + aw: out = [X; 0] - [V_chunk | U1] [W; -Tm].  The left
     // operand streams through LDS in slabs of kApplySlab columns, each loaded by all
     // threads at once (coalesced, one memory round trip per slab); the right operand
-    // is in LDS (W; Tm when it fit).  4 x 4 tiles with interleaved rows.
+    // is in LDS (W; Tm when it fit).  Each wave accumulates its 16 x 16 output tiles
+    // (tile q = wave + nw u) on the matrix cores across the slabs.
     const int K = w + aw;
     double* Bs = Vs;                                        // slab: Bs[kk * rows + i]
-    const int tr = (rows + 3) / 4, tc = (c + 3) / 4, ntiles = tr * tc;
-    for (int base = 0; base < ntiles; base += nth) {
-        const int tile = base + tid;
-        const bool active = tile < ntiles;
-        const int i0 = active ? tile % tr : 0, j0 = active ? (tile / tr) * 4 : 0;
-        double acc[4][4];
+    const int lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (rows + 15) / 16, tn = (c + 15) / 16, ntile = tm * tn;
+    v4d acc[kApplyTiles];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+    for (int u = 0; u < kApplyTiles; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += kApplySlab) {
+        const int ks = min(kApplySlab, K - k0);
+        __syncthreads();                                    // the previous slab is consumed
+        for (int e = tid; e < ks * rows; e += nth) {
+            const int kk = e / rows, i = e - kk * rows, k = k0 + kk;
+            double v;
+            if (k < w) v = (i == k) ? 1.0 : (i > k ? Vc[(int64_t)k * ldv + i] : 0.0);
+            else v = U1[(int64_t)(k - w) * a.add_u_ld + row0 + i];
+            Bs[(int64_t)kk * rows + i] = v;
+        }
+        __syncthreads();
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[r][s] = 0.0;
-        for (int k0 = 0; k0 < K; k0 += kApplySlab) {
-            const int ks = min(kApplySlab, K - k0);
-            __syncthreads();                                // the previous slab is consumed
-            for (int e = tid; e < ks * rows; e += nth) {
-                const int kk = e / rows, i = e - kk * rows, k = k0 + kk;
-                double v;
-                if (k < w) v = (i == k) ? 1.0 : (i > k ? Vc[(int64_t)k * ldv + i] : 0.0);
-                else v = U1[(int64_t)(k - w) * a.add_u_ld + row0 + i];
-                Bs[(int64_t)kk * rows + i] = v;
-            }
-            __syncthreads();
-            if (active) {
-                for (int kk = 0; kk < ks; ++kk) {
-                    const int k = k0 + kk;
-                    double av[4], bv[4];
+        for (int u = 0; u < kApplyTiles; ++u) {
+            const int q = wave + nw * u;
+            if (q >= ntile) break;
+            const int i0 = (q % tm) * 16, j0 = (q / tm) * 16;
+            const int ia = min(i0 + li, rows - 1), jb = min(j0 + li, c - 1);
+            const bool iok = i0 + li < rows, jok = j0 + li < c;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = i0 + r * tr;
-                        av[r] = i < rows ? Bs[(int64_t)kk * rows + i] : 0.0;
-                    }
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int j = j0 + s;
-                        bv[s] = j >= c ? 0.0 : (k < w ? W[(int64_t)j * w + k] : -Tm[(int64_t)j * aw + (k - w)]);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) acc[r][s] = fma(av[r], bv[s], acc[r][s]);
-                }
+            for (int q4 = 0; q4 < kApplySlab / 4; ++q4) {
+                const int kk = 4 * q4 + lk, k = k0 + kk;
+                const bool kok = kk < ks;
+                const int kkc = kok ? kk : 0;
+                const double av = Bs[(int64_t)kkc * rows + ia];
+                const int kb = kok ? k : 0;
+                const double bv = kb < w ? W[(int64_t)jb * ld + kb] : -Tm[(int64_t)jb * aw + (kb - w)];
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((iok && kok) ? av : 0.0,
+                                                              (jok && kok) ? bv : 0.0, acc[u], 0, 0, 0);
             }
         }
-        if (active) {
+    }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+    for (int u = 0; u < kApplyTiles; ++u) {
+        const int q = wave + nw * u;
+        if (q >= ntile) break;
+        const int i0 = (q % tm) * 16, j0 = (q / tm) * 16, j = j0 + li;
+        if (j >= c) continue;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int i = i0 + r * tr, cc = j0 + s;
-                    if (i < rows && cc < c) {
-                        const double x = (i < w) ? X[(int64_t)cc * w + i] : 0.0;
-                        out[(int64_t)cc * a.out_ld + row0 + i] = x - acc[r][s];
-                    }
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + lk + 4 * v;
+            if (i < rows) {
+                const double x = (i < w) ? X[(int64_t)j * ld + i] : 0.0;
+                out[(int64_t)j * a.out_ld + row0 + i] = x - acc[u][v];
+            }
         }
     }
 }
@@ -411,11 +353,14 @@ hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* 
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (2 * (size_t)w * c + apply_buf(w, ch) +
+    const size_t lds = sizeof(double) * (2 * (size_t)(w + 1) * c + apply_buf(w, ch) +
                                          (apply_stage_t(w, ch, c) ? (size_t)w * w : 0) + 32);
     if (lds > kApplyLdsMax) return hipErrorInvalidValue;
-    // wy_w keeps at most two 2 x 2 tiles per thread across its barrier
-    if (w * c > 8 * TSQR_THREADS || ((w + 1) / 2) * ((c + 1) / 2) > 2 * TSQR_THREADS)
+    // wy_w keeps at most kApplyKeep 16 x 16 tiles per wave across its barrier; the chunk
+    // product accumulates at most kApplyTiles per wave
+    const int nwave = TSQR_THREADS / 64;
+    if (((w + 15) / 16) * ((c + 15) / 16) > kApplyKeep * nwave ||
+        ((ch + 15) / 16) * ((c + 15) / 16) > kApplyTiles * nwave)
         return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_apply,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

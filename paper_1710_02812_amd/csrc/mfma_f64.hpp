@@ -115,4 +115,79 @@ __device__ __forceinline__ void mfma_tile_out(int M, int N, int r0, int c0, cons
     }
 }
 
+// A small product whose operands are already on chip: C (M x N) = A (M x K) B (K x N)
+// with a(i, k) and b(k, j) reading LDS (or cached global) elements; 16 x 16 output
+// tiles are dealt to the waves of the work-group (tile t to wave t mod nw), each a
+// chain of K / 4 matrix-core steps with one operand value per lane.  Reads are
+// clamped into range and zeroed outside it (no branch between the loads).
+// out(i, j, v) receives each element (i < M, j < N).
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void mfma_small(int M, int N, int K, FA a, FB b, FO out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+    for (int t = wave; t < tm * tn; t += nw) {
+        const int i0 = (t % tm) * 16, j0 = (t / tm) * 16;
+        const int ia = min(i0 + li, M - 1), jb = min(j0 + li, N - 1);
+        const bool iok = i0 + li < M, jok = j0 + li < N;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk, kc = min(k, K - 1);
+            const double av = a(ia, kc), bv = b(kc, jb);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((iok && k < K) ? av : 0.0,
+                                                       (jok && k < K) ? bv : 0.0, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + lk + 4 * v;
+            if (i < M && jok) out(i, j0 + li, acc[v]);
+        }
+    }
+}
+
+// mfma_small for in-place products: the wave's tiles t = wave + nw u (u < NT; the
+// caller checks that tm tn <= NT nw) are computed into acc, to be written with
+// mfma_small_store after a barrier.
+template <int NT, typename FA, typename FB>
+__device__ __forceinline__ void mfma_small_keep(int M, int N, int K, FA a, FB b, v4d (&acc)[NT]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int t = wave + nw * u;
+        if (t >= tm * tn) continue;
+        const int i0 = (t % tm) * 16, j0 = (t / tm) * 16;
+        const int ia = min(i0 + li, M - 1), jb = min(j0 + li, N - 1);
+        const bool iok = i0 + li < M, jok = j0 + li < N;
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk, kc = min(k, K - 1);
+            const double av = a(ia, kc), bv = b(kc, jb);
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((iok && k < K) ? av : 0.0,
+                                                          (jok && k < K) ? bv : 0.0, acc[u], 0, 0, 0);
+        }
+    }
+}
+template <int NT, typename FO>
+__device__ __forceinline__ void mfma_small_store(int M, int N, const v4d (&acc)[NT], FO out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int t = wave + nw * u;
+        if (t >= tm * tn) continue;
+        const int i0 = (t % tm) * 16, j = (t / tm) * 16 + li;
+        if (j >= N) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + lk + 4 * v;
+            if (i < M) out(i, j, acc[u][v]);
+        }
+    }
+}
+
 }  // namespace hsvd
