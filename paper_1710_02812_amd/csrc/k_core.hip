@@ -9,8 +9,11 @@
 // Columns are orthogonalised pairwise: a sweep visits every pair once through a
 // round-robin tournament, so each round rotates nc/2 disjoint pairs in parallel,
 // one lane group per pair (dot product by shuffle reduction, rotation in LDS).
-// A pair is rotated when |g_a . g_b| > tol * |g_a| |g_b|; sweeps stop after a sweep
-// without rotations.  When the core has more columns than the rank cap, pairs
+// Each sweep starts with a test on the Gram matrix G^T G (matrix cores): the sweeps
+// stop when no pair has |g_a . g_b| > tol * |g_a| |g_b|, and a sweep visits only the
+// pairs the test marked (rotating them above half that threshold, so that a marked
+// pair near it is not declined on a differently rounded dot product).  When the
+// core has more columns than the rank cap, pairs
 // whose two columns both had a norm below 1e-3 of the cap-th largest at the start
 // of the first sweep are skipped in every sweep: the cap drops such columns
 // whatever their mutual rotations, and their rotations against larger columns
@@ -33,6 +36,7 @@
 #include "hsvd_internal.hpp"
 #include "device_common.hpp"
 #include "house_qr.hpp"
+#include "mfma_f64.hpp"
 
 namespace hsvd {
 
@@ -93,6 +97,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     __shared__ int s_nr, s_nc, s_r1, s_r2, s_rot, s_bad, s_rank, s_safe;
     __shared__ unsigned char sflag[128];
     __shared__ unsigned long long s_mask[2];      // sflag as bits (columns 0..63, 64..127)
+    __shared__ unsigned s_pair[128 * 4];          // pair (i < j) still to rotate: bit j % 32 of word 4 i + j / 32
     __shared__ double s_dmax;
 
     if (tid == 0) {
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     bool classify = true;       // the skipped set is fixed at the first sweep of a phase
     int sweep = 0;
   resume:
-    for (; sweep < max_sweeps && !converged; ++sweep) {
+    for (; !converged; ++sweep) {
         for (int j = wave; j < nc; j += nw) {
             double s = 0.0;
             for (int i = lane64; i < nr; i += 64) {
@@ -245,8 +250,51 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             if (lane64 == 0) { s_mask[0] = b0; s_mask[1] = b1; }
         }
         classify = false;
+        for (int e = tid; e < 128 * 4; e += nth) s_pair[e] = 0u;
         __syncthreads();
         const unsigned long long mask0 = s_mask[0], mask1 = s_mask[1];
+        // Convergence test on the Gram matrix G^T G of the current columns (float64
+        // matrix cores, fragments straight from LDS): a pair still needs a rotation when
+        // (g_i . g_j)^2 > tol^2 |g_i|^2 |g_j|^2, the test a round applies.  No such pair
+        // (outside the skipped set): converged, without a sweep that rotates nothing.
+        // Otherwise the sweep visits only the marked pairs; a pair that a later
+        // rotation of the sweep disturbs is caught by the next test.
+        {
+            const int t16 = (nc + 15) / 16, ntile = t16 * (t16 + 1) / 2;
+            const int li = lane64 & 15, lk = lane64 >> 4;
+            for (int tt = wave; tt < ntile; tt += nw) {
+                int ti = 0, rem = tt;                     // upper triangle of tiles, row by row
+                while (rem >= t16 - ti) { rem -= t16 - ti; ++ti; }
+                const int tj = ti + rem;
+                const int ia = min(ti * 16 + li, nc - 1), jb = min(tj * 16 + li, nc - 1);
+                const bool iok = ti * 16 + li < nc, jok = tj * 16 + li < nc;
+                const double* gi = G + (int64_t)ia * ldg;
+                const double* gj = G + (int64_t)jb * ldg;
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+                for (int k0 = 0; k0 < ROWS; k0 += 4) {
+                    const double av = gi[k0 + lk], bv = gj[k0 + lk];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(iok ? av : 0.0, jok ? bv : 0.0, acc, 0, 0, 0);
+                }
+                const int j = tj * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = ti * 16 + lk + 4 * v;
+                    if (i < j && j < nc) {
+                        const bool fi = ((i < 64 ? mask0 >> i : mask1 >> (i - 64)) & 1ull) != 0;
+                        const bool fj = ((j < 64 ? mask0 >> j : mask1 >> (j - 64)) & 1ull) != 0;
+                        const double di = d[i], dj = d[j], c = acc[v];
+                        if (!(fi && fj) && di > 0.0 && dj > 0.0 && c * c > tol2 * di * dj) {
+                            atomicOr(&s_pair[i * 4 + (j >> 5)], 1u << (j & 31));
+                            s_rot = 1;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (s_rot == 0) { converged = true; break; }
+        if (sweep >= max_sweeps) break;
         int a = (grp == 0) ? 0 : grp;
         int b = (grp == 0) ? N - 1 : N - 1 - grp;
         for (int round = 0; round < N - 1; ++round) {
@@ -255,7 +303,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 // no LDS round trip before the loads or after the reduction
                 const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
                 const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
-                const bool valid = (a < nc) && (b < nc) && !(fa && fb);
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                const bool marked = hi < nc && ((s_pair[lo * 4 + (hi >> 5)] >> (hi & 31)) & 1u) != 0;
+                const bool valid = (a < nc) && (b < nc) && !(fa && fb) && marked;
                 double ra[TMAX], rb[TMAX];
                 double c0 = 0.0, c1 = 0.0, da = 0.0, db = 0.0;
                 double* ga = G + (int64_t)(valid ? a : 0) * ldg;
@@ -276,7 +326,10 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 }
                 const double c = group_sum(c0 + c1, gsz);
                 if (valid) {
-                    if (da > 0.0 && db > 0.0 && c * c > tol2 * da * db) {
+                    // a quarter of the test's threshold: the pair was marked on the Gram
+                    // value, and c here (a different rounding, running norms) must not
+                    // decline the rotation of a pair near the threshold
+                    if (da > 0.0 && db > 0.0 && c * c > 0.25 * tol2 * da * db) {
                         // tan of the rotation angle: t = sign(dd) g / (|dd| + sqrt(dd^2 + g^2)),
                         // dd = |g_b|^2 - |g_a|^2, g = 2 g_a.g_b (the smaller root of
                         // t^2 + 2 (dd/g) t - 1 = 0).
@@ -318,7 +371,6 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                         if (gl == 0) {
                             d[a] = da - tt * c;
                             d[b] = db + tt * c;
-                            s_rot = 1;
                         }
                     }
                 }
@@ -328,8 +380,6 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             else { a = (a + 1 == N - 1) ? 0 : a + 1; b = (b + 1 == N - 1) ? 0 : b + 1; }
             __syncthreads();
         }
-        converged = (s_rot == 0);
-        __syncthreads();
     }
     if (tid == 0 && flags) {
         unsigned f = 0;
