@@ -203,6 +203,7 @@ def run_uneven(args, torch):
     t = time.time()
     ws = synth.config3(seed=3, count=args.count, rank_hi=64)
     gen_s = time.time() - t
+    progress(f"uneven: generated {len(ws)} matrices in {gen_s:.1f} s")
     shapes = [(w.A.shape[0], w.A.shape[1], w.p, w.q, w.k) for w in ws]
     As = [torch.tensor(w.A, dtype=torch.float32, device="cuda") for w in ws]
     mk = lambda shp, dt: ([torch.empty((m, k), dtype=dt, device="cuda") for (m, n, _, _, k) in shp],
@@ -220,6 +221,7 @@ def run_uneven(args, torch):
     e1.record()
     torch.cuda.synchronize()
     ms_batched = e0.elapsed_time(e1) / args.steps
+    progress(f"uneven: batched plan {ms_batched:.1f} ms")
     ranks = plan.ranks()
     flags = plan.status()
     plan.set_profiling(True)
@@ -245,6 +247,7 @@ def run_uneven(args, torch):
     e1.record()
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / loop_steps
+    progress(f"uneven: loop of plans {ms_loop:.1f} ms")
     for pl in plans:
         pl.close()
     acc = None
@@ -293,6 +296,10 @@ def run_uneven(args, torch):
     print(json.dumps(res))
 
 
+def progress(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
 def run_learned(args, torch):
     """Learned block rank: train the network on the leaf ranks the plain method picks
     on four seeded field matrices (8192 x 4096, 8 x 4 grid of 1024^2), then time the
@@ -333,6 +340,7 @@ def run_learned(args, torch):
         ranks = run_plan(A, w)[5]
         Ts.append(torch.tensor(np.log2(np.maximum(ranks.reshape(-1), 1)).astype(np.float32), device="cuda"))
         del A
+    progress("learned: training set (4 field matrices) built")
     model = H.RankModel(seed=1)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -342,9 +350,11 @@ def run_learned(args, torch):
     train_ms = e0.elapsed_time(e1)
     prep_s = time.time() - t
 
+    progress(f"learned: network trained ({train_ms:.0f} ms)")
     w = field(4, 32, 8, 1024)
     A = torch.tensor(w.A, dtype=torch.float32, device="cuda")
     ms_plain, U0, S0, Vt0, r0, ranks0, _, st0 = run_plan(A, w, reps=args.steps)
+    progress(f"learned: plain plan {ms_plain:.1f} ms")
     e0.record()
     F = H.block_features(A, w.p, w.q)
     pred = model.predict(F)
@@ -358,6 +368,7 @@ def run_learned(args, torch):
         widths = np.where(fb != 0, np.minimum(2 * widths, 80), widths).astype(np.int32)
         ms_learned, U1, S1, Vt1, r1, ranks1, fb, st1 = run_plan(A, w, widths, reps=args.steps)
         refits += 1
+    progress(f"learned: learned-width plan {ms_learned:.1f} ms ({refits} refits)")
     acc = None
     cpu = None
     from oracle import metrics
