@@ -89,21 +89,31 @@ __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws,
     });
 }
 
-// Y_c = sum_{j < wx} P_j,c with P_j = X + j * c_ld (each ld x_ld), width wy.
+// Y_c = sum_{j < wx} P_j,c with P_j = X + j * c_ld (each ld x_ld), width wy; grid:
+// chunk x column, one thread per row (the partials summed in order j = 0, 1, ...).
 __global__ __launch_bounds__(256) void k_thin_sum(double* __restrict__ ws,
                                                   const ThinTask* __restrict__ tasks,
                                                   const ChunkRef* __restrict__ chunks, int chh) {
     const ChunkRef cr = chunks[blockIdx.x];
     const ThinTask t = tasks[cr.task];
+    const int c = blockIdx.y;
+    if (c >= t.wy) return;
     const int row0 = cr.chunk * chh;
     const int rows = min(chh, t.h - row0);
-    const double* X = ws + t.x_off;
-    double* Y = ws + t.y_off;
-    for (int e = threadIdx.x; e < rows * t.wy; e += blockDim.x) {
-        const int c = e / rows, r = e - c * rows;
+    const double* X = ws + t.x_off + (int64_t)c * t.x_ld + row0;
+    double* Y = ws + t.y_off + (int64_t)c * t.y_ld + row0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
         double s = 0.0;
-        for (int j = 0; j < t.wx; ++j) s += X[(int64_t)j * t.c_ld + (int64_t)c * t.x_ld + row0 + r];
-        Y[(int64_t)c * t.y_ld + row0 + r] = s;
+        int j = 0;
+        for (; j + 4 <= t.wx; j += 4) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = X[(int64_t)(j + u) * t.c_ld + r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += v[u];
+        }
+        for (; j < t.wx; ++j) s += X[(int64_t)j * t.c_ld + r];
+        Y[r] = s;
     }
 }
 
@@ -131,7 +141,7 @@ hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks
 hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
                            int chh, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_sum, dim3(nchunks), dim3(256), 0, s, ws, t, chunks, chh);
+    hipLaunchKernelGGL(k_thin_sum, dim3(nchunks, 128), dim3(256), 0, s, ws, t, chunks, chh);
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 // Wave w owns the 32 x 32 quarter (rows 32 (w & 1), columns 32 (w >> 1)) as 2 x 2
 // blocks of 16 x 16.  Per 4-deep step lane l holds A[i = l % 16][k = l / 16] and
 // B[k = l / 16][j = l % 16]; accumulator element v holds C[i = l / 16 + 4 v][j = l % 16].
-// Slabs of 32 along K are staged through LDS in the order they are read from memory
+// Slabs of MF_K along K are staged through LDS in the order they are read from memory
 // (conflict-free stores) while the next slab is fetched into registers.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -20,7 +20,7 @@ namespace hsvd {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int MF_T = 64;        // tile rows and columns
-constexpr int MF_K = 32;        // reduction slab
+constexpr int MF_K = 64;        // reduction slab
 
 // LDS doubles of the staging buffers: A slab then B slab
 template <int OP>
@@ -37,33 +37,34 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    TA pa[8];
-    double pb[8];
+    constexpr int NE = MF_T * MF_K / 256;                      // slab elements per thread
+    TA pa[NE];
+    double pb[NE];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
             if (OP == 0) {
-                const int r = e >> 5, kk = e & 31;            // A(r0 + r, k0 + kk)
+                const int r = e / MF_K, kk = e % MF_K;        // A(r0 + r, k0 + kk)
                 const int gr = r0 + r, gk = k0 + kk;
                 pa[u] = (gr < M && gk < K) ? A[(int64_t)gr * lda + gk] : (TA)0;
             } else {
-                const int kk = e >> 6, c = e & 63;            // A(r0 + c, k0 + kk)
+                const int kk = e / MF_T, c = e % MF_T;        // A(r0 + c, k0 + kk)
                 const int gk = k0 + kk, gc = r0 + c;
                 pa[u] = (gk < K && gc < M) ? A[(int64_t)gk * lda + gc] : (TA)0;
             }
-            const int bc = e >> 5, bk = e & 31;                // B(k0 + bk, c0 + bc)
+            const int bc = e / MF_K, bk = e % MF_K;            // B(k0 + bk, c0 + bc)
             const int gbc = c0 + bc, gbk = k0 + bk;
             pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : 0.0;
         }
     };
     auto stage = [&]() {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
-            if (OP == 0) As[(e >> 5) * AP + (e & 31)] = (double)pa[u];
-            else As[(e >> 6) * AP + (e & 63)] = (double)pa[u];
-            Bs[(e >> 5) * BP + (e & 31)] = pb[u];
+            if (OP == 0) As[(e / MF_K) * AP + (e % MF_K)] = (double)pa[u];
+            else As[(e / MF_T) * AP + (e % MF_T)] = (double)pa[u];
+            Bs[(e / MF_K) * BP + (e % MF_K)] = pb[u];
         }
     };
 #pragma unroll
