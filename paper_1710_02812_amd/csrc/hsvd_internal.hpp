@@ -64,7 +64,7 @@ __host__ __device__ inline int tsqr_levels(int nch, int F) {
 // Per-node storage: R (w*w) | V (F w * w, ld F w) | tau (w) | T (w*w).
 __host__ __device__ inline int64_t tsqr_slot_size(int w) { return (int64_t)(tsqr_fanin(w) + 2) * w * w + w; }
 // Rows per chunk: the factor kernel holds a chunk in registers: 16 lanes x 16 rows
-// per column (w <= 64) or 8 lanes x 20 rows (w <= 80).
+// per column (w <= 64) or 16 lanes x 10 rows (w <= 80).
 inline int tsqr_chunk_rows(int w) { return w <= 64 ? 256 : 160; }
 
 // out (h x c) = Q * X  (+ U1 * T when add_u_off >= 0), Q the explicit thin factor of a

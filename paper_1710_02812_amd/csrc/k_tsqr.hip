@@ -43,16 +43,16 @@ __device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l
     return i == l ? 1.0 : (i > l ? A[(int64_t)l * ld + i] : 0.0);
 }
 
-// Factor work-groups: CPL = 2 columns per lane group on 512 threads (each lane
-// reads a pivot value once for both of its columns; the pivot stays in registers;
-// panels above 64 columns hold 2 x 20 registers per lane and re-read the pivot).
+// Factor work-groups: CPL = 2 columns per 16-lane group (each lane reads a pivot
+// value once for both of its columns and keeps it in registers): 512 threads x 16
+// rows per lane for panels up to 64 columns (256-row chunks), 768 threads x 10 rows
+// for panels up to 80 (160-row chunks, 96 columns of capacity).
 constexpr int TSQR_CPL = 2;
-constexpr int TSQR_FTHREADS = 1024 / TSQR_CPL;
-template <int LANES, int RMAX>
-using TsqrQR = HouseQR<LANES, RMAX, true, (RMAX <= 16 ? RMAX : 8), TSQR_CPL, TSQR_FTHREADS>;
+template <int LANES, int RMAX, int NTHR>
+using TsqrQR = HouseQR<LANES, RMAX, true, RMAX, TSQR_CPL, NTHR>;
 
-template <int LANES, int RMAX>
-__global__ __launch_bounds__(TSQR_FTHREADS) void k_tsqr_factor(double* __restrict__ ws,
+template <int LANES, int RMAX, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
                                                               const TsqrTask* __restrict__ tasks,
                                                               const ChunkRef* __restrict__ chunks,
@@ -63,8 +63,8 @@ __global__ __launch_bounds__(TSQR_FTHREADS) void k_tsqr_factor(double* __restric
     double* z = tau + w;                             // 2w
     double* vbuf = z + 2 * w;                        // 2 * LANES * RMAX
     __shared__ int s_go;
-    TsqrQR<LANES, RMAX> q;
-    constexpr int NG = TsqrQR<LANES, RMAX>::NG;
+    TsqrQR<LANES, RMAX, NTHR> q;
+    constexpr int NG = TsqrQR<LANES, RMAX, NTHR>::NG;
 
     const ChunkRef cr = chunks[blockIdx.x];
     const TsqrTask t = tasks[cr.task];
@@ -323,15 +323,15 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     }
 }
 
-template <int LANES, int RMAX>
+template <int LANES, int RMAX, int NTHR>
 static hipError_t launch_factor_t(double* ws, int* iws, const TsqrTask* tasks,
                                   const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s) {
-    if (w > TsqrQR<LANES, RMAX>::WMAX) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * (TsqrQR<LANES, RMAX>::lds_doubles(w) + 32);
-    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX>,
+    if (w > TsqrQR<LANES, RMAX, NTHR>::WMAX) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * (TsqrQR<LANES, RMAX, NTHR>::lds_doubles(w) + 32);
+    hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX, NTHR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX>), dim3(nchunks), dim3(TSQR_FTHREADS), lds, s, ws,
+    hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX, NTHR>), dim3(nchunks), dim3(NTHR), lds, s, ws,
                        iws, tasks, chunks, w, ch);
     return hipGetLastError();
 }
@@ -343,10 +343,10 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const
     // a chunk and a stacked pair of R factors must fit the register block
     if (w <= 64) {
         if (ch > 16 * 16 || tsqr_fanin(w) * w > 16 * 16) return hipErrorInvalidValue;
-        return launch_factor_t<16, 16>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+        return launch_factor_t<16, 16, 512>(ws, iws, tasks, chunks, nchunks, w, ch, s);
     }
-    if (ch > 8 * 20 || tsqr_fanin(w) * w > 8 * 20) return hipErrorInvalidValue;
-    return launch_factor_t<8, 20>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+    if (ch > 16 * 10 || tsqr_fanin(w) * w > 16 * 10) return hipErrorInvalidValue;
+    return launch_factor_t<16, 10, 768>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
 hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
