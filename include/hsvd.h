@@ -169,7 +169,8 @@ typedef enum {
     HSVD_LAUNCH_GEMM_AX_BF16 = 10, /* Y = A_blk X on the bfloat16 matrix cores           */
     HSVD_LAUNCH_GEMM_ATX_BF16 = 11,/* Y = A_blk^T X on the bfloat16 matrix cores         */
     HSVD_LAUNCH_ENERGY = 12,       /* squared Frobenius norms of the blocks              */
-    HSVD_LAUNCH_FEATURES = 13      /* block features of a feature plan                   */
+    HSVD_LAUNCH_FEATURES = 13,     /* block features of a feature plan                   */
+    HSVD_LAUNCH_CHOLQR = 14        /* Cholesky QR passes (fast path of the panel QRs)    */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

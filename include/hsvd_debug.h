@@ -60,6 +60,19 @@ hsvd_status hsvd_debug_plan_check_batched(int32_t count, const int64_t* m, const
 hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
                             double* R, hipStream_t stream);
 
+/* The tall-skinny QR as the merge, re-projection and projection panels take it
+ * (w <= 64): two Cholesky QR passes (R1 = chol(P^T P), Q1 = P R1^-1, then the same on
+ * Q1; R = R2 R1, Q = Q1 R2^-1), with the Householder TSQR in their place when the
+ * first pass meets a pivot below 1e-10 of its column's squared norm or the second
+ * finds ||Q1^T Q1 - I||_F > 1/4.  P (batch x h x w, each col-major with ld h, device)
+ * is not modified; Q (same layout) and R (batch x w x w, col-major, upper triangular)
+ * are written with P = Q R.  Exactly zero columns of P give zero rows of R and zero
+ * columns of Q on the Cholesky path.  fell_back (host, batch ints) receives 1 where
+ * the Householder kernels ran, else 0.  Errors: HSVD_ERR_INVALID for null pointers or
+ * sizes out of range, HSVD_ERR_ALLOC, HSVD_ERR_HIP.                                   */
+hsvd_status hsvd_debug_cholqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
+                              double* R, int32_t* fell_back, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,7 +53,7 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
     return fail(HSVD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY,
+enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY, ST_CQ1, ST_CQ2,
                  ST_FEAT };
 
 struct Stage {
@@ -75,7 +75,6 @@ int pow2floor(int x) {
 
 int tsqr_chunk(int w, int /*c*/) { return tsqr_chunk_rows(w); }
 
-constexpr int THIN_CH = 256;
 
 }  // namespace
 
@@ -161,10 +160,14 @@ struct Node {            // a factor node: panel (h x W, ld), sigma (W), rank sl
 struct TsqrBuild {
     std::vector<TsqrTask> tasks;
     std::vector<ChunkRef> chunks;
+    bool cholqr = false;     // some task takes the Cholesky QR fast path
 };
 
-// Adds TSQR bookkeeping for a panel; returns index into tb.tasks.
-int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w, int ch) {
+// Adds TSQR bookkeeping for a panel; returns index into tb.tasks.  cholqr: the panel
+// (expected well-conditioned) first tries two Cholesky QR passes, the Householder
+// kernels running only if they fall back (panels up to 64 columns).
+int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w, int ch,
+             bool cholqr = false) {
     TsqrTask t{};
     t.p_off = panel;
     t.h = h;
@@ -176,12 +179,44 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
     t.store_off = P.alloc((int64_t)nodes * tsqr_slot_size(w));
     t.cnt_off = P.ialloc(nodes);
     t.r_out = P.alloc((int64_t)w * w);
+    if (cholqr && w <= 64 && ch == tsqr_chunk_rows(w)) {
+        t.cq_off = P.alloc(cq_size(w, t.nch, h));
+        t.cq_flag = P.ialloc(1);
+        t.cq_cnt = P.ialloc(std::max(1, cq_nodes(t.nch)));
+        tb.cholqr = true;
+    }
     for (int c = 0; c < t.nch; ++c) tb.chunks.push_back({(int)tb.tasks.size(), c});
     tb.tasks.push_back(t);
     return (int)tb.tasks.size() - 1;
 }
 
+void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks);
+
 void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
+    if (tb.cholqr) {
+        // pass 1 (G = P^T P, R1, M1 = R1^-1), Q1 = P M1, pass 2 (Q1^T Q1, R = R2 R1, M2)
+        Stage c{};
+        c.kind = ST_CQ1;
+        c.n = (int)tb.chunks.size();
+        c.w = w;
+        c.ch = ch;
+        c.tasks_off = P.put(tb.tasks);
+        c.refs_off = P.put(tb.chunks);
+        P.stages.push_back(c);
+        std::vector<ThinTask> q1;
+        for (const TsqrTask& t : tb.tasks) {
+            if (t.cq_flag < 0) continue;
+            ThinTask x{};
+            x.x_off = t.p_off; x.x_ld = t.p_ld;
+            x.c_off = t.cq_off + (int64_t)w * w; x.c_ld = w;                    // M1
+            x.y_off = t.cq_off + cq_q1(w, t.nch); x.y_ld = t.h;                 // Q1
+            x.h = t.h; x.wx = w; x.wy = w; x.accumulate = 0; x.cond = t.cq_flag;
+            q1.push_back(x);
+        }
+        if (!q1.empty()) push_thin(P, ST_NN, q1);
+        c.kind = ST_CQ2;
+        P.stages.push_back(c);
+    }
     Stage s{};
     s.kind = ST_TSQR_F;
     s.n = (int)tb.chunks.size();
@@ -195,6 +230,38 @@ void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
 // Apply stage for tasks applying the factors of `tb` (one ApplyTask per tsqr task, in order).
 void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<ApplyTask>& at,
                      int w, int ch, int c) {
+    if (tb.cholqr) {
+        // out = Q X + U1 T with Q = Q1 M2: C = M2 X (w x c), out = Q1 C, out += U1 T
+        std::vector<ThinTask> n1, n2, n3;
+        for (const ApplyTask& a : at) {
+            const TsqrTask& t = tb.tasks[a.tsqr];
+            if (t.cq_flag < 0) continue;
+            const int64_t C = P.alloc((int64_t)w * c);
+            ThinTask x{};
+            x.x_off = t.cq_off + 2 * (int64_t)w * w; x.x_ld = w;                  // M2
+            x.c_off = a.x_off; x.c_ld = w;
+            x.y_off = C; x.y_ld = w;
+            x.h = w; x.wx = w; x.wy = c; x.accumulate = 0; x.cond = t.cq_flag;
+            n1.push_back(x);
+            ThinTask y{};
+            y.x_off = t.cq_off + cq_q1(w, t.nch); y.x_ld = t.h;                   // Q1
+            y.c_off = C; y.c_ld = w;
+            y.y_off = a.out_off; y.y_ld = a.out_ld;
+            y.h = t.h; y.wx = w; y.wy = c; y.accumulate = 0; y.cond = t.cq_flag;
+            n2.push_back(y);
+            if (a.add_u_off >= 0) {
+                ThinTask z{};
+                z.x_off = a.add_u_off; z.x_ld = a.add_u_ld;
+                z.c_off = a.add_t_off; z.c_ld = a.add_w;
+                z.y_off = a.out_off; z.y_ld = a.out_ld;
+                z.h = t.h; z.wx = a.add_w; z.wy = c; z.accumulate = 1; z.cond = t.cq_flag;
+                n3.push_back(z);
+            }
+        }
+        if (!n1.empty()) push_thin(P, ST_NN, n1);
+        if (!n2.empty()) push_thin(P, ST_NN, n2);
+        if (!n3.empty()) push_thin(P, ST_NN, n3);
+    }
     Stage s{};
     s.kind = ST_TSQR_A;
     s.n = (int)tb.chunks.size();
@@ -333,7 +400,7 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         sb2.c_off = C2;
         sub2.push_back(sb2);
 
-        const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq);
+        const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq, true);
         Node o{};
         o.mat = a.mat;
         o.h = h;
@@ -629,7 +696,7 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
     push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16);
     for (size_t i = 0; i < roots.size(); ++i) {
         const int n = (int)P.mats[roots[i].mat].n;
-        add_tsqr(P, tb, Zs[i], n, n, W, ch);
+        add_tsqr(P, tb, Zs[i], n, n, W, ch, true);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<CoreTask> cores;
@@ -712,7 +779,7 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
     TsqrBuild tb;
     for (size_t mi = 0; mi < vs.size(); ++mi) {
         const int m = (int)P.mats[mi].m;
-        add_tsqr(P, tb, Ys[mi], m, m, W, ch);
+        add_tsqr(P, tb, Ys[mi], m, m, W, ch, true);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<Factors> fs(vs.size());
@@ -799,7 +866,7 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     TsqrBuild tb;
     for (size_t mi = 0; mi < in.size(); ++mi) {
         const int n = (int)P.mats[mi].n;
-        add_tsqr(P, tb, Zs[mi], n, n, W, ch);
+        add_tsqr(P, tb, Zs[mi], n, n, W, ch, true);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<Factors> fs(in.size());
@@ -1010,9 +1077,11 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 if (s.bf16 && P.opt.precision == HSVD_FP64) return "bf16 pass on a float64 plan";
                 break;
             }
+            case ST_CQ1:
             case ST_TSQR_F:
+            case ST_CQ2:
             case ST_TSQR_A: {
-                const TsqrTask* T = (const TsqrTask*)(b + (s.kind == ST_TSQR_F ? s.tasks_off : s.tsqr_off));
+                const TsqrTask* T = (const TsqrTask*)(b + (s.kind != ST_TSQR_A ? s.tasks_off : s.tsqr_off));
                 const ChunkRef* R = (const ChunkRef*)(b + s.refs_off);
                 int ntask = 0;
                 for (int i = 0; i < s.n; ++i) ntask = std::max(ntask, R[i].task + 1);
@@ -1026,6 +1095,14 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * tsqr_slot_size(s.w) - 1, WS)) return msg;
                     if (!span("tsqr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
                     if (!span("tsqr counters", t.cnt_off, t.cnt_off + nodes - 1, IW)) return msg;
+                    if (t.cq_flag >= 0) {
+                        if (s.w > 64 || s.ch > 256) return "cholqr geometry";
+                        if (!span("cholqr scratch", t.cq_off, t.cq_off + cq_size(s.w, t.nch, t.h) - 1, WS)) return msg;
+                        if (t.cq_flag >= IW || t.cq_cnt < 0 || t.cq_cnt + std::max(1, cq_nodes(t.nch)) > IW)
+                            return "cholqr slots";
+                    } else if (s.kind == ST_CQ1 || s.kind == ST_CQ2) {
+                        continue;                                   // no fast path: the passes skip it
+                    }
                     if (s.kind == ST_TSQR_A) {
                         const ApplyTask& a = ((const ApplyTask*)(b + s.tasks_off))[i];
                         if (a.tsqr != i) return "apply/tsqr order";
@@ -1065,6 +1142,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         if (!panel("reduce C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
                         if (t.acc_off >= 0 && !panel("reduce acc", t.acc_off, t.c_ld, t.wx, t.wy)) return msg;
                     } else if (s.kind == ST_NN) {
+                        if (t.cond >= IW) return "nn condition slot";
                         if (!panel("nn X", t.x_off, t.x_ld, t.h, t.wx)) return msg;
                         if (!panel("nn C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
                         if (!panel("nn Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
@@ -1153,12 +1231,17 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
                 e = launch_gemm(s.op, fp32, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
                                 (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             break;
+        case ST_CQ1:
+        case ST_CQ2:
+            e = launch_cholqr(s.kind == ST_CQ1 ? 1 : 2, P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
+                              (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
+            break;
         case ST_TSQR_F:
             e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
                                    (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
             break;
         case ST_TSQR_A:
-            e = launch_tsqr_apply(P.ws, (const TsqrTask*)(b + s.tsqr_off),
+            e = launch_tsqr_apply(P.ws, P.iws, (const TsqrTask*)(b + s.tsqr_off),
                                   (const ApplyTask*)(b + s.tasks_off),
                                   (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, s.c, st);
             break;
@@ -1170,7 +1253,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, s.w, st);
             break;
         case ST_NN:
-            e = launch_thin_nn(P.ws, (const ThinTask*)(b + s.tasks_off),
+            e = launch_thin_nn(P.ws, P.iws, (const ThinTask*)(b + s.tasks_off),
                                (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
             break;
         case ST_SUM:
@@ -1464,6 +1547,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                                   : (s.op == 0 ? HSVD_LAUNCH_GEMM_AX : HSVD_LAUNCH_GEMM_ATX);
                     break;
                 case ST_TSQR_F: kind = HSVD_LAUNCH_TSQR_FACTOR; break;
+                case ST_CQ1: case ST_CQ2: kind = HSVD_LAUNCH_CHOLQR; break;
                 case ST_TSQR_A: kind = HSVD_LAUNCH_TSQR_APPLY; break;
                 case ST_GRAM: kind = HSVD_LAUNCH_GRAM; break;
                 case ST_REDUCE: kind = HSVD_LAUNCH_REDUCE; break;
@@ -1518,9 +1602,23 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     int ntask = 0;
                     for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
                     for (int t = 0; t < ntask; ++t) {
+                        if (T[t].cq_flag >= 0) continue;          // counted with the Cholesky passes
                         const double h = T[t].h, w = s.w, mn = std::min(h, w), mx = std::max(h, w);
                         f += 2.0 * mx * mn * mn - 2.0 * mn * mn * mn / 3.0;
                         by += 2.0 * h * w * e8;
+                    }
+                    break;
+                }
+                case ST_CQ1: case ST_CQ2: {                       // Gram of the panel + w^3 / 3
+                    const ChunkRef* C = (const ChunkRef*)(b + s.refs_off);
+                    const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
+                    int ntask = 0;
+                    for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
+                    for (int t = 0; t < ntask; ++t) {
+                        if (T[t].cq_flag < 0) continue;
+                        const double h = T[t].h, w = s.w;
+                        f += 2.0 * h * w * w + w * w * w;
+                        by += (h * w + 2.0 * w * w) * e8;
                     }
                     break;
                 }
@@ -1531,6 +1629,7 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     int ntask = 0;
                     for (int t = 0; t < s.n; ++t) ntask = std::max(ntask, C[t].task + 1);
                     for (int t = 0; t < ntask; ++t) {
+                        if (T[A[t].tsqr].cq_flag >= 0) continue;  // counted with the thin products
                         const double h = T[A[t].tsqr].h, w = s.w, c = s.c;
                         f += 4.0 * h * w * c;
                         by += (h * w + h * c) * e8;

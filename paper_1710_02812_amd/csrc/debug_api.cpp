@@ -196,10 +196,117 @@ extern "C" hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h
     if (e == hipSuccess) e = hipMemcpyAsync(da, at.data(), sizeof(ApplyTask) * batch, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dc, cr.data(), sizeof(ChunkRef) * cr.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_tsqr_factor(ws, iws, dt, dc, (int)cr.size(), w, ch, stream);
-    if (e == hipSuccess) e = launch_tsqr_apply(ws, dt, da, dc, (int)cr.size(), w, ch, w, stream);
+    if (e == hipSuccess) e = launch_tsqr_apply(ws, iws, dt, da, dc, (int)cr.size(), w, ch, w, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(Q, ws + offQ, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(R, ws + offR, sizeof(double) * batch * w * w, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_tsqr: ") + hipGetErrorString(e));
+    return HSVD_OK;
+}
+
+extern "C" hsvd_status hsvd_debug_cholqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
+                                         double* R, int32_t* fell_back, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    if (!P || !Q || !R || !fell_back || batch < 1 || h < 1 || w < 1 || w > 64 || h > (1 << 26))
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_cholqr: bad argument");
+    Scratch sc;
+    const int ch = tsqr_chunk_rows(w);
+    const int nch = (int)((h + ch - 1) / ch);
+    const int nodes = tsqr_nodes(nch, tsqr_fanin(w));
+    const int cnodes = std::max(1, cq_nodes(nch));
+    const int nthin = (int)((h + THIN_CH - 1) / THIN_CH);
+    const int64_t hw = h * w, ww = (int64_t)w * w, slot = tsqr_slot_size(w), cqs = cq_size(w, nch, (int)h);
+    const int64_t offP = 0, offI = offP + batch * hw, offQ = offI + ww, offS = offQ + batch * hw,
+                  offR = offS + (int64_t)batch * nodes * slot, offCQ = offR + batch * ww,
+                  offC = offCQ + batch * cqs, tot = offC + batch * ww;
+    const int iper = nodes + 1 + cnodes;
+    double* ws = sc.get<double>(tot);
+    int* iws = sc.get<int>((size_t)batch * iper);
+    TsqrTask* dt = sc.get<TsqrTask>(batch);
+    ApplyTask* da = sc.get<ApplyTask>(batch);
+    ChunkRef* dc = sc.get<ChunkRef>((size_t)batch * nch);
+    ThinTask* dn = sc.get<ThinTask>(3 * (size_t)batch);
+    ChunkRef* dnc = sc.get<ChunkRef>((size_t)batch * (2 * nthin + 1));
+    if (!ws || !iws || !dt || !da || !dc || !dn || !dnc) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    std::vector<TsqrTask> tt(batch);
+    std::vector<ApplyTask> at(batch);
+    std::vector<ThinTask> nn(3 * (size_t)batch);           // Q1 = P M1 | C = M2 I | Q = Q1 C
+    std::vector<ChunkRef> cr, ncr;
+    for (int b = 0; b < batch; ++b) {
+        TsqrTask t{};
+        t.p_off = offP + b * hw;
+        t.store_off = offS + (int64_t)b * nodes * slot;
+        t.r_out = offR + b * ww;
+        t.h = (int)h;
+        t.p_ld = (int)h;
+        t.nch = nch;
+        t.chunk0 = b * nch;
+        t.cnt_off = b * iper;
+        t.levels = tsqr_levels(nch, tsqr_fanin(w));
+        t.cq_off = offCQ + b * cqs;
+        t.cq_flag = b * iper + nodes;
+        t.cq_cnt = t.cq_flag + 1;
+        tt[b] = t;
+        ApplyTask a{};
+        a.tsqr = b;
+        a.x_off = offI;
+        a.out_off = offQ + b * hw;
+        a.out_ld = (int)h;
+        a.add_u_off = -1;
+        at[b] = a;
+        for (int c = 0; c < nch; ++c) cr.push_back({b, c});
+        ThinTask& x = nn[b];                                // Q1 = P M1
+        x.x_off = t.p_off; x.x_ld = (int)h;
+        x.c_off = t.cq_off + ww; x.c_ld = w;
+        x.y_off = t.cq_off + cq_q1(w, nch); x.y_ld = (int)h;
+        x.h = (int)h; x.wx = w; x.wy = w; x.cond = t.cq_flag;
+        ThinTask& y = nn[batch + b];                        // C = M2 I
+        y.x_off = t.cq_off + 2 * ww; y.x_ld = w;
+        y.c_off = offI; y.c_ld = w;
+        y.y_off = offC + b * ww; y.y_ld = w;
+        y.h = w; y.wx = w; y.wy = w; y.cond = t.cq_flag;
+        ThinTask& z = nn[2 * batch + b];                    // Q = Q1 C
+        z.x_off = x.y_off; z.x_ld = (int)h;
+        z.c_off = y.y_off; z.c_ld = w;
+        z.y_off = a.out_off; z.y_ld = (int)h;
+        z.h = (int)h; z.wx = w; z.wy = w; z.cond = t.cq_flag;
+    }
+    // chunk lists of the three products: [Q1 | C | Q], each task's chunks in order
+    int n0 = 0, n1 = 0, n2 = 0;
+    for (int part = 0; part < 3; ++part)
+        for (int b = 0; b < batch; ++b) {
+            ThinTask& x = nn[part * batch + b];
+            x.nch = (x.h + THIN_CH - 1) / THIN_CH;
+            x.chunk0 = (int)ncr.size();
+            for (int c = 0; c < x.nch; ++c) ncr.push_back({b, c});
+            (part == 0 ? n0 : part == 1 ? n1 : n2) += x.nch;
+        }
+    for (int part = 0; part < 3; ++part)
+        for (int b = 0; b < batch; ++b) nn[part * batch + b].chunk0 -= (part == 0 ? 0 : part == 1 ? n0 : n0 + n1);
+    std::vector<double> I((size_t)ww, 0.0);
+    for (int i = 0; i < w; ++i) I[(size_t)i * w + i] = 1.0;
+    hipError_t e = hipMemcpyAsync(ws + offP, P, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + offI, I.data(), sizeof(double) * ww, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(iws, 0, sizeof(int) * batch * iper, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tt.data(), sizeof(TsqrTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(da, at.data(), sizeof(ApplyTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, cr.data(), sizeof(ChunkRef) * cr.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dn, nn.data(), sizeof(ThinTask) * nn.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dnc, ncr.data(), sizeof(ChunkRef) * ncr.size(), hipMemcpyHostToDevice, stream);
+    const int nc = (int)cr.size();
+    if (e == hipSuccess) e = launch_cholqr(1, ws, iws, dt, dc, nc, w, ch, stream);
+    if (e == hipSuccess) e = launch_thin_nn(ws, iws, dn, dnc, n0, THIN_CH, stream);
+    if (e == hipSuccess) e = launch_cholqr(2, ws, iws, dt, dc, nc, w, ch, stream);
+    if (e == hipSuccess) e = launch_tsqr_factor(ws, iws, dt, dc, nc, w, ch, stream);
+    if (e == hipSuccess) e = launch_thin_nn(ws, iws, dn + batch, dnc + n0, n1, THIN_CH, stream);
+    if (e == hipSuccess) e = launch_thin_nn(ws, iws, dn + 2 * batch, dnc + n0 + n1, n2, THIN_CH, stream);
+    if (e == hipSuccess) e = launch_tsqr_apply(ws, iws, dt, da, dc, nc, w, ch, w, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Q, ws + offQ, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(R, ws + offR, sizeof(double) * batch * ww, hipMemcpyDeviceToDevice, stream);
+    std::vector<int> flags((size_t)batch * iper);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), iws, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_cholqr: ") + hipGetErrorString(e));
+    for (int b = 0; b < batch; ++b) fell_back[b] = flags[(size_t)b * iper + nodes];
     return HSVD_OK;
 }

@@ -40,8 +40,15 @@ struct TsqrTask {
     int32_t chunk0;       // first flat chunk index of this task
     int32_t cnt_off;      // int arena: one counter per tree node
     int32_t levels;       // tree levels above the chunks
+    // Cholesky QR fast path (cq_flag < 0: none): scratch (cq_size doubles), the int
+    // slot of its outcome (0: the Cholesky outputs stand, 1: the Householder kernels
+    // run) and the first of its cq_nodes arrival counters (one when nch = 1)
+    int64_t cq_off = 0;
+    int32_t cq_flag = -1, cq_cnt = -1;
 };
 struct ChunkRef { int32_t task; int32_t chunk; };
+
+constexpr int THIN_CH = 256;    // rows per chunk of the thin-panel products
 
 constexpr int kTsqrMaxW = 80;
 // Fan-in F of the R-factor tree: up to F stacked w x w factors are merged by one
@@ -90,8 +97,8 @@ struct ThinTask {
     int32_t h, x_ld, y_ld, c_ld;
     int32_t wx, wy;       // widths
     int32_t nch, chunk0;
-    int32_t accumulate;   // reduce: 0 -> Cacc = C, 1 -> Cacc += C; nn: 0 set, 1 add
-    int32_t pad;
+    int32_t accumulate;   // reduce: 0 -> Cacc = C, 1 -> Cacc += C; nn: 0 set, 1 add, 2 sub
+    int32_t cond = -1;    // nn: runs only while iws[cond] == 0 (a Cholesky QR outcome), or always
 };
 
 // ---------------------------------------------------------------- Jacobi cores
@@ -158,17 +165,30 @@ hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
                               const ChunkRef* chunks, int nchunks, int w, int ch,
                               hipStream_t s);
-hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
+hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s);
 hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks,
                             int nchunks, int chh, hipStream_t s);
 // maxsz: the largest wx * wy over the tasks (grid: task x element slices of 256)
 hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int maxsz, hipStream_t s);
-hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks,
-                           int nchunks, int chh, hipStream_t s);
-hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks,
+hipError_t launch_thin_nn(double* ws, const int* iws, const ThinTask* t, const ChunkRef* chunks,
                           int nchunks, int chh, hipStream_t s);
+// Cholesky QR pass 1 or 2 over the chunks of TsqrTasks with cq_flag >= 0 (w <= 64)
+hipError_t launch_cholqr(int pass, double* ws, int* iws, const TsqrTask* tasks, const ChunkRef* chunks,
+                         int nchunks, int w, int ch, hipStream_t s);
+// The chunks' partial Grams are summed up a tree of fan-in kCqFan: cq_nodes counts its
+// nodes above the chunks (one arrival counter each; each holds a stored w x w sum).
+constexpr int kCqFan = 8;
+__host__ __device__ inline int cq_up(int n) { return (n + kCqFan - 1) / kCqFan; }
+__host__ __device__ inline int cq_nodes(int nch) {
+    int s = 0;
+    for (int n = nch; n > 1; n = cq_up(n)) s += cq_up(n);
+    return s;
+}
+// Scratch of a panel: R1 | M1 | M2 | chunk parts (nch w^2) | node sums | Q1 (h x w, ld h)
+__host__ __device__ inline int64_t cq_q1(int w, int nch) { return (int64_t)(3 + nch + cq_nodes(nch)) * w * w; }
+__host__ __device__ inline int64_t cq_size(int w, int nch, int h) { return cq_q1(w, nch) + (int64_t)h * w; }
 hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks,
                            int nchunks, int chh, hipStream_t s);
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,

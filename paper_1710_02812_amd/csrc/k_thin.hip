@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
 // Y_c (op)= X_c * C with C (wx x wy, ld c_ld) on the float64 matrix cores; grid: chunk
 // x (chh / 64) row tiles x (wy / 64) column tiles.  X_c (rows x wx, column-major) is the
 // transpose of a row-major wx x rows array.
-__global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws,
+__global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws, const int* __restrict__ iws,
                                                  const ThinTask* __restrict__ tasks,
                                                  const ChunkRef* __restrict__ chunks, int chh) {
     __shared__ double As[mfma_lds_a<1>()];
@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws,
     const int row0 = cr.chunk * chh;
     const int rows = min(chh, t.h - row0);
     if (rt >= rows || by >= t.wy) return;
+    if (t.cond >= 0 && iws[t.cond] != 0) return;
     v4d acc[2][2];
     mfma_tile<double, 1>(ws + t.x_off + row0, t.x_ld, ws + t.c_off, t.c_ld, rows, t.wy, t.wx, rt, by,
                          As, Bs, acc);
@@ -128,15 +129,11 @@ hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int max
     hipLaunchKernelGGL(k_thin_reduce, dim3(ntasks, (maxsz + 255) / 256), dim3(256), 0, s, ws, t);
     return hipGetLastError();
 }
-hipError_t launch_thin_nn(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
+hipError_t launch_thin_nn(double* ws, const int* iws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
                           int chh, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, (chh + TT - 1) / TT, 2), dim3(256), 0, s, ws, t, chunks, chh);
+    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, (chh + TT - 1) / TT, 2), dim3(256), 0, s, ws, iws, t, chunks, chh);
     return hipGetLastError();
-}
-hipError_t launch_thin_sub(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
-                           int chh, hipStream_t s) {
-    return launch_thin_nn(ws, t, chunks, nchunks, chh, s);
 }
 hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
                            int chh, hipStream_t s) {

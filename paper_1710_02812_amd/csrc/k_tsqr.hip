@@ -68,6 +68,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_factor(double* __restrict__ ws,
 
     const ChunkRef cr = chunks[blockIdx.x];
     const TsqrTask t = tasks[cr.task];
+    if (t.cq_flag >= 0 && iws[t.cq_flag] == 0) return;          // the Cholesky QR stood
     const int tid = threadIdx.x, nth = blockDim.x;
     const int row0 = cr.chunk * ch;
     const int rows = min(ch, t.h - row0);
@@ -189,6 +190,7 @@ __host__ __device__ inline bool apply_stage_t(int w, int ch, int c) {
 }
 
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict__ ws,
+                                                             const int* __restrict__ iws,
                                                              const TsqrTask* __restrict__ tsqr,
                                                              const ApplyTask* __restrict__ tasks,
                                                              const ChunkRef* __restrict__ chunks,
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
     const ChunkRef cr = chunks[blockIdx.x];
     const ApplyTask a = tasks[cr.task];
     const TsqrTask t = tsqr[a.tsqr];
+    if (t.cq_flag >= 0 && iws[t.cq_flag] == 0) return;          // the Cholesky QR stood
     const int tid = threadIdx.x, nth = blockDim.x;
     const double* store = ws + t.store_off;
     const int64_t S = tsqr_slot_size(w);
@@ -349,7 +352,7 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const
     return launch_factor_t<16, 10, 768>(ws, iws, tasks, chunks, nchunks, w, ch, s);
 }
 
-hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* tasks,
+hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
@@ -365,7 +368,7 @@ hipError_t launch_tsqr_apply(double* ws, const TsqrTask* tsqr, const ApplyTask* 
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_apply,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tsqr_apply, dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws, tsqr, tasks,
+    hipLaunchKernelGGL(k_tsqr_apply, dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws, iws, tsqr, tasks,
                        chunks, w, ch, c);
     return hipGetLastError();
 }

@@ -74,6 +74,7 @@ def test_null_handles():
     assert lib.hsvd_get_status(None, None) == 1
     assert lib.hsvd_debug_jacobi(None, 1, 4, None, None, None, 10, 0, None, None) == 1
     assert lib.hsvd_debug_tsqr(None, 1, 4, 4, None, None, None) == 1
+    assert lib.hsvd_debug_cholqr(None, 1, 4, 4, None, None, None, None) == 1
 
 
 @pytest.mark.parametrize("shape", [

@@ -151,6 +151,63 @@ def test_tsqr_random_panels(h, w):
                                rtol=1e-11, atol=1e-12 * np.abs(Rref).max())
 
 
+def _graded_panel(rng, h, w, kappa):
+    U = np.linalg.qr(rng.standard_normal((h, w)))[0]
+    V = np.linalg.qr(rng.standard_normal((w, w)))[0]
+    return (U * np.logspace(0, -np.log10(kappa), w)) @ V.T
+
+
+@pytest.mark.parametrize("h,w,kappa", [(100, 20, 1e3), (1000, 50, 5e3), (1024, 64, 1e4), (257, 64, 10.0),
+                                       (8192, 50, 1e3), (20000, 17, 1e2), (3000, 1, 1.0), (2048, 64, 1e5)])
+def test_cholqr_well_conditioned(h, w, kappa):
+    """Two Cholesky QR passes stand (no fallback) on panels of condition number up to
+    1e5, with a float64 QR: P = Q R, Q orthonormal, R upper with P's singular values."""
+    rng = np.random.default_rng(h + w)
+    P = np.stack([_graded_panel(rng, h, w, kappa), rng.standard_normal((h, w))])
+    print(f"cholqr h={h} w={w} kappa={kappa:g}", flush=True)
+    Q, R, fb = H.debug_cholqr(_t(P))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert fb == [0, 0]
+    for b in range(2):
+        assert np.all(np.tril(R[b], -1) == 0.0)
+        assert np.linalg.norm(Q[b] @ R[b] - P[b]) <= 1e-14 * np.sqrt(w) * np.linalg.norm(P[b])
+        assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(w)) <= 1e-14 * np.sqrt(h) * w
+        s_ref = np.linalg.svd(P[b], compute_uv=False)
+        assert np.max(np.abs(np.linalg.svd(R[b], compute_uv=False) - s_ref)) <= 1e-13 * s_ref[0]
+
+
+@pytest.mark.parametrize("h,w", [(600, 40), (5000, 64), (300, 7)])
+def test_cholqr_fallback_and_dead_columns(h, w):
+    """An ill-conditioned panel (a column within 1e-9 of its predecessors' span) falls
+    back to the Householder kernels; exactly zero columns stay on the Cholesky path as
+    zero rows of R and zero columns of Q; a panel wider than tall falls back too."""
+    rng = np.random.default_rng(10 * h + w)
+    good = rng.standard_normal((h, w))
+    bad = rng.standard_normal((h, w))
+    bad[:, -1] = bad[:, 0] + 1e-9 * rng.standard_normal(h)
+    dead = rng.standard_normal((h, w))
+    dead[:, [1, w // 2]] = 0.0
+    P = np.stack([good, bad, dead])
+    print(f"cholqr fallback h={h} w={w}", flush=True)
+    Q, R, fb = H.debug_cholqr(_t(P))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert fb == [0, 1, 0]
+    for b in range(3):
+        assert np.allclose(np.tril(R[b], -1), 0.0)
+        assert np.linalg.norm(Q[b] @ R[b] - P[b]) <= 1e-13 * np.sqrt(h * w) * np.linalg.norm(P[b])
+    live = np.ones(w, bool)
+    live[[1, w // 2]] = False
+    assert np.all(Q[2][:, ~live] == 0.0) and np.all(R[2][~live, :] == 0.0)
+    Ql = Q[2][:, live]
+    assert np.linalg.norm(Ql.T @ Ql - np.eye(live.sum())) <= 1e-14 * np.sqrt(h) * w
+    s_ref = np.linalg.svd(P[2], compute_uv=False)
+    assert np.max(np.abs(np.linalg.svd(R[2], compute_uv=False) - s_ref)) <= 1e-13 * s_ref[0]
+    Pw = rng.standard_normal((1, 5, 9))
+    Qw, Rw, fbw = H.debug_cholqr(_t(Pw))
+    assert fbw == [1]
+    assert np.linalg.norm(Qw.cpu().numpy()[0] @ Rw.cpu().numpy()[0] - Pw[0]) <= 1e-13 * np.linalg.norm(Pw[0])
+
+
 def _bf16(x):
     """Round to bfloat16 (nearest even) through float32, as the matrix-core passes do."""
     f = np.ascontiguousarray(x, dtype=np.float32)
