@@ -42,24 +42,36 @@ namespace hsvd {
 
 constexpr int CORE_THREADS = 1024;
 
-__device__ int select_rank(const double* sig, int nc, const CoreTask& t, const int* iws, int nr) {
+// First index i < nc (nc <= 128) where pred(i) fails, else nc; called by a whole wave.
+template <typename F>
+__device__ __forceinline__ int wave_first_fail(int nc, F pred) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long f0 = __ballot(lane < nc && !pred(lane));
+    const unsigned long long f1 = __ballot(lane + 64 < nc && !pred(lane + 64));
+    if (f0) return __builtin_ctzll(f0);
+    if (f1) return 64 + __builtin_ctzll(f1);
+    return nc;
+}
+
+// The truncation rank of sorted values sig (descending), for one wave: a zero floor
+// of max(rows, cols) eps sig_0, then the task's rule; at most kcap.
+__device__ int select_rank(const double* sig, int nc, const CoreTask& t, const int* iws) {
     if (nc == 0) return 0;
     const double s0 = sig[0];
     if (!(s0 > 0.0)) return 0;
     const int fr = t.floor_rows;
     const int fc = t.floor_cols < 0 ? nc : t.floor_cols;
     const double floor = (double)(fr > fc ? fr : fc) * kEps * s0;
-    int nonzero = 0;
-    while (nonzero < nc && sig[nonzero] > floor) ++nonzero;
+    const int nonzero = wave_first_fail(nc, [&](int i) { return sig[i] > floor; });
     int r;
     if (t.fixed_rank_slot >= 0) {
         r = iws[t.fixed_rank_slot];
     } else if (t.rule == 0) {
-        r = 0;
-        while (r < nc && sig[r] >= t.tol * s0) ++r;
+        const double lim = t.tol * s0;
+        r = wave_first_fail(nc, [&](int i) { return sig[i] >= lim; });
     } else {
         // smallest r whose discarded tail sum_{i>=r} s_i^2 is <= tol^2 * total,
-        // tails accumulated from the smallest value up
+        // tails accumulated from the smallest value up (in that order, by one lane)
         double total = 0.0;
         for (int i = nc - 1; i >= 0; --i) total += sig[i] * sig[i];
         const double lim = t.tol * t.tol * total;
@@ -73,7 +85,6 @@ __device__ int select_rank(const double* sig, int nc, const CoreTask& t, const i
     }
     if (r > nonzero) r = nonzero;
     if (r > t.kcap) r = t.kcap;
-    (void)nr;
     return r;
 }
 
@@ -421,9 +432,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         iws[t.flag_slot] = miss;
         if (miss && flags) atomicOr(flags, 4u);
     }
-    if (tid == 0) {
-        const int r = s_bad ? 0 : select_rank(sig, nc, t, iws, nr);
-        s_rank = r;
+    if (wave == 0) {
+        const int r = s_bad ? 0 : select_rank(sig, nc, t, iws);
         // accept the skipped small-small rotations only if they cannot change the result
         int safe = 1;
         if (skip && r > 0) {
@@ -431,12 +441,16 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             // other pair is orthogonal, so the kept columns are exact if none of them
             // is in S and S cannot hold a singular value as large as the r-th
             double small2 = 0.0;
-            int any_small = 0;
-            for (int j = 0; j < nc; ++j)
-                if (sflag[j]) { small2 += d[j] * d[j]; any_small = 1; }
+            bool any_small = false, kept_small = false;
+            for (int j = lane64; j < nc; j += 64) {
+                if (sflag[j]) { small2 = fma(d[j], d[j], small2); any_small = true; }
+                if (j < r && sflag[perm[j]]) kept_small = true;
+            }
+            small2 = wave_sum(small2);
+            any_small = __ballot(any_small) != 0ull;
+            kept_small = __ballot(kept_small) != 0ull;
             if (any_small) {
-                for (int i = 0; i < r; ++i)
-                    if (sflag[perm[i]]) safe = 0;
+                if (kept_small) safe = 0;
                 const double sm = sqrt(small2);
                 if (!(sm < sig[r - 1])) safe = 0;
                 int cap = t.kcap;
@@ -447,16 +461,19 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                     bool excluded = sm <= floor;
                     if (t.fixed_rank_slot < 0 && t.rule == 0) excluded = excluded || sm < t.tol * sig[0];
                     if (t.fixed_rank_slot < 0 && t.rule == 1) {
-                        double total = 0.0;
-                        for (int i = nc - 1; i >= 0; --i) total += sig[i] * sig[i];
-                        excluded = excluded || small2 <= t.tol * t.tol * total;
+                        double all2 = 0.0;
+                        for (int j = lane64; j < nc; j += 64) all2 = fma(sig[j], sig[j], all2);
+                        excluded = excluded || small2 <= t.tol * t.tol * wave_sum(all2);
                     }
                     if (!excluded) safe = 0;
                 }
             }
         }
-        s_safe = safe;
-        if (safe && t.rank_out >= 0) iws[t.rank_out] = r;
+        if (lane64 == 0) {
+            s_rank = r;
+            s_safe = safe;
+            if (safe && t.rank_out >= 0) iws[t.rank_out] = r;
+        }
     }
     __syncthreads();
     if (!s_safe) {                 // redo with full sweeps from the current state
