@@ -169,26 +169,37 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     __syncthreads();
 
     // ---- LQ preconditioning: G = L Q by Householder QR of G^T; the sweeps then
-    // run on L (same left singular pairs).  Group c (8 lanes) holds row c of G as
-    // column c of G^T, lane rows are G's columns; Q is not formed.
+    // run on L (same left singular pairs).  Row c of G is column c of G^T, held by
+    // the 16-lane group c % 64 (two columns per group), lane rows are G's columns;
+    // Q is not formed.
     if (t.precond && !accv && !s_bad && nc > 1) {
-        constexpr int RQ = ROWS / 8;              // rows of G^T (columns of G) per lane
-        HouseQR<8, RQ, false, 16> q;
-        const int c = tid >> 3, gl = tid & 7;
+        constexpr int RQ = ROWS / 16;             // rows of G^T (columns of G) per lane
+        using QR = HouseQR<16, RQ, false, 16, 2, CORE_THREADS>;
+        static_assert(QR::WMAX >= ROWS && QR::VB == ROWS, "preconditioner layout");
+        QR q;
+        const int gl = tid & 15;
 #pragma unroll
-        for (int s = 0; s < RQ; ++s) {
-            const int r = gl + 8 * s;
-            q.x[s] = (c < nr && r < nc) ? G[(int64_t)r * ldg + c] : 0.0;
+        for (int s = 0; s < 2; ++s) {
+            const int c = q.col_of(s);
+#pragma unroll
+            for (int u = 0; u < RQ; ++u) {
+                const int r = gl + 16 * u;
+                q.x[s * RQ + u] = (c < nr && r < nc) ? G[(int64_t)r * ldg + c] : 0.0;
+            }
         }
         // scratch: tau -> sig, the two pivot buffers -> the first 2 ROWS entries of G
         // (maxdim >= nc >= 2 here, so G holds >= 2 ROWS + 2); T and z are not used.
-        // Groups c >= nr hold zero columns of G^T; only c < ROWS have a row of G.
+        // Columns c >= nr of G^T are zero; only c < ROWS have a row of G.
         __syncthreads();                          // all of G is in registers
         q.factor(nc, nr, G, sig, d, G);
 #pragma unroll
-        for (int s = 0; s < RQ; ++s) {
-            const int r = gl + 8 * s;
-            if (r < nc && c < ROWS) G[(int64_t)r * ldg + c] = (r <= c) ? q.x[s] : 0.0;
+        for (int s = 0; s < 2; ++s) {
+            const int c = q.col_of(s);
+#pragma unroll
+            for (int u = 0; u < RQ; ++u) {
+                const int r = gl + 16 * u;
+                if (r < nc && c < ROWS) G[(int64_t)r * ldg + c] = (r <= c) ? q.x[s * RQ + u] : 0.0;
+            }
         }
         __syncthreads();
     }
