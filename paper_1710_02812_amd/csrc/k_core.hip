@@ -125,7 +125,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     }
     __syncthreads();
     const int nr = s_nr, nc = s_nc, r1 = s_r1;
-    const bool accv = (t.v_off >= 0) && with_v;
+    // right vectors are accumulated only for cores of at most 64 columns (the launch
+    // rejects with_v above that), so the wider variants compile without them
+    const bool accv = ROWS <= 64 && (t.v_off >= 0) && with_v;
 
     // ---- load the core
     int bad = 0;
@@ -205,11 +207,14 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     }
 
     // ---- one-sided Jacobi sweeps
-    // Round-robin tournament on N = nc rounded up to even players (player N-1 fixed):
-    // in round r group g pairs a = (r + g) mod (N-1) (a = r for g = 0) with
-    // b = (r - g) mod (N-1) (b = N-1 for g = 0); indices advance by one per round.
-    const int N = nc + (nc & 1);
-    const int npairs = N >> 1;
+    // Pair order by recursive halving: a team of columns [lo, hi) splits into
+    // A = [lo, lo + m) and B = [lo + m, hi), m = ceil((hi - lo) / 2) (B padded with a
+    // dummy when odd); for m rounds group j of the team keeps a = lo + j in registers
+    // and meets b = lo + m + (j + r) mod m, read from and written back to LDS; then A
+    // and B are teams of the next depth, all teams of a depth side by side.  Every pair
+    // meets once per sweep in about nc rounds (as the circle method), but only one of
+    // its two columns crosses LDS in a round.  Depth d has 2^d teams of at most
+    // ceil(nc / 2^d) columns, each given ceil(nc / 2^(d+1)) groups: <= 64 for nc <= 128.
     constexpr int gsz = 16;                         // lanes per pair: 64 groups cover nc <= 128
     const int grp = tid / gsz, gl = tid - grp * gsz;
     constexpr int TMAX = ROWS / gsz;                // rows per lane, unconditional (zero padded)
@@ -317,29 +322,40 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
         __syncthreads();
         if (s_rot == 0) { converged = true; break; }
         if (sweep >= max_sweeps) break;
-        int a = (grp == 0) ? 0 : grp;
-        int b = (grp == 0) ? N - 1 : N - 1 - grp;
-        for (int round = 0; round < N - 1; ++round) {
-            if (grp < npairs) {
-                // skip flags from registers, norms issued with the column loads:
-                // no LDS round trip before the loads or after the reduction
-                const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
+        for (int dep = 0; ((nc + (1 << dep) - 1) >> dep) >= 2; ++dep) {
+            const int gpt = (nc + (2 << dep) - 1) >> (dep + 1);      // groups (and rounds) per team
+            const int tm = grp / gpt, j = grp - tm * gpt;
+            int lo = 0, hi = nc;
+            for (int i = 0; i < dep; ++i) {
+                const int m = (hi - lo + 1) >> 1;
+                if ((tm >> (dep - 1 - i)) & 1) lo += m;
+                else hi = lo + m;
+            }
+            const int m = (hi - lo + 1) >> 1;
+            const bool act = tm < (1 << dep) && hi - lo >= 2 && j < m;
+            const int a = act ? lo + j : 0;
+            const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
+            double* ga = G + (int64_t)a * ldg;
+            double ra[TMAX];
+            double da = 0.0;
+            if (act) {
+                da = d[a];
+#pragma unroll
+                for (int t = 0; t < TMAX; ++t) ra[t] = ga[gl + t * gsz];
+            }
+            bool moved = false;
+            for (int r = 0; r < gpt; ++r) {
+                const int b = act ? lo + m + (j + r) % m : 0;
                 const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                const bool marked = hi < nc && ((s_pair[lo * 4 + (hi >> 5)] >> (hi & 31)) & 1u) != 0;
-                const bool valid = (a < nc) && (b < nc) && !(fa && fb) && marked;
-                double ra[TMAX], rb[TMAX];
-                double c0 = 0.0, c1 = 0.0, da = 0.0, db = 0.0;
-                double* ga = G + (int64_t)(valid ? a : 0) * ldg;
+                const bool marked = b < hi && ((s_pair[a * 4 + (b >> 5)] >> (b & 31)) & 1u) != 0;
+                const bool valid = act && r < m && b < hi && !(fa && fb) && marked;
+                double rb[TMAX];
+                double c0 = 0.0, c1 = 0.0, db = 0.0;
                 double* gb = G + (int64_t)(valid ? b : 0) * ldg;
                 if (valid) {
-                    da = d[a];
                     db = d[b];
 #pragma unroll
-                    for (int t = 0; t < TMAX; ++t) {
-                        ra[t] = ga[gl + t * gsz];
-                        rb[t] = gb[gl + t * gsz];
-                    }
+                    for (int t = 0; t < TMAX; ++t) rb[t] = gb[gl + t * gsz];
 #pragma unroll
                     for (int t = 0; t < TMAX; ++t) {          // TMAX may be odd (112 rows)
                         if (t & 1) c1 = fma(ra[t], rb[t], c1);
@@ -372,8 +388,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                         const double sn = cs * tt;
 #pragma unroll
                         for (int t = 0; t < TMAX; ++t) {
-                            ga[gl + t * gsz] = cs * ra[t] - sn * rb[t];
-                            gb[gl + t * gsz] = sn * ra[t] + cs * rb[t];
+                            const double xa = ra[t];
+                            ra[t] = cs * xa - sn * rb[t];
+                            gb[gl + t * gsz] = sn * xa + cs * rb[t];
                         }
                         if (accv) {
                             double* va = V + (int64_t)a * ldg;
@@ -390,16 +407,18 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                                 vb[gl + t * gsz] = sn * xa[t] + cs * xb[t];
                             }
                         }
-                        if (gl == 0) {
-                            d[a] = da - tt * c;
-                            d[b] = db + tt * c;
-                        }
+                        if (gl == 0) d[b] = db + tt * c;
+                        da = da - tt * c;
+                        moved = true;
                     }
                 }
+                __syncthreads();
             }
-            // advance the tournament
-            if (grp == 0) a = a + 1;
-            else { a = (a + 1 == N - 1) ? 0 : a + 1; b = (b + 1 == N - 1) ? 0 : b + 1; }
+            if (moved) {
+#pragma unroll
+                for (int t = 0; t < TMAX; ++t) ga[gl + t * gsz] = ra[t];
+                if (gl == 0) d[a] = da;
+            }
             __syncthreads();
         }
     }
