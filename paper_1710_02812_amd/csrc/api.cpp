@@ -570,6 +570,7 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         c.rank_out = nd.rank;
         c.floor_rows = (int)l.rowsz;
         c.floor_cols = (int)l.colsz;
+        c.precond = 1;                // left vectors only: LQ of R first (fewer sweeps)
         if (P.energy_off >= 0 && l.mat == 0) {
             c.energy_off = P.energy_off + b;
             c.flag_slot = P.ialloc(1);
