@@ -229,6 +229,11 @@ def run_uneven(args, torch):
     lt = plan.launch_times()
     plan.set_profiling(False)
     launches = len(lt)
+    kinds_ms = {}
+    for kind, tms in lt:
+        e = kinds_ms.setdefault(kind, [0, 0.0])
+        e[0] += 1
+        e[1] += tms
     plan.close()
     # property check at full size: exact low rank -> rank and singular values recovered
     s_err = max(float(np.max(np.abs(S.double().cpu().numpy()[:w.k] - w.meta["sigma"])))
@@ -286,6 +291,7 @@ def run_uneven(args, torch):
         "loop_of_plans_ms": round(ms_loop, 3),
         "batched_speedup_vs_loop": round(ms_loop / ms_batched, 3),
         "launches_per_step": launches,
+        "launch_kinds": {kk: {"launches": n, "ms": round(tms, 4)} for kk, (n, tms) in kinds_ms.items()},
         "ranks_recovered": rank_ok,
         "sigma_abs_err_max": s_err,
         "status_flags": flags & 0xFFFF,

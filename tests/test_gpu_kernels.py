@@ -158,10 +158,13 @@ def _graded_panel(rng, h, w, kappa):
 
 
 @pytest.mark.parametrize("h,w,kappa", [(100, 20, 1e3), (1000, 50, 5e3), (1024, 64, 1e4), (257, 64, 10.0),
-                                       (8192, 50, 1e3), (20000, 17, 1e2), (3000, 1, 1.0), (2048, 64, 1e5)])
+                                       (8192, 50, 1e3), (20000, 17, 1e2), (3000, 1, 1.0), (2048, 64, 1e5),
+                                       (70000, 16, 1e3), (16641, 64, 1e2)])
 def test_cholqr_well_conditioned(h, w, kappa):
     """Two Cholesky QR passes stand (no fallback) on panels of condition number up to
-    1e5, with a float64 QR: P = Q R, Q orthonormal, R upper with P's singular values."""
+    1e5, with a float64 QR: P = Q R, Q orthonormal, R upper with P's singular values.
+    Heights past 16384 rows (274 and 66 chunks of 256) sum the partial Grams up three
+    levels of the fan-in-8 tree."""
     rng = np.random.default_rng(h + w)
     P = np.stack([_graded_panel(rng, h, w, kappa), rng.standard_normal((h, w))])
     print(f"cholqr h={h} w={w} kappa={kappa:g}", flush=True)
