@@ -344,8 +344,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 for (int t = 0; t < TMAX; ++t) ra[t] = ga[gl + t * gsz];
             }
             bool moved = false;
-            for (int r = 0; r < gpt; ++r) {
-                const int b = act ? lo + m + (j + r) % m : 0;
+            int bi = j;                                        // (j + r) mod m
+            for (int r = 0; r < gpt; ++r, bi = (bi + 1 == m) ? 0 : bi + 1) {
+                const int b = act ? lo + m + bi : 0;
                 const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
                 const bool marked = b < hi && ((s_pair[a * 4 + (b >> 5)] >> (b & 31)) & 1u) != 0;
                 const bool valid = act && r < m && b < hi && !(fa && fb) && marked;
