@@ -7,10 +7,12 @@ namespace hsvd {
 // Move a double between lanes with a DPP control (GFX9 encodings):
 //   0xB1 quad_perm[1,0,3,2] (lane ^ 1), 0x4E quad_perm[2,3,0,1] (lane ^ 2),
 //   0x141 row_half_mirror (lane i <-> 7-i within 8), 0x140 row_mirror (i <-> 15-i).
+// Every control used here reads a lane of the same row, so no lane keeps an old value
+// (the plain move needs no initialised destination).
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
