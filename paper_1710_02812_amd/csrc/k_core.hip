@@ -336,6 +336,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             const int a = act ? lo + j : 0;
             const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
             double* ga = G + (int64_t)a * ldg;
+            // a's marks against every column (a < b throughout the depth), in registers
+            const unsigned pw0 = s_pair[a * 4], pw1 = s_pair[a * 4 + 1], pw2 = s_pair[a * 4 + 2],
+                           pw3 = s_pair[a * 4 + 3];
             double ra[TMAX];
             double da = 0.0;
             if (act) {
@@ -348,7 +351,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             for (int r = 0; r < gpt; ++r, bi = (bi + 1 == m) ? 0 : bi + 1) {
                 const int b = act ? lo + m + bi : 0;
                 const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
-                const bool marked = b < hi && ((s_pair[a * 4 + (b >> 5)] >> (b & 31)) & 1u) != 0;
+                const int bw = b >> 5;
+                const unsigned pw = bw == 0 ? pw0 : bw == 1 ? pw1 : bw == 2 ? pw2 : pw3;
+                const bool marked = b < hi && ((pw >> (b & 31)) & 1u) != 0;
                 const bool valid = act && r < m && b < hi && !(fa && fb) && marked;
                 double rb[TMAX];
                 double c0 = 0.0, c1 = 0.0, db = 0.0;
