@@ -336,9 +336,11 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             const int a = act ? lo + j : 0;
             const bool fa = ((a < 64 ? mask0 >> a : mask1 >> (a - 64)) & 1ull) != 0;
             double* ga = G + (int64_t)a * ldg;
-            // a's marks against every column (a < b throughout the depth), in registers
-            const unsigned pw0 = s_pair[a * 4], pw1 = s_pair[a * 4 + 1], pw2 = s_pair[a * 4 + 2],
-                           pw3 = s_pair[a * 4 + 3];
+            // a's marks against every column (a < b throughout the depth), in registers;
+            // when a is in the skipped set, the other members' marks are cleared
+            const unsigned long long sk0 = fa ? mask0 : 0ull, sk1 = fa ? mask1 : 0ull;
+            const unsigned pw0 = s_pair[a * 4] & ~(unsigned)sk0, pw1 = s_pair[a * 4 + 1] & ~(unsigned)(sk0 >> 32),
+                           pw2 = s_pair[a * 4 + 2] & ~(unsigned)sk1, pw3 = s_pair[a * 4 + 3] & ~(unsigned)(sk1 >> 32);
             double ra[TMAX];
             double da = 0.0;
             if (act) {
@@ -350,11 +352,10 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
             int bi = j;                                        // (j + r) mod m
             for (int r = 0; r < gpt; ++r, bi = (bi + 1 == m) ? 0 : bi + 1) {
                 const int b = act ? lo + m + bi : 0;
-                const bool fb = ((b < 64 ? mask0 >> b : mask1 >> (b - 64)) & 1ull) != 0;
                 const int bw = b >> 5;
                 const unsigned pw = bw == 0 ? pw0 : bw == 1 ? pw1 : bw == 2 ? pw2 : pw3;
                 const bool marked = b < hi && ((pw >> (b & 31)) & 1u) != 0;
-                const bool valid = act && r < m && b < hi && !(fa && fb) && marked;
+                const bool valid = act && r < m && marked;
                 double rb[TMAX];
                 double c0 = 0.0, c1 = 0.0, db = 0.0;
                 double* gb = G + (int64_t)(valid ? b : 0) * ldg;
