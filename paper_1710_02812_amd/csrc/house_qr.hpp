@@ -83,18 +83,52 @@ struct HouseQR {
 
     // Squared norm of the rows r > j of slot s (registers t < NT; rows past the
     // block hold zeros).
-    template <int NT>
-    __device__ double norm_below(int s, int j) const {
+    // Register TJ = j / LANES straddles row j; below it every register lies wholly above
+    // row j, past it wholly below (the callers dispatch on the wave-uniform j / LANES,
+    // so those registers need no per-lane test).
+    template <int NT, int TJ>
+    __device__ double norm_below_t(int s, int j) const {
         const int gl = threadIdx.x % LANES;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int r = gl + LANES * t;
-            const double m = (r > j) ? x[s * RMAX + t] : 0.0;
+            if (t < TJ) continue;
+            const double m = (t > TJ || gl + LANES * t > j) ? x[s * RMAX + t] : 0.0;
             if (t & 1) s1 = fma(m, m, s1);
             else s0 = fma(m, m, s0);
         }
         return gsum(s0 + s1);
+    }
+    template <int NT>
+    __device__ double norm_below(int s, int j) const {
+        switch (j / LANES) {
+#define HQ_NB(k) case k: if constexpr (k < NT) return norm_below_t<NT, k>(s, j); else break;
+            HQ_NB(0) HQ_NB(1) HQ_NB(2) HQ_NB(3) HQ_NB(4) HQ_NB(5) HQ_NB(6) HQ_NB(7)
+            HQ_NB(8) HQ_NB(9) HQ_NB(10) HQ_NB(11) HQ_NB(12) HQ_NB(13) HQ_NB(14) HQ_NB(15)
+#undef HQ_NB
+            default: break;
+        }
+        return 0.0;
+    }
+
+    // The scaled reflector into its registers and vb (zeros above row j, 1 at row j),
+    // beta at row j; register TJ = j / LANES is the only one with a per-lane test.
+    template <int NT, int TJ>
+    __device__ void reflect_rows(int s, int j, double beta, double s2, double scal, double* vb) {
+        const int gl = threadIdx.x % LANES;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int r = gl + LANES * t;
+            double v = 0.0;
+            if (t > TJ) {
+                if (s2 > 0.0) x[s * RMAX + t] *= scal;
+                v = x[s * RMAX + t];
+            } else if (t == TJ) {
+                if (r == j) { x[s * RMAX + t] = beta; v = 1.0; }
+                else if (r > j) { if (s2 > 0.0) x[s * RMAX + t] *= scal; v = x[s * RMAX + t]; }
+            }
+            vb[r] = v;
+        }
     }
 
     // Reflector of column j (slot s of the calling group): alpha = A_jj sits in
@@ -119,13 +153,12 @@ struct HouseQR {
             tau_j = fma(-alpha, rcp_nr(beta), 1.0);           // (beta - alpha) / beta
             scal = rcp_nr(alpha - beta);                      // |alpha - beta| >= |beta| > 0
         }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int r = gl + LANES * t;
-            double v = 0.0;
-            if (r == j) { x[s * RMAX + t] = beta; v = 1.0; }
-            else if (r > j) { if (s2 > 0.0) x[s * RMAX + t] *= scal; v = x[s * RMAX + t]; }
-            vb[r] = v;                                         // zeros above row j
+        switch (tj) {
+#define HQ_RF(k) case k: if constexpr (k < NT) reflect_rows<NT, k>(s, j, beta, s2, scal, vb); break;
+            HQ_RF(0) HQ_RF(1) HQ_RF(2) HQ_RF(3) HQ_RF(4) HQ_RF(5) HQ_RF(6) HQ_RF(7)
+            HQ_RF(8) HQ_RF(9) HQ_RF(10) HQ_RF(11) HQ_RF(12) HQ_RF(13) HQ_RF(14) HQ_RF(15)
+#undef HQ_RF
+            default: break;
         }
         if (gl == 0) tau[j] = tau_j;
     }
