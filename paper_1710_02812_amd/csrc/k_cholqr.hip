@@ -7,8 +7,9 @@
 //   pass 2: G2 = Q1^T Q1, R2 = chol(G2), R = R2 R1 -> the panel's R, M2 = R2^{-1}
 //   (the apply then forms Q X = Q1 (M2 X) with thin products)
 //
-// Partial Grams of 256-row chunks run on the float64 matrix cores; the last
-// work-group of a panel to finish sums them and factors (one work-group per panel).
+// Partial Grams of 256-row chunks run on the float64 matrix cores and are summed up a
+// tree of fan-in 8 (the last child of a node to arrive adds its siblings, in child
+// order); the work-group that completes the root factors the panel's Gram matrix.
 // Fallback (flag 1: the Householder kernels run, these outputs are ignored): a pass-1
 // pivot below 1e-10 of its column's squared norm (the column is nearly a combination
 // of the previous ones), or ||Q1^T Q1 - I||_F > 1/4 over the live columns (a first pass
@@ -21,7 +22,8 @@
 
 namespace hsvd {
 
-// Scratch of a panel (cq_size doubles from cq_off): R1 | M1 | M2 | parts (nch w^2) | Q1 (h x w, ld h)
+// Scratch of a panel (cq_size doubles from cq_off): R1 | M1 | M2 | chunk parts (nch w^2) |
+// node sums | Q1 (h x w, ld h)
 
 // Value of v in lane l (l uniform across the wave).
 __device__ __forceinline__ double readlane_d(double v, int l) {
