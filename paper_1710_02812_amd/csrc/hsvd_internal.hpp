@@ -48,7 +48,7 @@ struct TsqrTask {
 };
 struct ChunkRef { int32_t task; int32_t chunk; };
 
-constexpr int THIN_CH = 256;    // rows per chunk of the thin-panel products
+constexpr int THIN_CH = 128;    // rows per chunk of the thin-panel products
 
 constexpr int kTsqrMaxW = 80;
 // Fan-in F of the R-factor tree: up to F stacked w x w factors are merged by one
