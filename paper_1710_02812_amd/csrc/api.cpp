@@ -231,8 +231,8 @@ void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
 void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<ApplyTask>& at,
                      int w, int ch, int c) {
     if (tb.cholqr) {
-        // out = Q X + U1 T with Q = Q1 M2: C = M2 X (w x c), out = Q1 C, out += U1 T
-        std::vector<ThinTask> n1, n2, n3;
+        // out = Q X + U1 T with Q = Q1 M2: C = M2 X (w x c), then out = Q1 C + U1 T
+        std::vector<ThinTask> n1, n2;
         for (const ApplyTask& a : at) {
             const TsqrTask& t = tb.tasks[a.tsqr];
             if (t.cq_flag < 0) continue;
@@ -248,19 +248,15 @@ void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<App
             y.c_off = C; y.c_ld = w;
             y.y_off = a.out_off; y.y_ld = a.out_ld;
             y.h = t.h; y.wx = w; y.wy = c; y.accumulate = 0; y.cond = t.cq_flag;
-            n2.push_back(y);
             if (a.add_u_off >= 0) {
-                ThinTask z{};
-                z.x_off = a.add_u_off; z.x_ld = a.add_u_ld;
-                z.c_off = a.add_t_off; z.c_ld = a.add_w;
-                z.y_off = a.out_off; z.y_ld = a.out_ld;
-                z.h = t.h; z.wx = a.add_w; z.wy = c; z.accumulate = 1; z.cond = t.cq_flag;
-                n3.push_back(z);
+                y.x2_off = a.add_u_off; y.x2_ld = a.add_u_ld;
+                y.c2_off = a.add_t_off; y.c2_ld = a.add_w;
+                y.wx2 = a.add_w;
             }
+            n2.push_back(y);
         }
         if (!n1.empty()) push_thin(P, ST_NN, n1);
         if (!n2.empty()) push_thin(P, ST_NN, n2);
-        if (!n3.empty()) push_thin(P, ST_NN, n3);
     }
     Stage s{};
     s.kind = ST_TSQR_A;
@@ -1147,6 +1143,11 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         if (!panel("nn X", t.x_off, t.x_ld, t.h, t.wx)) return msg;
                         if (!panel("nn C", t.c_off, t.c_ld, t.wx, t.wy)) return msg;
                         if (!panel("nn Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
+                        if (t.x2_off >= 0) {
+                            if (t.wx2 < 1 || t.wx2 > 128) return "nn second width";
+                            if (!panel("nn X2", t.x2_off, t.x2_ld, t.h, t.wx2)) return msg;
+                            if (!panel("nn C2", t.c2_off, t.c2_ld, t.wx2, t.wy)) return msg;
+                        }
                     } else {
                         if (t.x_ld < t.h) return "sum ld";
                         if (!span("sum parts", t.x_off, t.x_off + (int64_t)(t.wx - 1) * t.c_ld + (int64_t)(t.wy - 1) * t.x_ld + t.h - 1, WS)) return msg;
@@ -1656,8 +1657,9 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                             f += 2.0 * h * wx * wy;
                             by += h * (wx + wy) * e8;
                         } else if (s.kind == ST_NN) {
-                            f += 2.0 * h * wx * wy;
-                            by += h * (wx + 2.0 * wy) * e8;
+                            const double wx2 = x.x2_off >= 0 ? x.wx2 : 0.0;
+                            f += 2.0 * h * (wx + wx2) * wy;
+                            by += h * (wx + wx2 + 2.0 * wy) * e8;
                         } else if (s.kind == ST_REDUCE) {
                             const double nch = (x.h + THIN_CH - 1) / THIN_CH;
                             f += nch * wx * wy;

@@ -91,7 +91,7 @@ struct ApplyTask {
 //   gram:  part[c] = X_c^T Y_c           (wx x wy), per chunk c
 //   reduce:C = sum_c part[c]; Cacc (+)= C  (one group per task)
 //   sub:   Y_c -= X_c * C
-//   nn:    O_c (+)= X_c * T
+//   nn:    O_c (+)= X_c * T (+ X2_c * T2)
 struct ThinTask {
     int64_t x_off, y_off, c_off, part_off, acc_off;
     int32_t h, x_ld, y_ld, c_ld;
@@ -99,6 +99,10 @@ struct ThinTask {
     int32_t nch, chunk0;
     int32_t accumulate;   // reduce: 0 -> Cacc = C, 1 -> Cacc += C; nn: 0 set, 1 add, 2 sub
     int32_t cond = -1;    // nn: runs only while iws[cond] == 0 (a Cholesky QR outcome), or always
+    // nn: a second product X2_c * C2 (X2 h x wx2, ld x2_ld; C2 wx2 x wy, ld c2_ld) summed
+    // with the first before the store (x2_off < 0: none)
+    int64_t x2_off = -1, c2_off = 0;
+    int32_t x2_ld = 0, c2_ld = 0, wx2 = 0, pad2 = 0;
 };
 
 // ---------------------------------------------------------------- Jacobi cores

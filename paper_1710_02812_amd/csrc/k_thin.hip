@@ -80,6 +80,9 @@ __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws, const 
     v4d acc[2][2];
     mfma_tile<double, 1>(ws + t.x_off + row0, t.x_ld, ws + t.c_off, t.c_ld, rows, t.wy, t.wx, rt, by,
                          As, Bs, acc);
+    if (t.x2_off >= 0)
+        mfma_tile<double, 1, false>(ws + t.x2_off + row0, t.x2_ld, ws + t.c2_off, t.c2_ld, rows, t.wy, t.wx2, rt,
+                                    by, As, Bs, acc);
     double* Y = ws + t.y_off + row0;
     const int mode = t.accumulate;
     mfma_tile_out(rows, t.wy, rt, by, acc, [&](int r, int c, double v) {

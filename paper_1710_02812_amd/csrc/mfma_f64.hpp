@@ -27,7 +27,8 @@ template <int OP>
 __host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (MF_K + 1) : MF_K * (MF_T + 1); }
 __host__ __device__ constexpr int mfma_lds_b() { return MF_T * (MF_K + 1); }
 
-template <typename TA, int OP>
+// With ZERO false the products add to acc as it stands (a second operand pair).
+template <typename TA, int OP, bool ZERO = true>
 __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                                           const double* __restrict__ B, int64_t ldb,
                                           int M, int N, int K, int r0, int c0, double* As, double* Bs,
@@ -67,10 +68,11 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
             Bs[(e / MF_K) * BP + (e % MF_K)] = pb[u];
         }
     };
+    if (ZERO)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += MF_K) {
         stage();
