@@ -249,6 +249,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                 for (int j = lane64; j < nc; j += 64) {
                     const double dj = d[j];
                     int pos = 0;
+#pragma unroll 8
                     for (int i = 0; i < nc; ++i) {
                         const double di = d[i];
                         pos += (di > dj) || (di == dj && i < j);
@@ -451,6 +452,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     for (int j = tid; j < nc; j += nth) {
         const double sj = d[j];
         int pos = 0;
+#pragma unroll 8
         for (int i = 0; i < nc; ++i) {
             const double si = d[i];
             pos += (si > sj) || (si == sj && i < j);
