@@ -241,7 +241,13 @@ struct HouseQR {
             // three phases: the updates of every column c > j (both slots), then the
             // look-ahead reflector of column j + 1 (the step's critical path), then z
             // and the T rows of the columns c < j.
+            // the wave holding column j + 1 forms the next reflector, the step's critical
+            // path: it runs at raised issue priority until the reflector is out, ahead of
+            // the update work of the other waves on its SIMD
+            const int my_wave = __builtin_amdgcn_readfirstlane(tid >> 6);
             for (int j = 0; j < kmax; ++j) {
+                const bool lead = j + 1 < kmax && ((((j + 1) % NG) * LANES) >> 6) == my_wave;
+                if (lead) __builtin_amdgcn_s_setprio(2);
                 const double* vj = vbuf + (j & 1) * VB;
                 const double tj = tau[j];
                 // the group reads the pivot only if one of its columns updates or forms z
@@ -285,6 +291,7 @@ struct HouseQR {
                         reflect<NT>(s, j + 1, s2, vbuf + ((j + 1) & 1) * VB, tau);
                     }
                 }
+                if (lead) __builtin_amdgcn_s_setprio(0);
                 if (WITH_T) {
 #pragma unroll
                     for (int s = 0; s < CPL; ++s) {                 // z and T rows
