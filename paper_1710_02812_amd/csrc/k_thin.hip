@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws, const 
                                     by, As, Bs, acc);
     double* Y = ws + t.y_off + row0;
     const int mode = t.accumulate;
-    mfma_tile_out(rows, t.wy, rt, by, acc, [&](int r, int c, double v) {
+    mfma_tile_out_lds(rows, t.wy, rt, by, acc, As, [&](int r, int c, double v) {
         double* y = Y + (int64_t)c * t.y_ld + r;
         if (mode == 0) *y = v;
         else if (mode == 1) *y += v;

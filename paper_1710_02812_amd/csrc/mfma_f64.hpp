@@ -118,6 +118,34 @@ __device__ __forceinline__ void mfma_tile_out(int M, int N, int r0, int c0, cons
     }
 }
 
+// mfma_tile_out with coalesced stores: the tile goes through buf (>= 64 x 65 doubles of
+// LDS, free after mfma_tile, which ends on a barrier), then wave w visits columns
+// w, w + 4, ... with lane l on row l, so each column's 64 rows are one contiguous run.
+// Every thread of the 256 calls it; it ends on a barrier (buf may be reused after).
+template <typename F>
+__device__ __forceinline__ void mfma_tile_out_lds(int M, int N, int r0, int c0, const v4d (&acc)[2][2],
+                                                  double* buf, F f) {
+    constexpr int LD = MF_T + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                buf[(wc + 16 * j + li) * LD + wr + 16 * i + lk + 4 * v] = acc[i][j][v];
+    __syncthreads();
+    const int gr = r0 + lane;
+    if (gr < M)
+        for (int c = wave; c < MF_T; c += 4) {
+            const int gc = c0 + c;
+            if (gc < N) f(gr, gc, buf[c * LD + lane]);
+        }
+    __syncthreads();
+}
+
 // A small product whose operands are already on chip: C (M x N) = A (M x K) B (K x N)
 // with a(i, k) and b(k, j) reading LDS (or cached global) elements; 16 x 16 output
 // tiles are dealt to the waves of the work-group (tile t to wave t mod nw), each a
