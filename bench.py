@@ -66,10 +66,15 @@ def parse():
                     help="run warmup + steps of one path only (for rocprofv3)")
     ap.add_argument("--path", default="fp32", choices=["mixed", "fp32", "fp64"],
                     help="the path --profile-only runs")
-    ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven", "learned"],
+    ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven", "learned", "refine"],
                     help="snapshot: the 8192^2 headline; uneven: 200 matrices of uneven shapes "
                          "in one batched plan against a loop of per-matrix plans; learned: "
-                         "32768 x 8192 field matrix, learned sketch widths against k + 14")
+                         "32768 x 8192 field matrix, learned sketch widths against k + 14; refine: "
+                         "the 8192^2 workload with Algorithm 2 to --refine-eps (at most "
+                         "--refine-steps iterations) against none and against the fixed cap")
+    ap.add_argument("--refine-steps", type=int, default=6, help="refine: iteration cap")
+    ap.add_argument("--refine-eps", type=float, default=1e-3,
+                    help="refine: stop when the singular values change by at most this (relative)")
     ap.add_argument("--count", type=int, default=200, help="uneven: number of matrices")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain copies of MIB MiB (counter calibration)")
@@ -194,6 +199,49 @@ def roofline_of(kind: str, e: dict) -> dict:
                  "alg_bytes_per_launch": e["bytes"] / e["launches"],
                  "intensity_flop_per_byte": intensity, "source_hash": kind_hash(kind)})
     return roof
+
+
+def run_refine(args, torch):
+    """Algorithm 2 iterated to a tolerance on the 8192^2 workload (float32 storage, k =
+    50): executes stopped by refine_eps against the projection alone and against the
+    fixed iteration cap; the residual ||A - U S Vt||_F / ||A||_F is taken with torch."""
+    from paper_1710_02812_amd import hsvd as H, synth
+    w = synth.config1(1, m=args.size, n=args.size, block=1024)
+    A64 = torch.tensor(w.A, dtype=torch.float64, device="cuda")
+    A = A64.float()
+    m, n = w.A.shape
+    nrm = torch.linalg.norm(A64).item()
+    res = {}
+    for label, steps, eps in (("projection_only", 0, 0.0), ("to_eps", args.refine_steps, args.refine_eps),
+                              ("fixed_cap", args.refine_steps, 0.0)):
+        plan = H.Plan(m, n, w.p, w.q, w.k, 0.0, precision=H.FP32, refine_steps=steps, refine_eps=eps)
+        U = torch.empty((m, w.k), dtype=torch.float32, device="cuda")
+        S = torch.empty((w.k,), dtype=torch.float32, device="cuda")
+        Vt = torch.empty((w.k, n), dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup):
+            plan.execute(A, U, S, Vt)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            plan.execute(A, U, S, Vt)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        resid = torch.linalg.norm(A64 - (U.double() * S.double()) @ Vt.double()).item() / nrm
+        res[label] = {"ms": ms, "iterations": plan.refine_iterations(), "rel_residual": resid,
+                      "flags": plan.status() & 0xFFFF}
+        plan.close()
+        progress(f"refine: {label} {res[label]}")
+    print(json.dumps({
+        "metric": "time-to-rank-k SVD (ms), Algorithm 2 to a tolerance", "value": res["to_eps"]["ms"],
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["to_eps"]["ms"], "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"snapshot-like {m}x{n}, 8x8 grid, k={w.k}, float32 storage, "
+                               f"refine_eps={args.refine_eps}, at most {args.refine_steps} iterations"},
+        "runs": res}))
 
 
 def run_uneven(args, torch):
@@ -438,6 +486,9 @@ def main():
         return
     if args.workload == "learned":
         run_learned(args, torch)
+        return
+    if args.workload == "refine":
+        run_refine(args, torch)
         return
     from paper_1710_02812_amd import hsvd as H, synth
 

@@ -78,6 +78,17 @@ typedef struct {
     int32_t  refine_steps;  /* iterations of Algorithm 2 after the projection, default 0 */
     int32_t  max_sweeps;    /* Jacobi sweep cap per core, default 40                    */
     uint64_t seed;          /* seed of the leaves' Gaussian test matrices, default 0    */
+    double   refine_eps;    /* Algorithm 2 to a tolerance, default 0 (off).  When > 0 and
+                               at least two iterations are asked for, the iterations stop
+                               after the first t >= 2 at which, for every matrix of the plan,
+                               ||s_t - s_(t-1)||_2 <= refine_eps ||s_(t-1)||_2 over its rank
+                               (s_t: singular values after iteration t); refine_steps (plus
+                               the mixed path's own iteration) is then the cap and the
+                               output is iteration t's.  Each test is taken on the device;
+                               the execute then waits for it (one 4-byte read-back per
+                               iteration from the second on, the last excepted), and
+                               per-launch timing (hsvd_set_profiling) is refused.  Must
+                               not be negative or NaN (HSVD_ERR_INVALID).                */
 } hsvd_options;
 
 /* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
@@ -103,7 +114,8 @@ hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int3
                          int32_t k, double tol, const hsvd_options* opt);
 
 /* Runs the method on A and writes the result.  Asynchronous, ordered on `stream`
- * (0 = the null stream); no host synchronisation inside.
+ * (0 = the null stream); no host synchronisation inside, except the waits of
+ * Algorithm 2 stopped on refine_eps (see hsvd_options).
  *   A  : m x n, row-major, contiguous (leading dimension n), read only.
  *   U  : m x k, row-major.   S : k, descending.   Vt : k x n, row-major.
  *   Element type double (FP64 plans) or float (FP32 plans).
@@ -141,6 +153,12 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan);
 /* Copies the effective rank of the last execute to *r_host (synchronises that
  * execute's stream).  Single-matrix plans only. */
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host);
+
+/* Iterations of Algorithm 2 (Section 3, iterative improvement) that the last execute
+ * of an SVD plan ran into its output: refine_steps (plus one on the mixed path) unless
+ * refine_eps stopped them earlier.  Host-side value, no synchronisation.
+ * HSVD_ERR_INVALID for NULL arguments or a block-feature plan.                    */
+hsvd_status hsvd_get_refine_iterations(hsvd_plan_t plan, int32_t* iters_host);
 
 /* Effective ranks of all `count` matrices of the last execute (count must equal
  * the plan's matrix count; synchronises). */

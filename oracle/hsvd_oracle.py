@@ -214,11 +214,12 @@ def sign_normalise(U, V):
 
 
 def hsvd(A, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
-         refine: int = 0, merge_fn=None):
+         refine: int = 0, merge_fn=None, refine_eps: float | None = None):
     """The whole method: returns (U [m x k], s [k], Vt [k x n], r), zero padded past r.
 
     Algorithm 1 gives (V-hat, S-hat); U follows by projection; `refine` runs
-    that many iterations of Algorithm 2.
+    that many iterations of Algorithm 2 (fewer when refine_eps stops them, as in
+    `improve`).
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -229,7 +230,7 @@ def hsvd(A, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
     U, s, V = project(A, Vh)
     r = s.size
     if refine > 0 and r > 0:
-        U, s, V = improve(A, V, r, refine)
+        U, s, V = improve(A, V, r, refine, refine_eps)
     U, V = sign_normalise(U, V)
     Uo = np.zeros((m, k))
     so = np.zeros(k)

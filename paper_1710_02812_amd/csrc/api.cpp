@@ -124,6 +124,16 @@ struct hsvd_plan_st {
     size_t outs_off = 0;           // OutputArgs array in the task blob
     int kmax = 0, mmax = 0, nmax = 0;
 
+    // Algorithm 2 stopped on a tolerance (refine_eps > 0, >= 2 iterations): the stages
+    // of iteration t end at seg_end[t]; after iteration t >= 1 a check compares its
+    // singular values with those of t - 1 (check_off[t]: RefineCheck array in the
+    // blob), and the output of an execute stopped after iteration t reads
+    // step_outs_off[t] with ranks in step_rank_slots[t].  Empty otherwise.
+    std::vector<size_t> seg_end, check_off, step_outs_off;
+    std::vector<std::vector<int>> step_rank_slots;
+    int check_slot = -1;
+    int refine_done = 0;           // iterations of Algorithm 2 run by the last execute
+
     // optional per-launch timing: events[i] .. events[i+1] bracket launch i
     bool profiling = false;
     std::vector<hipEvent_t> events;
@@ -922,8 +932,56 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     auto row_roots = merge_forest(P, row_forests);
     std::vector<Factors> f = build_projection(P, row_roots);
     const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
+    const bool eps_stop = P.opt.refine_eps > 0.0 && steps >= 2;
+    // output table of factors f (sign slots of its own)
+    auto out_table = [&](const std::vector<Factors>& ff, std::vector<int>& ranks) {
+        std::vector<OutputArgs> outs;
+        ranks.clear();
+        for (size_t mi = 0; mi < ff.size(); ++mi) {
+            const MatDesc& M = P.mats[mi];
+            OutputArgs o{};
+            o.u_off = ff[mi].U;
+            o.v_off = ff[mi].V;
+            o.sig_off = ff[mi].sig;
+            o.u_ld = (int)M.m;
+            o.v_ld = (int)M.n;
+            o.m = (int)M.m;
+            o.n = (int)M.n;
+            o.k = M.k;
+            o.rank_slot = ff[mi].rank;
+            o.sign_off = P.ialloc(M.k);
+            outs.push_back(o);
+            ranks.push_back(ff[mi].rank);
+        }
+        return outs;
+    };
+    P.seg_end.clear();
+    P.check_off.clear();
+    P.step_outs_off.clear();
+    P.step_rank_slots.clear();
+    P.refine_done = steps;
+    if (eps_stop) P.check_slot = P.ialloc(1);
+    std::vector<Factors> prev;
+    std::vector<OutputArgs> last_outs;
     for (int it = 0; it < steps; ++it) {
         f = build_refine_step(P, f);
+        if (eps_stop) {
+            P.seg_end.push_back(P.stages.size());
+            std::vector<RefineCheck> checks;
+            for (size_t mi = 0; it > 0 && mi < f.size(); ++mi) {
+                RefineCheck c{};
+                c.sig_old = prev[mi].sig;
+                c.sig_new = f[mi].sig;
+                c.rank_slot = f[mi].rank;
+                checks.push_back(c);
+            }
+            P.check_off.push_back(it > 0 ? P.put(checks) : 0);
+            std::vector<int> ranks;
+            last_outs = out_table(f, ranks);
+            P.step_outs_off.push_back(P.put(last_outs));
+            P.step_rank_slots.push_back(ranks);
+            prev = f;
+        }
         if (it + 1 < steps) {
             std::vector<Node> vs(f.size());
             for (size_t mi = 0; mi < f.size(); ++mi) {
@@ -937,29 +995,22 @@ hsvd_status build_plan(hsvd_plan_st& P) {
             f = build_projection(P, vs);
         }
     }
-    P.outs.clear();
-    P.rank_slots.clear();
     P.kmax = P.mmax = P.nmax = 0;
     for (size_t mi = 0; mi < f.size(); ++mi) {
         const MatDesc& M = P.mats[mi];
-        OutputArgs o{};
-        o.u_off = f[mi].U;
-        o.v_off = f[mi].V;
-        o.sig_off = f[mi].sig;
-        o.u_ld = (int)M.m;
-        o.v_ld = (int)M.n;
-        o.m = (int)M.m;
-        o.n = (int)M.n;
-        o.k = M.k;
-        o.rank_slot = f[mi].rank;
-        o.sign_off = P.ialloc(M.k);
-        P.outs.push_back(o);
-        P.rank_slots.push_back(f[mi].rank);
         P.kmax = std::max(P.kmax, M.k);
         P.mmax = std::max<int>(P.mmax, (int)M.m);
         P.nmax = std::max<int>(P.nmax, (int)M.n);
     }
-    P.outs_off = P.put(P.outs);
+    if (eps_stop) {
+        // the last iteration's table doubles as the plan's output
+        P.outs = last_outs;
+        P.outs_off = P.step_outs_off.back();
+        P.rank_slots = P.step_rank_slots.back();
+    } else {
+        P.outs = out_table(f, P.rank_slots);
+        P.outs_off = P.put(P.outs);
+    }
     return HSVD_OK;
 }
 
@@ -1291,6 +1342,7 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->refine_steps = 0;
     opt->max_sweeps = 40;
     opt->seed = 0;
+    opt->refine_eps = 0.0;
     return HSVD_OK;
 }
 
@@ -1325,6 +1377,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         return fail(HSVD_ERR_INVALID, "unknown rule");
     if (o.oversample < 0 || o.power_steps < 0 || o.refine_steps < 0 || o.max_sweeps < 1)
         return fail(HSVD_ERR_INVALID, "negative option");
+    if (!(o.refine_eps >= 0.0)) return fail(HSVD_ERR_INVALID, "need refine_eps >= 0");
 
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
@@ -1478,13 +1531,39 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
     if (e != hipSuccess) return hip_fail(e, "flags reset");
     const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
     if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
-    for (size_t i = 0; i < P.stages.size(); ++i) {
-        hsvd_status st = run_stage(P, P.stages[i], stream);
-        if (st != HSVD_OK) return st;
-        if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
+    size_t outs_off = P.outs_off;
+    if (P.seg_end.empty()) {
+        for (size_t i = 0; i < P.stages.size(); ++i) {
+            hsvd_status st = run_stage(P, P.stages[i], stream);
+            if (st != HSVD_OK) return st;
+            if (prof && (e = hipEventRecord(P.events[i + 1], stream)) != hipSuccess) return hip_fail(e, "event");
+        }
+    } else {
+        // Algorithm 2 until the singular values change by at most refine_eps (relative,
+        // 2-norm) between two iterations, at most refine_steps iterations: one 4-byte
+        // read-back and host wait per check (the decision itself is taken on the device)
+        const size_t nseg = P.seg_end.size();
+        size_t i = 0, used = nseg;
+        for (size_t t = 0; t < nseg; ++t) {
+            for (; i < P.seg_end[t]; ++i) {
+                hsvd_status st = run_stage(P, P.stages[i], stream);
+                if (st != HSVD_OK) return st;
+            }
+            if (t == 0 || t + 1 == nseg) continue;
+            e = launch_refine_check(P.ws, P.iws, (const RefineCheck*)((unsigned char*)P.dblob + P.check_off[t]),
+                                    (int)P.mats.size(), P.opt.refine_eps, P.check_slot, stream);
+            int done = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&done, P.iws + P.check_slot, sizeof(int), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "refinement check");
+            if (done) { used = t + 1; break; }
+        }
+        outs_off = P.step_outs_off[used - 1];
+        P.rank_slots = P.step_rank_slots[used - 1];
+        P.refine_done = (int)used;
     }
     e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws,
-                      (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)P.outs.size(), P.kmax, P.mmax,
+                      (const OutputArgs*)((unsigned char*)P.dblob + outs_off), (int)P.outs.size(), P.kmax, P.mmax,
                       P.nmax, (void* const*)P.dptrs, stream);
     if (e != hipSuccess) return hip_fail(e, "output launch");
     if (prof && (e = hipEventRecord(P.events.back(), stream)) != hipSuccess) return hip_fail(e, "event");
@@ -1518,6 +1597,8 @@ hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* c
 
 hsvd_status hsvd_set_profiling(hsvd_plan_t plan, int32_t enable) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (enable && !plan->seg_end.empty())
+        return fail(HSVD_ERR_UNSUPPORTED, "per-launch timing is not recorded when Algorithm 2 stops on refine_eps");
     if (enable && plan->events.empty()) {
         plan->events.resize(plan->stages.size() + 2);
         for (auto& ev : plan->events) {
@@ -1740,6 +1821,13 @@ hsvd_status hsvd_get_leaf_info(hsvd_plan_t plan, int32_t* ranks, int32_t* fallba
         if (ranks) ranks[b] = all[(size_t)plan->leaf_rank_slots[b]];
         if (fallback) fallback[b] = plan->leaf_flag_slots[b] >= 0 ? all[(size_t)plan->leaf_flag_slots[b]] : 0;
     }
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_refine_iterations(hsvd_plan_t plan, int32_t* iters_host) {
+    if (!plan || !iters_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan");
+    *iters_host = plan->refine_done;
     return HSVD_OK;
 }
 

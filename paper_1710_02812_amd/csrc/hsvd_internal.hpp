@@ -150,6 +150,12 @@ struct OutputArgs {
     int32_t sign_off;               // int arena: k signs
     int32_t pad;
 };
+// Stopping test of Algorithm 2 for one matrix: singular values of two consecutive
+// iterations (sig_old, sig_new, each rank_slot entries) compared in the 2-norm.
+struct RefineCheck {
+    int64_t sig_old, sig_new;
+    int32_t rank_slot, pad;
+};
 // Per-execute pointer table of a plan over `count` matrices: entries
 // [4 i .. 4 i + 3] are A, U, S, Vt of matrix i (device pointers).
 
@@ -207,6 +213,10 @@ hipError_t launch_block_features(const double* ws, int64_t sig_off, int64_t ener
                                  float* out, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// iws[out_slot] = 1 when every item has ||s_new - s_old||^2 <= eps^2 ||s_old||^2 over
+// its rank, else 0 (one work-group).
+hipError_t launch_refine_check(const double* ws, int* iws, const RefineCheck* items, int count, double eps,
+                               int out_slot, hipStream_t s);
 // Output of `count` matrices (args: device array; ptrs: the pointer table);
 // kmax, mmax, nmax bound k, m, n over the batch (grid sizes).
 hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,

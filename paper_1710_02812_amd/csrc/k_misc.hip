@@ -142,6 +142,44 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Stopping test of Algorithm 2 (the relative change of the singular values between
+// two iterations): one work-group, the items in turn, sums in a fixed order per lane
+// and a fixed tree, so the decision does not depend on timing.
+__global__ __launch_bounds__(256) void k_refine_check(const double* __restrict__ ws, int* __restrict__ iws,
+                                                      const RefineCheck* __restrict__ items, int count,
+                                                      double eps, int out_slot) {
+    __shared__ double s_num[256], s_den[256];
+    __shared__ int s_all;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_all = 1;
+    for (int i = 0; i < count; ++i) {
+        const RefineCheck c = items[i];
+        const int r = iws[c.rank_slot];
+        double num = 0.0, den = 0.0;
+        for (int j = tid; j < r; j += 256) {
+            const double o = ws[c.sig_old + j], d = ws[c.sig_new + j] - o;
+            num = fma(d, d, num);
+            den = fma(o, o, den);
+        }
+        s_num[tid] = num;
+        s_den[tid] = den;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) { s_num[tid] += s_num[tid + h]; s_den[tid] += s_den[tid + h]; }
+            __syncthreads();
+        }
+        if (tid == 0 && !(s_num[0] <= eps * eps * s_den[0])) s_all = 0;
+        __syncthreads();
+    }
+    if (tid == 0) iws[out_slot] = s_all;
+}
+
+hipError_t launch_refine_check(const double* ws, int* iws, const RefineCheck* items, int count, double eps,
+                               int out_slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(256), 0, s, ws, iws, items, count, eps, out_slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,
                          int kmax, int mmax, int nmax, void* const* ptrs, hipStream_t s) {
     if (count <= 0) return hipSuccess;

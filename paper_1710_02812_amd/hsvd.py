@@ -25,6 +25,7 @@ FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 
 EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute", "hsvd_destroy",
             "hsvd_get_rank", "hsvd_get_status", "hsvd_workspace_bytes", "hsvd_last_error",
+            "hsvd_get_refine_iterations",
             "hsvd_set_profiling", "hsvd_launch_times", "hsvd_launch_work",
             "hsvd_plan_batched", "hsvd_execute_batched", "hsvd_get_ranks",
             "hsvd_features_plan", "hsvd_features_execute", "hsvd_plan_widths", "hsvd_get_leaf_info",
@@ -48,7 +49,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("power_steps", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double)]
 
 
 _lib = None
@@ -70,6 +71,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_execute.argtypes = [vp, vp, vp, vp, vp, vp]
     L.hsvd_destroy.argtypes = [vp]
     L.hsvd_get_rank.argtypes = [vp, P(i32)]
+    L.hsvd_get_refine_iterations.argtypes = [vp, P(i32)]
     L.hsvd_get_status.argtypes = [vp, P(ctypes.c_uint32)]
     L.hsvd_workspace_bytes.argtypes = [vp, P(ctypes.c_size_t)]
     L.hsvd_last_error.restype = ctypes.c_char_p
@@ -123,7 +125,8 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed) -> Options:
+def _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed,
+             refine_eps: float = 0.0) -> Options:
     o = default_options()
     o.precision = precision
     o.rule = rule
@@ -135,6 +138,7 @@ def _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps,
     if max_sweeps is not None:
         o.max_sweeps = max_sweeps
     o.seed = seed
+    o.refine_eps = float(refine_eps)
     return o
 
 
@@ -144,7 +148,8 @@ class Plan:
     def __init__(self, m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, *,
                  precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
                  power_steps: int | None = None, refine_steps: int = 0,
-                 max_sweeps: int | None = None, seed: int = 0, leaf_widths=None):
+                 max_sweeps: int | None = None, seed: int = 0, leaf_widths=None,
+                 refine_eps: float = 0.0):
         """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths)."""
         o = default_options()
         o.precision = precision
@@ -157,6 +162,7 @@ class Plan:
         if max_sweeps is not None:
             o.max_sweeps = max_sweeps
         o.seed = seed
+        o.refine_eps = float(refine_eps)
         h = ctypes.c_void_p()
         if leaf_widths is None:
             _check(lib().hsvd_plan_ex(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
@@ -184,6 +190,12 @@ class Plan:
     def rank(self) -> int:
         r = ctypes.c_int32()
         _check(lib().hsvd_get_rank(self._h, ctypes.byref(r)))
+        return r.value
+
+    def refine_iterations(self) -> int:
+        """Algorithm 2 iterations the last execute ran (hsvd_get_refine_iterations)."""
+        r = ctypes.c_int32()
+        _check(lib().hsvd_get_refine_iterations(self._h, ctypes.byref(r)))
         return r.value
 
     def leaf_info(self):
@@ -370,7 +382,8 @@ class BatchPlan:
 
     def __init__(self, shapes, tol: float = 0.0, *, precision: int = FP64, rule: int = RULE_GAMMA,
                  oversample: int | None = None, power_steps: int | None = None,
-                 refine_steps: int = 0, max_sweeps: int | None = None, seed: int = 0):
+                 refine_steps: int = 0, max_sweeps: int | None = None, seed: int = 0,
+                 refine_eps: float = 0.0):
         """shapes: list of (m, n, p, q, k)."""
         c = len(shapes)
         i64a, i32a = ctypes.c_int64 * c, ctypes.c_int32 * c
@@ -379,7 +392,8 @@ class BatchPlan:
         ps = i32a(*[s[2] for s in shapes])
         qs = i32a(*[s[3] for s in shapes])
         ks = i32a(*[s[4] for s in shapes])
-        o = _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed)
+        o = _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed,
+                     refine_eps)
         h = ctypes.c_void_p()
         _check(lib().hsvd_plan_batched(ctypes.byref(h), c, ms, ns, ps, qs, ks, float(tol), ctypes.byref(o)))
         self._h = h

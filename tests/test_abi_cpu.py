@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = H.default_options()
     assert (o.precision, o.rule, o.oversample, o.power_steps, o.refine_steps, o.max_sweeps,
-            o.seed) == (0, 0, 14, 1, 0, 40, 0)
+            o.seed, o.refine_eps) == (0, 0, 14, 1, 0, 40, 0, 0.0)
 
 
 @pytest.mark.parametrize("args", [
@@ -61,6 +61,11 @@ def test_plan_rejects_bad_options_and_unsupported_rank():
     o = H.default_options()
     o.max_sweeps = 0
     assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
+    for bad in (-1e-3, float("nan")):
+        o = H.default_options()
+        o.refine_steps, o.refine_eps = 3, bad
+        assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
+        assert "refine_eps" in lib.hsvd_last_error().decode()
     assert lib.hsvd_plan(ctypes.byref(h), 1000, 1000, 2, 2, 65, 0.0) == 6
     assert lib.hsvd_plan(None, 100, 100, 2, 2, 5, 0.0) == 1
 
@@ -75,6 +80,7 @@ def test_null_handles():
     assert lib.hsvd_debug_jacobi(None, 1, 4, None, None, None, 10, 0, None, None) == 1
     assert lib.hsvd_debug_tsqr(None, 1, 4, 4, None, None, None) == 1
     assert lib.hsvd_debug_cholqr(None, 1, 4, 4, None, None, None, None) == 1
+    assert lib.hsvd_get_refine_iterations(None, ctypes.byref(r)) == 1
 
 
 @pytest.mark.parametrize("shape", [
@@ -90,6 +96,8 @@ def test_null_handles():
     (2049, 4097, 3, 9, 64, {"oversample": 40}),
     (8192, 8192, 8, 8, 50, {"precision": 2}),
     (1000, 900, 3, 4, 20, {"precision": 2, "refine_steps": 1}),
+    (1000, 900, 3, 4, 20, {"refine_steps": 4, "refine_eps": 1e-6}),
+    (1000, 900, 3, 4, 20, {"precision": 2, "refine_steps": 2, "refine_eps": 1e-3}),
 ])
 def test_plan_footprint_is_in_bounds(shape):
     """Every task of every launch stays inside the plan's buffers (host-side check)."""

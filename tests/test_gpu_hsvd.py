@@ -135,6 +135,63 @@ def test_refinement_step_matches_oracle():
     assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10
 
 
+def _refine_case():
+    rng = np.random.default_rng(9)
+    sigma = np.exp(-np.arange(30) / 4.0)
+    A, *_ = synth.low_rank(rng, 600, 600, sigma, noise=1e-9)
+    return A
+
+
+@pytest.mark.parametrize("eps_kind", ["between", "loose", "tight"])
+def test_refinement_to_tolerance_matches_oracle(eps_kind):
+    """Algorithm 2 iterated until the singular values change by at most eps (relative,
+    2-norm) between two iterations, at most 6: the GPU stops at the oracle's iteration
+    and returns its factors.  eps sits a factor of ~3 away from the changes on either
+    side (they fall ~8x per iteration here), far outside both paths' rounding."""
+    A = _refine_case()
+    ss = [oracle.hsvd(A, 3, 3, 20, 0.0, "gamma", refine=t)[1] for t in range(1, 7)]
+    ch = [np.linalg.norm(ss[t] - ss[t - 1]) / np.linalg.norm(ss[t - 1]) for t in range(1, 6)]
+    assert all(b < a / 3 for a, b in zip(ch, ch[1:])), ch
+    eps, want = {"between": (np.sqrt(ch[1] * ch[2]), 4), "loose": (1.0, 2), "tight": (1e-300, 6)}[eps_kind]
+    Uo, so, Vto, ro = oracle.hsvd(A, 3, 3, 20, 0.0, "gamma", refine=6, refine_eps=eps)
+    At = torch.tensor(A, device=DEV)
+    plan = H.Plan(600, 600, 3, 3, 20, refine_steps=6, refine_eps=eps)
+    U = torch.empty((600, 20), dtype=torch.float64, device=DEV)
+    S = torch.empty((20,), dtype=torch.float64, device=DEV)
+    Vt = torch.empty((20, 600), dtype=torch.float64, device=DEV)
+    for _ in range(2):                      # a second execute of the plan decides afresh
+        print("refine_eps", eps_kind, eps, flush=True)
+        plan.execute(At, U, S, Vt)
+        torch.cuda.synchronize()
+        assert plan.refine_iterations() == want
+        rg = plan.rank()
+        assert rg == ro
+        c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), rg, Uo, so, Vto, ro)
+        print(c, flush=True)
+        assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10
+    assert plan.status() & 0xFFFF == 0
+    with pytest.raises(H.HsvdError):
+        H._check(H.lib().hsvd_set_profiling(plan._h, 1))
+    plan.close()
+
+
+def test_refinement_without_tolerance_runs_every_iteration():
+    """refine_eps = 0 (default): all refine_steps iterations, as before."""
+    A = _refine_case()
+    At = torch.tensor(A, device=DEV)
+    plan = H.Plan(600, 600, 3, 3, 20, refine_steps=3)
+    U = torch.empty((600, 20), dtype=torch.float64, device=DEV)
+    S = torch.empty((20,), dtype=torch.float64, device=DEV)
+    Vt = torch.empty((20, 600), dtype=torch.float64, device=DEV)
+    plan.execute(At, U, S, Vt)
+    torch.cuda.synchronize()
+    assert plan.refine_iterations() == 3
+    Uo, so, Vto, ro = oracle.hsvd(A, 3, 3, 20, 0.0, "gamma", refine=3)
+    c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), plan.rank(), Uo, so, Vto, ro)
+    assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10
+    plan.close()
+
+
 def test_plan_reuse_and_repeatability():
     """Two executes of one plan give bit-identical results (no stale state)."""
     w = synth.config0(0)

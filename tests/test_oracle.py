@@ -267,6 +267,29 @@ def test_algorithm2_converges_to_top_subspace():
     assert errs[2] <= errs[1] * 0.1
 
 
+def test_algorithm2_tolerance_stop():
+    """Algorithm 2 to a tolerance: the first iteration t >= 2 whose singular values
+    moved by at most eps (relative 2-norm) from iteration t - 1 ends it, and its
+    factors are the result (the same as a fixed count of t); the cap still holds."""
+    rng = np.random.default_rng(52)
+    m, n, r = 200, 160, 8
+    sigma = np.concatenate([np.linspace(10, 6, r), 3.0 * np.exp(-np.arange(n - r) / 20)])
+    A, *_ = synth.low_rank(rng, m, n, sigma)
+    _, _, Vt, rr = oracle.hsvd(A, 2, 2, r, tol=0.0)
+    Vh = Vt[:rr].T
+    runs = [oracle.improve(A, Vh, rr, t) for t in range(1, 7)]
+    ch = [np.linalg.norm(runs[t][1] - runs[t - 1][1]) / np.linalg.norm(runs[t - 1][1]) for t in range(1, 6)]
+    assert all(b < a for a, b in zip(ch, ch[1:])), ch      # a power iteration settles
+    for stop in (2, 3, 4):
+        eps = np.sqrt(ch[stop - 2] * ch[stop - 3]) if stop > 2 else 2 * ch[0]
+        got = oracle.improve(A, Vh, rr, 6, eps)
+        for x, y in zip(got, runs[stop - 1]):
+            assert np.array_equal(x, y), stop
+    got = oracle.improve(A, Vh, rr, 3, 1e-300)                # never met: the cap
+    for x, y in zip(got, runs[2]):
+        assert np.array_equal(x, y)
+
+
 # ----------------------------------------------------------------------------- config C0
 def test_config0_against_constructed_svd():
     """C0 (512^2, rank 20, noise 1e-8): result within noise of the constructed factors."""
