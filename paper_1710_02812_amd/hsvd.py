@@ -423,6 +423,12 @@ class BatchPlan:
         _check(lib().hsvd_get_ranks(self._h, r, c))
         return list(r)
 
+    def refine_iterations(self) -> int:
+        """Algorithm 2 iterations the last execute ran (one count for the whole batch)."""
+        r = ctypes.c_int32()
+        _check(lib().hsvd_get_refine_iterations(self._h, ctypes.byref(r)))
+        return r.value
+
     def status(self) -> int:
         f = ctypes.c_uint32()
         _check(lib().hsvd_get_status(self._h, ctypes.byref(f)))

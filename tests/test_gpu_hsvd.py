@@ -175,6 +175,37 @@ def test_refinement_to_tolerance_matches_oracle(eps_kind):
     plan.close()
 
 
+def test_refinement_to_tolerance_batched_waits_for_every_matrix():
+    """A batch stops when every matrix meets eps: the slow matrix sets the count (4 here)
+    and the fast one (exact rank, converged at once) runs as many iterations."""
+    A1 = _refine_case()
+    rng = np.random.default_rng(10)
+    A2, *_ = synth.low_rank(rng, 400, 300, np.linspace(5.0, 1.0, 10))
+    ss = [oracle.hsvd(A1, 3, 3, 20, 0.0, "gamma", refine=t)[1] for t in range(1, 7)]
+    ch = [np.linalg.norm(ss[t] - ss[t - 1]) / np.linalg.norm(ss[t - 1]) for t in range(1, 6)]
+    eps = np.sqrt(ch[1] * ch[2])
+    print("batched refine_eps", eps, flush=True)
+    shapes = [(600, 600, 3, 3, 20), (400, 300, 2, 2, 10)]
+    plan = H.BatchPlan(shapes, refine_steps=6, refine_eps=eps)
+    As = [torch.tensor(A1, device=DEV), torch.tensor(A2, device=DEV)]
+    Us = [torch.empty((m, k), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+    Ss = [torch.empty((k,), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+    Vts = [torch.empty((k, n), dtype=torch.float64, device=DEV) for (m, n, _, _, k) in shapes]
+    plan.execute(As, Us, Ss, Vts)
+    torch.cuda.synchronize()
+    assert plan.refine_iterations() == 4
+    rs = plan.ranks()
+    assert plan.status() & 0xFFFF == 0
+    plan.close()
+    outs = list(zip(Us, Ss, Vts, rs))
+    for (U, S, Vt, r), (A, p, k) in zip(outs, ((A1, 3, 20), (A2, 2, 10))):
+        Uo, so, Vto, ro = oracle.hsvd(A, p, p, k, 0.0, "gamma", refine=4)
+        assert r == ro
+        c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), r, Uo, so, Vto, ro)
+        print(c, flush=True)
+        assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10
+
+
 def test_refinement_without_tolerance_runs_every_iteration():
     """refine_eps = 0 (default): all refine_steps iterations, as before."""
     A = _refine_case()
