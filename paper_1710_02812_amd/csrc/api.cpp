@@ -6,7 +6,9 @@
 // (0,1), (2,3), ... left to right, an odd last node carried up), the layout of
 // every panel in one device arena, and the task tables of each launch.  Ranks
 // chosen by the truncation rule stay on the device; kernels read them, so an
-// execute is a fixed sequence of launches with no host round trip.
+// execute is a fixed sequence of launches with no host round trip (except when
+// Algorithm 2 stops on a tolerance: one 4-byte read of the device's decision per
+// iteration from the second on).
 //
 // Execute = the stages below, in order:
 //   leaves      : Y = A_b Omega, then alternately QR and products with A_b^T / A_b
@@ -19,7 +21,8 @@
 //   row tree    : the same merge on the V panels (height n);
 //   projection  : Y = A V (split over column blocks), TSQR, Jacobi with rotations
 //                 -> U = Q_Y Z, V = V J (Section 3, left vectors by projection);
-//   refinement  : optional Algorithm 2 iterations;
+//   refinement  : optional Algorithm 2 iterations (a fixed count, or until the
+//                 singular values change by at most refine_eps between two);
 //   output      : sign normalisation and the row-major U, S, Vt writes.
 #include "../../include/hsvd.h"
 #include "hsvd_internal.hpp"
