@@ -47,9 +47,11 @@ __device__ __forceinline__ double vref(const double* A, int64_t ld, int i, int l
 // value once for both of its columns and keeps it in registers): 512 threads x 16
 // rows per lane for panels up to 64 columns (256-row chunks), 768 threads x 10 rows
 // for panels up to 80 (160-row chunks, 96 columns of capacity).
+// The 768-thread variant (3 waves per SIMD, <= 170 registers a lane) keeps no pivot
+// values in registers (read twice from LDS instead), which keeps it free of spills.
 constexpr int TSQR_CPL = 2;
 template <int LANES, int RMAX, int NTHR>
-using TsqrQR = HouseQR<LANES, RMAX, true, RMAX, TSQR_CPL, NTHR>;
+using TsqrQR = HouseQR<LANES, RMAX, true, (NTHR > 512 ? 1 : RMAX), TSQR_CPL, NTHR>;
 
 template <int LANES, int RMAX, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_tsqr_factor(double* __restrict__ ws,
