@@ -4,6 +4,30 @@
 
 namespace hsvd {
 
+// Arrival at a node of a reduction tree that spans work-groups (the last of `n`
+// children to arrive continues with the node).  Every wave first waits for its own
+// global stores; one thread then publishes them all with an agent-scope release on
+// the arrival count (one L2 write-back for the block), and only the last arrival takes
+// the agent-scope acquire (one L2 invalidate) before the block reads its siblings'
+// results.  Fences in every wave would write back and invalidate the L2 once per wave,
+// discarding the cached data of every other work-group on the same XCD.  The last
+// arrival resets the count; s_flag is a __shared__ int; all threads must call it.
+__device__ __forceinline__ bool tree_arrive(int* count, int n, int* s_flag) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);           // vmcnt(0): this wave's stores are done
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int old = __hip_atomic_fetch_add(count, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int last = old == n - 1;
+        if (last) {
+            atomicExch(count, 0);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *s_flag = last;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
 // Move a double between lanes with a DPP control (GFX9 encodings):
 //   0xB1 quad_perm[1,0,3,2] (lane ^ 1), 0x4E quad_perm[2,3,0,1] (lane ^ 2),
 //   0x141 row_half_mirror (lane i <-> 7-i within 8), 0x140 row_mirror (i <-> 15-i).

@@ -168,19 +168,12 @@ __global__ __launch_bounds__(256) void k_cholqr(double* __restrict__ ws, int* __
     double* level = parts;                              // the current level's sums
     int n = t.nch, idx = cr.chunk, cnt = t.cq_cnt;
     for (;;) {
-        __threadfence();
-        __syncthreads();
         const int parent = idx / kCqFan;
         const int first = parent * kCqFan, nchild = min(kCqFan, n - first);
         if (n > 1) {
-            if (tid == 0) {
-                const int old = atomicAdd(&iws[cnt + parent], 1);
-                s_last = (old == nchild - 1);
-                if (s_last) atomicExch(&iws[cnt + parent], 0);
-            }
+            if (!tree_arrive(&iws[cnt + parent], nchild, &s_last)) return;
+        } else {
             __syncthreads();
-            if (!s_last) return;
-            __threadfence();
         }
         const int up = n > 1 ? cq_up(n) : 1;
         double* next = level + (int64_t)n * ww;

@@ -110,17 +110,8 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_factor(double* __restrict__ ws,
             q.store_r(dst, cur_rows, w);
         }
         if (nsib == 1) break;                                       // reached the root
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            const int cslot = node_slot(t.nch, F, level, parent);
-            const int old = atomicAdd(&iws[t.cnt_off + cslot], 1);
-            s_go = (old == nsib - 1);
-            if (old == nsib - 1) atomicExch(&iws[t.cnt_off + cslot], 0);
-        }
-        __syncthreads();
-        if (!s_go) return;                                          // a later sibling merges
-        __threadfence();
+        if (!tree_arrive(&iws[t.cnt_off + node_slot(t.nch, F, level, parent)], nsib, &s_go))
+            return;                                                 // a later sibling merges
         {
             // the children are consecutive slots of the level below
             const double* c0 = store + S * node_slot(t.nch, F, level - 1, parent * F);
