@@ -179,6 +179,27 @@ def test_cholqr_well_conditioned(h, w, kappa):
         assert np.max(np.abs(np.linalg.svd(R[b], compute_uv=False) - s_ref)) <= 1e-13 * s_ref[0]
 
 
+def test_trees_with_many_panels_in_flight():
+    """Many panels factored at once, so that the work-groups of every reduction tree
+    (the TSQR R tree, wide 768-thread variant, and the Cholesky QR Gram tree) arrive
+    from all XCDs concurrently: each panel still gives P = Q R with Q orthonormal."""
+    rng = np.random.default_rng(77)
+    for kind, (b, h, w) in (("tsqr", (48, 3000, 80)), ("cholqr", (64, 4096, 50))):
+        P = rng.standard_normal((b, h, w))
+        print(f"{kind} batch={b} h={h} w={w}", flush=True)
+        if kind == "tsqr":
+            Q, R = H.debug_tsqr(_t(P))
+        else:
+            Q, R, fb = H.debug_cholqr(_t(P))
+            assert fb == [0] * b
+        Q, R = Q.cpu().numpy(), R.cpu().numpy()
+        res = np.linalg.norm(np.einsum("bij,bjk->bik", Q, R) - P, axis=(1, 2)) / np.linalg.norm(P, axis=(1, 2))
+        orth = np.linalg.norm(np.einsum("bji,bjk->bik", Q, Q) - np.eye(w), axis=(1, 2))
+        assert np.all(np.tril(R, -1) == 0.0) if kind == "cholqr" else np.allclose(np.tril(R, -1), 0.0)
+        assert res.max() <= 1e-13, (kind, res.max())
+        assert orth.max() <= 1e-13 * np.sqrt(h) * w, (kind, orth.max())
+
+
 @pytest.mark.parametrize("h,w", [(600, 40), (5000, 64), (300, 7)])
 def test_cholqr_fallback_and_dead_columns(h, w):
     """An ill-conditioned panel (a column within 1e-9 of its predecessors' span) falls
