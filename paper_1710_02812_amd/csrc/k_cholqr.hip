@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_cholqr(double* __restrict__ ws, int* __
     __shared__ double d0[64];
     __shared__ double s_d[64];
     __shared__ int s_last, s_fail, s_cfail;
+    __shared__ double s_part[4];
     const ChunkRef cr = chunks[blockIdx.x];
     const TsqrTask t = tasks[cr.task];
     if (t.cq_flag < 0) return;
@@ -215,19 +216,18 @@ __global__ __launch_bounds__(256) void k_cholqr(double* __restrict__ ws, int* __
     for (int j = tid; j < w; j += blockDim.x) d0[j] = G[(int64_t)j * ld + j];
     __syncthreads();
     if (PASS == 2) {
-        // ||Q1^T Q1 - I||_F over the live columns
-        if (tid < 64) {
-            double s = 0.0;
-            for (int e = tid; e < w * w; e += 64) {
-                const int j = e / w, i = e - j * w;
-                if (d0[i] != 0.0 && d0[j] != 0.0) {
-                    const double v = G[(int64_t)j * ld + i] - (i == j ? 1.0 : 0.0);
-                    s = fma(v, v, s);
-                }
-            }
-            s = wave_sum(s);
-            if (tid == 0 && !(s <= 1.0 / 16.0)) s_fail = 1;
+        // ||Q1^T Q1 - I||_F over the live columns, spread over the four waves
+        double s = 0.0;
+#pragma unroll 4
+        for (int e = tid; e < w * w; e += 256) {
+            const int j = e / w, i = e - j * w;
+            const double v = G[(int64_t)j * ld + i] - (i == j ? 1.0 : 0.0);
+            s = (d0[i] != 0.0 && d0[j] != 0.0) ? fma(v, v, s) : s;
         }
+        s = wave_sum(s);
+        if ((tid & 63) == 0) s_part[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0 && !((s_part[0] + s_part[1]) + (s_part[2] + s_part[3]) <= 1.0 / 16.0)) s_fail = 1;
         __syncthreads();
         if (s_fail) {
             if (tid == 0) iws[t.cq_flag] = 1;
