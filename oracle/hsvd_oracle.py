@@ -41,6 +41,9 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
      largest magnitude is positive (ties: lowest index).
   R9 'frob' rule (used by the learned-rank workload): smallest r whose discarded
      tail energy sum_{i>=r} s_i^2 is <= tol^2 * sum s_i^2, then the zero floor.
+  R17 Algorithm 2's error is tested after every iteration, the first one included
+     (against the Sigma-hat it was given, Algorithm 1's), and the loop ends at the
+     first error <= eps.
 """
 from __future__ import annotations
 
@@ -106,6 +109,25 @@ def leaf(block: np.ndarray, k: int, tol: float, rule: str):
     return U[:, :r], s[:r]
 
 
+def randomised_leaf(block: np.ndarray, k: int, tol: float, rule: str, omega: np.ndarray,
+                    power: int):
+    """Truncated SVD of one block by a randomised range finder (Conclusions: the block
+    SVDs may be randomised), used only to measure how far such leaves move the result
+    from the exact ones.
+
+    omega (cols x l) is the Gaussian test matrix, passed in.  Y = block omega; then
+    `power` times Q = orth(Y), Z = orth(block^T Q), Y = block Z; Q = orth(Y);
+    B = Q^T block = U_B S V^T; the leaf is (Q U_B, S) truncated by the same rule.
+    """
+    Q, _ = np.linalg.qr(block @ omega)
+    for _ in range(power):
+        Z, _ = np.linalg.qr(block.T @ Q)
+        Q, _ = np.linalg.qr(block @ Z)
+    Ub, s, _ = _svd(Q.T @ block)
+    r = truncation_rank(s, k, tol, rule, block.shape)
+    return (Q @ Ub)[:, :r], s[:r]
+
+
 def merge(U1, s1, U2, s2, k: int, tol: float, rule: str):
     """One merge-and-truncate step on left factors (Section 3, column-split identity).
 
@@ -161,13 +183,19 @@ def merge_tree(nodes, k: int, tol: float, rule: str, merge_fn=None):
 
 
 # ----------------------------------------------------------------------------- Algorithm 1
-def slab_nodes(A, p: int, q: int, k: int, tol: float, rule: str, merge_fn=None):
-    """For each row slab: column MAT tree, then V_i, S_i = SVD(U_i^T X_i) (Algorithm 1)."""
+def slab_nodes(A, p: int, q: int, k: int, tol: float, rule: str, merge_fn=None, leaf_fn=None):
+    """For each row slab: column MAT tree, then V_i, S_i = SVD(U_i^T X_i) (Algorithm 1).
+
+    leaf_fn(block, k, tol, rule, i, j) replaces the exact leaf SVD of block (i, j)."""
     m, n = A.shape
     out = []
-    for (r0, r1) in balanced_split(m, p):
+    for i, (r0, r1) in enumerate(balanced_split(m, p)):
         X = A[r0:r1]
-        leaves = [leaf(X[:, c0:c1], k, tol, rule) for (c0, c1) in balanced_split(n, q)]
+        if leaf_fn is None:
+            leaves = [leaf(X[:, c0:c1], k, tol, rule) for (c0, c1) in balanced_split(n, q)]
+        else:
+            leaves = [leaf_fn(X[:, c0:c1], k, tol, rule, i, j)
+                      for j, (c0, c1) in enumerate(balanced_split(n, q))]
         Ui, si = merge_tree(leaves, k, tol, rule, merge_fn)
         W = Ui.T @ X                                    # r_i x n
         _, sw, Vwt = _svd(W)
@@ -184,21 +212,32 @@ def project(A, V):
     return Uy[:, :r], sy[:r], V @ Vyt[:r].T
 
 
-def improve(A, V, r_freeze: int, iters: int, eps: float | None = None):
-    """Algorithm 2 (iterative improvement; R6).  Runs `iters` iterations, or until the
-    relative change of the singular values is <= eps when eps is given (at most `iters`)."""
-    s_prev = None
-    U = s = None
-    for _ in range(iters):
-        Ui, si, _ = _svd(A @ V)
-        Ui = Ui[:, :r_freeze]
+def improve(A, V, s_hat, iters: int, eps: float | None = None):
+    """Algorithm 2 (iterative improvement; R6, R17).
+
+    Input: A, V-hat (n x r) and Sigma-hat (r values: Algorithm 1's singular values).
+    Each iteration: U_i = left singular vectors of A V-hat (r of them);
+    U~ S~ V~^T = SVD(U_i^T A); Error = ||Sigma-hat - S~||_2 / ||Sigma-hat||_2;
+    Sigma-hat <- S~, V-hat <- V~, U-hat = U_i U~.  The loop is a do-while: the first
+    iteration is tested against the input Sigma-hat, and the loop ends at the first
+    Error <= eps (eps None: exactly `iters` iterations; otherwise at most `iters`).
+    Returns (U-hat, Sigma-hat, V-hat, iterations run).
+    """
+    s_hat = np.asarray(s_hat, dtype=np.float64)
+    r = V.shape[1]
+    U = None
+    t = 0
+    for t in range(1, iters + 1):
+        Ui, _, _ = _svd(A @ V)
+        Ui = Ui[:, :r]
         Ut, st, Vtt = _svd(Ui.T @ A)
-        U, s, V = Ui @ Ut, st, Vtt.T
-        if eps is not None and s_prev is not None:
-            if np.linalg.norm(s_prev - s) <= eps * np.linalg.norm(s_prev):
-                break
-        s_prev = s
-    return U, s, V
+        U, V = Ui @ Ut, Vtt.T
+        den = np.linalg.norm(s_hat)
+        err = np.linalg.norm(s_hat - st) / den if den > 0.0 else 0.0
+        s_hat = st
+        if eps is not None and err <= eps:
+            break
+    return U, s_hat, V, t
 
 
 def sign_normalise(U, V):
@@ -214,23 +253,28 @@ def sign_normalise(U, V):
 
 
 def hsvd(A, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
-         refine: int = 0, merge_fn=None, refine_eps: float | None = None):
+         refine: int = 0, merge_fn=None, refine_eps: float | None = None, leaf_fn=None,
+         info: dict | None = None):
     """The whole method: returns (U [m x k], s [k], Vt [k x n], r), zero padded past r.
 
     Algorithm 1 gives (V-hat, S-hat); U follows by projection; `refine` runs
     that many iterations of Algorithm 2 (fewer when refine_eps stops them, as in
-    `improve`).
+    `improve`, whose input Sigma-hat is Algorithm 1's).  `info`, when given,
+    receives the iterations of Algorithm 2 actually run.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if not (1 <= p <= m and 1 <= q <= n and 1 <= k <= min(m, n) and 0.0 <= tol < 1.0):
         raise ValueError("invalid arguments")
-    slabs = slab_nodes(A, p, q, k, tol, rule, merge_fn)
+    slabs = slab_nodes(A, p, q, k, tol, rule, merge_fn, leaf_fn)
     Vh, sh = merge_tree(slabs, k, tol, rule, merge_fn)
     U, s, V = project(A, Vh)
     r = s.size
+    done = 0
     if refine > 0 and r > 0:
-        U, s, V = improve(A, V, r, refine, refine_eps)
+        U, s, V, done = improve(A, V, sh[:r], refine, refine_eps)
+    if info is not None:
+        info["refine_iterations"] = done
     U, V = sign_normalise(U, V)
     Uo = np.zeros((m, k))
     so = np.zeros(k)

@@ -246,6 +246,12 @@ def test_projection_invariants_inexact_input():
     assert 1e-6 < e < 0.2
 
 
+def _algorithm1_sigma(A, p, q, k, tol=0.0):
+    """Algorithm 1's (V-hat, Sigma-hat): the root of the row-slab tree."""
+    slabs = oracle.slab_nodes(A, p, q, k, tol, "gamma")
+    return oracle.merge_tree(slabs, k, tol, "gamma")
+
+
 def test_algorithm2_converges_to_top_subspace():
     """Algorithm 2 is a power iteration: more iterations approach the top-r
     subspace (constructed), monotonically, to ~1e-10 on a gapped spectrum."""
@@ -253,13 +259,13 @@ def test_algorithm2_converges_to_top_subspace():
     m, n, r = 300, 240, 10
     sigma = np.concatenate([np.linspace(10, 5, r), 0.8 * np.exp(-np.arange(n - r) / 30)])
     A, U0, s0, V0 = synth.low_rank(rng, m, n, sigma)
-    U, s, Vt, rr = oracle.hsvd(A, 4, 4, r, tol=0.0)
-    assert rr == r
-    prev = metrics.sin_theta(Vt[:r].T, V0[:, :r])
-    Vh = Vt[:r].T
+    Vh, sh = _algorithm1_sigma(A, 4, 4, r)
+    assert sh.size == r
+    prev = metrics.sin_theta(Vh, V0[:, :r])
     errs = [prev]
     for it in range(1, 12):
-        _, _, V = oracle.improve(A, Vh, r, it)
+        _, _, V, done = oracle.improve(A, Vh, sh, it)
+        assert done == it
         errs.append(metrics.sin_theta(V, V0[:, :r]))
     assert all(b <= a * 1.0001 + 1e-15 for a, b in zip(errs, errs[1:]))
     assert errs[-1] <= 1e-10
@@ -267,27 +273,167 @@ def test_algorithm2_converges_to_top_subspace():
     assert errs[2] <= errs[1] * 0.1
 
 
+def _algorithm2_closed_form(s1, s2, theta0, s_hat0, iters):
+    """Algorithm 2 on X = diag(s1, s2) (plus a zero row) with rank 1 and
+    V-hat = (cos theta, sin theta): X V-hat = (s1 c, s2 s, 0) has the single
+    singular value rho = sqrt(s1^2 c^2 + s2^2 s^2) and left vector X V-hat / rho;
+    U_i^T X = (s1^2 c, s2^2 s) / rho, so S~ = sqrt(s1^4 c^2 + s2^4 s^2) / rho and
+    V~ points along (s1^2 c, s2^2 s): tan theta' = (s2 / s1)^2 tan theta.
+    Returns the per-iteration (S~, Error, theta)."""
+    out, sh, th = [], s_hat0, theta0
+    for _ in range(iters):
+        c, s = np.cos(th), np.sin(th)
+        rho = np.hypot(s1 * c, s2 * s)
+        st = np.hypot(s1 * s1 * c, s2 * s2 * s) / rho
+        err = abs(sh - st) / sh
+        th = np.arctan2(s2 * s2 * s, s1 * s1 * c)
+        out.append((st, err, th))
+        sh = st
+    return out
+
+
+def _alg2_pin(improve_fn) -> bool:
+    s1, s2, th0 = 2.0, 1.0, 0.5
+    X = np.array([[s1, 0.0], [0.0, s2], [0.0, 0.0]])
+    V0 = np.array([[np.cos(th0)], [np.sin(th0)]])
+    s_hat0 = 1.5                                   # far from both rho and S~_1
+    cf = _algorithm2_closed_form(s1, s2, th0, s_hat0, 8)
+    errs = [e for _, e, _ in cf]
+    ok = all(b < a for a, b in zip(errs, errs[1:]))
+    for stop in range(1, 6):
+        # eps between the errors of iterations stop and stop - 1 (the first
+        # iteration's own test ends the loop at stop = 1)
+        eps = errs[0] * 1.01 if stop == 1 else np.sqrt(errs[stop - 1] * errs[stop - 2])
+        U, s, V, done = improve_fn(X, V0, np.array([s_hat0]), 8, eps)
+        st, _, th = cf[stop - 1]
+        thp = cf[stop - 2][2] if stop > 1 else th0   # U-hat = U_i U~ spans X V-hat of
+        vp = np.array([np.cos(thp), np.sin(thp)])     # the iteration's input
+        u = X @ vp / np.linalg.norm(X @ vp)
+        v = np.array([np.cos(th), np.sin(th)])
+        ok = ok and done == stop and abs(s[0] - st) <= 1e-15 * st
+        ok = ok and abs(abs(V[:, 0] @ v) - 1.0) <= 1e-15 and abs(abs(U[:, 0] @ u) - 1.0) <= 1e-14
+    # Sigma-hat given as S~_1: Error_1 is rounding only and the loop ends after one
+    # iteration (errs[1] ~ 1e-3 would otherwise continue it)
+    ok = ok and improve_fn(X, V0, np.array([cf[0][0]]), 8, 1e-14)[3] == 1
+    # no tolerance: exactly `iters` iterations
+    return ok and improve_fn(X, V0, np.array([s_hat0]), 4)[3] == 4
+
+
+def test_algorithm2_stop_rule_closed_form():
+    """Algorithm 2's do-while: Error = ||Sigma-hat - S~|| / ||Sigma-hat|| is taken after
+    every iteration, the first against the Sigma-hat given as input, and the loop ends
+    at the first Error <= eps.  Pinned on a 2 x 2 diagonal input whose iterates have the
+    closed form of _algorithm2_closed_form (iteration counts, values and angles)."""
+    assert _alg2_pin(oracle.improve)
+
+
+def test_planted_algorithm2_stop_mistakes_are_caught():
+    """Skipping the first iteration's test, or testing it against the singular values
+    of X V-hat (the projection) instead of the Sigma-hat given, fails the pin."""
+    def skip_first(A, V, s_hat, iters, eps=None):
+        U, s, prev, t = None, None, None, 0
+        for t in range(1, iters + 1):
+            Ui = np.linalg.svd(A @ V, full_matrices=False)[0][:, :V.shape[1]]
+            Ut, s, Vtt = np.linalg.svd(Ui.T @ A, full_matrices=False)
+            U, V = Ui @ Ut, Vtt.T
+            if eps is not None and prev is not None and np.linalg.norm(prev - s) <= eps * np.linalg.norm(prev):
+                break
+            prev = s
+        return U, s, V, t
+
+    def projection_reference(A, V, s_hat, iters, eps=None):
+        s_proj = np.linalg.svd(A @ V, compute_uv=False)[:V.shape[1]]
+        return oracle.improve(A, V, s_proj, iters, eps)
+
+    assert not _alg2_pin(skip_first)
+    assert not _alg2_pin(projection_reference)
+
+
 def test_algorithm2_tolerance_stop():
-    """Algorithm 2 to a tolerance: the first iteration t >= 2 whose singular values
-    moved by at most eps (relative 2-norm) from iteration t - 1 ends it, and its
-    factors are the result (the same as a fixed count of t); the cap still holds."""
+    """Algorithm 2 to a tolerance on a generic input: the first iteration t >= 1 whose
+    singular values moved by at most eps (relative 2-norm) from those of t - 1 (for
+    t = 1: Algorithm 1's) ends it, with the factors of a fixed count of t; the cap
+    still holds; the whole method reports the count."""
     rng = np.random.default_rng(52)
     m, n, r = 200, 160, 8
     sigma = np.concatenate([np.linspace(10, 6, r), 3.0 * np.exp(-np.arange(n - r) / 20)])
     A, *_ = synth.low_rank(rng, m, n, sigma)
-    _, _, Vt, rr = oracle.hsvd(A, 2, 2, r, tol=0.0)
-    Vh = Vt[:rr].T
-    runs = [oracle.improve(A, Vh, rr, t) for t in range(1, 7)]
-    ch = [np.linalg.norm(runs[t][1] - runs[t - 1][1]) / np.linalg.norm(runs[t - 1][1]) for t in range(1, 6)]
+    Vh, sh = _algorithm1_sigma(A, 2, 2, r)
+    runs = [oracle.improve(A, Vh, sh, t) for t in range(1, 7)]
+    prev = [sh] + [x[1] for x in runs]
+    ch = [np.linalg.norm(prev[t] - prev[t - 1]) / np.linalg.norm(prev[t - 1]) for t in range(1, 7)]
     assert all(b < a for a, b in zip(ch, ch[1:])), ch      # a power iteration settles
-    for stop in (2, 3, 4):
-        eps = np.sqrt(ch[stop - 2] * ch[stop - 3]) if stop > 2 else 2 * ch[0]
-        got = oracle.improve(A, Vh, rr, 6, eps)
-        for x, y in zip(got, runs[stop - 1]):
+    for stop in (1, 2, 3, 4):
+        eps = np.sqrt(ch[stop - 1] * ch[stop - 2]) if stop > 1 else 2 * ch[0]
+        got = oracle.improve(A, Vh, sh, 6, eps)
+        assert got[3] == stop
+        for x, y in zip(got[:3], runs[stop - 1][:3]):
             assert np.array_equal(x, y), stop
-    got = oracle.improve(A, Vh, rr, 3, 1e-300)                # never met: the cap
-    for x, y in zip(got, runs[2]):
+    got = oracle.improve(A, Vh, sh, 3, 1e-300)                # never met: the cap
+    assert got[3] == 3
+    for x, y in zip(got[:3], runs[2][:3]):
         assert np.array_equal(x, y)
+    info = {}
+    oracle.hsvd(A, 2, 2, r, refine=6, refine_eps=2 * ch[0], info=info)
+    assert info["refine_iterations"] == 1
+
+
+# ----------------------------------------------------------------------------- tree schedule
+def test_merge_tree_pairing_inexact_closed_form():
+    """The pairing of the tree (Algorithm 1: neighbours (0,1), (2,3), ... left to right,
+    an odd last node carried up) decides the result once truncation loses information.
+    Three rank-1 nodes in R^2, k = 1: a = (e1, 3), b = (e2, 2), c = ((e1+e2)/sqrt2, 1).
+    merge(a, b) keeps (e1, 3) (eigenvalues 9 and 4 of diag(9, 4)); merging that with c
+    is the top eigenpair of [[9.5, 0.5], [0.5, 0.5]]: sigma^2 = (10 + sqrt 82) / 2.  Any
+    other pairing (b with c first, or a with c) gives another value."""
+    e1, e2 = np.array([[1.0], [0.0]]), np.array([[0.0], [1.0]])
+    a = (e1, np.array([3.0]))
+    b = (e2, np.array([2.0]))
+    c = ((e1 + e2) / np.sqrt(2.0), np.array([1.0]))
+    U, s = oracle.merge_tree([a, b, c], 1, 0.0, "gamma")
+    lam = (10.0 + np.sqrt(82.0)) / 2.0
+    u = np.array([lam - 0.5, 0.5])
+    u /= np.linalg.norm(u)
+    assert abs(s[0] - np.sqrt(lam)) <= 1e-15 * np.sqrt(lam)
+    assert abs(abs(U[:, 0] @ u) - 1.0) <= 1e-15
+    # the other pairings differ by far more than rounding
+    lam_bc = (5.0 + np.sqrt(17.0)) / 2.0             # merge(b, c): [[.5, .5], [.5, 4.5]]
+    v = np.array([0.5, lam_bc - 0.5])
+    v /= np.linalg.norm(v)
+    M = np.diag([9.0, 0.0]) + lam_bc * np.outer(v, v)
+    assert abs(np.sqrt(np.linalg.eigvalsh(M)[-1]) - s[0]) > 1e-2
+    U5, s5 = oracle.merge_tree([a, b, c, a, c], 1, 0.0, "gamma")
+    ab = oracle.merge(*a, *b, 1, 0.0, "gamma")
+    ca = oracle.merge(*c, *a, 1, 0.0, "gamma")
+    top = oracle.merge(*oracle.merge(*ab, *ca, 1, 0.0, "gamma"), *c, 1, 0.0, "gamma")
+    assert np.array_equal(s5, top[1]) and np.array_equal(U5, top[0])
+
+
+def _tree_pin(tree_fn):
+    e1, e2 = np.array([[1.0], [0.0]]), np.array([[0.0], [1.0]])
+    nodes = [(e1, np.array([3.0])), (e2, np.array([2.0])),
+             ((e1 + e2) / np.sqrt(2.0), np.array([1.0]))]
+    _, s = tree_fn(nodes, 1, 0.0, "gamma")
+    return abs(s[0] - np.sqrt((10.0 + np.sqrt(82.0)) / 2.0)) <= 1e-14
+
+
+def test_planted_tree_schedules_are_caught():
+    """Right-to-left pairing and carrying the odd node from the front both fail the pin."""
+    def right_to_left(nodes, k, tol, rule):
+        return oracle.merge_tree(list(reversed(nodes)), k, tol, rule)
+
+    def odd_first(nodes, k, tol, rule):
+        nodes = list(nodes)
+        while len(nodes) > 1:
+            head = [nodes[0]] if len(nodes) % 2 else []
+            rest = nodes[len(head):]
+            nodes = head + [oracle.merge(*rest[i], *rest[i + 1], k, tol, rule)
+                            for i in range(0, len(rest), 2)]
+        return nodes[0]
+
+    assert _tree_pin(oracle.merge_tree)
+    assert not _tree_pin(right_to_left)
+    assert not _tree_pin(odd_first)
 
 
 # ----------------------------------------------------------------------------- config C0
@@ -474,3 +620,44 @@ def test_mlp_training_fits_a_rank_map():
     theta, losses = mlp.train(theta0, X, t, steps=600, lr=3e-3)
     L1 = mlp.loss(mlp.fp16(theta), X, t)
     assert L1 < 0.02 * L0 and L1 < 0.05, (L0, L1)
+
+
+def test_adam_first_step_closed_form():
+    """Adam's first step (Kingma and Ba): with zero moments the bias-corrected
+    estimates are g and g^2, so the update is -lr g / (|g| + eps) exactly; a missing
+    bias correction would move by ~0.1 lr / (0.03 + ...) instead."""
+    g = np.array([3.0, -0.5, 1e-9, 0.0, -2e-4])
+    theta = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    lr, eps = 1e-2, 1e-8
+    new, m, v = mlp.adam(theta, g, np.zeros(5), np.zeros(5), 1, lr, eps=eps)
+    assert np.allclose(new - theta, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0.0)
+    assert np.allclose(m, 0.1 * g, rtol=1e-15) and np.allclose(v, 0.001 * g * g, rtol=1e-15)
+    # second step on the same gradient: m = 0.19 g, v = 0.001999 g^2, corrections
+    # 1 - 0.81 and 1 - 0.998001 give m-hat = g, v-hat = g^2 again
+    new2, _, _ = mlp.adam(new, g, m, v, 2, lr, eps=eps)
+    assert np.allclose(new2 - new, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=0.0)
+
+
+# ----------------------------------------------------------------------------- randomised leaves
+def test_randomised_leaf_exact_rank_is_exact():
+    """A block of exact rank <= l: the range finder captures its column space, so the
+    randomised leaf equals the exact one (constructed SVD) to rounding."""
+    rng = np.random.default_rng(61)
+    A, U0, s0, V0 = synth.low_rank(rng, 90, 70, np.array([4.0, 2.0, 1.0, 0.5, 0.25]))
+    om = rng.standard_normal((70, 9))
+    U, s = oracle.randomised_leaf(A, 5, 0.0, "gamma", om, 0)
+    assert s.size == 5 and metrics.e_sigma(s, s0) <= 1e-14
+    assert metrics.sin_theta(U, U0) <= 1e-13
+
+
+def test_randomised_leaf_power_steps_converge():
+    """Subspace iteration: with a gap at the cut, each power step shrinks the angle to
+    the block's exact top-k subspace by about (s_{l+1} / s_k)^2, down to rounding."""
+    rng = np.random.default_rng(62)
+    sig = np.concatenate([np.linspace(3, 1, 6), 0.05 * np.exp(-np.arange(54) / 10)])
+    A, U0, s0, V0 = synth.low_rank(rng, 80, 60, sig)
+    om = rng.standard_normal((60, 10))
+    errs = [metrics.sin_theta(oracle.randomised_leaf(A, 6, 0.0, "gamma", om, q)[0], U0[:, :6])
+            for q in range(5)]
+    assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1]
+    assert errs[4] <= 1e-13
