@@ -73,22 +73,29 @@ typedef struct {
     int32_t  rule;          /* hsvd_rule, default HSVD_RULE_GAMMA                       */
     int32_t  oversample;    /* leaf sketch width l = k + oversample (capped by the block
                                sides), default 14                                       */
-    int32_t  power_steps;   /* extra products with A per leaf after sketch and
-                               projection (0 = sketch + one projection), default 1     */
+    int32_t  power_steps;   /* power steps per leaf (each one product with A_b^T and one
+                               with A_b after the sketch Y = A_b Omega), 0..64, or -1
+                               (default): float64 plans iterate until converged -- after
+                               step t the leaf core gives the sketch's singular values
+                               s_0..s_{l-1}, and with r the leaf's truncation rank the
+                               step count is enough once (s_{l-1} / s_{r-1})^(2t+1) <= 1e-12
+                               for every leaf (the subspace-iteration bound on how far a
+                               further step could turn the kept subspace), at most 6
+                               steps; float32, mixed and width plans take 1 step for -1 */
     int32_t  refine_steps;  /* iterations of Algorithm 2 after the projection, default 0 */
     int32_t  max_sweeps;    /* Jacobi sweep cap per core, default 40                    */
     uint64_t seed;          /* seed of the leaves' Gaussian test matrices, default 0    */
     double   refine_eps;    /* Algorithm 2 to a tolerance, default 0 (off).  When > 0 and
                                at least two iterations are asked for, the iterations stop
-                               after the first t >= 2 at which, for every matrix of the plan,
+                               after the first t >= 1 at which, for every matrix of the plan,
                                ||s_t - s_(t-1)||_2 <= refine_eps ||s_(t-1)||_2 over its rank
-                               (s_t: singular values after iteration t); refine_steps (plus
-                               the mixed path's own iteration) is then the cap and the
-                               output is iteration t's.  Each test is taken on the device;
-                               the execute then waits for it (one 4-byte read-back per
-                               iteration from the second on, the last excepted), and
-                               per-launch timing (hsvd_set_profiling) is refused.  Must
-                               not be negative or NaN (HSVD_ERR_INVALID).                */
+                               (s_t: singular values after iteration t; s_0: Algorithm 1's,
+                               the root of the row-slab tree); refine_steps (plus the mixed
+                               path's own iteration) is then the cap and the output is
+                               iteration t's.  Each test is taken on the device; the execute
+                               then waits for it (one 4-byte read-back per iteration, the
+                               last excepted), and per-launch timing (hsvd_set_profiling) is
+                               refused.  Must not be negative or NaN (HSVD_ERR_INVALID).  */
 } hsvd_options;
 
 /* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
@@ -188,7 +195,8 @@ typedef enum {
     HSVD_LAUNCH_GEMM_ATX_BF16 = 11,/* Y = A_blk^T X on the bfloat16 matrix cores         */
     HSVD_LAUNCH_ENERGY = 12,       /* squared Frobenius norms of the blocks              */
     HSVD_LAUNCH_FEATURES = 13,     /* block features of a feature plan                   */
-    HSVD_LAUNCH_CHOLQR = 14        /* Cholesky QR passes (fast path of the panel QRs)    */
+    HSVD_LAUNCH_CHOLQR = 14,       /* Cholesky QR passes (fast path of the panel QRs)    */
+    HSVD_LAUNCH_CHECK = 15         /* the leaves' power-step convergence test            */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

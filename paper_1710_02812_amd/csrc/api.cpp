@@ -57,7 +57,7 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
 }
 
 enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY, ST_CQ1, ST_CQ2,
-                 ST_FEAT };
+                 ST_FEAT, ST_LEAFCHECK };
 
 struct Stage {
     StageKind kind;
@@ -68,6 +68,8 @@ struct Stage {
     int bf16 = 0;        // gemm on the bfloat16 matrix cores
     int64_t off = 0, off2 = 0;   // energy: output offset; features: sigma and energy offsets
     size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
+    int guard = -1;      // int-arena slot: the stage is skipped while it holds non-zero
+    int step = 0;        // leaf check: the power step it follows
 };
 
 int pow2floor(int x) {
@@ -99,6 +101,12 @@ struct hsvd_plan_st {
     double tol = 0.0;
     hsvd_options opt{};
     int W = 0, L = 0, g = 0;       // panel width (max k), leaf sketch width, products per leaf
+    // leaves' power steps until converged (power_steps = -1 on float64 plans): at most
+    // leaf_cap steps; iws[leaf_done] turns 1 once every leaf has passed its test, and the
+    // later steps' launches return at once (the slot is cleared at each execute)
+    int leaf_cap = 0, leaf_done = -1;
+    std::vector<int> reset_slots;  // int-arena slots cleared at the start of each execute
+    size_t reset_off = 0;          // their device copy in the task blob
 
     // arenas (host-side bookkeeping)
     int64_t ws_elems = 0;
@@ -491,14 +499,126 @@ std::vector<Node> merge_forest(hsvd_plan_st& P, std::vector<std::vector<Node>> t
 // finder with power steps (Y = A_b Omega_w, then alternately QR and products with
 // A_b^T / A_b), QR of the last product, Jacobi core -> (U_b, s_b, r_b).
 struct Leaf { int mat, i, j, w; int64_t rowsz, colsz, aoff; };
+struct LeafPanels { int64_t Y, Z, Qy, Qz; };
+
+// Leaf core task of leaf b (sketch width w): Jacobi on R^T of the last QR of Y = A_b Q_z,
+// writing the node's sigma and rank and the w x W rotation U_R (at ur).
+CoreTask leaf_core_task(hsvd_plan_st& P, const Leaf& l, int b, int w, int64_t r_out, int mode,
+                        int64_t ur, Node& nd) {
+    const int W = P.W;
+    nd.mat = l.mat;
+    nd.h = (int)l.rowsz;
+    nd.ld = (int)l.rowsz;
+    nd.panel = P.alloc(l.rowsz * W);
+    nd.sig = P.alloc(W);
+    nd.rank = P.ialloc(1);
+    CoreTask c = core_defaults(P, P.mats[l.mat].k);
+    c.mode = mode;
+    c.dim = w;
+    c.m_off = r_out;
+    c.m_ld = w;
+    c.u_off = ur;
+    c.u_ld = w;
+    c.sig_off = nd.sig;
+    c.out_w = W;
+    c.rank_out = nd.rank;
+    c.floor_rows = (int)l.rowsz;
+    c.floor_cols = (int)l.colsz;
+    c.precond = 1;                // left vectors only: LQ of R first (fewer sweeps)
+    if (P.energy_off >= 0 && l.mat == 0) {
+        c.energy_off = P.energy_off + b;
+        c.flag_slot = P.ialloc(1);
+        P.leaf_flag_slots[b] = c.flag_slot;
+    }
+    if (l.mat == 0) P.leaf_rank_slots[b] = nd.rank;
+    return c;
+}
+
+// Leaves whose power steps run until their subspaces have converged.  After the
+// sketch Y = A_b Omega and its QR, step t = 1, 2, ... forms Q_y, Z = A_b^T Q_y, its QR
+// and Q_z, Y = A_b Q_z and its QR, and the leaf core on R; a device-side test then
+// bounds how far one more step could still turn each leaf's kept subspace (subspace
+// iteration shrinks the angle to the block's top-r subspace by (s_{w+1} / s_r)^2 per
+// step, estimated from the core's values).  Every step reuses the same panels, so
+// whichever step passed the test last, the final apply U_b = Q_y U_R reads its
+// factors; the launches of the steps after it return at once.
+void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::vector<int>& ids, int w,
+                   int ch, int64_t I_w, const std::vector<LeafPanels>& pan, std::vector<Node>& nodes) {
+    const int W = P.W;
+    TsqrBuild tby, tbz;
+    for (size_t u = 0; u < ids.size(); ++u) {
+        const Leaf& l = leaves[ids[u]];
+        add_tsqr(P, tby, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch);
+        add_tsqr(P, tbz, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch);
+    }
+    push_tsqr_factor(P, tby, w, ch);
+    std::vector<CoreTask> cores;
+    std::vector<LeafCheck> checks;
+    std::vector<ApplyTask> aqy, aqz, aout;
+    std::vector<GemmTask> gz, gy;
+    for (size_t u = 0; u < ids.size(); ++u) {
+        const int b = ids[u];
+        const Leaf& l = leaves[b];
+        const int64_t ur = P.alloc((int64_t)w * W);
+        CoreTask c = leaf_core_task(P, l, b, w, tby.tasks[u].r_out, CORE_UPPER, ur, nodes[b]);
+        c.sigall_off = P.alloc(w);
+        cores.push_back(c);
+        LeafCheck k{};
+        k.sig_off = c.sigall_off;
+        k.w = w;
+        k.kcap = P.mats[l.mat].k;
+        k.rule = P.opt.rule;
+        k.tol = P.tol;
+        k.floor_rows = (int)l.rowsz;
+        k.floor_cols = (int)l.colsz;
+        checks.push_back(k);
+        ApplyTask a{};
+        a.tsqr = (int)u;
+        a.x_off = I_w;
+        a.add_u_off = -1;
+        a.out_off = pan[u].Qy; a.out_ld = (int)l.rowsz;
+        aqy.push_back(a);
+        a.out_off = pan[u].Qz; a.out_ld = (int)l.colsz;
+        aqz.push_back(a);
+        a.x_off = ur;
+        a.out_off = nodes[b].panel; a.out_ld = nodes[b].ld;
+        aout.push_back(a);
+        GemmTask x = gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz);
+        x.x_off = pan[u].Qy; x.x_ld = (int)l.rowsz;          // Z = A_b^T Q_y
+        x.y_off = pan[u].Z; x.y_ld = (int)l.colsz;
+        gz.push_back(x);
+        x.x_off = pan[u].Qz; x.x_ld = (int)l.colsz;          // Y = A_b Q_z
+        x.y_off = pan[u].Y; x.y_ld = (int)l.rowsz;
+        gy.push_back(x);
+    }
+    const size_t checks_off = P.put(checks);
+    for (int t = 1; t <= P.leaf_cap; ++t) {
+        const size_t first = P.stages.size();
+        push_tsqr_apply(P, tby, aqy, w, ch, w);
+        push_gemm(P, 1, gz, w);
+        push_tsqr_factor(P, tbz, w, ch);
+        push_tsqr_apply(P, tbz, aqz, w, ch, w);
+        push_gemm(P, 0, gy, w);
+        push_tsqr_factor(P, tby, w, ch);
+        push_core(P, cores, w, 0);
+        Stage s{};
+        s.kind = ST_LEAFCHECK;
+        s.n = (int)checks.size();
+        s.tasks_off = checks_off;
+        s.step = t;
+        P.stages.push_back(s);
+        if (t > 1)
+            for (size_t i = first; i < P.stages.size(); ++i) P.stages[i].guard = P.leaf_done;
+    }
+    push_tsqr_apply(P, tby, aout, w, ch, W);
+}
 
 void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::vector<int>& ids, int w,
                    int64_t omega_ld, std::vector<Node>& nodes) {
     const int W = P.W, g = P.g;
     const bool bf16 = P.opt.precision == HSVD_MIXED_BF16;
     const int64_t I_w = identity_panel(P, w);
-    struct Pan { int64_t Y, Z, Qy, Qz; };
-    std::vector<Pan> pan(ids.size());
+    std::vector<LeafPanels> pan(ids.size());
     for (size_t u = 0; u < ids.size(); ++u) {
         const Leaf& l = leaves[ids[u]];
         pan[u] = {P.alloc(l.rowsz * w), P.alloc(l.colsz * w), P.alloc(l.rowsz * w), P.alloc(l.colsz * w)};
@@ -515,6 +635,10 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         push_gemm(P, 0, gt, w, bf16);
     }
     const int ch = tsqr_chunk(w, std::max(w, W));
+    if (P.leaf_cap > 0) {
+        leaf_converge(P, leaves, ids, w, ch, I_w, pan, nodes);
+        return;
+    }
     TsqrBuild tb_last;
     for (int t = 1; t <= g; ++t) {
         const bool prev_is_y = ((t - 1) % 2 == 0);
@@ -558,35 +682,9 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
     std::vector<int64_t> ur(ids.size());
     for (size_t u = 0; u < ids.size(); ++u) {
         const int b = ids[u];
-        const Leaf& l = leaves[b];
-        Node& nd = nodes[b];
-        nd.mat = l.mat;
-        nd.h = (int)l.rowsz;
-        nd.ld = (int)l.rowsz;
-        nd.panel = P.alloc(l.rowsz * W);
-        nd.sig = P.alloc(W);
-        nd.rank = P.ialloc(1);
         ur[u] = P.alloc((int64_t)w * W);
-        CoreTask c = core_defaults(P, P.mats[l.mat].k);
-        c.mode = last_is_y ? CORE_UPPER : CORE_UPPER_T;
-        c.dim = w;
-        c.m_off = tb_last.tasks[u].r_out;
-        c.m_ld = w;
-        c.u_off = ur[u];
-        c.u_ld = w;
-        c.sig_off = nd.sig;
-        c.out_w = W;
-        c.rank_out = nd.rank;
-        c.floor_rows = (int)l.rowsz;
-        c.floor_cols = (int)l.colsz;
-        c.precond = 1;                // left vectors only: LQ of R first (fewer sweeps)
-        if (P.energy_off >= 0 && l.mat == 0) {
-            c.energy_off = P.energy_off + b;
-            c.flag_slot = P.ialloc(1);
-            P.leaf_flag_slots[b] = c.flag_slot;
-        }
-        if (l.mat == 0) P.leaf_rank_slots[b] = nd.rank;
-        cores.push_back(c);
+        cores.push_back(leaf_core_task(P, leaves[b], b, w, tb_last.tasks[u].r_out,
+                                       last_is_y ? CORE_UPPER : CORE_UPPER_T, ur[u], nodes[b]));
     }
     push_core(P, cores, w, 0);
     if (last_is_y) {
@@ -964,21 +1062,24 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     P.step_rank_slots.clear();
     P.refine_done = steps;
     if (eps_stop) P.check_slot = P.ialloc(1);
-    std::vector<Factors> prev;
+    // the first iteration is tested against Algorithm 1's singular values (the row
+    // tree's root), each later one against the iteration before it
+    std::vector<Factors> prev(f.size());
+    for (size_t mi = 0; mi < f.size(); ++mi) prev[mi].sig = row_roots[mi].sig;
     std::vector<OutputArgs> last_outs;
     for (int it = 0; it < steps; ++it) {
         f = build_refine_step(P, f);
         if (eps_stop) {
             P.seg_end.push_back(P.stages.size());
             std::vector<RefineCheck> checks;
-            for (size_t mi = 0; it > 0 && mi < f.size(); ++mi) {
+            for (size_t mi = 0; mi < f.size(); ++mi) {
                 RefineCheck c{};
                 c.sig_old = prev[mi].sig;
                 c.sig_new = f[mi].sig;
                 c.rank_slot = f[mi].rank;
                 checks.push_back(c);
             }
-            P.check_off.push_back(it > 0 ? P.put(checks) : 0);
+            P.check_off.push_back(P.put(checks));
             std::vector<int> ranks;
             last_outs = out_table(f, ranks);
             P.step_outs_off.push_back(P.put(last_outs));
@@ -1222,6 +1323,14 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 }
                 break;
             }
+            case ST_LEAFCHECK: {
+                const LeafCheck* T = (const LeafCheck*)(b + s.tasks_off);
+                if (P.leaf_done < 0 || P.leaf_done >= IW || s.step < 1) return "leaf check slot";
+                for (int i = 0; i < s.n; ++i)
+                    if (T[i].w < 1 || !span("leaf check sigma", T[i].sig_off, T[i].sig_off + T[i].w - 1, WS))
+                        return T[i].w < 1 ? "leaf check width" : msg;
+                break;
+            }
             case ST_FEAT: {
                 if (!span("feature sigma", s.off, s.off + 16LL * s.n - 1, WS)) return msg;
                 if (!span("feature energy", s.off2, s.off2 + s.n - 1, WS)) return msg;
@@ -1251,6 +1360,8 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         if (t.v_off >= 0 && (!s.with_v || !panel("core V", t.v_off, t.v_ld, t.dim, t.out_w))) return msg;
                     }
                     if (!span("core sigma", t.sig_off, t.sig_off + t.out_w - 1, WS)) return msg;
+                    if (t.sigall_off >= 0 && (t.mode == CORE_MERGE || !span("core all sigma", t.sigall_off, t.sigall_off + t.dim - 1, WS)))
+                        return t.mode == CORE_MERGE ? "all-sigma output of a merge core" : msg;
                     if (t.energy_off >= 0 && (t.energy_off >= WS || t.flag_slot < 0 || t.flag_slot >= IW))
                         return "core energy check";
                     if (t.rank_out >= IW || t.fixed_rank_slot >= IW) return "core rank slot";
@@ -1259,6 +1370,10 @@ std::string validate_plan(const hsvd_plan_st& P) {
             }
         }
     }
+    for (const Stage& s : P.stages)
+        if (s.guard >= IW) return "stage guard slot";
+    for (int slot : P.reset_slots)
+        if (slot < 0 || slot >= IW) return "reset slot";
     if (P.outs.size() != (P.kind == 0 ? P.mats.size() : 0)) return "output count";
     for (size_t mi = 0; mi < P.outs.size(); ++mi) {
         const OutputArgs& o = P.outs[mi];
@@ -1278,6 +1393,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
     unsigned char* b = (unsigned char*)P.dblob;
     hipError_t e = hipSuccess;
     const int fp32 = P.opt.precision != HSVD_FP64;
+    const int* guard = s.guard >= 0 ? P.iws + s.guard : nullptr;
     switch (s.kind) {
         case ST_GEMM:
             if (s.bf16)
@@ -1285,7 +1401,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
                                      (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             else
                 e = launch_gemm(s.op, fp32, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
-                                (const TileRef*)(b + s.refs_off), s.n, s.N, st);
+                                (const TileRef*)(b + s.refs_off), s.n, s.N, st, guard);
             break;
         case ST_CQ1:
         case ST_CQ2:
@@ -1294,12 +1410,12 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             break;
         case ST_TSQR_F:
             e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
-                                   (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
+                                   (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st, guard);
             break;
         case ST_TSQR_A:
             e = launch_tsqr_apply(P.ws, P.iws, (const TsqrTask*)(b + s.tsqr_off),
                                   (const ApplyTask*)(b + s.tasks_off),
-                                  (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, s.c, st);
+                                  (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, s.c, st, guard);
             break;
         case ST_GRAM:
             e = launch_thin_gram(P.ws, (const ThinTask*)(b + s.tasks_off),
@@ -1318,7 +1434,11 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             break;
         case ST_CORE:
             e = launch_core(P.ws, P.iws, (const CoreTask*)(b + s.tasks_off), s.n, s.maxdim,
-                            P.opt.max_sweeps, P.flags, s.with_v, st);
+                            P.opt.max_sweeps, P.flags, s.with_v, st, guard);
+            break;
+        case ST_LEAFCHECK:
+            e = launch_leaf_check(P.ws, P.iws, (const LeafCheck*)(b + s.tasks_off), s.n, s.step, P.leaf_done,
+                                  guard, st);
             break;
         case ST_ENERGY:
             e = launch_block_energy((const void* const*)P.dptrs, fp32, (const GemmTask*)(b + s.tasks_off),
@@ -1341,7 +1461,7 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->precision = HSVD_FP64;
     opt->rule = HSVD_RULE_GAMMA;
     opt->oversample = 14;
-    opt->power_steps = 1;
+    opt->power_steps = -1;
     opt->refine_steps = 0;
     opt->max_sweeps = 40;
     opt->seed = 0;
@@ -1378,8 +1498,9 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         return fail(HSVD_ERR_INVALID, "unknown precision");
     if (o.rule != HSVD_RULE_GAMMA && o.rule != HSVD_RULE_FROB)
         return fail(HSVD_ERR_INVALID, "unknown rule");
-    if (o.oversample < 0 || o.power_steps < 0 || o.refine_steps < 0 || o.max_sweeps < 1)
+    if (o.oversample < 0 || o.power_steps < -1 || o.refine_steps < 0 || o.max_sweeps < 1)
         return fail(HSVD_ERR_INVALID, "negative option");
+    if (o.power_steps > 64) return fail(HSVD_ERR_INVALID, "power_steps above 64");
     if (!(o.refine_eps >= 0.0)) return fail(HSVD_ERR_INVALID, "need refine_eps >= 0");
 
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
@@ -1406,7 +1527,16 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     P->L = (int)std::min<int64_t>(lwant, bmin);
     if (P->L < 1) P->L = 1;
     if (P->L > kTsqrMaxW) P->L = kTsqrMaxW;
-    P->g = 2 + o.power_steps;
+    // power_steps = -1: float64 plans iterate their leaves until converged (at most
+    // kLeafPowerCap steps); float32-storage and mixed plans, whose inputs carry their
+    // own rounding, and width plans take one step
+    const bool converge = o.power_steps < 0 && o.precision == HSVD_FP64 && !leaf_width && kind == 0;
+    P->g = 2 + (o.power_steps < 0 ? 1 : o.power_steps);
+    if (converge) {
+        P->leaf_cap = kLeafPowerCap;
+        P->leaf_done = P->ialloc(1);
+        P->reset_slots.push_back(P->leaf_done);
+    }
     P->kind = kind;
     if (leaf_width) {
         const MatDesc& M = P->mats[0];
@@ -1425,6 +1555,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
 
     if (kind == 1) build_features(*P);
     else build_plan(*P);
+    P->reset_off = P->put(P->reset_slots);
     const std::string verr = validate_plan(*P);
     if (!verr.empty()) { delete P; return fail(HSVD_ERR_INVALID, "plan validation: " + verr); }
     if (check_only) {
@@ -1530,8 +1661,9 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
         if (e != hipSuccess) return hip_fail(e, "pointer table");
         P.host_ptrs = tab;
     }
-    e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * 4, stream);
-    if (e != hipSuccess) return hip_fail(e, "flags reset");
+    e = launch_reset_state(P.flags, P.iws, (const int*)((unsigned char*)P.dblob + P.reset_off),
+                           (int)P.reset_slots.size(), stream);
+    if (e != hipSuccess) return hip_fail(e, "state reset");
     const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
     if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
     size_t outs_off = P.outs_off;
@@ -1552,7 +1684,7 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
                 hsvd_status st = run_stage(P, P.stages[i], stream);
                 if (st != HSVD_OK) return st;
             }
-            if (t == 0 || t + 1 == nseg) continue;
+            if (t + 1 == nseg) continue;
             e = launch_refine_check(P.ws, P.iws, (const RefineCheck*)((unsigned char*)P.dblob + P.check_off[t]),
                                     (int)P.mats.size(), P.opt.refine_eps, P.check_slot, stream);
             int done = 0;
@@ -1642,6 +1774,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_CORE: kind = HSVD_LAUNCH_CORE; break;
                 case ST_ENERGY: kind = HSVD_LAUNCH_ENERGY; break;
                 case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
+                case ST_LEAFCHECK: kind = HSVD_LAUNCH_CHECK; break;
             }
         }
         float ms = 0.f;
@@ -1772,6 +1905,10 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     }
                     break;
                 }
+                case ST_LEAFCHECK:
+                    f = 0.0;
+                    by = 0.0;
+                    break;
                 case ST_FEAT:
                     f = 40.0 * s.n;
                     by = s.n * (17.0 * e8 + 16.0 * 4.0);

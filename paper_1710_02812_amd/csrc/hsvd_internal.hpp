@@ -139,6 +139,9 @@ struct CoreTask {
     int64_t energy_off;
     int32_t flag_slot;
     int32_t pad2;
+    // >= 0: all singular values of the core (sorted, zero past its size), dim of them,
+    // before truncation (the leaves' power-step convergence test reads them)
+    int64_t sigall_off = -1;
 };
 
 // ---------------------------------------------------------------- output
@@ -165,19 +168,21 @@ constexpr int kMlpBatch = 64;
 
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return the hipError_t of the launch.
+// `guard` (device int or nullptr): when it points at a non-zero value every work-group
+// of the launch returns at once (stages of an iteration that has already stopped).
 // bfloat16 matrix-core passes: 128 x 64 output tiles (TileRef.tile = row tile * ceil(N / 64) + col tile)
 constexpr int kBf16TileRows = 128;
 hipError_t launch_gemm_bf16(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
                             const TileRef* tiles, int ntiles, int N, hipStream_t s);
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
-                       hipStream_t s);
+                       hipStream_t s, const int* guard = nullptr);
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
                               const ChunkRef* chunks, int nchunks, int w, int ch,
-                              hipStream_t s);
+                              hipStream_t s, const int* guard = nullptr);
 hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
-                             hipStream_t s);
+                             hipStream_t s, const int* guard = nullptr);
 hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks,
                             int nchunks, int chh, hipStream_t s);
 // maxsz: the largest wx * wy over the tasks (grid: task x element slices of 256)
@@ -202,7 +207,8 @@ __host__ __device__ inline int64_t cq_size(int w, int nch, int h) { return cq_q1
 hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks,
                            int nchunks, int chh, hipStream_t s);
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
-                       int max_sweeps, unsigned* flags, int with_v, hipStream_t s);
+                       int max_sweeps, unsigned* flags, int with_v, hipStream_t s,
+                       const int* guard = nullptr);
 hipError_t launch_mlp_train(float* master, float* m1, float* m2, const float* X, const float* T,
                             int count, int steps, int s0, int t0, float lr, float* grad_out,
                             float* loss_out, hipStream_t s);
@@ -217,6 +223,26 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // its rank, else 0 (one work-group).
 hipError_t launch_refine_check(const double* ws, int* iws, const RefineCheck* items, int count, double eps,
                                int out_slot, hipStream_t s);
+// Convergence test of the leaves' power steps (one item per leaf): after step t the
+// leaf's core has given the sketch's singular values s_0 >= ... >= s_{w-1} (zero past
+// its numerical rank); with r the leaf's truncation rank, the leaf has converged when
+// r == 0, s_{w-1} == 0, or (s_{w-1} / s_{r-1})^(2t+1) <= kLeafConvTol.  When every
+// leaf has converged iws[done_slot] is set to 1 (it is never cleared here).
+constexpr double kLeafConvTol = 1e-12;
+constexpr int kLeafPowerCap = 6;
+struct LeafCheck {
+    int64_t sig_off;      // w singular values of the sketch (descending, zero padded)
+    int32_t w;            // sketch width
+    int32_t kcap, rule;   // the leaf's rank cap and truncation rule
+    int32_t floor_rows, floor_cols;
+    int32_t pad;
+    double tol;
+};
+hipError_t launch_leaf_check(const double* ws, int* iws, const LeafCheck* items, int count, int step,
+                             int done_slot, const int* guard, hipStream_t s);
+// Per-execute state reset: flags[0..3] = 0 and iws[slots[i]] = 0 for i < nslots
+// (a kernel, so that a captured graph holds no memset node).
+hipError_t launch_reset_state(unsigned* flags, int* iws, const int* slots, int nslots, hipStream_t s);
 // Output of `count` matrices (args: device array; ptrs: the pointer table);
 // kmax, mmax, nmax bound k, m, n over the batch (grid sizes).
 hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,

@@ -93,7 +93,9 @@ template <int ROWS>
 __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, int* __restrict__ iws,
                                                        const CoreTask* __restrict__ tasks,
                                                        int maxdim, int max_sweeps,
-                                                       unsigned* __restrict__ flags, int with_v) {
+                                                       unsigned* __restrict__ flags, int with_v,
+                                                       const int* __restrict__ guard) {
+    if (guard && *guard) return;                  // a skipped stage (every group returns)
     extern __shared__ double sm[];
     const CoreTask t = tasks[blockIdx.x];
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -526,6 +528,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
 
     // ---- outputs
     for (int i = tid; i < t.out_w; i += nth) ws[t.sig_off + i] = (i < r) ? sig[i] : 0.0;
+    if (t.sigall_off >= 0 && t.mode != CORE_MERGE)
+        for (int i = tid; i < t.dim; i += nth) ws[t.sigall_off + i] = (i < nc && !s_bad) ? sig[i] : 0.0;
     if (t.mode == CORE_MERGE) {
         const int rowsT = t.t_ld, rowsU = t.u_ld, r2 = s_r2;
         for (int e = tid; e < rowsT * t.out_w; e += nth) {
@@ -557,27 +561,27 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
 
 template <int ROWS>
 hipError_t launch_core_rows(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
-                            int max_sweeps, unsigned* flags, int with_v, hipStream_t s) {
+                            int max_sweeps, unsigned* flags, int with_v, hipStream_t s, const int* guard) {
     const size_t lds = sizeof(double) * ((size_t)maxdim * (ROWS + 1) * (with_v ? 2 : 1) +
                                          2 * (size_t)maxdim + 1) + sizeof(int) * maxdim + 64;
     hipError_t e = hipFuncSetAttribute((const void*)k_core<ROWS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_core<ROWS>, dim3(ntasks), dim3(CORE_THREADS), lds, s, ws, iws, tasks, maxdim,
-                       max_sweeps, flags, with_v);
+                       max_sweeps, flags, with_v, guard);
     return hipGetLastError();
 }
 
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
-                         int max_sweeps, unsigned* flags, int with_v, hipStream_t s) {
+                         int max_sweeps, unsigned* flags, int with_v, hipStream_t s, const int* guard) {
     if (ntasks <= 0) return hipSuccess;
     if (maxdim < 1 || maxdim > 128 || (with_v && maxdim > 64)) return hipErrorInvalidValue;
     // rows padded to the smallest variant that holds the largest core of the launch
-    if (maxdim <= 32) return launch_core_rows<32>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
-    if (maxdim <= 64) return launch_core_rows<64>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
-    if (maxdim <= 96) return launch_core_rows<96>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
-    if (maxdim <= 112) return launch_core_rows<112>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
-    return launch_core_rows<128>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s);
+    if (maxdim <= 32) return launch_core_rows<32>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
+    if (maxdim <= 64) return launch_core_rows<64>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
+    if (maxdim <= 96) return launch_core_rows<96>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
+    if (maxdim <= 112) return launch_core_rows<112>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
+    return launch_core_rows<128>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
 }
 
 }  // namespace hsvd

@@ -20,7 +20,9 @@ template <typename TA, int OP>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict__ ptrs,
                                                    double* __restrict__ ws,
                                                    const GemmTask* __restrict__ tasks,
-                                                   const TileRef* __restrict__ tiles, int N) {
+                                                   const TileRef* __restrict__ tiles, int N,
+                                                   const int* __restrict__ guard) {
+    if (guard && *guard) return;                  // a skipped stage (every group returns)
     __shared__ double As[mfma_lds_a<OP>()];
     __shared__ double Bs[mfma_lds_b()];
     const TileRef tr = tiles[blockIdx.x];
@@ -38,19 +40,19 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict
 
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
-                       hipStream_t s) {
+                       hipStream_t s, const int* guard) {
     if (ntiles <= 0) return hipSuccess;
     dim3 g(ntiles), b(256);
     if (op == 0) {
         if (fp32)
-            hipLaunchKernelGGL((k_gemm_mfma<float, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N);
+            hipLaunchKernelGGL((k_gemm_mfma<float, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
         else
-            hipLaunchKernelGGL((k_gemm_mfma<double, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N);
+            hipLaunchKernelGGL((k_gemm_mfma<double, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
     } else {
         if (fp32)
-            hipLaunchKernelGGL((k_gemm_mfma<float, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N);
+            hipLaunchKernelGGL((k_gemm_mfma<float, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
         else
-            hipLaunchKernelGGL((k_gemm_mfma<double, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N);
+            hipLaunchKernelGGL((k_gemm_mfma<double, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
     }
     return hipGetLastError();
 }

@@ -180,6 +180,76 @@ hipError_t launch_refine_check(const double* ws, int* iws, const RefineCheck* it
     return hipGetLastError();
 }
 
+// Power-step convergence of the leaves (one work-group; one thread per item).  The
+// leaf's truncation rank r follows the same rule as its core: a zero floor of
+// max(rows, cols) eps s_0, then keep s_i >= tol s_0 (gamma) or the shortest prefix whose
+// discarded energy is <= tol^2 of the total (Frobenius), at most kcap.
+__global__ __launch_bounds__(256) void k_leaf_check(const double* __restrict__ ws, int* __restrict__ iws,
+                                                    const LeafCheck* __restrict__ items, int count,
+                                                    int step, int done_slot, const int* __restrict__ guard) {
+    if (guard && *guard) return;
+    __shared__ int s_all;
+    if (threadIdx.x == 0) s_all = 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const LeafCheck c = items[i];
+        const double* s = ws + c.sig_off;
+        const double s0 = s[0];
+        bool conv = true;
+        if (s0 > 0.0) {
+            const double floor = (double)(c.floor_rows > c.floor_cols ? c.floor_rows : c.floor_cols) * kEps * s0;
+            int nz = 0;
+            while (nz < c.w && s[nz] > floor) ++nz;
+            int r;
+            if (c.rule == 0) {
+                r = 0;
+                while (r < c.w && s[r] >= c.tol * s0) ++r;
+            } else {
+                double total = 0.0;
+                for (int j = c.w - 1; j >= 0; --j) total += s[j] * s[j];
+                const double lim = c.tol * c.tol * total;
+                double tail = 0.0;
+                r = c.w;
+                for (int j = c.w - 1; j >= 0; --j) {
+                    tail += s[j] * s[j];
+                    if (tail <= lim) r = j;
+                    else break;
+                }
+            }
+            if (r > nz) r = nz;
+            if (r > c.kcap) r = c.kcap;
+            const double last = s[c.w - 1];
+            if (r > 0 && last > floor && r < c.w) {
+                const double rho = last / s[r - 1];
+                double b = rho;
+                for (int e = 0; e < 2 * step; ++e) b *= rho;      // rho^(2 step + 1)
+                conv = b <= kLeafConvTol;
+            }
+        }
+        if (!conv) atomicAnd(&s_all, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_all) iws[done_slot] = 1;
+}
+
+hipError_t launch_leaf_check(const double* ws, int* iws, const LeafCheck* items, int count, int step,
+                             int done_slot, const int* guard, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_leaf_check, dim3(1), dim3(256), 0, s, ws, iws, items, count, step, done_slot, guard);
+    return hipGetLastError();
+}
+
+__global__ void k_reset_state(unsigned* __restrict__ flags, int* __restrict__ iws,
+                              const int* __restrict__ slots, int nslots) {
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < nslots; i += blockDim.x) iws[slots[i]] = 0;
+}
+
+hipError_t launch_reset_state(unsigned* flags, int* iws, const int* slots, int nslots, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, flags, iws, slots, nslots);
+    return hipGetLastError();
+}
+
 hipError_t launch_output(int fp32, const double* ws, int* iws, const OutputArgs* args, int count,
                          int kmax, int mmax, int nmax, void* const* ptrs, hipStream_t s) {
     if (count <= 0) return hipSuccess;

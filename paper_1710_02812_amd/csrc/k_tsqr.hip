@@ -58,7 +58,8 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_factor(double* __restrict__ ws,
                                                               int* __restrict__ iws,
                                                               const TsqrTask* __restrict__ tasks,
                                                               const ChunkRef* __restrict__ chunks,
-                                                              int w, int ch) {
+                                                              int w, int ch, const int* __restrict__ guard) {
+    if (guard && *guard) return;                     // a skipped stage (every group returns)
     extern __shared__ double sm[];
     double* T = sm;                                  // w x (w + 1)
     double* tau = T + (int64_t)w * (w + 1);
@@ -187,7 +188,9 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
                                                              const TsqrTask* __restrict__ tsqr,
                                                              const ApplyTask* __restrict__ tasks,
                                                              const ChunkRef* __restrict__ chunks,
-                                                             int w, int ch, int c) {
+                                                             int w, int ch, int c,
+                                                             const int* __restrict__ guard) {
+    if (guard && *guard) return;                     // a skipped stage (every group returns)
     extern __shared__ double sm[];
     const int ld = w + 1;
     double* X = sm;                                  // w x c (ld w + 1)
@@ -321,33 +324,34 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr_apply(double* __restrict_
 
 template <int LANES, int RMAX, int NTHR>
 static hipError_t launch_factor_t(double* ws, int* iws, const TsqrTask* tasks,
-                                  const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s) {
+                                  const ChunkRef* chunks, int nchunks, int w, int ch, hipStream_t s,
+                                  const int* guard) {
     if (w > TsqrQR<LANES, RMAX, NTHR>::WMAX) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * (TsqrQR<LANES, RMAX, NTHR>::lds_doubles(w) + 32);
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_factor<LANES, RMAX, NTHR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tsqr_factor<LANES, RMAX, NTHR>), dim3(nchunks), dim3(NTHR), lds, s, ws,
-                       iws, tasks, chunks, w, ch);
+                       iws, tasks, chunks, w, ch, guard);
     return hipGetLastError();
 }
 
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks, const ChunkRef* chunks,
-                              int nchunks, int w, int ch, hipStream_t s) {
+                              int nchunks, int w, int ch, hipStream_t s, const int* guard) {
     if (nchunks <= 0) return hipSuccess;
     if (w < 1 || w > kTsqrMaxW || ch != tsqr_chunk_rows(w)) return hipErrorInvalidValue;
     // a chunk and a stacked pair of R factors must fit the register block
     if (w <= 64) {
         if (ch > 16 * 16 || tsqr_fanin(w) * w > 16 * 16) return hipErrorInvalidValue;
-        return launch_factor_t<16, 16, 512>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+        return launch_factor_t<16, 16, 512>(ws, iws, tasks, chunks, nchunks, w, ch, s, guard);
     }
     if (ch > 16 * 10 || tsqr_fanin(w) * w > 16 * 10) return hipErrorInvalidValue;
-    return launch_factor_t<16, 10, 768>(ws, iws, tasks, chunks, nchunks, w, ch, s);
+    return launch_factor_t<16, 10, 768>(ws, iws, tasks, chunks, nchunks, w, ch, s, guard);
 }
 
 hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
-                             hipStream_t s) {
+                             hipStream_t s, const int* guard) {
     if (nchunks <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * (2 * (size_t)(w + 1) * c + apply_buf(w, ch) +
                                          (apply_stage_t(w, ch, c) ? (size_t)w * w : 0) + 32);
@@ -362,7 +366,7 @@ hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, c
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tsqr_apply, dim3(nchunks), dim3(TSQR_THREADS), lds, s, ws, iws, tsqr, tasks,
-                       chunks, w, ch, c);
+                       chunks, w, ch, c, guard);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = H.default_options()
     assert (o.precision, o.rule, o.oversample, o.power_steps, o.refine_steps, o.max_sweeps,
-            o.seed, o.refine_eps) == (0, 0, 14, 1, 0, 40, 0, 0.0)
+            o.seed, o.refine_eps) == (0, 0, 14, -1, 0, 40, 0, 0.0)
 
 
 @pytest.mark.parametrize("args", [
@@ -61,6 +61,10 @@ def test_plan_rejects_bad_options_and_unsupported_rank():
     o = H.default_options()
     o.max_sweeps = 0
     assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
+    for bad in (-2, 65):
+        o = H.default_options()
+        o.power_steps = bad
+        assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
     for bad in (-1e-3, float("nan")):
         o = H.default_options()
         o.refine_steps, o.refine_eps = 3, bad
@@ -89,6 +93,9 @@ def test_null_handles():
     (1000, 900, 3, 4, 20, {}),
     (1000, 900, 3, 4, 20, {"power_steps": 0}),
     (1000, 900, 3, 4, 20, {"power_steps": 2, "refine_steps": 2}),
+    (1000, 900, 3, 4, 20, {"power_steps": -1, "rule": 1}),
+    (8192, 8192, 8, 8, 50, {"power_steps": -1}),
+    (1000, 900, 3, 4, 20, {"power_steps": -1, "refine_steps": 3, "refine_eps": 1e-4}),
     (777, 333, 5, 3, 17, {"rule": 1}),
     (300, 200, 1, 1, 7, {}),
     (10, 7, 10, 7, 1, {}),
