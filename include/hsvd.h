@@ -78,7 +78,7 @@ typedef struct {
                                (default): float64 plans iterate until converged -- after
                                step t the leaf core gives the sketch's singular values
                                s_0..s_{l-1}, and with r the leaf's truncation rank the
-                               step count is enough once (s_{l-1} / s_{r-1})^(2t+1) <= 1e-12
+                               step count is enough once (s_{l-1} / s_{r-1})^(2t+1) <= 1e-15
                                for every leaf (the subspace-iteration bound on how far a
                                further step could turn the kept subspace), at most 6
                                steps; float32, mixed and width plans take 1 step for -1 */
