@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Time-to-rank-k benchmark of the hierarchical MAT SVD on one MI355X.
 
-Workload (the configuration the metric is quoted on): an 8192 x 8192
-snapshot-like matrix A[i,j] = sum_{r<50} exp(-r/8) sin(pi r x_i + phi_r)
-cos(pi r t_j) + 1e-6 N(0,1) (seeded, synthetic), an 8 x 8 grid of 1024^2
-blocks, rank cap k = 50, tol = 0.  A step is one hsvd_execute on an A already
+Default workload (the configuration the metric, "mixed vs FP64 at <= 1e-3 error", is
+quoted on): a 16384 x 16384 float32 matrix A = U diag(s) V^T + 1e-5 N(0,1) with
+s_i = exp(-i/10) for i < 256 (U, V seeded Haar bases), a 16 x 16 grid of 1024^2
+blocks, rank cap k = 64, tol = 0.  A step is one hsvd_execute on an A already
 resident in HBM (all stages: leaves, column tree, re-projection, row tree,
-projection, output; plus the refinement step on the mixed path).  Three paths
-are timed -- mixed (bfloat16 matrix-core passes, float32-accurate projection and
-one Algorithm 2 step, float64 QR and cores; A stored float32), float32 storage
-(float64 arithmetic) and float64 -- each with its error against the oracle.
-`value` is the time of the fastest path whose factored Frobenius error against
-the oracle is <= 1e-3 (`config.path` names it; the mixed path when accuracy is
-not computed).
+projection, output, and on the mixed path its Algorithm 2 step).  Three paths are
+timed on the same matrix: mixed (bfloat16 matrix-core passes, float64 projection and
+one Algorithm 2 step against the float32 A, float64 QR and cores), the plain float64
+form (A held as float64, one power step per leaf like the mixed path) and float32
+storage with float64 arithmetic.  `value` is the mixed path's time; `path_ms`,
+`mixed_speedup_vs_fp64` and `accuracy_vs_oracle` carry the comparison.
+
+Accuracy at this size comes from stored oracle values (tests/golden/c2_reference.json,
+written by tests/golden/make_c2_floor.py from the oracle alone): the oracle's rank and
+singular values (e_sigma), its residual, and a 64 x 64 two-sided sketch H^T X_o G of
+its factorisation, from which the Frobenius distance e_F of each path to the oracle is
+estimated (relative standard deviation ~5 %).  --accuracy full runs the oracle itself
+(several minutes) and reports the exact metrics.
 
 The roofline object is for the launch kind that takes most of a step.  Its
 launches are timed live with HIP events that the library records between its
@@ -20,7 +26,12 @@ launches on the execution stream; their algorithmic flops and bytes come from
 the plan (hsvd_launch_work).  `traffic` is the measured HBM traffic per launch
 from the committed rocprofv3 counter summary, used only while the kernel's
 sources are unchanged since the counters were taken.  cpu_baseline is the
-NumPy float64 oracle on the host cores.  Prints one JSON line.
+NumPy float64 oracle on the host cores, timed on a bounded sample (one row slab
+and the merges above it) and scaled to the whole job.  Prints one JSON line.
+
+Other workloads: --workload snapshot (8192^2 snapshot-like field, k = 50), uneven
+(200 matrices in one batched plan), learned (learned block ranks), refine
+(Algorithm 2 to a tolerance).
 
 --copy-probe runs a plain device copy (torch.mul by 1.0, one read and one write
 of a known size) for scaling the FETCH_SIZE / WRITE_SIZE counters.
@@ -66,8 +77,8 @@ def parse():
                     help="run warmup + steps of one path only (for rocprofv3)")
     ap.add_argument("--path", default="fp32", choices=["mixed", "fp32", "fp64"],
                     help="the path --profile-only runs")
-    ap.add_argument("--workload", default="snapshot", choices=["snapshot", "uneven", "learned", "refine"],
-                    help="snapshot: the 8192^2 headline; uneven: 200 matrices of uneven shapes "
+    ap.add_argument("--workload", default="c2", choices=["c2", "snapshot", "uneven", "learned", "refine"],
+                    help="c2: the 16384^2 mixed-vs-float64 headline; snapshot: the 8192^2 snapshot field; uneven: 200 matrices of uneven shapes "
                          "in one batched plan against a loop of per-matrix plans; learned: "
                          "32768 x 8192 field matrix, learned sketch widths against k + 14; refine: "
                          "the 8192^2 workload with Algorithm 2 to --refine-eps (at most "
@@ -76,6 +87,10 @@ def parse():
     ap.add_argument("--refine-eps", type=float, default=1e-3,
                     help="refine: stop when the singular values change by at most this (relative)")
     ap.add_argument("--count", type=int, default=200, help="uneven: number of matrices")
+    ap.add_argument("--accuracy", default="sketch", choices=["sketch", "full", "none"],
+                    help="c2: accuracy from the stored oracle sketch, from a full oracle run, or none")
+    ap.add_argument("--cpu-runs", type=int, default=3,
+                    help="c2: oracle sample runs at BLAS threads = physical cores (one more at 1 thread)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -114,9 +129,9 @@ def copy_probe(mib: int):
                       "launches": 5}))
 
 
-def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
+def time_path(H, torch, A, prec, args, k=50, p=8, q=8, **opts):
     m, n = A.shape
-    plan = H.Plan(m, n, p, q, k, 0.0, precision=prec)
+    plan = H.Plan(m, n, p, q, k, 0.0, precision=prec, **opts)
     dt = A.dtype
     U = torch.empty((m, k), dtype=dt, device=A.device)
     S = torch.empty((k,), dtype=dt, device=A.device)
@@ -134,8 +149,11 @@ def time_path(H, torch, A, prec, args, k=50, p=8, q=8):
     ms = t0.elapsed_time(t1) / args.steps
     flags = plan.status()
     r = plan.rank()
-    res = {"ms": ms, "flags": flags, "out": (U.double().cpu().numpy(), S.double().cpu().numpy(),
-                                             Vt.double().cpu().numpy(), r)}
+    res = {"ms": ms, "flags": flags}
+    if getattr(args, "workload", "") == "c2":
+        res["dev"] = (U.clone(), S.clone(), Vt.clone(), r)
+    else:
+        res["out"] = (U.double().cpu().numpy(), S.double().cpu().numpy(), Vt.double().cpu().numpy(), r)
     if args.profile_only:
         plan.close()
         return res
@@ -350,6 +368,229 @@ def run_uneven(args, torch):
     print(json.dumps(res))
 
 
+def cpu_facts() -> dict:
+    """CPU model, logical/physical core counts and the BLAS behind NumPy."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "model name" and model is None:
+                model = val
+            elif key == "physical id":
+                phys = val
+            elif key == "core id":
+                core = val
+                cores.add((phys, core))
+    except OSError:
+        pass
+    facts = {"model": model, "logical_cpus": os.cpu_count(),
+             "physical_cores": len(cores) or os.cpu_count()}
+    try:
+        from threadpoolctl import threadpool_info
+        facts["blas"] = [{kk: i.get(kk) for kk in ("internal_api", "version", "num_threads")}
+                         for i in threadpool_info()]
+    except Exception:
+        facts["blas"] = None
+    return facts
+
+
+def oracle_stages(A, p, q, k, threads):
+    """The oracle's stages on a bounded sample of the workload, at `threads` BLAS
+    threads: row slab 0 in full (its q exact leaf SVDs, its column merge tree, its
+    re-projection), one row merge (two n x k nodes) and the projection (A V and the
+    SVD of the m x k product).  Returns seconds per stage and the whole-job estimate
+    (slab stages x p, row merges x (p - 1))."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    from paper_1710_02812_amd import synth
+    m, n = A.shape
+    rows = oracle.balanced_split(m, p)
+    cols = oracle.balanced_split(n, q)
+    rng = np.random.default_rng(7)
+    Va, Vb = synth.orth(rng, n, k), synth.orth(rng, n, k)
+    sa, sb = np.exp(-np.arange(k) / 10.0), np.exp(-np.arange(k) / 10.0 - 0.05)
+    V = synth.orth(rng, n, k)
+    with threadpool_limits(limits=threads):
+        r0, r1 = rows[0]
+        X = A[r0:r1]
+        t0 = time.perf_counter()
+        leaves = [oracle.leaf(X[:, c0:c1], k, 0.0, "gamma") for (c0, c1) in cols]
+        t1 = time.perf_counter()
+        Ui, _ = oracle.merge_tree(leaves, k, 0.0, "gamma")
+        t2 = time.perf_counter()
+        W = Ui.T @ X
+        _, sw, Vwt = np.linalg.svd(W, full_matrices=False)
+        t3 = time.perf_counter()
+        oracle.merge(Va, sa, Vb, sb, k, 0.0, "gamma")
+        t4 = time.perf_counter()
+        oracle.project(A, V)
+        t5 = time.perf_counter()
+    st = {"leaves": (t1 - t0) * p, "column_merges": (t2 - t1) * p, "reprojection": (t3 - t2) * p,
+          "row_merges": (t4 - t3) * (p - 1), "projection": t5 - t4}
+    return {"sample_s": t5 - t0, "stages_s": st, "whole_s": sum(st.values())}
+
+
+def run_c2(args, torch):
+    """The 16384^2 mixed-precision workload: mixed path against the plain float64 form
+    and float32 storage, accuracy against the oracle, roofline and the oracle's CPU time."""
+    from paper_1710_02812_amd import hsvd as H, synth
+    size = args.size if args.size != 8192 else 16384
+    t = time.time()
+    w = synth.config2(2, m=size)
+    A32h = w.A.astype(np.float32)
+    del w.A
+    gen_s = time.time() - t
+    progress(f"c2: generated {size}^2 in {gen_s:.1f} s")
+    m, n = A32h.shape
+    p, q, k = w.p, w.q, w.k
+    A32 = torch.from_numpy(A32h).to("cuda")
+    A64 = A32.double()
+    torch.cuda.synchronize()
+    if args.profile_only:
+        prec = {"mixed": H.MIXED_BF16, "fp32": H.FP32, "fp64": H.FP64}[args.path]
+        opts = {} if args.path == "mixed" else {"power_steps": 1}
+        r = time_path(H, torch, A64 if args.path == "fp64" else A32, prec, args, k, p, q, **opts)
+        print(json.dumps({"profile_only": True, "path": args.path, "ms": r["ms"]}))
+        return
+    rmx = time_path(H, torch, A32, H.MIXED_BF16, args, k, p, q)
+    progress(f"c2: mixed {rmx['ms']:.3f} ms")
+    r64 = time_path(H, torch, A64, H.FP64, args, k, p, q, power_steps=1)
+    progress(f"c2: float64 {r64['ms']:.3f} ms")
+    r32 = time_path(H, torch, A32, H.FP32, args, k, p, q, power_steps=1)
+    progress(f"c2: float32 storage {r32['ms']:.3f} ms")
+    paths = {"mixed": rmx, "fp64": r64, "fp32": r32}
+
+    # accuracy against the oracle
+    acc = None
+    golden = os.path.join(ROOT, "tests", "golden")
+    floor = None
+    if os.path.exists(os.path.join(golden, "c2_floor.json")) and size == 16384:
+        fl = json.load(open(os.path.join(golden, "c2_floor.json")))
+        floor = {"F1_bf16_input_e_frob": fl["F1"]["e_frob"], "F2_randomised_leaves_e_frob": fl["F2"]["e_frob"],
+                 "floor": fl["floor"]}
+    gate = max(1e-3, floor["floor"]) if floor else 1e-3
+    nA2 = float((A64 * A64).sum().item())
+
+    def rel_residual(U, S, Vt, r):
+        Ud, Sd, Vd = U[:, :r].double(), S[:r].double(), Vt[:r].double()
+        cross = float((Sd * (Ud * (A64 @ Vd.T)).sum(0)).sum().item())
+        return float(np.sqrt(max(nA2 - 2.0 * cross + float((Sd * Sd).sum().item()), 0.0) / nA2))
+
+    if args.accuracy == "sketch" and size == 16384:
+        ref = json.load(open(os.path.join(golden, "c2_reference.json")))
+        Hm, Gm = synth.sketch_pair(ref["sketch_seed"], m, n, ref["sketch_t"])
+        Ht = torch.from_numpy(Hm).to("cuda")
+        Gt = torch.from_numpy(Gm).to("cuda")
+        sk0 = torch.tensor(ref["sketch"], dtype=torch.float64, device="cuda")
+        so = np.array(ref["sigma"])
+        ro = ref["rank"]
+        acc = {"method": "stored oracle values: rank, singular values, residual, 64 x 64 two-sided "
+                         "sketch of the oracle's factorisation (e_frob estimated, ~5 % rel. std)",
+               "gate_e_frob": gate}
+        for nm, r_ in paths.items():
+            U, S, Vt, r = r_["dev"]
+            skc = (Ht.T @ (U[:, :r].double() * S[:r].double())) @ (Vt[:r].double() @ Gt)
+            e_f = float(torch.linalg.norm(skc - sk0).item()) / ref["sketch_t"] / float(np.linalg.norm(so))
+            sh = S.double().cpu().numpy()[:r]
+            e_s = float(np.max(np.abs(sh - so))) / so[0] if r == ro else None
+            res = rel_residual(U, S, Vt, r)
+            acc[nm] = {"rank": r, "rank_oracle": ro, "e_frob_sketch": e_f, "e_sigma": e_s,
+                       "rel_residual": res, "residual_diff": abs(res - ref["rel_residual"]),
+                       "meets_gate": bool(r == ro and e_f <= gate)}
+        del Ht, Gt
+    elif args.accuracy == "full":
+        import oracle
+        from oracle import metrics
+        t = time.time()
+        Uo, so, Vto, ro = oracle.hsvd(A32h.astype(np.float64), p, q, k, 0.0)
+        progress(f"c2: oracle {time.time() - t:.1f} s")
+        acc = {"method": "full oracle run", "gate_e_frob": gate, "oracle_s": round(time.time() - t, 1)}
+        for nm, r_ in paths.items():
+            U, S, Vt, r = (x.double().cpu().numpy() if hasattr(x, "cpu") else x for x in r_["dev"])
+            c = metrics.compare(U, S, Vt, r, Uo, so, Vto, ro)
+            c = {kk: (float(v) if isinstance(v, float) else v) for kk, v in c.items()}
+            c["rel_residual"] = rel_residual(*r_["dev"])
+            c["meets_gate"] = bool(c["rank_hat"] == c["rank"] and c["e_frob"] <= gate)
+            acc[nm] = c
+    for r_ in paths.values():
+        r_.pop("dev", None)
+
+    # CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        facts = cpu_facts()
+        A64h = A32h.astype(np.float64)
+        runs = [oracle_stages(A64h, p, q, k, facts["physical_cores"]) for _ in range(max(1, args.cpu_runs))]
+        one = oracle_stages(A64h, p, q, k, 1)
+        del A64h
+        whole = np.array([r_["whole_s"] for r_ in runs]) * 1e3
+        cpu = {"value": round(float(whole.mean()), 1), "unit": "ms", "cores": facts["physical_cores"],
+               "kind": "oracle",
+               "sample": f"row slab 0 of {p} (its {q} exact leaf SVDs, column merge tree and re-projection), "
+                         f"one row merge and the projection, timed {len(runs)}x at "
+                         f"{facts['physical_cores']} BLAS threads and once at 1; slab stages scaled by {p}, "
+                         f"the row merge by {p - 1}",
+               "median_ms": round(float(np.median(whole)), 1),
+               "runs_ms": [round(float(x), 1) for x in whole],
+               "sample_s": round(float(np.mean([r_["sample_s"] for r_ in runs])), 2),
+               "stages_ms": {kk: round(v * 1e3, 1) for kk, v in runs[0]["stages_s"].items()},
+               "one_thread_ms": round(one["whole_s"] * 1e3, 1),
+               "one_thread_stages_ms": {kk: round(v * 1e3, 1) for kk, v in one["stages_s"].items()},
+               "cpu": facts}
+        progress(f"c2: oracle sample {cpu['value']:.0f} ms whole-job estimate")
+
+    kinds = rmx["kinds"]
+    dom = max(kinds, key=lambda kk: kinds[kk]["ms"])
+    roof = roofline_of(dom, kinds[dom])
+    tf, tb = rmx["work_total"]
+    t_roof = max(tf / (PEAK["fp64_TF"] * 1e12), tb / (PEAK["hbm_GBs"] * 1e9)) * 1e3
+
+    def kind_table(ks):
+        return {kk: {"launches": e["launches"], "ms": round(e["ms"], 4),
+                     "gflop": round(e["flops"] / 1e9, 3), "mbyte": round(e["bytes"] / 1e6, 2)}
+                for kk, e in ks.items()}
+
+    res = {
+        "metric": "time-to-rank-k SVD (ms) + MFMA/HBM roofline %, mixed vs FP64 at <=1e-3 err",
+        "value": round(rmx["ms"], 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(rmx["ms"], 4),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{m}x{n} float32, U diag(exp(-i/10)) V^T (i < 256) + 1e-5 N(0,1), "
+                               f"{p}x{q} grid of {m // p}x{n // q} blocks, k={k}, tol=0; mixed path "
+                               "(bfloat16 matrix-core passes, float64 QR and cores, float64 projection "
+                               "and one Algorithm 2 step against the float32 A)",
+                   "m": m, "n": n, "p": p, "q": q, "k": k, "path": "mixed", "storage": "f32"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "per_step_ms": rmx["per_step"],
+        "path_ms": {nm: round(r_["ms"], 4) for nm, r_ in paths.items()},
+        "path_per_step_ms": {nm: r_["per_step"] for nm, r_ in paths.items()},
+        "mixed_speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
+        "fp64_comparator": "A held as float64 (the float32 matrix widened), one power step per leaf as on "
+                           "the mixed path, all arithmetic float64",
+        "accuracy_vs_oracle": acc,
+        "intrinsic_floor": floor,
+        "whole_call_roofline": {"alg_flops": tf, "alg_bytes": tb, "t_roof_ms": t_roof,
+                                "frac": t_roof / rmx["ms"]},
+        "status_flags": {nm: r_["flags"] & 0xFFFF for nm, r_ in paths.items()},
+        "max_jacobi_sweeps": {nm: r_["flags"] >> 16 for nm, r_ in paths.items()},
+        "launch_kinds": {nm: kind_table(r_["kinds"]) for nm, r_ in paths.items()},
+        "launches_mixed": rmx["launches"],
+        "generate_s": round(gen_s, 2),
+    }
+    print(json.dumps(res))
+
+
 def progress(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -489,6 +730,9 @@ def main():
         return
     if args.workload == "refine":
         run_refine(args, torch)
+        return
+    if args.workload == "c2":
+        run_c2(args, torch)
         return
     from paper_1710_02812_amd import hsvd as H, synth
 

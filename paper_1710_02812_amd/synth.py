@@ -97,14 +97,24 @@ def config1(seed: int = 1, m: int = 8192, n: int = 8192, block: int = 1024) -> W
                     m // block, n // block, 50, 0.0, dtype="f32")
 
 
-def config2(seed: int = 2, m: int = 16384, block: int = 1024) -> Workload:
-    """16384^2, sigma_i = exp(-i/10) (i < 256) plus 1e-5 N(0,1); 16 x 16 grid, k = 64."""
+def config2(seed: int = 2, m: int = 16384, block: int = 1024, noise: str = "abs") -> Workload:
+    """16384^2, sigma_i = exp(-i/10) (i < 256) plus Gaussian noise; 16 x 16 grid, k = 64.
+
+    noise = "abs": 1e-5 N(0,1) entrywise (the literal reading; its spectral edge
+    1e-5 * 2 sqrt(m) ~ 2.6e-3 sits at sigma_60, so the rank-64 cut falls in the noise).
+    noise = "rel": 1e-5 times the signal's RMS entry, sqrt(sum sigma_i^2) / m, times
+    N(0,1) (the cut then falls in the clean exp(-i/10) decay).
+    """
+    if noise not in ("abs", "rel"):
+        raise ValueError("noise must be 'abs' or 'rel'")
     rng = np.random.default_rng(seed)
     sigma = np.exp(-np.arange(256) / 10.0)
-    A, U, s, V = low_rank(rng, m, m, sigma, noise=1e-5)
-    return Workload(f"C2_{m}x{m}_exp10_grid{m // block}x{m // block}_k64", A,
+    level = 1e-5 if noise == "abs" else 1e-5 * float(np.sqrt(np.sum(sigma ** 2))) / m
+    A, U, s, V = low_rank(rng, m, m, sigma, noise=level)
+    tag = "" if noise == "abs" else "_relnoise"
+    return Workload(f"C2{tag}_{m}x{m}_exp10_grid{m // block}x{m // block}_k64", A,
                     m // block, m // block, 64, 0.0, dtype="f32",
-                    meta={"sigma": s})
+                    meta={"sigma": s, "noise": level})
 
 
 def config3(seed: int = 3, count: int = 200, lo: int = 256, hi: int = 4096,
@@ -156,3 +166,16 @@ def config4(seed: int = 4, p: int = 32, q: int = 8, block: int = 1024,
                 (Ub[bi * block:(bi + 1) * block] * d) @ Vb[bj * block:(bj + 1) * block].T
     return Workload(f"C4_{m}x{n}_field_grid{p}x{q}", A, p, q, k, 1e-3, rule="frob",
                     dtype="f32", meta={"block_ranks": ranks})
+
+
+def sketch_pair(seed: int, m: int, n: int, t: int = 32) -> tuple[np.ndarray, np.ndarray]:
+    """Seeded Gaussian test matrices H (m x t) and G (n x t) for two-sided sketches.
+
+    For any m x n matrix D, E ||H^T D G||_F^2 = t^2 ||D||_F^2, so a stored t x t sketch
+    H^T X G of a reference factorisation lets the Frobenius distance of a candidate be
+    estimated without keeping the reference's m x k and n x k factors.  Draw order: H, G.
+    """
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((m, t))
+    G = rng.standard_normal((n, t))
+    return H, G
