@@ -61,6 +61,8 @@ KIND_SOURCES = {
     "tsqr_factor": ["k_tsqr.hip", "house_qr.hpp"], "tsqr_apply": ["k_tsqr.hip"],
     "gram": ["k_thin.hip"], "reduce": ["k_thin.hip"], "thin_nn": ["k_thin.hip"],
     "sum": ["k_thin.hip"], "core": ["k_core.hip", "house_qr.hpp"], "output": ["k_misc.hip"],
+    "cholqr": ["k_cholqr.hip"], "panel_qr": ["k_panelqr.hip"], "check": ["k_misc.hip"],
+    "energy": ["k_misc.hip"], "features": ["k_misc.hip"],
 }
 COMMON_SOURCES = ["device_common.hpp", "hsvd_internal.hpp"]
 

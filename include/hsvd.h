@@ -196,7 +196,8 @@ typedef enum {
     HSVD_LAUNCH_ENERGY = 12,       /* squared Frobenius norms of the blocks              */
     HSVD_LAUNCH_FEATURES = 13,     /* block features of a feature plan                   */
     HSVD_LAUNCH_CHOLQR = 14,       /* Cholesky QR passes (fast path of the panel QRs)    */
-    HSVD_LAUNCH_CHECK = 15         /* the leaves' power-step convergence test            */
+    HSVD_LAUNCH_CHECK = 15,        /* the leaves' power-step convergence test            */
+    HSVD_LAUNCH_PANEL_QR = 16      /* leaf panels: repeated Cholesky QR, one group each  */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

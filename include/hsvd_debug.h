@@ -73,6 +73,14 @@ hsvd_status hsvd_debug_tsqr(const double* P, int32_t batch, int64_t h, int32_t w
 hsvd_status hsvd_debug_cholqr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
                               double* R, int32_t* fell_back, hipStream_t stream);
 
+/* The leaves' one-launch panel QR (repeated Cholesky QR in one work-group per panel,
+ * the first pass shifted) on `batch` panels P (device, h x w col-major each, w <= 80),
+ * with the Householder TSQR run where it falls back; Q (h x w) and R (w x w, upper)
+ * as in hsvd_debug_tsqr, fell_back (host, batch ints) 1 where the Householder kernels
+ * ran.  P is not modified.  Errors as hsvd_debug_cholqr.                             */
+hsvd_status hsvd_debug_panel_qr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
+                                double* R, int32_t* fell_back, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

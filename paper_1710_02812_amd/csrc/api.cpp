@@ -57,7 +57,7 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
 }
 
 enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY, ST_CQ1, ST_CQ2,
-                 ST_FEAT, ST_LEAFCHECK };
+                 ST_FEAT, ST_LEAFCHECK, ST_PQR };
 
 struct Stage {
     StageKind kind;
@@ -70,6 +70,7 @@ struct Stage {
     size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
     int guard = -1;      // int-arena slot: the stage is skipped while it holds non-zero
     int step = 0;        // leaf check: the power step it follows
+    int need_r = 0;      // panel QR: R is formed
 };
 
 int pow2floor(int x) {
@@ -182,13 +183,20 @@ struct TsqrBuild {
     std::vector<TsqrTask> tasks;
     std::vector<ChunkRef> chunks;
     bool cholqr = false;     // some task takes the Cholesky QR fast path
+    bool pqr = false;        // some task takes the one-launch panel QR
 };
+
+// The one-launch panel QR (one work-group per panel) pays when there are enough panels
+// to fill the chip or they are short; a few tall panels keep the chunked TSQR.
+bool use_panel_qr(size_t npanels, int64_t hmax, int w) {
+    return w <= kPanelQrMaxW && (npanels >= 32 || hmax <= 2048);
+}
 
 // Adds TSQR bookkeeping for a panel; returns index into tb.tasks.  cholqr: the panel
 // (expected well-conditioned) first tries two Cholesky QR passes, the Householder
 // kernels running only if they fall back (panels up to 64 columns).
 int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w, int ch,
-             bool cholqr = false) {
+             bool cholqr = false, int64_t pq_dest = -1, int pq_ld = 0) {
     TsqrTask t{};
     t.p_off = panel;
     t.h = h;
@@ -205,6 +213,13 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
         t.cq_flag = P.ialloc(1);
         t.cq_cnt = P.ialloc(std::max(1, cq_nodes(t.nch)));
         tb.cholqr = true;
+    } else if (pq_dest >= 0 && w <= kPanelQrMaxW) {
+        // one-launch panel QR: Q to pq_dest, R to r_out; Householder on its fallback
+        t.pq_q_off = pq_dest;
+        t.pq_q_ld = pq_ld;
+        t.pq_scr = P.alloc(2 * (int64_t)w * w);
+        t.cq_flag = P.ialloc(1);
+        tb.pqr = true;
     }
     for (int c = 0; c < t.nch; ++c) tb.chunks.push_back({(int)tb.tasks.size(), c});
     tb.tasks.push_back(t);
@@ -213,7 +228,17 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
 
 void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks);
 
-void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
+void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch, bool need_r = true) {
+    if (tb.pqr) {
+        Stage q{};
+        q.kind = ST_PQR;
+        q.n = (int)tb.tasks.size();
+        q.w = w;
+        q.ch = ch;
+        q.need_r = need_r ? 1 : 0;
+        q.tasks_off = P.put(tb.tasks);
+        P.stages.push_back(q);
+    }
     if (tb.cholqr) {
         // pass 1 (G = P^T P, R1, M1 = R1^-1), Q1 = P M1, pass 2 (Q1^T Q1, R = R2 R1, M2)
         Stage c{};
@@ -251,6 +276,27 @@ void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch) {
 // Apply stage for tasks applying the factors of `tb` (one ApplyTask per tsqr task, in order).
 void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<ApplyTask>& at,
                      int w, int ch, int c) {
+    if (tb.pqr) {
+        // out = Q X (+ U1 T) from the explicit Q; an apply of the identity into the panel
+        // the panel QR already wrote is nothing more to do
+        std::vector<ThinTask> nn;
+        for (const ApplyTask& a : at) {
+            const TsqrTask& t = tb.tasks[a.tsqr];
+            if (t.pq_q_off < 0 || (a.out_off == t.pq_q_off && a.add_u_off < 0)) continue;
+            ThinTask y{};
+            y.x_off = t.pq_q_off; y.x_ld = t.pq_q_ld;
+            y.c_off = a.x_off; y.c_ld = w;
+            y.y_off = a.out_off; y.y_ld = a.out_ld;
+            y.h = t.h; y.wx = w; y.wy = c; y.accumulate = 0; y.cond = t.cq_flag;
+            if (a.add_u_off >= 0) {
+                y.x2_off = a.add_u_off; y.x2_ld = a.add_u_ld;
+                y.c2_off = a.add_t_off; y.c2_ld = a.add_w;
+                y.wx2 = a.add_w;
+            }
+            nn.push_back(y);
+        }
+        if (!nn.empty()) push_thin(P, ST_NN, nn);
+    }
     if (tb.cholqr) {
         // out = Q X + U1 T with Q = Q1 M2: C = M2 X (w x c), then out = Q1 C + U1 T
         std::vector<ThinTask> n1, n2;
@@ -546,10 +592,13 @@ void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
                    int ch, int64_t I_w, const std::vector<LeafPanels>& pan, std::vector<Node>& nodes) {
     const int W = P.W;
     TsqrBuild tby, tbz;
+    int64_t hmax = 1;
+    for (int b : ids) hmax = std::max({hmax, leaves[b].rowsz, leaves[b].colsz});
+    const bool pq = use_panel_qr(ids.size(), hmax, w);
     for (size_t u = 0; u < ids.size(); ++u) {
         const Leaf& l = leaves[ids[u]];
-        add_tsqr(P, tby, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch);
-        add_tsqr(P, tbz, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch);
+        add_tsqr(P, tby, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch, false, pq ? pan[u].Qy : -1, (int)l.rowsz);
+        add_tsqr(P, tbz, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch, false, pq ? pan[u].Qz : -1, (int)l.colsz);
     }
     push_tsqr_factor(P, tby, w, ch);
     std::vector<CoreTask> cores;
@@ -596,7 +645,7 @@ void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         const size_t first = P.stages.size();
         push_tsqr_apply(P, tby, aqy, w, ch, w);
         push_gemm(P, 1, gz, w);
-        push_tsqr_factor(P, tbz, w, ch);
+        push_tsqr_factor(P, tbz, w, ch, false);
         push_tsqr_apply(P, tbz, aqz, w, ch, w);
         push_gemm(P, 0, gy, w);
         push_tsqr_factor(P, tby, w, ch);
@@ -640,15 +689,22 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         return;
     }
     TsqrBuild tb_last;
+    int64_t hmax = 1;
+    for (int b : ids) hmax = std::max({hmax, leaves[b].rowsz, leaves[b].colsz});
+    const bool pq = use_panel_qr(ids.size(), hmax, w);
     for (int t = 1; t <= g; ++t) {
         const bool prev_is_y = ((t - 1) % 2 == 0);
         TsqrBuild tb;
         for (size_t u = 0; u < ids.size(); ++u) {
             const Leaf& l = leaves[ids[u]];
-            if (prev_is_y) add_tsqr(P, tb, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch);
-            else add_tsqr(P, tb, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch);
+            if (prev_is_y)
+                add_tsqr(P, tb, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch, false, pq ? pan[u].Qy : -1,
+                         (int)l.rowsz);
+            else
+                add_tsqr(P, tb, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch, false, pq ? pan[u].Qz : -1,
+                         (int)l.colsz);
         }
-        push_tsqr_factor(P, tb, w, ch);
+        push_tsqr_factor(P, tb, w, ch, t == g);
         if (t == g) { tb_last = tb; break; }
         std::vector<ApplyTask> at;
         for (size_t u = 0; u < ids.size(); ++u) {
@@ -1247,7 +1303,10 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     if (!span("tsqr store", t.store_off, t.store_off + (int64_t)nodes * tsqr_slot_size(s.w) - 1, WS)) return msg;
                     if (!span("tsqr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
                     if (!span("tsqr counters", t.cnt_off, t.cnt_off + nodes - 1, IW)) return msg;
-                    if (t.cq_flag >= 0) {
+                    if (t.pq_q_off >= 0) {
+                        if (s.kind == ST_CQ1 || s.kind == ST_CQ2) return "panel qr task in a Cholesky QR pass";
+                        if (t.cq_flag < 0 || t.cq_flag >= IW) return "panel qr flag slot";
+                    } else if (t.cq_flag >= 0) {
                         if (s.w > 64 || s.ch > 256) return "cholqr geometry";
                         if (!span("cholqr scratch", t.cq_off, t.cq_off + cq_size(s.w, t.nch, t.h) - 1, WS)) return msg;
                         if (t.cq_flag >= IW || t.cq_cnt < 0 || t.cq_cnt + std::max(1, cq_nodes(t.nch)) > IW)
@@ -1320,6 +1379,23 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const MatDesc& M = P.mats[t.mat];
                     if (t.lda != M.n || t.cols > M.n || t.a_off % M.n + t.cols > M.n) return "energy block";
                     if (!span("energy A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * M.n + t.cols - 1, M.m * M.n)) return msg;
+                }
+                break;
+            }
+            case ST_PQR: {
+                const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
+                if (s.w < 1 || s.w > kPanelQrMaxW) return "panel qr width";
+                for (int i = 0; i < s.n; ++i) {
+                    const TsqrTask& t = T[i];
+                    if (t.pq_q_off < 0) continue;
+                    if (!panel("panel qr P", t.p_off, t.p_ld, t.h, s.w)) return msg;
+                    if (!panel("panel qr Q", t.pq_q_off, t.pq_q_ld, t.h, s.w)) return msg;
+                    const int64_t p_end = t.p_off + (int64_t)(s.w - 1) * t.p_ld + t.h;
+                    const int64_t q_end = t.pq_q_off + (int64_t)(s.w - 1) * t.pq_q_ld + t.h;
+                    if (t.pq_q_off < p_end && t.p_off < q_end) return "panel qr Q overlaps P";
+                    if (!span("panel qr scratch", t.pq_scr, t.pq_scr + 2LL * s.w * s.w - 1, WS)) return msg;
+                    if (s.need_r && !span("panel qr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
+                    if (t.cq_flag < 0 || t.cq_flag >= IW) return "panel qr flag slot";
                 }
                 break;
             }
@@ -1407,6 +1483,9 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
         case ST_CQ2:
             e = launch_cholqr(s.kind == ST_CQ1 ? 1 : 2, P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
                               (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
+            break;
+        case ST_PQR:
+            e = launch_panel_qr(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off), s.n, s.w, s.need_r, st, guard);
             break;
         case ST_TSQR_F:
             e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
@@ -1775,6 +1854,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_ENERGY: kind = HSVD_LAUNCH_ENERGY; break;
                 case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
                 case ST_LEAFCHECK: kind = HSVD_LAUNCH_CHECK; break;
+                case ST_PQR: kind = HSVD_LAUNCH_PANEL_QR; break;
             }
         }
         float ms = 0.f;
@@ -1909,6 +1989,15 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     f = 0.0;
                     by = 0.0;
                     break;
+                case ST_PQR: {                                    // a QR of the panel and its explicit Q
+                    const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
+                    for (int t = 0; t < s.n; ++t) {
+                        const double h = T[t].h, w = s.w, mn = std::min(h, w), mx = std::max(h, w);
+                        f += 2.0 * (2.0 * mx * mn * mn - 2.0 * mn * mn * mn / 3.0);
+                        by += 2.0 * h * w * e8;
+                    }
+                    break;
+                }
                 case ST_FEAT:
                     f = 40.0 * s.n;
                     by = s.n * (17.0 * e8 + 16.0 * 4.0);

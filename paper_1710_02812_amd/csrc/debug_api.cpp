@@ -310,3 +310,75 @@ extern "C" hsvd_status hsvd_debug_cholqr(const double* P, int32_t batch, int64_t
     for (int b = 0; b < batch; ++b) fell_back[b] = flags[(size_t)b * iper + nodes];
     return HSVD_OK;
 }
+
+extern "C" hsvd_status hsvd_debug_panel_qr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
+                                           double* R, int32_t* fell_back, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    if (!P || !Q || !R || !fell_back || batch < 1 || h < 1 || w < 1 || w > kPanelQrMaxW ||
+        w > kTsqrMaxW || h > (1 << 26))
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_panel_qr: bad argument");
+    Scratch sc;
+    const int ch = tsqr_chunk_rows(w);
+    const int nch = (int)((h + ch - 1) / ch);
+    const int nodes = tsqr_nodes(nch, tsqr_fanin(w));
+    const int64_t hw = h * w, ww = (int64_t)w * w, slot = tsqr_slot_size(w);
+    // arena: P | I | Q | TSQR storage | R | panel QR scratch
+    const int64_t offP = 0, offI = offP + batch * hw, offQ = offI + ww, offS = offQ + batch * hw,
+                  offR = offS + (int64_t)batch * nodes * slot, offX = offR + batch * ww,
+                  tot = offX + 2 * batch * ww;
+    const int iper = nodes + 1;
+    double* ws = sc.get<double>(tot);
+    int* iws = sc.get<int>((size_t)batch * iper);
+    TsqrTask* dt = sc.get<TsqrTask>(batch);
+    ApplyTask* da = sc.get<ApplyTask>(batch);
+    ChunkRef* dc = sc.get<ChunkRef>((size_t)batch * nch);
+    if (!ws || !iws || !dt || !da || !dc) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    std::vector<TsqrTask> tt(batch);
+    std::vector<ApplyTask> at(batch);
+    std::vector<ChunkRef> cr;
+    for (int b = 0; b < batch; ++b) {
+        TsqrTask t{};
+        t.p_off = offP + b * hw;
+        t.store_off = offS + (int64_t)b * nodes * slot;
+        t.r_out = offR + b * ww;
+        t.h = (int)h;
+        t.p_ld = (int)h;
+        t.nch = nch;
+        t.chunk0 = b * nch;
+        t.cnt_off = b * iper;
+        t.levels = tsqr_levels(nch, tsqr_fanin(w));
+        t.cq_flag = b * iper + nodes;
+        t.pq_q_off = offQ + b * hw;
+        t.pq_q_ld = (int)h;
+        t.pq_scr = offX + 2 * b * ww;
+        tt[b] = t;
+        ApplyTask a{};                                   // Householder fallback: Q = Q_H I
+        a.tsqr = b;
+        a.x_off = offI;
+        a.out_off = offQ + b * hw;
+        a.out_ld = (int)h;
+        a.add_u_off = -1;
+        at[b] = a;
+        for (int c = 0; c < nch; ++c) cr.push_back({b, c});
+    }
+    std::vector<double> I((size_t)ww, 0.0);
+    for (int i = 0; i < w; ++i) I[(size_t)i * w + i] = 1.0;
+    hipError_t e = hipMemcpyAsync(ws + offP, P, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + offI, I.data(), sizeof(double) * ww, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(iws, 0, sizeof(int) * batch * iper, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tt.data(), sizeof(TsqrTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(da, at.data(), sizeof(ApplyTask) * batch, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, cr.data(), sizeof(ChunkRef) * cr.size(), hipMemcpyHostToDevice, stream);
+    const int nc = (int)cr.size();
+    if (e == hipSuccess) e = launch_panel_qr(ws, iws, dt, batch, w, 1, stream);
+    if (e == hipSuccess) e = launch_tsqr_factor(ws, iws, dt, dc, nc, w, ch, stream);
+    if (e == hipSuccess) e = launch_tsqr_apply(ws, iws, dt, da, dc, nc, w, ch, w, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Q, ws + offQ, sizeof(double) * batch * hw, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(R, ws + offR, sizeof(double) * batch * ww, hipMemcpyDeviceToDevice, stream);
+    std::vector<int> flags((size_t)batch * iper);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), iws, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_panel_qr: ") + hipGetErrorString(e));
+    for (int b = 0; b < batch; ++b) fell_back[b] = flags[(size_t)b * iper + nodes];
+    return HSVD_OK;
+}

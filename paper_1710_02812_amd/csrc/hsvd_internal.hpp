@@ -45,6 +45,11 @@ struct TsqrTask {
     // run) and the first of its cq_nodes arrival counters (one when nch = 1)
     int64_t cq_off = 0;
     int32_t cq_flag = -1, cq_cnt = -1;
+    // one-launch panel QR (k_panel_qr; pq_q_off < 0: none): explicit Q written to
+    // pq_q_off (h x w, ld pq_q_ld, not overlapping the panel), R to r_out when asked,
+    // 2 w^2 doubles of scratch at pq_scr; its outcome goes to cq_flag as above
+    int64_t pq_q_off = -1, pq_scr = 0;
+    int32_t pq_q_ld = 0, pq_pad = 0;
 };
 struct ChunkRef { int32_t task; int32_t chunk; };
 
@@ -180,6 +185,12 @@ hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
                               const ChunkRef* chunks, int nchunks, int w, int ch,
                               hipStream_t s, const int* guard = nullptr);
+// Panel QR of the leaves (one work-group per TsqrTask with pq_q_off >= 0, w <= kPanelQrMaxW):
+// repeated Cholesky QR, the first pass shifted; need_r also forms R at r_out.
+constexpr int kPanelQrMaxW = 96;
+constexpr int kPanelQrMaxPass = 4;
+hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntasks, int w, int need_r,
+                           hipStream_t s, const int* guard = nullptr);
 hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s, const int* guard = nullptr);

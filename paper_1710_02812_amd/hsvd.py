@@ -32,12 +32,13 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_rank_model_create", "hsvd_rank_model_destroy", "hsvd_rank_model_set_params",
             "hsvd_rank_model_get_params", "hsvd_rank_model_train", "hsvd_rank_model_grad",
             "hsvd_rank_model_predict",
-            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_plan_check",
+            "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
+            "hsvd_debug_plan_check",
             "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features", "cholqr",
-                "check"]
+                "check", "panel_qr"]
 
 
 class HsvdError(RuntimeError):
@@ -99,6 +100,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_debug_jacobi.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, P(ctypes.c_uint32), vp]
     L.hsvd_debug_tsqr.argtypes = [vp, i32, i64, i32, vp, vp, vp]
     L.hsvd_debug_cholqr.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
+    L.hsvd_debug_panel_qr.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
     L.hsvd_debug_gemm.argtypes = [i32, i32, i32, vp, i64, i64, i64, vp, i32, vp, vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
                                         P(ctypes.c_size_t)]
@@ -589,4 +591,19 @@ def debug_cholqr(P):
     fb = (ctypes.c_int32 * b)()
     _check(lib().hsvd_debug_cholqr(Pc.data_ptr(), b, h, w, Q.data_ptr(), R.data_ptr(), fb,
                                    _stream_handle()))
+    return Q.transpose(1, 2), R.transpose(1, 2), list(fb)
+
+
+def debug_panel_qr(P):
+    """The leaves' one-launch panel QR (repeated Cholesky QR, the first pass shifted;
+    Householder where it falls back) of float64 panels P (batch, h, w), w <= 80
+    -> (Q (batch, h, w), R (batch, w, w), fell_back list of 0/1 per panel)."""
+    import torch
+    b, h, w = P.shape
+    Pc = P.transpose(1, 2).contiguous()
+    Q = torch.empty_like(Pc)
+    R = torch.empty((b, w, w), dtype=torch.float64, device=P.device)
+    fb = (ctypes.c_int32 * b)()
+    _check(lib().hsvd_debug_panel_qr(Pc.data_ptr(), b, h, w, Q.data_ptr(), R.data_ptr(), fb,
+                                     _stream_handle()))
     return Q.transpose(1, 2), R.transpose(1, 2), list(fb)

@@ -232,6 +232,63 @@ def test_cholqr_fallback_and_dead_columns(h, w):
     assert np.linalg.norm(Qw.cpu().numpy()[0] @ Rw.cpu().numpy()[0] - Pw[0]) <= 1e-13 * np.linalg.norm(Pw[0])
 
 
+@pytest.mark.parametrize("h,w,kappa", [(1024, 78, 1e2), (1024, 78, 1e7), (1000, 33, 1e12), (257, 80, 1e4),
+                                       (64, 16, 1.0), (4096, 64, 1e9), (130, 1, 1.0), (1024, 80, 1e13)])
+def test_panel_qr(h, w, kappa):
+    """The leaves' one-launch panel QR (repeated Cholesky QR, the first pass shifted)
+    stands without the Householder fallback on panels of condition number up to 1e13:
+    P = Q R, Q orthonormal, R upper triangular with P's singular values (absolute error
+    1e-13 s_1, what a backward-stable QR gives)."""
+    rng = np.random.default_rng(h * 7 + w)
+    P = np.stack([_graded_panel(rng, h, w, kappa), rng.standard_normal((h, w))])
+    print(f"panel qr h={h} w={w} kappa={kappa:g}", flush=True)
+    Q, R, fb = H.debug_panel_qr(_t(P))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert fb == [0, 0]
+    for b in range(2):
+        assert np.all(np.tril(R[b], -1) == 0.0)
+        assert np.linalg.norm(Q[b] @ R[b] - P[b]) <= 1e-14 * np.sqrt(w) * np.linalg.norm(P[b])
+        assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(w)) <= 1e-14 * np.sqrt(h) * w
+        s_ref = np.linalg.svd(P[b], compute_uv=False)
+        assert np.max(np.abs(np.linalg.svd(R[b], compute_uv=False) - s_ref)) <= 1e-13 * s_ref[0]
+
+
+def test_panel_qr_fallback_dead_columns_and_many_panels():
+    """An exactly rank-deficient panel (rank 5 of 20 columns: the sketch of an exactly
+    low-rank block) falls back to the Householder kernels; exactly zero columns stay on
+    the Cholesky path as zero columns of Q and zero rows of R; a zero panel gives Q = 0,
+    R = 0; 256 leaf-shaped panels (1024 x 78) in one launch all stand."""
+    rng = np.random.default_rng(5)
+    h, w = 700, 20
+    low = rng.standard_normal((h, 5)) @ rng.standard_normal((5, w))
+    dead = rng.standard_normal((h, w))
+    dead[:, [0, 7]] = 0.0
+    P = np.stack([low, dead, np.zeros((h, w))])
+    Q, R, fb = H.debug_panel_qr(_t(P))
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert fb == [1, 0, 0]
+    for b in range(3):
+        assert np.allclose(np.tril(R[b], -1), 0.0)
+        assert np.linalg.norm(Q[b] @ R[b] - P[b]) <= 1e-13 * np.sqrt(h * w) * max(np.linalg.norm(P[b]), 1.0)
+    assert np.linalg.norm(Q[0].T @ Q[0] - np.eye(w)) <= 1e-13 * np.sqrt(h) * w
+    live = np.ones(w, bool)
+    live[[0, 7]] = False
+    assert np.all(Q[1][:, ~live] == 0.0) and np.all(R[1][~live, :] == 0.0)
+    Ql = Q[1][:, live]
+    assert np.linalg.norm(Ql.T @ Ql - np.eye(live.sum())) <= 1e-14 * np.sqrt(h) * w
+    assert np.all(Q[2] == 0.0) and np.all(R[2] == 0.0)
+    b, h, w = 256, 1024, 78
+    P = rng.standard_normal((b, h, w)) * np.logspace(0, -3, w)[None, None, :]
+    print(f"panel qr batch={b} h={h} w={w}", flush=True)
+    Q, R, fb = H.debug_panel_qr(_t(P))
+    assert fb == [0] * b
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    res = np.linalg.norm(np.einsum("bij,bjk->bik", Q, R) - P, axis=(1, 2)) / np.linalg.norm(P, axis=(1, 2))
+    orth = np.linalg.norm(np.einsum("bji,bjk->bik", Q, Q) - np.eye(w), axis=(1, 2))
+    assert res.max() <= 1e-14 * np.sqrt(w), res.max()
+    assert orth.max() <= 1e-14 * np.sqrt(h) * w, orth.max()
+
+
 def _bf16(x):
     """Round to bfloat16 (nearest even) through float32, as the matrix-core passes do."""
     f = np.ascontiguousarray(x, dtype=np.float32)
