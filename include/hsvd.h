@@ -291,6 +291,25 @@ hsvd_status hsvd_rank_model_grad(hsvd_rank_model_t model, const float* X, const 
 hsvd_status hsvd_rank_model_predict(hsvd_rank_model_t model, const float* X, int32_t count, float* out,
                                     hipStream_t stream);
 
+/* Allocation-free one-shot SVD, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: graph capture, tight serving loops, harnesses that
+ * forbid it).  Same method, arguments and results as hsvd_plan_ex followed by
+ * hsvd_execute on a single matrix (bit-identical outputs), but the plan's whole device
+ * state -- arena, int arena, status flags, task tables and pointer table -- is placed
+ * in a file-scope device array of 64 MiB (each GPU the library runs on holds its own
+ * copy until the process ends) instead of hipMalloc'd memory; the schedule is built in
+ * host memory.  The call clears the array with a kernel, uploads the task tables,
+ * enqueues the method on `stream` and synchronises `stream` before it returns
+ * (blocking); r_host (may be NULL) receives the effective rank.
+ *   A, U, S, Vt: as hsvd_execute (device, caller-owned).
+ *   Errors: as hsvd_plan_ex; HSVD_ERR_INVALID when the problem's device state exceeds
+ *   64 MiB (about 1024^2 on a 4 x 4 grid with k = 32) -- the message gives the bytes it
+ *   needs.  Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ *   (other threads, other streams) race and must be serialised by the caller.         */
+hsvd_status hsvd_svd_static(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k, double tol,
+                            const hsvd_options* opt, const void* A, void* U, void* S, void* Vt,
+                            int32_t* r_host, hipStream_t stream);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hsvd_last_error(void);
 

@@ -30,6 +30,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <random>
 #include <vector>
@@ -129,6 +131,7 @@ struct hsvd_plan_st {
     std::vector<void*> host_ptrs;  // its last uploaded contents
     hipStream_t last_stream = nullptr;
     bool executed = false;
+    bool external = false;         // device state not allocated by the plan (not freed)
 
     // final
     std::vector<OutputArgs> outs;  // per matrix
@@ -1551,7 +1554,7 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
 static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
                              const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
                              const hsvd_options* opt, size_t* check_only,
-                             const int32_t* leaf_width = nullptr, int kind = 0) {
+                             const int32_t* leaf_width = nullptr, int kind = 0, bool host_only = false) {
     if (!out && !check_only) return fail(HSVD_ERR_INVALID, "out is NULL");
     if (out) *out = nullptr;
     if (count < 1) return fail(HSVD_ERR_INVALID, "count must be >= 1");
@@ -1645,6 +1648,10 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
 
     hipError_t e = hipGetDevice(&P->device);
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice"); }
+    if (host_only) {                  // the caller places the device state itself
+        *out = P;
+        return HSVD_OK;
+    }
     e = hipMalloc(&P->ws, sizeof(double) * (size_t)std::max<int64_t>(P->ws_elems, 32));
     if (e != hipSuccess) { delete P; return fail(HSVD_ERR_ALLOC, "workspace allocation failed"); }
     e = hipMalloc(&P->iws, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
@@ -2014,6 +2021,10 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (!plan) return HSVD_OK;
     if (plan->executed) hipStreamSynchronize(plan->last_stream);
     for (auto& ev : plan->events) hipEventDestroy(ev);
+    if (plan->external) {             // device state in memory the plan does not own
+        delete plan;
+        return HSVD_OK;
+    }
     if (plan->ws) hipFree(plan->ws);
     if (plan->iws) hipFree(plan->iws);
     if (plan->flags) hipFree(plan->flags);
@@ -2085,6 +2096,92 @@ hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host) {
 }
 
 const char* hsvd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free entry point
+// The whole device state of one call (arena, int arena, status flags, task tables and the
+// pointer table) placed in a file-scope device array instead of hipMalloc'd memory.  In
+// host code `scratch` names a host-side stand-in: its device address is taken once per
+// device with hipGetSymbolAddress and only that address is used.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;   // per device: the address of that device's copy
+
+hsvd_status static_scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e,
+                                                   "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return HSVD_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+}  // namespace
+
+extern "C" {
+
+hsvd_status hsvd_svd_static(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k, double tol,
+                            const hsvd_options* opt, const void* A, void* U, void* S, void* Vt,
+                            int32_t* r_host, hipStream_t stream) {
+    if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL data pointer");
+    hsvd_plan_t P = nullptr;
+    hsvd_status st = plan_impl(&P, 1, &m, &n, &p, &q, &k, tol, opt, nullptr, nullptr, 0, true);
+    if (st != HSVD_OK) return st;
+    std::unique_ptr<hsvd_plan_st> hold(P);
+    P->external = true;
+    // layout: arena | int arena | flags | task blob | pointer table, 256-byte aligned
+    const size_t off_iws = align256(sizeof(double) * (size_t)std::max<int64_t>(P->ws_elems, 32));
+    const size_t off_flags = align256(off_iws + sizeof(int) * (size_t)std::max(P->iws_elems, 1));
+    const size_t off_blob = align256(off_flags + sizeof(unsigned) * 4);
+    const size_t off_ptrs = align256(off_blob + std::max<size_t>(P->blob.size(), 256));
+    const size_t total = align256(off_ptrs + sizeof(void*) * 4);
+    if (total > kStaticScratchBytes)
+        return fail(HSVD_ERR_INVALID, "hsvd_svd_static: this problem needs " + std::to_string(total) +
+                                          " bytes of device state; the allocation-free entry point holds at most " +
+                                          std::to_string(kStaticScratchBytes));
+    void* base = nullptr;
+    st = static_scratch_address(&base);
+    if (st != HSVD_OK) return st;
+    unsigned char* b = (unsigned char*)base;
+    P->ws = (double*)b;
+    P->iws = (int*)(b + off_iws);
+    P->flags = (unsigned*)(b + off_flags);
+    P->dblob = b + off_blob;
+    P->dptrs = (void**)(b + off_ptrs);
+    // the array keeps the previous call's contents: clear all of it (a kernel, no memset),
+    // then the task tables, the constant panels and the Gaussian test matrices
+    hipError_t e = launch_fill(P->ws, (int64_t)(total / sizeof(double)), 0.0, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice, stream);
+    for (auto& c : P->ws_init)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->ws + c.first, c.second.data(), c.second.size() * sizeof(double),
+                               hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_gaussian(P->ws + P->omega_off, P->omega_count, P->opt.seed, stream);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_svd_static: set-up");
+    st = execute_impl(*P, &A, &U, &S, &Vt, stream);
+    if (st != HSVD_OK) {
+        hipStreamSynchronize(stream);
+        return st;
+    }
+    int32_t r = 0;
+    e = hipMemcpyAsync(&r, P->iws + P->rank_slots[0], sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_svd_static");
+    if (r_host) *r_host = r;
+    return HSVD_OK;
+}
 
 }  // extern "C"
 

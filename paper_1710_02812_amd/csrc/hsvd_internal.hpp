@@ -171,6 +171,9 @@ struct RefineCheck {
 constexpr int kMlpParams = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1;   // 5313
 constexpr int kMlpBatch = 64;
 
+// Device state of the allocation-free entry point (a file-scope device array).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+
 // ---------------------------------------------------------------- launches
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // `guard` (device int or nullptr): when it points at a non-zero value every work-group

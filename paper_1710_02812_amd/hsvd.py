@@ -33,7 +33,7 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_rank_model_get_params", "hsvd_rank_model_train", "hsvd_rank_model_grad",
             "hsvd_rank_model_predict",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
-            "hsvd_debug_plan_check",
+            "hsvd_debug_plan_check", "hsvd_svd_static",
             "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_debug_gemm.argtypes = [i32, i32, i32, vp, i64, i64, i64, vp, i32, vp, vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
                                         P(ctypes.c_size_t)]
+    L.hsvd_svd_static.argtypes = [i64, i64, i32, i32, i32, f64, P(Options), vp, vp, vp, vp, P(i32), vp]
     for name in EXPORTED:
         if name != "hsvd_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -508,6 +509,31 @@ def svd(A, p: int, q: int, k: int, tol: float = 0.0, mixed: bool = False, **opts
     if flags:
         raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
     return U, S, Vt, r
+
+
+def svd_static(A, p: int, q: int, k: int, tol: float = 0.0, **opts):
+    """hsvd_svd_static: the allocation-free one-shot SVD of a torch device matrix
+    (float64, or float32 with precision=FP32 / MIXED_BF16).  Returns (U, S, Vt, r); the
+    outputs are allocated here by torch, the library itself allocates no device memory.
+    Blocking (the call synchronises the current stream)."""
+    import torch
+    if A.dtype not in (torch.float64, torch.float32) or A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D float64 or float32 device tensor")
+    A = A.contiguous()
+    m, n = A.shape
+    o = _options(opts.pop("precision", FP64 if A.dtype == torch.float64 else FP32),
+                 opts.pop("rule", RULE_GAMMA), opts.pop("oversample", None), opts.pop("power_steps", None),
+                 opts.pop("refine_steps", 0), opts.pop("max_sweeps", None), opts.pop("seed", 0),
+                 opts.pop("refine_eps", 0.0))
+    if opts:
+        raise TypeError(f"unknown options {sorted(opts)}")
+    U = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    S = torch.empty((k,), dtype=A.dtype, device=A.device)
+    Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
+    r = ctypes.c_int32()
+    _check(lib().hsvd_svd_static(m, n, p, q, k, float(tol), ctypes.byref(o), A.data_ptr(), U.data_ptr(),
+                                 S.data_ptr(), Vt.data_ptr(), ctypes.byref(r), _stream_handle()))
+    return U, S, Vt, r.value
 
 
 def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True, precondition: bool = False):
