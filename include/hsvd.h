@@ -57,9 +57,10 @@ typedef enum {
  *         re-projection run on the matrix cores with A and the panels rounded to
  *         bfloat16 and float32 sums; the projection and one iteration of
  *         Algorithm 2 (always added; refine_steps counts further ones) read the
- *         float32 A with float64 arithmetic, so S and the subspaces are refined
- *         against the unrounded input.  Factor panels, QR and the Jacobi cores
- *         are float64 throughout.                                               */
+ *         float32 A unrounded on the float32 matrix cores (panels rounded to
+ *         float32, float32 sums), so S and the subspaces are refined against the
+ *         unrounded input to float32 accuracy.  Factor panels, QR and the Jacobi
+ *         cores are float64 throughout.                                         */
 typedef enum { HSVD_FP64 = 0, HSVD_FP32 = 1, HSVD_MIXED_BF16 = 2 } hsvd_precision;
 
 /* Truncation rule (Section 3): GAMMA keeps s_i >= tol * s_1 of the matrix being
@@ -96,6 +97,13 @@ typedef struct {
                                then waits for it (one 4-byte read-back per iteration, the
                                last excepted), and per-launch timing (hsvd_set_profiling) is
                                refused.  Must not be negative or NaN (HSVD_ERR_INVALID).  */
+    int32_t  graph;         /* 1 (default): the first execute captures the plan's launch
+                               sequence into a hipGraph (on a stream private to the plan)
+                               and every execute launches that graph on the caller's
+                               stream; 0: every execute launches its kernels one by one.
+                               Plans stopped on refine_eps and executes with per-launch
+                               timing on always launch one by one.                      */
+    int32_t  reserved;      /* must be 0                                                */
 } hsvd_options;
 
 /* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
@@ -122,7 +130,11 @@ hsvd_status hsvd_plan_ex(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int3
 
 /* Runs the method on A and writes the result.  Asynchronous, ordered on `stream`
  * (0 = the null stream); no host synchronisation inside, except the waits of
- * Algorithm 2 stopped on refine_eps (see hsvd_options).
+ * Algorithm 2 stopped on refine_eps (see hsvd_options) and a wait for the previous
+ * execute when the data pointers differ from its (the device pointer table is
+ * replaced).  With opt.graph = 1 the first execute captures the launches into a
+ * hipGraph and every execute replays it (the graph reads A, U, S, Vt through the
+ * pointer table, so one graph serves every input).
  *   A  : m x n, row-major, contiguous (leading dimension n), read only.
  *   U  : m x k, row-major.   S : k, descending.   Vt : k x n, row-major.
  *   Element type double (FP64 plans) or float (FP32 plans).
@@ -176,8 +188,22 @@ hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count);
  * any core of that execute ran. */
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
 
-/* Device workspace owned by the plan, in bytes. */
+/* Bytes of the plan's device workspace: its float64 arena (panels, scratch, the
+ * leaves' Gaussian test matrices) and its int arena (ranks, counters, flags), as
+ * hsvd_set_workspace lays them out.  The task tables and the pointer table (a few
+ * hundred KB at most) are not included. */
 hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host);
+
+/* Moves the plan's workspace (see hsvd_workspace_bytes) into a caller-owned device
+ * buffer, e.g. memory from PyTorch's caching allocator: the current contents are copied
+ * there and the plan's own allocation is freed; later executes use the buffer.
+ *   dptr: device pointer on the plan's device, 256-byte aligned; bytes >= the value
+ *   hsvd_workspace_bytes reports.  The caller keeps ownership and must keep the buffer
+ *   alive and untouched until hsvd_destroy (or a later hsvd_set_workspace).
+ *   Synchronises the plan's last stream.  A captured graph is discarded (the next
+ *   execute captures again).  HSVD_ERR_INVALID for NULL, misaligned or short buffers
+ *   (the message gives the bytes needed) and for no side effects in that case.        */
+hsvd_status hsvd_set_workspace(hsvd_plan_t plan, void* dptr, size_t bytes);
 
 /* Launch kinds reported by hsvd_launch_times. */
 typedef enum {
@@ -197,7 +223,9 @@ typedef enum {
     HSVD_LAUNCH_FEATURES = 13,     /* block features of a feature plan                   */
     HSVD_LAUNCH_CHOLQR = 14,       /* Cholesky QR passes (fast path of the panel QRs)    */
     HSVD_LAUNCH_CHECK = 15,        /* the leaves' power-step convergence test            */
-    HSVD_LAUNCH_PANEL_QR = 16      /* leaf panels: repeated Cholesky QR, one group each  */
+    HSVD_LAUNCH_PANEL_QR = 16,     /* leaf panels: repeated Cholesky QR, one group each  */
+    HSVD_LAUNCH_GEMM_AX_F32 = 17,  /* Y = A_blk X on the float32 matrix cores (mixed)    */
+    HSVD_LAUNCH_GEMM_ATX_F32 = 18  /* Y = A_blk^T X on the float32 matrix cores (mixed)  */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.
@@ -309,6 +337,28 @@ hsvd_status hsvd_rank_model_predict(hsvd_rank_model_t model, const float* X, int
 hsvd_status hsvd_svd_static(int64_t m, int64_t n, int32_t p, int32_t q, int32_t k, double tol,
                             const hsvd_options* opt, const void* A, void* U, void* S, void* Vt,
                             int32_t* r_host, hipStream_t stream);
+
+/* Attaches the rank model (weights_host: the HSVD_RANK_MODEL_PARAMS float32 parameters
+ * in the layout above, bytes = 4 * HSVD_RANK_MODEL_PARAMS) to a single-matrix float64
+ * or float32-storage plan; weights_host == NULL detaches it.  Later executes of the plan
+ * take the learned path: the block features and the network's predictions are computed
+ * on the device, each block's sketch width is ceil(2^prediction) + 8 rounded up to a
+ * multiple of 8 (at most 80 and the block's sides), and a width plan (rebuilt only when
+ * the widths change: an unseen input pays its creation) runs the method.  The tolerance
+ * rule judges the result: a leaf whose sketch missed more than tol^2 of its block's
+ * energy doubles its width and the call runs again (at most 3 times); if a leaf still
+ * misses, the plan's own plain widths (k + oversample) compute the output.  Such
+ * executes synchronise the stream (two read-backs per run).  hsvd_get_rank,
+ * hsvd_get_status (bit HSVD_FLAG_RANK_FALLBACK: refits ran) and hsvd_get_leaf_info
+ * report the run that produced the output; hsvd_get_leaf_widths the widths.
+ * HSVD_ERR_INVALID for other plans or a wrong size; HSVD_ERR_UNSUPPORTED for mixed plans. */
+hsvd_status hsvd_set_rank_model(hsvd_plan_t plan, const void* weights_host, size_t bytes);
+
+/* After a learned execute: the p * q sketch widths of its last run (widths_host, count =
+ * p * q; may be NULL), the refits it ran and whether the plain widths produced the
+ * output (1) or the learned ones (0).  Host-side values, no synchronisation.          */
+hsvd_status hsvd_get_leaf_widths(hsvd_plan_t plan, int32_t* widths_host, int32_t count, int32_t* refits_host,
+                                 int32_t* plain_host);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hsvd_last_error(void);

@@ -35,9 +35,11 @@ hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double*
  * op 0: Y = A X with A rows x cols, X cols x N;  op 1: Y = A^T X with X rows x N.
  * kind 0: float64 arithmetic (A float64 when a_fp32 = 0, float32 otherwise);
  * kind 1: bfloat16 matrix cores (A float32, X rounded to float32 then bfloat16,
- * float32 sums; requires a_fp32 = 1).  A row-major with leading dimension lda;
- * X col-major (ld = its row count); Y col-major (ld = its row count: rows for
- * op 0, cols for op 1); 1 <= N <= 1024.  HSVD_ERR_INVALID on bad arguments. */
+ * float32 sums; requires a_fp32 = 1); kind 2: float32 matrix cores (A float32 as
+ * is, X rounded to float32, float32 sums; requires a_fp32 = 1).  A row-major with
+ * leading dimension lda; X col-major (ld = its row count); Y col-major (ld = its
+ * row count: rows for op 0, cols for op 1); 1 <= N <= 1024 (N <= 96 for kinds 1
+ * and 2).  HSVD_ERR_INVALID on bad arguments. */
 hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32, const void* A, int64_t rows,
                             int64_t cols, int64_t lda, const double* X, int32_t N, double* Y,
                             hipStream_t stream);

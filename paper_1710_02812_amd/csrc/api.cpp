@@ -68,6 +68,7 @@ struct Stage {
     int w = 0, ch = 0, c = 0, N = 0;
     int maxdim = 0, with_v = 0;
     int bf16 = 0;        // gemm on the bfloat16 matrix cores
+    int f32 = 0;         // gemm on the float32 matrix cores
     int64_t off = 0, off2 = 0;   // energy: output offset; features: sigma and energy offsets
     size_t tasks_off = 0, refs_off = 0, tsqr_off = 0;   // byte offsets in the task blob
     int guard = -1;      // int-arena slot: the stage is skipped while it holds non-zero
@@ -132,6 +133,23 @@ struct hsvd_plan_st {
     hipStream_t last_stream = nullptr;
     bool executed = false;
     bool external = false;         // device state not allocated by the plan (not freed)
+    bool ws_borrowed = false;      // arena and int arena in a caller buffer (hsvd_set_workspace)
+    // learned block rank (hsvd_set_rank_model): network parameters (device), the
+    // feature plan and its output, the predictions, the width plan of the last execute
+    // and its widths, the plan whose result the last execute returned (this plan when
+    // the plain widths stood in), and the refits that execute ran
+    float* rm_params = nullptr;
+    float* rm_feat = nullptr;
+    float* rm_pred = nullptr;
+    hsvd_plan_st* rm_features = nullptr;
+    hsvd_plan_st* rm_wplan = nullptr;
+    std::vector<int> rm_widths;
+    hsvd_plan_st* rm_ran = nullptr;
+    int rm_refits = 0, rm_plain = 0;
+    // the launch sequence captured on the first execute (opt.graph), replayed after
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 
     // final
     std::vector<OutputArgs> outs;  // per matrix
@@ -340,11 +358,14 @@ void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<App
     P.stages.push_back(s);
 }
 
-// A pass over A; bf16 selects the bfloat16 matrix-core kernel (128-row tiles).
-void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, bool bf16 = false) {
+// A pass over A on the float64 matrix cores (mma 0, 64 x 64 tiles), the bfloat16 ones
+// (mma 1) or the float32 ones (mma 2; both in strips of 256 rows holding every column).
+enum { MMA_F64 = 0, MMA_BF16 = 1, MMA_F32 = 2 };
+void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int mma = MMA_F64) {
     std::vector<TileRef> tiles;
-    const int nct = (N + 63) / 64;
-    const int th = bf16 ? kBf16TileRows : 64;
+    const bool strip = mma != MMA_F64;
+    const int nct = strip ? 1 : (N + 63) / 64;
+    const int th = strip ? kBf16TileRows : 64;
     for (size_t t = 0; t < tasks.size(); ++t) {
         const int out_rows = (op == 0) ? tasks[t].rows : tasks[t].cols;
         const int nrt = (out_rows + th - 1) / th;
@@ -353,7 +374,8 @@ void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, bool
     }
     Stage s{};
     s.kind = ST_GEMM;
-    s.bf16 = bf16 ? 1 : 0;
+    s.bf16 = mma == MMA_BF16 ? 1 : 0;
+    s.f32 = mma == MMA_F32 ? 1 : 0;
     s.op = op;
     s.n = (int)tiles.size();
     s.N = N;
@@ -684,7 +706,7 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
             t.y_off = pan[u].Y; t.y_ld = (int)l.rowsz;
             gt.push_back(t);
         }
-        push_gemm(P, 0, gt, w, bf16);
+        push_gemm(P, 0, gt, w, bf16 ? MMA_BF16 : MMA_F64);
     }
     const int ch = tsqr_chunk(w, std::max(w, W));
     if (P.leaf_cap > 0) {
@@ -734,7 +756,7 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
             }
             gt.push_back(x);
         }
-        push_gemm(P, prev_is_y ? 1 : 0, gt, w, bf16);
+        push_gemm(P, prev_is_y ? 1 : 0, gt, w, bf16 ? MMA_BF16 : MMA_F64);
     }
     const bool last_is_y = ((g - 1) % 2 == 0);
     std::vector<CoreTask> cores;
@@ -860,7 +882,7 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
         t.y_off = Zs[i]; t.y_ld = n;
         gt.push_back(t);
     }
-    push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16);
+    push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_BF16 : MMA_F64);
     for (size_t i = 0; i < roots.size(); ++i) {
         const int n = (int)P.mats[roots[i].mat].n;
         add_tsqr(P, tb, Zs[i], n, n, W, ch, true);
@@ -941,7 +963,8 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
         s.acc_off = -1;
         sums.push_back(s);
     }
-    push_gemm(P, 0, gt, W);
+    // mixed plans: float32-accurate products on the float32 matrix cores
+    push_gemm(P, 0, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_F32 : MMA_F64);
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
     for (size_t mi = 0; mi < vs.size(); ++mi) {
@@ -1028,7 +1051,7 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
         s.acc_off = -1;
         sums.push_back(s);
     }
-    push_gemm(P, 1, gt, W);
+    push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_F32 : MMA_F64);
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
     for (size_t mi = 0; mi < in.size(); ++mi) {
@@ -1280,12 +1303,15 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const int xr = s.op == 0 ? t.cols : t.rows, yr = s.op == 0 ? t.rows : t.cols;
                     if (!panel("gemm X", t.x_off, t.x_ld, xr, s.N)) return msg;
                     if (!panel("gemm Y", t.y_off, t.y_ld, yr, s.N)) return msg;
-                    const int th = s.bf16 ? kBf16TileRows : 64;
+                    const int th = (s.bf16 || s.f32) ? kBf16TileRows : 64;
                     if (t.tiles != (yr + th - 1) / th) return "gemm tile count";
                 }
+                const int nct = (s.bf16 || s.f32) ? 1 : (s.N + 63) / 64;
                 for (int i = 0; i < s.n; ++i)
-                    if (R[i].tile < 0 || R[i].tile >= T[R[i].task].tiles * ((s.N + 63) / 64)) return "gemm tile ref";
+                    if (R[i].tile < 0 || R[i].tile >= T[R[i].task].tiles * nct) return "gemm tile ref";
                 if (s.bf16 && P.opt.precision == HSVD_FP64) return "bf16 pass on a float64 plan";
+                if (s.bf16 && s.N > kBf16MaxN) return "bf16 pass wider than its tile";
+                if (s.f32 && (s.N > kBf16MaxN || P.opt.precision == HSVD_FP64)) return "float32 pass";
                 break;
             }
             case ST_CQ1:
@@ -1478,6 +1504,9 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             if (s.bf16)
                 e = launch_gemm_bf16(s.op, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
                                      (const TileRef*)(b + s.refs_off), s.n, s.N, st);
+            else if (s.f32)
+                e = launch_gemm_f32(s.op, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
+                                    (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             else
                 e = launch_gemm(s.op, fp32, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
                                 (const TileRef*)(b + s.refs_off), s.n, s.N, st, guard);
@@ -1548,13 +1577,106 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->max_sweeps = 40;
     opt->seed = 0;
     opt->refine_eps = 0.0;
+    opt->graph = 1;
+    opt->reserved = 0;
     return HSVD_OK;
+}
+
+// Bytes of the arena and the int arena as hsvd_set_workspace lays them out.
+static size_t workspace_need(const hsvd_plan_st& P) {
+    const size_t ws_bytes = sizeof(double) * (size_t)std::max<int64_t>(P.ws_elems, 32);
+    return (ws_bytes + 255) / 256 * 256 + sizeof(int) * (size_t)std::max(P.iws_elems, 1);
+}
+
+static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* const* U, void* const* S,
+                                void* const* Vt, hipStream_t stream);
+static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
+                             const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
+                             const hsvd_options* opt, size_t* check_only, const int32_t* leaf_width = nullptr,
+                             int kind = 0, bool host_only = false);
+
+// Sketch width of a leaf from the network's prediction y = log2(rank): ceil(2^y) plus a
+// margin of 8 columns, rounded up to a multiple of 8 (few width classes, one pipeline
+// each), between 8 and the largest width the leaf kernels take (and the block's sides).
+static int learned_width(float y, int64_t rows, int64_t cols) {
+    const int lmax = (int)std::min<int64_t>(kTsqrMaxW, std::min(rows, cols));
+    if (!std::isfinite(y) || y > 16.0f) return lmax;
+    const double k = std::ceil(std::exp2((double)y));
+    const int w = (int)(std::ceil((k + 8.0) / 8.0) * 8.0);
+    return std::max(1, std::min(std::max(w, 8), lmax));
+}
+
+// The learned path of an execute: features and prediction on the device, widths on the
+// host (one read-back), a width plan (rebuilt only when the widths change), then the
+// tolerance rule judges each leaf: a leaf whose sketch missed more than tol^2 of its
+// block's energy doubles its width and the call runs again (at most 3 times); if a leaf
+// still misses, the plain plan (widths k + oversample) computes the result instead.
+static hsvd_status learned_execute(hsvd_plan_st& P, const void* A, void* U, void* S, void* Vt,
+                                   hipStream_t stream) {
+    const MatDesc& M = P.mats[0];
+    const int nb = M.p * M.q;
+    void* f = P.rm_feat;
+    hsvd_status st = execute_impl(*P.rm_features, &A, &f, &f, &f, stream);
+    if (st != HSVD_OK) return st;
+    hipError_t e = launch_mlp_predict(P.rm_params, P.rm_feat, nb, P.rm_pred, stream);
+    std::vector<float> pred((size_t)nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(pred.data(), P.rm_pred, sizeof(float) * nb, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "rank prediction");
+    std::vector<int> widths((size_t)nb);
+    for (int i = 0; i < M.p; ++i)
+        for (int j = 0; j < M.q; ++j)
+            widths[(size_t)i * M.q + j] = learned_width(pred[(size_t)i * M.q + j], M.brow(i), M.bcol(j));
+    P.rm_refits = 0;
+    P.rm_plain = 0;
+    for (;;) {
+        if (!P.rm_wplan || widths != P.rm_widths) {
+            if (P.rm_wplan) hsvd_destroy(P.rm_wplan);
+            P.rm_wplan = nullptr;
+            int64_t m = M.m, n = M.n;
+            int32_t p = M.p, q = M.q, k = M.k;
+            st = plan_impl(&P.rm_wplan, 1, &m, &n, &p, &q, &k, P.tol, &P.opt, nullptr, widths.data(), 0, false);
+            if (st != HSVD_OK) return st;
+            P.rm_widths = widths;
+        }
+        st = execute_impl(*P.rm_wplan, &A, &U, &S, &Vt, stream);
+        if (st != HSVD_OK) return st;
+        P.rm_ran = P.rm_wplan;
+        std::vector<int32_t> fb((size_t)nb);
+        st = hsvd_get_leaf_info(P.rm_wplan, nullptr, fb.data(), nb);
+        if (st != HSVD_OK) return st;
+        bool missed = false, grow = false;
+        for (int b = 0; b < nb; ++b) {
+            if (!fb[b]) continue;
+            missed = true;
+            const int lim = learned_width(1e9f, M.brow(b / M.q), M.bcol(b % M.q));
+            if (widths[b] < lim) {
+                widths[b] = std::min(2 * widths[b], lim);
+                grow = true;
+            }
+        }
+        if (!missed) return HSVD_OK;
+        if (!grow || P.rm_refits == 3) break;
+        ++P.rm_refits;
+    }
+    P.rm_plain = 1;
+    P.rm_ran = &P;
+    return execute_impl(P, &A, &U, &S, &Vt, stream);
+}
+
+// Kernel attributes every plan may need, set before any launch could be captured.
+static hipError_t prepare_launches() {
+    hipError_t e = prepare_core_launches();
+    if (e == hipSuccess) e = prepare_panel_qr_launches();
+    if (e == hipSuccess) e = prepare_gemm_bf16_launches();
+    if (e == hipSuccess) e = prepare_gemm_f32_launches();
+    return e;
 }
 
 static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
                              const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
                              const hsvd_options* opt, size_t* check_only,
-                             const int32_t* leaf_width = nullptr, int kind = 0, bool host_only = false) {
+                             const int32_t* leaf_width, int kind, bool host_only) {
     if (!out && !check_only) return fail(HSVD_ERR_INVALID, "out is NULL");
     if (out) *out = nullptr;
     if (count < 1) return fail(HSVD_ERR_INVALID, "count must be >= 1");
@@ -1584,6 +1706,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         return fail(HSVD_ERR_INVALID, "negative option");
     if (o.power_steps > 64) return fail(HSVD_ERR_INVALID, "power_steps above 64");
     if (!(o.refine_eps >= 0.0)) return fail(HSVD_ERR_INVALID, "need refine_eps >= 0");
+    if ((o.graph != 0 && o.graph != 1) || o.reserved != 0) return fail(HSVD_ERR_INVALID, "graph must be 0 or 1, reserved 0");
 
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
@@ -1669,6 +1792,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
             e = hipMemcpy(P->ws + c.first, c.second.data(), c.second.size() * sizeof(double),
                           hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_gaussian(P->ws + P->omega_off, P->omega_count, o.seed, 0);
+    if (e == hipSuccess) e = prepare_launches();
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { hsvd_destroy(P); return hip_fail(e, "plan initialisation"); }
     *out = P;
@@ -1725,6 +1849,22 @@ hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t
     return hsvd_plan_ex(out, m, n, p, q, k, tol, nullptr);
 }
 
+// Every launch of one execute (a plan not stopped on refine_eps), in order, on `stream`.
+static hsvd_status enqueue_all(hsvd_plan_st& P, hipStream_t stream) {
+    hipError_t e = launch_reset_state(P.flags, P.iws, (const int*)((unsigned char*)P.dblob + P.reset_off),
+                                      (int)P.reset_slots.size(), stream);
+    if (e != hipSuccess) return hip_fail(e, "state reset");
+    for (size_t i = 0; i < P.stages.size(); ++i) {
+        hsvd_status st = run_stage(P, P.stages[i], stream);
+        if (st != HSVD_OK) return st;
+    }
+    e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws,
+                      (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)P.outs.size(), P.kmax, P.mmax,
+                      P.nmax, (void* const*)P.dptrs, stream);
+    if (e != hipSuccess) return hip_fail(e, "output launch");
+    return HSVD_OK;
+}
+
 static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* const* U, void* const* S,
                                 void* const* Vt, hipStream_t stream) {
     const size_t cnt = P.mats.size();
@@ -1747,10 +1887,37 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
         if (e != hipSuccess) return hip_fail(e, "pointer table");
         P.host_ptrs = tab;
     }
+    const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
+    if (P.opt.graph && P.seg_end.empty() && !prof) {
+        if (!P.gexec) {
+            // capture on a stream of the plan's own (the caller's may be the null
+            // stream, which cannot be captured); nothing runs during the capture
+            if (!P.cap_stream && (e = hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "capture stream");
+            if ((e = hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            hsvd_status st = enqueue_all(P, P.cap_stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(P.cap_stream, &g);
+            if (st != HSVD_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            P.graph = g;
+            if ((e = hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0)) != hipSuccess) {
+                P.gexec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+        if ((e = hipGraphLaunch(P.gexec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        P.last_stream = stream;
+        P.executed = true;
+        return HSVD_OK;
+    }
     e = launch_reset_state(P.flags, P.iws, (const int*)((unsigned char*)P.dblob + P.reset_off),
                            (int)P.reset_slots.size(), stream);
     if (e != hipSuccess) return hip_fail(e, "state reset");
-    const bool prof = P.profiling && P.events.size() == P.stages.size() + 2;
     if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
     size_t outs_off = P.outs_off;
     if (P.seg_end.empty()) {
@@ -1798,6 +1965,7 @@ hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
     if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan: use hsvd_features_execute");
     if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_execute_batched");
+    if (plan->rm_params) return learned_execute(*plan, A, U, S, Vt, stream);
     return execute_impl(*plan, &A, &U, &S, &Vt, stream);
 }
 
@@ -1848,6 +2016,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
             switch (s.kind) {
                 case ST_GEMM:
                     kind = s.bf16 ? (s.op == 0 ? HSVD_LAUNCH_GEMM_AX_BF16 : HSVD_LAUNCH_GEMM_ATX_BF16)
+                         : s.f32  ? (s.op == 0 ? HSVD_LAUNCH_GEMM_AX_F32 : HSVD_LAUNCH_GEMM_ATX_F32)
                                   : (s.op == 0 ? HSVD_LAUNCH_GEMM_AX : HSVD_LAUNCH_GEMM_ATX);
                     break;
                 case ST_TSQR_F: kind = HSVD_LAUNCH_TSQR_FACTOR; break;
@@ -2021,12 +2190,20 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (!plan) return HSVD_OK;
     if (plan->executed) hipStreamSynchronize(plan->last_stream);
     for (auto& ev : plan->events) hipEventDestroy(ev);
+    if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
+    if (plan->rm_wplan) hsvd_destroy(plan->rm_wplan);
+    if (plan->rm_features) hsvd_destroy(plan->rm_features);
+    if (plan->rm_params) hipFree(plan->rm_params);
+    if (plan->rm_feat) hipFree(plan->rm_feat);
+    if (plan->rm_pred) hipFree(plan->rm_pred);
     if (plan->external) {             // device state in memory the plan does not own
         delete plan;
         return HSVD_OK;
     }
-    if (plan->ws) hipFree(plan->ws);
-    if (plan->iws) hipFree(plan->iws);
+    if (plan->ws && !plan->ws_borrowed) hipFree(plan->ws);
+    if (plan->iws && !plan->ws_borrowed) hipFree(plan->iws);
     if (plan->flags) hipFree(plan->flags);
     if (plan->dblob) hipFree(plan->dblob);
     if (plan->dptrs) hipFree(plan->dptrs);
@@ -2049,6 +2226,7 @@ hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count) {
 
 hsvd_status hsvd_get_leaf_info(hsvd_plan_t plan, int32_t* ranks, int32_t* fallback, int32_t count) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->rm_ran && plan->rm_ran != plan) return hsvd_get_leaf_info(plan->rm_ran, ranks, fallback, count);
     if (plan->kind != 0 || count != (int32_t)plan->leaf_rank_slots.size())
         return fail(HSVD_ERR_INVALID, "count must be p * q of the plan's (first) matrix");
     hipError_t e = hipSuccess;
@@ -2073,12 +2251,18 @@ hsvd_status hsvd_get_refine_iterations(hsvd_plan_t plan, int32_t* iters_host) {
 
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host) {
     if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    if (plan->rm_ran && plan->rm_ran != plan) return hsvd_get_rank(plan->rm_ran, r_host);
     if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_get_ranks");
     return hsvd_get_ranks(plan, r_host, 1);
 }
 
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
     if (!plan || !flags_host) return fail(HSVD_ERR_INVALID, "NULL argument");
+    if (plan->rm_ran && plan->rm_ran != plan) {
+        hsvd_status st = hsvd_get_status(plan->rm_ran, flags_host);
+        if (st == HSVD_OK && plan->rm_refits > 0) *flags_host |= HSVD_FLAG_RANK_FALLBACK;
+        return st;
+    }
     hipError_t e = hipSuccess;
     if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
     unsigned fl[2] = {0, 0};
@@ -2090,8 +2274,100 @@ hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
 
 hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host) {
     if (!plan || !bytes_host) return fail(HSVD_ERR_INVALID, "NULL argument");
-    *bytes_host = sizeof(double) * (size_t)plan->ws_elems + sizeof(int) * (size_t)plan->iws_elems +
-                  plan->blob.size();
+    *bytes_host = workspace_need(*plan);
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_set_rank_model(hsvd_plan_t plan, const void* weights_host, size_t bytes) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (plan->kind != 0 || plan->mats.size() != 1 || plan->external || !plan->leaf_width.empty())
+        return fail(HSVD_ERR_INVALID, "rank models attach to single-matrix plans from hsvd_plan / hsvd_plan_ex");
+    if (plan->opt.precision != HSVD_FP64 && plan->opt.precision != HSVD_FP32)
+        return fail(HSVD_ERR_UNSUPPORTED, "rank models need a float64 or float32-storage plan");
+    if (weights_host && bytes != sizeof(float) * (size_t)kMlpParams)
+        return fail(HSVD_ERR_INVALID, "weights must be HSVD_RANK_MODEL_PARAMS floats");
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_set_rank_model");
+    if (!weights_host) {                              // detach
+        if (plan->rm_wplan) hsvd_destroy(plan->rm_wplan);
+        if (plan->rm_features) hsvd_destroy(plan->rm_features);
+        if (plan->rm_params) hipFree(plan->rm_params);
+        if (plan->rm_feat) hipFree(plan->rm_feat);
+        if (plan->rm_pred) hipFree(plan->rm_pred);
+        plan->rm_wplan = plan->rm_features = plan->rm_ran = nullptr;
+        plan->rm_params = plan->rm_feat = plan->rm_pred = nullptr;
+        plan->rm_widths.clear();
+        return HSVD_OK;
+    }
+    const MatDesc& M = plan->mats[0];
+    const int nb = M.p * M.q;
+    if (!plan->rm_params) {
+        e = hipMalloc(&plan->rm_params, sizeof(float) * kMlpParams);
+        if (e == hipSuccess) e = hipMalloc(&plan->rm_feat, sizeof(float) * 16 * (size_t)nb);
+        if (e == hipSuccess) e = hipMalloc(&plan->rm_pred, sizeof(float) * (size_t)nb);
+        if (e != hipSuccess) return fail(HSVD_ERR_ALLOC, "rank model allocation failed");
+        hsvd_options fo;
+        hsvd_default_options(&fo);
+        fo.precision = plan->opt.precision;
+        fo.seed = plan->opt.seed;
+        fo.graph = plan->opt.graph;
+        int64_t m = M.m, n = M.n;
+        int32_t p = M.p, q = M.q, one = 1;
+        hsvd_status st = plan_impl(&plan->rm_features, 1, &m, &n, &p, &q, &one, 0.0, &fo, nullptr, nullptr, 1, false);
+        if (st != HSVD_OK) return st;
+    }
+    e = hipMemcpy(plan->rm_params, weights_host, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hsvd_set_rank_model");
+    plan->rm_ran = nullptr;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_leaf_widths(hsvd_plan_t plan, int32_t* widths_host, int32_t count, int32_t* refits_host,
+                                 int32_t* plain_host) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (!plan->rm_params) return fail(HSVD_ERR_INVALID, "no rank model attached");
+    if (widths_host && count != (int32_t)plan->rm_widths.size())
+        return fail(HSVD_ERR_INVALID, "count must be p * q (after a learned execute)");
+    if (widths_host)
+        for (int32_t b = 0; b < count; ++b) widths_host[b] = plan->rm_widths[(size_t)b];
+    if (refits_host) *refits_host = plan->rm_refits;
+    if (plain_host) *plain_host = plan->rm_plain;
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_set_workspace(hsvd_plan_t plan, void* dptr, size_t bytes) {
+    if (!plan || !dptr) return fail(HSVD_ERR_INVALID, "NULL argument");
+    if (plan->external) return fail(HSVD_ERR_INVALID, "not a plan from hsvd_plan*");
+    if ((uintptr_t)dptr % 256) return fail(HSVD_ERR_INVALID, "workspace must be 256-byte aligned");
+    const size_t need = workspace_need(*plan);
+    if (bytes < need)
+        return fail(HSVD_ERR_INVALID, "workspace of " + std::to_string(bytes) + " bytes; the plan needs " +
+                                          std::to_string(need));
+    hipError_t e = hipSuccess;
+    if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
+    const size_t ws_bytes = sizeof(double) * (size_t)std::max<int64_t>(plan->ws_elems, 32);
+    const size_t iw_off = (ws_bytes + 255) / 256 * 256;
+    unsigned char* b = (unsigned char*)dptr;
+    if (e == hipSuccess && (unsigned char*)plan->ws != b)
+        e = hipMemcpy(b, plan->ws, ws_bytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess && (unsigned char*)plan->iws != b + iw_off)
+        e = hipMemcpy(b + iw_off, plan->iws, sizeof(int) * (size_t)std::max(plan->iws_elems, 1),
+                      hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();       // copies done before the old memory goes
+    if (e != hipSuccess) return hip_fail(e, "hsvd_set_workspace");
+    if (!plan->ws_borrowed) {
+        hipFree(plan->ws);
+        hipFree(plan->iws);
+    }
+    plan->ws = (double*)b;
+    plan->iws = (int*)(b + iw_off);
+    plan->ws_borrowed = true;
+    // a captured graph holds the old addresses: the next execute captures again
+    if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    plan->gexec = nullptr;
+    plan->graph = nullptr;
     return HSVD_OK;
 }
 
@@ -2154,6 +2430,7 @@ hsvd_status hsvd_svd_static(int64_t m, int64_t n, int32_t p, int32_t q, int32_t 
     void* base = nullptr;
     st = static_scratch_address(&base);
     if (st != HSVD_OK) return st;
+    if (hipError_t pe = prepare_launches(); pe != hipSuccess) return hip_fail(pe, "kernel attributes");
     unsigned char* b = (unsigned char*)base;
     P->ws = (double*)b;
     P->iws = (int*)(b + off_iws);

@@ -104,16 +104,18 @@ extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32,
                                        int64_t rows, int64_t cols, int64_t lda, const double* X,
                                        int32_t N, double* Y, hipStream_t stream) {
     using hsvd_detail::set_error;
-    if (!A || !X || !Y || (op != 0 && op != 1) || (kind != 0 && kind != 1) || rows < 1 || cols < 1 ||
-        lda < cols || N < 1 || N > 1024 || (kind == 1 && !a_fp32) || rows > (1 << 20) || cols > (1 << 20))
+    if (!A || !X || !Y || (op != 0 && op != 1) || kind < 0 || kind > 2 || rows < 1 || cols < 1 ||
+        lda < cols || N < 1 || N > 1024 || (kind != 0 && !a_fp32) || rows > (1 << 20) || cols > (1 << 20))
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_gemm: bad argument");
     const int64_t xr = op == 0 ? cols : rows, yr = op == 0 ? rows : cols;
     Scratch sc;
     double* ws = sc.get<double>(xr * N + yr * N);
     GemmTask* dt = sc.get<GemmTask>(1);
     void** dptrs = sc.get<void*>(4);
-    const int tile_rows = kind == 1 ? kBf16TileRows : 64;
-    const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = (N + 63) / 64;
+    const int tile_rows = kind != 0 ? kBf16TileRows : 64;
+    if (kind != 0 && N > kBf16MaxN)
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_gemm: bfloat16 and float32 passes take N <= 96");
+    const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = kind != 0 ? 1 : (N + 63) / 64;
     TileRef* dtiles = sc.get<TileRef>((size_t)nrt * nct);
     if (!ws || !dt || !dtiles || !dptrs) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
     GemmTask t{};
@@ -136,8 +138,9 @@ extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32,
     if (e == hipSuccess)
         e = hipMemcpyAsync(dtiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = kind == 1 ? launch_gemm_bf16(op, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream)
-                      : launch_gemm(op, a_fp32, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream);
+        e = kind == 1   ? launch_gemm_bf16(op, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream)
+            : kind == 2 ? launch_gemm_f32(op, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream)
+                        : launch_gemm(op, a_fp32, (const void* const*)dptrs, ws, dt, dtiles, nrt * nct, N, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(Y, ws + xr * N, sizeof(double) * yr * N, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_gemm: ") + hipGetErrorString(e));

@@ -175,13 +175,35 @@ constexpr int kMlpBatch = 64;
 constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
 
 // ---------------------------------------------------------------- launches
+// Raises a kernel's dynamic-LDS limit once per device (bit dev of *done); plans call
+// prepare_launches() at creation so that no attribute is set during a graph capture.
+inline hipError_t set_lds_limit_once(const void* fn, int bytes, unsigned long long* done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned long long bit = 1ull << (dev & 63);
+    if (__atomic_load_n(done, __ATOMIC_ACQUIRE) & bit) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) __atomic_fetch_or(done, bit, __ATOMIC_RELEASE);
+    return e;
+}
+hipError_t prepare_core_launches();
+hipError_t prepare_panel_qr_launches();
+hipError_t prepare_gemm_bf16_launches();
+hipError_t prepare_gemm_f32_launches();
+
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // `guard` (device int or nullptr): when it points at a non-zero value every work-group
 // of the launch returns at once (stages of an iteration that has already stopped).
-// bfloat16 matrix-core passes: 128 x 64 output tiles (TileRef.tile = row tile * ceil(N / 64) + col tile)
-constexpr int kBf16TileRows = 128;
+// bfloat16 matrix-core passes: strips of 256 output rows holding all N <= 96 output
+// columns (TileRef.tile = strip index), so that each element of A is read once
+constexpr int kBf16TileRows = 256;
+constexpr int kBf16MaxN = 96;
 hipError_t launch_gemm_bf16(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
                             const TileRef* tiles, int ntiles, int N, hipStream_t s);
+// float32 matrix-core passes (mixed plans' float32-accurate products): same strips
+hipError_t launch_gemm_f32(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
+                           const TileRef* tiles, int ntiles, int N, hipStream_t s);
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s, const int* guard = nullptr);

@@ -560,16 +560,35 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
 }
 
 template <int ROWS>
+size_t core_lds(int maxdim, int with_v) {
+    return sizeof(double) * ((size_t)maxdim * (ROWS + 1) * (with_v ? 2 : 1) + 2 * (size_t)maxdim + 1) +
+           sizeof(int) * maxdim + 64;
+}
+
+template <int ROWS>
+hipError_t prepare_core_rows() {
+    static unsigned long long done = 0;
+    return set_lds_limit_once((const void*)k_core<ROWS>, (int)core_lds<ROWS>(ROWS, ROWS <= 64), &done);
+}
+
+template <int ROWS>
 hipError_t launch_core_rows(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                             int max_sweeps, unsigned* flags, int with_v, hipStream_t s, const int* guard) {
-    const size_t lds = sizeof(double) * ((size_t)maxdim * (ROWS + 1) * (with_v ? 2 : 1) +
-                                         2 * (size_t)maxdim + 1) + sizeof(int) * maxdim + 64;
-    hipError_t e = hipFuncSetAttribute((const void*)k_core<ROWS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const size_t lds = core_lds<ROWS>(maxdim, with_v);
+    hipError_t e = prepare_core_rows<ROWS>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_core<ROWS>, dim3(ntasks), dim3(CORE_THREADS), lds, s, ws, iws, tasks, maxdim,
                        max_sweeps, flags, with_v, guard);
     return hipGetLastError();
+}
+
+hipError_t prepare_core_launches() {
+    hipError_t e = prepare_core_rows<32>();
+    if (e == hipSuccess) e = prepare_core_rows<64>();
+    if (e == hipSuccess) e = prepare_core_rows<96>();
+    if (e == hipSuccess) e = prepare_core_rows<112>();
+    if (e == hipSuccess) e = prepare_core_rows<128>();
+    return e;
 }
 
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,

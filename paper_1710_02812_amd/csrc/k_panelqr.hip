@@ -345,12 +345,16 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws
     if (tid == 0) iws[t.cq_flag] = failed_all ? 1 : 0;
 }
 
+hipError_t prepare_panel_qr_launches() {
+    static unsigned long long done = 0;
+    return set_lds_limit_once((const void*)k_panel_qr, (int)PQ_LDS_BYTES, &done);
+}
+
 hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntasks, int w, int need_r,
                            hipStream_t s, const int* guard) {
     if (ntasks <= 0) return hipSuccess;
     if (w < 1 || w > kPanelQrMaxW) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)k_panel_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)PQ_LDS_BYTES);
+    hipError_t e = prepare_panel_qr_launches();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_panel_qr, dim3(ntasks), dim3(PQ_THREADS), PQ_LDS_BYTES, s, ws, iws, tasks, w, need_r,
                        guard);

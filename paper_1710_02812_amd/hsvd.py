@@ -33,12 +33,13 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_rank_model_get_params", "hsvd_rank_model_train", "hsvd_rank_model_grad",
             "hsvd_rank_model_predict",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
-            "hsvd_debug_plan_check", "hsvd_svd_static",
+            "hsvd_debug_plan_check", "hsvd_svd_static", "hsvd_set_workspace", "hsvd_set_rank_model",
+            "hsvd_get_leaf_widths",
             "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features", "cholqr",
-                "check", "panel_qr"]
+                "check", "panel_qr", "gemm_ax_f32", "gemm_atx_f32"]
 
 
 class HsvdError(RuntimeError):
@@ -51,7 +52,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("power_steps", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,6 +78,9 @@ def lib() -> ctypes.CDLL:
     L.hsvd_get_refine_iterations.argtypes = [vp, P(i32)]
     L.hsvd_get_status.argtypes = [vp, P(ctypes.c_uint32)]
     L.hsvd_workspace_bytes.argtypes = [vp, P(ctypes.c_size_t)]
+    L.hsvd_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+    L.hsvd_set_rank_model.argtypes = [vp, vp, ctypes.c_size_t]
+    L.hsvd_get_leaf_widths.argtypes = [vp, P(i32), i32, P(i32), P(i32)]
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
     L.hsvd_launch_times.argtypes = [vp, P(i32), P(ctypes.c_float), i32, P(i32)]
@@ -153,9 +158,11 @@ class Plan:
                  precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
                  power_steps: int | None = None, refine_steps: int = 0,
                  max_sweeps: int | None = None, seed: int = 0, leaf_widths=None,
-                 refine_eps: float = 0.0):
-        """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths)."""
+                 refine_eps: float = 0.0, graph: bool = True):
+        """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths);
+        graph: replay a hipGraph captured on the first execute."""
         o = default_options()
+        o.graph = 1 if graph else 0
         o.precision = precision
         o.rule = rule
         if oversample is not None:
@@ -242,6 +249,31 @@ class Plan:
         b = ctypes.c_size_t()
         _check(lib().hsvd_workspace_bytes(self._h, ctypes.byref(b)))
         return b.value
+
+    def set_rank_model(self, model):
+        """Attaches a RankModel's current parameters (None detaches): later executes
+        take the learned path (hsvd_set_rank_model)."""
+        if model is None:
+            _check(lib().hsvd_set_rank_model(self._h, None, 0))
+            return
+        theta = model.params() if isinstance(model, RankModel) else np.asarray(model, dtype=np.float32)
+        buf = (ctypes.c_float * theta.size)(*theta.ravel().tolist())
+        _check(lib().hsvd_set_rank_model(self._h, buf, 4 * theta.size))
+
+    def leaf_widths(self):
+        """(p x q widths, refits, plain) of the last learned execute (hsvd_get_leaf_widths)."""
+        c = self.p * self.q
+        w = (ctypes.c_int32 * c)()
+        rf, pl = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hsvd_get_leaf_widths(self._h, w, c, ctypes.byref(rf), ctypes.byref(pl)))
+        return np.array(list(w), dtype=np.int32).reshape(self.p, self.q), rf.value, pl.value
+
+    def set_workspace(self, buf):
+        """Moves the plan's workspace into `buf`, a device tensor (any dtype) of at least
+        workspace_bytes() bytes whose storage is 256-byte aligned; keep it alive until
+        close()."""
+        self._ws_buf = buf
+        _check(lib().hsvd_set_workspace(self._h, buf.data_ptr(), buf.numel() * buf.element_size()))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -336,47 +368,30 @@ class RankModel:
             pass
 
 
-def widths_from_prediction(pred_log2, margin: int = 8, lmax: int = 80, quantum: int = 8):
-    """Sketch width per block: ceil(2^prediction) + margin, rounded up to a multiple
-    of `quantum` (fewer width classes), clipped to [quantum, lmax]."""
-    k = np.ceil(np.exp2(np.asarray(pred_log2, dtype=np.float64)))
-    w = np.ceil((k + margin) / quantum) * quantum
-    return np.clip(w, quantum, lmax).astype(np.int32)
-
-
-def learned_svd(A, p: int, q: int, k: int, tol: float, model: "RankModel", margin: int = 8,
-                lmax: int = 80, max_refits: int = 3, **opts):
-    """Hierarchical SVD whose leaves take the sketch widths the network predicts.
-    Blocks whose leaf reports missed energy beyond tol^2 get twice the width and
-    the call runs again (at most max_refits times).  Returns (U, S, Vt, r, info)."""
+def learned_svd(A, p: int, q: int, k: int, tol: float, model: "RankModel", **opts):
+    """Hierarchical SVD with the learned sketch widths (a plan with the model attached:
+    features, prediction, widths, refits and the plain-width fallback all run in the
+    library).  Returns (U, S, Vt, r, info) with info = widths, refits, plain, leaf ranks
+    and fallback flags of the run that produced the output."""
     import torch
     A = A.contiguous()
     m, n = A.shape
-    F = block_features(A, p, q)
-    pred = model.predict(F).cpu().numpy()
-    widths = widths_from_prediction(pred, margin, lmax).reshape(p, q)
     prec = FP64 if A.dtype == torch.float64 else FP32
     opts.setdefault("rule", RULE_FROB)
-    refits = 0
-    while True:
-        plan = Plan(m, n, p, q, k, tol, precision=prec, leaf_widths=widths, **opts)
-        U = torch.empty((m, k), dtype=A.dtype, device=A.device)
-        S = torch.empty((k,), dtype=A.dtype, device=A.device)
-        Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
-        plan.execute(A, U, S, Vt)
-        ranks, fb = plan.leaf_info()
-        r = plan.rank()
-        flags = plan.status() & 0xFFFF
-        plan.close()
-        if flags & ~FLAG_RANK_FALLBACK:
-            raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
-        grow = (fb != 0) & (widths < lmax)
-        if not grow.any() or refits >= max_refits:
-            break
-        widths = np.where(grow, np.minimum(2 * widths, lmax), widths).astype(np.int32)
-        refits += 1
-    info = {"widths": widths, "leaf_ranks": ranks, "fallback": fb, "refits": refits,
-            "predicted_log2": pred.reshape(p, q)}
+    plan = Plan(m, n, p, q, k, tol, precision=prec, **opts)
+    plan.set_rank_model(model)
+    U = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    S = torch.empty((k,), dtype=A.dtype, device=A.device)
+    Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
+    plan.execute(A, U, S, Vt)
+    r = plan.rank()
+    widths, refits, plain = plan.leaf_widths()
+    ranks, fb = plan.leaf_info()
+    flags = plan.status() & 0xFFFF
+    plan.close()
+    if flags & ~FLAG_RANK_FALLBACK:
+        raise HsvdError(5 if flags & FLAG_NOCONV else 4, f"device status flags {flags:#x}")
+    info = {"widths": widths, "refits": refits, "plain": plain, "leaf_ranks": ranks, "fallback": fb}
     return U, S, Vt, r, info
 
 
@@ -563,9 +578,10 @@ def plan_check(m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, **opts)
     return b.value
 
 
-def debug_gemm(A, X, op: int = 0, bf16: bool = False):
+def debug_gemm(A, X, op: int = 0, bf16: bool = False, f32: bool = False):
     """One pass product on a single block: op 0 -> A @ X, op 1 -> A.T @ X (float64 result).
-    A: (rows, cols) float32/float64 device tensor (row-major); X: float64 (K, N)."""
+    A: (rows, cols) float32/float64 device tensor (row-major); X: float64 (K, N).
+    bf16 / f32: the bfloat16 / float32 matrix-core kernels (A float32)."""
     import torch
     rows, cols = A.shape
     K, N = X.shape
@@ -574,7 +590,7 @@ def debug_gemm(A, X, op: int = 0, bf16: bool = False):
     Xc = X.t().contiguous()                  # col-major storage
     yr = rows if op == 0 else cols
     Y = torch.empty((N, yr), dtype=torch.float64, device=A.device)
-    _check(lib().hsvd_debug_gemm(op, int(bf16), int(Ac.dtype == torch.float32), Ac.data_ptr(),
+    _check(lib().hsvd_debug_gemm(op, 1 if bf16 else 2 if f32 else 0, int(Ac.dtype == torch.float32), Ac.data_ptr(),
                                  rows, cols, cols, Xc.data_ptr(), N, Y.data_ptr(), _stream_handle()))
     return Y.t()
 

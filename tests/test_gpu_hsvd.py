@@ -381,3 +381,62 @@ def test_batched_plan_reuse_with_new_pointers():
     for s1, s2 in zip(res[0], res[1]):
         assert np.allclose(2.0 * s1, s2, rtol=1e-12, atol=0)
     plan.close()
+
+
+@pytest.mark.parametrize("prec,m,p,k", [(H.FP64, 512, 2, 20), (H.MIXED_BF16, 2048, 2, 32), (H.FP32, 1500, 3, 24)])
+def test_graph_replays_match_direct_launches(prec, m, p, k):
+    """A plan that captured its launches into a hipGraph on the first execute replays
+    it on every later execute: across alternating inputs (the pointer table changes),
+    with eager device work and synchronisations between the replays, every replay is
+    bit-identical to a plan of the same options that launches its kernels one by one."""
+    rng = np.random.default_rng(m + k)
+    dt = torch.float64 if prec == H.FP64 else torch.float32
+    As = []
+    for _ in range(2):
+        A, *_ = synth.low_rank(rng, m, m, 10.0 ** (-np.arange(k) / (k / 4.0)), noise=1e-9)
+        As.append(torch.tensor(A, dtype=dt, device=DEV))
+    pg = H.Plan(m, m, p, p, k, 0.0, precision=prec, graph=True)
+    pe = H.Plan(m, m, p, p, k, 0.0, precision=prec, graph=False)
+    outs = lambda: (torch.empty((m, k), dtype=dt, device=DEV), torch.empty((k,), dtype=dt, device=DEV),
+                    torch.empty((k, m), dtype=dt, device=DEV))
+    Ug, Sg, Vg = outs()
+    Ue, Se, Ve = outs()
+    for it in range(4):
+        A = As[it % 2]
+        print(f"graph replay {it} prec={prec}", flush=True)
+        pg.execute(A, Ug, Sg, Vg)
+        junk = A.double() @ A.double().T          # eager work between replays
+        torch.cuda.synchronize()
+        pe.execute(A, Ue, Se, Ve)
+        torch.cuda.synchronize()
+        assert float(junk[0, 0]) == float(junk[0, 0])
+        assert torch.equal(Ug, Ue) and torch.equal(Sg, Se) and torch.equal(Vg, Ve), it
+        assert pg.rank() == pe.rank() == k
+    pg.close()
+    pe.close()
+
+
+def test_set_workspace_from_torch_memory():
+    """hsvd_set_workspace moves a plan's arena into a torch-allocated buffer: executes
+    before and after the move (and after a second move) give bit-identical results; a
+    buffer below hsvd_workspace_bytes is refused and leaves the plan working."""
+    w = synth.config0(3)
+    A = torch.tensor(w.A, dtype=torch.float64, device=DEV)
+    m, n = A.shape
+    plan = H.Plan(m, n, w.p, w.q, w.k, w.tol)
+    outs = lambda: (torch.empty((m, w.k), dtype=torch.float64, device=DEV),
+                    torch.empty((w.k,), dtype=torch.float64, device=DEV),
+                    torch.empty((w.k, n), dtype=torch.float64, device=DEV))
+    U0, S0, V0 = outs()
+    plan.execute(A, U0, S0, V0)
+    need = plan.workspace_bytes()
+    with pytest.raises(H.HsvdError, match="needs"):
+        plan.set_workspace(torch.empty(need - 256, dtype=torch.uint8, device=DEV))
+    for rep in range(2):
+        buf = torch.empty(need + 1024, dtype=torch.uint8, device=DEV)
+        plan.set_workspace(buf)
+        U1, S1, V1 = outs()
+        plan.execute(A, U1, S1, V1)
+        torch.cuda.synchronize()
+        assert torch.equal(U0, U1) and torch.equal(S0, S1) and torch.equal(V0, V1), rep
+    plan.close()

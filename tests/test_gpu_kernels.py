@@ -298,7 +298,9 @@ def _bf16(x):
 
 
 @pytest.mark.parametrize("rows,cols,op,N", [(300, 200, 0, 50), (1024, 1024, 0, 64), (1000, 130, 1, 17),
-                                            (129, 257, 1, 64), (1024, 1024, 1, 50), (77, 33, 0, 100)])
+                                            (129, 257, 1, 64), (1024, 1024, 1, 50), (77, 33, 0, 96),
+                                            (1024, 1024, 0, 78), (1024, 1024, 1, 78), (1031, 517, 0, 80),
+                                            (517, 1031, 1, 80), (2048, 301, 1, 7)])
 def test_gemm_bf16_matrix_cores(rows, cols, op, N):
     """bfloat16 MFMA pass: equals the float64 product of the bfloat16-rounded operands
     up to float32 summation error (this also fixes the MFMA lane layout)."""
@@ -313,6 +315,14 @@ def test_gemm_bf16_matrix_cores(rows, cols, op, N):
     ref = (Ab @ Xb) if op == 0 else (Ab.T @ Xb)
     bound = (np.abs(Ab) @ np.abs(Xb)) if op == 0 else (np.abs(Ab).T @ np.abs(Xb))
     assert np.all(np.abs(Y - ref) <= 2.0 * K * 2.0 ** -24 * bound + 1e-30)
+    # the float32 matrix-core kernel: the float64 product of A and the float32-rounded X
+    # up to float32 summation error
+    Y32 = H.debug_gemm(At, _t(X), op=op, f32=True).cpu().numpy()
+    A64 = A.astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    ref32 = (A64 @ X32) if op == 0 else (A64.T @ X32)
+    bound32 = (np.abs(A64) @ np.abs(X32)) if op == 0 else (np.abs(A64).T @ np.abs(X32))
+    assert np.all(np.abs(Y32 - ref32) <= 2.0 * K * 2.0 ** -24 * bound32 + 1e-30)
     # and the float64-arithmetic kernel on the same float32 A is exact to float64 rounding
     Y64 = H.debug_gemm(At, _t(X), op=op, bf16=False).cpu().numpy()
     A64 = A.astype(np.float64)

@@ -165,4 +165,26 @@ def test_learned_rank_gain():
     assert learned_cols <= 0.75 * plain_cols
     # every block got at least the width its true leaf rank needs
     assert np.all(info["widths"] >= ranks_plain)
+    assert info["plain"] == 0
+    model.close()
+
+
+def test_learned_path_recovers_from_a_bad_prediction():
+    """A network that predicts rank 1 for every block (output weights zero, bias -5:
+    sketch width 16) under-sketches the rank-32 blocks: their leaves report the energy
+    their sketch missed, the library doubles their widths and runs again, and the
+    result still meets the 1e-3 bound against the oracle with the oracle's rank."""
+    w = _field(7)
+    model = H.RankModel(seed=2)
+    theta = model.params()
+    theta[5248:5312] = 0.0
+    theta[5312] = -5.0
+    model.set_params(theta)
+    A = torch.tensor(w.A, device=DEV)
+    U, S, Vt, r, info = H.learned_svd(A, w.p, w.q, w.k, w.tol, model)
+    Uo, so, Vto, ro = oracle.hsvd(w.A, w.p, w.q, w.k, w.tol, "frob")
+    c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), r, Uo, so, Vto, ro)
+    print("bad prediction", c, "refits", info["refits"], "plain", info["plain"], flush=True)
+    assert info["refits"] >= 1 or info["plain"] == 1
+    assert r == ro and c["e_frob"] <= 1e-3
     model.close()
