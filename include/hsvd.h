@@ -103,8 +103,21 @@ typedef struct {
                                stream; 0: every execute launches its kernels one by one.
                                Plans stopped on refine_eps and executes with per-launch
                                timing on always launch one by one.                      */
-    int32_t  reserved;      /* must be 0                                                */
+    int32_t  order;         /* order of the two sets of merges (Section 3): HSVD_ORDER_ROWS_LAST
+                               runs Algorithm 1 as printed (column merges inside each row
+                               slab, then the row-slab tree: right vectors from the trees,
+                               left ones by projection); HSVD_ORDER_COLS_LAST the opposite
+                               order (row merges inside each column slab, then the
+                               column-slab tree: left vectors from the trees, right ones by
+                               projection); HSVD_ORDER_AUTO (default) picks COLS_LAST for a
+                               single matrix with m < n, so that the last tree and the
+                               projection run on the shorter side, else ROWS_LAST.  Width
+                               and feature plans are always ROWS_LAST.                  */
 } hsvd_options;
+
+#define HSVD_ORDER_AUTO 0
+#define HSVD_ORDER_ROWS_LAST 1
+#define HSVD_ORDER_COLS_LAST 2
 
 /* Status flags read by hsvd_get_status (bit set = condition seen in the last execute). */
 #define HSVD_FLAG_NONFINITE 0x1u   /* a core matrix held NaN or Inf                        */
@@ -164,6 +177,19 @@ hsvd_status hsvd_plan_batched(hsvd_plan_t* out, int32_t count, const int64_t* m,
  * the call first waits for the previous execute and uploads the new pointers.   */
 hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* const* U,
                                  void* const* S, void* const* Vt, hipStream_t stream);
+
+/* Plan for the SVD of X (m x n) through its Gram matrix (Section 4 results: the method
+ * applied to X^T X): each execute forms G = X^T X (n x n, float64 matrix cores, float64
+ * sums, held in the plan's workspace), runs the method on G with a p x q grid of G
+ * (1 <= p, q <= n; tol and the rule apply to G's singular values, which are X's
+ * squared), takes V-hat from G's row-slab tree (G's right singular vectors are X's) and
+ * projects X itself onto it (Section 3: SVD(X V-hat)), so that U, S and Vt are X's:
+ * U (m x k), S (k), Vt (k x n), as hsvd_execute.  refine_steps run Algorithm 2 on X.
+ * Execute with hsvd_execute.  Options as hsvd_plan_ex; MIXED_BF16 and batched use are
+ * HSVD_ERR_UNSUPPORTED; order is ignored (G is square).  The workspace holds G (and, for
+ * tall X, n^2-sized partial sums of up to ceil(1024 / tiles) row chunks).            */
+hsvd_status hsvd_plan_gram(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                           double tol, const hsvd_options* opt);
 
 /* Frees the plan and its workspace after synchronising its last stream.
  * plan == NULL is accepted and does nothing. */
@@ -225,7 +251,8 @@ typedef enum {
     HSVD_LAUNCH_CHECK = 15,        /* the leaves' power-step convergence test            */
     HSVD_LAUNCH_PANEL_QR = 16,     /* leaf panels: repeated Cholesky QR, one group each  */
     HSVD_LAUNCH_GEMM_AX_F32 = 17,  /* Y = A_blk X on the float32 matrix cores (mixed)    */
-    HSVD_LAUNCH_GEMM_ATX_F32 = 18  /* Y = A_blk^T X on the float32 matrix cores (mixed)  */
+    HSVD_LAUNCH_GEMM_ATX_F32 = 18, /* Y = A_blk^T X on the float32 matrix cores (mixed)  */
+    HSVD_LAUNCH_GRAM_XTX = 19      /* G = X^T X of a Gram plan (float64 matrix cores)    */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

@@ -7,6 +7,6 @@ under tests/test_oracle.py.
 """
 from .hsvd_oracle import (EPS, balanced_split, truncation_rank, leaf, randomised_leaf,  # noqa: F401
                           merge,
-                          merge_complement, merge_tree, slab_nodes, project, improve,
-                          sign_normalise, hsvd, flop_model)
+                          merge_complement, merge_tree, slab_nodes, col_slab_nodes, project, improve,
+                          sign_normalise, hsvd, hsvd_gram, flop_model)
 from . import metrics  # noqa: F401

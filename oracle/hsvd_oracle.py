@@ -44,6 +44,15 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
   R17 Algorithm 2's error is tested after every iteration, the first one included
      (against the Sigma-hat it was given, Algorithm 1's), and the loop ends at the
      first error <= eps.
+  R18 the opposite order of the two sets of merges (Section 3: either order gives the
+     singular values and one side's vectors) merges the blocks' right factors inside
+     each column slab, re-projects U_j from SVD(X_j V_j), merges the (U_j, S_j) up the
+     column-slab tree and projects V from SVD(X^T U).
+  R19 Gram input (the method applied to X^T X, as in Section 4's runs that form the product
+     first and then split it into blocks):
+     the trees run on G = X^T X formed in float64, with the grid, tol and rule taken
+     on G; V-hat from G's row-slab tree is X's, and U, s come from projecting X itself
+     (not from square roots of G's values), so the results are X's factors.
 """
 from __future__ import annotations
 
@@ -204,6 +213,24 @@ def slab_nodes(A, p: int, q: int, k: int, tol: float, rule: str, merge_fn=None, 
     return out
 
 
+def col_slab_nodes(A, p: int, q: int, k: int, tol: float, rule: str, merge_fn=None):
+    """The opposite order of the two sets of merges (Section 3): for each column slab
+    X_j, the blocks' right factors (V_b, S_b) -- the left factors of X_b^T -- are merged
+    pairwise up a tree (the row-wise merge of S_b V_b^T), then U_j, S_j = SVD(X_j V_j)
+    truncated by the same rule (R2).  Returns the column-slab nodes (U_j, S_j)."""
+    m, n = A.shape
+    out = []
+    for (c0, c1) in balanced_split(n, q):
+        X = A[:, c0:c1]
+        leaves = [leaf(X[r0:r1].T, k, tol, rule) for (r0, r1) in balanced_split(m, p)]
+        Vj, _ = merge_tree(leaves, k, tol, rule, merge_fn)
+        Y = X @ Vj                                       # m x r_j
+        Uy, sy, _ = _svd(Y)
+        r = truncation_rank(sy, k, tol, rule, Y.shape)
+        out.append((Uy[:, :r], sy[:r]))
+    return out
+
+
 def project(A, V):
     """Left vectors by projection: SVD(A V) = U_y S_y V_y^T; U = U_y, V <- V V_y (Section 3)."""
     Y = A @ V
@@ -254,25 +281,75 @@ def sign_normalise(U, V):
 
 def hsvd(A, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
          refine: int = 0, merge_fn=None, refine_eps: float | None = None, leaf_fn=None,
-         info: dict | None = None):
+         info: dict | None = None, order: str = "rows_last"):
     """The whole method: returns (U [m x k], s [k], Vt [k x n], r), zero padded past r.
 
-    Algorithm 1 gives (V-hat, S-hat); U follows by projection; `refine` runs
-    that many iterations of Algorithm 2 (fewer when refine_eps stops them, as in
-    `improve`, whose input Sigma-hat is Algorithm 1's).  `info`, when given,
-    receives the iterations of Algorithm 2 actually run.
+    order "rows_last" (Algorithm 1 as printed): the row-slab tree gives (V-hat, S-hat)
+    and U follows by projection.  order "cols_last" (the opposite order of the two sets
+    of merges, Section 3): the column-slab tree of `col_slab_nodes` gives (U-hat, S-hat)
+    and V follows by the projection SVD(A^T U-hat).  `refine` runs that many iterations
+    of Algorithm 2 (fewer when refine_eps stops them, as in `improve`, whose input
+    Sigma-hat is the tree's); for cols_last they are Algorithm 2 stated for A^T, whose
+    right vectors are A's left ones.  `info`, when given, receives the iterations of
+    Algorithm 2 actually run.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if not (1 <= p <= m and 1 <= q <= n and 1 <= k <= min(m, n) and 0.0 <= tol < 1.0):
         raise ValueError("invalid arguments")
-    slabs = slab_nodes(A, p, q, k, tol, rule, merge_fn, leaf_fn)
-    Vh, sh = merge_tree(slabs, k, tol, rule, merge_fn)
-    U, s, V = project(A, Vh)
+    if order not in ("rows_last", "cols_last"):
+        raise ValueError("order must be rows_last or cols_last")
+    if order == "rows_last":
+        slabs = slab_nodes(A, p, q, k, tol, rule, merge_fn, leaf_fn)
+        Vh, sh = merge_tree(slabs, k, tol, rule, merge_fn)
+        U, s, V = project(A, Vh)
+    else:
+        if leaf_fn is not None:
+            raise ValueError("leaf_fn applies to rows_last")
+        slabs = col_slab_nodes(A, p, q, k, tol, rule, merge_fn)
+        Uh, sh = merge_tree(slabs, k, tol, rule, merge_fn)
+        V, s, U = project(A.T, Uh)                       # A^T U-hat = V_y S_y W^T, U = U-hat W
     r = s.size
     done = 0
     if refine > 0 and r > 0:
-        U, s, V, done = improve(A, V, sh[:r], refine, refine_eps)
+        if order == "rows_last":
+            U, s, V, done = improve(A, V, sh[:r], refine, refine_eps)
+        else:
+            V, s, U, done = improve(A.T, U, sh[:r], refine, refine_eps)
+    if info is not None:
+        info["refine_iterations"] = done
+    U, V = sign_normalise(U, V)
+    Uo = np.zeros((m, k))
+    so = np.zeros(k)
+    Vto = np.zeros((k, n))
+    Uo[:, :r] = U
+    so[:r] = s
+    Vto[:r] = V.T
+    return Uo, so, Vto, r
+
+
+def hsvd_gram(X, p: int, q: int, k: int, tol: float = 0.0, rule: str = "gamma",
+              refine: int = 0, refine_eps: float | None = None, info: dict | None = None):
+    """The method applied to the Gram matrix G = X^T X (R19), returning X's factors.
+
+    G's right singular vectors are X's and its singular values are X's squared, so
+    Algorithm 1's row-slab tree runs on G (p x q grid over n x n; `tol` and `rule`
+    apply to G's values), V-hat is taken from its root and U, s follow by the projection
+    SVD(X V-hat) of Section 3.  Algorithm 2 runs on X; its first iteration is tested
+    against the projection's singular values.  Returns (U, s, Vt, r) as `hsvd`.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    m, n = X.shape
+    if not (1 <= p <= n and 1 <= q <= n and 1 <= k <= min(m, n) and 0.0 <= tol < 1.0):
+        raise ValueError("invalid arguments")
+    G = X.T @ X
+    slabs = slab_nodes(G, p, q, k, tol, rule)
+    Vh, _ = merge_tree(slabs, k, tol, rule)
+    U, s, V = project(X, Vh)
+    r = s.size
+    done = 0
+    if refine > 0 and r > 0:
+        U, s, V, done = improve(X, V, s, refine, refine_eps)
     if info is not None:
         info["refine_iterations"] = done
     U, V = sign_normalise(U, V)

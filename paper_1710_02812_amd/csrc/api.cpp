@@ -59,7 +59,7 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
 }
 
 enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY, ST_CQ1, ST_CQ2,
-                 ST_FEAT, ST_LEAFCHECK, ST_PQR };
+                 ST_FEAT, ST_LEAFCHECK, ST_PQR, ST_GRAMX };
 
 struct Stage {
     StageKind kind;
@@ -74,6 +74,7 @@ struct Stage {
     int guard = -1;      // int-arena slot: the stage is skipped while it holds non-zero
     int step = 0;        // leaf check: the power step it follows
     int need_r = 0;      // panel QR: R is formed
+    int a64 = 0;         // passes over a float64 matrix held in the arena (the Gram matrix)
 };
 
 int pow2floor(int x) {
@@ -89,8 +90,12 @@ int tsqr_chunk(int w, int /*c*/) { return tsqr_chunk_rows(w); }
 
 // One matrix of a plan: shape, grid, rank cap and the balanced split points.
 struct MatDesc {
+    // The plan works on the logical matrix: the input itself, or its transpose when the
+    // plan merges column slabs last (trans; Section 3: the order of the two sets of MAT
+    // operations).  m, n, p, q, rs, cs are logical; the input is (trans ? n x m : m x n).
     int64_t m = 0, n = 0;
     int p = 0, q = 0, k = 0;
+    bool trans = false;
     std::vector<int64_t> rs, cs;
     int64_t brow(int i) const { return rs[i + 1] - rs[i]; }
     int64_t bcol(int j) const { return cs[j + 1] - cs[j]; }
@@ -99,6 +104,13 @@ struct MatDesc {
 struct hsvd_plan_st {
     std::vector<MatDesc> mats;     // one for hsvd_plan, count for hsvd_plan_batched
     int kind = 0;                  // 0: SVD plan, 1: block-feature plan
+    bool trans = false;            // every matrix is handled transposed (column slabs merged last)
+    // Gram plans (hsvd_plan_gram): the trees decompose G = X^T X (matrix 0, held in the
+    // arena at gram_off, pointer-table entry 0 points there); the projection, Algorithm 2
+    // and the output use X (matrix 1).  ntree: the matrices the trees run on.
+    bool gram = false;
+    int64_t gram_off = -1;
+    int ntree = 0;
     std::vector<int> leaf_width;   // per-block sketch widths (width plans), else empty
     std::vector<int> leaf_rank_slots, leaf_flag_slots;   // per block of matrix 0
     int64_t energy_off = -1;       // block energies (width and feature plans)
@@ -362,6 +374,7 @@ void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<App
 // (mma 1) or the float32 ones (mma 2; both in strips of 256 rows holding every column).
 enum { MMA_F64 = 0, MMA_BF16 = 1, MMA_F32 = 2 };
 void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int mma = MMA_F64) {
+    if (P.trans) op = 1 - op;                     // logical A_blk X = (stored block)^T X
     std::vector<TileRef> tiles;
     const bool strip = mma != MMA_F64;
     const int nct = strip ? 1 : (N + 63) / 64;
@@ -376,6 +389,7 @@ void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int 
     s.kind = ST_GEMM;
     s.bf16 = mma == MMA_BF16 ? 1 : 0;
     s.f32 = mma == MMA_F32 ? 1 : 0;
+    s.a64 = (P.gram && !tasks.empty() && tasks[0].mat == 0) ? 1 : 0;
     s.op = op;
     s.n = (int)tiles.size();
     s.N = N;
@@ -437,13 +451,25 @@ int64_t identity_panel(hsvd_plan_st& P, int w) {
     return off;
 }
 
+// A pass task over the logical block at logical offset a_off (r0 * n + c0), rows x cols.
+// For a transposed plan the block is stored transposed in the input (rows and cols
+// swap, the leading dimension is the logical m) and push_gemm flips the product.
 GemmTask gemm_task(const hsvd_plan_st& P, int mat, int64_t a_off, int64_t rows, int64_t cols) {
+    const MatDesc& M = P.mats[mat];
     GemmTask t{};
     t.mat = mat;
-    t.lda = P.mats[mat].n;
-    t.a_off = a_off;
-    t.rows = (int)rows;
-    t.cols = (int)cols;
+    if (!M.trans) {
+        t.lda = M.n;
+        t.a_off = a_off;
+        t.rows = (int)rows;
+        t.cols = (int)cols;
+    } else {
+        const int64_t r0 = a_off / M.n, c0 = a_off % M.n;
+        t.lda = M.m;
+        t.a_off = c0 * M.m + r0;
+        t.rows = (int)cols;
+        t.cols = (int)rows;
+    }
     return t;
 }
 
@@ -802,7 +828,7 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
 // Returns one forest per (matrix, row slab), matrices in order, slabs top to bottom.
 std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
     std::vector<Leaf> leaves;
-    for (int mi = 0; mi < (int)P.mats.size(); ++mi) {
+    for (int mi = 0; mi < P.ntree; ++mi) {
         const MatDesc& M = P.mats[mi];
         for (int i = 0; i < M.p; ++i)
             for (int j = 0; j < M.q; ++j) {
@@ -890,7 +916,7 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
     push_tsqr_factor(P, tb, W, ch);
     std::vector<CoreTask> cores;
     std::vector<ApplyTask> at;
-    std::vector<std::vector<Node>> out(P.mats.size());
+    std::vector<std::vector<Node>> out(P.ntree);
     for (size_t i = 0; i < roots.size(); ++i) {
         const int mi = roots[i].mat;
         const int n = (int)P.mats[mi].n;
@@ -930,7 +956,7 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
     return out;
 }
 
-struct Factors { int64_t U, V, sig; int rank; };
+struct Factors { int64_t U, V, sig; int rank; int mat; };
 
 // Left vectors by projection, for every matrix: Y = A V (split over column
 // blocks), TSQR(Y) = Q R, Jacobi on R (with rotations J): U = Q Z, V <- V J.
@@ -941,12 +967,12 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
     std::vector<ThinTask> sums;
     std::vector<int64_t> Ys(vs.size());
     for (size_t mi = 0; mi < vs.size(); ++mi) {
-        const MatDesc& M = P.mats[mi];
+        const MatDesc& M = P.mats[vs[mi].mat];
         const int64_t m = M.m, n = M.n;
         const int64_t parts = P.alloc((int64_t)M.q * m * W);
         for (int i = 0; i < M.p; ++i)
             for (int j = 0; j < M.q; ++j) {
-                GemmTask t = gemm_task(P, (int)mi, M.rs[i] * n + M.cs[j], M.brow(i), M.bcol(j));
+                GemmTask t = gemm_task(P, vs[mi].mat, M.rs[i] * n + M.cs[j], M.brow(i), M.bcol(j));
                 t.x_off = vs[mi].panel + M.cs[j];
                 t.x_ld = vs[mi].ld;
                 t.y_off = parts + (int64_t)j * m * W + M.rs[i];
@@ -968,7 +994,7 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
     for (size_t mi = 0; mi < vs.size(); ++mi) {
-        const int m = (int)P.mats[mi].m;
+        const int m = (int)P.mats[vs[mi].mat].m;
         add_tsqr(P, tb, Ys[mi], m, m, W, ch, true);
     }
     push_tsqr_factor(P, tb, W, ch);
@@ -977,9 +1003,10 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
     std::vector<ApplyTask> at;
     std::vector<ThinTask> nns;
     for (size_t mi = 0; mi < vs.size(); ++mi) {
-        const MatDesc& M = P.mats[mi];
+        const MatDesc& M = P.mats[vs[mi].mat];
         const int64_t m = M.m, n = M.n;
         Factors& f = fs[mi];
+        f.mat = vs[mi].mat;
         f.U = P.alloc(m * W);
         f.V = P.alloc(n * W);
         f.sig = P.alloc(W);
@@ -1030,11 +1057,11 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     std::vector<ThinTask> sums;
     std::vector<int64_t> Zs(in.size());
     for (size_t mi = 0; mi < in.size(); ++mi) {
-        const MatDesc& M = P.mats[mi];
+        const MatDesc& M = P.mats[in[mi].mat];
         const int64_t m = M.m, n = M.n;
         const int64_t parts = P.alloc((int64_t)M.p * n * W);
         for (int i = 0; i < M.p; ++i) {
-            GemmTask t = gemm_task(P, (int)mi, M.rs[i] * n, M.brow(i), n);
+            GemmTask t = gemm_task(P, in[mi].mat, M.rs[i] * n, M.brow(i), n);
             t.x_off = in[mi].U + M.rs[i];
             t.x_ld = (int)m;
             t.y_off = parts + (int64_t)i * n * W;
@@ -1055,7 +1082,7 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
     for (size_t mi = 0; mi < in.size(); ++mi) {
-        const int n = (int)P.mats[mi].n;
+        const int n = (int)P.mats[in[mi].mat].n;
         add_tsqr(P, tb, Zs[mi], n, n, W, ch, true);
     }
     push_tsqr_factor(P, tb, W, ch);
@@ -1064,9 +1091,10 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     std::vector<ApplyTask> at;
     std::vector<ThinTask> nns;
     for (size_t mi = 0; mi < in.size(); ++mi) {
-        const MatDesc& M = P.mats[mi];
+        const MatDesc& M = P.mats[in[mi].mat];
         const int64_t m = M.m, n = M.n;
         Factors& f = fs[mi];
+        f.mat = in[mi].mat;
         f.U = P.alloc(m * W);
         f.V = P.alloc(n * W);
         f.sig = P.alloc(W);
@@ -1108,11 +1136,51 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     return fs;
 }
 
+// G = X^T X into the arena: partial Grams over row chunks of X (upper-triangle tiles,
+// mirrored), summed by the thin-sum kernel unless there is a single chunk.  For the sum
+// the n^2 contiguous elements are viewed as wy <= 128 columns of H rows (the last one
+// running past n^2 into slack that is allocated and whose sums are not used).
+void build_gram(hsvd_plan_st& P) {
+    const MatDesc& X = P.mats[1];
+    const int64_t m = X.m, n = X.n, nn = n * n;
+    const int T = (int)((n + 63) / 64), ntile = T * (T + 1) / 2;
+    int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + ntile - 1) / ntile, (m + 255) / 256));
+    const int64_t rows = (m + nch - 1) / nch;
+    nch = (m + rows - 1) / rows;
+    const int64_t H = (nn + 127) / 128, wy = (nn + H - 1) / H;
+    P.gram_off = P.alloc(nch == 1 ? nn : wy * H);
+    const int64_t parts = nch == 1 ? P.gram_off : P.alloc(nch * nn + wy * H);
+    std::vector<GramRef> refs;
+    for (int64_t c = 0; c < nch; ++c)
+        for (int a = 0; a < T; ++a)
+            for (int b = a; b < T; ++b) refs.push_back({a, b, (int)c, 0});
+    Stage s{};
+    s.kind = ST_GRAMX;
+    s.n = (int)refs.size();
+    s.off = parts;
+    s.off2 = rows;
+    s.tasks_off = P.put(refs);
+    P.stages.push_back(s);
+    if (nch > 1) {                                // only for n < 2880 (fewer than 1024 tiles)
+        ThinTask t{};
+        t.x_off = parts; t.x_ld = (int)H;
+        t.c_ld = (int)nn;
+        t.wx = (int)nch; t.wy = (int)wy;
+        t.y_off = P.gram_off; t.y_ld = (int)H;
+        t.h = (int)H;
+        t.acc_off = -1;
+        push_thin(P, ST_SUM, {t});
+    }
+}
+
 hsvd_status build_plan(hsvd_plan_st& P) {
+    if (P.gram) build_gram(P);
     auto slabs = build_leaves(P);
     auto col_roots = merge_forest(P, slabs);
     auto row_forests = build_reprojection(P, col_roots);
     auto row_roots = merge_forest(P, row_forests);
+    if (P.gram)                                   // V-hat of G = X^T X is X's: project against X
+        for (Node& r : row_roots) r.mat = 1;
     std::vector<Factors> f = build_projection(P, row_roots);
     const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
     const bool eps_stop = P.opt.refine_eps > 0.0 && steps >= 2;
@@ -1121,15 +1189,16 @@ hsvd_status build_plan(hsvd_plan_st& P) {
         std::vector<OutputArgs> outs;
         ranks.clear();
         for (size_t mi = 0; mi < ff.size(); ++mi) {
-            const MatDesc& M = P.mats[mi];
+            const MatDesc& M = P.mats[ff[mi].mat];
             OutputArgs o{};
-            o.u_off = ff[mi].U;
-            o.v_off = ff[mi].V;
+            // a transposed plan's right vectors are the input's left vectors
+            o.u_off = M.trans ? ff[mi].V : ff[mi].U;
+            o.v_off = M.trans ? ff[mi].U : ff[mi].V;
             o.sig_off = ff[mi].sig;
-            o.u_ld = (int)M.m;
-            o.v_ld = (int)M.n;
-            o.m = (int)M.m;
-            o.n = (int)M.n;
+            o.u_ld = (int)(M.trans ? M.n : M.m);
+            o.v_ld = (int)(M.trans ? M.m : M.n);
+            o.m = (int)(M.trans ? M.n : M.m);
+            o.n = (int)(M.trans ? M.m : M.n);
             o.k = M.k;
             o.rank_slot = ff[mi].rank;
             o.sign_off = P.ialloc(M.k);
@@ -1147,7 +1216,9 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     // the first iteration is tested against Algorithm 1's singular values (the row
     // tree's root), each later one against the iteration before it
     std::vector<Factors> prev(f.size());
-    for (size_t mi = 0; mi < f.size(); ++mi) prev[mi].sig = row_roots[mi].sig;
+    // (a Gram plan's tree holds X^T X's values, X's squared: its first iteration is
+    // tested against the projection's values, X's own)
+    for (size_t mi = 0; mi < f.size(); ++mi) prev[mi].sig = P.gram ? f[mi].sig : row_roots[mi].sig;
     std::vector<OutputArgs> last_outs;
     for (int it = 0; it < steps; ++it) {
         f = build_refine_step(P, f);
@@ -1171,10 +1242,10 @@ hsvd_status build_plan(hsvd_plan_st& P) {
         if (it + 1 < steps) {
             std::vector<Node> vs(f.size());
             for (size_t mi = 0; mi < f.size(); ++mi) {
-                vs[mi].mat = (int)mi;
+                vs[mi].mat = f[mi].mat;
                 vs[mi].panel = f[mi].V;
-                vs[mi].ld = (int)P.mats[mi].n;
-                vs[mi].h = (int)P.mats[mi].n;
+                vs[mi].ld = (int)P.mats[f[mi].mat].n;
+                vs[mi].h = (int)P.mats[f[mi].mat].n;
                 vs[mi].rank = f[mi].rank;
                 vs[mi].sig = f[mi].sig;
             }
@@ -1183,10 +1254,10 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     }
     P.kmax = P.mmax = P.nmax = 0;
     for (size_t mi = 0; mi < f.size(); ++mi) {
-        const MatDesc& M = P.mats[mi];
+        const MatDesc& M = P.mats[f[mi].mat];
         P.kmax = std::max(P.kmax, M.k);
-        P.mmax = std::max<int>(P.mmax, (int)M.m);
-        P.nmax = std::max<int>(P.nmax, (int)M.n);
+        P.mmax = std::max<int>(P.mmax, (int)std::max(M.m, M.n));
+        P.nmax = std::max<int>(P.nmax, (int)std::max(M.m, M.n));
     }
     if (eps_stop) {
         // the last iteration's table doubles as the plan's output
@@ -1297,9 +1368,10 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const GemmTask& t = T[i];
                     if (t.mat < 0 || t.mat >= (int)P.mats.size()) return "gemm matrix index";
                     const MatDesc& M = P.mats[t.mat];
-                    if (t.lda != M.n) return "gemm leading dimension";
-                    if (!span("gemm A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * M.n + t.cols - 1, M.m * M.n)) return msg;
-                    if (t.cols > M.n || t.a_off % M.n + t.cols > M.n) return "gemm A block crosses a row";
+                    const int64_t ld = M.trans ? M.m : M.n;     // the input's row length
+                    if (t.lda != ld) return "gemm leading dimension";
+                    if (!span("gemm A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * ld + t.cols - 1, M.m * M.n)) return msg;
+                    if (t.cols > ld || t.a_off % ld + t.cols > ld) return "gemm A block crosses a row";
                     const int xr = s.op == 0 ? t.cols : t.rows, yr = s.op == 0 ? t.rows : t.cols;
                     if (!panel("gemm X", t.x_off, t.x_ld, xr, s.N)) return msg;
                     if (!panel("gemm Y", t.y_off, t.y_ld, yr, s.N)) return msg;
@@ -1406,9 +1478,23 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const GemmTask& t = T[i];
                     if (t.mat < 0 || t.mat >= (int)P.mats.size()) return "energy matrix index";
                     const MatDesc& M = P.mats[t.mat];
-                    if (t.lda != M.n || t.cols > M.n || t.a_off % M.n + t.cols > M.n) return "energy block";
-                    if (!span("energy A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * M.n + t.cols - 1, M.m * M.n)) return msg;
+                    const int64_t ld = M.trans ? M.m : M.n;
+                    if (t.lda != ld || t.cols > ld || t.a_off % ld + t.cols > ld) return "energy block";
+                    if (!span("energy A", t.a_off, t.a_off + (int64_t)(t.rows - 1) * ld + t.cols - 1, M.m * M.n)) return msg;
                 }
+                break;
+            }
+            case ST_GRAMX: {
+                if (!P.gram || P.mats.size() != 2) return "Gram stage outside a Gram plan";
+                const MatDesc& X = P.mats[1];
+                const int T = (int)((X.n + 63) / 64);
+                const int64_t rows = s.off2, nch = (X.m + rows - 1) / std::max<int64_t>(rows, 1);
+                if (rows < 1) return "Gram chunk rows";
+                if (!span("Gram partials", s.off, s.off + nch * X.n * X.n - 1, WS)) return msg;
+                const GramRef* R = (const GramRef*)(b + s.tasks_off);
+                for (int i = 0; i < s.n; ++i)
+                    if (R[i].ti < 0 || R[i].ti > R[i].tj || R[i].tj >= T || R[i].chunk < 0 || R[i].chunk >= nch)
+                        return "Gram tile ref";
                 break;
             }
             case ST_PQR: {
@@ -1479,13 +1565,14 @@ std::string validate_plan(const hsvd_plan_st& P) {
         if (s.guard >= IW) return "stage guard slot";
     for (int slot : P.reset_slots)
         if (slot < 0 || slot >= IW) return "reset slot";
-    if (P.outs.size() != (P.kind == 0 ? P.mats.size() : 0)) return "output count";
+    if (P.outs.size() != (P.kind == 0 ? (size_t)P.ntree : 0)) return "output count";
     for (size_t mi = 0; mi < P.outs.size(); ++mi) {
         const OutputArgs& o = P.outs[mi];
-        const MatDesc& M = P.mats[mi];
-        if (o.m != M.m || o.n != M.n || o.k != M.k || o.k > P.W) return "output shape";
-        if (!panel("out U", o.u_off, o.u_ld, M.m, P.W)) return msg;
-        if (!panel("out V", o.v_off, o.v_ld, M.n, P.W)) return msg;
+        const MatDesc& M = P.mats[P.gram ? 1 : mi];
+        const int64_t om = M.trans ? M.n : M.m, on = M.trans ? M.m : M.n;   // the input's shape
+        if (o.m != om || o.n != on || o.k != M.k || o.k > P.W) return "output shape";
+        if (!panel("out U", o.u_off, o.u_ld, om, P.W)) return msg;
+        if (!panel("out V", o.v_off, o.v_ld, on, P.W)) return msg;
         if (!span("out sigma", o.sig_off, o.sig_off + P.W - 1, WS)) return msg;
         if (!span("out signs", o.sign_off, o.sign_off + M.k - 1, IW)) return msg;
         if (o.rank_slot < 0 || o.rank_slot >= IW) return "out rank slot";
@@ -1497,7 +1584,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
 hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
     unsigned char* b = (unsigned char*)P.dblob;
     hipError_t e = hipSuccess;
-    const int fp32 = P.opt.precision != HSVD_FP64;
+    const int fp32 = P.opt.precision != HSVD_FP64 && !s.a64;
     const int* guard = s.guard >= 0 ? P.iws + s.guard : nullptr;
     switch (s.kind) {
         case ST_GEMM:
@@ -1516,6 +1603,12 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             e = launch_cholqr(s.kind == ST_CQ1 ? 1 : 2, P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),
                               (const ChunkRef*)(b + s.refs_off), s.n, s.w, s.ch, st);
             break;
+        case ST_GRAMX: {
+            const MatDesc& X = P.mats[1];
+            e = launch_gram_xtx(P.opt.precision != HSVD_FP64, (const void* const*)P.dptrs, 1, X.m, X.n, s.off2, P.ws,
+                                s.off, (const GramRef*)(b + s.tasks_off), s.n, st);
+            break;
+        }
         case ST_PQR:
             e = launch_panel_qr(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off), s.n, s.w, s.need_r, st, guard);
             break;
@@ -1578,7 +1671,7 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->seed = 0;
     opt->refine_eps = 0.0;
     opt->graph = 1;
-    opt->reserved = 0;
+    opt->order = HSVD_ORDER_AUTO;
     return HSVD_OK;
 }
 
@@ -1687,7 +1780,8 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         const int32_t p = ps[i], q = qs[i], k = ks[i];
         const std::string at = count > 1 ? " (matrix " + std::to_string(i) + ")" : "";
         if (m < 1 || n < 1) return fail(HSVD_ERR_INVALID, "m and n must be >= 1" + at);
-        if (p < 1 || p > m) return fail(HSVD_ERR_INVALID, "need 1 <= p <= m" + at);
+        if (p < 1 || p > (kind == 2 ? n : m))       // a Gram plan's grid is over the n x n X^T X
+            return fail(HSVD_ERR_INVALID, std::string(kind == 2 ? "need 1 <= p <= n" : "need 1 <= p <= m") + at);
         if (q < 1 || q > n) return fail(HSVD_ERR_INVALID, "need 1 <= q <= n" + at);
         if (k < 1 || k > std::min(m, n)) return fail(HSVD_ERR_INVALID, "need 1 <= k <= min(m, n)" + at);
         if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
@@ -1706,26 +1800,54 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         return fail(HSVD_ERR_INVALID, "negative option");
     if (o.power_steps > 64) return fail(HSVD_ERR_INVALID, "power_steps above 64");
     if (!(o.refine_eps >= 0.0)) return fail(HSVD_ERR_INVALID, "need refine_eps >= 0");
-    if ((o.graph != 0 && o.graph != 1) || o.reserved != 0) return fail(HSVD_ERR_INVALID, "graph must be 0 or 1, reserved 0");
+    if (o.graph != 0 && o.graph != 1) return fail(HSVD_ERR_INVALID, "graph must be 0 or 1");
+    if (o.order < HSVD_ORDER_AUTO || o.order > HSVD_ORDER_COLS_LAST) return fail(HSVD_ERR_INVALID, "unknown order");
 
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
     P->tol = tol;
     P->opt = o;
+    // merge order: column slabs last (the plan works on the transpose) when asked, or
+    // automatically for a single short-fat matrix so that the last tree and the final
+    // projection run on the shorter side; learned-width and feature plans keep the
+    // order of Algorithm 1
+    const bool gram = kind == 2;                 // hsvd_plan_gram: the trees decompose X^T X
+    if (gram) {
+        kind = 0;
+        if (count != 1 || leaf_width || o.precision == HSVD_MIXED_BF16) {
+            delete P;
+            return fail(HSVD_ERR_UNSUPPORTED, "Gram plans take one float64 or float32 matrix");
+        }
+    }
+    P->gram = gram;
+    P->trans = !gram && (o.order == HSVD_ORDER_COLS_LAST ||
+                         (o.order == HSVD_ORDER_AUTO && count == 1 && ms[0] < ns[0] && !leaf_width && kind == 0));
+    if (P->trans && (leaf_width || kind != 0)) {
+        delete P;
+        return fail(HSVD_ERR_UNSUPPORTED, "width and feature plans merge row slabs last");
+    }
     int kmax = 0, lwant = 1;
     int64_t bmin = INT64_MAX;
-    for (int i = 0; i < count; ++i) {
+    const int nmat = gram ? 2 : count;
+    for (int i = 0; i < nmat; ++i) {
         MatDesc M;
-        M.m = ms[i]; M.n = ns[i]; M.p = ps[i]; M.q = qs[i]; M.k = ks[i];
+        M.trans = P->trans;
+        if (gram && i == 0) { M.m = ns[0]; M.n = ns[0]; M.p = ps[0]; M.q = qs[0]; }      // G = X^T X
+        else if (gram) { M.m = ms[0]; M.n = ns[0]; M.q = qs[0];                            // X (projection blocks)
+                         M.p = (int)std::max<int64_t>(1, std::min<int64_t>(ms[0], (ms[0] + 2047) / 2048)); }
+        else if (!P->trans) { M.m = ms[i]; M.n = ns[i]; M.p = ps[i]; M.q = qs[i]; }
+        else { M.m = ns[i]; M.n = ms[i]; M.p = qs[i]; M.q = ps[i]; }
+        M.k = ks[gram ? 0 : i];
         M.rs.resize(M.p + 1);
         M.cs.resize(M.q + 1);
         for (int r = 0; r <= M.p; ++r) M.rs[r] = (M.m / M.p) * r + std::min<int64_t>(r, M.m % M.p);
         for (int c = 0; c <= M.q; ++c) M.cs[c] = (M.n / M.q) * c + std::min<int64_t>(c, M.n % M.q);
-        bmin = std::min(bmin, std::min(M.m / M.p, M.n / M.q));
+        if (!(gram && i == 1)) bmin = std::min(bmin, std::min(M.m / M.p, M.n / M.q));
         kmax = std::max(kmax, M.k);
         lwant = std::max(lwant, M.k + o.oversample);
         P->mats.push_back(std::move(M));
     }
+    P->ntree = gram ? 1 : (int)P->mats.size();
     // one panel width and one sketch width for the whole batch (per-matrix rank caps
     // stay in the tasks)
     P->W = kmax;
@@ -1780,13 +1902,13 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     e = hipMalloc(&P->iws, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
     if (e == hipSuccess) e = hipMalloc(&P->flags, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMalloc(&P->dblob, std::max<size_t>(P->blob.size(), 256));
-    if (e == hipSuccess) e = hipMalloc((void**)&P->dptrs, sizeof(void*) * 4 * (size_t)count);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->dptrs, sizeof(void*) * 4 * P->mats.size());
     if (e != hipSuccess) { hsvd_destroy(P); return fail(HSVD_ERR_ALLOC, "allocation failed"); }
     e = hipMemcpy(P->dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(P->iws, 0, sizeof(int) * (size_t)std::max(P->iws_elems, 1));
     if (e == hipSuccess) e = hipMemset(P->flags, 0, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMemset(P->ws, 0, sizeof(double) * (size_t)P->ws_elems);
-    if (e == hipSuccess) e = hipMemset(P->dptrs, 0, sizeof(void*) * 4 * (size_t)count);
+    if (e == hipSuccess) e = hipMemset(P->dptrs, 0, sizeof(void*) * 4 * P->mats.size());
     for (auto& c : P->ws_init)
         if (e == hipSuccess)
             e = hipMemcpy(P->ws + c.first, c.second.data(), c.second.size() * sizeof(double),
@@ -1842,6 +1964,11 @@ hsvd_status hsvd_debug_plan_check_batched(int32_t count, const int64_t* m, const
     hsvd_status st = plan_impl(nullptr, count, m, n, p, q, k, tol, opt, &bytes);
     if (workspace_bytes) *workspace_bytes = bytes;
     return st;
+}
+
+hsvd_status hsvd_plan_gram(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
+                           double tol, const hsvd_options* opt) {
+    return plan_impl(out, 1, &m, &n, &p, &q, &k, tol, opt, nullptr, nullptr, 2);
 }
 
 hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q, int32_t k,
@@ -1939,7 +2066,7 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
             }
             if (t + 1 == nseg) continue;
             e = launch_refine_check(P.ws, P.iws, (const RefineCheck*)((unsigned char*)P.dblob + P.check_off[t]),
-                                    (int)P.mats.size(), P.opt.refine_eps, P.check_slot, stream);
+                                    P.ntree, P.opt.refine_eps, P.check_slot, stream);
             int done = 0;
             if (e == hipSuccess) e = hipMemcpyAsync(&done, P.iws + P.check_slot, sizeof(int), hipMemcpyDeviceToHost, stream);
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1964,6 +2091,14 @@ hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void
                          hipStream_t stream) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
     if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan: use hsvd_features_execute");
+    if (plan->gram) {                             // entry 0: G in the arena; entry 1: X
+        const void* As[2] = {plan->ws + plan->gram_off, A};
+        void* Us[2] = {U, U};
+        void* Ss[2] = {S, S};
+        void* Vs[2] = {Vt, Vt};
+        if (!A) return fail(HSVD_ERR_INVALID, "NULL data pointer");
+        return execute_impl(*plan, As, Us, Ss, Vs, stream);
+    }
     if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_execute_batched");
     if (plan->rm_params) return learned_execute(*plan, A, U, S, Vt, stream);
     return execute_impl(*plan, &A, &U, &S, &Vt, stream);
@@ -1980,6 +2115,7 @@ hsvd_status hsvd_execute_batched(hsvd_plan_t plan, const void* const* A, void* c
                                  void* const* Vt, hipStream_t stream) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
     if (plan->kind != 0) return fail(HSVD_ERR_INVALID, "feature plan: use hsvd_features_execute");
+    if (plan->gram) return fail(HSVD_ERR_INVALID, "Gram plan: use hsvd_execute");
     if (!A || !U || !S || !Vt) return fail(HSVD_ERR_INVALID, "NULL pointer array");
     return execute_impl(*plan, A, U, S, Vt, stream);
 }
@@ -2031,6 +2167,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
                 case ST_LEAFCHECK: kind = HSVD_LAUNCH_CHECK; break;
                 case ST_PQR: kind = HSVD_LAUNCH_PANEL_QR; break;
+                case ST_GRAMX: kind = HSVD_LAUNCH_GRAM_XTX; break;
             }
         }
         float ms = 0.f;
@@ -2165,6 +2302,12 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     f = 0.0;
                     by = 0.0;
                     break;
+                case ST_GRAMX: {                                  // G = X^T X, symmetric: m n (n + 1) flops
+                    const MatDesc& X = P.mats[1];
+                    f = (double)X.m * X.n * (X.n + 1.0);
+                    by = (double)X.m * X.n * eA + (double)X.n * X.n * e8;
+                    break;
+                }
                 case ST_PQR: {                                    // a QR of the panel and its explicit Q
                     const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
                     for (int t = 0; t < s.n; ++t) {
@@ -2213,7 +2356,7 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan) {
 
 hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count) {
     if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
-    if (count != (int32_t)plan->mats.size()) return fail(HSVD_ERR_INVALID, "count does not match the plan");
+    if (count != (int32_t)plan->rank_slots.size()) return fail(HSVD_ERR_INVALID, "count does not match the plan");
     hipError_t e = hipSuccess;
     if (plan->executed) e = hipStreamSynchronize(plan->last_stream);
     std::vector<int> all((size_t)plan->iws_elems);
@@ -2235,9 +2378,12 @@ hsvd_status hsvd_get_leaf_info(hsvd_plan_t plan, int32_t* ranks, int32_t* fallba
     if (e == hipSuccess && !all.empty())
         e = hipMemcpy(all.data(), plan->iws, sizeof(int) * all.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hsvd_get_leaf_info");
+    const MatDesc& M0 = plan->mats[0];
     for (int32_t b = 0; b < count; ++b) {
-        if (ranks) ranks[b] = all[(size_t)plan->leaf_rank_slots[b]];
-        if (fallback) fallback[b] = plan->leaf_flag_slots[b] >= 0 ? all[(size_t)plan->leaf_flag_slots[b]] : 0;
+        // block b of the input's grid is logical block (j, i) of a transposed plan
+        const int32_t lb = M0.trans ? (b % M0.p) * M0.q + b / M0.p : b;
+        if (ranks) ranks[b] = all[(size_t)plan->leaf_rank_slots[lb]];
+        if (fallback) fallback[b] = plan->leaf_flag_slots[lb] >= 0 ? all[(size_t)plan->leaf_flag_slots[lb]] : 0;
     }
     return HSVD_OK;
 }
@@ -2252,7 +2398,7 @@ hsvd_status hsvd_get_refine_iterations(hsvd_plan_t plan, int32_t* iters_host) {
 hsvd_status hsvd_get_rank(hsvd_plan_t plan, int32_t* r_host) {
     if (!plan || !r_host) return fail(HSVD_ERR_INVALID, "NULL argument");
     if (plan->rm_ran && plan->rm_ran != plan) return hsvd_get_rank(plan->rm_ran, r_host);
-    if (plan->mats.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_get_ranks");
+    if (plan->rank_slots.size() != 1) return fail(HSVD_ERR_INVALID, "batched plan: use hsvd_get_ranks");
     return hsvd_get_ranks(plan, r_host, 1);
 }
 
@@ -2280,8 +2426,9 @@ hsvd_status hsvd_workspace_bytes(hsvd_plan_t plan, size_t* bytes_host) {
 
 hsvd_status hsvd_set_rank_model(hsvd_plan_t plan, const void* weights_host, size_t bytes) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
-    if (plan->kind != 0 || plan->mats.size() != 1 || plan->external || !plan->leaf_width.empty())
-        return fail(HSVD_ERR_INVALID, "rank models attach to single-matrix plans from hsvd_plan / hsvd_plan_ex");
+    if (plan->kind != 0 || plan->mats.size() != 1 || plan->external || !plan->leaf_width.empty() || plan->trans)
+        return fail(HSVD_ERR_INVALID, "rank models attach to single-matrix plans from hsvd_plan / hsvd_plan_ex "
+                                      "that merge row slabs last");
     if (plan->opt.precision != HSVD_FP64 && plan->opt.precision != HSVD_FP32)
         return fail(HSVD_ERR_UNSUPPORTED, "rank models need a float64 or float32-storage plan");
     if (weights_host && bytes != sizeof(float) * (size_t)kMlpParams)

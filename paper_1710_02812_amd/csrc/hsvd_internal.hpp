@@ -25,6 +25,8 @@ struct GemmTask {
     int32_t mat;          // matrix index: A = Aptrs[mat]
 };
 struct TileRef { int32_t task; int32_t tile; };
+// A tile of the Gram matrix G = X^T X (upper triangle, ti <= tj) over one row chunk of X.
+struct GramRef { int32_t ti, tj, chunk, pad; };
 
 // ---------------------------------------------------------------- tall-skinny QR (TSQR)
 // Panel P (h x w, col-major, ld) split into nch row chunks of `ch` rows; each chunk
@@ -204,6 +206,11 @@ hipError_t launch_gemm_bf16(int op, const void* const* ptrs, double* ws, const G
 // float32 matrix-core passes (mixed plans' float32-accurate products): same strips
 hipError_t launch_gemm_f32(int op, const void* const* ptrs, double* ws, const GemmTask* tasks,
                            const TileRef* tiles, int ntiles, int N, hipStream_t s);
+// G = X^T X partials: one per row chunk of `rows_per_chunk` rows of matrix `mat`
+// (X row-major m x n, float32 or float64); partial c at ws + parts_off + c n^2.
+hipError_t launch_gram_xtx(int fp32, const void* const* ptrs, int mat, int64_t m, int64_t n,
+                           int64_t rows_per_chunk, double* ws, int64_t parts_off, const GramRef* refs, int nrefs,
+                           hipStream_t s);
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s, const int* guard = nullptr);

@@ -38,6 +38,45 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict
     mfma_tile_out(M, N, r0, c0, acc, [&](int r, int c, double v) { Y[(int64_t)c * t.y_ld + r] = v; });
 }
 
+// Gram matrix of the input, G = X^T X (X row-major m x n, G n x n), for the plans that
+// decompose X^T X: tile (ti, tj) with ti <= tj of G over the rows of chunk kc, written
+// to partial kc (col-major, ld n) at (ti, tj) and mirrored at (tj, ti); the partials are
+// summed by the thin-sum kernel.  refs: one GramRef per (tile, chunk).
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gram_xtx(const void* const* __restrict__ ptrs, int mat, int64_t m,
+                                                  int64_t n, int64_t rows_per_chunk, double* __restrict__ ws,
+                                                  int64_t parts_off, const GramRef* __restrict__ refs) {
+    __shared__ double As[mfma_lds_a<1>()];
+    __shared__ double Bs[mfma_lds_b()];
+    const GramRef g = refs[blockIdx.x];
+    const TA* X = (const TA*)ptrs[4 * mat];
+    const int64_t row0 = (int64_t)g.chunk * rows_per_chunk;
+    const int K = (int)std::min<int64_t>(rows_per_chunk, m - row0);
+    const int r0 = g.ti * GT, c0 = g.tj * GT;
+    v4d acc[2][2];
+    mfma_tile<TA, 1, true, TA, true>(X + row0 * n, n, X + row0 * n, n, (int)n, (int)n, K, r0, c0, As, Bs, acc);
+    double* part = ws + parts_off + (int64_t)g.chunk * n * n;
+    const bool diag = g.ti == g.tj;               // a diagonal tile writes each pair once
+    mfma_tile_out((int)n, (int)n, r0, c0, acc, [&](int r, int c, double v) {
+        if (diag && r > c) return;
+        part[(int64_t)c * n + r] = v;
+        part[(int64_t)r * n + c] = v;
+    });
+}
+
+hipError_t launch_gram_xtx(int fp32, const void* const* ptrs, int mat, int64_t m, int64_t n,
+                           int64_t rows_per_chunk, double* ws, int64_t parts_off, const GramRef* refs, int nrefs,
+                           hipStream_t s) {
+    if (nrefs <= 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(k_gram_xtx<float>, dim3(nrefs), dim3(256), 0, s, ptrs, mat, m, n, rows_per_chunk, ws,
+                           parts_off, refs);
+    else
+        hipLaunchKernelGGL(k_gram_xtx<double>, dim3(nrefs), dim3(256), 0, s, ptrs, mat, m, n, rows_per_chunk, ws,
+                           parts_off, refs);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
                        hipStream_t s, const int* guard) {

@@ -28,9 +28,11 @@ __host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (MF_K +
 __host__ __device__ constexpr int mfma_lds_b() { return MF_T * (MF_K + 1); }
 
 // With ZERO false the products add to acc as it stands (a second operand pair).
-template <typename TA, int OP, bool ZERO = true>
+// TB / BROW: B's element type and layout (BROW: B row-major, B(k, j) = B[k * ldb + j],
+// read with consecutive threads on consecutive columns).
+template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false>
 __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
-                                          const double* __restrict__ B, int64_t ldb,
+                                          const TB* __restrict__ B, int64_t ldb,
                                           int M, int N, int K, int r0, int c0, double* As, double* Bs,
                                           v4d (&acc)[2][2]) {
     constexpr int AP = OP == 0 ? MF_K + 1 : MF_T + 1;
@@ -40,7 +42,7 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
     const int li = lane & 15, lk = lane >> 4;
     constexpr int NE = MF_T * MF_K / 256;                      // slab elements per thread
     TA pa[NE];
-    double pb[NE];
+    TB pb[NE];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
@@ -54,9 +56,10 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                 const int gk = k0 + kk, gc = r0 + c;
                 pa[u] = (gk < K && gc < M) ? A[(int64_t)gk * lda + gc] : (TA)0;
             }
-            const int bc = e / MF_K, bk = e % MF_K;            // B(k0 + bk, c0 + bc)
+            const int bc = BROW ? e % MF_T : e / MF_K, bk = BROW ? e / MF_T : e % MF_K;   // B(k0 + bk, c0 + bc)
             const int gbc = c0 + bc, gbk = k0 + bk;
-            pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : 0.0;
+            if (BROW) pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbk * ldb + gbc] : (TB)0;
+            else pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : (TB)0;
         }
     };
     auto stage = [&]() {
@@ -65,7 +68,8 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
             const int e = tid + 256 * u;
             if (OP == 0) As[(e / MF_K) * AP + (e % MF_K)] = (double)pa[u];
             else As[(e / MF_T) * AP + (e % MF_T)] = (double)pa[u];
-            Bs[(e / MF_K) * BP + (e % MF_K)] = pb[u];
+            if (BROW) Bs[(e % MF_T) * BP + (e / MF_T)] = (double)pb[u];
+            else Bs[(e / MF_K) * BP + (e % MF_K)] = (double)pb[u];
         }
     };
     if (ZERO)

@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR
                 5: "ERR_NOCONV", 6: "ERR_UNSUPPORTED"}
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 RULE_GAMMA, RULE_FROB = 0, 1
+ORDER_AUTO, ORDER_ROWS_LAST, ORDER_COLS_LAST = 0, 1, 2
 FLAG_RANK_FALLBACK = 4
 FLAG_NONFINITE, FLAG_NOCONV = 0x1, 0x2
 
@@ -34,12 +35,12 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_rank_model_predict",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
             "hsvd_debug_plan_check", "hsvd_svd_static", "hsvd_set_workspace", "hsvd_set_rank_model",
-            "hsvd_get_leaf_widths",
+            "hsvd_get_leaf_widths", "hsvd_plan_gram",
             "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features", "cholqr",
-                "check", "panel_qr", "gemm_ax_f32", "gemm_atx_f32"]
+                "check", "panel_qr", "gemm_ax_f32", "gemm_atx_f32", "gram_xtx"]
 
 
 class HsvdError(RuntimeError):
@@ -53,7 +54,7 @@ class Options(ctypes.Structure):
                 ("oversample", ctypes.c_int32), ("power_steps", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,6 +81,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_workspace_bytes.argtypes = [vp, P(ctypes.c_size_t)]
     L.hsvd_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     L.hsvd_set_rank_model.argtypes = [vp, vp, ctypes.c_size_t]
+    L.hsvd_plan_gram.argtypes = [P(vp), i64, i64, i32, i32, i32, f64, P(Options)]
     L.hsvd_get_leaf_widths.argtypes = [vp, P(i32), i32, P(i32), P(i32)]
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
@@ -158,11 +160,14 @@ class Plan:
                  precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
                  power_steps: int | None = None, refine_steps: int = 0,
                  max_sweeps: int | None = None, seed: int = 0, leaf_widths=None,
-                 refine_eps: float = 0.0, graph: bool = True):
+                 refine_eps: float = 0.0, graph: bool = True, order: int = ORDER_AUTO, gram: bool = False):
         """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths);
-        graph: replay a hipGraph captured on the first execute."""
+        graph: replay a hipGraph captured on the first execute; order: ORDER_AUTO,
+        ORDER_ROWS_LAST (Algorithm 1 as printed) or ORDER_COLS_LAST (the opposite order);
+        gram: decompose X^T X (p x q grid of the n x n Gram matrix; hsvd_plan_gram)."""
         o = default_options()
         o.graph = 1 if graph else 0
+        o.order = order
         o.precision = precision
         o.rule = rule
         if oversample is not None:
@@ -175,7 +180,11 @@ class Plan:
         o.seed = seed
         o.refine_eps = float(refine_eps)
         h = ctypes.c_void_p()
-        if leaf_widths is None:
+        if gram:
+            if leaf_widths is not None:
+                raise ValueError("Gram plans take no leaf widths")
+            _check(lib().hsvd_plan_gram(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
+        elif leaf_widths is None:
             _check(lib().hsvd_plan_ex(ctypes.byref(h), m, n, p, q, k, float(tol), ctypes.byref(o)))
         else:
             wv = [int(x) for x in list(np.asarray(leaf_widths).reshape(-1))]

@@ -32,9 +32,18 @@ def run_gpu(A, p, q, k, tol=0.0, dtype=torch.float64, **opts):
     return U.double().cpu().numpy(), S.double().cpu().numpy(), Vt.double().cpu().numpy(), r
 
 
+def oracle_order(m, n, opts):
+    """The merge order a plan takes: HSVD_ORDER_AUTO runs the opposite order (column
+    slabs merged last) for a short-fat matrix, Algorithm 1's otherwise."""
+    order = opts.get("order", H.ORDER_AUTO)
+    if order == H.ORDER_COLS_LAST or (order == H.ORDER_AUTO and m < n):
+        return "cols_last"
+    return "rows_last"
+
+
 def check_parity(A, p, q, k, tol=0.0, rule="gamma", dtype=torch.float64, gate=1e-10, **opts):
     Ao = A if dtype == torch.float64 else A.astype(np.float32).astype(np.float64)
-    Uo, so, Vto, ro = oracle.hsvd(Ao, p, q, k, tol, rule)
+    Uo, so, Vto, ro = oracle.hsvd(Ao, p, q, k, tol, rule, order=oracle_order(*A.shape, opts))
     Ug, sg, Vtg, rg = run_gpu(A, p, q, k, tol, dtype,
                               rule=(H.RULE_GAMMA if rule == "gamma" else H.RULE_FROB), **opts)
     assert rg == ro, (rg, ro)
@@ -440,3 +449,109 @@ def test_set_workspace_from_torch_memory():
         torch.cuda.synchronize()
         assert torch.equal(U0, U1) and torch.equal(S0, S1) and torch.equal(V0, V1), rep
     plan.close()
+
+
+@pytest.mark.parametrize("m,n,p,q,k,order", [(512, 512, 2, 2, 20, H.ORDER_COLS_LAST),
+                                             (700, 1300, 5, 3, 12, H.ORDER_ROWS_LAST),
+                                             (1300, 700, 3, 5, 12, H.ORDER_COLS_LAST),
+                                             (600, 2000, 1, 4, 16, H.ORDER_AUTO),
+                                             (2000, 600, 4, 1, 16, H.ORDER_AUTO)])
+def test_merge_order_parity_fp64(m, n, p, q, k, order):
+    """Both orders of the two sets of merges (Algorithm 1 as printed, and column slabs
+    merged last) and the automatic choice, against the oracle's same order; one-direction
+    grids (p x 1, 1 x q) included."""
+    rng = np.random.default_rng(m + 3 * n + p + q)
+    sigma = 10.0 ** (-np.arange(k) / (k / 3.0))
+    A, *_ = synth.low_rank(rng, m, n, sigma, noise=1e-9)
+    print(f"order {order}: {m}x{n} {p}x{q} k={k}", flush=True)
+    check_parity(A, p, q, k, order=order)
+
+
+def test_merge_order_mixed_and_float32():
+    """The opposite order on the float32-storage and mixed paths (short-fat input, auto)."""
+    rng = np.random.default_rng(99)
+    A, *_ = synth.low_rank(rng, 1024, 3072, 10.0 ** (-np.arange(24) / 8.0), noise=1e-6)
+    check_parity(A, 2, 6, 24, dtype=torch.float32, gate=1e-5)
+    Uo, so, Vto, ro = oracle.hsvd(A.astype(np.float32).astype(np.float64), 2, 6, 24, 0.0, order="cols_last")
+    Ug, sg, Vtg, rg = run_gpu(A, 2, 6, 24, 0.0, torch.float32, mixed=True)
+    c = metrics.compare(Ug, sg, Vtg, rg, Uo, so, Vto, ro)
+    print("mixed cols_last", c, flush=True)
+    assert rg == ro and c["e_frob"] <= 1e-3
+
+
+# ----------------------------------------------------------------------------- Gram input
+def check_gram(X, p, q, k, tol=0.0, dtype=torch.float64, gate=1e-9, refine=0, refine_eps=None, **opts):
+    Xo = X if dtype == torch.float64 else X.astype(np.float32).astype(np.float64)
+    info = {}
+    Uo, so, Vto, ro = oracle.hsvd_gram(Xo, p, q, k, tol, refine=refine, refine_eps=refine_eps, info=info)
+    Xt = torch.tensor(X, dtype=dtype, device=DEV)
+    plan = H.Plan(X.shape[0], X.shape[1], p, q, k, tol, gram=True, refine_steps=refine,
+                  refine_eps=refine_eps or 0.0,
+                  precision=H.FP64 if dtype == torch.float64 else H.FP32, **opts)
+    U = torch.empty((X.shape[0], k), dtype=dtype, device=DEV)
+    S = torch.empty((k,), dtype=dtype, device=DEV)
+    Vt = torch.empty((k, X.shape[1]), dtype=dtype, device=DEV)
+    plan.execute(Xt, U, S, Vt)
+    rg = plan.rank()
+    assert plan.status() & 0xFFFF == 0
+    if refine_eps:
+        assert plan.refine_iterations() == info["refine_iterations"]
+    plan.close()
+    Ug, sg, Vtg = (t.double().cpu().numpy() for t in (U, S, Vt))
+    assert rg == ro, (rg, ro)
+    c = metrics.compare(Ug, sg, Vtg, rg, Uo, so, Vto, ro)
+    print(f"gram {X.shape} {p}x{q} k={k}", c, flush=True)
+    assert c["e_sigma"] <= gate and c["e_frob"] <= gate
+    assert np.all(sg[rg:] == 0) and np.all(Ug[:, rg:] == 0) and np.all(Vtg[rg:] == 0)
+    for i in range(rg):
+        j = np.argmax(np.abs(Ug[:, i]))
+        assert Ug[j, i] > 0
+    return c
+
+
+@pytest.mark.parametrize("m,n,p,q,k", [(3000, 300, 3, 2, 12), (20000, 256, 4, 4, 25),
+                                       (700, 200, 2, 3, 10), (150, 400, 4, 4, 16)])
+def test_gram_parity_fp64(m, n, p, q, k):
+    """Gram plans (X^T X formed on the device, trees on it, projection of X) against the
+    oracle's Gram reading: tall X with several row chunks of partial Grams, an n that is
+    not a multiple of the 64-wide Gram tiles, and a short-fat X whose Gram is rank-deficient."""
+    rng = np.random.default_rng(m + n + k)
+    sigma = 10.0 ** (-np.arange(k) / (k / 3.0))
+    X, *_ = synth.low_rank(rng, m, n, sigma, noise=1e-9)
+    c = check_gram(X, p, q, k)
+    assert c["sin_u"] <= 1e-8 and c["sin_v"] <= 1e-8
+
+
+def test_gram_tol_refinement_and_float32():
+    """tol on X^T X's values, Algorithm 2 on X (fixed count and to a tolerance), and the
+    float32-storage path of a Gram plan."""
+    rng = np.random.default_rng(41)
+    X, *_ = synth.low_rank(rng, 2500, 320, 10.0 ** (-np.arange(20) / 4.0), noise=1e-6)
+    check_gram(X, 2, 4, 20, tol=1e-6)
+    check_gram(X, 4, 4, 12, refine=2)
+    check_gram(X, 4, 4, 12, refine=6, refine_eps=1e-6)
+    check_gram(X, 2, 2, 12, dtype=torch.float32, gate=1e-5)
+
+
+def test_gram_plan_reuse_and_errors():
+    """A Gram plan re-forms X^T X on every execute (a second input of the same shape
+    gives that input's factors); mixed precision is refused."""
+    rng = np.random.default_rng(43)
+    plan = H.Plan(1200, 256, 2, 2, 10, gram=True)
+    outs = []
+    for s in (0, 1):
+        X, *_ = synth.low_rank(rng, 1200, 256, (1.0 + s) * 10.0 ** (-np.arange(10) / (3.0 + s)), noise=1e-8)
+        U = torch.empty((1200, 10), dtype=torch.float64, device=DEV)
+        S = torch.empty((10,), dtype=torch.float64, device=DEV)
+        Vt = torch.empty((10, 256), dtype=torch.float64, device=DEV)
+        plan.execute(torch.tensor(X, device=DEV), U, S, Vt)
+        torch.cuda.synchronize()
+        so = oracle.hsvd_gram(X, 2, 2, 10)[1]
+        assert np.max(np.abs(S.cpu().numpy() - so)) <= 1e-9 * so[0]
+        outs.append(S.cpu().numpy())
+    assert np.max(np.abs(outs[0] - outs[1])) > 1e-3
+    plan.close()
+    with pytest.raises(H.HsvdError):
+        H.Plan(1200, 256, 2, 2, 10, gram=True, precision=H.MIXED_BF16)
+    with pytest.raises(H.HsvdError):
+        H.Plan(1200, 256, 300, 2, 10, gram=True)

@@ -661,3 +661,102 @@ def test_randomised_leaf_power_steps_converge():
             for q in range(5)]
     assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1]
     assert errs[4] <= 1e-13
+
+
+# ----------------------------------------------------------------------------- opposite merge order
+def test_cols_last_is_rows_last_of_the_transpose():
+    """The opposite order of the two sets of merges on A is Algorithm 1 on A^T with the
+    roles of U and V exchanged (Section 3: either order gives the singular values and
+    one side's vectors): equal to rounding on an inexact input, ragged grid."""
+    rng = np.random.default_rng(21)
+    A, *_ = synth.low_rank(rng, 300, 500, 10.0 ** (-np.arange(12) / 4.0), noise=1e-7)
+    U, s, Vt, r = oracle.hsvd(A, 3, 4, 12, 0.0, order="cols_last")
+    Ut, st, Vtt, rt = oracle.hsvd(A.T, 4, 3, 12, 0.0)
+    c = metrics.compare(U, s, Vt, r, Vtt.T, st, Ut.T, rt)
+    assert r == rt == 12
+    assert c["e_sigma"] <= 1e-14 and c["e_frob"] <= 1e-13
+    assert c["sin_u"] <= 1e-12 and c["sin_v"] <= 1e-12
+    # and it is a different approximation from Algorithm 1's on the same inexact input
+    c2 = metrics.compare(U, s, Vt, r, *oracle.hsvd(A, 3, 4, 12, 0.0))
+    assert c2["sin_u"] > 1e-12
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (2, 3), (5, 2), (8, 8), (3, 1), (1, 5)])
+def test_cols_last_exact_recovery(p, q):
+    """Exactly low-rank input (rank 6 < k): the opposite order recovers the singular
+    values and both subspaces to rounding, for grids with odd carries both ways."""
+    rng = np.random.default_rng(100 + 10 * p + q)
+    A, U0, s0, V0 = synth.low_rank(rng, 400, 320, np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.1]))
+    U, s, Vt, r = oracle.hsvd(A, p, q, 10, 0.0, order="cols_last")
+    assert r == 6
+    assert metrics.e_sigma(s[:r], s0) <= 1e-12
+    assert metrics.sin_theta(U[:, :r], U0) <= 1e-12 and metrics.sin_theta(Vt[:r].T, V0) <= 1e-12
+
+
+def test_cols_last_one_block_is_truncated_svd():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((60, 45))
+    U, s, Vt, r = oracle.hsvd(A, 1, 1, 7, 0.0, order="cols_last")
+    Ul, sl, Vlt = np.linalg.svd(A, full_matrices=False)
+    assert r == 7
+    assert np.max(np.abs(s[:7] - sl[:7])) <= 1e-13 * sl[0]
+    assert metrics.sin_theta(U[:, :7], Ul[:, :7]) <= 1e-12
+
+
+# ----------------------------------------------------------------------------- Gram input
+def test_gram_one_block_is_truncated_svd():
+    """One block of X^T X: V-hat is X's top right singular subspace and the projection
+    of X gives X's own singular values (not their squares) and left vectors."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((80, 50))
+    U, s, Vt, r = oracle.hsvd_gram(X, 1, 1, 7)
+    Ul, sl, Vlt = np.linalg.svd(X, full_matrices=False)
+    assert r == 7
+    assert np.max(np.abs(s[:7] - sl[:7])) <= 1e-12 * sl[0]
+    assert metrics.sin_theta(U[:, :7], Ul[:, :7]) <= 1e-10
+    assert metrics.sin_theta(Vt[:7].T, Vlt[:7].T) <= 1e-10
+
+
+@pytest.mark.parametrize("p,q", [(2, 3), (5, 2), (8, 8), (3, 1)])
+def test_gram_exact_recovery(p, q):
+    """Exactly low-rank X (rank 6 < k): the blocks of X^T X are exactly low rank, so the
+    trees on it and the projection of X recover X's SVD to rounding."""
+    rng = np.random.default_rng(200 + 10 * p + q)
+    X, U0, s0, V0 = synth.low_rank(rng, 400, 320, np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.1]))
+    U, s, Vt, r = oracle.hsvd_gram(X, p, q, 10)
+    assert r == 6
+    assert metrics.e_sigma(s[:r], s0) <= 1e-12
+    assert metrics.sin_theta(U[:, :r], U0) <= 1e-10 and metrics.sin_theta(Vt[:r].T, V0) <= 1e-10
+
+
+def test_gram_tol_applies_to_squared_values():
+    """The truncation threshold is taken on X^T X's values, X's squared: tol = 1e-4 keeps
+    sigma_i >= 1e-2 sigma_1 (Section 4 sets gamma = 1e-4 on X^T X for this reason)."""
+    rng = np.random.default_rng(9)
+    s0 = np.array([1.0, 0.5, 0.1, 0.02, 0.005, 0.001])
+    X, *_ = synth.low_rank(rng, 300, 120, s0)
+    U, s, Vt, r = oracle.hsvd_gram(X, 2, 2, 6, 1e-4)
+    assert r == 4
+    assert np.max(np.abs(s[:4] - s0[:4])) <= 1e-12
+    assert np.all(s[4:] == 0.0)
+    assert oracle.hsvd(X, 2, 2, 6, 1e-4)[3] == 6          # the same tol on X keeps all six
+
+
+def test_gram_refinement_converges_to_truncated_svd():
+    """Algorithm 2 on X after the Gram tree: on an inexact input (blocks truncated) the
+    iterations converge to X's top-k SVD; the first iteration is tested against the
+    projection's values, so a loose eps stops after one."""
+    rng = np.random.default_rng(10)
+    X, *_ = synth.low_rank(rng, 400, 200, 10.0 ** (-np.arange(12) / 4.0), noise=1e-4)
+    Ul, sl, Vlt = np.linalg.svd(X, full_matrices=False)
+    U0, s0, Vt0, r0 = oracle.hsvd_gram(X, 4, 4, 8)
+    U, s, Vt, r = oracle.hsvd_gram(X, 4, 4, 8, refine=40)
+    assert r0 == r == 8
+    e0 = metrics.sin_theta(Vt0[:8].T, Vlt[:8].T)
+    assert e0 > 1e-8
+    assert np.max(np.abs(s[:8] - sl[:8])) <= 1e-12 * sl[0]
+    assert metrics.sin_theta(Vt[:8].T, Vlt[:8].T) <= 1e-10
+    assert metrics.sin_theta(U[:, :8], Ul[:, :8]) <= 1e-10
+    info = {}
+    oracle.hsvd_gram(X, 4, 4, 8, refine=5, refine_eps=0.5, info=info)
+    assert info["refine_iterations"] == 1
