@@ -52,7 +52,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c1_8192.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_mixed_16384.md")
 CSRC = os.path.join(ROOT, "paper_1710_02812_amd", "csrc")
 # sources each launch kind's kernel is built from (hash guards the traffic figure)
 KIND_SOURCES = {
@@ -62,7 +62,7 @@ KIND_SOURCES = {
     "gram": ["k_thin.hip"], "reduce": ["k_thin.hip"], "thin_nn": ["k_thin.hip"],
     "sum": ["k_thin.hip"], "core": ["k_core.hip", "house_qr.hpp"], "output": ["k_misc.hip"],
     "cholqr": ["k_cholqr.hip"], "panel_qr": ["k_panelqr.hip"], "check": ["k_misc.hip"],
-    "gemm_ax_f32": ["k_gemm_f32.hip"], "gemm_atx_f32": ["k_gemm_f32.hip"],
+    "gemm_ax_f32": ["k_gemm_f32.hip"], "gemm_atx_f32": ["k_gemm_f32.hip"], "gram_xtx": ["k_gemm.hip"],
     "energy": ["k_misc.hip"], "features": ["k_misc.hip"],
 }
 COMMON_SOURCES = ["device_common.hpp", "hsvd_internal.hpp"]
@@ -95,8 +95,8 @@ def parse():
     ap.add_argument("--noise", default="abs", choices=["abs", "rel"],
                     help="c2: abs = 1e-5 N(0,1) (the literal reading, cut in the noise bulk); rel = 1e-5 x "
                          "the signal's RMS entry (cut in the clean exp(-i/10) decay)")
-    ap.add_argument("--cpu-runs", type=int, default=3,
-                    help="c2: oracle sample runs at BLAS threads = physical cores (one more at 1 thread)")
+    ap.add_argument("--cpu-runs", type=int, default=5,
+                    help="c2: oracle sample runs at BLAS threads = physical cores, and as many at 1 thread")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -403,6 +403,19 @@ def cpu_facts() -> dict:
     return facts
 
 
+def stage_flops(m, n, p, q, k):
+    """Flops of the oracle's stages by the Section 3.1 cost model (LAPACK-style SVD
+    6 h w^2 + 16 w^3 of an h x w block with h >= w, a merge at height h 14 h k^2 + 176 k^3)
+    on the whole job."""
+    br, bc = m / p, n / q
+    lo, hi = min(br, bc), max(br, bc)
+    return {"leaves": p * q * (6 * hi * lo * lo + 16 * lo ** 3),
+            "column_merges": p * (q - 1) * (14 * br * k * k + 176 * k ** 3),
+            "reprojection": p * (2 * k * br * n + 6 * n * k * k + 16 * k ** 3),
+            "row_merges": (p - 1) * (14 * n * k * k + 176 * k ** 3),
+            "projection": 2 * m * n * k + 6 * m * k * k + 16 * k ** 3}
+
+
 def oracle_stages(A, p, q, k, threads):
     """The oracle's stages on a bounded sample of the workload, at `threads` BLAS
     threads: row slab 0 in full (its q exact leaf SVDs, its column merge tree, its
@@ -530,22 +543,34 @@ def run_c2(args, torch):
     if not args.no_cpu_baseline:
         facts = cpu_facts()
         A64h = A32h.astype(np.float64)
-        runs = [oracle_stages(A64h, p, q, k, facts["physical_cores"]) for _ in range(max(1, args.cpu_runs))]
-        one = oracle_stages(A64h, p, q, k, 1)
+        nrun = max(1, args.cpu_runs)
+        runs = [oracle_stages(A64h, p, q, k, facts["physical_cores"]) for _ in range(nrun)]
+        ones = [oracle_stages(A64h, p, q, k, 1) for _ in range(nrun)]
         del A64h
         whole = np.array([r_["whole_s"] for r_ in runs]) * 1e3
+        whole1 = np.array([r_["whole_s"] for r_ in ones]) * 1e3
+        flops = stage_flops(m, n, p, q, k)
+
+        def stage_table(rs):
+            med = {kk: float(np.median([r_["stages_s"][kk] for r_ in rs])) for kk in rs[0]["stages_s"]}
+            return {kk: {"median_ms": round(v * 1e3, 1), "model_gflop": round(flops[kk] / 1e9, 2),
+                         "gflop_s": round(flops[kk] / v / 1e9, 1) if v > 0 else None} for kk, v in med.items()}
         cpu = {"value": round(float(whole.mean()), 1), "unit": "ms", "cores": facts["physical_cores"],
                "kind": "oracle",
                "sample": f"row slab 0 of {p} (its {q} exact leaf SVDs, column merge tree and re-projection), "
-                         f"one row merge and the projection, timed {len(runs)}x at "
-                         f"{facts['physical_cores']} BLAS threads and once at 1; slab stages scaled by {p}, "
-                         f"the row merge by {p - 1}",
+                         f"one row merge and the projection, timed {nrun}x at {facts['physical_cores']} "
+                         f"BLAS threads and {nrun}x at 1; slab stages scaled by {p}, the row merge by {p - 1}",
+               "mean_ms": round(float(whole.mean()), 1),
                "median_ms": round(float(np.median(whole)), 1),
                "runs_ms": [round(float(x), 1) for x in whole],
                "sample_s": round(float(np.mean([r_["sample_s"] for r_ in runs])), 2),
-               "stages_ms": {kk: round(v * 1e3, 1) for kk, v in runs[0]["stages_s"].items()},
-               "one_thread_ms": round(one["whole_s"] * 1e3, 1),
-               "one_thread_stages_ms": {kk: round(v * 1e3, 1) for kk, v in one["stages_s"].items()},
+               "stages": stage_table(runs),
+               "one_thread": {"mean_ms": round(float(whole1.mean()), 1),
+                              "median_ms": round(float(np.median(whole1)), 1),
+                              "runs_ms": [round(float(x), 1) for x in whole1],
+                              "stages": stage_table(ones)},
+               "flop_model": "Section 3.1 costs: a b_r x b_c block SVD 6 b_r b_c^2 + 16 b_c^3, a merge at "
+                             "height h 14 h k^2 + 176 k^3, a product 2 x (its multiply-adds)",
                "cpu": facts}
         progress(f"c2: oracle sample {cpu['value']:.0f} ms whole-job estimate")
 
