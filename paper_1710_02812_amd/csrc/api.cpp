@@ -75,6 +75,11 @@ struct Stage {
     int step = 0;        // leaf check: the power step it follows
     int need_r = 0;      // panel QR: R is formed
     int a64 = 0;         // passes over a float64 matrix held in the arena (the Gram matrix)
+    // > 0: the stage belongs to leaf class `branch` of a plan whose leaves have several
+    // sketch widths; the classes of a run of such stages are independent and run on
+    // streams of their own between a fork and a join
+    int branch = 0;
+    int done_slot = -1;  // leaf check: int-arena slot of its leaf class's "all converged"
 };
 
 int pow2floor(int x) {
@@ -118,9 +123,10 @@ struct hsvd_plan_st {
     hsvd_options opt{};
     int W = 0, L = 0, g = 0;       // panel width (max k), leaf sketch width, products per leaf
     // leaves' power steps until converged (power_steps = -1 on float64 plans): at most
-    // leaf_cap steps; iws[leaf_done] turns 1 once every leaf has passed its test, and the
-    // later steps' launches return at once (the slot is cleared at each execute)
-    int leaf_cap = 0, leaf_done = -1;
+    // leaf_cap steps; per class of leaves an int-arena slot turns 1 once every leaf of
+    // the class has passed its test, and the class's later steps return at once (the
+    // slot is cleared at each execute)
+    int leaf_cap = 0;
     std::vector<int> reset_slots;  // int-arena slots cleared at the start of each execute
     size_t reset_off = 0;          // their device copy in the task blob
 
@@ -160,6 +166,10 @@ struct hsvd_plan_st {
     int rm_refits = 0, rm_plain = 0;
     // the launch sequence captured on the first execute (opt.graph), replayed after
     hipStream_t cap_stream = nullptr;
+    int nbranch = 0;                          // leaf classes run concurrently (0: none)
+    std::vector<hipStream_t> bstreams;        // one per class
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 
@@ -427,6 +437,11 @@ void push_core(hsvd_plan_st& P, const std::vector<CoreTask>& tasks, int maxdim, 
     P.stages.push_back(s);
 }
 
+// The tree cores' orthogonality threshold: loose on mixed-precision plans.
+double tree_orth_tol(const hsvd_plan_st& P) {
+    return P.opt.precision == HSVD_MIXED_BF16 ? kMixedOrthTol : 0.0;
+}
+
 CoreTask core_defaults(const hsvd_plan_st& P, int k) {
     CoreTask c{};
     c.rank_in = -1;
@@ -537,6 +552,7 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         c.floor_rows = h;
         c.floor_cols = -1;
         c.precond = 1;
+        c.orth_tol = tree_orth_tol(P);
         cores.push_back(c);
         ApplyTask ap{};
         ap.tsqr = ti;
@@ -622,6 +638,7 @@ CoreTask leaf_core_task(hsvd_plan_st& P, const Leaf& l, int b, int w, int64_t r_
     c.floor_rows = (int)l.rowsz;
     c.floor_cols = (int)l.colsz;
     c.precond = 1;                // left vectors only: LQ of R first (fewer sweeps)
+    c.orth_tol = tree_orth_tol(P);
     if (P.energy_off >= 0 && l.mat == 0) {
         c.energy_off = P.energy_off + b;
         c.flag_slot = P.ialloc(1);
@@ -692,6 +709,9 @@ void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         gy.push_back(x);
     }
     const size_t checks_off = P.put(checks);
+    // this class's "every leaf has converged" slot (cleared at the start of an execute)
+    const int done = P.ialloc(1);
+    P.reset_slots.push_back(done);
     for (int t = 1; t <= P.leaf_cap; ++t) {
         const size_t first = P.stages.size();
         push_tsqr_apply(P, tby, aqy, w, ch, w);
@@ -706,9 +726,10 @@ void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
         s.n = (int)checks.size();
         s.tasks_off = checks_off;
         s.step = t;
+        s.done_slot = done;
         P.stages.push_back(s);
         if (t > 1)
-            for (size_t i = first; i < P.stages.size(); ++i) P.stages[i].guard = P.leaf_done;
+            for (size_t i = first; i < P.stages.size(); ++i) P.stages[i].guard = done;
     }
     push_tsqr_apply(P, tby, aout, w, ch, W);
 }
@@ -822,6 +843,19 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
     }
 }
 
+// Sketch width of a matrix of a batched plan: its own k + oversample (within its
+// smallest block side and the leaf kernels' limit), rounded up to a multiple of 8 so
+// that the batch has few width classes (each class is one pipeline of launches, the
+// classes run concurrently).
+int batch_width(const hsvd_plan_st& P, const MatDesc& M) {
+    int64_t bmin = INT64_MAX;
+    for (int i = 0; i < M.p; ++i) bmin = std::min(bmin, M.brow(i));
+    for (int j = 0; j < M.q; ++j) bmin = std::min(bmin, M.bcol(j));
+    const int lim = (int)std::min<int64_t>(bmin, kTsqrMaxW);
+    const int w = ((M.k + P.opt.oversample + 7) / 8) * 8;
+    return std::max(1, std::min(w, lim));
+}
+
 // Leaves of every block of every matrix.  Sketch width P.L for all, or the
 // per-block widths of a width plan (leaves grouped by width: one pipeline per
 // class).  Width plans first compute every block's energy for the leaf check.
@@ -838,7 +872,8 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
                 l.rowsz = M.brow(i);
                 l.colsz = M.bcol(j);
                 l.aoff = M.rs[i] * M.n + M.cs[j];
-                l.w = P.leaf_width.empty() ? P.L : P.leaf_width[(size_t)i * M.q + j];
+                l.w = !P.leaf_width.empty() ? P.leaf_width[(size_t)i * M.q + j]
+                      : P.ntree > 1 ? batch_width(P, M) : P.L;
                 leaves.push_back(l);
             }
     }
@@ -868,12 +903,16 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
         if (std::find(widths.begin(), widths.end(), l.w) == widths.end()) widths.push_back(l.w);
     std::sort(widths.begin(), widths.end());
     std::vector<Node> nodes(leaves.size());
-    for (int w : widths) {
+    for (size_t c = 0; c < widths.size(); ++c) {
         std::vector<int> ids;
         for (size_t b = 0; b < leaves.size(); ++b)
-            if (leaves[b].w == w) ids.push_back((int)b);
-        leaf_pipeline(P, leaves, ids, w, bcmax, nodes);
+            if (leaves[b].w == widths[c]) ids.push_back((int)b);
+        const size_t first = P.stages.size();
+        leaf_pipeline(P, leaves, ids, widths[c], bcmax, nodes);
+        if (widths.size() > 1)
+            for (size_t i = first; i < P.stages.size(); ++i) P.stages[i].branch = (int)c + 1;
     }
+    if (widths.size() > 1) P.nbranch = (int)widths.size();
     std::vector<std::vector<Node>> slabs;
     int prev_mat = -1, prev_i = -1;
     for (size_t b = 0; b < leaves.size(); ++b) {
@@ -934,6 +973,7 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
         c.m_off = tb.tasks[i].r_out;
         c.m_ld = W;
         c.rank_in = roots[i].rank;
+        c.orth_tol = tree_orth_tol(P);
         c.u_off = X;
         c.u_ld = W;
         c.sig_off = nd.sig;
@@ -1516,7 +1556,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
             }
             case ST_LEAFCHECK: {
                 const LeafCheck* T = (const LeafCheck*)(b + s.tasks_off);
-                if (P.leaf_done < 0 || P.leaf_done >= IW || s.step < 1) return "leaf check slot";
+                if (s.done_slot < 0 || s.done_slot >= IW || s.step < 1) return "leaf check slot";
                 for (int i = 0; i < s.n; ++i)
                     if (T[i].w < 1 || !span("leaf check sigma", T[i].sig_off, T[i].sig_off + T[i].w - 1, WS))
                         return T[i].w < 1 ? "leaf check width" : msg;
@@ -1641,7 +1681,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
                             P.opt.max_sweeps, P.flags, s.with_v, st, guard);
             break;
         case ST_LEAFCHECK:
-            e = launch_leaf_check(P.ws, P.iws, (const LeafCheck*)(b + s.tasks_off), s.n, s.step, P.leaf_done,
+            e = launch_leaf_check(P.ws, P.iws, (const LeafCheck*)(b + s.tasks_off), s.n, s.step, s.done_slot,
                                   guard, st);
             break;
         case ST_ENERGY:
@@ -1848,8 +1888,9 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         P->mats.push_back(std::move(M));
     }
     P->ntree = gram ? 1 : (int)P->mats.size();
-    // one panel width and one sketch width for the whole batch (per-matrix rank caps
-    // stay in the tasks)
+    // one panel width for the whole batch (per-matrix rank caps stay in the tasks);
+    // the sketch width of a single matrix (a batched plan's matrices take their own,
+    // batch_width)
     P->W = kmax;
     P->L = (int)std::min<int64_t>(lwant, bmin);
     if (P->L < 1) P->L = 1;
@@ -1859,11 +1900,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     // own rounding, and width plans take one step
     const bool converge = o.power_steps < 0 && o.precision == HSVD_FP64 && !leaf_width && kind == 0;
     P->g = 2 + (o.power_steps < 0 ? 1 : o.power_steps);
-    if (converge) {
-        P->leaf_cap = kLeafPowerCap;
-        P->leaf_done = P->ialloc(1);
-        P->reset_slots.push_back(P->leaf_done);
-    }
+    if (converge) P->leaf_cap = kLeafPowerCap;
     P->kind = kind;
     if (leaf_width) {
         const MatDesc& M = P->mats[0];
@@ -1915,6 +1952,18 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
                           hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_gaussian(P->ws + P->omega_off, P->omega_count, o.seed, 0);
     if (e == hipSuccess) e = prepare_launches();
+    // streams and events of the concurrent leaf classes (default priority)
+    if (e == hipSuccess && P->nbranch > 0) {
+        e = hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming);
+        for (int b = 0; b < P->nbranch && e == hipSuccess; ++b) {
+            hipStream_t bs = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+            if (e == hipSuccess) P->bstreams.push_back(bs);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) P->join_ev.push_back(ev);
+        }
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { hsvd_destroy(P); return hip_fail(e, "plan initialisation"); }
     *out = P;
@@ -1977,14 +2026,44 @@ hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t
 }
 
 // Every launch of one execute (a plan not stopped on refine_eps), in order, on `stream`.
+// Stages [begin, end) on `stream`; a run of leaf-class stages (branch > 0) forks: each
+// class runs in order on its own stream after an event recorded on `stream`, and
+// `stream` waits for every class before the stage after the run (under graph capture
+// the classes become parallel branches of the graph).
+static hsvd_status run_stages(hsvd_plan_st& P, size_t begin, size_t end, hipStream_t stream) {
+    for (size_t i = begin; i < end;) {
+        if (P.stages[i].branch == 0 || P.bstreams.empty()) {
+            hsvd_status st = run_stage(P, P.stages[i], stream);
+            if (st != HSVD_OK) return st;
+            ++i;
+            continue;
+        }
+        size_t j = i;
+        while (j < end && P.stages[j].branch > 0) ++j;
+        hipError_t e = hipEventRecord(P.fork_ev, stream);
+        if (e != hipSuccess) return hip_fail(e, "fork");
+        for (int b = 1; b <= P.nbranch; ++b) {
+            hipStream_t bs = P.bstreams[(size_t)b - 1];
+            if ((e = hipStreamWaitEvent(bs, P.fork_ev, 0)) != hipSuccess) return hip_fail(e, "fork");
+            for (size_t k = i; k < j; ++k)
+                if (P.stages[k].branch == b) {
+                    hsvd_status st = run_stage(P, P.stages[k], bs);
+                    if (st != HSVD_OK) return st;
+                }
+            if ((e = hipEventRecord(P.join_ev[(size_t)b - 1], bs)) != hipSuccess) return hip_fail(e, "join");
+            if ((e = hipStreamWaitEvent(stream, P.join_ev[(size_t)b - 1], 0)) != hipSuccess) return hip_fail(e, "join");
+        }
+        i = j;
+    }
+    return HSVD_OK;
+}
+
 static hsvd_status enqueue_all(hsvd_plan_st& P, hipStream_t stream) {
     hipError_t e = launch_reset_state(P.flags, P.iws, (const int*)((unsigned char*)P.dblob + P.reset_off),
                                       (int)P.reset_slots.size(), stream);
     if (e != hipSuccess) return hip_fail(e, "state reset");
-    for (size_t i = 0; i < P.stages.size(); ++i) {
-        hsvd_status st = run_stage(P, P.stages[i], stream);
-        if (st != HSVD_OK) return st;
-    }
+    hsvd_status st0 = run_stages(P, 0, P.stages.size(), stream);
+    if (st0 != HSVD_OK) return st0;
     e = launch_output(P.opt.precision != HSVD_FP64, P.ws, P.iws,
                       (const OutputArgs*)((unsigned char*)P.dblob + P.outs_off), (int)P.outs.size(), P.kmax, P.mmax,
                       P.nmax, (void* const*)P.dptrs, stream);
@@ -2047,7 +2126,10 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
     if (e != hipSuccess) return hip_fail(e, "state reset");
     if (prof && (e = hipEventRecord(P.events[0], stream)) != hipSuccess) return hip_fail(e, "event");
     size_t outs_off = P.outs_off;
-    if (P.seg_end.empty()) {
+    if (P.seg_end.empty() && !prof) {
+        hsvd_status st = run_stages(P, 0, P.stages.size(), stream);
+        if (st != HSVD_OK) return st;
+    } else if (P.seg_end.empty()) {                // per-launch events: one stream, in order
         for (size_t i = 0; i < P.stages.size(); ++i) {
             hsvd_status st = run_stage(P, P.stages[i], stream);
             if (st != HSVD_OK) return st;
@@ -2060,10 +2142,9 @@ static hsvd_status execute_impl(hsvd_plan_st& P, const void* const* A, void* con
         const size_t nseg = P.seg_end.size();
         size_t i = 0, used = nseg;
         for (size_t t = 0; t < nseg; ++t) {
-            for (; i < P.seg_end[t]; ++i) {
-                hsvd_status st = run_stage(P, P.stages[i], stream);
-                if (st != HSVD_OK) return st;
-            }
+            hsvd_status st = run_stages(P, i, P.seg_end[t], stream);
+            if (st != HSVD_OK) return st;
+            i = P.seg_end[t];
             if (t + 1 == nseg) continue;
             e = launch_refine_check(P.ws, P.iws, (const RefineCheck*)((unsigned char*)P.dblob + P.check_off[t]),
                                     P.ntree, P.opt.refine_eps, P.check_slot, stream);
@@ -2336,6 +2417,9 @@ hsvd_status hsvd_destroy(hsvd_plan_t plan) {
     if (plan->gexec) hipGraphExecDestroy(plan->gexec);
     if (plan->graph) hipGraphDestroy(plan->graph);
     if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
+    for (hipStream_t bs : plan->bstreams) hipStreamDestroy(bs);
+    for (hipEvent_t ev : plan->join_ev) hipEventDestroy(ev);
+    if (plan->fork_ev) hipEventDestroy(plan->fork_ev);
     if (plan->rm_wplan) hsvd_destroy(plan->rm_wplan);
     if (plan->rm_features) hsvd_destroy(plan->rm_features);
     if (plan->rm_params) hipFree(plan->rm_params);

@@ -149,7 +149,17 @@ struct CoreTask {
     // >= 0: all singular values of the core (sorted, zero past its size), dim of them,
     // before truncation (the leaves' power-step convergence test reads them)
     int64_t sigall_off = -1;
+    // > 0: the sweeps stop once no pair has |g_a . g_b| > orth_tol |g_a| |g_b|; else the
+    // working-precision threshold max(rows, 1) 2^-52
+    double orth_tol = 0.0;
 };
+
+// Column-orthogonality threshold of the mixed-precision plans' tree cores (leaves,
+// merges, slab re-projections): their inputs carry bfloat16 rounding (2^-9 relative),
+// so sweeps past cosines of about sqrt(2^-52) change nothing the result can see; the
+// projection and Algorithm 2 cores, which set the output's orthonormality, keep the
+// working-precision threshold.
+constexpr double kMixedOrthTol = 1e-8;
 
 // ---------------------------------------------------------------- output
 struct OutputArgs {

@@ -220,7 +220,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     constexpr int gsz = 16;                         // lanes per pair: 64 groups cover nc <= 128
     const int grp = tid / gsz, gl = tid - grp * gsz;
     constexpr int TMAX = ROWS / gsz;                // rows per lane, unconditional (zero padded)
-    const double tol = (double)(nr > 1 ? nr : 1) * kEps;
+    const double tol = t.orth_tol > 0.0 ? t.orth_tol : (double)(nr > 1 ? nr : 1) * kEps;
     const double tol2 = tol * tol;
     // skip threshold: squared norm <= (1e-3)^2 of the cap-th largest squared norm
     constexpr double kSkip2 = 1e-6;
