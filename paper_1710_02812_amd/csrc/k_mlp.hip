@@ -171,28 +171,80 @@ __global__ __launch_bounds__(256) void k_mlp_predict(const float* __restrict__ m
 }
 
 // Squared Frobenius norm of each block (one work-group per GemmTask block).
-__global__ __launch_bounds__(256) void k_block_energy(const void* const* __restrict__ ptrs, int fp32,
-                                                      const GemmTask* __restrict__ tasks,
-                                                      double* __restrict__ ws, int64_t out_off) {
-    __shared__ double red[4];
-    const GemmTask t = tasks[blockIdx.x];
+// Energy ||A_b||_F^2 of every block, one 512-thread work-group per block.  The block is
+// read as a flat sequence of 16-byte vectors (4 floats or 2 doubles of one row) when its
+// rows allow it (and it has fewer than 2^31 of them), each thread keeping 8 in flight;
+// otherwise element by element.
+// Sums in float64, wave sums then one value per wave combined in wave order.
+constexpr int EN_THREADS = 512;
+constexpr int EN_UNROLL = 8;
+
+template <typename T, typename V, int PER>
+__device__ __forceinline__ double energy_vec(const T* base, int64_t lda, int rows, int cols) {
+    const int nv = cols / PER;                    // vectors per row
+    const int total = rows * nv;
     double s = 0.0;
-    for (int r = 0; r < t.rows; ++r) {
-        if (fp32) {
-            const float* row = (const float*)ptrs[4 * t.mat] + t.a_off + (int64_t)r * t.lda;
-            for (int c = threadIdx.x; c < t.cols; c += blockDim.x) {
-                const double v = row[c];
-                s = fma(v, v, s);
+    for (int e0 = threadIdx.x; e0 < total; e0 += EN_THREADS * EN_UNROLL) {
+        V v[EN_UNROLL];
+#pragma unroll
+        for (int u = 0; u < EN_UNROLL; ++u) {
+            const int e = e0 + u * EN_THREADS;
+            if (e < total) {
+                const int r = e / nv, c = e - r * nv;
+                v[u] = *(const V*)(base + (int64_t)r * lda + (int64_t)c * PER);
+            } else {
+                v[u] = V{};
             }
-        } else {
-            const double* row = (const double*)ptrs[4 * t.mat] + t.a_off + (int64_t)r * t.lda;
-            for (int c = threadIdx.x; c < t.cols; c += blockDim.x) s = fma(row[c], row[c], s);
         }
+#pragma unroll
+        for (int u = 0; u < EN_UNROLL; ++u)
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const double x = (double)v[u][q];
+                s = fma(x, x, s);
+            }
+    }
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ double energy_plain(const T* base, int64_t lda, int rows, int cols) {
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r)
+        for (int c = threadIdx.x; c < cols; c += EN_THREADS) {
+            const double x = (double)base[(int64_t)r * lda + c];
+            s = fma(x, x, s);
+        }
+    return s;
+}
+
+__global__ __launch_bounds__(EN_THREADS) void k_block_energy(const void* const* __restrict__ ptrs, int fp32,
+                                                             const GemmTask* __restrict__ tasks,
+                                                             double* __restrict__ ws, int64_t out_off) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    __shared__ double red[EN_THREADS / 64];
+    const GemmTask t = tasks[blockIdx.x];
+    double s;
+    if (fp32) {
+        const float* base = (const float*)ptrs[4 * t.mat] + t.a_off;
+        const bool vec = t.cols % 4 == 0 && t.lda % 4 == 0 && ((uintptr_t)base & 15) == 0 &&
+                         (int64_t)t.rows * (t.cols / 4) < ((int64_t)1 << 31) - EN_THREADS * EN_UNROLL;
+        s = vec ? energy_vec<float, f4, 4>(base, t.lda, t.rows, t.cols) : energy_plain(base, t.lda, t.rows, t.cols);
+    } else {
+        const double* base = (const double*)ptrs[4 * t.mat] + t.a_off;
+        const bool vec = t.cols % 2 == 0 && t.lda % 2 == 0 && ((uintptr_t)base & 15) == 0 &&
+                         (int64_t)t.rows * (t.cols / 2) < ((int64_t)1 << 31) - EN_THREADS * EN_UNROLL;
+        s = vec ? energy_vec<double, d2, 2>(base, t.lda, t.rows, t.cols) : energy_plain(base, t.lda, t.rows, t.cols);
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) ws[out_off + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < EN_THREADS / 64; ++w) tot += red[w];
+        ws[out_off + blockIdx.x] = tot;
+    }
 }
 
 // Features of block b from its sketch singular values (sig_off + 16 b, descending,
@@ -233,7 +285,7 @@ hipError_t launch_mlp_predict(const float* master, const float* X, int count, fl
 hipError_t launch_block_energy(const void* const* ptrs, int fp32, const GemmTask* tasks, int ntasks,
                                double* ws, int64_t out_off, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_block_energy, dim3(ntasks), dim3(256), 0, s, ptrs, fp32, tasks, ws, out_off);
+    hipLaunchKernelGGL(k_block_energy, dim3(ntasks), dim3(EN_THREADS), 0, s, ptrs, fp32, tasks, ws, out_off);
     return hipGetLastError();
 }
 
