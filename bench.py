@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=8192, help="matrix side (multiple of the block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1 (default): plans choose their launch-shape tunables at creation (untimed, "
+                         "reported as plan_s); 0: the defaults")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of one path only (for rocprofv3)")
@@ -137,7 +140,12 @@ def copy_probe(mib: int):
 
 def time_path(H, torch, A, prec, args, k=50, p=8, q=8, **opts):
     m, n = A.shape
+    if getattr(args, "autotune", False):
+        opts.setdefault("autotune", True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
     plan = H.Plan(m, n, p, q, k, 0.0, precision=prec, **opts)
+    plan_s = time.perf_counter() - tp
     dt = A.dtype
     U = torch.empty((m, k), dtype=dt, device=A.device)
     S = torch.empty((k,), dtype=dt, device=A.device)
@@ -155,7 +163,7 @@ def time_path(H, torch, A, prec, args, k=50, p=8, q=8, **opts):
     ms = t0.elapsed_time(t1) / args.steps
     flags = plan.status()
     r = plan.rank()
-    res = {"ms": ms, "flags": flags}
+    res = {"ms": ms, "flags": flags, "plan_s": round(plan_s, 3), "tuning": plan.tuning()}
     if getattr(args, "workload", "") == "c2":
         res["dev"] = (U.clone(), S.clone(), Vt.clone(), r)
     else:
@@ -609,6 +617,7 @@ def run_c2(args, torch):
         "per_step_ms": rmx["per_step"],
         "path_ms": {nm: round(r_["ms"], 4) for nm, r_ in paths.items()},
         "path_per_step_ms": {nm: r_["per_step"] for nm, r_ in paths.items()},
+        "plan": {nm: {"plan_s": r_["plan_s"], **r_["tuning"]} for nm, r_ in paths.items()},
         "mixed_speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
         "fp64_comparator": "A held as float64 (the float32 matrix widened), one power step per leaf as on "
                            "the mixed path, all arithmetic float64",

@@ -113,6 +113,27 @@ typedef struct {
                                single matrix with m < n, so that the last tree and the
                                projection run on the shorter side, else ROWS_LAST.  Width
                                and feature plans are always ROWS_LAST.                  */
+    int32_t  thin_rows;     /* rows per chunk of the thin-panel products of the merges
+                               (partial Grams C = X^T Y, their sums, Y - X C): 0 (default:
+                               128) or a multiple of 64 in 64..1024.  Fewer, taller chunks
+                               mean fewer partial sums and fewer work-groups.           */
+    int32_t  merge_qr;      /* QR of the merge complements: bit 0 set, the column-merge
+                               levels (the first tree) factor them by the one-launch
+                               panel QR (one work-group per panel) instead of the
+                               multi-work-group Cholesky QR; bit 1, the same for the
+                               row-merge levels.  Default 0.                             */
+    int32_t  autotune;      /* 1: hsvd_plan_ex / hsvd_plan_batched / hsvd_plan_gram choose
+                               thin_rows and merge_qr themselves: each candidate plan
+                               executes on a Gaussian input of the plan's shapes (three
+                               timed executes after a warm-up, the median compared), one
+                               tunable at a time starting from the defaults, the fastest
+                               kept.  The choice is cached for the process under a key of
+                               the shapes, grid, k, options and device, and appended to
+                               the file named by the environment variable HSVD_TUNE_CACHE
+                               (read at the first autotuned plan) when it is set.  Needs
+                               device memory for the candidates and the input while the
+                               plan is made; its results are those of a plan made with the
+                               chosen values.  Default 0.                               */
 } hsvd_options;
 
 #define HSVD_ORDER_AUTO 0
@@ -213,6 +234,13 @@ hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count);
  * hold the HSVD_FLAG_* conditions, bits 16..31 the largest number of Jacobi sweeps
  * any core of that execute ran. */
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
+
+/* The thin_rows and merge_qr a plan runs with (the defaults resolved: thin_rows 128
+ * when 0) and, for an autotuned plan, the median execute time (ms) of the chosen
+ * candidate during tuning (0 when it was not tuned, or when the choice came from the
+ * cache with no time recorded).  Any pointer may be NULL.  Host only.            */
+hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* tuned,
+                            float* tuned_ms);
 
 /* Bytes of the plan's device workspace: its float64 arena (panels, scratch, the
  * leaves' Gaussian test matrices) and its int arena (ranks, counters, flags), as

@@ -29,8 +29,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <random>
@@ -106,6 +111,9 @@ struct MatDesc {
     int64_t bcol(int j) const { return cs[j + 1] - cs[j]; }
 };
 
+// Values chosen by the plan-time autotuner (0: the defaults).
+struct Tuning { int thin_rows = 0, merge_qr = 0; float ms = 0.0f; };
+
 struct hsvd_plan_st {
     std::vector<MatDesc> mats;     // one for hsvd_plan, count for hsvd_plan_batched
     int kind = 0;                  // 0: SVD plan, 1: block-feature plan
@@ -166,6 +174,11 @@ struct hsvd_plan_st {
     int rm_refits = 0, rm_plain = 0;
     // the launch sequence captured on the first execute (opt.graph), replayed after
     hipStream_t cap_stream = nullptr;
+    int thin_ch = THIN_CH;                    // rows per chunk of the thin products
+    int merge_qr = 0;                         // bit 0 / bit 1: panel QR in column / row merges
+    bool merging_rows = false;                // build time: the row-merge tree is being built
+    int tuned = 0;                            // 1: thin_ch and merge_qr came from the autotuner
+    float tuned_ms = 0.0f;                    // its median execute time (ms)
     int nbranch = 0;                          // leaf classes run concurrently (0: none)
     std::vector<hipStream_t> bstreams;        // one per class
     hipEvent_t fork_ev = nullptr;
@@ -412,7 +425,7 @@ void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int 
 void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks) {
     std::vector<ChunkRef> chunks;
     for (size_t t = 0; t < tasks.size(); ++t) {
-        tasks[t].nch = (tasks[t].h + THIN_CH - 1) / THIN_CH;
+        tasks[t].nch = (tasks[t].h + P.thin_ch - 1) / P.thin_ch;
         tasks[t].chunk0 = (int)chunks.size();
         if (kind != ST_REDUCE)
             for (int c = 0; c < tasks[t].nch; ++c) chunks.push_back({(int)t, c});
@@ -502,7 +515,7 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         const Node& a = pr.first;
         const Node& b = pr.second;
         const int h = a.h;
-        const int nch = (h + THIN_CH - 1) / THIN_CH;
+        const int nch = (h + P.thin_ch - 1) / P.thin_ch;
         const int64_t part = P.alloc((int64_t)nch * W * W);
         const int64_t C1 = P.alloc((int64_t)W * W), C2 = P.alloc((int64_t)W * W);
         const int64_t Cacc = P.alloc((int64_t)W * W);
@@ -529,7 +542,9 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         sb2.c_off = C2;
         sub2.push_back(sb2);
 
-        const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq, true);
+        // the complement's QR: Cholesky QR, or the one-launch panel QR (explicit Q)
+        const bool pq = ((P.merge_qr >> (P.merging_rows ? 1 : 0)) & 1) && W <= kPanelQrMaxW;
+        const int ti = add_tsqr(P, tb, b.panel, h, b.ld, W, chq, !pq, pq ? P.alloc((int64_t)h * W) : -1, h);
         Node o{};
         o.mat = a.mat;
         o.h = h;
@@ -1216,8 +1231,10 @@ void build_gram(hsvd_plan_st& P) {
 hsvd_status build_plan(hsvd_plan_st& P) {
     if (P.gram) build_gram(P);
     auto slabs = build_leaves(P);
+    P.merging_rows = false;
     auto col_roots = merge_forest(P, slabs);
     auto row_forests = build_reprojection(P, col_roots);
+    P.merging_rows = true;
     auto row_roots = merge_forest(P, row_forests);
     if (P.gram)                                   // V-hat of G = X^T X is X's: project against X
         for (Node& r : row_roots) r.mat = 1;
@@ -1663,18 +1680,18 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             break;
         case ST_GRAM:
             e = launch_thin_gram(P.ws, (const ThinTask*)(b + s.tasks_off),
-                                 (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+                                 (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st);
             break;
         case ST_REDUCE:
             e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, s.w, st);
             break;
         case ST_NN:
             e = launch_thin_nn(P.ws, P.iws, (const ThinTask*)(b + s.tasks_off),
-                               (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+                               (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st);
             break;
         case ST_SUM:
             e = launch_thin_sum(P.ws, (const ThinTask*)(b + s.tasks_off),
-                                (const ChunkRef*)(b + s.refs_off), s.n, THIN_CH, st);
+                                (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st);
             break;
         case ST_CORE:
             e = launch_core(P.ws, P.iws, (const CoreTask*)(b + s.tasks_off), s.n, s.maxdim,
@@ -1712,6 +1729,9 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->refine_eps = 0.0;
     opt->graph = 1;
     opt->order = HSVD_ORDER_AUTO;
+    opt->thin_rows = 0;
+    opt->merge_qr = 0;
+    opt->autotune = 0;
     return HSVD_OK;
 }
 
@@ -1806,6 +1826,160 @@ static hipError_t prepare_launches() {
     return e;
 }
 
+// ---------------------------------------------------------------- plan-time autotuning
+// The tunables (thin_rows, merge_qr) change how the work is cut into launches, never
+// the arithmetic of a result's entries beyond the order of float64 sums.  Candidates are
+// timed as whole executes on a Gaussian input of the plan's shapes; the choice is kept
+// per (device, plan kind, options, shapes) for the process and, with HSVD_TUNE_CACHE
+// set, in that file (one line per key: hash, thin_rows, merge_qr, median ms).
+namespace {
+std::mutex g_tune_mu;
+std::map<uint64_t, Tuning> g_tune;
+bool g_tune_file_read = false;
+
+uint64_t tune_key(int32_t count, const int64_t* ms, const int64_t* ns, const int32_t* ps, const int32_t* qs,
+                  const int32_t* ks, double tol, const hsvd_options& o, int kind) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipGetDeviceProperties(&prop, dev);
+    std::string k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    char buf[256];
+    snprintf(buf, sizeof buf, "|%d|%d,%d,%d,%d,%d,%d,%d,%.17g", kind, o.precision, o.rule, o.oversample,
+             o.power_steps, o.refine_steps, o.order, o.graph, tol);
+    k += buf;
+    for (int i = 0; i < count; ++i) {
+        snprintf(buf, sizeof buf, "|%lldx%lld:%dx%d:%d", (long long)ms[i], (long long)ns[i], ps[i], qs[i], ks[i]);
+        k += buf;
+    }
+    uint64_t h = 1469598103934665603ull;          // FNV-1a, 64 bit
+    for (unsigned char c : k) { h ^= c; h *= 1099511628211ull; }
+    return h;
+}
+
+void tune_file_read() {
+    const char* path = std::getenv("HSVD_TUNE_CACHE");
+    if (!path || g_tune_file_read) return;
+    g_tune_file_read = true;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string hex;
+        Tuning t{};
+        if (!(is >> hex >> t.thin_rows >> t.merge_qr >> t.ms)) continue;
+        if (t.thin_rows != 0 && (t.thin_rows < 64 || t.thin_rows > 1024 || t.thin_rows % 64)) continue;
+        if (t.merge_qr < 0 || t.merge_qr > 3) continue;
+        g_tune[std::stoull(hex, nullptr, 16)] = t;
+    }
+}
+
+void tune_file_append(uint64_t key, const Tuning& t) {
+    const char* path = std::getenv("HSVD_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    char buf[96];
+    snprintf(buf, sizeof buf, "%016llx %d %d %.4f\n", (unsigned long long)key, t.thin_rows, t.merge_qr, t.ms);
+    f << buf;
+}
+}  // namespace
+
+static hsvd_status autotune(int32_t count, const int64_t* ms, const int64_t* ns, const int32_t* ps,
+                            const int32_t* qs, const int32_t* ks, double tol, const hsvd_options& o, int kind,
+                            Tuning* out) {
+    const uint64_t key = tune_key(count, ms, ns, ps, qs, ks, tol, o, kind);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_file_read();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *out = it->second;
+            return HSVD_OK;
+        }
+    }
+    // a Gaussian input and outputs for every matrix, in the plan's element type
+    const bool f32 = o.precision != HSVD_FP64;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    const int nmat = count;
+    std::vector<void*> bufs;
+    auto release = [&]() { for (void* b : bufs) hipFree(b); bufs.clear(); };
+    std::vector<const void*> A(nmat);
+    std::vector<void*> U(nmat), S(nmat), V(nmat);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nmat && e == hipSuccess; ++i) {
+        void *a = nullptr, *u = nullptr, *sv = nullptr, *v = nullptr;
+        e = hipMalloc(&a, es * (size_t)ms[i] * ns[i]);
+        if (e == hipSuccess) bufs.push_back(a);
+        if (e == hipSuccess && (e = hipMalloc(&u, es * (size_t)ms[i] * ks[i])) == hipSuccess) bufs.push_back(u);
+        if (e == hipSuccess && (e = hipMalloc(&sv, es * (size_t)ks[i])) == hipSuccess) bufs.push_back(sv);
+        if (e == hipSuccess && (e = hipMalloc(&v, es * (size_t)ks[i] * ns[i])) == hipSuccess) bufs.push_back(v);
+        if (e == hipSuccess)
+            e = f32 ? launch_gaussian_f32((float*)a, ms[i] * ns[i], 0x7417ull + (uint64_t)i, 0)
+                    : launch_gaussian((double*)a, ms[i] * ns[i], 0x7417ull + (uint64_t)i, 0);
+        A[i] = a; U[i] = u; S[i] = sv; V[i] = v;
+    }
+    hipStream_t st = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release();
+        if (st) hipStreamDestroy(st);
+        return hip_fail(e, "autotune set-up");
+    }
+    hipEvent_t ev[4] = {};
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    // median of three timed executes after one warm-up; a candidate the plan builder or
+    // the device rejects scores +inf
+    auto run = [&](int thin_rows, int merge_qr) -> float {
+        hsvd_options c = o;
+        c.autotune = 0;
+        c.thin_rows = thin_rows;
+        c.merge_qr = merge_qr;
+        hsvd_plan_t cp = nullptr;
+        if (plan_impl(&cp, count, ms, ns, ps, qs, ks, tol, &c, nullptr, nullptr, kind, false) != HSVD_OK)
+            return INFINITY;
+        auto exec = [&]() -> bool {
+            if (nmat == 1)
+                return hsvd_execute(cp, A[0], U[0], S[0], V[0], st) == HSVD_OK;
+            return hsvd_execute_batched(cp, A.data(), U.data(), S.data(), V.data(), st) == HSVD_OK;
+        };
+        float t[3] = {INFINITY, INFINITY, INFINITY};
+        bool ok = exec() && hipStreamSynchronize(st) == hipSuccess;
+        for (int r = 0; r < 3 && ok; ++r) {
+            ok = hipEventRecord(ev[0], st) == hipSuccess && exec() && hipEventRecord(ev[1], st) == hipSuccess &&
+                 hipEventSynchronize(ev[1]) == hipSuccess && hipEventElapsedTime(&t[r], ev[0], ev[1]) == hipSuccess;
+        }
+        hsvd_destroy(cp);
+        if (!ok) return INFINITY;
+        std::sort(t, t + 3);
+        return t[1];
+    };
+    Tuning best{};
+    best.ms = (e == hipSuccess) ? run(0, 0) : INFINITY;
+    for (int tr : {256, 512}) {
+        const float x = run(tr, 0);
+        if (x < best.ms) { best.ms = x; best.thin_rows = tr; }
+    }
+    for (int bit : {1, 2}) {
+        const int mq = best.merge_qr | bit;
+        const float x = run(best.thin_rows, mq);
+        if (x < best.ms) { best.ms = x; best.merge_qr = mq; }
+    }
+    for (auto& x : ev)
+        if (x) hipEventDestroy(x);
+    hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+    release();
+    if (!std::isfinite(best.ms)) return fail(HSVD_ERR_HIP, "autotune: no candidate ran");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+        tune_file_append(key, best);
+    }
+    *out = best;
+    return HSVD_OK;
+}
+
 static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms, const int64_t* ns,
                              const int32_t* ps, const int32_t* qs, const int32_t* ks, double tol,
                              const hsvd_options* opt, size_t* check_only,
@@ -1842,11 +2016,26 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     if (!(o.refine_eps >= 0.0)) return fail(HSVD_ERR_INVALID, "need refine_eps >= 0");
     if (o.graph != 0 && o.graph != 1) return fail(HSVD_ERR_INVALID, "graph must be 0 or 1");
     if (o.order < HSVD_ORDER_AUTO || o.order > HSVD_ORDER_COLS_LAST) return fail(HSVD_ERR_INVALID, "unknown order");
+    if (o.thin_rows != 0 && (o.thin_rows < 64 || o.thin_rows > 1024 || o.thin_rows % 64))
+        return fail(HSVD_ERR_INVALID, "thin_rows must be 0 or a multiple of 64 in 64..1024");
+    if (o.merge_qr < 0 || o.merge_qr > 3) return fail(HSVD_ERR_INVALID, "merge_qr must be 0..3");
+    if (o.autotune != 0 && o.autotune != 1) return fail(HSVD_ERR_INVALID, "autotune must be 0 or 1");
 
+    Tuning tuned{};
+    if (o.autotune && !check_only && !host_only && kind != 1) {
+        hsvd_status st = autotune(count, ms, ns, ps, qs, ks, tol, o, kind, &tuned);
+        if (st != HSVD_OK) return st;
+        o.thin_rows = tuned.thin_rows;
+        o.merge_qr = tuned.merge_qr;
+    }
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
     P->tol = tol;
     P->opt = o;
+    P->thin_ch = o.thin_rows ? o.thin_rows : THIN_CH;
+    P->merge_qr = o.merge_qr;
+    P->tuned = (o.autotune && !check_only && !host_only && kind != 1) ? 1 : 0;
+    P->tuned_ms = tuned.ms;
     // merge order: column slabs last (the plan works on the transpose) when asked, or
     // automatically for a single short-fat matrix so that the last tree and the final
     // projection run on the shorter side; learned-width and feature plans keep the
@@ -2352,7 +2541,7 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                             f += 2.0 * h * (wx + wx2) * wy;
                             by += h * (wx + wx2 + 2.0 * wy) * e8;
                         } else if (s.kind == ST_REDUCE) {
-                            const double nch = (x.h + THIN_CH - 1) / THIN_CH;
+                            const double nch = (x.h + P.thin_ch - 1) / P.thin_ch;
                             f += nch * wx * wy;
                             by += (nch + 1.0) * wx * wy * e8;
                         } else {                              // wx partial products of h x wy
@@ -2499,6 +2688,16 @@ hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
     if (e == hipSuccess) e = hipMemcpy(fl, plan->flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hsvd_get_status");
     *flags_host = (fl[0] & 0xFFFFu) | (std::min(fl[1], 0xFFFFu) << 16);
+    return HSVD_OK;
+}
+
+hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* tuned,
+                            float* tuned_ms) {
+    if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
+    if (thin_rows) *thin_rows = plan->thin_ch;
+    if (merge_qr) *merge_qr = plan->merge_qr;
+    if (tuned) *tuned = plan->tuned;
+    if (tuned_ms) *tuned_ms = plan->tuned_ms;
     return HSVD_OK;
 }
 

@@ -271,6 +271,7 @@ hipError_t launch_block_energy(const void* const* ptrs, int fp32, const GemmTask
 hipError_t launch_block_features(const double* ws, int64_t sig_off, int64_t energy_off, int nblocks,
                                  float* out, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);
+hipError_t launch_gaussian_f32(float* out, int64_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // iws[out_slot] = 1 when every item has ||s_new - s_old||^2 <= eps^2 ||s_old||^2 over
 // its rank, else 0 (one work-group).

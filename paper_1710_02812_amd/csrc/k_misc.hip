@@ -25,8 +25,9 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
     return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-// out[e] ~ N(0, 1): Box-Muller on the Philox block of counter e/2.
-__global__ void k_gaussian(double* out, int64_t count, uint64_t seed) {
+// out[e] ~ N(0, 1): Box-Muller on the Philox block of counter e/2 (rounded to T).
+template <typename T>
+__global__ void k_gaussian(T* out, int64_t count, uint64_t seed) {
     const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (2 * pair >= count) return;
     const uint4 c = make_uint4((uint32_t)pair, (uint32_t)(pair >> 32), 0x5eedu, 0u);
@@ -36,8 +37,8 @@ __global__ void k_gaussian(double* out, int64_t count, uint64_t seed) {
     const double rad = sqrt(-2.0 * log(u1));
     double sn, cs;
     sincospi(2.0 * u2, &sn, &cs);
-    out[2 * pair] = rad * cs;
-    if (2 * pair + 1 < count) out[2 * pair + 1] = rad * sn;
+    out[2 * pair] = (T)(rad * cs);
+    if (2 * pair + 1 < count) out[2 * pair + 1] = (T)(rad * sn);
 }
 
 __global__ void k_fill(double* p, int64_t count, double v) {
@@ -129,7 +130,15 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ ws, 
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const int64_t pairs = (count + 1) / 2;
-    hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out,
+    hipLaunchKernelGGL(k_gaussian<double>, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out,
+                       count, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_gaussian_f32(float* out, int64_t count, uint64_t seed, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t pairs = (count + 1) / 2;
+    hipLaunchKernelGGL(k_gaussian<float>, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out,
                        count, seed);
     return hipGetLastError();
 }

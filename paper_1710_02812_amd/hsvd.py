@@ -35,7 +35,7 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_rank_model_predict",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
             "hsvd_debug_plan_check", "hsvd_svd_static", "hsvd_set_workspace", "hsvd_set_rank_model",
-            "hsvd_get_leaf_widths", "hsvd_plan_gram",
+            "hsvd_get_leaf_widths", "hsvd_plan_gram", "hsvd_get_tuning",
             "hsvd_debug_gemm",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
@@ -54,7 +54,9 @@ class Options(ctypes.Structure):
                 ("oversample", ctypes.c_int32), ("power_steps", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double),
-                ("graph", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("thin_rows", ctypes.c_int32), ("merge_qr", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 _lib = None
@@ -82,6 +84,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     L.hsvd_set_rank_model.argtypes = [vp, vp, ctypes.c_size_t]
     L.hsvd_plan_gram.argtypes = [P(vp), i64, i64, i32, i32, i32, f64, P(Options)]
+    L.hsvd_get_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(ctypes.c_float)]
     L.hsvd_get_leaf_widths.argtypes = [vp, P(i32), i32, P(i32), P(i32)]
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
@@ -160,14 +163,19 @@ class Plan:
                  precision: int = FP64, rule: int = RULE_GAMMA, oversample: int | None = None,
                  power_steps: int | None = None, refine_steps: int = 0,
                  max_sweeps: int | None = None, seed: int = 0, leaf_widths=None,
-                 refine_eps: float = 0.0, graph: bool = True, order: int = ORDER_AUTO, gram: bool = False):
+                 refine_eps: float = 0.0, graph: bool = True, order: int = ORDER_AUTO, gram: bool = False,
+                 thin_rows: int = 0, merge_qr: int = 0, autotune: bool = False):
         """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths);
         graph: replay a hipGraph captured on the first execute; order: ORDER_AUTO,
         ORDER_ROWS_LAST (Algorithm 1 as printed) or ORDER_COLS_LAST (the opposite order);
-        gram: decompose X^T X (p x q grid of the n x n Gram matrix; hsvd_plan_gram)."""
+        gram: decompose X^T X (p x q grid of the n x n Gram matrix; hsvd_plan_gram);
+        thin_rows, merge_qr: launch-shape tunables; autotune: let the plan time and pick them."""
         o = default_options()
         o.graph = 1 if graph else 0
         o.order = order
+        o.thin_rows = thin_rows
+        o.merge_qr = merge_qr
+        o.autotune = 1 if autotune else 0
         o.precision = precision
         o.rule = rule
         if oversample is not None:
@@ -211,6 +219,14 @@ class Plan:
         r = ctypes.c_int32()
         _check(lib().hsvd_get_rank(self._h, ctypes.byref(r)))
         return r.value
+
+    def tuning(self) -> dict:
+        """thin_rows, merge_qr the plan runs with; tuned, tuned_ms (hsvd_get_tuning)."""
+        tr, mq, tu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_float()
+        _check(lib().hsvd_get_tuning(self._h, ctypes.byref(tr), ctypes.byref(mq), ctypes.byref(tu),
+                                     ctypes.byref(ms)))
+        return {"thin_rows": tr.value, "merge_qr": mq.value, "tuned": bool(tu.value), "tuned_ms": ms.value}
 
     def refine_iterations(self) -> int:
         """Algorithm 2 iterations the last execute ran (hsvd_get_refine_iterations)."""

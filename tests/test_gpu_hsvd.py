@@ -555,3 +555,47 @@ def test_gram_plan_reuse_and_errors():
         H.Plan(1200, 256, 2, 2, 10, gram=True, precision=H.MIXED_BF16)
     with pytest.raises(H.HsvdError):
         H.Plan(1200, 256, 300, 2, 10, gram=True)
+
+
+# ----------------------------------------------------------------------------- launch-shape tunables
+@pytest.mark.parametrize("thin_rows,merge_qr", [(64, 0), (512, 0), (128, 1), (128, 2), (256, 3)])
+def test_tunables_keep_parity(thin_rows, merge_qr):
+    """Chunk rows of the thin products and the panel-QR merge path (column merges, row
+    merges, both) change the launch shapes only: every setting meets the float64 gate."""
+    rng = np.random.default_rng(60 + thin_rows + merge_qr)
+    A, *_ = synth.low_rank(rng, 1500, 1100, 10.0 ** (-np.arange(16) / 5.0), noise=1e-9)
+    check_parity(A, 3, 4, 16, thin_rows=thin_rows, merge_qr=merge_qr)
+
+
+def test_autotune_matches_an_explicit_plan(tmp_path, monkeypatch):
+    """An autotuned plan reports its choice, records it in HSVD_TUNE_CACHE, and gives the
+    same bits as a plan made with the chosen values; the result meets the gate."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HSVD_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(61)
+    A, *_ = synth.low_rank(rng, 2304, 1536, 10.0 ** (-np.arange(20) / 6.0), noise=1e-9)
+    At = torch.tensor(A, device=DEV)
+    m, n = A.shape
+    outs = []
+    tp = H.Plan(m, n, 4, 3, 20, autotune=True)
+    tu = tp.tuning()
+    print("tuning", tu, flush=True)
+    assert tu["tuned"] and tu["thin_rows"] in (128, 256, 512) and 0 <= tu["merge_qr"] <= 3
+    lines = cache.read_text().split("\n")
+    assert any(ln.split()[1:3] == [str(tu["thin_rows"] if tu["thin_rows"] != 128 else 0), str(tu["merge_qr"])]
+               for ln in lines if ln.strip())
+    ep = H.Plan(m, n, 4, 3, 20, thin_rows=tu["thin_rows"], merge_qr=tu["merge_qr"])
+    for plan in (tp, ep):
+        U = torch.empty((m, 20), dtype=torch.float64, device=DEV)
+        S = torch.empty((20,), dtype=torch.float64, device=DEV)
+        Vt = torch.empty((20, n), dtype=torch.float64, device=DEV)
+        plan.execute(At, U, S, Vt)
+        torch.cuda.synchronize()
+        outs.append((U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), plan.rank()))
+        plan.close()
+    assert outs[0][3] == outs[1][3]
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
+    Uo, so, Vto, ro = oracle.hsvd(A, 4, 3, 20)
+    c = metrics.compare(*outs[0], Uo, so, Vto, ro)
+    assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10
