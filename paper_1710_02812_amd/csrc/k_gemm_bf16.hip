@@ -15,13 +15,16 @@
 //     wave covers 512 contiguous bytes), transposed on the way into LDS by packing 8
 //     rows of a column into one 16-byte store, then read as A operands like X.
 // Slabs are double-buffered (one barrier per slab) and the next slab's global loads
-// are issued before the current slab's matrix-core work.  Work-groups are ordered so
-// that consecutive strips (the strips of one block, which share X) run on the same XCD.
+// are issued before the current slab's matrix-core work (op 0 keeps A one slab
+// ahead, X two: its panel comes through L2 from other XCDs' writes).  Work-groups
+// are ordered so that consecutive strips (the strips of one block, which share X) run
+// on the same XCD.
 //
 // MFMA 16x16x32 operand layout (lane l of 64): A fragment row l % 16, reduction
 // indices 8 (l / 16) .. 8 (l / 16) + 7; B fragment column l % 16, same reduction
 // indices; the 4 accumulators of lane l hold column l % 16, rows 4 (l / 16) + e.
 #include "hsvd_internal.hpp"
+#include <type_traits>
 
 namespace hsvd {
 
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(BT) void k_gemm_bf16(const void* const* __restrict_
     const double* X = ws + t.x_off;
     const int NT = (N + 15) >> 4;
     const int nslab = (K + BK - 1) / BK;
+    auto k_of = [&](int sl) { return sl * BK; };
 
     // ---- X slab: element e = (column c, k kk), kk fastest; 12 per thread at N = 96
     constexpr int XE = NMAX * BK / BT;
@@ -96,29 +100,7 @@ __global__ __launch_bounds__(BT) void k_gemm_bf16(const void* const* __restrict_
     };
 
     // ---- A operand
-    // op 0: per wave 2 row tiles x 2 k-steps of 8 floats (direct fragments)
-    float ar[2][2][8];
-    auto load_a0 = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int gr = r0 + 32 * wave + 16 * i + li;
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int gk = k0 + 32 * s + 8 * lq;
-                const float* src = Ab + (int64_t)gr * lda + gk;
-                if (gr < out_rows && gk + 8 <= K && ((uintptr_t)src & 15) == 0) {
-                    const f32x4 v0 = *(const f32x4*)src;
-                    const f32x4 v1 = *(const f32x4*)(src + 4);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) { ar[i][s][e] = v0[e]; ar[i][s][4 + e] = v1[e]; }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        ar[i][s][e] = (gr < out_rows && gk + e < K) ? src[e] : 0.0f;
-                }
-            }
-        }
-    };
+    // op 0: per wave 2 row tiles x 2 k-steps of 8 floats (direct fragments, below)
     // op 1: the slab of A is 64 rows x 256 columns; item (row group g of 8 rows, column
     // pair c2): 4 items per thread (8 row groups x 128 column pairs / 512 threads)
     constexpr int AI = (BK / 8) * (BM / 2) / BT;
@@ -162,36 +144,109 @@ __global__ __launch_bounds__(BT) void k_gemm_bf16(const void* const* __restrict_
 #pragma unroll
         for (int j = 0; j < NMAX / 16; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    load_x(0);
-    if (OP == 0) load_a0(0);
-    else load_a1(0);
+    if constexpr (OP == 0) {
+        // op 0 keeps two slabs of A in flight (A is the HBM stream; X comes from L2 and
+        // stays one slab ahead): slab sl + 2 is requested while slab sl is multiplied
+        float ar[2][2][8];                           // the next slab
+        auto load_to = [&](float (&dst)[2][2][8], int k0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int gr = r0 + 32 * wave + 16 * i + li;
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int gk = k0 + 32 * s2 + 8 * lq;
+                    const float* src = Ab + (int64_t)gr * lda + gk;
+                    if (gr < out_rows && gk + 8 <= K && ((uintptr_t)src & 15) == 0) {
+                        const f32x4 v0 = *(const f32x4*)src;
+                        const f32x4 v1 = *(const f32x4*)(src + 4);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) { dst[i][s2][e] = v0[e]; dst[i][s2][4 + e] = v1[e]; }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            dst[i][s2][e] = (gr < out_rows && gk + e < K) ? src[e] : 0.0f;
+                    }
+                }
+            }
+        };
+        // X (from L2, one pass-wide panel) two slabs ahead, A one slab ahead
+        double xq[XE];                               // X of the slab after next
+        auto load_xq = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < XE; ++u) {
+                const int e = tid + BT * u, c = e / BK, kk = e % BK;
+                const int gk = k0 + kk;
+                xq[u] = (c < N && gk < K) ? X[(int64_t)c * t.x_ld + gk] : 0.0;
+            }
+        };
+        auto store_xq = [&](__bf16* dst) {
+#pragma unroll
+            for (int u = 0; u < XE; ++u) {
+                const int e = tid + BT * u, c = e / BK, kk = e % BK;
+                dst[c * PK + kk] = (__bf16)(float)xq[u];
+            }
+        };
+        load_x(k_of(0));
+        load_to(ar, k_of(0));
+        store_x(Xs);
+        if (nslab > 1) load_x(k_of(1));
+        __syncthreads();
+        auto step = [&](auto bufc, int sl) {
+            constexpr int B = decltype(bufc)::value;   // xr holds slab sl + 1 when B == 0
+            const __bf16* xs = Xs + (sl & 1) * XS;
+            bf16x8 afr[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) afr[i][s2] = to_bf16x8(ar[i][s2]);
+            if (sl + 1 < nslab) load_to(ar, k_of(sl + 1));
+            if (sl + 2 < nslab) {
+                if (B == 0) load_xq(k_of(sl + 2));
+                else load_x(k_of(sl + 2));
+            }
+#pragma unroll
+            for (int j = 0; j < NMAX / 16; ++j) {
+                if (j < NT) {
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        const bf16x8 b = *(const bf16x8*)&xs[(16 * j + li) * PK + 32 * s2 + 8 * lq];
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[i][s2], b, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            if (sl + 1 < nslab) {
+                if (B == 0) store_x(Xs + ((sl & 1) ^ 1) * XS);
+                else store_xq(Xs + ((sl & 1) ^ 1) * XS);
+            }
+            __syncthreads();
+        };
+        for (int sl = 0; sl < nslab; sl += 2) {
+            step(std::integral_constant<int, 0>{}, sl);
+            if (sl + 1 < nslab) step(std::integral_constant<int, 1>{}, sl + 1);
+        }
+    } else {
+    load_x(k_of(0));
+    load_a1(k_of(0));
     store_x(Xs);
-    if (OP == 1) store_a1(As);
+    store_a1(As);
     __syncthreads();
     for (int sl = 0; sl < nslab; ++sl) {
         const int buf = sl & 1;
         const __bf16* xs = Xs + buf * XS;
         const __bf16* as = As + buf * AS;
         bf16x8 afr[2][2];
-        if (OP == 0) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int s = 0; s < 2; ++s) afr[i][s] = to_bf16x8(ar[i][s]);
-        }
         const bool more = sl + 1 < nslab;
         if (more) {                                  // next slab's loads in flight
-            load_x((sl + 1) * BK);
-            if (OP == 0) load_a0((sl + 1) * BK);
-            else load_a1((sl + 1) * BK);
+            load_x(k_of(sl + 1));
+            load_a1(k_of(sl + 1));
         }
-        if (OP == 1) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    afr[i][s] = *(const bf16x8*)&as[(32 * wave + 16 * i + li) * PK + 32 * s + 8 * lq];
-        }
+            for (int s = 0; s < 2; ++s)
+                afr[i][s] = *(const bf16x8*)&as[(32 * wave + 16 * i + li) * PK + 32 * s + 8 * lq];
 #pragma unroll
         for (int j = 0; j < NMAX / 16; ++j) {
             if (j < NT) {
@@ -206,9 +261,10 @@ __global__ __launch_bounds__(BT) void k_gemm_bf16(const void* const* __restrict_
         }
         if (more) {
             store_x(Xs + (buf ^ 1) * XS);
-            if (OP == 1) store_a1(As + (buf ^ 1) * AS);
+            store_a1(As + (buf ^ 1) * AS);
         }
         __syncthreads();
+    }
     }
     double* Y = ws + t.y_off;
 #pragma unroll

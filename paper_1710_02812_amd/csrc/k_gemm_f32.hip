@@ -16,6 +16,7 @@
 // both pitches put the 64 lanes of a read on distinct banks.  Accumulator element e of
 // lane l holds C[i = 4 (l / 16) + e][j = l % 16].
 #include "hsvd_internal.hpp"
+#include <type_traits>
 
 namespace hsvd {
 
@@ -59,11 +60,14 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
     const double* X = ws + t.x_off;
     const int NT = (N + 15) >> 4;
     const int nslab = (K + FK - 1) / FK;
+    auto k_of = [&](int sl) { return sl * FK; };
 
+    // Two slabs of A and X are in flight at once (registers hold slab sl + 1 and slab
+    // sl + 2 while slab sl is multiplied out of LDS): one slab's loads cover less than
+    // the loaded-memory latency at full bandwidth.
     // X slab: 32 x 96 elements, 6 per thread, k fastest
     constexpr int XE = FN * FK / FT;
-    double xr[XE];
-    auto load_x = [&](int k0) {
+    auto load_x = [&](double (&xr)[XE], int k0) {
 #pragma unroll
         for (int u = 0; u < XE; ++u) {
             const int e = tid + FT * u, c = e / FK, kk = e % FK;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
             xr[u] = (c < N && gk < K) ? X[(int64_t)c * t.x_ld + gk] : 0.0;
         }
     };
-    auto store_x = [&](float* dst) {
+    auto store_x = [&](const double (&xr)[XE], float* dst) {
 #pragma unroll
         for (int u = 0; u < XE; ++u) {
             const int e = tid + FT * u, c = e / FK, kk = e % FK;
@@ -80,8 +84,7 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
     };
     // A slab: 256 x 32 floats = 2048 float4, 4 per thread
     constexpr int AE = FM * FK / 4 / FT;
-    f32x4 ar[AE];
-    auto load_a = [&](int k0) {
+    auto load_a = [&](f32x4 (&ar)[AE], int k0) {
 #pragma unroll
         for (int u = 0; u < AE; ++u) {
             const int e = tid + FT * u;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
             ar[u] = v;
         }
     };
-    auto store_a = [&](float* dst) {
+    auto store_a = [&](const f32x4 (&ar)[AE], float* dst) {
 #pragma unroll
         for (int u = 0; u < AE; ++u) {
             const int e = tid + FT * u;
@@ -117,19 +120,30 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
 #pragma unroll
         for (int j = 0; j < FN / 16; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    load_x(0);
-    load_a(0);
-    store_x(Xs);
-    store_a(As);
+    double x0[XE], x1[XE];                      // X of slabs in flight (alternating)
+    f32x4 a0[AE], a1[AE];                       // A likewise
+    load_x(x0, k_of(0));
+    load_a(a0, k_of(0));
+    if (nslab > 1) {
+        load_x(x1, k_of(1));
+        load_a(a1, k_of(1));
+    }
+    store_x(x0, Xs);
+    store_a(a0, As);
     __syncthreads();
-    for (int sl = 0; sl < nslab; ++sl) {
-        const int buf = sl & 1;
-        const float* xs = Xs + buf * XSZ;
-        const float* as = As + buf * ASZ;
-        const bool more = sl + 1 < nslab;
-        if (more) {
-            load_x((sl + 1) * FK);
-            load_a((sl + 1) * FK);
+    // step sl: LDS buffer sl & 1 holds slab sl; registers set (sl + 1) & 1 hold slab sl + 1;
+    // the set sl & 1 (slab sl, already in LDS) is refilled with slab sl + 2
+    auto step = [&](auto setc, int sl) {
+        constexpr int B = decltype(setc)::value;
+        double (&xn)[XE] = B == 0 ? x0 : x1;
+        f32x4 (&an)[AE] = B == 0 ? a0 : a1;
+        const double (&xh)[XE] = B == 0 ? x1 : x0;
+        const f32x4 (&ah)[AE] = B == 0 ? a1 : a0;
+        const float* xs = Xs + B * XSZ;
+        const float* as = As + B * ASZ;
+        if (sl + 2 < nslab) {
+            load_x(xn, k_of(sl + 2));
+            load_a(an, k_of(sl + 2));
         }
 #pragma unroll
         for (int ks = 0; ks < FK / 4; ++ks) {
@@ -150,11 +164,15 @@ __global__ __launch_bounds__(FT) void k_gemm_f32(const void* const* __restrict__
                 }
             }
         }
-        if (more) {
-            store_x(Xs + (buf ^ 1) * XSZ);
-            store_a(As + (buf ^ 1) * ASZ);
+        if (sl + 1 < nslab) {
+            store_x(xh, Xs + (B ^ 1) * XSZ);
+            store_a(ah, As + (B ^ 1) * ASZ);
         }
         __syncthreads();
+    };
+    for (int sl = 0; sl < nslab; sl += 2) {
+        step(std::integral_constant<int, 0>{}, sl);
+        if (sl + 1 < nslab) step(std::integral_constant<int, 1>{}, sl + 1);
     }
     double* Y = ws + t.y_off;
 #pragma unroll
