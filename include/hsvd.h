@@ -122,8 +122,12 @@ typedef struct {
                                panel QR (one work-group per panel) instead of the
                                multi-work-group Cholesky QR; bit 1, the same for the
                                row-merge levels.  Default 0.                             */
+    int32_t  leaf_qr;       /* QR of the leaves' sketch and power panels: 0 (default) the
+                               one-launch panel QR when a launch has >= 128 panels, else
+                               the chunked Householder TSQR; 1 always the panel QR; 2
+                               always the TSQR.                                          */
     int32_t  autotune;      /* 1: hsvd_plan_ex / hsvd_plan_batched / hsvd_plan_gram choose
-                               thin_rows and merge_qr themselves: each candidate plan
+                               leaf_qr, thin_rows and merge_qr themselves: each candidate plan
                                executes on a Gaussian input of the plan's shapes (three
                                timed executes after a warm-up, the median compared), one
                                tunable at a time starting from the defaults, the fastest
@@ -235,12 +239,12 @@ hsvd_status hsvd_get_ranks(hsvd_plan_t plan, int32_t* r_host, int32_t count);
  * any core of that execute ran. */
 hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host);
 
-/* The thin_rows and merge_qr a plan runs with (the defaults resolved: thin_rows 128
- * when 0) and, for an autotuned plan, the median execute time (ms) of the chosen
- * candidate during tuning (0 when it was not tuned, or when the choice came from the
- * cache with no time recorded).  Any pointer may be NULL.  Host only.            */
-hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* tuned,
-                            float* tuned_ms);
+/* The thin_rows, merge_qr and leaf_qr a plan runs with (thin_rows resolved: 128 when
+ * 0), whether they came from the autotuner (*tuned = 1), and then the median execute
+ * time (ms) of the chosen candidate during tuning.  Any pointer may be NULL.  Host
+ * only.                                                                           */
+hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* leaf_qr,
+                            int32_t* tuned, float* tuned_ms);
 
 /* Bytes of the plan's device workspace: its float64 arena (panels, scratch, the
  * leaves' Gaussian test matrices) and its int arena (ranks, counters, flags), as

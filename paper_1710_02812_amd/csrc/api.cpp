@@ -112,7 +112,7 @@ struct MatDesc {
 };
 
 // Values chosen by the plan-time autotuner (0: the defaults).
-struct Tuning { int thin_rows = 0, merge_qr = 0; float ms = 0.0f; };
+struct Tuning { int thin_rows = 0, merge_qr = 0, leaf_qr = 0; float ms = 0.0f; };
 
 struct hsvd_plan_st {
     std::vector<MatDesc> mats;     // one for hsvd_plan, count for hsvd_plan_batched
@@ -176,6 +176,7 @@ struct hsvd_plan_st {
     hipStream_t cap_stream = nullptr;
     int thin_ch = THIN_CH;                    // rows per chunk of the thin products
     int merge_qr = 0;                         // bit 0 / bit 1: panel QR in column / row merges
+    int leaf_qr = 0;                          // leaves' QR: 0 by panel count, 1 panel QR, 2 TSQR
     bool merging_rows = false;                // build time: the row-merge tree is being built
     int tuned = 0;                            // 1: thin_ch and merge_qr came from the autotuner
     float tuned_ms = 0.0f;                    // its median execute time (ms)
@@ -242,10 +243,14 @@ struct TsqrBuild {
     bool pqr = false;        // some task takes the one-launch panel QR
 };
 
-// The one-launch panel QR (one work-group per panel) pays when there are enough panels
-// to fill the chip or they are short; a few tall panels keep the chunked TSQR.
-bool use_panel_qr(size_t npanels, int64_t hmax, int w) {
-    return w <= kPanelQrMaxW && (npanels >= 32 || hmax <= 2048);
+// The leaves' QR: the one-launch panel QR (one work-group per panel) pays when the
+// panels of a launch fill at least half the chip; fewer panels keep the chunked
+// Householder TSQR, whose chunks spread each panel over several work-groups
+// (hsvd_options.leaf_qr overrides the choice).
+bool use_panel_qr(const hsvd_plan_st& P, size_t npanels, int64_t hmax, int w) {
+    (void)hmax;
+    if (w > kPanelQrMaxW || P.leaf_qr == 2) return false;
+    return P.leaf_qr == 1 || npanels >= 128;
 }
 
 // Adds TSQR bookkeeping for a panel; returns index into tb.tasks.  cholqr: the panel
@@ -677,7 +682,7 @@ void leaf_converge(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
     TsqrBuild tby, tbz;
     int64_t hmax = 1;
     for (int b : ids) hmax = std::max({hmax, leaves[b].rowsz, leaves[b].colsz});
-    const bool pq = use_panel_qr(ids.size(), hmax, w);
+    const bool pq = use_panel_qr(P, ids.size(), hmax, w);
     for (size_t u = 0; u < ids.size(); ++u) {
         const Leaf& l = leaves[ids[u]];
         add_tsqr(P, tby, pan[u].Y, (int)l.rowsz, (int)l.rowsz, w, ch, false, pq ? pan[u].Qy : -1, (int)l.rowsz);
@@ -778,7 +783,7 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
     TsqrBuild tb_last;
     int64_t hmax = 1;
     for (int b : ids) hmax = std::max({hmax, leaves[b].rowsz, leaves[b].colsz});
-    const bool pq = use_panel_qr(ids.size(), hmax, w);
+    const bool pq = use_panel_qr(P, ids.size(), hmax, w);
     for (int t = 1; t <= g; ++t) {
         const bool prev_is_y = ((t - 1) % 2 == 0);
         TsqrBuild tb;
@@ -1731,6 +1736,7 @@ hsvd_status hsvd_default_options(hsvd_options* opt) {
     opt->order = HSVD_ORDER_AUTO;
     opt->thin_rows = 0;
     opt->merge_qr = 0;
+    opt->leaf_qr = 0;
     opt->autotune = 0;
     return HSVD_OK;
 }
@@ -1831,7 +1837,7 @@ static hipError_t prepare_launches() {
 // the arithmetic of a result's entries beyond the order of float64 sums.  Candidates are
 // timed as whole executes on a Gaussian input of the plan's shapes; the choice is kept
 // per (device, plan kind, options, shapes) for the process and, with HSVD_TUNE_CACHE
-// set, in that file (one line per key: hash, thin_rows, merge_qr, median ms).
+// set, in that file (one line per key: hash, thin_rows, merge_qr, leaf_qr, median ms).
 namespace {
 std::mutex g_tune_mu;
 std::map<uint64_t, Tuning> g_tune;
@@ -1866,9 +1872,9 @@ void tune_file_read() {
         std::istringstream is(line);
         std::string hex;
         Tuning t{};
-        if (!(is >> hex >> t.thin_rows >> t.merge_qr >> t.ms)) continue;
+        if (!(is >> hex >> t.thin_rows >> t.merge_qr >> t.leaf_qr >> t.ms)) continue;
         if (t.thin_rows != 0 && (t.thin_rows < 64 || t.thin_rows > 1024 || t.thin_rows % 64)) continue;
-        if (t.merge_qr < 0 || t.merge_qr > 3) continue;
+        if (t.merge_qr < 0 || t.merge_qr > 3 || t.leaf_qr < 0 || t.leaf_qr > 2) continue;
         g_tune[std::stoull(hex, nullptr, 16)] = t;
     }
 }
@@ -1878,7 +1884,8 @@ void tune_file_append(uint64_t key, const Tuning& t) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     char buf[96];
-    snprintf(buf, sizeof buf, "%016llx %d %d %.4f\n", (unsigned long long)key, t.thin_rows, t.merge_qr, t.ms);
+    snprintf(buf, sizeof buf, "%016llx %d %d %d %.4f\n", (unsigned long long)key, t.thin_rows, t.merge_qr,
+             t.leaf_qr, t.ms);
     f << buf;
 }
 }  // namespace
@@ -1930,11 +1937,12 @@ static hsvd_status autotune(int32_t count, const int64_t* ms, const int64_t* ns,
         if (e == hipSuccess) e = hipEventCreate(&x);
     // median of three timed executes after one warm-up; a candidate the plan builder or
     // the device rejects scores +inf
-    auto run = [&](int thin_rows, int merge_qr) -> float {
+    auto run = [&](int thin_rows, int merge_qr, int leaf_qr) -> float {
         hsvd_options c = o;
         c.autotune = 0;
         c.thin_rows = thin_rows;
         c.merge_qr = merge_qr;
+        c.leaf_qr = leaf_qr;
         hsvd_plan_t cp = nullptr;
         if (plan_impl(&cp, count, ms, ns, ps, qs, ks, tol, &c, nullptr, nullptr, kind, false) != HSVD_OK)
             return INFINITY;
@@ -1955,14 +1963,18 @@ static hsvd_status autotune(int32_t count, const int64_t* ms, const int64_t* ns,
         return t[1];
     };
     Tuning best{};
-    best.ms = (e == hipSuccess) ? run(0, 0) : INFINITY;
+    best.ms = (e == hipSuccess) ? run(0, 0, 0) : INFINITY;
+    for (int lq : {1, 2}) {
+        const float x = run(0, 0, lq);
+        if (x < best.ms) { best.ms = x; best.leaf_qr = lq; }
+    }
     for (int tr : {256, 512}) {
-        const float x = run(tr, 0);
+        const float x = run(tr, 0, best.leaf_qr);
         if (x < best.ms) { best.ms = x; best.thin_rows = tr; }
     }
     for (int bit : {1, 2}) {
         const int mq = best.merge_qr | bit;
-        const float x = run(best.thin_rows, mq);
+        const float x = run(best.thin_rows, mq, best.leaf_qr);
         if (x < best.ms) { best.ms = x; best.merge_qr = mq; }
     }
     for (auto& x : ev)
@@ -2019,6 +2031,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     if (o.thin_rows != 0 && (o.thin_rows < 64 || o.thin_rows > 1024 || o.thin_rows % 64))
         return fail(HSVD_ERR_INVALID, "thin_rows must be 0 or a multiple of 64 in 64..1024");
     if (o.merge_qr < 0 || o.merge_qr > 3) return fail(HSVD_ERR_INVALID, "merge_qr must be 0..3");
+    if (o.leaf_qr < 0 || o.leaf_qr > 2) return fail(HSVD_ERR_INVALID, "leaf_qr must be 0..2");
     if (o.autotune != 0 && o.autotune != 1) return fail(HSVD_ERR_INVALID, "autotune must be 0 or 1");
 
     Tuning tuned{};
@@ -2027,6 +2040,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         if (st != HSVD_OK) return st;
         o.thin_rows = tuned.thin_rows;
         o.merge_qr = tuned.merge_qr;
+        o.leaf_qr = tuned.leaf_qr;
     }
     hsvd_plan_st* P = new (std::nothrow) hsvd_plan_st();
     if (!P) return fail(HSVD_ERR_ALLOC, "host allocation failed");
@@ -2034,6 +2048,7 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
     P->opt = o;
     P->thin_ch = o.thin_rows ? o.thin_rows : THIN_CH;
     P->merge_qr = o.merge_qr;
+    P->leaf_qr = o.leaf_qr;
     P->tuned = (o.autotune && !check_only && !host_only && kind != 1) ? 1 : 0;
     P->tuned_ms = tuned.ms;
     // merge order: column slabs last (the plan works on the transpose) when asked, or
@@ -2691,11 +2706,12 @@ hsvd_status hsvd_get_status(hsvd_plan_t plan, uint32_t* flags_host) {
     return HSVD_OK;
 }
 
-hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* tuned,
-                            float* tuned_ms) {
+hsvd_status hsvd_get_tuning(hsvd_plan_t plan, int32_t* thin_rows, int32_t* merge_qr, int32_t* leaf_qr,
+                            int32_t* tuned, float* tuned_ms) {
     if (!plan) return fail(HSVD_ERR_INVALID, "plan is NULL");
     if (thin_rows) *thin_rows = plan->thin_ch;
     if (merge_qr) *merge_qr = plan->merge_qr;
+    if (leaf_qr) *leaf_qr = plan->leaf_qr;
     if (tuned) *tuned = plan->tuned;
     if (tuned_ms) *tuned_ms = plan->tuned_ms;
     return HSVD_OK;

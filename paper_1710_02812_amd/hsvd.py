@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("refine_eps", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("thin_rows", ctypes.c_int32), ("merge_qr", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("leaf_qr", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,7 +84,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     L.hsvd_set_rank_model.argtypes = [vp, vp, ctypes.c_size_t]
     L.hsvd_plan_gram.argtypes = [P(vp), i64, i64, i32, i32, i32, f64, P(Options)]
-    L.hsvd_get_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(ctypes.c_float)]
+    L.hsvd_get_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(ctypes.c_float)]
     L.hsvd_get_leaf_widths.argtypes = [vp, P(i32), i32, P(i32), P(i32)]
     L.hsvd_last_error.restype = ctypes.c_char_p
     L.hsvd_set_profiling.argtypes = [vp, i32]
@@ -164,7 +164,7 @@ class Plan:
                  power_steps: int | None = None, refine_steps: int = 0,
                  max_sweeps: int | None = None, seed: int = 0, leaf_widths=None,
                  refine_eps: float = 0.0, graph: bool = True, order: int = ORDER_AUTO, gram: bool = False,
-                 thin_rows: int = 0, merge_qr: int = 0, autotune: bool = False):
+                 thin_rows: int = 0, merge_qr: int = 0, leaf_qr: int = 0, autotune: bool = False):
         """leaf_widths: optional p x q per-block sketch widths (hsvd_plan_widths);
         graph: replay a hipGraph captured on the first execute; order: ORDER_AUTO,
         ORDER_ROWS_LAST (Algorithm 1 as printed) or ORDER_COLS_LAST (the opposite order);
@@ -175,6 +175,7 @@ class Plan:
         o.order = order
         o.thin_rows = thin_rows
         o.merge_qr = merge_qr
+        o.leaf_qr = leaf_qr
         o.autotune = 1 if autotune else 0
         o.precision = precision
         o.rule = rule
@@ -221,12 +222,13 @@ class Plan:
         return r.value
 
     def tuning(self) -> dict:
-        """thin_rows, merge_qr the plan runs with; tuned, tuned_ms (hsvd_get_tuning)."""
-        tr, mq, tu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """thin_rows, merge_qr, leaf_qr the plan runs with; tuned, tuned_ms (hsvd_get_tuning)."""
+        tr, mq, lq, tu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ms = ctypes.c_float()
-        _check(lib().hsvd_get_tuning(self._h, ctypes.byref(tr), ctypes.byref(mq), ctypes.byref(tu),
-                                     ctypes.byref(ms)))
-        return {"thin_rows": tr.value, "merge_qr": mq.value, "tuned": bool(tu.value), "tuned_ms": ms.value}
+        _check(lib().hsvd_get_tuning(self._h, ctypes.byref(tr), ctypes.byref(mq), ctypes.byref(lq),
+                                     ctypes.byref(tu), ctypes.byref(ms)))
+        return {"thin_rows": tr.value, "merge_qr": mq.value, "leaf_qr": lq.value, "tuned": bool(tu.value),
+                "tuned_ms": ms.value}
 
     def refine_iterations(self) -> int:
         """Algorithm 2 iterations the last execute ran (hsvd_get_refine_iterations)."""

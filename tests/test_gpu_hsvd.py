@@ -558,13 +558,15 @@ def test_gram_plan_reuse_and_errors():
 
 
 # ----------------------------------------------------------------------------- launch-shape tunables
-@pytest.mark.parametrize("thin_rows,merge_qr", [(64, 0), (512, 0), (128, 1), (128, 2), (256, 3)])
-def test_tunables_keep_parity(thin_rows, merge_qr):
-    """Chunk rows of the thin products and the panel-QR merge path (column merges, row
-    merges, both) change the launch shapes only: every setting meets the float64 gate."""
+@pytest.mark.parametrize("thin_rows,merge_qr,leaf_qr", [(64, 0, 0), (512, 0, 1), (128, 1, 2), (128, 2, 1),
+                                                         (256, 3, 2)])
+def test_tunables_keep_parity(thin_rows, merge_qr, leaf_qr):
+    """Chunk rows of the thin products, the panel-QR merge path (column merges, row
+    merges, both) and the leaves' QR (panel QR, chunked TSQR) change the launch shapes
+    only: every setting meets the float64 gate."""
     rng = np.random.default_rng(60 + thin_rows + merge_qr)
     A, *_ = synth.low_rank(rng, 1500, 1100, 10.0 ** (-np.arange(16) / 5.0), noise=1e-9)
-    check_parity(A, 3, 4, 16, thin_rows=thin_rows, merge_qr=merge_qr)
+    check_parity(A, 3, 4, 16, thin_rows=thin_rows, merge_qr=merge_qr, leaf_qr=leaf_qr)
 
 
 def test_autotune_matches_an_explicit_plan(tmp_path, monkeypatch):
@@ -582,9 +584,10 @@ def test_autotune_matches_an_explicit_plan(tmp_path, monkeypatch):
     print("tuning", tu, flush=True)
     assert tu["tuned"] and tu["thin_rows"] in (128, 256, 512) and 0 <= tu["merge_qr"] <= 3
     lines = cache.read_text().split("\n")
-    assert any(ln.split()[1:3] == [str(tu["thin_rows"] if tu["thin_rows"] != 128 else 0), str(tu["merge_qr"])]
+    assert any(ln.split()[1:4] == [str(tu["thin_rows"] if tu["thin_rows"] != 128 else 0), str(tu["merge_qr"]),
+                                   str(tu["leaf_qr"])]
                for ln in lines if ln.strip())
-    ep = H.Plan(m, n, 4, 3, 20, thin_rows=tu["thin_rows"], merge_qr=tu["merge_qr"])
+    ep = H.Plan(m, n, 4, 3, 20, thin_rows=tu["thin_rows"], merge_qr=tu["merge_qr"], leaf_qr=tu["leaf_qr"])
     for plan in (tp, ep):
         U = torch.empty((m, 20), dtype=torch.float64, device=DEV)
         S = torch.empty((20,), dtype=torch.float64, device=DEV)
