@@ -60,7 +60,8 @@ KIND_SOURCES = {
     "gemm_ax_bf16": ["k_gemm_bf16.hip"], "gemm_atx_bf16": ["k_gemm_bf16.hip"],
     "tsqr_factor": ["k_tsqr.hip", "house_qr.hpp"], "tsqr_apply": ["k_tsqr.hip"],
     "gram": ["k_thin.hip"], "reduce": ["k_thin.hip"], "thin_nn": ["k_thin.hip"],
-    "sum": ["k_thin.hip"], "core": ["k_core.hip", "house_qr.hpp"], "output": ["k_misc.hip"],
+    "sum": ["k_thin.hip"], "core": ["k_core.hip", "house_qr.hpp", "core_common.hpp"],
+    "core_wide": ["k_core_wide.hip", "core_common.hpp"], "output": ["k_misc.hip"],
     "cholqr": ["k_cholqr.hip"], "panel_qr": ["k_panelqr.hip"], "check": ["k_misc.hip"],
     "gemm_ax_f32": ["k_gemm_f32.hip"], "gemm_atx_f32": ["k_gemm_f32.hip"], "gram_xtx": ["k_gemm.hip"],
     "energy": ["k_misc.hip"], "features": ["k_misc.hip"],

@@ -157,6 +157,8 @@ hsvd_status hsvd_default_options(hsvd_options* opt);
 /* Creates a plan for an m x n input on a p x q grid, rank cap k, truncation tol.
  *   Requires 1 <= p <= m, 1 <= q <= n, 1 <= k <= min(m, n), 0 <= tol < 1, out != NULL.
  *   k may exceed a block side: leaf ranks are capped by min(block rows, block cols).
+ *   HSVD_ERR_UNSUPPORTED for k > 80 (the merge cores of this build hold 2k <= 160
+ *   columns; the leaves' sketch width is at most 80 columns).
  *   Allocates the device workspace on the current HIP device and generates the
  *   leaves' Gaussian test matrices there (synchronously).  Uses default options. */
 hsvd_status hsvd_plan(hsvd_plan_t* out, int64_t m, int64_t n, int32_t p, int32_t q,
@@ -284,7 +286,8 @@ typedef enum {
     HSVD_LAUNCH_PANEL_QR = 16,     /* leaf panels: repeated Cholesky QR, one group each  */
     HSVD_LAUNCH_GEMM_AX_F32 = 17,  /* Y = A_blk X on the float32 matrix cores (mixed)    */
     HSVD_LAUNCH_GEMM_ATX_F32 = 18, /* Y = A_blk^T X on the float32 matrix cores (mixed)  */
-    HSVD_LAUNCH_GRAM_XTX = 19      /* G = X^T X of a Gram plan (float64 matrix cores)    */
+    HSVD_LAUNCH_GRAM_XTX = 19,     /* G = X^T X of a Gram plan (float64 matrix cores)    */
+    HSVD_LAUNCH_CORE_WIDE = 20     /* Jacobi SVD of merge cores above 128 columns        */
 } hsvd_launch_kind;
 
 /* Turns per-launch timing on (1) or off (0) for later executes of this plan.

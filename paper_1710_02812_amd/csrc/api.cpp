@@ -514,7 +514,7 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
     std::vector<Node> outs;
     std::vector<ThinTask> gram1, red1, sub1, gram2, red2, sub2;
     TsqrBuild tb;
-    std::vector<CoreTask> cores;
+    std::vector<CoreTask> cores, wide;
     std::vector<ApplyTask> applies;
     for (const auto& pr : pairs) {
         const Node& a = pr.first;
@@ -573,7 +573,15 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         c.floor_cols = -1;
         c.precond = 1;
         c.orth_tol = tree_orth_tol(P);
-        cores.push_back(c);
+        // a core of two children of rank above kCoreMaxN / 2 may exceed the LDS-resident
+        // cores: such merges go to the wide cores, with a scratch panel each
+        if (2 * P.mats[a.mat].k > kCoreMaxN) {
+            c.precond = 0;
+            c.scr_off = P.alloc(kWideScratch);
+            wide.push_back(c);
+        } else {
+            cores.push_back(c);
+        }
         ApplyTask ap{};
         ap.tsqr = ti;
         ap.x_off = X;
@@ -593,7 +601,8 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
     push_thin(P, ST_REDUCE, red2);
     push_thin(P, ST_NN, sub2);
     push_tsqr_factor(P, tb, W, chq);
-    push_core(P, cores, 2 * W, 0);
+    if (!cores.empty()) push_core(P, cores, std::min(2 * W, kCoreMaxN), 0);
+    if (!wide.empty()) push_core(P, wide, 2 * W, 0);
     push_tsqr_apply(P, tb, applies, W, chq, W);
     return outs;
 }
@@ -1591,12 +1600,18 @@ std::string validate_plan(const hsvd_plan_st& P) {
             }
             case ST_CORE: {
                 const CoreTask* T = (const CoreTask*)(b + s.tasks_off);
-                if (s.maxdim > 128 || (s.with_v && s.maxdim > 64)) return "core size";
+                const bool wide = s.maxdim > kCoreMaxN;
+                if (s.maxdim < 1 || s.maxdim > kWideCoreMaxN || (s.with_v && s.maxdim > kCoreMaxV)) return "core size";
                 for (int i = 0; i < s.n; ++i) {
                     const CoreTask& t = T[i];
                     const int W = P.W;
+                    if (wide) {
+                        if (t.scr_off < 0 || !span("wide core scratch", t.scr_off, t.scr_off + kWideScratch - 1, WS))
+                            return "wide core scratch";
+                        if (t.energy_off >= 0 || t.v_off >= 0) return "wide core outputs";
+                    }
                     if (t.mode == CORE_MERGE) {
-                        if (2 * W > s.maxdim) return "merge core exceeds maxdim";
+                        if (2 * t.kcap > s.maxdim || t.kcap > W) return "merge core exceeds maxdim";
                         if (!span("core s1", t.s1_off, t.s1_off + W - 1, WS)) return msg;
                         if (!span("core s2", t.s2_off, t.s2_off + W - 1, WS)) return msg;
                         if (!panel("core C", t.c_off, t.c_ld, W, W)) return msg;
@@ -2012,7 +2027,8 @@ static hsvd_status plan_impl(hsvd_plan_t* out, int32_t count, const int64_t* ms,
         if (k < 1 || k > std::min(m, n)) return fail(HSVD_ERR_INVALID, "need 1 <= k <= min(m, n)" + at);
         if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
             return fail(HSVD_ERR_UNSUPPORTED, "m and n must be below 2^30" + at);
-        if (k > 64) return fail(HSVD_ERR_UNSUPPORTED, "k > 64 is not supported by this build" + at);
+        if (k > kMaxRank)
+            return fail(HSVD_ERR_UNSUPPORTED, "k > " + std::to_string(kMaxRank) + " is not supported by this build" + at);
     }
     if (!(tol >= 0.0 && tol < 1.0)) return fail(HSVD_ERR_INVALID, "need 0 <= tol < 1");
     hsvd_options o;
@@ -2447,7 +2463,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_REDUCE: kind = HSVD_LAUNCH_REDUCE; break;
                 case ST_NN: kind = HSVD_LAUNCH_THIN_NN; break;
                 case ST_SUM: kind = HSVD_LAUNCH_SUM; break;
-                case ST_CORE: kind = HSVD_LAUNCH_CORE; break;
+                case ST_CORE: kind = s.maxdim > kCoreMaxN ? HSVD_LAUNCH_CORE_WIDE : HSVD_LAUNCH_CORE; break;
                 case ST_ENERGY: kind = HSVD_LAUNCH_ENERGY; break;
                 case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
                 case ST_LEAFCHECK: kind = HSVD_LAUNCH_CHECK; break;
@@ -2569,7 +2585,7 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                 case ST_CORE: {
                     const CoreTask* T = (const CoreTask*)(b + s.tasks_off);
                     for (int t = 0; t < s.n; ++t) {
-                        const double d = (T[t].mode == CORE_MERGE) ? 2.0 * P.W : (double)T[t].dim;
+                        const double d = (T[t].mode == CORE_MERGE) ? 2.0 * T[t].kcap : (double)T[t].dim;
                         f += 22.0 * d * d * d;
                         by += (d * d + d * T[t].out_w + T[t].out_w) * e8;
                     }

@@ -43,14 +43,16 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
                                          int32_t precondition, uint32_t* flags_host,
                                          hipStream_t stream) {
     using hsvd_detail::set_error;
-    if (!M || !U || !S || batch < 1 || n < 1 || n > 128 || (V && n > 64) || max_sweeps < 1 ||
-        (precondition != 0 && precondition != 1) || (precondition && V))
+    if (!M || !U || !S || batch < 1 || n < 1 || n > kWideCoreMaxN || (V && n > kCoreMaxV) || max_sweeps < 1 ||
+        (precondition != 0 && precondition != 1) || (precondition && V) || (precondition && n > kCoreMaxN))
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_jacobi: bad argument");
     Scratch sc;
     const int64_t nn = (int64_t)n * n;
-    // arena: copies of M | U | V | S
+    const bool wide = n > kCoreMaxN;
+    // arena: copies of M | U | V | S | wide-core scratch panels
     const int64_t offM = 0, offU = offM + batch * nn, offV = offU + batch * nn,
-                  offS = offV + batch * nn, tot = offS + (int64_t)batch * n;
+                  offS = offV + batch * nn, offW = offS + (int64_t)batch * n,
+                  tot = offW + (wide ? batch * kWideScratch : 0);
     double* ws = sc.get<double>(tot);
     int* iws = sc.get<int>(batch);
     unsigned* flags = sc.get<unsigned>(2);
@@ -80,6 +82,7 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
         c.floor_cols = -1;
         c.fixed_rank_slot = -1;
         c.precond = precondition;
+        c.scr_off = wide ? offW + b * kWideScratch : -1;
         c.energy_off = -1;
         c.flag_slot = -1;
         // keep every nonzero column: rank = count above a zero floor of 0

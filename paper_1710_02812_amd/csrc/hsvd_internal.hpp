@@ -152,7 +152,21 @@ struct CoreTask {
     // > 0: the sweeps stop once no pair has |g_a . g_b| > orth_tol |g_a| |g_b|; else the
     // working-precision threshold max(rows, 1) 2^-52
     double orth_tol = 0.0;
+    // cores of more than kCoreMaxN columns: a kWideScratch-element float64 scratch panel
+    // that holds the core's columns while it is decomposed (else -1)
+    int64_t scr_off = -1;
 };
+
+// Core sizes: LDS-resident cores up to kCoreMaxN columns (accumulated right vectors up
+// to kCoreMaxV); merge and dense cores up to kWideCoreMaxN columns keep their columns in
+// a scratch panel of kWideCoreRows x kWideCoreMaxN.
+constexpr int kCoreMaxN = 128;
+constexpr int kCoreMaxV = 96;
+constexpr int kWideCoreMaxN = 160;
+constexpr int kWideCoreRows = 160;
+constexpr int64_t kWideScratch = (int64_t)kWideCoreRows * kWideCoreMaxN;
+// Rank cap of a plan: merge cores of 2k columns must fit the wide cores.
+constexpr int kMaxRank = kWideCoreMaxN / 2;
 
 // Column-orthogonality threshold of the mixed-precision plans' tree cores (leaves,
 // merges, slab re-projections): their inputs carry bfloat16 rounding (2^-9 relative),
@@ -200,6 +214,7 @@ inline hipError_t set_lds_limit_once(const void* fn, int bytes, unsigned long lo
     return e;
 }
 hipError_t prepare_core_launches();
+hipError_t prepare_core_wide();
 hipError_t prepare_panel_qr_launches();
 hipError_t prepare_gemm_bf16_launches();
 hipError_t prepare_gemm_f32_launches();
@@ -262,6 +277,8 @@ hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                        int max_sweeps, unsigned* flags, int with_v, hipStream_t s,
                        const int* guard = nullptr);
+hipError_t launch_core_wide(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
+                            int max_sweeps, unsigned* flags, hipStream_t s, const int* guard);
 hipError_t launch_mlp_train(float* master, float* m1, float* m2, const float* X, const float* T,
                             int count, int steps, int s0, int t0, float lr, float* grad_out,
                             float* loss_out, hipStream_t s);

@@ -33,60 +33,11 @@
 // on merge cores this halves the number of sweeps.
 // Columns are then sorted by norm, the truncation rule picks the rank r, and the
 // normalised left vectors, singular values and (optionally) V are written.
-#include "hsvd_internal.hpp"
-#include "device_common.hpp"
+#include "core_common.hpp"
 #include "house_qr.hpp"
 #include "mfma_f64.hpp"
 
 namespace hsvd {
-
-constexpr int CORE_THREADS = 1024;
-
-// First index i < nc (nc <= 128) where pred(i) fails, else nc; called by a whole wave.
-template <typename F>
-__device__ __forceinline__ int wave_first_fail(int nc, F pred) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long f0 = __ballot(lane < nc && !pred(lane));
-    const unsigned long long f1 = __ballot(lane + 64 < nc && !pred(lane + 64));
-    if (f0) return __builtin_ctzll(f0);
-    if (f1) return 64 + __builtin_ctzll(f1);
-    return nc;
-}
-
-// The truncation rank of sorted values sig (descending), for one wave: a zero floor
-// of max(rows, cols) eps sig_0, then the task's rule; at most kcap.
-__device__ int select_rank(const double* sig, int nc, const CoreTask& t, const int* iws) {
-    if (nc == 0) return 0;
-    const double s0 = sig[0];
-    if (!(s0 > 0.0)) return 0;
-    const int fr = t.floor_rows;
-    const int fc = t.floor_cols < 0 ? nc : t.floor_cols;
-    const double floor = (double)(fr > fc ? fr : fc) * kEps * s0;
-    const int nonzero = wave_first_fail(nc, [&](int i) { return sig[i] > floor; });
-    int r;
-    if (t.fixed_rank_slot >= 0) {
-        r = iws[t.fixed_rank_slot];
-    } else if (t.rule == 0) {
-        const double lim = t.tol * s0;
-        r = wave_first_fail(nc, [&](int i) { return sig[i] >= lim; });
-    } else {
-        // smallest r whose discarded tail sum_{i>=r} s_i^2 is <= tol^2 * total,
-        // tails accumulated from the smallest value up (in that order, by one lane)
-        double total = 0.0;
-        for (int i = nc - 1; i >= 0; --i) total += sig[i] * sig[i];
-        const double lim = t.tol * t.tol * total;
-        double tail = 0.0;
-        r = nc;
-        for (int i = nc - 1; i >= 0; --i) {
-            tail += sig[i] * sig[i];
-            if (tail <= lim) r = i;
-            else break;
-        }
-    }
-    if (r > nonzero) r = nonzero;
-    if (r > t.kcap) r = t.kcap;
-    return r;
-}
 
 // ROWS: every column is padded with zeros to ROWS >= maxdim rows (a multiple of 16)
 template <int ROWS>
@@ -127,9 +78,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
     }
     __syncthreads();
     const int nr = s_nr, nc = s_nc, r1 = s_r1;
-    // right vectors are accumulated only for cores of at most 64 columns (the launch
+    // right vectors are accumulated only for cores of at most 96 columns (the launch
     // rejects with_v above that), so the wider variants compile without them
-    const bool accv = ROWS <= 64 && (t.v_off >= 0) && with_v;
+    const bool accv = ROWS <= 96 && (t.v_off >= 0) && with_v;
 
     // ---- load the core
     int bad = 0;
@@ -378,24 +329,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
                     // value, and c here (a different rounding, running norms) must not
                     // decline the rotation of a pair near the threshold
                     if (da > 0.0 && db > 0.0 && c * c > 0.25 * tol2 * da * db) {
-                        // tan of the rotation angle: t = sign(dd) g / (|dd| + sqrt(dd^2 + g^2)),
-                        // dd = |g_b|^2 - |g_a|^2, g = 2 g_a.g_b (the smaller root of
-                        // t^2 + 2 (dd/g) t - 1 = 0).
-                        const double dd = db - da, gg = 2.0 * c;
-                        double tt;
-                        if (fmax(fabs(dd), fabs(gg)) < 1e150) {
-                            // the angle only steers convergence: hardware estimates suffice;
-                            // orthogonality comes from the refined cs below
-                            const double x = fma(dd, dd, gg * gg);
-                            const double hyp = x * __builtin_amdgcn_rsq(x);
-                            tt = copysign(1.0, dd) * gg * __builtin_amdgcn_rcp(fabs(dd) + hyp);
-                        } else {
-                            const double zeta = dd / gg, az = fabs(zeta);
-                            tt = (az > 1e150) ? 0.5 / zeta
-                                              : copysign(1.0 / (az + sqrt(1.0 + zeta * zeta)), zeta);
-                        }
-                        const double cs = rsqrt_nr(fma(tt, tt, 1.0));
-                        const double sn = cs * tt;
+                        double cs, sn, tt;
+                        jacobi_rotation(da, db, c, cs, sn, tt);
 #pragma unroll
                         for (int t = 0; t < TMAX; ++t) {
                             const double xa = ra[t];
@@ -568,7 +503,7 @@ size_t core_lds(int maxdim, int with_v) {
 template <int ROWS>
 hipError_t prepare_core_rows() {
     static unsigned long long done = 0;
-    return set_lds_limit_once((const void*)k_core<ROWS>, (int)core_lds<ROWS>(ROWS, ROWS <= 64), &done);
+    return set_lds_limit_once((const void*)k_core<ROWS>, (int)core_lds<ROWS>(ROWS, ROWS <= 96), &done);
 }
 
 template <int ROWS>
@@ -588,13 +523,18 @@ hipError_t prepare_core_launches() {
     if (e == hipSuccess) e = prepare_core_rows<96>();
     if (e == hipSuccess) e = prepare_core_rows<112>();
     if (e == hipSuccess) e = prepare_core_rows<128>();
+    if (e == hipSuccess) e = prepare_core_wide();
     return e;
 }
 
 hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                          int max_sweeps, unsigned* flags, int with_v, hipStream_t s, const int* guard) {
     if (ntasks <= 0) return hipSuccess;
-    if (maxdim < 1 || maxdim > 128 || (with_v && maxdim > 64)) return hipErrorInvalidValue;
+    if (maxdim > kCoreMaxN) {
+        if (maxdim > kWideCoreMaxN || with_v) return hipErrorInvalidValue;
+        return launch_core_wide(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, s, guard);
+    }
+    if (maxdim < 1 || (with_v && maxdim > kCoreMaxV)) return hipErrorInvalidValue;
     // rows padded to the smallest variant that holds the largest core of the launch
     if (maxdim <= 32) return launch_core_rows<32>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);
     if (maxdim <= 64) return launch_core_rows<64>(ws, iws, tasks, ntasks, maxdim, max_sweeps, flags, with_v, s, guard);

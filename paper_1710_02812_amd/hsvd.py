@@ -40,7 +40,7 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features", "cholqr",
-                "check", "panel_qr", "gemm_ax_f32", "gemm_atx_f32", "gram_xtx"]
+                "check", "panel_qr", "gemm_ax_f32", "gemm_atx_f32", "gram_xtx", "core_wide"]
 
 
 class HsvdError(RuntimeError):

@@ -70,7 +70,8 @@ def test_plan_rejects_bad_options_and_unsupported_rank():
         o.refine_steps, o.refine_eps = 3, bad
         assert lib.hsvd_plan_ex(ctypes.byref(h), 100, 100, 2, 2, 5, 0.0, ctypes.byref(o)) == 1
         assert "refine_eps" in lib.hsvd_last_error().decode()
-    assert lib.hsvd_plan(ctypes.byref(h), 1000, 1000, 2, 2, 65, 0.0) == 6
+    assert lib.hsvd_plan(ctypes.byref(h), 1000, 1000, 2, 2, 81, 0.0) == 6
+    assert "k > 80" in lib.hsvd_last_error().decode()
     assert lib.hsvd_plan(None, 100, 100, 2, 2, 5, 0.0) == 1
 
 
@@ -105,6 +106,9 @@ def test_null_handles():
     (1000, 900, 3, 4, 20, {"precision": 2, "refine_steps": 1}),
     (1000, 900, 3, 4, 20, {"refine_steps": 4, "refine_eps": 1e-6}),
     (1000, 900, 3, 4, 20, {"precision": 2, "refine_steps": 2, "refine_eps": 1e-3}),
+    (1200, 1100, 3, 3, 80, {}),
+    (1000, 1300, 2, 3, 72, {"precision": 2, "refine_steps": 1}),
+    (16384, 16384, 16, 16, 80, {"precision": 2}),
 ])
 def test_plan_footprint_is_in_bounds(shape):
     """Every task of every launch stays inside the plan's buffers (host-side check)."""
@@ -126,7 +130,7 @@ def test_batched_plan_rejects_bad_arguments():
     ps, qs, ks = _arr(i32, [2, 20]), _arr(i32, [2, 2]), _arr(i32, [5, 5])
     assert lib.hsvd_plan_batched(ctypes.byref(h), 2, ms, ns, ps, qs, ks, 0.0, None) == 1
     assert "matrix 1" in lib.hsvd_last_error().decode()
-    ks = _arr(i32, [5, 65])
+    ks = _arr(i32, [5, 81])
     ms, ns = _arr(i64, [100, 100]), _arr(i64, [100, 100])
     assert lib.hsvd_plan_batched(ctypes.byref(h), 2, ms, ns, _arr(i32, [2, 2]), qs, ks, 0.0, None) == 6
     assert lib.hsvd_execute_batched(None, None, None, None, None, None) == 1
@@ -135,13 +139,14 @@ def test_batched_plan_rejects_bad_arguments():
 
 def test_batched_plan_footprint_uneven_batch():
     """The 200-matrix uneven batch (shapes and grids of the uneven workload, ranks
-    capped at 64): every task of every launch stays inside its buffers."""
+    5..80, so that both the LDS-resident and the wide merge cores run): every task of
+    every launch stays inside its buffers."""
     from paper_1710_02812_amd import synth
     rng = np.random.default_rng(3)
     shapes = []
     for _ in range(200):
         m, n = int(rng.integers(256, 4097)), int(rng.integers(256, 4097))
-        k = int(rng.integers(5, 65))
+        k = int(rng.integers(5, 81))
         shapes.append((m, n, -(-m // 512), -(-n // 512), k))
     b = H.plan_check_batched(shapes)
     assert b > 0

@@ -345,6 +345,49 @@ def test_batched_uneven_fp64():
         assert np.max(np.abs(S.cpu().numpy()[:r] - w.meta["sigma"])) <= 1e-12
 
 
+@pytest.mark.parametrize("m,n,p,q,k,rank,tol", [
+    (1200, 1100, 3, 3, 80, 80, 0.0),      # every merge core 160 columns
+    (1000, 1300, 2, 3, 72, 72, 0.0),      # 144 columns; short-fat: column slabs merged last
+    (900, 900, 3, 2, 80, 30, 1e-10),      # wide-routed merges with 60 active columns
+])
+def test_wide_merge_cores_fp64(m, n, p, q, k, rank, tol):
+    """Rank caps above 64: merge cores of 2k > 128 columns run on the wide cores (their
+    columns in a global scratch panel); float64 parity with the oracle at the 1e-10 gates."""
+    rng = np.random.default_rng(m + k + rank)
+    sigma = 10.0 ** (-np.arange(rank) / (rank / 3.0))
+    A, *_ = synth.low_rank(rng, m, n, sigma, noise=1e-13 if tol > 0 else 1e-9)
+    print(f"wide merges {m}x{n} {p}x{q} k={k} rank={rank}", flush=True)
+    check_parity(A, p, q, k, tol)
+
+
+def test_wide_merge_cores_mixed():
+    """The mixed path with k = 80 (wide merge cores, float32 and bfloat16 passes) against
+    the oracle on the float32-rounded input, at the mixed gate 1e-3."""
+    rng = np.random.default_rng(80)
+    sigma = np.exp(-np.arange(80) / 10.0)
+    A, *_ = synth.low_rank(rng, 2048, 2048, sigma, noise=1e-7)
+    print("wide merges mixed 2048", flush=True)
+    check_parity(A, 4, 4, 80, 0.0, dtype=torch.float32, gate=1e-3, mixed=True)
+
+
+def test_batched_uneven_wide_fp64():
+    """A batch whose rank caps straddle 64 (ranks up to 80, a 1 x 1 grid among them):
+    merge cores of both kinds in the same levels; every matrix matches the oracle at
+    the float64 gate and recovers its rank."""
+    ws = _uneven(6, 1400, 80, seed=22)
+    assert max(w.k for w in ws) > 64 and min(w.k for w in ws) <= 64
+    print("batched wide fp64", [(w.A.shape, w.k) for w in ws], flush=True)
+    As = [torch.tensor(w.A, device=DEV) for w in ws]
+    outs = H.svd_batched(As, [w.p for w in ws], [w.q for w in ws], [w.k for w in ws])
+    torch.cuda.synchronize()
+    for w, (U, S, Vt, r) in zip(ws, outs):
+        Uo, so, Vto, ro = oracle.hsvd(w.A, w.p, w.q, w.k, 0.0)
+        assert r == ro == w.k
+        c = metrics.compare(U.cpu().numpy(), S.cpu().numpy(), Vt.cpu().numpy(), r, Uo, so, Vto, ro)
+        assert c["e_sigma"] <= 1e-10 and c["e_frob"] <= 1e-10, (w.name, c)
+        assert np.max(np.abs(S.cpu().numpy()[:r] - w.meta["sigma"])) <= 1e-12
+
+
 def test_batched_uneven_fp32_and_mixed():
     ws = _uneven(8, 1500, 48, seed=5)
     As = [torch.tensor(w.A.astype(np.float32), device=DEV) for w in ws]

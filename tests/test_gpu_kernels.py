@@ -18,13 +18,13 @@ def _t(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 90, 100, 128])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 80, 90, 96, 100, 128])
 def test_jacobi_dense_random(n):
     rng = np.random.default_rng(n)
     M = rng.standard_normal((3, n, n))
     M[1] *= np.exp(-np.arange(n) / 3.0)[None, :]          # graded columns
     print(f"jacobi n={n}", flush=True)
-    U, S, V, flags, sweeps = H.debug_jacobi(_t(M), with_v=(n <= 64))
+    U, S, V, flags, sweeps = H.debug_jacobi(_t(M), with_v=(n <= 96))
     print(f'sweeps {sweeps}', flush=True)
     assert flags == 0
     U, S = U.cpu().numpy(), S.cpu().numpy()
@@ -35,9 +35,12 @@ def test_jacobi_dense_random(n):
         nz = S[b] > 1e-12 * S[b][0]
         Ub = U[b][:, nz]
         assert np.linalg.norm(Ub.T @ Ub - np.eye(nz.sum())) <= 1e-13 * n
-        if n <= 64:
+        if n <= 96:
+            # columns past the zero floor (max(rows, cols) 2^-52 sigma_1) are written as zero
             Vb = V.cpu().numpy()[b]
-            assert np.linalg.norm(Vb.T @ Vb - np.eye(n)) <= 1e-13 * n
+            pos = S[b] > 0.0
+            assert np.all(Vb[:, ~pos] == 0.0)
+            assert np.linalg.norm(Vb[:, pos].T @ Vb[:, pos] - np.eye(pos.sum())) <= 1e-13 * n
             rec = (U[b] * S[b]) @ Vb.T
             assert np.linalg.norm(rec - M[b]) <= 1e-13 * n * np.linalg.norm(M[b])
 
@@ -105,6 +108,67 @@ def test_jacobi_merge_matrix_preconditioned(k):
     Ur = np.linalg.svd(E[0])[0][:, :k]
     Uk = U1.cpu().numpy()[0][:, :k]
     assert np.linalg.norm(Uk - Ur @ (Ur.T @ Uk), 2) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [129, 150, 160])
+def test_jacobi_wide_dense(n):
+    """Cores of more than 128 columns (columns in a global scratch panel, three-phase
+    sweeps): singular values against LAPACK, orthonormal left vectors, and U^T M with
+    orthogonal rows of norms S, on a random and a column-graded matrix."""
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((2, n, n))
+    M[1] *= np.exp(-np.arange(n) / 6.0)[None, :]
+    print(f"wide jacobi n={n}", flush=True)
+    U, S, _, flags, sweeps = H.debug_jacobi(_t(M), with_v=False)
+    print(f"sweeps {sweeps}", flush=True)
+    assert flags == 0
+    U, S = U.cpu().numpy(), S.cpu().numpy()
+    for b in range(2):
+        s_ref = np.linalg.svd(M[b], compute_uv=False)
+        assert np.max(np.abs(S[b] - s_ref)) <= 1e-13 * s_ref[0] * n / 8
+        assert np.all(np.diff(S[b]) <= 0)
+        nz = S[b] > 1e-12 * S[b][0]
+        Ub = U[b][:, nz]
+        assert np.linalg.norm(Ub.T @ Ub - np.eye(nz.sum())) <= 1e-13 * n
+        B = Ub.T @ M[b]
+        assert np.linalg.norm(B @ B.T - np.diag(S[b][nz] ** 2)) <= 1e-13 * n * s_ref[0] ** 2
+
+
+@pytest.mark.parametrize("k", [72, 80])
+def test_jacobi_wide_merge_matrix(k):
+    """Merge-shaped cores of 2k > 128 columns (two children of rank k sharing most of
+    their directions) on the wide cores: singular values and the top-k left subspace
+    against LAPACK."""
+    rng = np.random.default_rng(k)
+    E = _merge_matrix(rng, k)[None]
+    U, S, _, f, sw = H.debug_jacobi(_t(E), with_v=False)
+    print(f"wide merge core k={k} sweeps {sw}", flush=True)
+    assert f == 0
+    s_ref = np.linalg.svd(E[0], compute_uv=False)
+    S = S.cpu().numpy()[0]
+    assert np.max(np.abs(S - s_ref)) <= 1e-13 * s_ref[0] * 2 * k / 8
+    Ur = np.linalg.svd(E[0])[0][:, :k]
+    Uk = U.cpu().numpy()[0][:, :k]
+    assert np.linalg.norm(Uk - Ur @ (Ur.T @ Uk), 2) <= 1e-11
+
+
+def test_jacobi_wide_rank_deficient_zero_and_cap():
+    """Wide cores on a rank-6 matrix, a zero matrix, and under a one-sweep cap."""
+    rng = np.random.default_rng(7)
+    n = 140
+    A = rng.standard_normal((n, 6)) @ rng.standard_normal((6, n))
+    Z = np.zeros((n, n))
+    U, S, _, flags, _ = H.debug_jacobi(_t(np.stack([A, Z])), with_v=False)
+    S = S.cpu().numpy()
+    assert flags == 0
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(S[0] - s_ref)) <= 1e-12 * s_ref[0]
+    assert np.all(S[1] == 0.0)
+    assert np.all(U.cpu().numpy()[1] == 0.0)
+    M = rng.standard_normal((1, n, n))
+    _, _, _, flags, sweeps = H.debug_jacobi(_t(M), max_sweeps=1, with_v=False)
+    assert sweeps == 1
+    assert flags & H.FLAG_NOCONV
 
 
 def test_jacobi_rank_deficient_and_zero():
