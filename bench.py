@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--refine-eps", type=float, default=1e-3,
                     help="refine: stop when the singular values change by at most this (relative)")
     ap.add_argument("--count", type=int, default=200, help="uneven: number of matrices")
+    ap.add_argument("--rank-hi", type=int, default=80, help="uneven: ranks drawn from U{5..rank_hi} (at most 80)")
     ap.add_argument("--accuracy", default="sketch", choices=["sketch", "full", "none"],
                     help="c2: accuracy from the stored oracle sketch, from a full oracle run, or none")
     ap.add_argument("--noise", default="abs", choices=["abs", "rel"],
@@ -279,11 +280,11 @@ def run_refine(args, torch):
 
 
 def run_uneven(args, torch):
-    """Uneven batch: m, n ~ U{256..4096}, rank ~ U{5..64}, sigma_i = exp(-i/6), no
+    """Uneven batch: m, n ~ U{256..4096}, rank ~ U{5..80}, sigma_i = exp(-i/6), no
     noise, blocks <= 512, k = rank, float32 storage (float64 arithmetic)."""
     from paper_1710_02812_amd import hsvd as H, synth
     t = time.time()
-    ws = synth.config3(seed=3, count=args.count, rank_hi=64)
+    ws = synth.config3(seed=3, count=args.count, rank_hi=args.rank_hi)
     gen_s = time.time() - t
     progress(f"uneven: generated {len(ws)} matrices in {gen_s:.1f} s")
     shapes = [(w.A.shape[0], w.A.shape[1], w.p, w.q, w.k) for w in ws]
@@ -366,7 +367,7 @@ def run_uneven(args, torch):
         "value": round(ms_batched, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_batched, 4), "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(ws)} matrices, m,n ~ U{{256..4096}}, rank ~ U{{5..64}}, "
+        "config": {"workload": f"{len(ws)} matrices, m,n ~ U{{256..4096}}, rank ~ U{{5..{args.rank_hi}}}, "
                                "sigma_i = exp(-i/6), no noise, blocks <= 512, k = rank, float32 storage, "
                                "one batched plan",
                    "count": len(ws), "elements": int(elems), "storage": "f32"},

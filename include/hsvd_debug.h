@@ -23,11 +23,11 @@ extern "C" {
  * sigma), S (n, descending) and, when V != NULL (then n <= 96), the right singular
  * vectors V (n x n), so that M = U diag(S) V^T.  Columns with sigma = 0 are 0.
  * precondition = 1 first replaces M by L of M = L Q (left pairs only; V must be
- * NULL; n <= 128), as the merge cores do; 0 runs the sweeps on M itself.
+ * NULL), as the merge cores do; 0 runs the sweeps on M itself.
  * *flags_host (may be NULL) receives the status flags (HSVD_FLAG_*) in bits 0..15
  * and the largest number of sweeps any core ran in bits 16..31.
  * HSVD_ERR_INVALID for null M/U/S, n outside 1..160, V with n > 96, max_sweeps < 1,
- * precondition not 0/1, precondition with V or with n > 128.               */
+ * precondition not 0/1 or precondition with V.                            */
 hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t n, double* U, double* S,
                               double* V, int32_t max_sweeps, int32_t precondition,
                               uint32_t* flags_host, hipStream_t stream);

@@ -85,6 +85,7 @@ struct Stage {
     // streams of their own between a fork and a join
     int branch = 0;
     int done_slot = -1;  // leaf check: int-arena slot of its leaf class's "all converged"
+    int pw = 0;          // panel width of the matrices the stage works on
 };
 
 int pow2floor(int x) {
@@ -105,6 +106,7 @@ struct MatDesc {
     // operations).  m, n, p, q, rs, cs are logical; the input is (trans ? n x m : m x n).
     int64_t m = 0, n = 0;
     int p = 0, q = 0, k = 0;
+    int pw = 0;                    // width of the matrix's panels (its rank class's max k)
     bool trans = false;
     std::vector<int64_t> rs, cs;
     int64_t brow(int i) const { return rs[i + 1] - rs[i]; }
@@ -576,7 +578,6 @@ std::vector<Node> merge_level(hsvd_plan_st& P, const std::vector<std::pair<Node,
         // a core of two children of rank above kCoreMaxN / 2 may exceed the LDS-resident
         // cores: such merges go to the wide cores, with a scratch panel each
         if (2 * P.mats[a.mat].k > kCoreMaxN) {
-            c.precond = 0;
             c.scr_off = P.alloc(kWideScratch);
             wide.push_back(c);
         } else {
@@ -885,13 +886,35 @@ int batch_width(const hsvd_plan_st& P, const MatDesc& M) {
     return std::max(1, std::min(w, lim));
 }
 
-// Leaves of every block of every matrix.  Sketch width P.L for all, or the
-// per-block widths of a width plan (leaves grouped by width: one pipeline per
-// class).  Width plans first compute every block's energy for the leaf check.
+// Leaves of every block of every matrix (of the matrices in `only`, when given).
+// Sketch width P.L for all, or the per-block widths of a width plan, or a batched
+// plan's per-matrix widths (leaves grouped by width: one pipeline per class, run as
+// concurrent branches when branch_classes).  Width plans first compute every block's
+// energy for the leaf check.  One Gaussian test matrix serves every leaf of the plan.
 // Returns one forest per (matrix, row slab), matrices in order, slabs top to bottom.
-std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
+std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P, const std::vector<int>* only = nullptr,
+                                            bool branch_classes = true) {
+    auto leaf_w = [&](const MatDesc& M, int i, int j) {
+        return !P.leaf_width.empty() ? P.leaf_width[(size_t)i * M.q + j]
+               : P.ntree > 1 ? batch_width(P, M) : P.L;
+    };
+    int64_t bcmax = 1;
+    int wmax = 1;
+    for (int mi = 0; mi < P.ntree; ++mi) {
+        const MatDesc& M = P.mats[mi];
+        for (int i = 0; i < M.p; ++i)
+            for (int j = 0; j < M.q; ++j) {
+                bcmax = std::max(bcmax, M.bcol(j));
+                wmax = std::max(wmax, leaf_w(M, i, j));
+            }
+    }
+    if (P.omega_count == 0) {
+        P.omega_count = bcmax * wmax;
+        P.omega_off = P.alloc(P.omega_count);
+    }
     std::vector<Leaf> leaves;
     for (int mi = 0; mi < P.ntree; ++mi) {
+        if (only && std::find(only->begin(), only->end(), mi) == only->end()) continue;
         const MatDesc& M = P.mats[mi];
         for (int i = 0; i < M.p; ++i)
             for (int j = 0; j < M.q; ++j) {
@@ -901,21 +924,14 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
                 l.rowsz = M.brow(i);
                 l.colsz = M.bcol(j);
                 l.aoff = M.rs[i] * M.n + M.cs[j];
-                l.w = !P.leaf_width.empty() ? P.leaf_width[(size_t)i * M.q + j]
-                      : P.ntree > 1 ? batch_width(P, M) : P.L;
+                l.w = leaf_w(M, i, j);
                 leaves.push_back(l);
             }
     }
-    int64_t bcmax = 1;
-    int wmax = 1;
-    for (const Leaf& l : leaves) {
-        bcmax = std::max(bcmax, l.colsz);
-        wmax = std::max(wmax, l.w);
+    if (P.leaf_rank_slots.empty()) {
+        P.leaf_rank_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
+        P.leaf_flag_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
     }
-    P.omega_count = bcmax * wmax;
-    P.omega_off = P.alloc(P.omega_count);
-    P.leaf_rank_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
-    P.leaf_flag_slots.assign((size_t)P.mats[0].p * P.mats[0].q, -1);
     if (!P.leaf_width.empty()) {
         P.energy_off = P.alloc((int64_t)leaves.size());
         std::vector<GemmTask> et;
@@ -938,10 +954,10 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
             if (leaves[b].w == widths[c]) ids.push_back((int)b);
         const size_t first = P.stages.size();
         leaf_pipeline(P, leaves, ids, widths[c], bcmax, nodes);
-        if (widths.size() > 1)
+        if (widths.size() > 1 && branch_classes)
             for (size_t i = first; i < P.stages.size(); ++i) P.stages[i].branch = (int)c + 1;
     }
-    if (widths.size() > 1) P.nbranch = (int)widths.size();
+    if (widths.size() > 1 && branch_classes) P.nbranch = (int)widths.size();
     std::vector<std::vector<Node>> slabs;
     int prev_mat = -1, prev_i = -1;
     for (size_t b = 0; b < leaves.size(); ++b) {
@@ -957,7 +973,7 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P) {
 
 // Slab re-projection: V_i, s_i = SVD(U_i^T A_i), for the column-tree root of every
 // (matrix, slab) in the order build_leaves produced them.  Returns one row forest
-// per matrix.
+// per matrix present, in matrix order.
 std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::vector<Node>& roots) {
     const int W = P.W;
     const int ch = tsqr_chunk(W, W);
@@ -1022,7 +1038,11 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
     }
     push_core(P, cores, W, 0);
     push_tsqr_apply(P, tb, at, W, ch, W);
-    return out;
+    // the forests of the matrices present (a rank class of a batched plan holds some)
+    std::vector<std::vector<Node>> present;
+    for (auto& f : out)
+        if (!f.empty()) present.push_back(std::move(f));
+    return present;
 }
 
 struct Factors { int64_t U, V, sig; int rank; int mat; };
@@ -1242,8 +1262,128 @@ void build_gram(hsvd_plan_st& P) {
     }
 }
 
+// Output table of factors ff, one entry per matrix (sign slots of its own).
+std::vector<OutputArgs> output_table(hsvd_plan_st& P, const std::vector<Factors>& ff, std::vector<int>& ranks) {
+    std::vector<OutputArgs> outs;
+    ranks.clear();
+    for (size_t mi = 0; mi < ff.size(); ++mi) {
+        const MatDesc& M = P.mats[ff[mi].mat];
+        OutputArgs o{};
+        // a transposed plan's right vectors are the input's left vectors
+        o.u_off = M.trans ? ff[mi].V : ff[mi].U;
+        o.v_off = M.trans ? ff[mi].U : ff[mi].V;
+        o.sig_off = ff[mi].sig;
+        o.u_ld = (int)(M.trans ? M.n : M.m);
+        o.v_ld = (int)(M.trans ? M.m : M.n);
+        o.m = (int)(M.trans ? M.n : M.m);
+        o.n = (int)(M.trans ? M.m : M.n);
+        o.k = M.k;
+        o.rank_slot = ff[mi].rank;
+        o.sign_off = P.ialloc(M.k);
+        outs.push_back(o);
+        ranks.push_back(ff[mi].rank);
+    }
+    return outs;
+}
+
+void output_extents(hsvd_plan_st& P, const std::vector<Factors>& f) {
+    P.kmax = P.mmax = P.nmax = 0;
+    for (size_t mi = 0; mi < f.size(); ++mi) {
+        const MatDesc& M = P.mats[f[mi].mat];
+        P.kmax = std::max(P.kmax, M.k);
+        P.mmax = std::max<int>(P.mmax, (int)std::max(M.m, M.n));
+        P.nmax = std::max<int>(P.nmax, (int)std::max(M.m, M.n));
+    }
+}
+
+// Next projection input from an Algorithm 2 step's factors (V and sigma).
+std::vector<Node> nodes_of(const hsvd_plan_st& P, const std::vector<Factors>& f) {
+    std::vector<Node> vs(f.size());
+    for (size_t mi = 0; mi < f.size(); ++mi) {
+        vs[mi].mat = f[mi].mat;
+        vs[mi].panel = f[mi].V;
+        vs[mi].ld = (int)P.mats[f[mi].mat].n;
+        vs[mi].h = (int)P.mats[f[mi].mat].n;
+        vs[mi].rank = f[mi].rank;
+        vs[mi].sig = f[mi].sig;
+    }
+    return vs;
+}
+
+// Rank classes of a batched plan: the matrices grouped by leaf sketch width (adjacent
+// widths merged into at most kRankClasses groups).  Each class gets the panel width of
+// its largest rank cap, so that matrices of small rank do not pay for the batch's
+// largest, and its stages form a branch of their own (the classes are independent).
+// One class for everything else, and for plans stopping Algorithm 2 on refine_eps
+// (whose host checks split the stage list into segments).
+constexpr int kRankClasses = 4;
+std::vector<std::vector<int>> rank_classes(const hsvd_plan_st& P, bool eps_stop) {
+    std::vector<std::vector<int>> cls;
+    if (P.ntree < 2 || P.gram || !P.leaf_width.empty() || eps_stop) {
+        cls.emplace_back();
+        for (int mi = 0; mi < P.ntree; ++mi) cls[0].push_back(mi);
+        return cls;
+    }
+    std::vector<int> widths;
+    for (int mi = 0; mi < P.ntree; ++mi) {
+        const int w = batch_width(P, P.mats[mi]);
+        if (std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+    }
+    std::sort(widths.begin(), widths.end());
+    const int nw = (int)widths.size(), nc = std::min(nw, kRankClasses);
+    cls.resize(nc);
+    for (int mi = 0; mi < P.ntree; ++mi) {
+        const int wi = (int)(std::find(widths.begin(), widths.end(), batch_width(P, P.mats[mi])) - widths.begin());
+        cls[(size_t)wi * nc / nw].push_back(mi);
+    }
+    return cls;
+}
+
 hsvd_status build_plan(hsvd_plan_st& P) {
     if (P.gram) build_gram(P);
+    const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
+    const bool eps_stop = P.opt.refine_eps > 0.0 && steps >= 2;
+    P.seg_end.clear();
+    P.check_off.clear();
+    P.step_outs_off.clear();
+    P.step_rank_slots.clear();
+    P.refine_done = steps;
+    const std::vector<std::vector<int>> classes = rank_classes(P, eps_stop);
+    if (classes.size() > 1) {
+        // every class's whole pipeline with its own panel width, as a branch
+        const int wall = P.W;
+        std::vector<Factors> fall(P.ntree);
+        for (size_t c = 0; c < classes.size(); ++c) {
+            const std::vector<int>& ids = classes[c];
+            int w = 1;
+            for (int mi : ids) w = std::max(w, P.mats[mi].k);
+            P.W = w;
+            const size_t first = P.stages.size();
+            auto slabs = build_leaves(P, &ids, false);
+            P.merging_rows = false;
+            auto col_roots = merge_forest(P, slabs);
+            auto row_forests = build_reprojection(P, col_roots);
+            P.merging_rows = true;
+            auto row_roots = merge_forest(P, row_forests);
+            std::vector<Factors> f = build_projection(P, row_roots);
+            for (int it = 0; it < steps; ++it) {
+                f = build_refine_step(P, f);
+                if (it + 1 < steps) f = build_projection(P, nodes_of(P, f));
+            }
+            for (const Factors& x : f) fall[(size_t)x.mat] = x;
+            for (int mi : ids) P.mats[mi].pw = w;
+            for (size_t i = first; i < P.stages.size(); ++i) {
+                P.stages[i].branch = (int)c + 1;
+                P.stages[i].pw = w;
+            }
+        }
+        P.W = wall;
+        P.nbranch = (int)classes.size();
+        output_extents(P, fall);
+        P.outs = output_table(P, fall, P.rank_slots);
+        P.outs_off = P.put(P.outs);
+        return HSVD_OK;
+    }
     auto slabs = build_leaves(P);
     P.merging_rows = false;
     auto col_roots = merge_forest(P, slabs);
@@ -1253,36 +1393,6 @@ hsvd_status build_plan(hsvd_plan_st& P) {
     if (P.gram)                                   // V-hat of G = X^T X is X's: project against X
         for (Node& r : row_roots) r.mat = 1;
     std::vector<Factors> f = build_projection(P, row_roots);
-    const int steps = P.opt.refine_steps + (P.opt.precision == HSVD_MIXED_BF16 ? 1 : 0);
-    const bool eps_stop = P.opt.refine_eps > 0.0 && steps >= 2;
-    // output table of factors f (sign slots of its own)
-    auto out_table = [&](const std::vector<Factors>& ff, std::vector<int>& ranks) {
-        std::vector<OutputArgs> outs;
-        ranks.clear();
-        for (size_t mi = 0; mi < ff.size(); ++mi) {
-            const MatDesc& M = P.mats[ff[mi].mat];
-            OutputArgs o{};
-            // a transposed plan's right vectors are the input's left vectors
-            o.u_off = M.trans ? ff[mi].V : ff[mi].U;
-            o.v_off = M.trans ? ff[mi].U : ff[mi].V;
-            o.sig_off = ff[mi].sig;
-            o.u_ld = (int)(M.trans ? M.n : M.m);
-            o.v_ld = (int)(M.trans ? M.m : M.n);
-            o.m = (int)(M.trans ? M.n : M.m);
-            o.n = (int)(M.trans ? M.m : M.n);
-            o.k = M.k;
-            o.rank_slot = ff[mi].rank;
-            o.sign_off = P.ialloc(M.k);
-            outs.push_back(o);
-            ranks.push_back(ff[mi].rank);
-        }
-        return outs;
-    };
-    P.seg_end.clear();
-    P.check_off.clear();
-    P.step_outs_off.clear();
-    P.step_rank_slots.clear();
-    P.refine_done = steps;
     if (eps_stop) P.check_slot = P.ialloc(1);
     // the first iteration is tested against Algorithm 1's singular values (the row
     // tree's root), each later one against the iteration before it
@@ -1305,38 +1415,23 @@ hsvd_status build_plan(hsvd_plan_st& P) {
             }
             P.check_off.push_back(P.put(checks));
             std::vector<int> ranks;
-            last_outs = out_table(f, ranks);
+            last_outs = output_table(P, f, ranks);
             P.step_outs_off.push_back(P.put(last_outs));
             P.step_rank_slots.push_back(ranks);
             prev = f;
         }
-        if (it + 1 < steps) {
-            std::vector<Node> vs(f.size());
-            for (size_t mi = 0; mi < f.size(); ++mi) {
-                vs[mi].mat = f[mi].mat;
-                vs[mi].panel = f[mi].V;
-                vs[mi].ld = (int)P.mats[f[mi].mat].n;
-                vs[mi].h = (int)P.mats[f[mi].mat].n;
-                vs[mi].rank = f[mi].rank;
-                vs[mi].sig = f[mi].sig;
-            }
-            f = build_projection(P, vs);
-        }
+        if (it + 1 < steps) f = build_projection(P, nodes_of(P, f));
     }
-    P.kmax = P.mmax = P.nmax = 0;
-    for (size_t mi = 0; mi < f.size(); ++mi) {
-        const MatDesc& M = P.mats[f[mi].mat];
-        P.kmax = std::max(P.kmax, M.k);
-        P.mmax = std::max<int>(P.mmax, (int)std::max(M.m, M.n));
-        P.nmax = std::max<int>(P.nmax, (int)std::max(M.m, M.n));
-    }
+    for (Stage& st : P.stages) st.pw = P.W;
+    for (MatDesc& M : P.mats) M.pw = P.W;
+    output_extents(P, f);
     if (eps_stop) {
         // the last iteration's table doubles as the plan's output
         P.outs = last_outs;
         P.outs_off = P.step_outs_off.back();
         P.rank_slots = P.step_rank_slots.back();
     } else {
-        P.outs = out_table(f, P.rank_slots);
+        P.outs = output_table(P, f, P.rank_slots);
         P.outs_off = P.put(P.outs);
     }
     return HSVD_OK;
@@ -1604,7 +1699,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 if (s.maxdim < 1 || s.maxdim > kWideCoreMaxN || (s.with_v && s.maxdim > kCoreMaxV)) return "core size";
                 for (int i = 0; i < s.n; ++i) {
                     const CoreTask& t = T[i];
-                    const int W = P.W;
+                    const int W = s.pw;
                     if (wide) {
                         if (t.scr_off < 0 || !span("wide core scratch", t.scr_off, t.scr_off + kWideScratch - 1, WS))
                             return "wide core scratch";
@@ -1647,10 +1742,11 @@ std::string validate_plan(const hsvd_plan_st& P) {
         const OutputArgs& o = P.outs[mi];
         const MatDesc& M = P.mats[P.gram ? 1 : mi];
         const int64_t om = M.trans ? M.n : M.m, on = M.trans ? M.m : M.n;   // the input's shape
-        if (o.m != om || o.n != on || o.k != M.k || o.k > P.W) return "output shape";
-        if (!panel("out U", o.u_off, o.u_ld, om, P.W)) return msg;
-        if (!panel("out V", o.v_off, o.v_ld, on, P.W)) return msg;
-        if (!span("out sigma", o.sig_off, o.sig_off + P.W - 1, WS)) return msg;
+        const MatDesc& Mt = P.mats[mi];             // the matrix whose trees made the factors
+        if (o.m != om || o.n != on || o.k != M.k || o.k > Mt.pw) return "output shape";
+        if (!panel("out U", o.u_off, o.u_ld, om, Mt.pw)) return msg;
+        if (!panel("out V", o.v_off, o.v_ld, on, Mt.pw)) return msg;
+        if (!span("out sigma", o.sig_off, o.sig_off + Mt.pw - 1, WS)) return msg;
         if (!span("out signs", o.sign_off, o.sign_off + M.k - 1, IW)) return msg;
         if (o.rank_slot < 0 || o.rank_slot >= IW) return "out rank slot";
     }
@@ -2493,7 +2589,7 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
         double f = 0.0, by = 0.0;
         if (i == n - 1) {                                   // output: U, Vt from the panels
             for (const MatDesc& M : P.mats)
-                by += (double)(M.m + M.n) * P.W * e8 + (double)(M.m + M.n) * M.k * eA + M.k * eA;
+                by += (double)(M.m + M.n) * M.pw * e8 + (double)(M.m + M.n) * M.k * eA + M.k * eA;
         } else {
             const Stage& s = P.stages[i];
             switch (s.kind) {

@@ -44,7 +44,7 @@ extern "C" hsvd_status hsvd_debug_jacobi(const double* M, int32_t batch, int32_t
                                          hipStream_t stream) {
     using hsvd_detail::set_error;
     if (!M || !U || !S || batch < 1 || n < 1 || n > kWideCoreMaxN || (V && n > kCoreMaxV) || max_sweeps < 1 ||
-        (precondition != 0 && precondition != 1) || (precondition && V) || (precondition && n > kCoreMaxN))
+        (precondition != 0 && precondition != 1) || (precondition && V))
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_jacobi: bad argument");
     Scratch sc;
     const int64_t nn = (int64_t)n * n;

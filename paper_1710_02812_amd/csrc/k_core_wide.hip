@@ -21,8 +21,12 @@
 // LDS-resident cores; the sweeps stop after one that rotates nothing (or at the sweep
 // cap).  The column norms are the singular values; they are sorted, the rank rule
 // picks r, and the normalised left vectors are written as by the LDS-resident cores.
-// No LQ preconditioning, no skipped set and no right vectors here.
+// As there, a core that wants only left vectors is first replaced by L of G = L Q (a
+// Householder QR of G^T held in registers, three of its columns per 16-lane group):
+// L has G's left singular pairs and columns far closer to orthogonal, which about
+// halves the sweeps of a merge core.  No skipped set and no right vectors here.
 #include "core_common.hpp"
+#include "house_qr.hpp"
 
 namespace hsvd {
 
@@ -182,6 +186,35 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core_wide(double* __restrict__
     }
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
+
+    // ---- LQ preconditioning: row c of G (column c of G^T) in slot c / 64 of group c % 64,
+    // lane rows are G's columns; G^T = Q R leaves R in the registers and L = R^T goes
+    // back to the panel.  Scratch: tau -> sig, the pivot buffers -> the team buffer.
+    if (t.precond && !s_bad && nc > 1) {
+        using QR = HouseQR<16, WT, false, 16, 3, CORE_THREADS>;
+        static_assert(QR::WMAX >= WC && QR::VB == WR, "preconditioner layout");
+        QR q;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int c = q.col_of(s);
+#pragma unroll
+            for (int u = 0; u < WT; ++u) {
+                const int r = gl + 16 * u;
+                q.x[s * WT + u] = (c < nr && r < nc) ? S[(int64_t)r * WR + c] : 0.0;
+            }
+        }
+        q.factor(nc, nr, d, sig, d, L);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int c = q.col_of(s);
+#pragma unroll
+            for (int u = 0; u < WT; ++u) {
+                const int r = gl + 16 * u;
+                if (r < nc && c < WR) S[(int64_t)r * WR + c] = (r <= c) ? q.x[s * WT + u] : 0.0;
+            }
+        }
+        __syncthreads();
+    }
 
     const double tol = t.orth_tol > 0.0 ? t.orth_tol : (double)(nr > 1 ? nr : 1) * kEps;
     const double tol2 = tol * tol;

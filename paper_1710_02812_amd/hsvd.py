@@ -429,8 +429,10 @@ class BatchPlan:
     def __init__(self, shapes, tol: float = 0.0, *, precision: int = FP64, rule: int = RULE_GAMMA,
                  oversample: int | None = None, power_steps: int | None = None,
                  refine_steps: int = 0, max_sweeps: int | None = None, seed: int = 0,
-                 refine_eps: float = 0.0):
-        """shapes: list of (m, n, p, q, k)."""
+                 refine_eps: float = 0.0, thin_rows: int = 0, merge_qr: int = 0, leaf_qr: int = 0,
+                 autotune: bool = False):
+        """shapes: list of (m, n, p, q, k); thin_rows, merge_qr, leaf_qr: launch-shape
+        tunables (0: defaults); autotune: let the plan time and pick them."""
         c = len(shapes)
         i64a, i32a = ctypes.c_int64 * c, ctypes.c_int32 * c
         ms = i64a(*[s[0] for s in shapes])
@@ -440,6 +442,8 @@ class BatchPlan:
         ks = i32a(*[s[4] for s in shapes])
         o = _options(precision, rule, oversample, power_steps, refine_steps, max_sweeps, seed,
                      refine_eps)
+        o.thin_rows, o.merge_qr, o.leaf_qr = thin_rows, merge_qr, leaf_qr
+        o.autotune = 1 if autotune else 0
         h = ctypes.c_void_p()
         _check(lib().hsvd_plan_batched(ctypes.byref(h), c, ms, ns, ps, qs, ks, float(tol), ctypes.byref(o)))
         self._h = h

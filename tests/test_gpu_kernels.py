@@ -119,11 +119,15 @@ def test_jacobi_wide_dense(n):
     M = rng.standard_normal((2, n, n))
     M[1] *= np.exp(-np.arange(n) / 6.0)[None, :]
     print(f"wide jacobi n={n}", flush=True)
-    U, S, _, flags, sweeps = H.debug_jacobi(_t(M), with_v=False)
-    print(f"sweeps {sweeps}", flush=True)
-    assert flags == 0
-    U, S = U.cpu().numpy(), S.cpu().numpy()
-    for b in range(2):
+    for pre in (False, True):
+        U, S, _, flags, sweeps = H.debug_jacobi(_t(M), with_v=False, precondition=pre)
+        print(f"precondition={pre} sweeps {sweeps}", flush=True)
+        assert flags == 0
+        _check_left_pairs(M, U.cpu().numpy(), S.cpu().numpy(), n)
+
+
+def _check_left_pairs(M, U, S, n):
+    for b in range(M.shape[0]):
         s_ref = np.linalg.svd(M[b], compute_uv=False)
         assert np.max(np.abs(S[b] - s_ref)) <= 1e-13 * s_ref[0] * n / 8
         assert np.all(np.diff(S[b]) <= 0)
@@ -137,19 +141,23 @@ def test_jacobi_wide_dense(n):
 @pytest.mark.parametrize("k", [72, 80])
 def test_jacobi_wide_merge_matrix(k):
     """Merge-shaped cores of 2k > 128 columns (two children of rank k sharing most of
-    their directions) on the wide cores: singular values and the top-k left subspace
-    against LAPACK."""
+    their directions) on the wide cores, plain and LQ-preconditioned: singular values
+    and the top-k left subspace against LAPACK; preconditioning takes fewer sweeps."""
     rng = np.random.default_rng(k)
     E = _merge_matrix(rng, k)[None]
-    U, S, _, f, sw = H.debug_jacobi(_t(E), with_v=False)
-    print(f"wide merge core k={k} sweeps {sw}", flush=True)
-    assert f == 0
     s_ref = np.linalg.svd(E[0], compute_uv=False)
-    S = S.cpu().numpy()[0]
-    assert np.max(np.abs(S - s_ref)) <= 1e-13 * s_ref[0] * 2 * k / 8
     Ur = np.linalg.svd(E[0])[0][:, :k]
-    Uk = U.cpu().numpy()[0][:, :k]
-    assert np.linalg.norm(Uk - Ur @ (Ur.T @ Uk), 2) <= 1e-11
+    sweeps = []
+    for pre in (False, True):
+        U, S, _, f, sw = H.debug_jacobi(_t(E), with_v=False, precondition=pre)
+        print(f"wide merge core k={k} precondition={pre} sweeps {sw}", flush=True)
+        assert f == 0
+        S = S.cpu().numpy()[0]
+        assert np.max(np.abs(S - s_ref)) <= 1e-13 * s_ref[0] * 2 * k / 8
+        Uk = U.cpu().numpy()[0][:, :k]
+        assert np.linalg.norm(Uk - Ur @ (Ur.T @ Uk), 2) <= 1e-11
+        sweeps.append(sw)
+    assert sweeps[1] < sweeps[0]
 
 
 def test_jacobi_wide_rank_deficient_zero_and_cap():
