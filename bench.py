@@ -293,7 +293,11 @@ def run_uneven(args, torch):
                           [torch.empty((k,), dtype=dt, device="cuda") for (m, n, _, _, k) in shp],
                           [torch.empty((k, n), dtype=dt, device="cuda") for (m, n, _, _, k) in shp])
     Us, Ss, Vts = mk(shapes, torch.float32)
-    plan = H.BatchPlan(shapes, precision=H.FP32)
+    t = time.time()
+    plan = H.BatchPlan(shapes, precision=H.FP32, autotune=bool(args.autotune))
+    plan_s = time.time() - t
+    tuning = plan.tuning()
+    progress(f"uneven: plan {plan_s:.1f} s, tuning {tuning}")
     for _ in range(args.warmup):
         plan.execute(As, Us, Ss, Vts)
     torch.cuda.synchronize()
@@ -371,6 +375,7 @@ def run_uneven(args, torch):
                                "sigma_i = exp(-i/6), no noise, blocks <= 512, k = rank, float32 storage, "
                                "one batched plan",
                    "count": len(ws), "elements": int(elems), "storage": "f32"},
+        "plan": {"plan_s": round(plan_s, 2), "tuning": tuning},
         "loop_of_plans_ms": round(ms_loop, 3),
         "batched_speedup_vs_loop": round(ms_loop / ms_batched, 3),
         "launches_per_step": launches,

@@ -450,6 +450,10 @@ class BatchPlan:
         self.shapes = [tuple(s) for s in shapes]
         self.precision = precision
 
+    def tuning(self) -> dict:
+        """thin_rows, merge_qr, leaf_qr the plan runs with; tuned, tuned_ms (hsvd_get_tuning)."""
+        return Plan.tuning(self)
+
     def execute(self, As, Us, Ss, Vts, stream=None):
         """Enqueues the method on every matrix (lists of torch device tensors)."""
         import torch
