@@ -430,9 +430,10 @@ class BatchPlan:
                  oversample: int | None = None, power_steps: int | None = None,
                  refine_steps: int = 0, max_sweeps: int | None = None, seed: int = 0,
                  refine_eps: float = 0.0, thin_rows: int = 0, merge_qr: int = 0, leaf_qr: int = 0,
-                 autotune: bool = False):
+                 autotune: bool = False, graph: bool = True):
         """shapes: list of (m, n, p, q, k); thin_rows, merge_qr, leaf_qr: launch-shape
-        tunables (0: defaults); autotune: let the plan time and pick them."""
+        tunables (0: defaults); autotune: let the plan time and pick them; graph: replay a
+        hipGraph captured on the first execute."""
         c = len(shapes)
         i64a, i32a = ctypes.c_int64 * c, ctypes.c_int32 * c
         ms = i64a(*[s[0] for s in shapes])
@@ -444,6 +445,7 @@ class BatchPlan:
                      refine_eps)
         o.thin_rows, o.merge_qr, o.leaf_qr = thin_rows, merge_qr, leaf_qr
         o.autotune = 1 if autotune else 0
+        o.graph = 1 if graph else 0
         h = ctypes.c_void_p()
         _check(lib().hsvd_plan_batched(ctypes.byref(h), c, ms, ns, ps, qs, ks, float(tol), ctypes.byref(o)))
         self._h = h
