@@ -34,7 +34,9 @@ Other workloads: --workload snapshot (8192^2 snapshot-like field, k = 50), uneve
 (Algorithm 2 to a tolerance).
 
 --copy-probe runs a plain device copy (torch.mul by 1.0, one read and one write
-of a known size) for scaling the FETCH_SIZE / WRITE_SIZE counters.
+of a known size) for scaling the FETCH_SIZE / WRITE_SIZE counters.  --peak-probe
+runs the library's own peak probes (HBM read and copy, matrix-core chains) and
+prints the rates they reach beside the published peaks.
 """
 from __future__ import annotations
 
@@ -102,6 +104,9 @@ def parse():
                          "the signal's RMS entry (cut in the clean exp(-i/10) decay)")
     ap.add_argument("--cpu-runs", type=int, default=5,
                     help="c2: oracle sample runs at BLAS threads = physical cores, and as many at 1 thread")
+    ap.add_argument("--peak-probe", type=int, default=0, metavar="MIB",
+                    help="run the library's own peak probes (HBM read and copy over MIB MiB, "
+                         "matrix-core chains) and print their rates beside the published peaks")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -138,6 +143,43 @@ def copy_probe(mib: int):
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                       "launches": 5}))
+
+
+PUBLISHED = {"hbm_tb_s": 8.0, "mfma_f64_tflop_s": 78.6, "mfma_bf16_tflop_s": 2500.0, "mfma_f32_tflop_s": 157.3}
+
+
+def peak_probe(mib: int, reps: int = 5):
+    """The library's own peak probes (hsvd_debug_probe): streaming read and copy of
+    `mib` MiB, and chains of float64, bfloat16 and float32 matrix-core instructions;
+    best of `reps` launches each, beside the published peaks."""
+    import torch
+    from paper_1710_02812_amd import hsvd as H
+    buf = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for kind, iters in (("read", 0), ("copy", 0), ("mfma_f64", 4096), ("mfma_bf16", 4096), ("mfma_f32", 4096)):
+        best = None
+        for _ in range(reps + 1):                     # the first launch is a warm-up
+            ms, work = H.debug_probe(kind, buf if kind in ("read", "copy") else None, iters)
+            rate = work / (ms * 1e-3)
+            best = rate if best is None else max(best, rate)
+        out[kind] = best
+    res = {
+        "hbm_read_tb_s": round(out["read"] / 1e12, 3),
+        "hbm_copy_tb_s": round(out["copy"] / 1e12, 3),
+        "mfma_f64_tflop_s": round(out["mfma_f64"] / 1e12, 2),
+        "mfma_bf16_tflop_s": round(out["mfma_bf16"] / 1e12, 1),
+        "mfma_f32_tflop_s": round(out["mfma_f32"] / 1e12, 2),
+        "buffer_mib": mib, "reps": reps, "published": PUBLISHED,
+    }
+    res["frac_of_published"] = {
+        "hbm_read": round(res["hbm_read_tb_s"] / PUBLISHED["hbm_tb_s"], 3),
+        "hbm_copy": round(res["hbm_copy_tb_s"] / PUBLISHED["hbm_tb_s"], 3),
+        "mfma_f64": round(res["mfma_f64_tflop_s"] / PUBLISHED["mfma_f64_tflop_s"], 3),
+        "mfma_bf16": round(res["mfma_bf16_tflop_s"] / PUBLISHED["mfma_bf16_tflop_s"], 3),
+        "mfma_f32": round(res["mfma_f32_tflop_s"] / PUBLISHED["mfma_f32_tflop_s"], 3),
+    }
+    print(json.dumps(res))
 
 
 def time_path(H, torch, A, prec, args, k=50, p=8, q=8, **opts):
@@ -793,6 +835,9 @@ def main():
     import torch
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.peak_probe:
+        peak_probe(args.peak_probe)
         return
     if args.workload == "uneven":
         run_uneven(args, torch)

@@ -84,6 +84,22 @@ hsvd_status hsvd_debug_cholqr(const double* P, int32_t batch, int64_t h, int32_t
 hsvd_status hsvd_debug_panel_qr(const double* P, int32_t batch, int64_t h, int32_t w, double* Q,
                                 double* R, int32_t* fell_back, hipStream_t stream);
 
+/* Peak probes of the device (measurement only, no part of the method): the rates a
+ * plain kernel of this library reaches, beside which the method's kernels are read.
+ *   kind 0: streams the first `bytes` of buf through 16-byte loads (HBM read rate);
+ *   kind 1: copies the first half of those bytes onto the second half (read + write);
+ *   kinds 2, 3, 4: every wave runs 4 independent accumulation chains of `iters`
+ *   float64 16x16x4, bfloat16 16x16x32 (float32 sums) or float32 16x16x4 matrix-core
+ *   instructions, 8 waves on every SIMD; buf is not used.
+ * buf: device memory of at least `bytes` bytes, 16-byte aligned (kinds 0 and 1).
+ * Blocks until the launch is done: *ms_host receives its duration (HIP events around
+ * it on `stream`), *work_host the bytes moved (kinds 0, 1) or the flops (kinds 2-4).
+ * Errors: HSVD_ERR_INVALID for null outputs, kind outside 0..4, bytes < 32 or an
+ * unaligned buf (kinds 0, 1), iters outside 1..2^24 (kinds 2-4); HSVD_ERR_ALLOC,
+ * HSVD_ERR_HIP.                                                                       */
+hsvd_status hsvd_debug_probe(int32_t kind, void* buf, int64_t bytes, int32_t iters, double* ms_host,
+                             double* work_host, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -388,3 +388,31 @@ extern "C" hsvd_status hsvd_debug_panel_qr(const double* P, int32_t batch, int64
     for (int b = 0; b < batch; ++b) fell_back[b] = flags[(size_t)b * iper + nodes];
     return HSVD_OK;
 }
+
+extern "C" hsvd_status hsvd_debug_probe(int32_t kind, void* buf, int64_t bytes, int32_t iters, double* ms_host,
+                                        double* work_host, hipStream_t stream) {
+    using hsvd_detail::set_error;
+    const bool mem = kind == 0 || kind == 1;
+    if (!ms_host || !work_host || kind < 0 || kind > 4 ||
+        (mem && (!buf || bytes < 32 || ((uintptr_t)buf & 15))) || (!mem && (iters < 1 || iters > (1 << 24))))
+        return set_error(HSVD_ERR_INVALID, "hsvd_debug_probe: bad argument");
+    Scratch sc;
+    float* sink = sc.get<float>(2048);
+    if (!sink) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    double work = 0.0;
+    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+    if (e == hipSuccess) e = launch_probe(kind, buf, bytes, iters, sink, &work, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    for (hipEvent_t x : ev)
+        if (x) hipEventDestroy(x);
+    if (e != hipSuccess) return set_error(HSVD_ERR_HIP, std::string("hsvd_debug_probe: ") + hipGetErrorString(e));
+    *ms_host = ms;
+    *work_host = work;
+    return HSVD_OK;
+}

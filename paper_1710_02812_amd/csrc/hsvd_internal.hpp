@@ -279,6 +279,10 @@ hipError_t launch_core(double* ws, int* iws, const CoreTask* tasks, int ntasks, 
                        const int* guard = nullptr);
 hipError_t launch_core_wide(double* ws, int* iws, const CoreTask* tasks, int ntasks, int maxdim,
                             int max_sweeps, unsigned* flags, hipStream_t s, const int* guard);
+// Peak probes (measurement only): kind 0 read, 1 copy, 2 / 3 / 4 float64 / bfloat16 /
+// float32 matrix cores; `sink` holds 2048 floats; *work gets the bytes or flops.
+hipError_t launch_probe(int kind, void* buf, int64_t bytes, int iters, float* sink, double* work,
+                        hipStream_t s);
 hipError_t launch_mlp_train(float* master, float* m1, float* m2, const float* X, const float* T,
                             int count, int steps, int s0, int t0, float lr, float* grad_out,
                             float* loss_out, hipStream_t s);

@@ -36,7 +36,7 @@ EXPORTED = ["hsvd_default_options", "hsvd_plan", "hsvd_plan_ex", "hsvd_execute",
             "hsvd_debug_jacobi", "hsvd_debug_tsqr", "hsvd_debug_cholqr", "hsvd_debug_panel_qr",
             "hsvd_debug_plan_check", "hsvd_svd_static", "hsvd_set_workspace", "hsvd_set_rank_model",
             "hsvd_get_leaf_widths", "hsvd_plan_gram", "hsvd_get_tuning",
-            "hsvd_debug_gemm",
+            "hsvd_debug_gemm", "hsvd_debug_probe",
             "hsvd_debug_plan_check_batched"]
 LAUNCH_KINDS = ["gemm_ax", "gemm_atx", "tsqr_factor", "tsqr_apply", "gram", "reduce", "thin_nn",
                 "sum", "core", "output", "gemm_ax_bf16", "gemm_atx_bf16", "energy", "features", "cholqr",
@@ -112,6 +112,7 @@ def lib() -> ctypes.CDLL:
     L.hsvd_debug_cholqr.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
     L.hsvd_debug_panel_qr.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
     L.hsvd_debug_gemm.argtypes = [i32, i32, i32, vp, i64, i64, i64, vp, i32, vp, vp]
+    L.hsvd_debug_probe.argtypes = [i32, vp, i64, i32, P(f64), P(f64), vp]
     L.hsvd_debug_plan_check.argtypes = [i64, i64, i32, i32, i32, f64, P(Options),
                                         P(ctypes.c_size_t)]
     L.hsvd_svd_static.argtypes = [i64, i64, i32, i32, i32, f64, P(Options), vp, vp, vp, vp, P(i32), vp]
@@ -603,6 +604,20 @@ def debug_jacobi(M, max_sweeps: int = 40, with_v: bool = True, precondition: boo
                                    int(precondition), ctypes.byref(fl), _stream_handle()))
     return (U.transpose(1, 2), S, V.transpose(1, 2) if with_v else None, fl.value & 0xFFFF,
             fl.value >> 16)
+
+
+PROBE_KINDS = {"read": 0, "copy": 1, "mfma_f64": 2, "mfma_bf16": 3, "mfma_f32": 4}
+
+
+def debug_probe(kind: str, buf=None, iters: int = 0, stream=None):
+    """One peak-probe launch (hsvd_debug_probe): (ms, bytes or flops).  buf: a torch
+    device tensor for the memory probes (its whole size is streamed)."""
+    ms, work = ctypes.c_double(), ctypes.c_double()
+    ptr = buf.data_ptr() if buf is not None else None
+    nbytes = buf.numel() * buf.element_size() if buf is not None else 0
+    _check(lib().hsvd_debug_probe(PROBE_KINDS[kind], ptr, nbytes, iters, ctypes.byref(ms), ctypes.byref(work),
+                                  _stream_handle(stream)))
+    return ms.value, work.value
 
 
 def plan_check(m: int, n: int, p: int, q: int, k: int, tol: float = 0.0, **opts) -> int:

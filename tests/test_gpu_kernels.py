@@ -400,3 +400,22 @@ def test_gemm_bf16_matrix_cores(rows, cols, op, N):
     A64 = A.astype(np.float64)
     ref64 = (A64 @ X) if op == 0 else (A64.T @ X)
     assert np.max(np.abs(Y64 - ref64)) <= 1e-13 * np.max(np.abs(ref64)) * np.sqrt(K)
+
+
+def test_peak_probes_are_plausible():
+    """The library's peak probes: each reports the work it did and a rate below the
+    device's published peak (HBM 8 TB/s; float64, bfloat16, float32 matrix cores 78.6,
+    2500, 157.3 TFLOP/s), and above a tenth of it."""
+    buf = torch.ones(64 << 20, dtype=torch.float32, device=DEV)       # 256 MiB
+    for kind, peak in (("read", 8e12), ("copy", 8e12), ("mfma_f64", 78.6e12),
+                       ("mfma_bf16", 2500e12), ("mfma_f32", 157.3e12)):
+        mem = kind in ("read", "copy")
+        H.debug_probe(kind, buf if mem else None, 0 if mem else 256)      # warm-up
+        ms, work = H.debug_probe(kind, buf if mem else None, 0 if mem else 2048)
+        rate = work / (ms * 1e-3)
+        print(f"probe {kind}: {rate / 1e12:.2f} T/s", flush=True)
+        if mem:                  # read streams the buffer; copy reads one half, writes the other
+            assert work == buf.numel() * 4
+        assert 0.1 * peak < rate <= 1.05 * peak, (kind, rate)
+    with pytest.raises(H.HsvdError):
+        H.debug_probe("mfma_f64", None, 0)
