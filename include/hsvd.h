@@ -191,8 +191,11 @@ hsvd_status hsvd_execute(hsvd_plan_t plan, const void* A, void* U, void* S, void
  * merges of different matrices are independent), executed together: every launch
  * of an execute covers the same stage of all matrices.  m[i], n[i], p[i], q[i],
  * k[i] (host arrays) describe matrix i with the same constraints as hsvd_plan_ex;
- * tol and opt apply to all.  The panels of the batch share one width (max k) and
- * one sketch width; each matrix keeps its own rank cap k[i].
+ * tol and opt apply to all.  Each matrix keeps its own rank cap k[i] and takes its own
+ * sketch width (k[i] + oversample, rounded up to a multiple of 8, at most 80); the
+ * matrices are grouped into at most 4 rank classes of adjacent sketch widths, each
+ * class running its whole pipeline with the panel width of its largest k[i], the
+ * classes concurrently (a batch stopping Algorithm 2 on refine_eps runs as one class).
  * HSVD_ERR_INVALID names the first bad matrix; count must be 1..65535.         */
 hsvd_status hsvd_plan_batched(hsvd_plan_t* out, int32_t count, const int64_t* m, const int64_t* n,
                               const int32_t* p, const int32_t* q, const int32_t* k, double tol,

@@ -468,6 +468,37 @@ def test_graph_replays_match_direct_launches(prec, m, p, k):
     pe.close()
 
 
+def test_batched_rank_classes_graph_replays_match_direct_launches():
+    """A batch whose matrices fall into several rank classes (concurrent branches of the
+    captured graph, wide merge cores among them): every replay, across alternating inputs
+    with eager work and synchronisations between them, is bit-identical to a plan of the
+    same batch that launches its kernels one by one."""
+    ws = _uneven(6, 1100, 80, seed=22)
+    shapes = [(w.A.shape[0], w.A.shape[1], w.p, w.q, w.k) for w in ws]
+    inputs = [[torch.tensor(s * w.A, dtype=torch.float32, device=DEV) for w in ws] for s in (1.0, 0.5)]
+    mk = lambda: ([torch.empty((m, k), dtype=torch.float32, device=DEV) for (m, n, _, _, k) in shapes],
+                  [torch.empty((k,), dtype=torch.float32, device=DEV) for (m, n, _, _, k) in shapes],
+                  [torch.empty((k, n), dtype=torch.float32, device=DEV) for (m, n, _, _, k) in shapes])
+    pg = H.BatchPlan(shapes, precision=H.FP32, graph=True)
+    pe = H.BatchPlan(shapes, precision=H.FP32, graph=False)
+    og, oe = mk(), mk()
+    for it in range(4):
+        As = inputs[it % 2]
+        print(f"batched graph replay {it}", flush=True)
+        pg.execute(As, *og)
+        junk = As[0].double() @ As[0].double().T
+        torch.cuda.synchronize()
+        pe.execute(As, *oe)
+        torch.cuda.synchronize()
+        assert float(junk[0, 0]) == float(junk[0, 0])
+        for xg, xe in zip(og, oe):
+            for a, b in zip(xg, xe):
+                assert torch.equal(a, b), it
+        assert pg.ranks() == pe.ranks() == [w.k for w in ws]
+    pg.close()
+    pe.close()
+
+
 def test_set_workspace_from_torch_memory():
     """hsvd_set_workspace moves a plan's arena into a torch-allocated buffer: executes
     before and after the move (and after a second move) give bit-identical results; a
