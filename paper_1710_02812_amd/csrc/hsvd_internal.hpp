@@ -169,11 +169,12 @@ constexpr int64_t kWideScratch = (int64_t)kWideCoreRows * kWideCoreMaxN;
 constexpr int kMaxRank = kWideCoreMaxN / 2;
 
 // Column-orthogonality threshold of the mixed-precision plans' tree cores (leaves,
-// merges, slab re-projections): their inputs carry bfloat16 rounding (2^-9 relative),
-// so sweeps past cosines of about sqrt(2^-52) change nothing the result can see; the
-// projection and Algorithm 2 cores, which set the output's orthonormality, keep the
-// working-precision threshold.
-constexpr double kMixedOrthTol = 1e-8;
+// merges, slab re-projections): their inputs carry bfloat16 rounding (2^-9, about 2e-3
+// relative), so cosines of 1e-5, two orders below it, leave left vectors whose error
+// (about the threshold times sigma_1 over the gap at the cut) stays below the input's
+// own; the projection and Algorithm 2 cores, which set the output's orthonormality and
+// refine against the unrounded input, keep the working-precision threshold.
+constexpr double kMixedOrthTol = 1e-5;
 
 // ---------------------------------------------------------------- output
 struct OutputArgs {
