@@ -457,9 +457,10 @@ void push_core(hsvd_plan_st& P, const std::vector<CoreTask>& tasks, int maxdim, 
     P.stages.push_back(s);
 }
 
-// The tree cores' orthogonality threshold: loose on mixed-precision plans.
+// The tree cores' orthogonality threshold: loose on mixed-precision and float32-storage
+// plans, below their inputs' own rounding.
 double tree_orth_tol(const hsvd_plan_st& P) {
-    return P.opt.precision == HSVD_MIXED_BF16 ? kMixedOrthTol : 0.0;
+    return P.opt.precision == HSVD_MIXED_BF16 ? kMixedOrthTol : P.opt.precision == HSVD_FP32 ? kF32OrthTol : 0.0;
 }
 
 CoreTask core_defaults(const hsvd_plan_st& P, int k) {

@@ -175,6 +175,9 @@ constexpr int kMaxRank = kWideCoreMaxN / 2;
 // own; the projection and Algorithm 2 cores, which set the output's orthonormality and
 // refine against the unrounded input, keep the working-precision threshold.
 constexpr double kMixedOrthTol = 1e-5;
+// The same for float32-storage plans, whose inputs carry float32 rounding (2^-24,
+// about 6e-8): 1e-9, two orders below it.
+constexpr double kF32OrthTol = 1e-9;
 
 // ---------------------------------------------------------------- output
 struct OutputArgs {
