@@ -255,6 +255,14 @@ bool use_panel_qr(const hsvd_plan_st& P, size_t npanels, int64_t hmax, int w) {
     return P.leaf_qr == 1 || npanels >= 128;
 }
 
+// Tall panels wider than the Cholesky QR's 64 columns (slab re-projections, projections
+// and Algorithm 2 panels of rank caps above 64): the one-launch panel QR, one work-group
+// per panel, when a launch has at least 128 of them; fewer keep the chunked Householder
+// TSQR, whose chunks spread each panel over several work-groups.
+bool wide_panel_qr(size_t npanels, int w) {
+    return w > 64 && w <= kPanelQrMaxW && npanels >= 128;
+}
+
 // Adds TSQR bookkeeping for a panel; returns index into tb.tasks.  cholqr: the panel
 // (expected well-conditioned) first tries two Cholesky QR passes, the Householder
 // kernels running only if they fall back (panels up to 64 columns).
@@ -994,9 +1002,10 @@ std::vector<std::vector<Node>> build_reprojection(hsvd_plan_st& P, const std::ve
         gt.push_back(t);
     }
     push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_BF16 : MMA_F64);
+    const bool pq = wide_panel_qr(roots.size(), W);
     for (size_t i = 0; i < roots.size(); ++i) {
         const int n = (int)P.mats[roots[i].mat].n;
-        add_tsqr(P, tb, Zs[i], n, n, W, ch, true);
+        add_tsqr(P, tb, Zs[i], n, n, W, ch, true, pq ? P.alloc((int64_t)n * W) : -1, n);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<CoreTask> cores;
@@ -1083,9 +1092,10 @@ std::vector<Factors> build_projection(hsvd_plan_st& P, const std::vector<Node>& 
     push_gemm(P, 0, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_F32 : MMA_F64);
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
+    const bool pq = wide_panel_qr(vs.size(), W);
     for (size_t mi = 0; mi < vs.size(); ++mi) {
         const int m = (int)P.mats[vs[mi].mat].m;
-        add_tsqr(P, tb, Ys[mi], m, m, W, ch, true);
+        add_tsqr(P, tb, Ys[mi], m, m, W, ch, true, pq ? P.alloc((int64_t)m * W) : -1, m);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<Factors> fs(vs.size());
@@ -1171,9 +1181,10 @@ std::vector<Factors> build_refine_step(hsvd_plan_st& P, const std::vector<Factor
     push_gemm(P, 1, gt, W, P.opt.precision == HSVD_MIXED_BF16 ? MMA_F32 : MMA_F64);
     push_thin(P, ST_SUM, sums);
     TsqrBuild tb;
+    const bool pq = wide_panel_qr(in.size(), W);
     for (size_t mi = 0; mi < in.size(); ++mi) {
         const int n = (int)P.mats[in[mi].mat].n;
-        add_tsqr(P, tb, Zs[mi], n, n, W, ch, true);
+        add_tsqr(P, tb, Zs[mi], n, n, W, ch, true, pq ? P.alloc((int64_t)n * W) : -1, n);
     }
     push_tsqr_factor(P, tb, W, ch);
     std::vector<Factors> fs(in.size());

@@ -388,6 +388,33 @@ def test_batched_uneven_wide_fp64():
         assert np.max(np.abs(S.cpu().numpy()[:r] - w.meta["sigma"])) <= 1e-12
 
 
+def test_batched_wide_tall_panels_take_the_panel_qr():
+    """A batch of 132 matrices of rank caps 65..72 (panels wider than the Cholesky QR's
+    64 columns, and enough of them for the one-launch panel QR in the re-projection,
+    projection and Algorithm 2 steps): every matrix matches the oracle at the float64
+    gate and recovers its rank; float32 storage at its gate."""
+    rng = np.random.default_rng(132)
+    ws = []
+    for j in range(132):
+        m, n = int(rng.integers(200, 321)), int(rng.integers(200, 321))
+        k = int(rng.integers(65, 73))
+        A, *_ = synth.low_rank(rng, m, n, np.exp(-np.arange(k) / 8.0), noise=0.0)
+        ws.append((A, k))
+    shapes = [(A.shape[0], A.shape[1], 1, 1, k) for A, k in ws]
+    print("batched wide tall panels", len(ws), flush=True)
+    for dt, gate, opts in ((torch.float64, 1e-10, {}), (torch.float32, 1e-5, {"refine_steps": 1})):
+        As = [torch.tensor(A, dtype=dt, device=DEV) for A, _ in ws]
+        outs = H.svd_batched(As, [1] * len(ws), [1] * len(ws), [k for _, k in ws], **opts)
+        torch.cuda.synchronize()
+        for (A, k), (U, S, Vt, r) in zip(ws[::11], outs[::11]):
+            Ao = A if dt == torch.float64 else A.astype(np.float32).astype(np.float64)
+            Uo, so, Vto, ro = oracle.hsvd(Ao, 1, 1, k, 0.0, refine=opts.get("refine_steps", 0))
+            assert r == ro == k
+            c = metrics.compare(U.double().cpu().numpy(), S.double().cpu().numpy(),
+                                Vt.double().cpu().numpy(), r, Uo, so, Vto, ro)
+            assert c["e_sigma"] <= gate and c["e_frob"] <= gate, (A.shape, k, c)
+
+
 def test_batched_uneven_fp32_and_mixed():
     ws = _uneven(8, 1500, 48, seed=5)
     As = [torch.tensor(w.A.astype(np.float32), device=DEV) for w in ws]
