@@ -11,9 +11,9 @@
 //     [column][k] so that a lane's B operand (8 consecutive k) is one 16-byte read;
 //   * op 0: a lane's A operand is 8 consecutive floats of one row of A, read straight
 //     from global memory as two 16-byte loads (4 lanes cover 128 contiguous bytes);
-//   * op 1: the slab of A (64 rows x 256 columns) is read as rows (8-byte loads, a
-//     wave covers 512 contiguous bytes), transposed on the way into LDS by packing 8
-//     rows of a column into one 16-byte store, then read as A operands like X.
+//   * op 1: the slab of A (64 rows x 256 columns) is read as rows (16-byte loads, a
+//     wave covers 1 KB of a row), transposed on the way into LDS by packing 8 rows of a
+//     column into one 16-byte store, then read as A operands like X.
 // Slabs are double-buffered (one barrier per slab) and the next slab's global loads
 // are issued before the current slab's matrix-core work (op 0 keeps A one slab
 // ahead, X two: its panel comes through L2 from other XCDs' writes).  Work-groups
@@ -102,39 +102,38 @@ __global__ __launch_bounds__(BT) void k_gemm_bf16(const void* const* __restrict_
     // ---- A operand
     // op 0: per wave 2 row tiles x 2 k-steps of 8 floats (direct fragments, below)
     // op 1: the slab of A is 64 rows x 256 columns; item (row group g of 8 rows, column
-    // pair c2): 4 items per thread (8 row groups x 128 column pairs / 512 threads)
-    constexpr int AI = (BK / 8) * (BM / 2) / BT;
-    f32x2 at[AI][8];
+    // quad c4): one per thread (8 row groups x 64 column quads = 512), a 16-byte load per
+    // row, a wave's load covering 1 KB of one row
+    constexpr int AQ = BM / 4;                    // column quads of a slab row
+    static_assert((BK / 8) * AQ == BT, "one op-1 item per thread");
+    f32x4 at[8];
     auto load_a1 = [&](int k0) {
+        const int g = tid / AQ, c4 = tid % AQ;
+        const int gc = r0 + 4 * c4;               // output rows are columns of A
 #pragma unroll
-        for (int u = 0; u < AI; ++u) {
-            const int it = tid + BT * u, g = it / (BM / 2), c2 = it % (BM / 2);
-            const int gc = r0 + 2 * c2;           // output rows are columns of A
+        for (int e = 0; e < 8; ++e) {
+            const int gk = k0 + 8 * g + e;
+            const float* src = Ab + (int64_t)gk * lda + gc;
+            f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (gk < K) {
+                if (gc + 4 <= out_rows && ((uintptr_t)src & 15) == 0) v = *(const f32x4*)src;
+                else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gk = k0 + 8 * g + e;
-                const float* src = Ab + (int64_t)gk * lda + gc;
-                f32x2 v = {0.0f, 0.0f};
-                if (gk < K) {
-                    if (gc + 1 < out_rows && ((uintptr_t)src & 7) == 0) v = *(const f32x2*)src;
-                    else {
-                        if (gc < out_rows) v[0] = src[0];
-                        if (gc + 1 < out_rows) v[1] = src[1];
-                    }
+                    for (int q = 0; q < 4; ++q)
+                        if (gc + q < out_rows) v[q] = src[q];
                 }
-                at[u][e] = v;
             }
+            at[e] = v;
         }
     };
     auto store_a1 = [&](__bf16* dst) {
+        const int g = tid / AQ, c4 = tid % AQ;
 #pragma unroll
-        for (int u = 0; u < AI; ++u) {
-            const int it = tid + BT * u, g = it / (BM / 2), c2 = it % (BM / 2);
-            float c0[8], c1[8];
+        for (int q = 0; q < 4; ++q) {
+            float c[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) { c0[e] = at[u][e][0]; c1[e] = at[u][e][1]; }
-            *(bf16x8*)&dst[(2 * c2) * PK + 8 * g] = to_bf16x8(c0);
-            *(bf16x8*)&dst[(2 * c2 + 1) * PK + 8 * g] = to_bf16x8(c1);
+            for (int e = 0; e < 8; ++e) c[e] = at[e][q];
+            *(bf16x8*)&dst[(4 * c4 + q) * PK + 8 * g] = to_bf16x8(c);
         }
     };
 
