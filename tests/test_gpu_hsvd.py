@@ -392,7 +392,7 @@ def test_batched_wide_tall_panels_take_the_panel_qr():
     """A batch of 132 matrices of rank caps 65..72 (panels wider than the Cholesky QR's
     64 columns, and enough of them for the one-launch panel QR in the re-projection,
     projection and Algorithm 2 steps): every matrix matches the oracle at the float64
-    gate and recovers its rank; float32 storage at its gate."""
+    gate and recovers its rank; float32 storage and the mixed path at their gates."""
     rng = np.random.default_rng(132)
     ws = []
     for j in range(132):
@@ -402,7 +402,8 @@ def test_batched_wide_tall_panels_take_the_panel_qr():
         ws.append((A, k))
     shapes = [(A.shape[0], A.shape[1], 1, 1, k) for A, k in ws]
     print("batched wide tall panels", len(ws), flush=True)
-    for dt, gate, opts in ((torch.float64, 1e-10, {}), (torch.float32, 1e-5, {"refine_steps": 1})):
+    for dt, gate, opts in ((torch.float64, 1e-10, {}), (torch.float32, 1e-5, {"refine_steps": 1}),
+                           (torch.float32, 1e-3, {"mixed": True})):
         As = [torch.tensor(A, dtype=dt, device=DEV) for A, _ in ws]
         outs = H.svd_batched(As, [1] * len(ws), [1] * len(ws), [k for _, k in ws], **opts)
         torch.cuda.synchronize()
