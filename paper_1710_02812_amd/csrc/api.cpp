@@ -86,6 +86,8 @@ struct Stage {
     int branch = 0;
     int done_slot = -1;  // leaf check: int-arena slot of its leaf class's "all converged"
     int pw = 0;          // panel width of the matrices the stage works on
+    int ordered = 0;     // panel QR: the tasks run in the dispatch order at order_off
+    size_t order_off = 0;
 };
 
 int pow2floor(int x) {
@@ -308,6 +310,14 @@ void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch, bool 
         q.ch = ch;
         q.need_r = need_r ? 1 : 0;
         q.tasks_off = P.put(tb.tasks);
+        // one work-group per panel: the tallest panels first, so that a launch over
+        // panels of uneven heights (a batch) does not end on its longest work-groups
+        std::vector<int> order(tb.tasks.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return tb.tasks[a].h > tb.tasks[b].h; });
+        q.ordered = 1;
+        q.order_off = P.put(order);
         P.stages.push_back(q);
     }
     if (tb.cholqr) {
@@ -455,7 +465,13 @@ void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks) {
     P.stages.push_back(s);
 }
 
-void push_core(hsvd_plan_st& P, const std::vector<CoreTask>& tasks, int maxdim, int with_v) {
+// One work-group per core: the widest cores first (a merge core's width is at most twice
+// its rank cap), so that a launch over cores of uneven widths does not end on its longest
+// work-groups; cores of one width keep their order.
+void push_core(hsvd_plan_st& P, std::vector<CoreTask> tasks, int maxdim, int with_v) {
+    auto width = [](const CoreTask& t) { return t.mode == CORE_MERGE ? 2 * t.kcap : t.dim; };
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [&](const CoreTask& a, const CoreTask& b) { return width(a) > width(b); });
     Stage s{};
     s.kind = ST_CORE;
     s.n = (int)tasks.size();
@@ -1678,6 +1694,14 @@ std::string validate_plan(const hsvd_plan_st& P) {
             case ST_PQR: {
                 const TsqrTask* T = (const TsqrTask*)(b + s.tasks_off);
                 if (s.w < 1 || s.w > kPanelQrMaxW) return "panel qr width";
+                if (s.ordered) {
+                    const int* O = (const int*)(b + s.order_off);
+                    std::vector<char> seen((size_t)s.n, 0);
+                    for (int i = 0; i < s.n; ++i) {
+                        if (O[i] < 0 || O[i] >= s.n || seen[(size_t)O[i]]) return "panel qr order";
+                        seen[(size_t)O[i]] = 1;
+                    }
+                }
                 for (int i = 0; i < s.n; ++i) {
                     const TsqrTask& t = T[i];
                     if (t.pq_q_off < 0) continue;
@@ -1795,7 +1819,8 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             break;
         }
         case ST_PQR:
-            e = launch_panel_qr(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off), s.n, s.w, s.need_r, st, guard);
+            e = launch_panel_qr(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off), s.n, s.w, s.need_r, st, guard,
+                                s.ordered ? (const int*)(b + s.order_off) : nullptr);
             break;
         case ST_TSQR_F:
             e = launch_tsqr_factor(P.ws, P.iws, (const TsqrTask*)(b + s.tasks_off),

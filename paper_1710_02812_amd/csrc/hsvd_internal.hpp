@@ -250,8 +250,9 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
 // repeated Cholesky QR, the first pass shifted; need_r also forms R at r_out.
 constexpr int kPanelQrMaxW = 96;
 constexpr int kPanelQrMaxPass = 4;
+// `order` (device, ntasks task indices, or nullptr for task order): the dispatch order
 hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntasks, int w, int need_r,
-                           hipStream_t s, const int* guard = nullptr);
+                           hipStream_t s, const int* guard = nullptr, const int* order = nullptr);
 hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s, const int* guard = nullptr);

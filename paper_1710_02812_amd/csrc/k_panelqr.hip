@@ -124,7 +124,8 @@ __device__ __forceinline__ void pq_steps(double (&x)[2][16], double (&dpiv)[2], 
 
 __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws, int* __restrict__ iws,
                                                          const TsqrTask* __restrict__ tasks, int w, int need_r,
-                                                         const int* __restrict__ guard) {
+                                                         const int* __restrict__ guard,
+                                                         const int* __restrict__ order) {
     if (guard && *guard) return;                  // a skipped stage (every group returns)
     extern __shared__ double pq_sm[];
     double* Ga = pq_sm;                           // G, then the multipliers, then M
@@ -134,7 +135,9 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws
     __shared__ int s_fail;
     __shared__ double s_rho[8];
     __shared__ double s_tr[8];
-    const TsqrTask t = tasks[blockIdx.x];
+    // panels in the launch's dispatch order (tallest first: the longest work-groups start
+    // first and the launch's tail is short), or in task order
+    const TsqrTask t = tasks[order ? order[blockIdx.x] : (int)blockIdx.x];
     if (t.pq_q_off < 0) return;
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -351,13 +354,13 @@ hipError_t prepare_panel_qr_launches() {
 }
 
 hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntasks, int w, int need_r,
-                           hipStream_t s, const int* guard) {
+                           hipStream_t s, const int* guard, const int* order) {
     if (ntasks <= 0) return hipSuccess;
     if (w < 1 || w > kPanelQrMaxW) return hipErrorInvalidValue;
     hipError_t e = prepare_panel_qr_launches();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_panel_qr, dim3(ntasks), dim3(PQ_THREADS), PQ_LDS_BYTES, s, ws, iws, tasks, w, need_r,
-                       guard);
+                       guard, order);
     return hipGetLastError();
 }
 
