@@ -64,7 +64,7 @@ hsvd_status hip_fail(hipError_t e, const char* what) {
 }
 
 enum StageKind { ST_GEMM, ST_TSQR_F, ST_TSQR_A, ST_GRAM, ST_REDUCE, ST_NN, ST_SUM, ST_CORE, ST_ENERGY, ST_CQ1, ST_CQ2,
-                 ST_FEAT, ST_LEAFCHECK, ST_PQR, ST_GRAMX };
+                 ST_FEAT, ST_LEAFCHECK, ST_PQR, ST_GRAMX, ST_ESUM };
 
 struct Stage {
     StageKind kind;
@@ -88,6 +88,7 @@ struct Stage {
     int pw = 0;          // panel width of the matrices the stage works on
     int ordered = 0;     // panel QR: the tasks run in the dispatch order at order_off
     size_t order_off = 0;
+    int64_t e_part = -1; // gemm (op 0, float64 matrix cores): per-tile partial block energies
 };
 
 int pow2floor(int x) {
@@ -421,9 +422,12 @@ void push_tsqr_apply(hsvd_plan_st& P, const TsqrBuild& tb, const std::vector<App
 // A pass over A on the float64 matrix cores (mma 0, 64 x 64 tiles), the bfloat16 ones
 // (mma 1) or the float32 ones (mma 2; both in strips of 256 rows holding every column).
 enum { MMA_F64 = 0, MMA_BF16 = 1, MMA_F32 = 2 };
-void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int mma = MMA_F64) {
+// Returns each task's range of tiles (first, count) in the launch.
+std::vector<std::pair<int, int>> push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N,
+                                           int mma = MMA_F64) {
     if (P.trans) op = 1 - op;                     // logical A_blk X = (stored block)^T X
     std::vector<TileRef> tiles;
+    std::vector<std::pair<int, int>> ranges;
     const bool strip = mma != MMA_F64;
     const int nct = strip ? 1 : (N + 63) / 64;
     const int th = strip ? kBf16TileRows : 64;
@@ -431,6 +435,7 @@ void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int 
         const int out_rows = (op == 0) ? tasks[t].rows : tasks[t].cols;
         const int nrt = (out_rows + th - 1) / th;
         tasks[t].tiles = nrt;
+        ranges.push_back({(int)tiles.size(), nrt * nct});
         for (int i = 0; i < nrt * nct; ++i) tiles.push_back({(int)t, i});
     }
     Stage s{};
@@ -443,6 +448,27 @@ void push_gemm(hsvd_plan_st& P, int op, std::vector<GemmTask> tasks, int N, int 
     s.N = N;
     s.tasks_off = P.put(tasks);
     s.refs_off = P.put(tiles);
+    P.stages.push_back(s);
+    return ranges;
+}
+
+// A sketch pass Y = A_blk X on the float64 matrix cores (the stage just pushed) that
+// also yields each block's energy ||A_blk||_F^2: its tiles write partial sums, and a
+// small stage adds each task's partials in tile order into outs[task].
+bool energy_fusable(const hsvd_plan_st& P) { return !P.trans && P.opt.precision != HSVD_MIXED_BF16; }
+void fuse_energy(hsvd_plan_st& P, const std::vector<std::pair<int, int>>& ranges,
+                 const std::vector<int64_t>& outs) {
+    const int ntiles = P.stages.back().n;
+    const int64_t part = P.alloc(std::max(ntiles, 1));
+    P.stages.back().e_part = part;
+    std::vector<EnergySum> es;
+    for (size_t u = 0; u < ranges.size(); ++u) es.push_back({outs[u], ranges[u].first, ranges[u].second});
+    Stage s{};
+    s.kind = ST_ESUM;
+    s.n = (int)es.size();
+    s.off2 = part;
+    s.w = ntiles;
+    s.tasks_off = P.put(es);
     P.stages.push_back(s);
 }
 
@@ -808,7 +834,12 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
             t.y_off = pan[u].Y; t.y_ld = (int)l.rowsz;
             gt.push_back(t);
         }
-        push_gemm(P, 0, gt, w, bf16 ? MMA_BF16 : MMA_F64);
+        const auto ranges = push_gemm(P, 0, gt, w, bf16 ? MMA_BF16 : MMA_F64);
+        if (P.energy_off >= 0 && energy_fusable(P)) {   // width plans: the leaves' energies
+            std::vector<int64_t> outs;
+            for (int b : ids) outs.push_back(P.energy_off + b);
+            fuse_energy(P, ranges, outs);
+        }
     }
     const int ch = tsqr_chunk(w, std::max(w, W));
     if (P.leaf_cap > 0) {
@@ -959,6 +990,8 @@ std::vector<std::vector<Node>> build_leaves(hsvd_plan_st& P, const std::vector<i
     }
     if (!P.leaf_width.empty()) {
         P.energy_off = P.alloc((int64_t)leaves.size());
+    }
+    if (!P.leaf_width.empty() && !energy_fusable(P)) {   // else summed in the sketch pass
         std::vector<GemmTask> et;
         for (const Leaf& l : leaves) et.push_back(gemm_task(P, l.mat, l.aoff, l.rowsz, l.colsz));
         Stage s{};
@@ -1477,24 +1510,28 @@ void build_features(hsvd_plan_st& P) {
     P.energy_off = P.alloc(nb);
     const int64_t sigs = P.alloc(16LL * nb);
     std::vector<GemmTask> et, gt;
-    std::vector<int64_t> Ys(nb);
+    std::vector<int64_t> Ys(nb), outs(nb);
     for (int i = 0; i < M.p; ++i)
         for (int j = 0; j < M.q; ++j) {
             const int b = i * M.q + j;
             GemmTask t = gemm_task(P, 0, M.rs[i] * M.n + M.cs[j], M.brow(i), M.bcol(j));
             et.push_back(t);
             Ys[b] = P.alloc(M.brow(i) * 16);
+            outs[b] = P.energy_off + b;
             t.x_off = P.omega_off; t.x_ld = (int)bcmax;
             t.y_off = Ys[b]; t.y_ld = (int)M.brow(i);
             gt.push_back(t);
         }
-    Stage se{};
-    se.kind = ST_ENERGY;
-    se.n = nb;
-    se.off = P.energy_off;
-    se.tasks_off = P.put(et);
-    P.stages.push_back(se);
-    push_gemm(P, 0, gt, 16);
+    if (!energy_fusable(P)) {
+        Stage se{};
+        se.kind = ST_ENERGY;
+        se.n = nb;
+        se.off = P.energy_off;
+        se.tasks_off = P.put(et);
+        P.stages.push_back(se);
+    }
+    const auto ranges = push_gemm(P, 0, gt, 16);
+    if (energy_fusable(P)) fuse_energy(P, ranges, outs);   // the energies in the sketch pass
     const int ch = tsqr_chunk(16, 16);
     TsqrBuild tb;
     for (int b = 0; b < nb; ++b) {
@@ -1575,6 +1612,8 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 const int nct = (s.bf16 || s.f32) ? 1 : (s.N + 63) / 64;
                 for (int i = 0; i < s.n; ++i)
                     if (R[i].tile < 0 || R[i].tile >= T[R[i].task].tiles * nct) return "gemm tile ref";
+                if (s.e_part >= 0 && (s.op != 0 || s.bf16 || s.f32 || !span("gemm energy parts", s.e_part, s.e_part + s.n - 1, WS)))
+                    return s.e_part >= 0 && (s.op != 0 || s.bf16 || s.f32) ? "fused energy on a pass other than A X" : msg;
                 if (s.bf16 && P.opt.precision == HSVD_FP64) return "bf16 pass on a float64 plan";
                 if (s.bf16 && s.N > kBf16MaxN) return "bf16 pass wider than its tile";
                 if (s.f32 && (s.N > kBf16MaxN || P.opt.precision == HSVD_FP64)) return "float32 pass";
@@ -1724,6 +1763,15 @@ std::string validate_plan(const hsvd_plan_st& P) {
                         return T[i].w < 1 ? "leaf check width" : msg;
                 break;
             }
+            case ST_ESUM: {
+                const EnergySum* T = (const EnergySum*)(b + s.tasks_off);
+                if (!span("energy parts", s.off2, s.off2 + std::max(s.w, 1) - 1, WS)) return msg;
+                for (int i = 0; i < s.n; ++i) {
+                    if (T[i].first < 0 || T[i].count < 1 || T[i].first + T[i].count > s.w) return "energy part range";
+                    if (!span("energy sum out", T[i].out, T[i].out, WS)) return msg;
+                }
+                break;
+            }
             case ST_FEAT: {
                 if (!span("feature sigma", s.off, s.off + 16LL * s.n - 1, WS)) return msg;
                 if (!span("feature energy", s.off2, s.off2 + s.n - 1, WS)) return msg;
@@ -1805,7 +1853,7 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
                                     (const TileRef*)(b + s.refs_off), s.n, s.N, st);
             else
                 e = launch_gemm(s.op, fp32, (const void* const*)P.dptrs, P.ws, (const GemmTask*)(b + s.tasks_off),
-                                (const TileRef*)(b + s.refs_off), s.n, s.N, st, guard);
+                                (const TileRef*)(b + s.refs_off), s.n, s.N, st, guard, s.e_part);
             break;
         case ST_CQ1:
         case ST_CQ2:
@@ -1857,6 +1905,9 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
         case ST_ENERGY:
             e = launch_block_energy((const void* const*)P.dptrs, fp32, (const GemmTask*)(b + s.tasks_off),
                                     s.n, P.ws, s.off, st);
+            break;
+        case ST_ESUM:
+            e = launch_energy_sum(P.ws, s.off2, (const EnergySum*)(b + s.tasks_off), s.n, st);
             break;
         case ST_FEAT:
             e = launch_block_features(P.ws, s.off, s.off2, s.n, (float*)P.host_ptrs[1], st);
@@ -2597,7 +2648,7 @@ hsvd_status hsvd_launch_times(hsvd_plan_t plan, int32_t* kinds_host, float* ms_h
                 case ST_NN: kind = HSVD_LAUNCH_THIN_NN; break;
                 case ST_SUM: kind = HSVD_LAUNCH_SUM; break;
                 case ST_CORE: kind = s.maxdim > kCoreMaxN ? HSVD_LAUNCH_CORE_WIDE : HSVD_LAUNCH_CORE; break;
-                case ST_ENERGY: kind = HSVD_LAUNCH_ENERGY; break;
+                case ST_ENERGY: case ST_ESUM: kind = HSVD_LAUNCH_ENERGY; break;
                 case ST_FEAT: kind = HSVD_LAUNCH_FEATURES; break;
                 case ST_LEAFCHECK: kind = HSVD_LAUNCH_CHECK; break;
                 case ST_PQR: kind = HSVD_LAUNCH_PANEL_QR; break;
@@ -2732,6 +2783,10 @@ hsvd_status hsvd_launch_work(hsvd_plan_t plan, double* flops_host, double* bytes
                     }
                     break;
                 }
+                case ST_ESUM:                                     // partial sums of the fused pass
+                    f = s.w;
+                    by = (s.w + s.n) * e8;
+                    break;
                 case ST_LEAFCHECK:
                     f = 0.0;
                     by = 0.0;

@@ -25,6 +25,8 @@ struct GemmTask {
     int32_t mat;          // matrix index: A = Aptrs[mat]
 };
 struct TileRef { int32_t task; int32_t tile; };
+// A block's energy from the partial sums of the tiles that read it (a fused sketch pass).
+struct EnergySum { int64_t out; int32_t first, count; };
 // A tile of the Gram matrix G = X^T X (upper triangle, ti <= tj) over one row chunk of X.
 struct GramRef { int32_t ti, tj, chunk, pad; };
 
@@ -240,9 +242,11 @@ hipError_t launch_gemm_f32(int op, const void* const* ptrs, double* ws, const Ge
 hipError_t launch_gram_xtx(int fp32, const void* const* ptrs, int mat, int64_t m, int64_t n,
                            int64_t rows_per_chunk, double* ws, int64_t parts_off, const GramRef* refs, int nrefs,
                            hipStream_t s);
+// e_part >= 0 (op 0 only): tile i also writes its part of its block's energy (the
+// squares of the A rows it reads; 0 from column tiles past the first) to ws[e_part + i].
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
-                       hipStream_t s, const int* guard = nullptr);
+                       hipStream_t s, const int* guard = nullptr, int64_t e_part = -1);
 hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
                               const ChunkRef* chunks, int nchunks, int w, int ch,
                               hipStream_t s, const int* guard = nullptr);
@@ -294,6 +298,8 @@ hipError_t launch_mlp_train(float* master, float* m1, float* m2, const float* X,
 hipError_t launch_mlp_predict(const float* master, const float* X, int count, float* out, hipStream_t s);
 hipError_t launch_block_energy(const void* const* ptrs, int fp32, const GemmTask* tasks, int ntasks,
                                double* ws, int64_t out_off, hipStream_t s);
+// ws[t.out] = sum of ws[part_off + t.first + c], c < t.count, in that order, per task.
+hipError_t launch_energy_sum(double* ws, int64_t part_off, const EnergySum* tasks, int ntasks, hipStream_t s);
 hipError_t launch_block_features(const double* ws, int64_t sig_off, int64_t energy_off, int nblocks,
                                  float* out, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint64_t seed, hipStream_t s);

@@ -6,7 +6,12 @@
 // One 256-thread work-group computes a 64 x 64 output tile on the float64 matrix
 // cores; the reduction dimension streams through LDS in slabs of 32 with
 // coalesced reads of A and X.
+// op 0 with an energy buffer also sums the squares of the A elements it reads: tile i
+// of the launch writes its part of its block's energy ||A_blk||_F^2 (the squares of its
+// 64 rows; 0 from column tiles past the first, which read the same rows) to
+// ws[e_part + i], so a block's sketch and its energy take one pass over A.
 #include "hsvd_internal.hpp"
+#include "device_common.hpp"
 #include "mfma_f64.hpp"
 
 namespace hsvd {
@@ -21,10 +26,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict
                                                    double* __restrict__ ws,
                                                    const GemmTask* __restrict__ tasks,
                                                    const TileRef* __restrict__ tiles, int N,
-                                                   const int* __restrict__ guard) {
+                                                   const int* __restrict__ guard, int64_t e_part) {
     if (guard && *guard) return;                  // a skipped stage (every group returns)
     __shared__ double As[mfma_lds_a<OP>()];
     __shared__ double Bs[mfma_lds_b()];
+    __shared__ double s_sq[4];
     const TileRef tr = tiles[blockIdx.x];
     const GemmTask t = tasks[tr.task];
     const int nct = (N + GT - 1) / GT;
@@ -33,9 +39,17 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict
     const int K = OP == 0 ? t.cols : t.rows;      // reduction length
     const TA* Ab = (const TA*)ptrs[4 * t.mat] + t.a_off;
     v4d acc[2][2];
-    mfma_tile<TA, OP>(Ab, t.lda, ws + t.x_off, t.x_ld, M, N, K, r0, c0, As, Bs, acc);
+    double ssq = 0.0;
+    mfma_tile<TA, OP, true, double, false, OP == 0>(Ab, t.lda, ws + t.x_off, t.x_ld, M, N, K, r0, c0, As, Bs, acc,
+                                                    &ssq);
     double* Y = ws + t.y_off;
     mfma_tile_out(M, N, r0, c0, acc, [&](int r, int c, double v) { Y[(int64_t)c * t.y_ld + r] = v; });
+    if (OP == 0 && e_part >= 0) {
+        ssq = wave_sum(ssq);
+        if ((threadIdx.x & 63) == 0) s_sq[threadIdx.x >> 6] = ssq;
+        __syncthreads();
+        if (threadIdx.x == 0) ws[e_part + blockIdx.x] = c0 == 0 ? (s_sq[0] + s_sq[1]) + (s_sq[2] + s_sq[3]) : 0.0;
+    }
 }
 
 // Gram matrix of the input, G = X^T X (X row-major m x n, G n x n), for the plans that
@@ -79,19 +93,20 @@ hipError_t launch_gram_xtx(int fp32, const void* const* ptrs, int mat, int64_t m
 
 hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
                        const GemmTask* tasks, const TileRef* tiles, int ntiles, int N,
-                       hipStream_t s, const int* guard) {
+                       hipStream_t s, const int* guard, int64_t e_part) {
     if (ntiles <= 0) return hipSuccess;
+    if (op != 0 && e_part >= 0) return hipErrorInvalidValue;
     dim3 g(ntiles), b(256);
     if (op == 0) {
         if (fp32)
-            hipLaunchKernelGGL((k_gemm_mfma<float, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
+            hipLaunchKernelGGL((k_gemm_mfma<float, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
         else
-            hipLaunchKernelGGL((k_gemm_mfma<double, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
+            hipLaunchKernelGGL((k_gemm_mfma<double, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
     } else {
         if (fp32)
-            hipLaunchKernelGGL((k_gemm_mfma<float, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
+            hipLaunchKernelGGL((k_gemm_mfma<float, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
         else
-            hipLaunchKernelGGL((k_gemm_mfma<double, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard);
+            hipLaunchKernelGGL((k_gemm_mfma<double, 1>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
     }
     return hipGetLastError();
 }

@@ -289,6 +289,23 @@ hipError_t launch_block_energy(const void* const* ptrs, int fp32, const GemmTask
     return hipGetLastError();
 }
 
+__global__ void k_energy_sum(double* __restrict__ ws, int64_t part_off, const EnergySum* __restrict__ tasks,
+                             int ntasks) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntasks) return;
+    const EnergySum t = tasks[i];
+    const double* p = ws + part_off + t.first;
+    double s = 0.0;
+    for (int c = 0; c < t.count; ++c) s += p[c];
+    ws[t.out] = s;
+}
+
+hipError_t launch_energy_sum(double* ws, int64_t part_off, const EnergySum* tasks, int ntasks, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_energy_sum, dim3((ntasks + 127) / 128), dim3(128), 0, s, ws, part_off, tasks, ntasks);
+    return hipGetLastError();
+}
+
 hipError_t launch_block_features(const double* ws, int64_t sig_off, int64_t energy_off, int nblocks,
                                  float* out, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;

@@ -30,11 +30,13 @@ __host__ __device__ constexpr int mfma_lds_b() { return MF_T * (MF_K + 1); }
 // With ZERO false the products add to acc as it stands (a second operand pair).
 // TB / BROW: B's element type and layout (BROW: B row-major, B(k, j) = B[k * ldb + j],
 // read with consecutive threads on consecutive columns).
-template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false>
+// SQ: *ssq (per thread) accumulates the squares of the A elements this thread stages
+// (over the work-group: the squared Frobenius norm of the tile's rows of A, OP 0).
+template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false, bool SQ = false>
 __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                                           const TB* __restrict__ B, int64_t ldb,
                                           int M, int N, int K, int r0, int c0, double* As, double* Bs,
-                                          v4d (&acc)[2][2]) {
+                                          v4d (&acc)[2][2], double* ssq = nullptr) {
     constexpr int AP = OP == 0 ? MF_K + 1 : MF_T + 1;
     constexpr int BP = MF_K + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -66,6 +68,7 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
+            if constexpr (SQ) *ssq = fma((double)pa[u], (double)pa[u], *ssq);
             if (OP == 0) As[(e / MF_K) * AP + (e % MF_K)] = (double)pa[u];
             else As[(e / MF_T) * AP + (e % MF_T)] = (double)pa[u];
             if (BROW) Bs[(e % MF_T) * BP + (e / MF_T)] = (double)pb[u];

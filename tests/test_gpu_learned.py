@@ -188,3 +188,39 @@ def test_learned_path_recovers_from_a_bad_prediction():
     assert info["refits"] >= 1 or info["plain"] == 1
     assert r == ro and c["e_frob"] <= 1e-3
     model.close()
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32])
+def test_width_plan_energies_from_the_sketch_pass(precision):
+    """The leaves' block energies come out of the sketch pass (partial sums per tile).
+    Blocks of exact rank below their sketch width (72 and 80 columns: two column tiles
+    of the pass, only the first of which counts the block's rows) miss nothing and are
+    not flagged; 8-column sketches of blocks of rank 40 and 70 with a flat spectrum miss
+    about half their energy and are flagged, the rank-3 block is not, nor the zero block.
+    A doubled energy would flag the first case, a halved one would clear the second."""
+    rng = np.random.default_rng(11)
+    m, n, p, q, bs = 512, 512, 2, 2, 256
+    ranks = [[3, 70], [40, 0]]
+    A = np.zeros((m, n))
+    for i in range(p):
+        for j in range(q):
+            r = ranks[i][j]
+            if r:
+                A[i * bs:(i + 1) * bs, j * bs:(j + 1) * bs] = synth.low_rank(
+                    rng, bs, bs, np.exp(-np.arange(r) / 20.0))[0]
+    dt = torch.float64 if precision == H.FP64 else torch.float32
+    At = torch.tensor(A, device=DEV, dtype=dt)
+    k, tol = 80, 1e-3
+    out = (torch.empty((m, k), dtype=dt, device=DEV), torch.empty((k,), dtype=dt, device=DEV),
+           torch.empty((k, n), dtype=dt, device=DEV))
+    for widths, expect in (([[72, 80], [80, 72]], [[0, 0], [0, 0]]),
+                           ([[8, 8], [8, 8]], [[0, 1], [1, 0]])):
+        plan = H.Plan(m, n, p, q, k, tol, precision=precision, rule=H.RULE_FROB, leaf_widths=widths)
+        plan.execute(At, *out)
+        torch.cuda.synchronize()
+        ranks_got, flags = plan.leaf_info()
+        print(precision, widths, ranks_got.tolist(), flags.tolist(), flush=True)
+        assert flags.tolist() == expect
+        if expect == [[0, 0], [0, 0]]:
+            assert ranks_got.tolist() == ranks
+        plan.close()
