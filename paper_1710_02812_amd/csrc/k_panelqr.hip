@@ -20,7 +20,8 @@
 // dead: zero rows of R and zero columns of Q.
 //
 // Products run on the float64 matrix cores (v_mfma_f64_16x16x4_f64) from slabs of 64
-// rows staged through LDS: the Gram matrix as its upper-triangle 16 x 16 tiles, the
+// rows staged through LDS (the next slab loaded into registers while the current one
+// is multiplied): the Gram matrix as its upper-triangle 16 x 16 tiles, the
 // product Q = X M (M = R_p^-1, upper triangular) as 64 x 16 tiles that stop at M's
 // diagonal.  The Cholesky factor comes from elimination without pivoting with one row
 // of G per lane (two halves of 64 rows) and 16 columns per wave held in registers: the
@@ -56,15 +57,25 @@ __device__ __forceinline__ double pq_recip(double p) {
     return fma(r, e, r);
 }
 
-// Slab [row0, row0 + 64) of the panel X (col-major, ld) into S[c * PQ_SP + r],
-// zero past h rows and past w columns (up to T * 16 columns).
-__device__ __forceinline__ void pq_stage(const double* __restrict__ X, int64_t ld, int h, int w, int T,
-                                         int row0, double* S) {
-    const int n = T * 16 * PQ_RS;
-    for (int e = threadIdx.x; e < n; e += PQ_THREADS) {
-        const int c = e >> 6, r = e & 63;
-        const int gr = row0 + r;
-        S[c * PQ_SP + r] = (c < w && gr < h) ? X[(int64_t)c * ld + gr] : 0.0;
+// Slab [row0, row0 + 64) of the panel X (col-major, ld), zero past h rows and past w
+// columns (up to T * 16 columns): element e = tid + PQ_THREADS u (column e / 64, row
+// e % 64) into v[u], then into S[c * PQ_SP + r].  Loading the next slab into registers
+// before the current one's products keeps its latency off the slab loop.
+constexpr int PQ_PF = kPanelQrMaxW / 16 * 2;   // slab elements per thread (T <= 6)
+__device__ __forceinline__ void pq_load(const double* __restrict__ X, int64_t ld, int h, int w, int T,
+                                        int row0, double (&v)[PQ_PF]) {
+#pragma unroll
+    for (int u = 0; u < PQ_PF; ++u) {
+        const int e = threadIdx.x + PQ_THREADS * u;
+        const int c = e >> 6, gr = row0 + (e & 63);
+        v[u] = (u < 2 * T && c < w && gr < h) ? X[(int64_t)c * ld + gr] : 0.0;
+    }
+}
+__device__ __forceinline__ void pq_put(const double (&v)[PQ_PF], int T, double* S) {
+#pragma unroll
+    for (int u = 0; u < PQ_PF; ++u) {
+        const int e = threadIdx.x + PQ_THREADS * u;
+        if (u < 2 * T) S[(e >> 6) * PQ_SP + (e & 63)] = v[u];
     }
 }
 
@@ -166,9 +177,12 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws
             ti[u] = a;
             tj[u] = a + tt;
         }
+        double pf[PQ_PF];
+        pq_load(X, ldx, h, w, T, 0, pf);
         for (int row0 = 0; row0 < h; row0 += PQ_RS) {
-            pq_stage(X, ldx, h, w, T, row0, Sb);
+            pq_put(pf, T, Sb);
             __syncthreads();
+            if (row0 + PQ_RS < h) pq_load(X, ldx, h, w, T, row0 + PQ_RS, pf);
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
                 if (q + 8 * u < NT) {
@@ -318,12 +332,14 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws
             }
         }
         __syncthreads();
-        // ---- Q = X M, slab by slab (in place when X is Q: a slab is staged before it
-        // is overwritten, and slabs are disjoint)
+        // ---- Q = X M, slab by slab (in place when X is Q: a slab is read before it is
+        // overwritten, and the slab read ahead is never the one being written)
         const int ntile = 4 * T;                  // 4 row tiles of 16 x T column tiles
+        pq_load(X, ldx, h, w, T, 0, pf);
         for (int row0 = 0; row0 < h; row0 += PQ_RS) {
-            pq_stage(X, ldx, h, w, T, row0, Sb);
+            pq_put(pf, T, Sb);
             __syncthreads();
+            if (row0 + PQ_RS < h) pq_load(X, ldx, h, w, T, row0 + PQ_RS, pf);
             for (int tt = q; tt < ntile; tt += 8) {
                 const int rt = tt & 3, ct = tt >> 2;
                 const int kend = min(16 * (ct + 1), K4);
