@@ -89,6 +89,7 @@ struct Stage {
     int ordered = 0;     // panel QR: the tasks run in the dispatch order at order_off
     size_t order_off = 0;
     int64_t e_part = -1; // gemm (op 0, float64 matrix cores): per-tile partial block energies
+    int tx = 2, ty = 2;  // thin gram / nn: 64-column tiles of the widest X and Y
 };
 
 int pow2floor(int x) {
@@ -486,6 +487,11 @@ void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks) {
     s.n = (kind == ST_REDUCE) ? (int)tasks.size() : (int)chunks.size();
     if (kind == ST_REDUCE)
         for (const ThinTask& t : tasks) s.w = std::max(s.w, t.wx * t.wy);
+    s.tx = s.ty = 1;                              // no work-groups for tiles no task has
+    for (const ThinTask& t : tasks) {
+        if (t.wx > 64) s.tx = 2;
+        if (t.wy > 64) s.ty = 2;
+    }
     s.tasks_off = P.put(tasks);
     s.refs_off = P.put(chunks);
     P.stages.push_back(s);
@@ -1677,6 +1683,9 @@ std::string validate_plan(const hsvd_plan_st& P) {
                 for (int i = 0; i < ntask; ++i) {
                     const ThinTask& t = T[i];
                     if (t.wx > 128 || t.wy > 128) return "thin width";
+                    if (s.tx < 1 || s.tx > 2 || s.ty < 1 || s.ty > 2) return "thin tile grid";
+                    if ((s.kind == ST_GRAM && t.wx > 64 * s.tx) || ((s.kind == ST_GRAM || s.kind == ST_NN) && t.wy > 64 * s.ty))
+                        return "thin tile grid narrower than a task";
                     if (s.kind == ST_GRAM) {
                         if (!panel("gram X", t.x_off, t.x_ld, t.h, t.wx)) return msg;
                         if (!panel("gram Y", t.y_off, t.y_ld, t.h, t.wy)) return msg;
@@ -1881,14 +1890,14 @@ hsvd_status run_stage(hsvd_plan_st& P, const Stage& s, hipStream_t st) {
             break;
         case ST_GRAM:
             e = launch_thin_gram(P.ws, (const ThinTask*)(b + s.tasks_off),
-                                 (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st);
+                                 (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st, s.tx, s.ty);
             break;
         case ST_REDUCE:
             e = launch_thin_reduce(P.ws, (const ThinTask*)(b + s.tasks_off), s.n, s.w, st);
             break;
         case ST_NN:
             e = launch_thin_nn(P.ws, P.iws, (const ThinTask*)(b + s.tasks_off),
-                               (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st);
+                               (const ChunkRef*)(b + s.refs_off), s.n, P.thin_ch, st, s.ty);
             break;
         case ST_SUM:
             e = launch_thin_sum(P.ws, (const ThinTask*)(b + s.tasks_off),

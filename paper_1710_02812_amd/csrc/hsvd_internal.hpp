@@ -260,12 +260,13 @@ hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntas
 hipError_t launch_tsqr_apply(double* ws, const int* iws, const TsqrTask* tsqr, const ApplyTask* tasks,
                              const ChunkRef* chunks, int nchunks, int w, int ch, int c,
                              hipStream_t s, const int* guard = nullptr);
+// tx, ty: 64-column tiles of the widest X and Y of the tasks (1 or 2)
 hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks,
-                            int nchunks, int chh, hipStream_t s);
+                            int nchunks, int chh, hipStream_t s, int tx = 2, int ty = 2);
 // maxsz: the largest wx * wy over the tasks (grid: task x element slices of 256)
 hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int maxsz, hipStream_t s);
 hipError_t launch_thin_nn(double* ws, const int* iws, const ThinTask* t, const ChunkRef* chunks,
-                          int nchunks, int chh, hipStream_t s);
+                          int nchunks, int chh, hipStream_t s, int ty = 2);
 // Cholesky QR pass 1 or 2 over the chunks of TsqrTasks with cq_flag >= 0 (w <= 64)
 hipError_t launch_cholqr(int pass, double* ws, int* iws, const TsqrTask* tasks, const ChunkRef* chunks,
                          int nchunks, int w, int ch, hipStream_t s);

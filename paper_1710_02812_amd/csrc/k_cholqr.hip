@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_cholqr(double* __restrict__ ws, int* __
         double sum[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) sum[u] = 0.0;
-#pragma unroll 4
+#pragma unroll 2
         for (int c = 0; c < kCqFan; ++c) {
             const double* src = level + (int64_t)(first + min(c, nchild - 1)) * ww;
 #pragma unroll

@@ -13,6 +13,7 @@
 namespace hsvd {
 
 constexpr int TT = MF_T;
+constexpr int TK = 32;          // slab depth: the reductions here are short (panel widths)
 
 // part (wx x wy) = X_c^T Y_c for one chunk on the float64 matrix cores; grid: chunk x
 // (wx / 64) x (wy / 64) tiles.  X_c^T is a row-major wx x rows array (leading
@@ -20,8 +21,8 @@ constexpr int TT = MF_T;
 __global__ __launch_bounds__(256) void k_thin_gram(double* __restrict__ ws,
                                                    const ThinTask* __restrict__ tasks,
                                                    const ChunkRef* __restrict__ chunks, int chh) {
-    __shared__ double As[mfma_lds_a<0>()];
-    __shared__ double Bs[mfma_lds_b()];
+    __shared__ double As[mfma_lds_a<0, TK>()];
+    __shared__ double Bs[mfma_lds_b<TK>()];
     const ChunkRef cr = chunks[blockIdx.x];
     const ThinTask t = tasks[cr.task];
     const int bx = blockIdx.y * TT, by = blockIdx.z * TT;
@@ -29,8 +30,8 @@ __global__ __launch_bounds__(256) void k_thin_gram(double* __restrict__ ws,
     const int row0 = cr.chunk * chh;
     const int rows = min(chh, t.h - row0);
     v4d acc[2][2];
-    mfma_tile<double, 0>(ws + t.x_off + row0, t.x_ld, ws + t.y_off + row0, t.y_ld, t.wx, t.wy, rows,
-                         bx, by, As, Bs, acc);
+    mfma_tile<double, 0, true, double, false, false, TK>(ws + t.x_off + row0, t.x_ld, ws + t.y_off + row0, t.y_ld,
+                                                        t.wx, t.wy, rows, bx, by, As, Bs, acc);
     double* P = ws + t.part_off + (int64_t)cr.chunk * t.wx * t.wy;
     mfma_tile_out(t.wx, t.wy, bx, by, acc, [&](int r, int c, double v) { P[(int64_t)c * t.wx + r] = v; });
 }
@@ -68,8 +69,9 @@ __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
 __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws, const int* __restrict__ iws,
                                                  const ThinTask* __restrict__ tasks,
                                                  const ChunkRef* __restrict__ chunks, int chh) {
-    __shared__ double As[mfma_lds_a<1>()];
-    __shared__ double Bs[mfma_lds_b()];
+    __shared__ double As[MF_T * (MF_T + 1)];     // the A slabs, then the output tile
+    __shared__ double Bs[mfma_lds_b<TK>()];
+    static_assert(mfma_lds_a<1, TK>() <= MF_T * (MF_T + 1), "A staging");
     const ChunkRef cr = chunks[blockIdx.x];
     const ThinTask t = tasks[cr.task];
     const int rt = blockIdx.y * TT, by = blockIdx.z * TT;
@@ -78,11 +80,11 @@ __global__ __launch_bounds__(256) void k_thin_nn(double* __restrict__ ws, const 
     if (rt >= rows || by >= t.wy) return;
     if (t.cond >= 0 && iws[t.cond] != 0) return;
     v4d acc[2][2];
-    mfma_tile<double, 1>(ws + t.x_off + row0, t.x_ld, ws + t.c_off, t.c_ld, rows, t.wy, t.wx, rt, by,
-                         As, Bs, acc);
+    mfma_tile<double, 1, true, double, false, false, TK>(ws + t.x_off + row0, t.x_ld, ws + t.c_off, t.c_ld, rows,
+                                                        t.wy, t.wx, rt, by, As, Bs, acc);
     if (t.x2_off >= 0)
-        mfma_tile<double, 1, false>(ws + t.x2_off + row0, t.x2_ld, ws + t.c2_off, t.c2_ld, rows, t.wy, t.wx2, rt,
-                                    by, As, Bs, acc);
+        mfma_tile<double, 1, false, double, false, false, TK>(ws + t.x2_off + row0, t.x2_ld, ws + t.c2_off, t.c2_ld,
+                                                             rows, t.wy, t.wx2, rt, by, As, Bs, acc);
     double* Y = ws + t.y_off + row0;
     const int mode = t.accumulate;
     mfma_tile_out_lds(rows, t.wy, rt, by, acc, As, [&](int r, int c, double v) {
@@ -122,9 +124,10 @@ __global__ __launch_bounds__(256) void k_thin_sum(double* __restrict__ ws,
 }
 
 hipError_t launch_thin_gram(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
-                            int chh, hipStream_t s) {
+                            int chh, hipStream_t s, int tx, int ty) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_gram, dim3(nchunks, 2, 2), dim3(256), 0, s, ws, t, chunks, chh);
+    if (tx < 1 || tx > 2 || ty < 1 || ty > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_thin_gram, dim3(nchunks, tx, ty), dim3(256), 0, s, ws, t, chunks, chh);
     return hipGetLastError();
 }
 hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int maxsz, hipStream_t s) {
@@ -133,9 +136,10 @@ hipError_t launch_thin_reduce(double* ws, const ThinTask* t, int ntasks, int max
     return hipGetLastError();
 }
 hipError_t launch_thin_nn(double* ws, const int* iws, const ThinTask* t, const ChunkRef* chunks, int nchunks,
-                          int chh, hipStream_t s) {
+                          int chh, hipStream_t s, int ty) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, (chh + TT - 1) / TT, 2), dim3(256), 0, s, ws, iws, t, chunks, chh);
+    if (ty < 1 || ty > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_thin_nn, dim3(nchunks, (chh + TT - 1) / TT, ty), dim3(256), 0, s, ws, iws, t, chunks, chh);
     return hipGetLastError();
 }
 hipError_t launch_thin_sum(double* ws, const ThinTask* t, const ChunkRef* chunks, int nchunks,

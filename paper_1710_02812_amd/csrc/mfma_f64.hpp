@@ -22,27 +22,31 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int MF_T = 64;        // tile rows and columns
 constexpr int MF_K = 64;        // reduction slab
 
-// LDS doubles of the staging buffers: A slab then B slab
-template <int OP>
-__host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (MF_K + 1) : MF_K * (MF_T + 1); }
-__host__ __device__ constexpr int mfma_lds_b() { return MF_T * (MF_K + 1); }
+// LDS doubles of the staging buffers (slabs of KS along K): A slab then B slab
+template <int OP, int KS = MF_K>
+__host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (KS + 1) : KS * (MF_T + 1); }
+template <int KS = MF_K>
+__host__ __device__ constexpr int mfma_lds_b() { return MF_T * (KS + 1); }
 
 // With ZERO false the products add to acc as it stands (a second operand pair).
 // TB / BROW: B's element type and layout (BROW: B row-major, B(k, j) = B[k * ldb + j],
 // read with consecutive threads on consecutive columns).
 // SQ: *ssq (per thread) accumulates the squares of the A elements this thread stages
 // (over the work-group: the squared Frobenius norm of the tile's rows of A, OP 0).
-template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false, bool SQ = false>
+// KS: the slab depth (64, or 32 for short reductions: half the staging registers and
+// LDS, so that more work-groups share a compute unit).
+template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false, bool SQ = false,
+          int KS = MF_K>
 __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                                           const TB* __restrict__ B, int64_t ldb,
                                           int M, int N, int K, int r0, int c0, double* As, double* Bs,
                                           v4d (&acc)[2][2], double* ssq = nullptr) {
-    constexpr int AP = OP == 0 ? MF_K + 1 : MF_T + 1;
-    constexpr int BP = MF_K + 1;
+    constexpr int AP = OP == 0 ? KS + 1 : MF_T + 1;
+    constexpr int BP = KS + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    constexpr int NE = MF_T * MF_K / 256;                      // slab elements per thread
+    constexpr int NE = MF_T * KS / 256;                      // slab elements per thread
     TA pa[NE];
     TB pb[NE];
     auto fetch = [&](int k0) {
@@ -50,7 +54,7 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
         for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
             if (OP == 0) {
-                const int r = e / MF_K, kk = e % MF_K;        // A(r0 + r, k0 + kk)
+                const int r = e / KS, kk = e % KS;        // A(r0 + r, k0 + kk)
                 const int gr = r0 + r, gk = k0 + kk;
                 pa[u] = (gr < M && gk < K) ? A[(int64_t)gr * lda + gk] : (TA)0;
             } else {
@@ -58,7 +62,7 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                 const int gk = k0 + kk, gc = r0 + c;
                 pa[u] = (gk < K && gc < M) ? A[(int64_t)gk * lda + gc] : (TA)0;
             }
-            const int bc = BROW ? e % MF_T : e / MF_K, bk = BROW ? e / MF_T : e % MF_K;   // B(k0 + bk, c0 + bc)
+            const int bc = BROW ? e % MF_T : e / KS, bk = BROW ? e / MF_T : e % KS;   // B(k0 + bk, c0 + bc)
             const int gbc = c0 + bc, gbk = k0 + bk;
             if (BROW) pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbk * ldb + gbc] : (TB)0;
             else pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : (TB)0;
@@ -69,10 +73,10 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
         for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
             if constexpr (SQ) *ssq = fma((double)pa[u], (double)pa[u], *ssq);
-            if (OP == 0) As[(e / MF_K) * AP + (e % MF_K)] = (double)pa[u];
+            if (OP == 0) As[(e / KS) * AP + (e % KS)] = (double)pa[u];
             else As[(e / MF_T) * AP + (e % MF_T)] = (double)pa[u];
             if (BROW) Bs[(e % MF_T) * BP + (e / MF_T)] = (double)pb[u];
-            else Bs[(e / MF_K) * BP + (e % MF_K)] = (double)pb[u];
+            else Bs[(e / KS) * BP + (e % KS)] = (double)pb[u];
         }
     };
     if (ZERO)
@@ -81,12 +85,12 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     fetch(0);
-    for (int k0 = 0; k0 < K; k0 += MF_K) {
+    for (int k0 = 0; k0 < K; k0 += KS) {
         stage();
         __syncthreads();
-        if (k0 + MF_K < K) fetch(k0 + MF_K);                  // in flight during the products
+        if (k0 + KS < K) fetch(k0 + KS);                  // in flight during the products
 #pragma unroll
-        for (int q = 0; q < MF_K / 4; ++q) {
+        for (int q = 0; q < KS / 4; ++q) {
             const int kk = 4 * q + lk;
             double a[2], b[2];
 #pragma unroll
