@@ -302,14 +302,25 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(double* __restrict__ ws, 
 #pragma unroll
                 for (int t = 0; t < TMAX; ++t) ra[t] = ga[gl + t * gsz];
             }
+            // the rounds in which this group meets a marked partner, once per depth: bit r
+            // for b = lo + m + (j + r) mod m, i.e. the marks of B = [lo + m, hi) (at most
+            // m <= 64 columns) rotated by j within m bits
+            unsigned long long rmask = 0ull;
+            if (act) {
+                const unsigned long long lo64 = (unsigned long long)pw0 | ((unsigned long long)pw1 << 32);
+                const unsigned long long hi64 = (unsigned long long)pw2 | ((unsigned long long)pw3 << 32);
+                const int off = lo + m, nb = hi - off;
+                unsigned long long win = off == 0 ? lo64
+                                       : off < 64 ? (lo64 >> off) | (hi64 << (64 - off)) : hi64 >> (off - 64);
+                if (nb < 64) win &= (1ull << nb) - 1ull;
+                rmask = j == 0 ? win : (win >> j) | (win << (m - j));
+                if (m < 64) rmask &= (1ull << m) - 1ull;
+            }
             bool moved = false;
             int bi = j;                                        // (j + r) mod m
             for (int r = 0; r < gpt; ++r, bi = (bi + 1 == m) ? 0 : bi + 1) {
-                const int b = act ? lo + m + bi : 0;
-                const int bw = b >> 5;
-                const unsigned pw = bw == 0 ? pw0 : bw == 1 ? pw1 : bw == 2 ? pw2 : pw3;
-                const bool marked = b < hi && ((pw >> (b & 31)) & 1u) != 0;
-                const bool valid = act && r < m && marked;
+                const bool valid = ((rmask >> r) & 1ull) != 0;
+                const int b = lo + m + bi;
                 double rb[TMAX];
                 double c0 = 0.0, c1 = 0.0, db = 0.0;
                 double* gb = G + (int64_t)(valid ? b : 0) * ldg;
