@@ -430,7 +430,7 @@ std::vector<std::pair<int, int>> push_gemm(hsvd_plan_st& P, int op, std::vector<
     std::vector<TileRef> tiles;
     std::vector<std::pair<int, int>> ranges;
     const bool strip = mma != MMA_F64;
-    const int nct = strip ? 1 : (N + 63) / 64;
+    const int nct = strip ? 1 : gemm_f64_col_tiles(N);
     const int th = strip ? kBf16TileRows : 64;
     for (size_t t = 0; t < tasks.size(); ++t) {
         const int out_rows = (op == 0) ? tasks[t].rows : tasks[t].cols;
@@ -1615,7 +1615,7 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const int th = (s.bf16 || s.f32) ? kBf16TileRows : 64;
                     if (t.tiles != (yr + th - 1) / th) return "gemm tile count";
                 }
-                const int nct = (s.bf16 || s.f32) ? 1 : (s.N + 63) / 64;
+                const int nct = (s.bf16 || s.f32) ? 1 : gemm_f64_col_tiles(s.N);
                 for (int i = 0; i < s.n; ++i)
                     if (R[i].tile < 0 || R[i].tile >= T[R[i].task].tiles * nct) return "gemm tile ref";
                 if (s.e_part >= 0 && (s.op != 0 || s.bf16 || s.f32 || !span("gemm energy parts", s.e_part, s.e_part + s.n - 1, WS)))

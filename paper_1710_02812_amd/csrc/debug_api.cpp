@@ -118,7 +118,7 @@ extern "C" hsvd_status hsvd_debug_gemm(int32_t op, int32_t kind, int32_t a_fp32,
     const int tile_rows = kind != 0 ? kBf16TileRows : 64;
     if (kind != 0 && N > kBf16MaxN)
         return set_error(HSVD_ERR_INVALID, "hsvd_debug_gemm: bfloat16 and float32 passes take N <= 96");
-    const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = kind != 0 ? 1 : (N + 63) / 64;
+    const int nrt = (int)((yr + tile_rows - 1) / tile_rows), nct = kind != 0 ? 1 : gemm_f64_col_tiles(N);
     TileRef* dtiles = sc.get<TileRef>((size_t)nrt * nct);
     if (!ws || !dt || !dtiles || !dptrs) return set_error(HSVD_ERR_ALLOC, "scratch allocation failed");
     GemmTask t{};

@@ -25,6 +25,9 @@ struct GemmTask {
     int32_t mat;          // matrix index: A = Aptrs[mat]
 };
 struct TileRef { int32_t task; int32_t tile; };
+// Column tiles of a float64 matrix-core pass over N output columns: one 64 x 96 tile up to
+// 96 columns (A read once), else 64-column tiles.
+__host__ __device__ inline int gemm_f64_col_tiles(int N) { return (N > 64 && N <= 96) ? 1 : (N + 63) / 64; }
 // A block's energy from the partial sums of the tiles that read it (a fused sketch pass).
 struct EnergySum { int64_t out; int32_t first, count; };
 // A tile of the Gram matrix G = X^T X (upper triangle, ti <= tj) over one row chunk of X.

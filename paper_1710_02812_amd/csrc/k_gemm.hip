@@ -18,30 +18,31 @@ namespace hsvd {
 
 constexpr int GT = MF_T;  // output tile (rows and columns)
 
-// One 64 x 64 output tile per 256-thread work-group on the float64 matrix cores.
+// One 64 x NC output tile per 256-thread work-group on the float64 matrix cores (NC = 64,
+// or 96 with 32-deep slabs when the product has 65..96 columns, so that A is read once).
 //   OP 0: Y = A_blk X   (A_blk row-major: the tile's A operand as stored)
 //   OP 1: Y = A_blk^T X (the stored rows of A_blk are the reduction index)
-template <typename TA, int OP>
+template <typename TA, int OP, int NC = MF_T, int KS = MF_K>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const void* const* __restrict__ ptrs,
                                                    double* __restrict__ ws,
                                                    const GemmTask* __restrict__ tasks,
                                                    const TileRef* __restrict__ tiles, int N,
                                                    const int* __restrict__ guard, int64_t e_part) {
     if (guard && *guard) return;                  // a skipped stage (every group returns)
-    __shared__ double As[mfma_lds_a<OP>()];
-    __shared__ double Bs[mfma_lds_b()];
+    __shared__ double As[mfma_lds_a<OP, KS>()];
+    __shared__ double Bs[mfma_lds_b<KS, NC>()];
     __shared__ double s_sq[4];
     const TileRef tr = tiles[blockIdx.x];
     const GemmTask t = tasks[tr.task];
-    const int nct = (N + GT - 1) / GT;
-    const int r0 = (tr.tile / nct) * GT, c0 = (tr.tile % nct) * GT;
+    const int nct = gemm_f64_col_tiles(N);
+    const int r0 = (tr.tile / nct) * GT, c0 = (tr.tile % nct) * NC;
     const int M = OP == 0 ? t.rows : t.cols;      // output rows
     const int K = OP == 0 ? t.cols : t.rows;      // reduction length
     const TA* Ab = (const TA*)ptrs[4 * t.mat] + t.a_off;
-    v4d acc[2][2];
+    v4d acc[2][NC / 32];
     double ssq = 0.0;
-    mfma_tile<TA, OP, true, double, false, OP == 0>(Ab, t.lda, ws + t.x_off, t.x_ld, M, N, K, r0, c0, As, Bs, acc,
-                                                    &ssq);
+    mfma_tile<TA, OP, true, double, false, OP == 0, KS, NC>(Ab, t.lda, ws + t.x_off, t.x_ld, M, N, K, r0, c0, As, Bs,
+                                                            acc, &ssq);
     double* Y = ws + t.y_off;
     mfma_tile_out(M, N, r0, c0, acc, [&](int r, int c, double v) { Y[(int64_t)c * t.y_ld + r] = v; });
     if (OP == 0 && e_part >= 0) {
@@ -97,6 +98,20 @@ hipError_t launch_gemm(int op, int fp32, const void* const* ptrs, double* ws,
     if (ntiles <= 0) return hipSuccess;
     if (op != 0 && e_part >= 0) return hipErrorInvalidValue;
     dim3 g(ntiles), b(256);
+    if (N > 64 && N <= 96) {                      // one 64 x 96 tile per row strip
+        if (op == 0) {
+            if (fp32)
+                hipLaunchKernelGGL((k_gemm_mfma<float, 0, 96, 32>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
+            else
+                hipLaunchKernelGGL((k_gemm_mfma<double, 0, 96, 32>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
+        } else {
+            if (fp32)
+                hipLaunchKernelGGL((k_gemm_mfma<float, 1, 96, 32>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
+            else
+                hipLaunchKernelGGL((k_gemm_mfma<double, 1, 96, 32>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);
+        }
+        return hipGetLastError();
+    }
     if (op == 0) {
         if (fp32)
             hipLaunchKernelGGL((k_gemm_mfma<float, 0>), g, b, 0, s, ptrs, ws, tasks, tiles, N, guard, e_part);

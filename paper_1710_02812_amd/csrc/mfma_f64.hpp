@@ -25,8 +25,8 @@ constexpr int MF_K = 64;        // reduction slab
 // LDS doubles of the staging buffers (slabs of KS along K): A slab then B slab
 template <int OP, int KS = MF_K>
 __host__ __device__ constexpr int mfma_lds_a() { return OP == 0 ? MF_T * (KS + 1) : KS * (MF_T + 1); }
-template <int KS = MF_K>
-__host__ __device__ constexpr int mfma_lds_b() { return MF_T * (KS + 1); }
+template <int KS = MF_K, int NC = MF_T>
+__host__ __device__ constexpr int mfma_lds_b() { return NC * (KS + 1); }
 
 // With ZERO false the products add to acc as it stands (a second operand pair).
 // TB / BROW: B's element type and layout (BROW: B row-major, B(k, j) = B[k * ldb + j],
@@ -35,20 +35,26 @@ __host__ __device__ constexpr int mfma_lds_b() { return MF_T * (KS + 1); }
 // (over the work-group: the squared Frobenius norm of the tile's rows of A, OP 0).
 // KS: the slab depth (64, or 32 for short reductions: half the staging registers and
 // LDS, so that more work-groups share a compute unit).
+// NC: the tile's columns, 64 or 96 (a 64 x 96 tile: wave w owns rows 32 (w & 1) and
+// columns 48 (w >> 1) as 2 x 3 blocks, so that a product up to 96 columns wide reads
+// its A once).
 template <typename TA, int OP, bool ZERO = true, typename TB = double, bool BROW = false, bool SQ = false,
-          int KS = MF_K>
+          int KS = MF_K, int NC = MF_T>
 __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                                           const TB* __restrict__ B, int64_t ldb,
                                           int M, int N, int K, int r0, int c0, double* As, double* Bs,
-                                          v4d (&acc)[2][2], double* ssq = nullptr) {
+                                          v4d (&acc)[2][NC / 32], double* ssq = nullptr) {
+    static_assert(NC == 64 || NC == 96, "tile columns");
+    constexpr int NJ = NC / 32;                              // column blocks per wave
     constexpr int AP = OP == 0 ? KS + 1 : MF_T + 1;
     constexpr int BP = KS + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * (NC / 2);
     const int li = lane & 15, lk = lane >> 4;
-    constexpr int NE = MF_T * KS / 256;                      // slab elements per thread
+    constexpr int NE = MF_T * KS / 256;                      // A slab elements per thread
+    constexpr int NEB = NC * KS / 256;                       // B slab elements per thread
     TA pa[NE];
-    TB pb[NE];
+    TB pb[NEB];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
@@ -62,7 +68,11 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
                 const int gk = k0 + kk, gc = r0 + c;
                 pa[u] = (gk < K && gc < M) ? A[(int64_t)gk * lda + gc] : (TA)0;
             }
-            const int bc = BROW ? e % MF_T : e / KS, bk = BROW ? e / MF_T : e % KS;   // B(k0 + bk, c0 + bc)
+        }
+#pragma unroll
+        for (int u = 0; u < NEB; ++u) {
+            const int e = tid + 256 * u;
+            const int bc = BROW ? e % NC : e / KS, bk = BROW ? e / NC : e % KS;   // B(k0 + bk, c0 + bc)
             const int gbc = c0 + bc, gbk = k0 + bk;
             if (BROW) pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbk * ldb + gbc] : (TB)0;
             else pb[u] = (gbc < N && gbk < K) ? B[(int64_t)gbc * ldb + gbk] : (TB)0;
@@ -75,7 +85,11 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
             if constexpr (SQ) *ssq = fma((double)pa[u], (double)pa[u], *ssq);
             if (OP == 0) As[(e / KS) * AP + (e % KS)] = (double)pa[u];
             else As[(e / MF_T) * AP + (e % MF_T)] = (double)pa[u];
-            if (BROW) Bs[(e % MF_T) * BP + (e / MF_T)] = (double)pb[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NEB; ++u) {
+            const int e = tid + 256 * u;
+            if (BROW) Bs[(e % NC) * BP + (e / NC)] = (double)pb[u];
             else Bs[(e / KS) * BP + (e % KS)] = (double)pb[u];
         }
     };
@@ -83,7 +97,7 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += KS) {
         stage();
@@ -92,17 +106,18 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
             const int kk = 4 * q + lk;
-            double a[2], b[2];
+            double a[2], b[NJ];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int row = wr + 16 * i + li;
                 a[i] = OP == 0 ? As[row * AP + kk] : As[kk * AP + row];
-                b[i] = Bs[(wc + 16 * i + li) * BP + kk];
             }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) b[j] = Bs[(wc + 16 * j + li) * BP + kk];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < NJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
@@ -110,13 +125,13 @@ __device__ __forceinline__ void mfma_tile(const TA* __restrict__ A, int64_t lda,
 }
 
 // Visits the tile's outputs: f(row, col, value) for rows < M, columns < N.
-template <typename F>
-__device__ __forceinline__ void mfma_tile_out(int M, int N, int r0, int c0, const v4d (&acc)[2][2], F f) {
+template <typename F, int NJ>
+__device__ __forceinline__ void mfma_tile_out(int M, int N, int r0, int c0, const v4d (&acc)[2][NJ], F f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * (16 * NJ);    // NJ = tile columns / 32
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const int gc = c0 + wc + 16 * j + li;
         if (gc >= N) continue;
 #pragma unroll

@@ -402,6 +402,29 @@ def test_gemm_bf16_matrix_cores(rows, cols, op, N):
     assert np.max(np.abs(Y64 - ref64)) <= 1e-13 * np.max(np.abs(ref64)) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("N", [17, 64, 65, 78, 96, 97, 128])
+@pytest.mark.parametrize("op", [0, 1])
+@pytest.mark.parametrize("a64", [False, True])
+def test_gemm_float64_passes_every_width(N, op, a64):
+    """The float64 matrix-core pass over a block, across the width where one 64 x 96 tile
+    replaces two 64-column tiles (65..96 columns: A read once): exact to float64 rounding
+    against the host product, ragged rows and columns included."""
+    rows, cols = 203, 141
+    rng = np.random.default_rng(N + 7 * op + (11 if a64 else 0))
+    A = rng.standard_normal((rows, cols))
+    if not a64:
+        A = A.astype(np.float32)
+    K = cols if op == 0 else rows
+    X = rng.standard_normal((K, N))
+    print(f"gemm f64 op{op} N={N} a64={a64}", flush=True)
+    Y = H.debug_gemm(torch.tensor(A, device=DEV), _t(X), op=op).cpu().numpy()
+    A64 = A.astype(np.float64)
+    ref = (A64 @ X) if op == 0 else (A64.T @ X)
+    bound = (np.abs(A64) @ np.abs(X)) if op == 0 else (np.abs(A64).T @ np.abs(X))
+    assert Y.shape == ref.shape
+    assert np.all(np.abs(Y - ref) <= 2.0 * K * 2.0 ** -53 * bound + 1e-300)
+
+
 def test_peak_probes_are_plausible():
     """The library's peak probes: each reports the work it did and a rate below the
     device's published peak (HBM 8 TB/s; float64, bfloat16, float32 matrix cores 78.6,
