@@ -303,14 +303,17 @@ int add_tsqr(hsvd_plan_st& P, TsqrBuild& tb, int64_t panel, int h, int ld, int w
 
 void push_thin(hsvd_plan_st& P, StageKind kind, std::vector<ThinTask> tasks);
 
-void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch, bool need_r = true) {
+// span_only (panel QR): the factor only has to span the panel for the next power step,
+// so the panel QR stops after its shifted first pass.
+void push_tsqr_factor(hsvd_plan_st& P, const TsqrBuild& tb, int w, int ch, bool need_r = true,
+                      bool span_only = false) {
     if (tb.pqr) {
         Stage q{};
         q.kind = ST_PQR;
         q.n = (int)tb.tasks.size();
         q.w = w;
         q.ch = ch;
-        q.need_r = need_r ? 1 : 0;
+        q.need_r = span_only && !need_r ? kPqrSpanOnly : need_r ? 1 : 0;
         q.tasks_off = P.put(tb.tasks);
         // one work-group per panel: the tallest panels first, so that a launch over
         // panels of uneven heights (a batch) does not end on its longest work-groups
@@ -868,7 +871,10 @@ void leaf_pipeline(hsvd_plan_st& P, const std::vector<Leaf>& leaves, const std::
                 add_tsqr(P, tb, pan[u].Z, (int)l.colsz, (int)l.colsz, w, ch, false, pq ? pan[u].Qz : -1,
                          (int)l.colsz);
         }
-        push_tsqr_factor(P, tb, w, ch, t == g);
+        // the sketch's own QR (float32 storage and mixed plans, one power step): its Q
+        // only sets the subspace that Z = A_b^T Q spans, so the panel QR stops after its
+        // shifted pass (a well-conditioned basis of the same span); the later QRs stay full
+        push_tsqr_factor(P, tb, w, ch, t == g, t == 1 && t < g && P.opt.precision != HSVD_FP64);
         if (t == g) { tb_last = tb; break; }
         std::vector<ApplyTask> at;
         for (size_t u = 0; u < ids.size(); ++u) {
@@ -1759,7 +1765,8 @@ std::string validate_plan(const hsvd_plan_st& P) {
                     const int64_t q_end = t.pq_q_off + (int64_t)(s.w - 1) * t.pq_q_ld + t.h;
                     if (t.pq_q_off < p_end && t.p_off < q_end) return "panel qr Q overlaps P";
                     if (!span("panel qr scratch", t.pq_scr, t.pq_scr + 2LL * s.w * s.w - 1, WS)) return msg;
-                    if (s.need_r && !span("panel qr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
+                    if (s.need_r != 0 && s.need_r != 1 && s.need_r != kPqrSpanOnly) return "panel qr mode";
+                    if (s.need_r == 1 && !span("panel qr R", t.r_out, t.r_out + (int64_t)s.w * s.w - 1, WS)) return msg;
                     if (t.cq_flag < 0 || t.cq_flag >= IW) return "panel qr flag slot";
                 }
                 break;

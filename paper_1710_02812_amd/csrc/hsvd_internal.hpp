@@ -254,7 +254,11 @@ hipError_t launch_tsqr_factor(double* ws, int* iws, const TsqrTask* tasks,
                               const ChunkRef* chunks, int nchunks, int w, int ch,
                               hipStream_t s, const int* guard = nullptr);
 // Panel QR of the leaves (one work-group per TsqrTask with pq_q_off >= 0, w <= kPanelQrMaxW):
-// repeated Cholesky QR, the first pass shifted; need_r also forms R at r_out.
+// repeated Cholesky QR, the first pass shifted; need_r 1 also forms R at r_out, and
+// kPqrSpanOnly stops after the shifted first pass (Q spans the panel and is well
+// conditioned but not orthonormal to working precision; no R), for a sketch whose Q only
+// feeds the next power step.
+constexpr int kPqrSpanOnly = 2;          // panel QR mode: the shifted first pass only
 constexpr int kPanelQrMaxW = 96;
 constexpr int kPanelQrMaxPass = 4;
 // `order` (device, ntasks task indices, or nullptr for task order): the dispatch order

@@ -17,7 +17,10 @@
 // what the shift covers, such as the sketch of an exactly low-rank block), a
 // non-finite value, or the pass cap sets the panel's fallback flag: the Householder
 // kernels then factor it and these outputs are ignored.  Exactly zero columns are
-// dead: zero rows of R and zero columns of Q.
+// dead: zero rows of R and zero columns of Q.  In the span-only mode the factorization
+// stops after pass 1: Q = P R_1^-1 spans the panel and is well conditioned but not
+// orthonormal to working precision, which is all a sketch's basis needs before the
+// next power step.
 //
 // Products run on the float64 matrix cores (v_mfma_f64_16x16x4_f64) from slabs of 64
 // rows staged through LDS (the next slab loaded into registers while the current one
@@ -263,14 +266,14 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel_qr(double* __restrict__ ws
         double rmin = 1.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) rmin = fmin(rmin, s_rho[i]);
-        const bool done = pass >= 2 && rmin >= 0.25;
+        const bool done = need_r == kPqrSpanOnly || (pass >= 2 && rmin >= 0.25);
         if (s_fail || (!done && pass == kPanelQrMaxPass)) {
             failed_all = true;
             break;
         }
         // ---- R accumulation: T_p = R_p T_(p-1), R_p(i, k) = sqrt(D_i) m_(k i) right of
         // the diagonal (m_(k i) = Lm[i][k]), sqrt(D_i) on it
-        if (need_r) {
+        if (need_r == 1) {
             double* Tout = done ? ws + t.r_out : Tbuf + (int64_t)(pass & 1) * w * w;
             const double* Tin = Tbuf + (int64_t)((pass - 1) & 1) * w * w;
             for (int tt = q; tt < NT; tt += 8) {
@@ -373,6 +376,7 @@ hipError_t launch_panel_qr(double* ws, int* iws, const TsqrTask* tasks, int ntas
                            hipStream_t s, const int* guard, const int* order) {
     if (ntasks <= 0) return hipSuccess;
     if (w < 1 || w > kPanelQrMaxW) return hipErrorInvalidValue;
+    if (need_r != 0 && need_r != 1 && need_r != kPqrSpanOnly) return hipErrorInvalidValue;
     hipError_t e = prepare_panel_qr_launches();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_panel_qr, dim3(ntasks), dim3(PQ_THREADS), PQ_LDS_BYTES, s, ws, iws, tasks, w, need_r,
