@@ -829,8 +829,9 @@ def run_learned(args, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "sharding of the method is described in DESIGN.md and not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the method's multi-GPU "
+              "sharding (row slabs per GPU, a tree reduction of the row merges) is not run here.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_probe:

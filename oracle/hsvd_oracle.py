@@ -24,7 +24,7 @@ identity of Section 3); the faster complement form (eqs. orthmerge1/orthmerge)
 is implemented separately in ``merge_complement`` and is used only to cross-check
 that identity, never as the reference.
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
   R1 truncation keeps s_i >= tol * s_0 (ties kept), caps r <= k, and drops values
      <= max(shape) * 2^-52 * s_0 (numerical zero).  tol = 0 means fixed rank k.
   R2 the same rule is applied to leaves, merges and the slab re-projection; the
