@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void k_thin_reduce(double* __restrict__ ws,
 // Y_c (op)= X_c * C with C (wx x wy, ld c_ld) on the float64 matrix cores; grid: chunk
 // x (chh / 64) row tiles x (wy / 64) column tiles.  X_c (rows x wx, column-major) is the
 // transpose of a row-major wx x rows array.
-// Three work-groups per CU: the register cap costs one 8-byte spill outside the slab
-// loop and shortens the Q updates of a merge level by about a tenth.
+// Three work-groups per CU: the register cap costs one spilled register (a 4-byte
+// store and reload) and shortens the Q updates of a merge level by about a tenth.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_thin_nn(double* __restrict__ ws, const int* __restrict__ iws,
                                                  const ThinTask* __restrict__ tasks,
                                                  const ChunkRef* __restrict__ chunks, int chh) {
